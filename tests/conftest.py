@@ -1,0 +1,21 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
+    config.addinivalue_line("markers", "slow: oracle runs of more than a few seconds")
+
+
+@pytest.fixture(scope="session")
+def genetic_code():
+    from oracle import brute
+    return brute.load_genetic_code(os.path.join(GOLDEN, "genetic_code.txt"))
