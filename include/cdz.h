@@ -1,0 +1,158 @@
+/*
+ * cdz.h -- C ABI of the MI355X codon-constrained partition-function library.
+ *
+ * The library computes, for an amino-acid sequence psi (m residues, n = 3m
+ * bases), the partition function summed jointly over every codon sequence
+ * encoding psi and every non-crossing secondary structure of that sequence
+ * (paper Section 2b, eqs. structure-q, sequence-q, amino-q), biased by
+ * per-codon and codon-pair weights (the soft constraints of Section 3a).  From
+ * it follow the pair matrix, base and codon marginals (Section 2c, eqs.
+ * pair-probability, marginal-base, marginal-codon) and exact joint samples of
+ * sequence and structure (Section 4a).  The secondary-structure model is a
+ * nearest-neighbour loop model (see cdz_energy).  Every call runs its dynamic
+ * program in HIP kernels on the device that is current when cdz_create is
+ * called; the host only validates inputs and builds small per-position tables.
+ *
+ * Conventions
+ *   - Bases A=0 C=1 G=2 U=3.  Pair types AU=0 CG=1 GC=2 UA=3 GU=4 UG=5.
+ *   - Residues are the letters "ARNDCQEGHILKMFPSTWYV"; start and stop codons
+ *     are not part of psi (SI S3c).  The codons of a residue are numbered in
+ *     lexicographic order of their spelling under A<C<G<U ("slot" s, at most
+ *     6 per residue); all per-codon inputs and outputs use this slot order
+ *     and are padded with zeros to 6 slots.
+ *   - Energies are in units of kT (the paper's unitless free energies); +inf
+ *     marks a forbidden entry.
+ *   - The caller owns every input and output buffer.  The handle owns all
+ *     device workspace and keeps the last forward pass for cdz_marginals and
+ *     cdz_sample on the same problem.
+ *   - Every call returns a cdz_status; no exception crosses the ABI.  Inputs
+ *     are validated before any device work.  cdz_last_error() describes the
+ *     last failure of a handle.  Handles are not thread-safe; use one handle
+ *     per host thread / stream.
+ */
+#ifndef CDZ_H
+#define CDZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CDZ_OK = 0,
+  CDZ_ERR_ARG = 1,      /* null pointer, n_aa < 1, n_samples < 0, bad option   */
+  CDZ_ERR_PROTEIN = 2,  /* a letter outside the 20 standard amino acids        */
+  CDZ_ERR_NUMERIC = 3,  /* non-finite weights/tables, or scaling out of range  */
+  CDZ_ERR_NOMEM = 4,    /* device allocation failed                            */
+  CDZ_ERR_BUDGET = 5,   /* workspace would exceed options.mem_budget_bytes     */
+  CDZ_ERR_HIP = 6,      /* a HIP runtime call failed                           */
+  CDZ_ERR_STATE = 7     /* sample/marginals without a usable forward pass      */
+} cdz_status;
+
+typedef enum {
+  CDZ_FP32_SCALED = 0,  /* FP32 arrays, one power-of-two exponent per diagonal;
+                           exponents, exterior loop and log Z in FP64          */
+  CDZ_FP64 = 1          /* the same dynamic program entirely in FP64           */
+} cdz_precision;
+
+/* Nearest-neighbour loop model, energies in kT (+inf = forbidden).
+ *   hairpin closed by (i,j), L = j-i-1 >= 3 unpaired bases:
+ *       hairpin[L] (L <= 30) or hairpin[30] + extrap*ln(L/30),
+ *       plus mismatch[b(i+1)][b(j-1)][type(i,j)]
+ *   stacked pair (i,j) on (i+1,j-1): stack[type(i,j)][type(i+1,j-1)]
+ *   bulge, one side empty, L in 1..30 unpaired: bulge[L]
+ *   interior loop, l1,l2 >= 1, l1+l2 <= 30, inner pair (k,l):
+ *       interior[l1+l2] + mismatch[b(i+1)][b(j-1)][type(i,j)]
+ *                       + mismatch[b(l+1)][b(k-1)][type(l,k)]
+ *   multiloop: ml_a + ml_b*(inner branches + 1) + ml_c*(unpaired bases)
+ *   exterior loop: 0.  Hairpins need >= 3 unpaired bases; no pseudoknots.
+ * The record is 199 doubles in exactly this field order. */
+typedef struct {
+  double stack[6][6];
+  double hairpin[31];
+  double bulge[31];
+  double interior[31];
+  double mismatch[4][4][6];
+  double ml_a, ml_b, ml_c;
+  double extrap;
+} cdz_energy;
+
+/* One protein and its soft constraints (Section 3a).
+ *   aa      : n_aa letters (not NUL-terminated necessarily).
+ *   theta1  : [n_aa][6] log codon weights, slot order; NULL = all zero.
+ *   theta2  : [n_aa][6][6] log codon-pair weights; theta2[a][x][y] weighs
+ *             codon x at residue a-1 followed by codon y at residue a; row 0
+ *             is ignored (open chain, no pair term before the first codon);
+ *             NULL = no pair terms.
+ * W(c) = exp(sum_a theta1[a][c_a] + sum_{a>=1} theta2[a][c_{a-1}][c_a]). */
+typedef struct {
+  int32_t n_aa;
+  const char *aa;
+  const double *theta1;
+  const double *theta2;
+} cdz_problem;
+
+typedef struct {
+  cdz_precision prec;
+  size_t mem_budget_bytes; /* 0 = unlimited; otherwise CDZ_ERR_BUDGET above it */
+  void *hip_stream;        /* hipStream_t to run on; NULL = the null stream     */
+} cdz_options;
+
+typedef struct cdz_handle cdz_handle;
+
+/* Create a handle bound to the current HIP device.  `energy` is copied.
+ * Returns CDZ_ERR_NUMERIC if an energy is NaN or -inf. */
+cdz_status cdz_create(const cdz_energy *energy, const cdz_options *opts, cdz_handle **out);
+void cdz_destroy(cdz_handle *h);
+
+/* log Z (natural log of the partition function, = -q_psi of eq. amino-q).
+ * Runs the forward pass and keeps it in the handle. */
+cdz_status cdz_partition(cdz_handle *h, const cdz_problem *prob, double *log_z);
+
+/* log Z plus marginals (Section 2c), all row-major host buffers of doubles:
+ *   pair       [n][n]   P[i][j] = Pr(i pairs with j), P[i][i] = Pr(i unpaired)
+ *   base       [n][4]   Pr(base of position p = b)
+ *   codon      [n_aa][6] Pr(codon of residue a = slot s)  (= d log Z / d theta1)
+ *   codon_pair [n_aa][6][6] Pr(codons of residues a-1, a = x, y), row 0 zero
+ *                        (= d log Z / d theta2)
+ * Any output pointer may be NULL.  Runs forward (unless the handle holds the
+ * forward of the same problem) and the outside (adjoint) pass. */
+cdz_status cdz_marginals(cdz_handle *h, const cdz_problem *prob, double *log_z,
+                         double *pair, double *base, double *codon, double *codon_pair);
+
+/* n_samples exact joint samples of (codon sequence, structure) from the
+ * Boltzmann distribution, drawn by stochastic traceback of the forward pass
+ * with Philox4x32-10 (key = seed, counter = (draw index, sample index, 0, 0)).
+ *   codons [n_samples][n_aa]  slot of each residue
+ *   pairs  [n_samples][n]     partner of each position, -1 = unpaired */
+cdz_status cdz_sample(cdz_handle *h, const cdz_problem *prob, uint64_t seed,
+                      int32_t n_samples, uint8_t *codons, int32_t *pairs);
+
+/* Device-pointer form of the forward pass for callers that keep the weights
+ * on the device (PyTorch): theta1_dev [n_aa][6], theta2_dev [n_aa][6][6] or
+ * NULL, doubles in device memory.  log_z is a host pointer.  The stream is the
+ * handle's stream. */
+cdz_status cdz_forward_dev(cdz_handle *h, int32_t n_aa, const char *aa,
+                           const double *theta1_dev, const double *theta2_dev,
+                           double *log_z);
+
+/* Adjoint of cdz_forward_dev: writes d(log Z)/d theta1 [n_aa][6] and
+ * d(log Z)/d theta2 [n_aa][6][6] (device doubles; theta2 grad may be NULL),
+ * each scaled by grad_logz.  Needs the forward of the same problem. */
+cdz_status cdz_backward_dev(cdz_handle *h, double grad_logz, double *dtheta1_dev,
+                            double *dtheta2_dev);
+
+/* Per-phase device times (ms) of the last call, measured with HIP events on
+ * the handle's stream: [0] forward, [1] outside + marginals, [2] sampling,
+ * [3] dominant kernel average (forward diagonal kernel), [4] launches of it. */
+cdz_status cdz_last_timings(cdz_handle *h, double *ms5);
+
+const char *cdz_status_string(cdz_status s);
+const char *cdz_last_error(const cdz_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDZ_H */

@@ -1,0 +1,175 @@
+"""ctypes binding of libcdz.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of its own; all dynamic programming runs in the HIP library.  The
+binding raises if the library is not built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcdz.so")
+
+CDZ_FP32_SCALED = 0
+CDZ_FP64 = 1
+STATUS = ["CDZ_OK", "CDZ_ERR_ARG", "CDZ_ERR_PROTEIN", "CDZ_ERR_NUMERIC", "CDZ_ERR_NOMEM",
+          "CDZ_ERR_BUDGET", "CDZ_ERR_HIP", "CDZ_ERR_STATE"]
+EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_sample",
+           "cdz_forward_dev", "cdz_backward_dev", "cdz_last_timings", "cdz_status_string",
+           "cdz_last_error"]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class cdz_problem(ctypes.Structure):
+    _fields_ = [("n_aa", ctypes.c_int32), ("aa", ctypes.c_char_p),
+                ("theta1", _dp), ("theta2", _dp)]
+
+
+class cdz_options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("mem_budget_bytes", ctypes.c_size_t),
+                ("hip_stream", ctypes.c_void_p)]
+
+
+class CdzError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS[status] if 0 <= status < len(STATUS) else status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        sig = {
+            "cdz_create": ([_dp, ctypes.POINTER(cdz_options), ctypes.POINTER(vp)], ctypes.c_int),
+            "cdz_destroy": ([vp], None),
+            "cdz_partition": ([vp, ctypes.POINTER(cdz_problem), _dp], ctypes.c_int),
+            "cdz_marginals": ([vp, ctypes.POINTER(cdz_problem), _dp, _dp, _dp, _dp, _dp], ctypes.c_int),
+            "cdz_sample": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_uint64, ctypes.c_int32,
+                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "cdz_forward_dev": ([vp, ctypes.c_int32, ctypes.c_char_p, vp, vp, _dp], ctypes.c_int),
+            "cdz_backward_dev": ([vp, ctypes.c_double, vp, vp], ctypes.c_int),
+            "cdz_last_timings": ([vp, _dp], ctypes.c_int),
+            "cdz_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "cdz_last_error": ([vp], ctypes.c_char_p),
+            "cdz_debug_logz_suffix": ([vp], ctypes.c_double),
+        }
+        for name, (args, res) in sig.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = res
+        _lib = L
+    return _lib
+
+
+def _arr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+class _Prob:
+    """Keeps the marshalled buffers alive while a call runs."""
+
+    def __init__(self, prob):
+        self.aa = prob.prot.encode()
+        self.t1 = None if prob.theta1 is None else np.ascontiguousarray(prob.theta1, np.float64)
+        self.t2 = None if prob.theta2 is None else np.ascontiguousarray(prob.theta2, np.float64)
+        self.c = cdz_problem(len(prob.prot), self.aa, _arr(self.t1), _arr(self.t2))
+
+
+class Handle:
+    def __init__(self, ptr, energy_buf):
+        self.ptr = ptr
+        self._energy = energy_buf
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                lib().cdz_destroy(self.ptr)
+        except Exception:
+            pass
+        self.ptr = None
+
+    def check(self, st: int):
+        if st != 0:
+            msg = lib().cdz_last_error(self.ptr).decode(errors="replace")
+            raise CdzError(st, msg)
+
+
+def cdz_create(energy, prec: str = "fp32", mem_budget_bytes: int = 0, stream: int = 0) -> Handle:
+    """energy: an object with .packed() (199 doubles in cdz_energy order)."""
+    buf = np.ascontiguousarray(energy.packed(), np.float64)
+    opts = cdz_options(CDZ_FP64 if prec == "fp64" else CDZ_FP32_SCALED, mem_budget_bytes,
+                       ctypes.c_void_p(stream) if stream else None)
+    out = ctypes.c_void_p()
+    st = lib().cdz_create(_arr(buf), ctypes.byref(opts), ctypes.byref(out))
+    if st != 0:
+        raise CdzError(st, "cdz_create")
+    return Handle(out, buf)
+
+
+def cdz_partition(h: Handle, prob) -> float:
+    p = _Prob(prob)
+    out = np.zeros(1)
+    h.check(lib().cdz_partition(h.ptr, ctypes.byref(p.c), _arr(out)))
+    return float(out[0])
+
+
+def cdz_marginals(h: Handle, prob) -> dict:
+    p = _Prob(prob)
+    m, n = len(prob.prot), 3 * len(prob.prot)
+    out = {"logz": np.zeros(1), "pair": np.zeros((n, n)), "base": np.zeros((n, 4)),
+           "codon": np.zeros((m, 6)), "codon_pair": np.zeros((m, 6, 6))}
+    h.check(lib().cdz_marginals(h.ptr, ctypes.byref(p.c), _arr(out["logz"]), _arr(out["pair"]),
+                                _arr(out["base"]), _arr(out["codon"]), _arr(out["codon_pair"])))
+    out["logz"] = float(out["logz"][0])
+    return out
+
+
+def cdz_sample(h: Handle, prob, seed: int, n_samples: int):
+    p = _Prob(prob)
+    m, n = len(prob.prot), 3 * len(prob.prot)
+    cod = np.zeros((n_samples, m), np.uint8)
+    pairs = np.zeros((n_samples, n), np.int32)
+    h.check(lib().cdz_sample(h.ptr, ctypes.byref(p.c), ctypes.c_uint64(seed), n_samples,
+                             cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                             pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return cod, pairs
+
+
+def cdz_forward_dev(h: Handle, aa: str, theta1_ptr: int, theta2_ptr: int) -> float:
+    out = np.zeros(1)
+    h.check(lib().cdz_forward_dev(h.ptr, len(aa), aa.encode(), ctypes.c_void_p(theta1_ptr),
+                                  ctypes.c_void_p(theta2_ptr) if theta2_ptr else None, _arr(out)))
+    return float(out[0])
+
+
+def cdz_backward_dev(h: Handle, grad_logz: float, dtheta1_ptr: int, dtheta2_ptr: int) -> None:
+    h.check(lib().cdz_backward_dev(h.ptr, float(grad_logz), ctypes.c_void_p(dtheta1_ptr),
+                                   ctypes.c_void_p(dtheta2_ptr) if dtheta2_ptr else None))
+
+
+def cdz_last_timings(h: Handle) -> np.ndarray:
+    out = np.zeros(5)
+    h.check(lib().cdz_last_timings(h.ptr, _arr(out)))
+    return out
+
+
+def cdz_status_string(st: int) -> str:
+    return lib().cdz_status_string(st).decode()
+
+
+def cdz_last_error(h: Handle) -> str:
+    return lib().cdz_last_error(h.ptr).decode(errors="replace")

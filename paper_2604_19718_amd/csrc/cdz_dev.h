@@ -1,0 +1,127 @@
+// cdz_dev.h -- device-side problem description and helpers shared by the
+// forward, outside and sampling kernels of the codon-constrained McCaskill
+// dynamic program (gfx950 / CDNA4, wave64).
+//
+// Layout.  Position p (0 <= p < n) carries the codon slot of its residue,
+// d[p] <= 6 values.  P[p] = sum_{q<p} d[q] flattens (position, slot) into a
+// state index k in [0, S).  Every DP array is an S x S row-major matrix in
+// HBM whose block (P[i].., P[j]..) of shape d[i] x d[j] holds the tensor of
+// range [i..j] over the slots of its two end positions; this is the block
+// layout of the paper's Fig. structures(b) with non-square blocks.  A row of
+// blocks is contiguous along the contraction index of the O(n) split sums, so
+// the lanes of a wavefront read consecutive addresses there.  Transposed
+// copies exist where a split runs down a column.
+//
+// Scaling.  Every entry of diagonal dl = j - i is stored as true * 2^-E[dl]
+// (one integer exponent per diagonal, chosen from the maxima of the two
+// previous diagonals); adjoint entries are stored as true * 2^(E[dl] - EZ)
+// with EZ = round(log2 Z).  All factors between diagonals are exact powers
+// of two.  The exterior loop and log Z are accumulated in FP64 with their own
+// per-position exponents.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define CDZ_NT 256      // threads per workgroup of the cell kernels
+#define CDZ_MAXLOOP 30  // bulge / interior loop size bound
+#define CDZ_NWIN 496    // (l1, l2) pairs with l1 + l2 <= 30, including (0, 0)
+
+// Boltzmann table offsets inside DevProb::tab
+#define TB_ST 0      // stack [6][6]
+#define TB_BU 36     // bulge [31]
+#define TB_IN 67     // interior [31]
+#define TB_MM 98     // mismatch [4][4][6]
+#define TB_MLAB 194  // exp(-(ml_a + ml_b))
+#define TB_MLB 195   // exp(-ml_b)
+#define TB_MLC 196   // exp(-ml_c)
+#define TB_LEN 197
+
+template <typename T>
+struct DevProb {
+  int n, m, S;
+  long long ld;
+  const int *d;            // [n]
+  const int *P;            // [n + 1]
+  const int *posOf;        // [S] position of state index k
+  const signed char *nt;   // [n][6] base of position p in slot s, -1 beyond d
+  const T *v;              // [n][6] vertex factors (exp(theta1) at middle bases)
+  const T *e;              // [n][6][6] edge factor between p and p+1
+  const double *vd, *ed;   // the same in FP64 (exterior loop)
+  const T *tab;            // Boltzmann tables, TB_* offsets
+  const T *Bhp;            // [n] hairpin factor by loop length L (mismatch excluded)
+  // forward arrays, S x S each (see header comment)
+  T *U, *Qb, *G, *F, *DI, *Qm1, *Qm1Lr, *Qm1Lt, *Qm1p, *QmX, *Qm, *Qmt;
+  int *E;                  // [n + 1] diagonal exponents
+  unsigned *maxb;          // [n + 1] float bits of max |entry| per diagonal
+  double *Z5;              // [n][6] prefix exterior partition function
+  int *G5;                 // [n]
+  double *Z3;              // [n][6] suffix exterior partition function
+  int *H3;                 // [n]
+  double *res;             // [8] results: log Z (prefix), log Z (suffix), EZ, ...
+};
+
+__device__ __forceinline__ int cdz_ptype(int x, int y) {
+  // nibble (4x + y) of this constant is the pair type, 15 = no pair:
+  // AU=0 CG=1 GC=2 UA=3 GU=4 UG=5
+  const unsigned long long PT = 0xF5F34F2FF1FF0FFFull;
+  if (x < 0 || y < 0) return -1;
+  int t = (int)((PT >> (4 * (x * 4 + y))) & 15ull);
+  return t == 15 ? -1 : t;
+}
+
+template <typename T>
+__device__ __forceinline__ T cdz_p2(int e);
+template <>
+__device__ __forceinline__ float cdz_p2<float>(int e) {
+  e = e > 127 ? 127 : e;
+  return e < -149 ? 0.0f : ldexpf(1.0f, e);
+}
+template <>
+__device__ __forceinline__ double cdz_p2<double>(int e) {
+  e = e > 1023 ? 1023 : e;
+  return e < -1074 ? 0.0 : ldexp(1.0, e);
+}
+
+// (l1, l2) of window index w: w enumerates l1 = 0..30, then l2 = 0..30-l1
+__device__ __forceinline__ void cdz_win(int w, int &l1, int &l2) {
+  int a = 0, base = 0;
+  while (base + (31 - a) <= w) {
+    base += 31 - a;
+    a++;
+  }
+  l1 = a;
+  l2 = w - base;
+}
+
+template <typename T>
+__device__ __forceinline__ T cdz_wave_sum(T x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ __forceinline__ float cdz_wave_max(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+// Sum R per-thread values over the workgroup; result in out[0..R) (LDS),
+// visible to all threads after the call.  scratch holds (NT/64) * R values.
+template <typename T, int R>
+__device__ __forceinline__ void cdz_block_sum(T (&v)[R], T *scratch, T *out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    T s = cdz_wave_sum(v[r]);
+    if (lane == 0) scratch[wv * R + r] = s;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += CDZ_NT) {
+    T s = 0;
+#pragma unroll
+    for (int w = 0; w < CDZ_NT / 64; w++) s += scratch[w * R + r];
+    out[r] = s;
+  }
+  __syncthreads();
+}

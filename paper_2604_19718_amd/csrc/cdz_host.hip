@@ -1,0 +1,403 @@
+// cdz_host.hip -- C ABI of the codon-constrained partition-function library:
+// input validation, per-position tables, device workspace, kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cdz.h"
+#include "cdz_dev.h"
+#include "cdz_internal.h"
+
+// ---------------------------------------------------------------------------
+// Genetic code: the sense codons of each residue (standard code; start and
+// stop codons are not designed, SI S3c).  Slots are the codons sorted by
+// spelling under A < C < G < U.
+// ---------------------------------------------------------------------------
+namespace {
+struct AaCodons {
+  char aa;
+  const char *codons[6];
+};
+const AaCodons kCode[20] = {
+    {'A', {"GCU", "GCC", "GCA", "GCG"}},
+    {'R', {"CGU", "CGC", "CGA", "CGG", "AGA", "AGG"}},
+    {'N', {"AAU", "AAC"}},
+    {'D', {"GAU", "GAC"}},
+    {'C', {"UGU", "UGC"}},
+    {'Q', {"CAA", "CAG"}},
+    {'E', {"GAA", "GAG"}},
+    {'G', {"GGU", "GGC", "GGA", "GGG"}},
+    {'H', {"CAU", "CAC"}},
+    {'I', {"AUU", "AUC", "AUA"}},
+    {'L', {"UUA", "UUG", "CUU", "CUC", "CUA", "CUG"}},
+    {'K', {"AAA", "AAG"}},
+    {'M', {"AUG"}},
+    {'F', {"UUU", "UUC"}},
+    {'P', {"CCU", "CCC", "CCA", "CCG"}},
+    {'S', {"UCU", "UCC", "UCA", "UCG", "AGU", "AGC"}},
+    {'T', {"ACU", "ACC", "ACA", "ACG"}},
+    {'W', {"UGG"}},
+    {'Y', {"UAU", "UAC"}},
+    {'V', {"GUU", "GUC", "GUA", "GUG"}},
+};
+
+int base_code(char c) {
+  switch (c) {
+    case 'A': return 0;
+    case 'C': return 1;
+    case 'G': return 2;
+    case 'U': return 3;
+  }
+  return -1;
+}
+
+// slots[aa][s][r] = base; count[aa]
+struct CodeTable {
+  int count[128];
+  signed char base[128][6][3];
+  CodeTable() {
+    memset(count, 0, sizeof(count));
+    memset(base, -1, sizeof(base));
+    for (const auto &row : kCode) {
+      std::vector<std::string> cs;
+      for (const char *c : row.codons)
+        if (c) cs.push_back(c);
+      std::sort(cs.begin(), cs.end(), [](const std::string &x, const std::string &y) {
+        for (int r = 0; r < 3; r++)
+          if (x[r] != y[r]) return base_code(x[r]) < base_code(y[r]);
+        return false;
+      });
+      int a = (unsigned char)row.aa;
+      count[a] = (int)cs.size();
+      for (size_t s = 0; s < cs.size(); s++)
+        for (int r = 0; r < 3; r++) base[a][s][r] = (signed char)base_code(cs[s][r]);
+    }
+  }
+};
+const CodeTable &code_table() {
+  static CodeTable t;
+  return t;
+}
+
+const char *kStatusText[] = {"ok", "invalid argument", "invalid protein letter",
+                             "non-finite input or scaling out of range", "device allocation failed",
+                             "memory budget exceeded", "HIP runtime error", "no matching forward pass"};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+cdz_status cdz_fail(cdz_handle *h, cdz_status s, const std::string &msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+#define HIPCHK(h, x)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess)                                                          \
+      return cdz_fail((h), CDZ_ERR_HIP, std::string(#x " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char *cdz_status_string(cdz_status s) {
+  int k = (int)s;
+  return (k >= 0 && k <= 7) ? kStatusText[k] : "unknown status";
+}
+
+extern "C" const char *cdz_last_error(const cdz_handle *h) { return h ? h->err.c_str() : ""; }
+
+extern "C" cdz_status cdz_create(const cdz_energy *energy, const cdz_options *opts,
+                                 cdz_handle **out) {
+  if (!energy || !out) return CDZ_ERR_ARG;
+  *out = nullptr;
+  const double *p = reinterpret_cast<const double *>(energy);
+  for (size_t k = 0; k < sizeof(cdz_energy) / sizeof(double); k++)
+    if (std::isnan(p[k]) || p[k] == -INFINITY) return CDZ_ERR_NUMERIC;
+  if (opts && opts->prec != CDZ_FP32_SCALED && opts->prec != CDZ_FP64) return CDZ_ERR_ARG;
+  cdz_handle *h = new cdz_handle();
+  h->en = *energy;
+  if (opts) h->opt = *opts;
+  else {
+    h->opt.prec = CDZ_FP32_SCALED;
+    h->opt.mem_budget_bytes = 0;
+    h->opt.hip_stream = nullptr;
+  }
+  h->stream = reinterpret_cast<hipStream_t>(h->opt.hip_stream);
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return CDZ_ERR_HIP;
+  }
+  for (auto &ev : h->ev)
+    if (hipEventCreate(&ev) != hipSuccess) {
+      delete h;
+      return CDZ_ERR_HIP;
+    }
+  *out = h;
+  return CDZ_OK;
+}
+
+extern "C" void cdz_destroy(cdz_handle *h) {
+  if (!h) return;
+  if (h->ws) (void)hipFree(h->ws);
+  for (auto &ev : h->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  delete h;
+}
+
+// ---------------------------------------------------------------------------
+// Problem tables
+// ---------------------------------------------------------------------------
+cdz_status build_tables(cdz_handle *h, int32_t n_aa, const char *aa, const double *theta1,
+                        const double *theta2, HostTables &t) {
+  if (n_aa < 1 || !aa) return cdz_fail(h, CDZ_ERR_ARG, "n_aa < 1 or aa == NULL");
+  const CodeTable &ct = code_table();
+  const int m = n_aa, n = 3 * m;
+  t.m = m;
+  t.n = n;
+  t.d.assign(n, 0);
+  t.P.assign(n + 1, 0);
+  t.nt.assign((size_t)n * 6, -1);
+  t.v.assign((size_t)n * 6, 0.0);
+  t.e.assign((size_t)n * 36, 0.0);
+  t.aa.assign(aa, aa + m);
+  for (int a = 0; a < m; a++) {
+    unsigned char c = (unsigned char)aa[a];
+    if (c >= 128 || ct.count[c] == 0)
+      return cdz_fail(h, CDZ_ERR_PROTEIN, std::string("invalid residue letter at ") + std::to_string(a));
+    const int cnt = ct.count[c];
+    for (int s = 0; s < cnt; s++) {
+      if (theta1 && !std::isfinite(theta1[a * 6 + s]))
+        return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite theta1");
+      if (theta2 && a >= 1)
+        for (int s0 = 0; s0 < ct.count[(unsigned char)aa[a - 1]]; s0++)
+          if (!std::isfinite(theta2[(a * 6 + s0) * 6 + s]))
+            return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite theta2");
+    }
+    for (int r = 0; r < 3; r++) {
+      const int p = 3 * a + r;
+      t.d[p] = cnt;
+      for (int s = 0; s < cnt; s++) {
+        t.nt[p * 6 + s] = ct.base[c][s][r];
+        t.v[p * 6 + s] = (r == 1 && theta1) ? std::exp(theta1[a * 6 + s]) : 1.0;
+      }
+    }
+  }
+  for (int p = 0; p < n; p++) t.P[p + 1] = t.P[p] + t.d[p];
+  t.S = t.P[n];
+  t.posOf.resize(t.S);
+  for (int p = 0; p < n; p++)
+    for (int k = t.P[p]; k < t.P[p + 1]; k++) t.posOf[k] = p;
+  for (int p = 0; p + 1 < n; p++)
+    for (int s = 0; s < t.d[p]; s++)
+      for (int u = 0; u < t.d[p + 1]; u++) {
+        double w;
+        if (p % 3 != 2) w = (s == u) ? 1.0 : 0.0;  // inside a codon: same slot
+        else w = theta2 ? std::exp(theta2[((p / 3 + 1) * 6 + s) * 6 + u]) : 1.0;
+        t.e[p * 36 + s * 6 + u] = w;
+      }
+  const cdz_energy &E = h->en;
+  t.tab.assign(TB_LEN, 0.0);
+  for (int k = 0; k < 36; k++) t.tab[TB_ST + k] = std::exp(-E.stack[k / 6][k % 6]);
+  for (int L = 0; L <= 30; L++) {
+    t.tab[TB_BU + L] = std::exp(-E.bulge[L]);
+    t.tab[TB_IN + L] = std::exp(-E.interior[L]);
+  }
+  for (int x = 0; x < 4; x++)
+    for (int y = 0; y < 4; y++)
+      for (int q = 0; q < 6; q++) t.tab[TB_MM + x * 24 + y * 6 + q] = std::exp(-E.mismatch[x][y][q]);
+  t.tab[TB_MLAB] = std::exp(-(E.ml_a + E.ml_b));
+  t.tab[TB_MLB] = std::exp(-E.ml_b);
+  t.tab[TB_MLC] = std::exp(-E.ml_c);
+  t.Bhp.assign(n, 0.0);
+  for (int L = 3; L < n; L++)
+    t.Bhp[L] = L <= 30 ? std::exp(-E.hairpin[L])
+                       : std::exp(-(E.hairpin[30] + E.extrap * std::log((double)L / 30.0)));
+  // key of the problem, to reuse the forward pass
+  uint64_t hsh = 1469598103934665603ull;
+  auto mix = [&](const void *p, size_t nb) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t k = 0; k < nb; k++) hsh = (hsh ^ b[k]) * 1099511628211ull;
+  };
+  mix(aa, m);
+  mix(t.v.data(), t.v.size() * 8);
+  mix(t.e.data(), t.e.size() * 8);
+  int prec = (int)h->opt.prec;
+  mix(&prec, sizeof(prec));
+  t.key = hsh;
+  return CDZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace: one device allocation carved into tables and S x S arrays
+// ---------------------------------------------------------------------------
+namespace {
+struct Carver {
+  size_t off = 0;
+  template <typename X>
+  X *take(char *base, size_t count) {
+    off = (off + 255) / 256 * 256;
+    X *p = base ? reinterpret_cast<X *>(base + off) : nullptr;
+    off += count * sizeof(X);
+    return p;
+  }
+};
+}  // namespace
+
+template <typename T>
+static size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool adjoint) {
+  Carver c;
+  const int n = t.n, S = t.S;
+  const long long ld = ((long long)S + 31) / 32 * 32;
+  const size_t S2 = (size_t)ld * ld;
+  D.n = n;
+  D.m = t.m;
+  D.S = S;
+  D.ld = ld;
+  D.d = c.take<int>(base, n);
+  D.P = c.take<int>(base, n + 1);
+  D.posOf = c.take<int>(base, S);
+  D.nt = c.take<signed char>(base, (size_t)n * 6);
+  D.v = c.take<T>(base, (size_t)n * 6);
+  D.e = c.take<T>(base, (size_t)n * 36);
+  D.vd = c.take<double>(base, (size_t)n * 6);
+  D.ed = c.take<double>(base, (size_t)n * 36);
+  D.tab = c.take<T>(base, TB_LEN);
+  D.Bhp = c.take<T>(base, n);
+  D.E = c.take<int>(base, n + 1);
+  D.maxb = c.take<unsigned>(base, n + 1);
+  D.Z5 = c.take<double>(base, (size_t)n * 6);
+  D.G5 = c.take<int>(base, n);
+  D.Z3 = c.take<double>(base, (size_t)n * 6);
+  D.H3 = c.take<int>(base, n);
+  D.res = c.take<double>(base, 8);
+  T **arrs[] = {&D.U, &D.Qb, &D.G, &D.F, &D.DI, &D.Qm1, &D.Qm1Lr, &D.Qm1Lt,
+                &D.Qm1p, &D.QmX, &D.Qm, &D.Qmt};
+  for (T **a : arrs) *a = c.take<T>(base, S2);
+  if (adjoint) adj_carve<T>(c.off, base, t, A, S2);
+  return c.off + 256;
+}
+
+template <typename T>
+static cdz_status upload(cdz_handle *h, const HostTables &t, DevProb<T> &D) {
+  std::vector<T> v(t.v.begin(), t.v.end()), e(t.e.begin(), t.e.end()), tab(t.tab.begin(), t.tab.end()),
+      bhp(t.Bhp.begin(), t.Bhp.end());
+  hipStream_t st = h->stream;
+  HIPCHK(h, hipMemcpyAsync((void *)D.d, t.d.data(), t.n * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync((void *)D.P, t.P.data(), (t.n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync((void *)D.posOf, t.posOf.data(), t.S * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync((void *)D.nt, t.nt.data(), t.nt.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync((void *)D.v, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync((void *)D.e, e.data(), e.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync((void *)D.vd, t.v.data(), t.v.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync((void *)D.ed, t.e.data(), t.e.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync((void *)D.tab, tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync((void *)D.Bhp, bhp.data(), bhp.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  // the staging vectors must outlive the copies
+  HIPCHK(h, hipStreamSynchronize(st));
+  return CDZ_OK;
+}
+
+template <typename T>
+__global__ void cdz_fwd_diag(DevProb<T> D, int dl);
+
+template <typename T>
+static size_t fwd_shmem(int n) {
+  return ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 72 + 36 + 72 + 36 + 36) * sizeof(T);
+}
+
+template <typename T>
+static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
+  const int n = D.n;
+  hipStream_t st = h->stream;
+  HIPCHK(h, hipMemsetAsync(D.maxb, 0, (n + 1) * sizeof(unsigned), st));
+  const size_t shm = fwd_shmem<T>(n);
+  HIPCHK(h, hipEventRecord(h->ev[0], st));
+  for (int dl = 0; dl <= n; dl++) {
+    const int ncell = n - dl > 0 ? n - dl : 0;
+    hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(ncell + 1), dim3(CDZ_NT), shm, st, D, dl);
+  }
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipEventRecord(h->ev[1], st));
+  double res[8];
+  HIPCHK(h, hipMemcpyAsync(res, D.res, sizeof(res), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  float ms = 0;
+  HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+  h->times[0] = ms;
+  h->times[3] = ms / (n + 1);
+  h->times[4] = n + 1;
+  if (!std::isfinite(res[0]) || !std::isfinite(res[1]))
+    return cdz_fail(h, CDZ_ERR_NUMERIC, "log Z not finite (scaling out of range)");
+  h->logz = res[0];
+  h->logz_suffix = res[1];
+  h->EZ = res[2];
+  return CDZ_OK;
+}
+
+template <typename T>
+static cdz_status forward_impl(cdz_handle *h, const HostTables &t, bool adjoint) {
+  DevProb<T> D;
+  DevAdj<T> A;
+  memset(&D, 0, sizeof(D));
+  memset(&A, 0, sizeof(A));
+  const size_t need = carve<T>(nullptr, t, D, A, adjoint);
+  if (h->opt.mem_budget_bytes && need > h->opt.mem_budget_bytes)
+    return cdz_fail(h, CDZ_ERR_BUDGET, "workspace of " + std::to_string(need) + " bytes exceeds the budget");
+  if (need > h->ws_bytes) {
+    if (h->ws) HIPCHK(h, hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+    if (hipMalloc(&h->ws, need) != hipSuccess) {
+      h->ws = nullptr;
+      (void)hipGetLastError();
+      return cdz_fail(h, CDZ_ERR_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+    }
+    h->ws_bytes = need;
+  }
+  carve<T>((char *)h->ws, t, D, A, adjoint);
+  cdz_status s = upload<T>(h, t, D);
+  if (s != CDZ_OK) return s;
+  s = launch_forward<T>(h, D);
+  if (s != CDZ_OK) return s;
+  store_dev(h, D, A);
+  return CDZ_OK;
+}
+
+cdz_status ensure_forward(cdz_handle *h, const HostTables &t, bool adjoint) {
+  if (h->have_fwd && h->fwd_key == t.key && (!adjoint || h->fwd_adjoint)) return CDZ_OK;
+  h->have_fwd = false;
+  cdz_status s = h->opt.prec == CDZ_FP64 ? forward_impl<double>(h, t, adjoint)
+                                         : forward_impl<float>(h, t, adjoint);
+  if (s != CDZ_OK) return s;
+  h->have_fwd = true;
+  h->fwd_key = t.key;
+  h->fwd_adjoint = adjoint;
+  h->tables = t;
+  return CDZ_OK;
+}
+
+extern "C" cdz_status cdz_partition(cdz_handle *h, const cdz_problem *prob, double *log_z) {
+  if (!h || !prob || !log_z) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
+  HostTables t;
+  cdz_status s = build_tables(h, prob->n_aa, prob->aa, prob->theta1, prob->theta2, t);
+  if (s != CDZ_OK) return s;
+  s = ensure_forward(h, t, false);
+  if (s != CDZ_OK) return s;
+  *log_z = h->logz;
+  return CDZ_OK;
+}
+
+extern "C" cdz_status cdz_last_timings(cdz_handle *h, double *ms5) {
+  if (!h || !ms5) return CDZ_ERR_ARG;
+  for (int k = 0; k < 5; k++) ms5[k] = h->times[k];
+  return CDZ_OK;
+}
+
+// debug/test hook: log Z computed from the suffix exterior pass of the last forward
+extern "C" double cdz_debug_logz_suffix(const cdz_handle *h) { return h ? h->logz_suffix : NAN; }

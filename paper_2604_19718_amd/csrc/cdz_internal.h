@@ -1,0 +1,75 @@
+// cdz_internal.h -- host-side state shared by the translation units of the
+// library (handle, per-problem tables, adjoint workspace description).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cdz.h"
+#include "cdz_dev.h"
+
+// Per-problem host tables (FP64), built before any device work.
+struct HostTables {
+  int m = 0, n = 0, S = 0;
+  std::string aa;
+  std::vector<int> d, P, posOf;
+  std::vector<signed char> nt;  // [n][6]
+  std::vector<double> v, e;     // [n][6], [n][6][6]
+  std::vector<double> tab, Bhp;
+  uint64_t key = 0;
+};
+
+// Adjoint (outside) workspace, S x S arrays in the same block layout.
+//   Qbb, Qm1b, Qm1pb, QmXb, Qmb : adjoints of the forward arrays
+//   QmXbt                       : QmXb transposed (column gathers)
+//   DIb                         : adjoint of DI (block of the inner pair's neighbours)
+//   Gb, Fb                      : outer-edge-dressed adjoints of a cell's loop sums,
+//                                 at block (i+1, j-1) of the closing pair (i, j)
+//   Ub                          : adjoint of the unpaired runs
+//   eta                         : [n][6][6] FP64 edge marginals (x Z)
+template <typename T>
+struct DevAdj {
+  T *Qbb, *Qm1b, *Qm1pb, *QmXb, *QmXbt, *Qmb, *DIb, *Gb, *Fb, *Ub;
+  double *eta;
+  double *out;  // [16] scalars
+};
+
+template <typename T>
+void adj_carve(size_t &off, char *base, const HostTables &t, DevAdj<T> &A, size_t S2);
+
+struct cdz_handle {
+  cdz_energy en;
+  cdz_options opt;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipEvent_t ev[8] = {};
+  double times[5] = {0, 0, 0, 0, 0};
+  // last forward pass
+  bool have_fwd = false, fwd_adjoint = false;
+  uint64_t fwd_key = 0;
+  double logz = 0, logz_suffix = 0, EZ = 0;
+  HostTables tables;
+  DevProb<float> pf;
+  DevProb<double> pd;
+  DevAdj<float> af;
+  DevAdj<double> ad;
+};
+
+inline void store_dev(cdz_handle *h, const DevProb<float> &D, const DevAdj<float> &A) {
+  h->pf = D;
+  h->af = A;
+}
+inline void store_dev(cdz_handle *h, const DevProb<double> &D, const DevAdj<double> &A) {
+  h->pd = D;
+  h->ad = A;
+}
+
+cdz_status cdz_fail(cdz_handle *h, cdz_status s, const std::string &msg);
+cdz_status build_tables(cdz_handle *h, int32_t n_aa, const char *aa, const double *theta1,
+                        const double *theta2, HostTables &t);
+cdz_status ensure_forward(cdz_handle *h, const HostTables &t, bool adjoint);
