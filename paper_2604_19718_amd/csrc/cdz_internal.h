@@ -27,13 +27,18 @@ struct HostTables {
 //   DIb                         : adjoint of DI (block of the inner pair's neighbours)
 //   Gb, Fb                      : outer-edge-dressed adjoints of a cell's loop sums,
 //                                 at block (i+1, j-1) of the closing pair (i, j)
-//   Ub                          : adjoint of the unpaired runs
-//   eta                         : [n][6][6] FP64 edge marginals (x Z)
+//   Qm1Lb                       : adjoint of Qm1L (block (i-1, j))
+//   UbL, UbR                    : run adjoints pushed by enclosing loops, by
+//                                 row (left runs, hairpins) and by column
+//                                 (right runs), so no two cells of one
+//                                 diagonal write the same element
+//   Ub                          : total adjoint of the unpaired runs
 template <typename T>
 struct DevAdj {
-  T *Qbb, *Qm1b, *Qm1pb, *QmXb, *QmXbt, *Qmb, *DIb, *Gb, *Fb, *Ub;
-  double *eta;
-  double *out;  // [16] scalars
+  T *Qbb, *Qm1b, *Qm1pb, *QmXb, *QmXbt, *Qmb, *Qm1Lb, *DIb, *Gb, *Fb, *Ub, *UbL, *UbR;
+  double *eta;   // [n][6][6] edge marginals times Z / 2^EZ
+  double *pair;  // [n][n] pair probabilities (upper triangle)
+  double *out;   // [16] scalars
 };
 
 template <typename T>

@@ -1,4 +1,22 @@
-// cdz_out.hip -- outside (adjoint) pass; workspace carving for now.
+// cdz_out.hip -- outside pass: the hand-written adjoint of the forward
+// recursions (reverse mode, pull form), then the marginals.
+//
+// The adjoint X' of a forward entry X is dZ/dX.  Cells are processed in
+// decreasing anti-diagonal order, one launch per diagonal, one workgroup per
+// cell; every adjoint of a cell is gathered from cells on larger diagonals
+// (no atomics).  Stored adjoints are true * 2^(E[dl] - EZ); with that choice
+// every adjoint term carries exactly the power-of-two factor of the forward
+// term it reverses.
+//
+// Marginals (Section 2c of the paper): every derivation uses each backbone
+// edge factor e_p exactly once, so eta_p(s,t) = e_p(s,t) dZ/de_p(s,t) / Z is
+// the joint probability of slots (s, t) at positions (p, p+1).  Codon
+// marginals are eta at the edge inside a codon, codon-pair marginals eta at
+// the edge between two codons (equal to d log Z / d theta1 and d theta2),
+// and pair probabilities are sum Qb * Qb' / Z.
+#include <cmath>
+#include <cstring>
+
 #include "cdz_internal.h"
 
 template <typename T>
@@ -9,10 +27,869 @@ void adj_carve(size_t &off, char *base, const HostTables &t, DevAdj<T> &A, size_
     off += bytes;
     return p;
   };
-  T **arrs[] = {&A.Qbb, &A.Qm1b, &A.Qm1pb, &A.QmXb, &A.QmXbt, &A.Qmb, &A.DIb, &A.Gb, &A.Fb, &A.Ub};
+  T **arrs[] = {&A.Qbb, &A.Qm1b, &A.Qm1pb, &A.QmXb, &A.QmXbt, &A.Qmb, &A.Qm1Lb,
+                &A.DIb, &A.Gb, &A.Fb, &A.Ub, &A.UbL, &A.UbR};
   for (T **a : arrs) *a = reinterpret_cast<T *>(take(S2 * sizeof(T)));
   A.eta = reinterpret_cast<double *>(take((size_t)t.n * 36 * sizeof(double)));
+  A.pair = reinterpret_cast<double *>(take((size_t)t.n * t.n * sizeof(double)));
   A.out = reinterpret_cast<double *>(take(16 * sizeof(double)));
 }
 template void adj_carve<float>(size_t &, char *, const HostTables &, DevAdj<float> &, size_t);
 template void adj_carve<double>(size_t &, char *, const HostTables &, DevAdj<double> &, size_t);
+
+#define NRUN 29  // run lengths 1..29 inside an interior loop
+
+template <typename T>
+static size_t out_shmem(int n) {
+  return ((size_t)(n + 1) * 4 + 15) / 16 * 16 +
+         (size_t)((CDZ_NT / 64) * 72 + 72 + 72 + 6 * 36 + 2 * NRUN * 36) * sizeof(T);
+}
+
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A, int dl) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = D.n, tid = threadIdx.x;
+  const long long ld = D.ld;
+  int *sE = reinterpret_cast<int *>(smem_raw);
+  T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
+  T *sAcc = red + (CDZ_NT / 64) * 72;  // Qm' (36) | Qm1L' (36)
+  T *sW = sAcc + 72;                   // DI' (36) | bulge part of Qb' (36)
+  T *sQm1pb = sW + 72, *sQm1Lb = sQm1pb + 36, *sQm1b = sQm1Lb + 36;
+  T *sQbb = sQm1b + 36, *sGb = sQbb + 36, *sFb = sGb + 36;
+  T *sT = sFb + 36, *sV = sT + NRUN * 36;
+  for (int k = tid; k < n; k += CDZ_NT) sE[k] = D.E[k];
+  __syncthreads();
+  const int EZ = (int)D.res[2];
+  const int i = blockIdx.x, j = i + dl;
+  const int di = D.d[i], dj = D.d[j], Pi = D.P[i], Pj = D.P[j];
+  const T *tab = D.tab;
+
+  if (dl >= 4) {
+    // ---- split gathers: Qm'[i][j] along row i, Qm1L'[i][j] down column j
+    {
+      T acc[72];
+#pragma unroll
+      for (int r = 0; r < 72; r++) acc[r] = 0;
+      if (j + 5 <= n - 1) {
+        const int K0 = D.P[j + 5], K1 = D.P[n];
+        for (int k = K0 + tid; k < K1; k += CDZ_NT) {
+          const int p = D.posOf[k];
+          const T f = cdz_p2<T>(sE[dl] + sE[p - j - 1] - sE[p - i]);
+          T a[6], b[6];
+#pragma unroll
+          for (int s = 0; s < 6; s++) a[s] = s < di ? A.QmXb[(Pi + s) * ld + k] * f : T(0);
+#pragma unroll
+          for (int t = 0; t < 6; t++) b[t] = t < dj ? D.Qm1Lr[(Pj + t) * ld + k] : T(0);
+#pragma unroll
+          for (int s = 0; s < 6; s++)
+#pragma unroll
+            for (int t = 0; t < 6; t++) acc[s * 6 + t] = fma(a[s], b[t], acc[s * 6 + t]);
+        }
+      }
+      if (i >= 5) {
+        const int dm1 = D.d[i - 1], Pm1 = D.P[i - 1], K1 = D.P[i - 4];
+        for (int k = tid; k < K1; k += CDZ_NT) {
+          const int p = D.posOf[k];
+          const T f = cdz_p2<T>(sE[i - 1 - p] + sE[dl] - sE[j - p]);
+          T a[6], c[6];
+#pragma unroll
+          for (int b = 0; b < 6; b++) a[b] = b < dm1 ? D.Qmt[(Pm1 + b) * ld + k] * f : T(0);
+#pragma unroll
+          for (int s2 = 0; s2 < 6; s2++) c[s2] = s2 < dj ? A.QmXbt[(Pj + s2) * ld + k] : T(0);
+#pragma unroll
+          for (int b = 0; b < 6; b++)
+#pragma unroll
+            for (int s2 = 0; s2 < 6; s2++) acc[36 + b * 6 + s2] = fma(a[b], c[s2], acc[36 + b * 6 + s2]);
+        }
+      }
+      cdz_block_sum<T, 72>(acc, red, sAcc);
+    }
+    // ---- window gathers: DI'[i][j] from enclosing interior loops, and the
+    //      bulge part of Qb'[i][j] from enclosing bulges
+    {
+      T w[72];
+#pragma unroll
+      for (int r = 0; r < 72; r++) w[r] = 0;
+      for (int win = 1 + tid; win < CDZ_NWIN; win += CDZ_NT) {
+        int l1, l2;
+        cdz_win(win, l1, l2);
+        if (l1 >= 1 && l2 >= 1) {
+          const int I = i - l1 - 1, J = j + l2 + 1;
+          if (I < 0 || J > n - 1) continue;
+          const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[dl] + sE[l2 - 1] - sE[dl + l1 + l2 + 2]);
+          const int pa = i - l1, da = D.d[pa], Pa = D.P[pa];
+          const int pz = j + l2, dz = D.d[pz], Pz = D.P[pz];
+          const int db = D.d[i - 1], Pb = D.P[i - 1], dc = D.d[j + 1], Pc = D.P[j + 1];
+          T m[36];  // m(b, dd) = sum_a U[pa][i-1](a,b) Fb[pa][pz](a,dd)
+#pragma unroll
+          for (int b = 0; b < 6; b++)
+#pragma unroll
+            for (int dd = 0; dd < 6; dd++) {
+              T s = 0;
+              if (b < db && dd < dz)
+                for (int a = 0; a < da; a++) s += D.U[(Pa + a) * ld + Pb + b] * A.Fb[(Pa + a) * ld + Pz + dd];
+              m[b * 6 + dd] = s;
+            }
+#pragma unroll
+          for (int c = 0; c < 6; c++) {
+            if (c >= dc) continue;
+            T ur[6];
+#pragma unroll
+            for (int dd = 0; dd < 6; dd++) ur[dd] = dd < dz ? D.U[(Pc + c) * ld + Pz + dd] : T(0);
+#pragma unroll
+            for (int b = 0; b < 6; b++) {
+              T s = 0;
+#pragma unroll
+              for (int dd = 0; dd < 6; dd++) s += m[b * 6 + dd] * ur[dd];
+              w[b * 6 + c] += f * s;
+            }
+          }
+        } else if (l2 == 0) {
+          // enclosing left bulge (i-l1-1, j+1): run i-l1..i-1, inner pair (i, j)
+          if (i - l1 - 1 < 0 || j + 1 > n - 1) continue;
+          const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[dl] - sE[dl + l1 + 2]);
+          const int pa = i - l1, da = D.d[pa], Pa = D.P[pa], db = D.d[i - 1], Pb = D.P[i - 1];
+          T m[36];  // m(a, x) = sum_b U[pa][i-1](a,b) e_{i-1}(b,x)
+#pragma unroll
+          for (int a = 0; a < 6; a++)
+#pragma unroll
+            for (int x = 0; x < 6; x++) {
+              T s = 0;
+              if (a < da && x < di)
+                for (int b = 0; b < db; b++) s += D.U[(Pa + a) * ld + Pb + b] * D.e[(i - 1) * 36 + b * 6 + x];
+              m[a * 6 + x] = s;
+            }
+#pragma unroll
+          for (int y = 0; y < 6; y++) {
+            if (y >= dj) continue;
+            T g[6];
+#pragma unroll
+            for (int a = 0; a < 6; a++) g[a] = a < da ? A.Gb[(Pa + a) * ld + Pj + y] : T(0);
+#pragma unroll
+            for (int x = 0; x < 6; x++) {
+              T s = 0;
+#pragma unroll
+              for (int a = 0; a < 6; a++) s += m[a * 6 + x] * g[a];
+              w[36 + x * 6 + y] += f * s;
+            }
+          }
+        } else {
+          // enclosing right bulge (i-1, j+l2+1): inner pair (i, j), run j+1..j+l2
+          if (i < 1 || j + l2 + 1 > n - 1) continue;
+          const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[dl] + sE[l2 - 1] - sE[dl + l2 + 2]);
+          const int pz = j + l2, dz = D.d[pz], Pz = D.P[pz], dc = D.d[j + 1], Pc = D.P[j + 1];
+          T m[36];  // m(y, dd) = sum_c e_j(y,c) U[j+1][pz](c,dd)
+#pragma unroll
+          for (int y = 0; y < 6; y++)
+#pragma unroll
+            for (int dd = 0; dd < 6; dd++) {
+              T s = 0;
+              if (y < dj && dd < dz)
+                for (int c = 0; c < dc; c++) s += D.e[j * 36 + y * 6 + c] * D.U[(Pc + c) * ld + Pz + dd];
+              m[y * 6 + dd] = s;
+            }
+#pragma unroll
+          for (int x = 0; x < 6; x++) {
+            if (x >= di) continue;
+            T g[6];
+#pragma unroll
+            for (int dd = 0; dd < 6; dd++) g[dd] = dd < dz ? A.Gb[(Pi + x) * ld + Pz + dd] : T(0);
+#pragma unroll
+            for (int y = 0; y < 6; y++) {
+              T s = 0;
+#pragma unroll
+              for (int dd = 0; dd < 6; dd++) s += g[dd] * m[y * 6 + dd];
+              w[36 + x * 6 + y] += f * s;
+            }
+          }
+        }
+      }
+      cdz_block_sum<T, 72>(w, red, sW);
+    }
+    const int s = tid / 6, t = tid % 6;
+    // ---- Qm', QmX', Qm1p', Qm1L', DI'
+    if (tid < 36) {
+      T qlb = 0;
+      if (i >= 1 && s < D.d[i - 1] && t < dj) {
+        qlb = sAcc[36 + tid];
+        A.Qm1Lb[(D.P[i - 1] + s) * ld + Pj + t] = qlb;
+      }
+      sQm1Lb[tid] = qlb;
+      if (i >= 1 && j + 1 <= n - 1 && s < D.d[i - 1] && t < D.d[j + 1])
+        A.DIb[(D.P[i - 1] + s) * ld + D.P[j + 1] + t] = sW[tid];
+      T qpb = 0;
+      if (s < di && t < dj) {
+        const T qmb = sAcc[tid];
+        T qxb = qmb;
+        if (i >= 1 && j + 1 <= n - 1)
+          qxb += tab[TB_MLAB] * cdz_p2<T>(sE[dl] - sE[dl + 2]) * A.Gb[(Pi + s) * ld + Pj + t];
+        qpb = qmb;
+        if (i >= 1) {
+          const int dp = D.d[i - 1], Pp = D.P[i - 1];
+          T a = 0;
+          for (int q = 0; q < dp; q++)
+            a += A.Qm1pb[(Pp + q) * ld + Pj + t] * D.v[(i - 1) * 6 + q] * D.e[(i - 1) * 36 + q * 6 + s];
+          qpb += tab[TB_MLC] * cdz_p2<T>(sE[dl] - sE[dl + 1]) * a;
+        }
+        const long long o = (Pi + s) * ld + Pj + t;
+        A.Qmb[o] = qmb;
+        A.QmXb[o] = qxb;
+        A.QmXbt[(Pj + t) * ld + Pi + s] = qxb;
+        A.Qm1pb[o] = qpb;
+      }
+      sQm1pb[tid] = qpb;
+    }
+    __syncthreads();
+    // ---- Qm1'
+    if (tid < 36) {
+      T q1b = 0;
+      if (s < di && t < dj) {
+        q1b = sQm1pb[tid];
+        if (i >= 1)
+          for (int b = 0; b < D.d[i - 1]; b++) q1b += D.e[(i - 1) * 36 + b * 6 + s] * sQm1Lb[b * 6 + t];
+        if (j + 1 <= n - 1) {
+          const int dq = D.d[j + 1], Pq = D.P[j + 1];
+          T a = 0;
+          for (int q = 0; q < dq; q++)
+            a += A.Qm1b[(Pi + s) * ld + Pq + q] * D.v[(j + 1) * 6 + q] * D.e[j * 36 + t * 6 + q];
+          q1b += tab[TB_MLC] * cdz_p2<T>(sE[dl] - sE[dl + 1]) * a;
+        }
+        A.Qm1b[(Pi + s) * ld + Pj + t] = q1b;
+      }
+      sQm1b[tid] = q1b;
+    }
+    __syncthreads();
+    // ---- Qb'
+    if (tid < 36) {
+      const int x = s, y = t;
+      T qbb = 0;
+      if (x < di && y < dj) {
+        qbb = sQm1b[tid] * tab[TB_MLB] + sW[36 + tid];
+        const int nx = D.nt[i * 6 + x], ny = D.nt[j * 6 + y];
+        const int tin = cdz_ptype(ny, nx);  // inner pair read in loop order (j, i)
+        if (i >= 1 && j + 1 <= n - 1 && tin >= 0) {
+          for (int b = 0; b < D.d[i - 1]; b++) {
+            const T eb = D.e[(i - 1) * 36 + b * 6 + x];
+            if (eb == T(0)) continue;
+            const int nb = D.nt[(i - 1) * 6 + b];
+            for (int c = 0; c < D.d[j + 1]; c++) {
+              const int nc = D.nt[(j + 1) * 6 + c];
+              qbb += sW[b * 6 + c] * eb * D.e[j * 36 + y * 6 + c] * tab[TB_MM + nc * 24 + nb * 6 + tin];
+            }
+          }
+        }
+        {  // exterior loop: prefix before i, suffix after j (FP64)
+          double zl = 1.0;
+          int G = 0;
+          if (i >= 1) {
+            zl = 0;
+            for (int q = 0; q < D.d[i - 1]; q++) zl += D.Z5[(i - 1) * 6 + q] * D.ed[(i - 1) * 36 + q * 6 + x];
+            G = D.G5[i - 1];
+          }
+          qbb += (T)(zl * D.Z3[j * 6 + y] * ldexp(1.0, G + D.H3[j] + sE[dl] - EZ));
+        }
+        const int txy = cdz_ptype(nx, ny);
+        if (i >= 1 && j + 1 <= n - 1 && txy >= 0) {  // stacked under (i-1, j+1)
+          const T f2 = cdz_p2<T>(sE[dl] - sE[dl + 2]);
+          const int Pp = D.P[i - 1], Pq = D.P[j + 1];
+          for (int q = 0; q < D.d[i - 1]; q++) {
+            const T eq = D.e[(i - 1) * 36 + q * 6 + x];
+            if (eq == T(0)) continue;
+            for (int r = 0; r < D.d[j + 1]; r++) {
+              const int to = cdz_ptype(D.nt[(i - 1) * 6 + q], D.nt[(j + 1) * 6 + r]);
+              if (to < 0) continue;
+              const T ac = A.Qbb[(Pp + q) * ld + Pq + r] * D.v[(i - 1) * 6 + q] * D.v[(j + 1) * 6 + r];
+              qbb += ac * eq * D.e[j * 36 + y * 6 + r] * tab[TB_ST + to * 6 + txy] * f2;
+            }
+          }
+        }
+        A.Qbb[(Pi + x) * ld + Pj + y] = qbb;
+      }
+      sQbb[tid] = qbb;
+    }
+    __syncthreads();
+    // ---- outer-edge-dressed adjoints of this cell's loop sums, block (i+1, j-1)
+    const int d1 = D.d[i + 1], dm = D.d[j - 1], P1 = D.P[i + 1], Pm = D.P[j - 1];
+    if (tid < 36) {
+      const int a = s, dd = t;
+      T gb = 0, fb = 0;
+      if (a < d1 && dd < dm) {
+        const int na = D.nt[(i + 1) * 6 + a], nd = D.nt[(j - 1) * 6 + dd];
+        for (int q = 0; q < di; q++) {
+          const T ea = D.e[i * 36 + q * 6 + a];
+          if (ea == T(0)) continue;
+          for (int r = 0; r < dj; r++) {
+            const int to = cdz_ptype(D.nt[i * 6 + q], D.nt[j * 6 + r]);
+            if (to < 0) continue;
+            const T w = sQbb[q * 6 + r] * D.v[i * 6 + q] * D.v[j * 6 + r] * ea * D.e[(j - 1) * 36 + dd * 6 + r];
+            gb += w;
+            fb += w * tab[TB_MM + na * 24 + nd * 6 + to];
+          }
+        }
+        A.Gb[(P1 + a) * ld + Pm + dd] = gb;
+        A.Fb[(P1 + a) * ld + Pm + dd] = fb;
+      }
+      sGb[tid] = gb;
+      sFb[tid] = fb;
+    }
+    __syncthreads();
+    // ---- push the adjoints of this cell's loop runs: left runs (and
+    //      hairpin) into row i+1 of UbL, right runs into column j-1 of UbR
+    for (int idx = tid; idx < 2 * NRUN * 36; idx += CDZ_NT) {
+      const int side = idx / (NRUN * 36), rem = idx % (NRUN * 36), L = rem / 36 + 1, q = rem % 36;
+      const int r0 = q / 6, r1 = q % 6;
+      T val = 0;
+      if (side == 0) {  // T_L(a, c) = sum_dd Fb(a,dd) U[j-L][j-1](c,dd)
+        const int pc = j - L;
+        if (pc > i + 1 && r0 < d1 && r1 < D.d[pc]) {
+          const int Pc = D.P[pc];
+          for (int dd = 0; dd < dm; dd++) val += sFb[r0 * 6 + dd] * D.U[(Pc + r1) * ld + Pm + dd];
+        }
+        sT[rem] = val;
+      } else {  // V_L(b, dd) = sum_a U[i+1][i+L](a,b) Fb(a,dd)
+        const int pb = i + L;
+        if (pb < j - 1 && r0 < D.d[pb] && r1 < dm) {
+          const int Pb = D.P[pb];
+          for (int a = 0; a < d1; a++) val += D.U[(P1 + a) * ld + Pb + r0] * sFb[a * 6 + r1];
+        }
+        sV[rem] = val;
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 2 * NRUN * 36; idx += CDZ_NT) {
+      const int side = idx / (NRUN * 36), rem = idx % (NRUN * 36), L = rem / 36 + 1, q = rem % 36;
+      const int r0 = q / 6, r1 = q % 6;
+      if (side == 0) {
+        // left run (i+1 .. i+L), l1 = L, inner pair starts at k = i+L+1
+        const int l1 = L, pe = i + l1, k = pe + 1;
+        if (k + 4 > j - 1 || r0 >= d1 || r1 >= D.d[pe]) continue;
+        const int a = r0, b = r1, Pb = D.P[pe];
+        T acc = 0;
+        for (int l2 = 1; l1 + l2 <= CDZ_MAXLOOP; l2++) {
+          const int l = j - 1 - l2;
+          if (l - k < 4) break;
+          const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[l - k] + sE[l2 - 1] - sE[dl]);
+          const int dc = D.d[l + 1], Pc = D.P[l + 1];
+          T sm = 0;
+          for (int c = 0; c < dc; c++) sm += sT[(l2 - 1) * 36 + a * 6 + c] * D.DI[(Pb + b) * ld + Pc + c];
+          acc += f * sm;
+        }
+        {  // left bulge with inner pair (k, j-1)
+          const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[j - 1 - k] - sE[dl]);
+          const int dk = D.d[k], Pk = D.P[k];
+          T sm = 0;
+          for (int x = 0; x < dk; x++) {
+            const T ex = D.e[(k - 1) * 36 + b * 6 + x];
+            if (ex == T(0)) continue;
+            for (int y = 0; y < dm; y++) sm += sGb[a * 6 + y] * ex * D.Qb[(Pk + x) * ld + Pm + y];
+          }
+          acc += f * sm;
+        }
+        A.UbL[(P1 + a) * ld + Pb + b] += acc;
+      } else {
+        // right run (j-L .. j-1), l2 = L, inner pair ends at l = j-L-1
+        const int l2 = L, ps = j - l2, l = ps - 1;
+        if (l - (i + 1) < 4 || r0 >= D.d[ps] || r1 >= dm) continue;
+        const int c = r0, dd = r1, Pc = D.P[ps];
+        T acc = 0;
+        for (int l1 = 1; l1 + l2 <= CDZ_MAXLOOP; l1++) {
+          const int k = i + 1 + l1;
+          if (l - k < 4) break;
+          const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[l - k] + sE[l2 - 1] - sE[dl]);
+          const int db = D.d[k - 1], Pb = D.P[k - 1];
+          T sm = 0;
+          for (int b = 0; b < db; b++) sm += D.DI[(Pb + b) * ld + Pc + c] * sV[(l1 - 1) * 36 + b * 6 + dd];
+          acc += f * sm;
+        }
+        {  // right bulge with inner pair (i+1, l)
+          const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[l2 - 1] + sE[l - i - 1] - sE[dl]);
+          const int dl_ = D.d[l], Pl = D.P[l];
+          T sm = 0;
+          for (int y = 0; y < dl_; y++) {
+            const T ey = D.e[l * 36 + y * 6 + c];
+            if (ey == T(0)) continue;
+            for (int x = 0; x < d1; x++) sm += sGb[x * 6 + dd] * D.Qb[(P1 + x) * ld + Pl + y] * ey;
+          }
+          acc += f * sm;
+        }
+        A.UbR[(Pc + c) * ld + Pm + dd] += acc;
+      }
+    }
+    __syncthreads();
+    // hairpin closed by (i, j): its run i+1..j-1 (same row as the left runs)
+    if (tid < 36 && s < d1 && t < dm)
+      A.UbL[(P1 + s) * ld + Pm + t] += D.Bhp[dl - 1] * cdz_p2<T>(sE[dl - 2] - sE[dl]) * sFb[tid];
+  } else if (tid < 36) {
+    const int s = tid / 6, t = tid % 6;
+    if (s < di && t < dj) {
+      const long long o = (Pi + s) * ld + Pj + t;
+      A.Qbb[o] = 0;
+      A.Qm1b[o] = 0;
+      A.Qm1pb[o] = 0;
+      A.QmXb[o] = 0;
+      A.Qmb[o] = 0;
+      A.QmXbt[(Pj + t) * ld + Pi + s] = 0;
+    }
+  }
+  __syncthreads();
+  // ---- total adjoint of the unpaired run [i..j]
+  if (tid < 36) {
+    const int a = tid / 6, c = tid % 6;
+    if (a < di && c < dj) {
+      const long long o = (Pi + a) * ld + Pj + c;
+      T u = A.UbL[o] + A.UbR[o];
+      if (j + 1 <= n - 1) {
+        const int dq = D.d[j + 1], Pq = D.P[j + 1];
+        T sm = 0;
+        for (int b = 0; b < dq; b++) sm += A.Ub[(Pi + a) * ld + Pq + b] * D.e[j * 36 + c * 6 + b] * D.v[(j + 1) * 6 + b];
+        u += sm * cdz_p2<T>(sE[dl] - sE[dl + 1]);
+      }
+      A.Ub[o] = u;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Edge marginals: one workgroup per backbone edge p (between p and p+1)
+// gathers every term of dZ/de_p * e_p.  Terms come from the cells whose
+// statements use e_p: row p (edge right after a closing base), row p+1
+// (edge right before a pair / run start), column p+1 and column p.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T loop_inner(const DevProb<T> &D, int i, int j, int a, int dd, int to,
+                                        const int *sE, int dl) {
+  // inner part X(a, dd) of the loop closed by (i, j) for outer pair type to:
+  // sum of hairpin, stack, multiloop, bulge and interior terms with the outer
+  // edges e_i, e_{j-1} removed (units of the cell)
+  const long long ld = D.ld;
+  const long long o = (D.P[i + 1] + a) * ld + D.P[j - 1] + dd;
+  const int na = D.nt[(i + 1) * 6 + a], nd = D.nt[(j - 1) * 6 + dd];
+  const T mm = D.tab[TB_MM + na * 24 + nd * 6 + to];
+  T x = D.Bhp[dl - 1] * D.U[o] * mm + D.tab[TB_MLAB] * D.QmX[o];
+  if (dl - 2 >= 4) {
+    const int t2 = cdz_ptype(na, nd);
+    if (t2 >= 0) x += D.Qb[o] * D.tab[TB_ST + to * 6 + t2];
+  }
+  return x * cdz_p2<T>(sE[dl - 2] - sE[dl]) + D.G[o] + D.F[o] * mm;
+}
+
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = D.n, tid = threadIdx.x, p = blockIdx.x;
+  const long long ld = D.ld;
+  int *sE = reinterpret_cast<int *>(smem_raw);
+  double *red = reinterpret_cast<double *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
+  for (int k = tid; k < n; k += CDZ_NT) sE[k] = D.E[k];
+  __syncthreads();
+  const int EZ = (int)D.res[2];
+  const int dp = D.d[p], dq = D.d[p + 1], Pp = D.P[p], Pq = D.P[p + 1];
+  const T *ep = D.e + p * 36;
+  const T *tab = D.tab;
+  double acc[36];
+#pragma unroll
+  for (int r = 0; r < 36; r++) acc[r] = 0;
+  const int nR1 = n - p - 5 > 0 ? n - p - 5 : 0;  // cells (p+1, j), j >= p+5
+  const int nR0 = n - p - 4 > 0 ? n - p - 4 : 0;  // cells (p, j), j >= p+4
+  const int nC1 = p + 2;                          // cells (i, p+1), i <= p+1
+  const int nC0 = p - 3 > 0 ? p - 3 : 0;          // cells (i, p), i <= p-4
+  const int total = nR1 + nR0 + nC1 + nC0 + 1;
+  for (int it = tid; it < total; it += CDZ_NT) {
+    int w = it;
+    if (w < nR1) {
+      // ---- cell (i, j) = (p+1, j): the edge before its first base
+      const int i = p + 1, j = p + 5 + w, dl = j - i, di = dq, dj = D.d[j], Pj = D.P[j];
+      const long long Pi = Pq;
+      // DI dressing
+      if (j + 1 <= n - 1) {
+        const int dc = D.d[j + 1], Pc = D.P[j + 1];
+        for (int x = 0; x < di; x++)
+          for (int y = 0; y < dj; y++) {
+            const T qb = D.Qb[(Pi + x) * ld + Pj + y];
+            if (qb == T(0)) continue;
+            const int tin = cdz_ptype(D.nt[j * 6 + y], D.nt[i * 6 + x]);
+            for (int c = 0; c < dc; c++) {
+              const T wyc = qb * D.e[j * 36 + y * 6 + c];
+              const int nc = D.nt[(j + 1) * 6 + c];
+#pragma unroll
+              for (int b = 0; b < 6; b++)
+                if (b < dp)
+                  acc[b * 6 + x] += (double)(A.DIb[(Pp + b) * ld + Pc + c] * ep[b * 6 + x] * wyc *
+                                             tab[TB_MM + nc * 24 + D.nt[p * 6 + b] * 6 + tin]);
+            }
+          }
+      }
+      // Qm1L dressing
+#pragma unroll
+      for (int b = 0; b < 6; b++)
+        if (b < dp)
+          for (int t = 0; t < di; t++) {
+            T sm = 0;
+            for (int s2 = 0; s2 < dj; s2++) sm += A.Qm1Lb[(Pp + b) * ld + Pj + s2] * D.Qm1[(Pi + t) * ld + Pj + s2];
+            acc[b * 6 + t] += (double)(sm * ep[b * 6 + t]);
+          }
+      // left bulges with inner pair (i, j): M(b, y) = sum_l1 f sum_a Gb(a,y) U(a,b)
+      if (j + 1 <= n - 1) {
+        T M[36];
+#pragma unroll
+        for (int r = 0; r < 36; r++) M[r] = 0;
+        for (int l1 = 1; l1 <= CDZ_MAXLOOP && i - l1 - 1 >= 0; l1++) {
+          const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[dl] - sE[dl + l1 + 2]);
+          const int pa = i - l1, da = D.d[pa], Pa = D.P[pa];
+#pragma unroll
+          for (int b = 0; b < 6; b++)
+#pragma unroll
+            for (int y = 0; y < 6; y++)
+              if (b < dp && y < dj) {
+                T sm = 0;
+                for (int a = 0; a < da; a++) sm += A.Gb[(Pa + a) * ld + Pj + y] * D.U[(Pa + a) * ld + Pp + b];
+                M[b * 6 + y] += f * sm;
+              }
+        }
+#pragma unroll
+        for (int b = 0; b < 6; b++)
+#pragma unroll
+          for (int x = 0; x < 6; x++)
+            if (b < dp && x < di) {
+              T sm = 0;
+#pragma unroll
+              for (int y = 0; y < 6; y++)
+                if (y < dj) sm += D.Qb[(Pi + x) * ld + Pj + y] * M[b * 6 + y];
+              acc[b * 6 + x] += (double)(sm * ep[b * 6 + x]);
+            }
+      }
+      // exterior loop: pair (i, j) right after the prefix [0..p]
+      {
+        const double sc = ldexp(1.0, D.G5[p] + sE[dl] + D.H3[j] - EZ);
+        for (int x = 0; x < di; x++) {
+          double sm = 0;
+          for (int t = 0; t < dj; t++) sm += (double)D.Qb[(Pi + x) * ld + Pj + t] * D.Z3[j * 6 + t];
+          sm *= sc;
+#pragma unroll
+          for (int s = 0; s < 6; s++)
+            if (s < dp) acc[s * 6 + x] += D.Z5[p * 6 + s] * D.ed[p * 36 + s * 6 + x] * sm;
+        }
+      }
+      continue;
+    }
+    w -= nR1;
+    if (w < nR0) {
+      // ---- cell (p, j): the edge after its first base
+      const int i = p, j = p + 4 + w, dl = j - i, di = dp, dj = D.d[j], Pj = D.P[j];
+      const long long Pi = Pp;
+      const int dm = D.d[j - 1];
+      for (int s = 0; s < di; s++)
+        for (int s2 = 0; s2 < dj; s2++) {
+          const int to = cdz_ptype(D.nt[i * 6 + s], D.nt[j * 6 + s2]);
+          if (to < 0) continue;
+          const T ac = A.Qbb[(Pi + s) * ld + Pj + s2] * D.v[i * 6 + s] * D.v[j * 6 + s2];
+          if (ac == T(0)) continue;
+#pragma unroll
+          for (int a = 0; a < 6; a++)
+            if (a < dq && ep[s * 6 + a] != T(0)) {
+              T sm = 0;
+              for (int dd = 0; dd < dm; dd++)
+                sm += loop_inner<T>(D, i, j, a, dd, to, sE, dl) * D.e[(j - 1) * 36 + dd * 6 + s2];
+              acc[s * 6 + a] += (double)(ac * ep[s * 6 + a] * sm);
+            }
+        }
+      // multiloop unpaired prefix base i
+      {
+        const T f = tab[TB_MLC] * cdz_p2<T>(sE[dl - 1] - sE[dl]);
+#pragma unroll
+        for (int s = 0; s < 6; s++)
+#pragma unroll
+          for (int t = 0; t < 6; t++)
+            if (s < dp && t < dq) {
+              T sm = 0;
+              for (int s2 = 0; s2 < dj; s2++)
+                sm += A.Qm1pb[(Pi + s) * ld + Pj + s2] * D.Qm1p[(Pq + t) * ld + Pj + s2];
+              acc[s * 6 + t] += (double)(sm * f * D.v[i * 6 + s] * ep[s * 6 + t]);
+            }
+      }
+      continue;
+    }
+    w -= nR0;
+    if (w < nC1) {
+      // ---- cell (i, p+1): the edge before its last base
+      const int i = w, j = p + 1, dl = j - i, di = D.d[i], dj = dq;
+      const long long Pi = D.P[i], Pj = Pq;
+      if (dl >= 4) {
+        const int d1 = D.d[i + 1];
+        for (int s = 0; s < di; s++)
+          for (int s2 = 0; s2 < dj; s2++) {
+            const int to = cdz_ptype(D.nt[i * 6 + s], D.nt[j * 6 + s2]);
+            if (to < 0) continue;
+            const T ac = A.Qbb[(Pi + s) * ld + Pj + s2] * D.v[i * 6 + s] * D.v[j * 6 + s2];
+            if (ac == T(0)) continue;
+#pragma unroll
+            for (int dd = 0; dd < 6; dd++)
+              if (dd < dp && ep[dd * 6 + s2] != T(0)) {
+                T sm = 0;
+                for (int a = 0; a < d1; a++)
+                  sm += D.e[i * 36 + s * 6 + a] * loop_inner<T>(D, i, j, a, dd, to, sE, dl);
+                acc[dd * 6 + s2] += (double)(ac * ep[dd * 6 + s2] * sm);
+              }
+          }
+        // multiloop unpaired tail base j
+        const T f = tab[TB_MLC] * cdz_p2<T>(sE[dl - 1] - sE[dl]);
+#pragma unroll
+        for (int t = 0; t < 6; t++)
+#pragma unroll
+          for (int s2 = 0; s2 < 6; s2++)
+            if (t < dp && s2 < dq) {
+              T sm = 0;
+              for (int s = 0; s < di; s++) sm += A.Qm1b[(Pi + s) * ld + Pj + s2] * D.Qm1[(Pi + s) * ld + Pp + t];
+              acc[t * 6 + s2] += (double)(sm * f * ep[t * 6 + s2] * D.v[j * 6 + s2]);
+            }
+      }
+      if (dl >= 1) {
+        // unpaired run [i..p+1] extended from [i..p]
+        const T f = cdz_p2<T>(sE[dl - 1] - sE[dl]);
+#pragma unroll
+        for (int c = 0; c < 6; c++)
+#pragma unroll
+          for (int b = 0; b < 6; b++)
+            if (c < dp && b < dq) {
+              T sm = 0;
+              for (int a = 0; a < di; a++) sm += A.Ub[(Pi + a) * ld + Pj + b] * D.U[(Pi + a) * ld + Pp + c];
+              acc[c * 6 + b] += (double)(sm * f * ep[c * 6 + b] * D.v[j * 6 + b]);
+            }
+      }
+      continue;
+    }
+    w -= nC1;
+    if (w < nC0) {
+      // ---- cell (i, p): the edge after its last base
+      const int i = w, j = p, dl = j - i, di = D.d[i], dj = dp;
+      const long long Pi = D.P[i], Pj = Pp;
+      // DI dressing
+      if (i >= 1) {
+        const int db = D.d[i - 1], Pb = D.P[i - 1];
+        for (int x = 0; x < di; x++)
+          for (int y = 0; y < dj; y++) {
+            const T qb = D.Qb[(Pi + x) * ld + Pj + y];
+            if (qb == T(0)) continue;
+            const int tin = cdz_ptype(D.nt[j * 6 + y], D.nt[i * 6 + x]);
+            for (int b = 0; b < db; b++) {
+              const T wb = D.e[(i - 1) * 36 + b * 6 + x] * qb;
+              if (wb == T(0)) continue;
+              const int nb = D.nt[(i - 1) * 6 + b];
+#pragma unroll
+              for (int c = 0; c < 6; c++)
+                if (c < dq)
+                  acc[y * 6 + c] += (double)(A.DIb[(Pb + b) * ld + Pq + c] * wb * ep[y * 6 + c] *
+                                             tab[TB_MM + D.nt[(p + 1) * 6 + c] * 24 + nb * 6 + tin]);
+            }
+          }
+      }
+      // right bulges with inner pair (i, p): M(x, c) = sum_l2 f sum_dd U(c,dd) Gb(x,dd)
+      if (i >= 1) {
+        T M[36];
+#pragma unroll
+        for (int r = 0; r < 36; r++) M[r] = 0;
+        for (int l2 = 1; l2 <= CDZ_MAXLOOP && p + l2 + 1 <= n - 1; l2++) {
+          const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[dl] + sE[l2 - 1] - sE[dl + l2 + 2]);
+          const int pz = p + l2, dz = D.d[pz], Pz = D.P[pz];
+#pragma unroll
+          for (int x = 0; x < 6; x++)
+#pragma unroll
+            for (int c = 0; c < 6; c++)
+              if (x < di && c < dq) {
+                T sm = 0;
+                for (int dd = 0; dd < dz; dd++) sm += D.U[(Pq + c) * ld + Pz + dd] * A.Gb[(Pi + x) * ld + Pz + dd];
+                M[x * 6 + c] += f * sm;
+              }
+        }
+#pragma unroll
+        for (int y = 0; y < 6; y++)
+#pragma unroll
+          for (int c = 0; c < 6; c++)
+            if (y < dj && c < dq) {
+              T sm = 0;
+#pragma unroll
+              for (int x = 0; x < 6; x++)
+                if (x < di) sm += D.Qb[(Pi + x) * ld + Pj + y] * M[x * 6 + c];
+              acc[y * 6 + c] += (double)(sm * ep[y * 6 + c]);
+            }
+      }
+      continue;
+    }
+    // ---- exterior loop: base p+1 unpaired right after the prefix [0..p]
+    {
+      const double sc = ldexp(1.0, D.G5[p] + D.H3[p + 1] - EZ);
+#pragma unroll
+      for (int s = 0; s < 6; s++)
+#pragma unroll
+        for (int t = 0; t < 6; t++)
+          if (s < dp && t < dq)
+            acc[s * 6 + t] += D.Z5[p * 6 + s] * D.ed[p * 36 + s * 6 + t] * D.vd[(p + 1) * 6 + t] *
+                              D.Z3[(p + 1) * 6 + t] * sc;
+    }
+  }
+  double *out = red + (CDZ_NT / 64) * 36;
+  cdz_block_sum<double, 36>(acc, red, out);
+  for (int r = tid; r < 36; r += CDZ_NT) A.eta[p * 36 + r] = out[r];
+}
+
+// pair probabilities P[i][j] = r * sum Qb~ Qb'~ over cells with j - i >= 4
+template <typename T>
+__global__ void cdz_pairprob(DevProb<T> D, DevAdj<T> A, double r) {
+  const long long n = D.n, ld = D.ld;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n * n) return;
+  const int i = (int)(c / n), j = (int)(c % n);
+  double v = 0;
+  if (j >= i + 4) {
+    const int di = D.d[i], dj = D.d[j], Pi = D.P[i], Pj = D.P[j];
+    for (int s = 0; s < di; s++)
+      for (int t = 0; t < dj; t++)
+        v += (double)D.Qb[(Pi + s) * ld + Pj + t] * (double)A.Qbb[(Pi + s) * ld + Pj + t];
+    v *= r;
+  }
+  A.pair[c] = v;
+}
+
+// d log Z / d theta from the edge marginals (device outputs, scaled by g)
+__global__ void cdz_grad_theta(const double *eta, const int *d, int m, double scale,
+                               double *dth1, double *dth2) {
+  const int a = blockIdx.x, q = threadIdx.x;  // q < 36
+  if (a >= m) return;
+  const int da = d[3 * a], x = q / 6, y = q % 6;
+  if (q < 6) dth1[a * 6 + q] = q < da ? scale * eta[(3 * a) * 36 + q * 6 + q] : 0.0;
+  if (dth2) {
+    double v = 0;
+    if (a >= 1 && x < d[3 * a - 1] && y < da) v = scale * eta[(3 * a - 1) * 36 + x * 6 + y];
+    dth2[(a * 6 + x) * 6 + y] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+#define HIPCHK(h, x)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (x);                                                                      \
+    if (e_ != hipSuccess)                                                                     \
+      return cdz_fail((h), CDZ_ERR_HIP, std::string(#x " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
+  const int n = D.n;
+  hipStream_t st = h->stream;
+  const size_t S2b = (size_t)D.ld * D.ld * sizeof(T);
+  HIPCHK(h, hipEventRecord(h->ev[2], st));
+  HIPCHK(h, hipMemsetAsync(A.UbL, 0, S2b, st));
+  HIPCHK(h, hipMemsetAsync(A.UbR, 0, S2b, st));
+  const size_t shm = out_shmem<T>(n);
+  for (int dl = n - 1; dl >= 0; dl--)
+    hipLaunchKernelGGL(cdz_out_diag<T>, dim3(n - dl), dim3(CDZ_NT), shm, st, D, A, dl);
+  HIPCHK(h, hipGetLastError());
+  if (n >= 2) {
+    const size_t shm2 = ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 36 + 36) * 8;
+    hipLaunchKernelGGL(cdz_eta<T>, dim3(n - 1), dim3(CDZ_NT), shm2, st, D, A);
+  }
+  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz);
+  const long long nn = (long long)n * n;
+  hipLaunchKernelGGL(cdz_pairprob<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, D, A, r);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipEventRecord(h->ev[3], st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  float ms = 0;
+  HIPCHK(h, hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
+  h->times[1] = ms;
+  return CDZ_OK;
+}
+
+static cdz_status outside(cdz_handle *h) {
+  return h->opt.prec == CDZ_FP64 ? run_outside<double>(h, h->pd, h->ad)
+                                 : run_outside<float>(h, h->pf, h->af);
+}
+
+static const double *eta_dev(cdz_handle *h) { return h->opt.prec == CDZ_FP64 ? h->ad.eta : h->af.eta; }
+static const double *pair_dev(cdz_handle *h) { return h->opt.prec == CDZ_FP64 ? h->ad.pair : h->af.pair; }
+static const int *d_dev(cdz_handle *h) { return h->opt.prec == CDZ_FP64 ? h->pd.d : h->pf.d; }
+
+extern "C" cdz_status cdz_marginals(cdz_handle *h, const cdz_problem *prob, double *log_z,
+                                    double *pair, double *base, double *codon, double *codon_pair) {
+  if (!h || !prob) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
+  HostTables t;
+  cdz_status s = build_tables(h, prob->n_aa, prob->aa, prob->theta1, prob->theta2, t);
+  if (s != CDZ_OK) return s;
+  s = ensure_forward(h, t, true);
+  if (s != CDZ_OK) return s;
+  s = outside(h);
+  if (s != CDZ_OK) return s;
+  const int n = t.n, m = t.m;
+  std::vector<double> eta((size_t)n * 36);
+  HIPCHK(h, hipMemcpy(eta.data(), eta_dev(h), eta.size() * 8, hipMemcpyDeviceToHost));
+  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz);
+  std::vector<double> cod((size_t)m * 6, 0.0);
+  for (int a = 0; a < m; a++)
+    for (int c = 0; c < t.d[3 * a]; c++) cod[a * 6 + c] = r * eta[(size_t)(3 * a) * 36 + c * 6 + c];
+  if (log_z) *log_z = h->logz;
+  if (codon) memcpy(codon, cod.data(), cod.size() * 8);
+  if (codon_pair) {
+    for (int k = 0; k < m * 36; k++) codon_pair[k] = 0.0;
+    for (int a = 1; a < m; a++)
+      for (int x = 0; x < t.d[3 * a - 1]; x++)
+        for (int y = 0; y < t.d[3 * a]; y++)
+          codon_pair[a * 36 + x * 6 + y] = r * eta[(size_t)(3 * a - 1) * 36 + x * 6 + y];
+  }
+  if (base) {
+    for (int p = 0; p < n; p++) {
+      for (int b = 0; b < 4; b++) base[p * 4 + b] = 0.0;
+      for (int c = 0; c < t.d[p]; c++) base[p * 4 + t.nt[p * 6 + c]] += cod[(p / 3) * 6 + c];
+    }
+  }
+  if (pair) {
+    HIPCHK(h, hipMemcpy(pair, pair_dev(h), (size_t)n * n * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; i++)
+      for (int j = i + 1; j < n; j++) pair[(size_t)j * n + i] = pair[(size_t)i * n + j];
+    for (int i = 0; i < n; i++) {
+      double sm = 0;
+      for (int j = 0; j < n; j++)
+        if (j != i) sm += pair[(size_t)i * n + j];
+      pair[(size_t)i * n + i] = 1.0 - sm;
+    }
+  }
+  return CDZ_OK;
+}
+
+extern "C" cdz_status cdz_forward_dev(cdz_handle *h, int32_t n_aa, const char *aa,
+                                      const double *theta1_dev, const double *theta2_dev,
+                                      double *log_z) {
+  if (!h || !aa || !theta1_dev || !log_z || n_aa < 1) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
+  std::vector<double> t1((size_t)n_aa * 6), t2;
+  HIPCHK(h, hipMemcpyAsync(t1.data(), theta1_dev, t1.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  if (theta2_dev) {
+    t2.resize((size_t)n_aa * 36);
+    HIPCHK(h, hipMemcpyAsync(t2.data(), theta2_dev, t2.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  HostTables t;
+  cdz_status s = build_tables(h, n_aa, aa, t1.data(), theta2_dev ? t2.data() : nullptr, t);
+  if (s != CDZ_OK) return s;
+  s = ensure_forward(h, t, true);
+  if (s != CDZ_OK) return s;
+  *log_z = h->logz;
+  return CDZ_OK;
+}
+
+extern "C" cdz_status cdz_backward_dev(cdz_handle *h, double grad_logz, double *dtheta1_dev,
+                                       double *dtheta2_dev) {
+  if (!h || !dtheta1_dev) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
+  if (!h->have_fwd || !h->fwd_adjoint) return cdz_fail(h, CDZ_ERR_STATE, "no forward pass to differentiate");
+  cdz_status s = outside(h);
+  if (s != CDZ_OK) return s;
+  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz);
+  hipLaunchKernelGGL(cdz_grad_theta, dim3(h->tables.m), dim3(64), 0, h->stream, eta_dev(h), d_dev(h),
+                     h->tables.m, grad_logz * r, dtheta1_dev, dtheta2_dev);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return CDZ_OK;
+}
+
+template __global__ void cdz_out_diag<float>(DevProb<float>, DevAdj<float>, int);
+template __global__ void cdz_out_diag<double>(DevProb<double>, DevAdj<double>, int);
