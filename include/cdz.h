@@ -146,8 +146,20 @@ cdz_status cdz_backward_dev(cdz_handle *h, double grad_logz, double *dtheta1_dev
 
 /* Per-phase device times (ms) of the last call, measured with HIP events on
  * the handle's stream: [0] forward, [1] outside + marginals, [2] sampling,
- * [3] dominant kernel average (forward diagonal kernel), [4] launches of it. */
+ * [3] average forward diagonal kernel (profiling on, else 0), [4] launches. */
 cdz_status cdz_last_timings(cdz_handle *h, double *ms5);
+
+/* Drop the forward pass kept in the handle, so the next call recomputes it
+ * (used to time complete passes). */
+cdz_status cdz_reset(cdz_handle *h);
+
+/* When on, every diagonal launch is bracketed by HIP events on the handle's
+ * stream and cdz_kernel_timings reports summed kernel times:
+ *   [0] forward diagonal kernels, ms   [1] their number of launches
+ *   [2] outside diagonal kernels, ms   [3] their number of launches
+ *   [4] edge-marginal kernel, ms       [5] sampling kernel, ms */
+cdz_status cdz_set_profiling(cdz_handle *h, int on);
+cdz_status cdz_kernel_timings(cdz_handle *h, double *ms6);
 
 const char *cdz_status_string(cdz_status s);
 const char *cdz_last_error(const cdz_handle *h);

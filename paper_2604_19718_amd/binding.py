@@ -20,8 +20,8 @@ CDZ_FP64 = 1
 STATUS = ["CDZ_OK", "CDZ_ERR_ARG", "CDZ_ERR_PROTEIN", "CDZ_ERR_NUMERIC", "CDZ_ERR_NOMEM",
           "CDZ_ERR_BUDGET", "CDZ_ERR_HIP", "CDZ_ERR_STATE"]
 EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_sample",
-           "cdz_forward_dev", "cdz_backward_dev", "cdz_last_timings", "cdz_status_string",
-           "cdz_last_error"]
+           "cdz_forward_dev", "cdz_backward_dev", "cdz_last_timings", "cdz_reset",
+           "cdz_set_profiling", "cdz_kernel_timings", "cdz_status_string", "cdz_last_error"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -65,6 +65,9 @@ def lib():
             "cdz_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "cdz_last_error": ([vp], ctypes.c_char_p),
             "cdz_debug_logz_suffix": ([vp], ctypes.c_double),
+            "cdz_reset": ([vp], ctypes.c_int),
+            "cdz_set_profiling": ([vp, ctypes.c_int], ctypes.c_int),
+            "cdz_kernel_timings": ([vp, _dp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             if hasattr(L, name):
@@ -164,6 +167,20 @@ def cdz_backward_dev(h: Handle, grad_logz: float, dtheta1_ptr: int, dtheta2_ptr:
 def cdz_last_timings(h: Handle) -> np.ndarray:
     out = np.zeros(5)
     h.check(lib().cdz_last_timings(h.ptr, _arr(out)))
+    return out
+
+
+def cdz_reset(h: Handle) -> None:
+    h.check(lib().cdz_reset(h.ptr))
+
+
+def cdz_set_profiling(h: Handle, on: bool) -> None:
+    h.check(lib().cdz_set_profiling(h.ptr, 1 if on else 0))
+
+
+def cdz_kernel_timings(h: Handle) -> np.ndarray:
+    out = np.zeros(6)
+    h.check(lib().cdz_kernel_timings(h.ptr, _arr(out)))
     return out
 
 

@@ -145,8 +145,10 @@ extern "C" cdz_status cdz_create(const cdz_energy *energy, const cdz_options *op
 extern "C" void cdz_destroy(cdz_handle *h) {
   if (!h) return;
   if (h->ws) (void)hipFree(h->ws);
+  if (h->smp) (void)hipFree(h->smp);
   for (auto &ev : h->ev)
     if (ev) (void)hipEventDestroy(ev);
+  for (auto &ev : h->pev) (void)hipEventDestroy(ev);
   delete h;
 }
 
@@ -317,10 +319,13 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   hipStream_t st = h->stream;
   HIPCHK(h, hipMemsetAsync(D.maxb, 0, (n + 1) * sizeof(unsigned), st));
   const size_t shm = fwd_shmem<T>(n);
+  if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
   HIPCHK(h, hipEventRecord(h->ev[0], st));
   for (int dl = 0; dl <= n; dl++) {
     const int ncell = n - dl > 0 ? n - dl : 0;
+    if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
     hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(ncell + 1), dim3(CDZ_NT), shm, st, D, dl);
+    if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
   }
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->ev[1], st));
@@ -330,8 +335,16 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   float ms = 0;
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
   h->times[0] = ms;
-  h->times[3] = ms / (n + 1);
-  h->times[4] = n + 1;
+  if (h->profiling) {
+    double tot = 0;
+    for (int dl = 0; dl <= n; dl++) {
+      float k = 0;
+      HIPCHK(h, hipEventElapsedTime(&k, h->pev[2 * dl], h->pev[2 * dl + 1]));
+      tot += k;
+    }
+    h->prof_fwd_ms = tot;
+    h->prof_fwd_launches = n + 1;
+  }
   if (!std::isfinite(res[0]) || !std::isfinite(res[1]))
     return cdz_fail(h, CDZ_ERR_NUMERIC, "log Z not finite (scaling out of range)");
   h->logz = res[0];
@@ -395,8 +408,43 @@ extern "C" cdz_status cdz_partition(cdz_handle *h, const cdz_problem *prob, doub
 
 extern "C" cdz_status cdz_last_timings(cdz_handle *h, double *ms5) {
   if (!h || !ms5) return CDZ_ERR_ARG;
-  for (int k = 0; k < 5; k++) ms5[k] = h->times[k];
+  for (int k = 0; k < 3; k++) ms5[k] = h->times[k];
+  ms5[3] = h->prof_fwd_launches ? h->prof_fwd_ms / h->prof_fwd_launches : 0.0;
+  ms5[4] = h->prof_fwd_launches;
   return CDZ_OK;
+}
+
+extern "C" cdz_status cdz_kernel_timings(cdz_handle *h, double *ms6) {
+  if (!h || !ms6) return CDZ_ERR_ARG;
+  ms6[0] = h->prof_fwd_ms;
+  ms6[1] = h->prof_fwd_launches;
+  ms6[2] = h->prof_out_ms;
+  ms6[3] = h->prof_out_launches;
+  ms6[4] = h->prof_eta_ms;
+  ms6[5] = h->prof_smp_ms;
+  return CDZ_OK;
+}
+
+extern "C" cdz_status cdz_set_profiling(cdz_handle *h, int on) {
+  if (!h) return CDZ_ERR_ARG;
+  h->profiling = on != 0;
+  return CDZ_OK;
+}
+
+extern "C" cdz_status cdz_reset(cdz_handle *h) {
+  if (!h) return CDZ_ERR_ARG;
+  h->have_fwd = false;
+  return CDZ_OK;
+}
+
+hipError_t prof_reserve(cdz_handle *h, int launches) {
+  while ((int)h->pev.size() < 2 * launches) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    h->pev.push_back(e);
+  }
+  return hipSuccess;
 }
 
 // debug/test hook: log Z computed from the suffix exterior pass of the last forward

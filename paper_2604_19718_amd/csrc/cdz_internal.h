@@ -52,8 +52,15 @@ struct cdz_handle {
   std::string err;
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  void *smp = nullptr;  // sampler workspace (stacks, group sums, outputs)
+  size_t smp_bytes = 0;
   hipEvent_t ev[8] = {};
   double times[5] = {0, 0, 0, 0, 0};
+  // per-launch event timing of the diagonal kernels (cdz_set_profiling)
+  bool profiling = false;
+  std::vector<hipEvent_t> pev;
+  double prof_fwd_ms = 0, prof_out_ms = 0, prof_eta_ms = 0, prof_smp_ms = 0;
+  int prof_fwd_launches = 0, prof_out_launches = 0;
   // last forward pass
   bool have_fwd = false, fwd_adjoint = false;
   uint64_t fwd_key = 0;
@@ -78,3 +85,4 @@ cdz_status cdz_fail(cdz_handle *h, cdz_status s, const std::string &msg);
 cdz_status build_tables(cdz_handle *h, int32_t n_aa, const char *aa, const double *theta1,
                         const double *theta2, HostTables &t);
 cdz_status ensure_forward(cdz_handle *h, const HostTables &t, bool adjoint);
+hipError_t prof_reserve(cdz_handle *h, int launches);

@@ -783,12 +783,18 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   HIPCHK(h, hipMemsetAsync(A.UbL, 0, S2b, st));
   HIPCHK(h, hipMemsetAsync(A.UbR, 0, S2b, st));
   const size_t shm = out_shmem<T>(n);
-  for (int dl = n - 1; dl >= 0; dl--)
+  if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
+  for (int dl = n - 1; dl >= 0; dl--) {
+    if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
     hipLaunchKernelGGL(cdz_out_diag<T>, dim3(n - dl), dim3(CDZ_NT), shm, st, D, A, dl);
+    if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
+  }
   HIPCHK(h, hipGetLastError());
   if (n >= 2) {
     const size_t shm2 = ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 36 + 36) * 8;
+    if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n], st));
     hipLaunchKernelGGL(cdz_eta<T>, dim3(n - 1), dim3(CDZ_NT), shm2, st, D, A);
+    if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n + 1], st));
   }
   const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz);
   const long long nn = (long long)n * n;
@@ -799,6 +805,19 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   float ms = 0;
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
   h->times[1] = ms;
+  if (h->profiling) {
+    double tot = 0;
+    for (int dl = 0; dl < n; dl++) {
+      float k = 0;
+      HIPCHK(h, hipEventElapsedTime(&k, h->pev[2 * dl], h->pev[2 * dl + 1]));
+      tot += k;
+    }
+    h->prof_out_ms = tot;
+    h->prof_out_launches = n;
+    float k = 0;
+    if (n >= 2) HIPCHK(h, hipEventElapsedTime(&k, h->pev[2 * n], h->pev[2 * n + 1]));
+    h->prof_eta_ms = k;
+  }
   return CDZ_OK;
 }
 
