@@ -33,12 +33,38 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+def build_variant(out_path: str, defines) -> str:
+    """Build a throwaway copy of the oracle with extra -D switches (the
+    planted-mistake variants used by tests/test_oracle_mutations.py)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", out_path]
+    cmd += ["-D" + d for d in defines]
+    cmd += [os.path.join(_HERE, s) for s in _SOURCES] + ["-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
+def load(path: str):
+    """Open an oracle library and declare its entry points."""
+    return _configure(ctypes.CDLL(path))
+
+
+def use(L) -> None:
+    """Route this module's functions to library L (None: the default build)."""
+    global _lib
+    _lib = L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        L = ctypes.CDLL(_LIB_PATH)
+        _lib = _configure(ctypes.CDLL(_LIB_PATH))
+    return _lib
+
+
+def _configure(L):
+    if True:
         d = ctypes.POINTER(ctypes.c_double)
         L.orc_logz.argtypes = [ctypes.c_int, ctypes.c_char_p, d, d, d, d]
         L.orc_logz.restype = ctypes.c_int
@@ -60,8 +86,7 @@ def lib():
         if hasattr(L, "orc_philox_u01"):
             L.orc_philox_u01.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
             L.orc_philox_u01.restype = ctypes.c_double
-        _lib = L
-    return _lib
+    return L
 
 
 def _dp(a: Optional[np.ndarray]):

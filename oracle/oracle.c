@@ -42,6 +42,10 @@
  * range of length L carry exp(-g L) and the result is exact in real
  * arithmetic: log Z = log Z~ + g n.
  *
+ * The PLANT_* switches exist only for tests/test_oracle_mutations.py, which
+ * builds each one into a throwaway library and checks that the pins notice
+ * the planted mistake; the default build defines none of them.
+ *
  * Marginals come from a literal reverse-mode (push/scatter) pass over the
  * same statements.  Because each derivation uses every vertex factor v_p and
  * every backbone edge factor e_p exactly once,
@@ -154,7 +158,11 @@ static int model_build(Model *M, int m, const char *aa, const double *theta1,
           M->e[p][s][t] = (s == t) ? 1.0 : 0.0;
         } else {
           int a = p / 3 + 1; /* codon-pair weight of codons a-1, a */
+#ifdef PLANT_PAIR_TRANSPOSE
+          M->e[p][s][t] = theta2 ? exp(theta2[(a * NS + t) * NS + s]) : 1.0;
+#else
           M->e[p][s][t] = theta2 ? exp(theta2[(a * NS + s) * NS + t]) : 1.0;
+#endif
         }
       }
   }
@@ -170,7 +178,11 @@ static int model_build(Model *M, int m, const char *aa, const double *theta1,
       for (int t = 0; t < 6; t++) M->Bmm[x][y][t] = exp(-E->mismatch[x][y][t]);
   M->hp30 = E->hairpin[30];
   M->extrap = E->extrap;
+#ifdef PLANT_ML_CLOSING
+  M->Bmla_b = exp(-E->ml_a);
+#else
   M->Bmla_b = exp(-(E->ml_a + E->ml_b));
+#endif
   M->Bmlb = exp(-E->ml_b);
   M->Bmlc = exp(-E->ml_c);
   return 0;
@@ -187,7 +199,11 @@ static void model_free(Model *M) {
 static double hairpin_B(const Model *M, int L) {
   if (L < 3) return 0.0;
   if (L <= 30) return exp(-M->hp[L]);
+#ifdef PLANT_HAIRPIN_EXTRAP
+  return exp(-M->hp30);
+#else
   return exp(-(M->hp30 + M->extrap * log((double)L / 30.0)));
+#endif
 }
 
 static int arrays_alloc(Arrays *A, int n, int with_adjoint) {
@@ -287,7 +303,11 @@ static void cell_forward(const Model *M, Arrays *A, int i, int j) {
             double qq = q[x * 6 + y];
             if (qq == 0.0) continue;
             int t2 = ptype(M->nt[i + 1][x], M->nt[j - 1][y]);
+#ifdef PLANT_STACK_SWAP
+            sum += M->e[i][s][x] * qq * M->e[j - 1][y][s2] * M->Bst[t2][t];
+#else
             sum += M->e[i][s][x] * qq * M->e[j - 1][y][s2] * M->Bst[t][t2];
+#endif
           }
         acc[s][s2] += sum;
       }
@@ -389,8 +409,13 @@ static void cell_forward(const Model *M, Arrays *A, int i, int j) {
             double qq = qb[x * 6 + y];
             if (qq == 0.0) continue;
             int t2 = ptype(M->nt[j][y], M->nt[i][x]);
+#ifdef PLANT_INNER_MISMATCH
+            s += M->e[i - 1][b][x] * qq * M->e[j][y][c] *
+                 M->Bmm[M->nt[i - 1][b]][M->nt[j + 1][c]][t2];
+#else
             s += M->e[i - 1][b][x] * qq * M->e[j][y][c] *
                  M->Bmm[M->nt[j + 1][c]][M->nt[i - 1][b]][t2];
+#endif
           }
         dI[b * 6 + c] = s;
       }
@@ -420,7 +445,11 @@ static void cell_forward(const Model *M, Arrays *A, int i, int j) {
   /* QmX: >= 1 branch in [i..u-1] followed by the last branch starting at u.
    * Qm[i][u-1] vanishes for u-1-i < 4 and Qm1[u][j] for j-u < 4. */
   double *qx = CELL(A->QmX, i, j);
+#ifdef PLANT_SPLIT_RANGE
+  for (int u = i + 6; u <= j - 4; u++) {
+#else
   for (int u = i + 5; u <= j - 4; u++) {
+#endif
     const double *qm = CELL(A->Qm, i, u - 1);
     const double *q1u = CELL(A->Qm1, u, j);
     int du1 = M->d[u - 1], du = M->d[u];
@@ -581,7 +610,9 @@ static void cell_reverse(const Model *M, Arrays *A, int i, int j) {
         for (int t = 0; t < dm; t++) {
           double a = q1l[s * 6 + t], e = M->e[j - 1][t][s2], v = M->v[j][s2];
           q1lb[s * 6 + t] += g * e * v * M->Bmlc;
+#ifndef PLANT_REVERSE_EDGE
           EB(j - 1, t, s2) += g * a * v * M->Bmlc;
+#endif
           VB(j, s2) += g * a * e * M->Bmlc;
         }
       }
@@ -1381,9 +1412,13 @@ static void s_pair(Samp *S, int i, int j, int s, int s2) {
         for (int x = 0; x < M->d[k]; x++)
           for (int y = 0; y < M->d[l]; y++) {
             int t2 = ptype(M->nt[l][y], M->nt[k][x]);
+#ifdef PLANT_SAMPLER_BULGE
+            double w = t2 < 0 ? 0.0 : M->e[k - 1][cb][x] * q[x * 6 + y] * M->e[l][y][cc];
+#else
             double w = t2 < 0 ? 0.0
                               : M->e[k - 1][cb][x] * q[x * 6 + y] * M->e[l][y][cc] *
                                     M->Bmm[M->nt[l + 1][cc]][M->nt[k - 1][cb]][t2];
+#endif
             ALT(w, {
               push(S, F_RUN, l + 1, j - 1, cc, cd);
               push(S, F_B, k, l, x, y);

@@ -150,6 +150,34 @@ def zero_energy() -> Energy:
     return e
 
 
+def hairpin_only_energy(seed: int) -> Energy:
+    """The synthetic tables with every loop except hairpins forbidden: every
+    structure is a set of side-by-side hairpins in the exterior loop, so long
+    hairpins carry a visible share of Z (a test model)."""
+    e = energy_tables(seed)
+    e.stack[:] = math.inf
+    e.bulge[:] = math.inf
+    e.interior[:] = math.inf
+    e.ml_a = math.inf
+    return e
+
+
+def interior_rich_energy(seed: int) -> Energy:
+    """Stacks and bulges forbidden, interior loops favourable and strongly
+    mismatch-dependent, so that helices are built from interior loops (a test
+    model for the interior-loop terms)."""
+    e = energy_tables(seed)
+    r = Stream(seed, TAG_ENERGY, 99)
+    e.stack[:] = math.inf
+    e.bulge[:] = math.inf
+    for L in range(2, 31):
+        e.interior[L] = -2.0 + 0.1 * L
+    e.mismatch[:] = np.array([[[r.uniform_ab(-4.0, 0.0) for _ in range(6)]
+                               for _ in range(4)] for _ in range(4)])
+    e.hairpin[3:] = e.hairpin[3:] - 3.0
+    return e
+
+
 def protein(seed: int, m: int, index: int = 0) -> str:
     r = Stream(seed, TAG_PROTEIN, index)
     return "".join(AA_ORDER[r.randint(20)] for _ in range(m))

@@ -140,6 +140,33 @@ def test_long_low_degeneracy_proteins(prot, genetic_code):
         assert abs(oracle.logz(prob, en) - _sum_over_sequences(prob, en, genetic_code)) < 1e-9
 
 
+def test_hairpin_only_model_long_protein(genetic_code):
+    """Only exterior hairpins allowed: hairpins longer than 30 (logarithmic
+    extrapolation) carry a visible share of Z."""
+    prot = "MWMWKMWMWMWIMWMWMWMWMWMWMWMWMWMWKMWMWC"
+    en = I.hairpin_only_energy(1001)
+    prob = _prob(prot, seed=9)
+    assert abs(oracle.logz(prob, en) - _sum_over_sequences(prob, en, genetic_code)) < 1e-10
+
+
+@pytest.mark.parametrize("prot", ["RSLWA", "LSRGA"])
+def test_sampler_interior_rich_model(prot, genetic_code):
+    """Helices built from interior loops: the inner-pair slot decisions and
+    their mismatch terms drive the joint distribution."""
+    from scipy.stats import chi2 as chi2dist
+    en = I.interior_rich_energy(1001)
+    prob = _prob(prot, seed=13)
+    ref = brute.enumerate_ensemble(prob, en, genetic_code)
+    got = oracle.marginals(prob, en)
+    assert abs(got["logz"] - ref["logz"]) < 1e-10
+    for key in ("pair", "codon", "codon_pair"):
+        np.testing.assert_allclose(got[key], ref[key], atol=1e-11)
+    N = 200_000
+    cod, pairs = oracle.sample(prob, en, 90210, N)
+    tv, chi2, dof = _joint_tv(cod, pairs, ref["joint"])
+    assert chi2dist.sf(chi2, dof) > 1e-4
+
+
 def _forbid_pairs(en):
     e = en.copy()
     e.hairpin[:] = math.inf  # no innermost pair can close, hence no pair at all
