@@ -471,5 +471,35 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
   }
 }
 
+// Per-position scale from a finished forward pass: C[p] = log2 of the prefix
+// exterior partition function Z5[p] (FP64).  Every vertex factor v_p is
+// multiplied by 2^-g_p with g_p = round(C[p]) - round(C[p-1]); each range
+// [i..j] then carries the exact factor 2^-(round C[j] - round C[i-1]), which
+// follows the free-energy landscape of the sequence, so inside and outside
+// values of every cell stay near 1 in the next pass.  res[3] accumulates the
+// total shift sum_p g_p (log Z = log Z~ + res[3] ln 2).
+template <typename T>
+__global__ void cdz_rescale(DevProb<T> D) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= D.n) return;
+  auto C = [&](int q) -> long long {
+    if (q < 0) return 0;
+    double z = 0;
+    for (int t = 0; t < 6; t++) z += D.Z5[q * 6 + t];
+    return (z > 0 && isfinite(z)) ? llrint(D.G5[q] + log2(z)) : 0;
+  };
+  const long long g = C(p) - C(p - 1);
+  const double f = ldexp(1.0, (int)(-g));
+  double *vd = const_cast<double *>(D.vd);
+  T *v = const_cast<T *>(D.v);
+  for (int s = 0; s < 6; s++) {
+    vd[p * 6 + s] *= f;
+    v[p * 6 + s] = (T)((double)v[p * 6 + s] * f);
+  }
+  if (p == D.n - 1) D.res[3] += (double)C(p);
+}
+
+template __global__ void cdz_rescale<float>(DevProb<float>);
+template __global__ void cdz_rescale<double>(DevProb<double>);
 template __global__ void cdz_fwd_diag<float>(DevProb<float>, int);
 template __global__ void cdz_fwd_diag<double>(DevProb<double>, int);

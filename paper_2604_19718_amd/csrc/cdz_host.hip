@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "cdz.h"
@@ -314,18 +315,31 @@ static size_t fwd_shmem(int n) {
 }
 
 template <typename T>
+__global__ void cdz_rescale(DevProb<T> D);
+
+template <typename T>
 static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   const int n = D.n;
   hipStream_t st = h->stream;
-  HIPCHK(h, hipMemsetAsync(D.maxb, 0, (n + 1) * sizeof(unsigned), st));
   const size_t shm = fwd_shmem<T>(n);
+  // FP32: a first pass finds the free-energy landscape (prefix exterior
+  // partition function), the vertex factors are rescaled by it, and the
+  // second pass runs on the rescaled tables.  FP64 has the range for one pass.
+  const int passes = std::is_same<T, float>::value ? 2 : 1;
+  HIPCHK(h, hipMemsetAsync(D.res, 0, 8 * sizeof(double), st));
   if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
   HIPCHK(h, hipEventRecord(h->ev[0], st));
-  for (int dl = 0; dl <= n; dl++) {
-    const int ncell = n - dl > 0 ? n - dl : 0;
-    if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
-    hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(ncell + 1), dim3(CDZ_NT), shm, st, D, dl);
-    if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
+  for (int pass = 0; pass < passes; pass++) {
+    HIPCHK(h, hipMemsetAsync(D.maxb, 0, (n + 1) * sizeof(unsigned), st));
+    const bool timed = h->profiling && pass == passes - 1;
+    for (int dl = 0; dl <= n; dl++) {
+      const int ncell = n - dl > 0 ? n - dl : 0;
+      if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
+      hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(ncell + 1), dim3(CDZ_NT), shm, st, D, dl);
+      if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
+    }
+    if (pass + 1 < passes)
+      hipLaunchKernelGGL(cdz_rescale<T>, dim3((n + 255) / 256), dim3(256), 0, st, D);
   }
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->ev[1], st));
@@ -347,9 +361,11 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   }
   if (!std::isfinite(res[0]) || !std::isfinite(res[1]))
     return cdz_fail(h, CDZ_ERR_NUMERIC, "log Z not finite (scaling out of range)");
-  h->logz = res[0];
-  h->logz_suffix = res[1];
-  h->EZ = res[2];
+  const double L2 = 0.6931471805599453094;
+  h->logz = res[0] + res[3] * L2;
+  h->logz_suffix = res[1] + res[3] * L2;
+  h->EZ = res[2];  // exponent of the scaled Z, used by the adjoint
+  h->logz_scaled = res[0];
   return CDZ_OK;
 }
 

@@ -65,6 +65,7 @@ struct cdz_handle {
   bool have_fwd = false, fwd_adjoint = false;
   uint64_t fwd_key = 0;
   double logz = 0, logz_suffix = 0, EZ = 0;
+  double logz_scaled = 0;  // log of the partition function of the scaled tables
   HostTables tables;
   DevProb<float> pf;
   DevProb<double> pd;

@@ -753,8 +753,8 @@ __global__ void cdz_pairprob(DevProb<T> D, DevAdj<T> A, double r) {
 // d log Z / d theta from the edge marginals (device outputs, scaled by g)
 __global__ void cdz_grad_theta(const double *eta, const int *d, int m, double scale,
                                double *dth1, double *dth2) {
-  const int a = blockIdx.x, q = threadIdx.x;  // q < 36
-  if (a >= m) return;
+  const int a = blockIdx.x, q = threadIdx.x;  // one thread per (x, y) slot pair
+  if (a >= m || q >= 36) return;
   const int da = d[3 * a], x = q / 6, y = q % 6;
   if (q < 6) dth1[a * 6 + q] = q < da ? scale * eta[(3 * a) * 36 + q * 6 + q] : 0.0;
   if (dth2) {
@@ -796,7 +796,7 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
     hipLaunchKernelGGL(cdz_eta<T>, dim3(n - 1), dim3(CDZ_NT), shm2, st, D, A);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n + 1], st));
   }
-  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz);
+  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz_scaled);
   const long long nn = (long long)n * n;
   hipLaunchKernelGGL(cdz_pairprob<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, D, A, r);
   HIPCHK(h, hipGetLastError());
@@ -843,7 +843,7 @@ extern "C" cdz_status cdz_marginals(cdz_handle *h, const cdz_problem *prob, doub
   const int n = t.n, m = t.m;
   std::vector<double> eta((size_t)n * 36);
   HIPCHK(h, hipMemcpy(eta.data(), eta_dev(h), eta.size() * 8, hipMemcpyDeviceToHost));
-  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz);
+  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz_scaled);
   std::vector<double> cod((size_t)m * 6, 0.0);
   for (int a = 0; a < m; a++)
     for (int c = 0; c < t.d[3 * a]; c++) cod[a * 6 + c] = r * eta[(size_t)(3 * a) * 36 + c * 6 + c];
@@ -902,12 +902,42 @@ extern "C" cdz_status cdz_backward_dev(cdz_handle *h, double grad_logz, double *
   if (!h->have_fwd || !h->fwd_adjoint) return cdz_fail(h, CDZ_ERR_STATE, "no forward pass to differentiate");
   cdz_status s = outside(h);
   if (s != CDZ_OK) return s;
-  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz);
+  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz_scaled);
   hipLaunchKernelGGL(cdz_grad_theta, dim3(h->tables.m), dim3(64), 0, h->stream, eta_dev(h), d_dev(h),
                      h->tables.m, grad_logz * r, dtheta1_dev, dtheta2_dev);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return CDZ_OK;
+}
+
+// Diagnostic copy of one workspace array of the last pass to the host:
+// which = 0..11 forward (U Qb G F DI Qm1 Qm1Lr Qm1Lt Qm1p QmX Qm Qmt),
+// 12..24 adjoint (Qbb Qm1b Qm1pb QmXb QmXbt Qmb Qm1Lb DIb Gb Fb Ub UbL UbR),
+// 25 diagonal exponents (int32, n + 1).  Element type is the handle's
+// precision; ld x ld elements.
+template <typename T>
+static cdz_status debug_copy(cdz_handle *h, const DevProb<T> &D, const DevAdj<T> &A, int which,
+                             void *dst, size_t bytes) {
+  const T *fw[] = {D.U, D.Qb, D.G, D.F, D.DI, D.Qm1, D.Qm1Lr, D.Qm1Lt, D.Qm1p, D.QmX, D.Qm, D.Qmt};
+  const T *bw[] = {A.Qbb, A.Qm1b, A.Qm1pb, A.QmXb, A.QmXbt, A.Qmb, A.Qm1Lb, A.DIb, A.Gb, A.Fb, A.Ub, A.UbL, A.UbR};
+  const void *src = nullptr;
+  size_t need = (size_t)D.ld * D.ld * sizeof(T);
+  if (which >= 0 && which < 12) src = fw[which];
+  else if (which >= 12 && which < 25) src = h->fwd_adjoint ? bw[which - 12] : nullptr;
+  else if (which == 25) {
+    src = D.E;
+    need = (size_t)(D.n + 1) * sizeof(int);
+  }
+  if (!src || bytes < need) return cdz_fail(h, CDZ_ERR_ARG, "bad debug copy request");
+  HIPCHK(h, hipMemcpy(dst, src, need, hipMemcpyDeviceToHost));
+  return CDZ_OK;
+}
+
+extern "C" cdz_status cdz_debug_copy(cdz_handle *h, int which, void *dst, size_t bytes, long long *ld) {
+  if (!h || !dst || !h->have_fwd) return cdz_fail(h, CDZ_ERR_STATE, "no forward pass");
+  if (ld) *ld = h->opt.prec == CDZ_FP64 ? h->pd.ld : h->pf.ld;
+  return h->opt.prec == CDZ_FP64 ? debug_copy<double>(h, h->pd, h->ad, which, dst, bytes)
+                                 : debug_copy<float>(h, h->pf, h->af, which, dst, bytes);
 }
 
 template __global__ void cdz_out_diag<float>(DevProb<float>, DevAdj<float>, int);

@@ -121,4 +121,5 @@ def test_samples_900nt(full):
     for a in range(prob.m):
         freq[a] = np.bincount(cod[:, a], minlength=6)[:6] / N
     p = np.clip(m32["codon"], 0, 1)
-    assert np.all(np.abs(freq - p) <= 5 * np.sqrt(p * (1 - p) / N) + 1e-9)
+    # 5 sigma plus 3 counts of slack: rare codons (N p << 1) are discrete
+    assert np.all(np.abs(freq - p) <= 5 * np.sqrt(p * (1 - p) / N) + 3.0 / N)

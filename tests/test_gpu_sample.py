@@ -77,8 +77,8 @@ def test_marginal_frequencies_300nt(prec):
     for a in range(prob.m):
         freq[a] = np.bincount(cod[:, a], minlength=6)[:6] / N
     p = np.clip(ref["codon"], 0, 1)
-    z = np.abs(freq - p) - 5 * np.sqrt(p * (1 - p) / N)
-    assert z.max() <= 1e-9, z.max()
+    z = np.abs(freq - p) - 5 * np.sqrt(p * (1 - p) / N) - 3.0 / N  # rare codons are discrete
+    assert z.max() <= 0, z.max()
     n = prob.n
     pf = np.zeros((n, n))
     for k in range(N):
