@@ -24,6 +24,7 @@
 
 #define CDZ_NT 256      // threads per workgroup of the cell kernels
 #define CDZ_MAXLOOP 30  // bulge / interior loop size bound
+#define CDZ_MAX_LDS 65536  // dynamic LDS per workgroup the diagonal kernels may ask for
 #define CDZ_NWIN 496    // (l1, l2) pairs with l1 + l2 <= 30, including (0, 0)
 
 // Boltzmann table offsets inside DevProb::tab

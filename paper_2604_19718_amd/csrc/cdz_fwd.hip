@@ -38,13 +38,16 @@ __device__ int choose_exponent(const DevProb<T> &D, int dl, const int *sE) {
   return sE[dl - 1];
 }
 
-// FP64 exterior loop, one step each way (see the host-side description):
+// FP64 exterior loop, one step each way:
 //   Z5[j](t) = prefix [0..j] with slot t at j
 //   Z3[p](s) = suffix [p+1..n-1] given slot s at p, edge e_p included
+// Every term is evaluated by its own thread with fully unrolled slot loops,
+// so the loads of a step are issued together.
 template <typename T>
 __device__ void exterior_step(const DevProb<T> &D, int dl, const int *sE, double *red) {
   const int n = D.n, tid = threadIdx.x;
   const long long ld = D.ld;
+  double *tot = red + (CDZ_NT / 64) * 6;
   // ---- prefix Z5[j], j = dl - 1
   int j = dl - 1;
   if (j == 0) {
@@ -53,50 +56,62 @@ __device__ void exterior_step(const DevProb<T> &D, int dl, const int *sE, double
   } else if (j > 0 && j < n) {
     const int R = D.G5[j - 1], dj = D.d[j], Pj = D.P[j];
     double part[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = 1 + tid; k <= j - 4; k += CDZ_NT) {
-      const int dk = D.d[k], dk1 = D.d[k - 1], Pk = D.P[k];
-      const double sc = ldexp(1.0, D.G5[k - 1] + sE[j - k] - R);
-      double zl[6];
+    // item 0: j unpaired; item 1: 0 pairs j; item k >= 2: (k-1) pairs j
+    const int nit = j >= 3 ? j - 2 : 1;  // item 0 always; items 1.. need j >= 4
+    for (int it = tid; it < nit; it += CDZ_NT) {
+      if (it == 0) {
+        double z[6];
 #pragma unroll
-      for (int x = 0; x < 6; x++) {
-        double a = 0;
-        if (x < dk)
-          for (int s = 0; s < dk1; s++) a += D.Z5[(k - 1) * 6 + s] * D.ed[(k - 1) * 36 + s * 6 + x];
-        zl[x] = a * sc;
-      }
+        for (int s = 0; s < 6; s++) z[s] = D.Z5[(j - 1) * 6 + s];
 #pragma unroll
-      for (int t = 0; t < 6; t++) {
-        if (t < dj) {
+        for (int t = 0; t < 6; t++) {
+          double a = 0;
+#pragma unroll
+          for (int s = 0; s < 6; s++) a += z[s] * D.ed[(j - 1) * 36 + s * 6 + t];
+          part[t] += t < dj ? a * D.vd[j * 6 + t] : 0.0;
+        }
+      } else if (it == 1) {
+        if (j >= 4) {
+          const double sc = ldexp(1.0, sE[j] - R);
+          const int d0 = D.d[0];
+#pragma unroll
+          for (int t = 0; t < 6; t++) {
+            double a = 0;
+#pragma unroll
+            for (int x = 0; x < 6; x++)
+              if (x < d0 && t < dj) a += (double)D.Qb[x * ld + Pj + t];
+            part[t] += a * sc;
+          }
+        }
+      } else {
+        const int k = it - 1;  // 1 <= k <= j-4
+        const int dk = D.d[k], Pk = D.P[k];
+        const double sc = ldexp(1.0, D.G5[k - 1] + sE[j - k] - R);
+        double z[6], zl[6];
+#pragma unroll
+        for (int s = 0; s < 6; s++) z[s] = D.Z5[(k - 1) * 6 + s];
+#pragma unroll
+        for (int x = 0; x < 6; x++) {
+          double a = 0;
+#pragma unroll
+          for (int s = 0; s < 6; s++) a += z[s] * D.ed[(k - 1) * 36 + s * 6 + x];
+          zl[x] = x < dk ? a * sc : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 6; t++) {
           double a = 0;
 #pragma unroll
           for (int x = 0; x < 6; x++)
-            if (x < dk) a += zl[x] * (double)D.Qb[(Pk + x) * ld + Pj + t];
+            if (x < dk && t < dj) a += zl[x] * (double)D.Qb[(Pk + x) * ld + Pj + t];
           part[t] += a;
         }
       }
     }
-    if (tid == 0) {
-      const int dp = D.d[j - 1];
-      for (int t = 0; t < dj; t++) {
-        double a = 0;
-        for (int s = 0; s < dp; s++) a += D.Z5[(j - 1) * 6 + s] * D.ed[(j - 1) * 36 + s * 6 + t];
-        part[t] += a * D.vd[j * 6 + t];
-      }
-      if (j >= 4) {
-        const double sc = ldexp(1.0, sE[j] - R);
-        for (int t = 0; t < dj; t++) {
-          double a = 0;
-          for (int x = 0; x < D.d[0]; x++) a += (double)D.Qb[x * ld + Pj + t];
-          part[t] += a * sc;
-        }
-      }
-    }
-    double *tot = red + 4 * 6;  // LDS, after the reduction scratch
     cdz_block_sum<double, 6>(part, red, tot);
     if (tid == 0) {
       double mx = 0;
-      for (int t = 0; t < dj; t++) mx = fmax(mx, fabs(tot[t]));
-      int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
+      for (int t = 0; t < 6; t++) mx = fmax(mx, fabs(tot[t]));
+      const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
       for (int t = 0; t < 6; t++) D.Z5[j * 6 + t] = t < dj ? ldexp(tot[t], -e) : 0.0;
       D.G5[j] = R + e;
     }
@@ -110,41 +125,41 @@ __device__ void exterior_step(const DevProb<T> &D, int dl, const int *sE, double
   } else if (p >= 0) {
     const int R = D.H3[p + 1], dp = D.d[p], d1 = D.d[p + 1], P1 = D.P[p + 1];
     double part[6] = {0, 0, 0, 0, 0, 0};
-    for (int jj = p + 5 + tid; jj <= n - 1; jj += CDZ_NT) {
-      const int dq = D.d[jj], Pq = D.P[jj];
-      const double sc = ldexp(1.0, sE[jj - p - 1] + D.H3[jj] - R);
+    // item 0: p+1 unpaired; item it >= 1: p+1 pairs jj = p + 4 + it
+    const int nit = n - 5 - p >= 0 ? n - 4 - p : 1;  // item 0 always
+    for (int it = tid; it < nit; it += CDZ_NT) {
       double w[6];
+      if (it == 0) {
 #pragma unroll
-      for (int x = 0; x < 6; x++) {
-        double a = 0;
-        if (x < d1)
-          for (int t = 0; t < dq; t++) a += (double)D.Qb[(P1 + x) * ld + Pq + t] * D.Z3[jj * 6 + t];
-        w[x] = a * sc;
-      }
+        for (int t = 0; t < 6; t++) w[t] = D.vd[(p + 1) * 6 + t] * D.Z3[(p + 1) * 6 + t];
+      } else {
+        const int jj = p + 4 + it, dq = D.d[jj], Pq = D.P[jj];
+        const double sc = ldexp(1.0, sE[jj - p - 1] + D.H3[jj] - R);
+        double z3[6];
 #pragma unroll
-      for (int s = 0; s < 6; s++)
-        if (s < dp) {
+        for (int t = 0; t < 6; t++) z3[t] = D.Z3[jj * 6 + t];
+#pragma unroll
+        for (int x = 0; x < 6; x++) {
           double a = 0;
 #pragma unroll
-          for (int x = 0; x < 6; x++)
-            if (x < d1) a += D.ed[p * 36 + s * 6 + x] * w[x];
-          part[s] += a;
+          for (int t = 0; t < 6; t++)
+            if (x < d1 && t < dq) a += (double)D.Qb[(P1 + x) * ld + Pq + t] * z3[t];
+          w[x] = a * sc;
         }
-    }
-    if (tid == 0) {
-      for (int s = 0; s < dp; s++) {
+      }
+#pragma unroll
+      for (int s = 0; s < 6; s++) {
         double a = 0;
-        for (int t = 0; t < d1; t++)
-          a += D.ed[p * 36 + s * 6 + t] * D.vd[(p + 1) * 6 + t] * D.Z3[(p + 1) * 6 + t];
-        part[s] += a;
+#pragma unroll
+        for (int x = 0; x < 6; x++) a += D.ed[p * 36 + s * 6 + x] * w[x];
+        part[s] += s < dp ? a : 0.0;
       }
     }
-    double *tot = red + 4 * 6;
     cdz_block_sum<double, 6>(part, red, tot);
     if (tid == 0) {
       double mx = 0;
-      for (int s = 0; s < dp; s++) mx = fmax(mx, fabs(tot[s]));
-      int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
+      for (int s = 0; s < 6; s++) mx = fmax(mx, fabs(tot[s]));
+      const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
       for (int s = 0; s < 6; s++) D.Z3[p * 6 + s] = s < dp ? ldexp(tot[s], -e) : 0.0;
       D.H3[p] = R + e;
     }
@@ -153,24 +168,31 @@ __device__ void exterior_step(const DevProb<T> &D, int dl, const int *sE, double
   // ---- totals after the last diagonal
   if (dl == n) {
     double part[2] = {0, 0};
-    for (int jj = 4 + tid; jj < n; jj += CDZ_NT) {
-      // position 0 pairs with jj, suffix after jj
-      const int dq = D.d[jj], Pq = D.P[jj];
-      double a = 0;
-      for (int x = 0; x < D.d[0]; x++)
-        for (int t = 0; t < dq; t++) a += (double)D.Qb[x * ld + Pq + t] * D.Z3[jj * 6 + t];
-      part[0] += a * ldexp(1.0, sE[jj] + D.H3[jj] - D.H3[0]);
+    const int nit = n >= 4 ? n - 3 : 1;  // item 0 always
+    for (int it = tid; it < nit; it += CDZ_NT) {
+      if (it == 0) {
+        double a = 0;
+#pragma unroll
+        for (int s = 0; s < 6; s++) a += D.vd[s] * D.Z3[s];
+        part[0] += a;
+      } else {
+        const int jj = 3 + it, dq = D.d[jj], Pq = D.P[jj], d0 = D.d[0];
+        double a = 0;
+#pragma unroll
+        for (int x = 0; x < 6; x++)
+#pragma unroll
+          for (int t = 0; t < 6; t++)
+            if (x < d0 && t < dq) a += (double)D.Qb[x * ld + Pq + t] * D.Z3[jj * 6 + t];
+        part[0] += a * ldexp(1.0, sE[jj] + D.H3[jj] - D.H3[0]);
+      }
     }
-    if (tid == 0)
-      for (int s = 0; s < D.d[0]; s++) part[0] += D.vd[s] * D.Z3[s];
-    double *tot = red + 4 * 2;
     cdz_block_sum<double, 2>(part, red, tot);
     if (tid == 0) {
       double z5 = 0;
-      for (int t = 0; t < D.d[n - 1]; t++) z5 += D.Z5[(n - 1) * 6 + t];
+      for (int t = 0; t < 6; t++) z5 += D.Z5[(n - 1) * 6 + t];
       const double L2 = 0.6931471805599453094;
-      double lz5 = log(z5) + D.G5[n - 1] * L2;
-      double lz3 = log(tot[0]) + D.H3[0] * L2;
+      const double lz5 = log(z5) + D.G5[n - 1] * L2;
+      const double lz3 = log(tot[0]) + D.H3[0] * L2;
       D.res[0] = lz5;
       D.res[1] = lz3;
       D.res[2] = rint(lz5 / L2);  // EZ, the adjoint scale exponent
@@ -180,16 +202,42 @@ __device__ void exterior_step(const DevProb<T> &D, int dl, const int *sE, double
 
 }  // namespace
 
+// LDS stage of one cell: every small block the O(1) recurrences of the cell
+// read, fetched by one parallel load phase.
+template <typename T>
+struct CellStage {
+  T tab[TB_LEN];
+  T eIm1[36], eI[36], eJm1[36], eJ[36];  // edge factors e_{i-1}, e_i, e_{j-1}, e_j
+  T vI[6], vJ[6];
+  T Uin[36];   // U[i+1][j-1]
+  T Xin[36];   // QmX[i+1][j-1]
+  T Bin[36];   // Qb[i+1][j-1]
+  T M1l[36];   // Qm1[i][j-1]
+  T M1pr[36];  // Qm1p[i+1][j]
+  T Ul[36];    // U[i][j-1]
+  T split[36], gf[72], qb[36], qm1[36];
+  signed char nt[6][6];  // bases of positions i-1, i, i+1, j-1, j, j+1
+  int d[6], P[6];
+};
+
+template <typename T>
+__device__ __forceinline__ void stage_block(T *dst, const T *A, long long ld, int r0, int c0, int dr,
+                                            int dc, int q) {
+  const int r = q / 6, c = q % 6;
+  dst[q] = (r < dr && c < dc) ? A[(long long)(r0 + r) * ld + c0 + c] : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ int win_base(int l1) {  // first window index with this l1
+  return 31 * l1 - l1 * (l1 - 1) / 2;
+}
+
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1]
-  T *sbuf = reinterpret_cast<T *>(smem_raw + ((size_t)(D.n + 1) * 4 + 15) / 16 * 16);
-  T *red = sbuf;                        // (NT/64) * 72
-  T *sSplit = red + (CDZ_NT / 64) * 72; // 36
-  T *sGF = sSplit + 36;                 // 72 (G then F)
-  T *sQb = sGF + 72;                    // 36
-  T *sQm1 = sQb + 36;                   // 36
+  T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(D.n + 1) * 4 + 15) / 16 * 16);
+  CellStage<T> &C = *reinterpret_cast<CellStage<T> *>(red + (CDZ_NT / 64) * 72);
   const int n = D.n, tid = threadIdx.x;
   const long long ld = D.ld;
   for (int k = tid; k < dl && k <= n; k += CDZ_NT) sE[k] = D.E[k];
@@ -204,7 +252,61 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
     return;
   }
   const int i = blockIdx.x, j = i + dl;
-  const int di = D.d[i], dj = D.d[j], Pi = D.P[i], Pj = D.P[j];
+
+  // ---- stage: positions i-1, i, i+1, j-1, j, j+1 (clamped; unused when absent)
+  if (tid < 6) {
+    const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
+    const int p = pos[tid];
+    const bool ok = p >= 0 && p < n;
+    C.d[tid] = ok ? D.d[p] : 0;
+    C.P[tid] = ok ? D.P[p] : 0;
+#pragma unroll
+    for (int s = 0; s < 6; s++) C.nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
+  }
+  for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+  __syncthreads();
+  const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
+  const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
+  {
+    const int g = tid / 36, q = tid % 36;
+    switch (g) {
+      case 0:
+        if (dl >= 2) stage_block(C.Uin, D.U, ld, P1, Pm, d1, dm, q);
+        else C.Uin[q] = 0;
+        break;
+      case 1:
+        if (dl >= 2) stage_block(C.Xin, D.QmX, ld, P1, Pm, d1, dm, q);
+        else C.Xin[q] = 0;
+        break;
+      case 2:
+        if (dl >= 2) stage_block(C.Bin, D.Qb, ld, P1, Pm, d1, dm, q);
+        else C.Bin[q] = 0;
+        break;
+      case 3:
+        if (dl >= 1) stage_block(C.M1l, D.Qm1, ld, Pi, Pm, di, dm, q);
+        else C.M1l[q] = 0;
+        break;
+      case 4:
+        if (dl >= 1) stage_block(C.M1pr, D.Qm1p, ld, P1, Pj, d1, dj, q);
+        else C.M1pr[q] = 0;
+        break;
+      case 5:
+        if (dl >= 1) stage_block(C.Ul, D.U, ld, Pi, Pm, di, dm, q);
+        else C.Ul[q] = 0;
+        break;
+      case 6:
+        C.eIm1[q] = i >= 1 ? D.e[(i - 1) * 36 + q] : T(0);
+        C.eI[q] = D.e[i * 36 + q];
+        C.eJm1[q] = j >= 1 ? D.e[(j - 1) * 36 + q] : T(0);
+        C.eJ[q] = D.e[j * 36 + q];
+        if (q < 6) {
+          C.vI[q] = D.v[i * 6 + q];
+          C.vJ[q] = D.v[j * 6 + q];
+        }
+        break;
+    }
+  }
+  __syncthreads();
   float vmax = 0.f;
 
   // ---- unpaired run U[i][j]
@@ -213,12 +315,12 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
     if (s < di && t < dj) {
       T u = 0;
       if (dl == 0) {
-        u = (s == t) ? D.v[i * 6 + s] : T(0);
+        u = (s == t) ? C.vI[s] : T(0);
       } else {
-        const int dp = D.d[j - 1], Pp = D.P[j - 1];
         T a = 0;
-        for (int c = 0; c < dp; c++) a += D.U[(Pi + s) * ld + Pp + c] * D.e[(j - 1) * 36 + c * 6 + t];
-        u = a * D.v[j * 6 + t] * cdz_p2<T>(sE[dl - 1] - Ed);
+#pragma unroll
+        for (int c = 0; c < 6; c++) a += C.Ul[s * 6 + c] * C.eJm1[c * 6 + t];
+        u = a * C.vJ[t] * cdz_p2<T>(sE[dl - 1] - Ed);
       }
       D.U[(Pi + s) * ld + Pj + t] = u;
       vmax = fmaxf(vmax, (float)fabs(u));
@@ -235,26 +337,39 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
   }
   if (dl >= 4) {
     // ---- split: QmX[i][j] = sum_k Qm[i][k] f(k) Qm1Lt[j][k], k over the
-    //      states of positions i+4 .. j-5 (u - 1 = pos(k))
+    //      states of positions i+4 .. j-5 (u - 1 = pos(k)); the stream is
+    //      unrolled so that the loads of several k are in flight together
     {
+      constexpr int UN = sizeof(T) == 4 ? 4 : 2;
       T acc[36];
 #pragma unroll
       for (int r = 0; r < 36; r++) acc[r] = 0;
       const int K0 = D.P[i + 4], K1 = D.P[j - 4];
-      for (int k = K0 + tid; k < K1; k += CDZ_NT) {
-        const int p = D.posOf[k];
-        const T f = cdz_p2<T>(sE[p - i] + sE[j - p - 1] - Ed);
-        T a[6], b[6];
+      for (int k0 = K0 + tid; k0 < K1; k0 += UN * CDZ_NT) {
+        T a[UN][6], b[UN][6];
+        int pp[UN];
 #pragma unroll
-        for (int s = 0; s < 6; s++) a[s] = s < di ? D.Qm[(Pi + s) * ld + k] * f : T(0);
+        for (int u = 0; u < UN; u++) {
+          const int k = k0 + u * CDZ_NT;
+          const bool ok = k < K1;
+          pp[u] = ok ? D.posOf[k] : i + 4;
 #pragma unroll
-        for (int t = 0; t < 6; t++) b[t] = t < dj ? D.Qm1Lt[(Pj + t) * ld + k] : T(0);
+          for (int s = 0; s < 6; s++) a[u][s] = (ok && s < di) ? D.Qm[(Pi + s) * ld + k] : T(0);
 #pragma unroll
-        for (int s = 0; s < 6; s++)
+          for (int t = 0; t < 6; t++) b[u][t] = (ok && t < dj) ? D.Qm1Lt[(Pj + t) * ld + k] : T(0);
+        }
 #pragma unroll
-          for (int t = 0; t < 6; t++) acc[s * 6 + t] = fma(a[s], b[t], acc[s * 6 + t]);
+        for (int u = 0; u < UN; u++) {
+          const T f = cdz_p2<T>(sE[pp[u] - i] + sE[j - pp[u] - 1] - Ed);
+#pragma unroll
+          for (int s = 0; s < 6; s++) {
+            const T as = a[u][s] * f;
+#pragma unroll
+            for (int t = 0; t < 6; t++) acc[s * 6 + t] = fma(as, b[u][t], acc[s * 6 + t]);
+          }
+        }
       }
-      cdz_block_sum<T, 36>(acc, red, sSplit);
+      cdz_block_sum<T, 36>(acc, red, C.split);
     }
     // ---- bulge and interior window: G (bulges, outer edges not applied),
     //      F (interior loops, outer edges and outer mismatch not applied);
@@ -263,7 +378,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
       T gf[72];
 #pragma unroll
       for (int r = 0; r < 72; r++) gf[r] = 0;
-      const int d1 = D.d[i + 1], dm = D.d[j - 1], Pa = D.P[i + 1], Pm = D.P[j - 1];
+      const T *tab = C.tab;
       for (int w = 1 + tid; w < CDZ_NWIN; w += CDZ_NT) {
         int l1, l2;
         cdz_win(w, l1, l2);
@@ -272,138 +387,136 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
         const int din = l - k, dk = D.d[k], dlp = D.d[l], Pk = D.P[k], Pl = D.P[l];
         if (l2 == 0) {
           // left bulge: run i+1..k-1, inner pair (k, j-1)
-          const T f = D.tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[din] - Ed);
+          const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[din] - Ed);
           const int db = D.d[k - 1], Pb = D.P[k - 1];
+          T q[36], ek[36], ul[36];
+#pragma unroll
+          for (int r = 0; r < 36; r++) {
+            q[r] = (r / 6 < dk && r % 6 < dlp) ? D.Qb[(Pk + r / 6) * ld + Pl + r % 6] : T(0);
+            ek[r] = D.e[(k - 1) * 36 + r];
+            ul[r] = (r / 6 < d1 && r % 6 < db) ? D.U[(P1 + r / 6) * ld + Pb + r % 6] : T(0);
+          }
           T m[36];  // m(b, y) = sum_x e_{k-1}(b,x) Qb[k][l](x,y)
 #pragma unroll
           for (int b = 0; b < 6; b++)
 #pragma unroll
             for (int y = 0; y < 6; y++) {
               T a = 0;
-              if (b < db && y < dlp)
 #pragma unroll
-                for (int x = 0; x < 6; x++)
-                  if (x < dk) a += D.e[(k - 1) * 36 + b * 6 + x] * D.Qb[(Pk + x) * ld + Pl + y];
+              for (int x = 0; x < 6; x++) a += ek[b * 6 + x] * q[x * 6 + y];
               m[b * 6 + y] = a;
             }
 #pragma unroll
-          for (int a = 0; a < 6; a++) {
-            if (a >= d1) continue;
-            T ur[6];
-#pragma unroll
-            for (int b = 0; b < 6; b++) ur[b] = b < db ? D.U[(Pa + a) * ld + Pb + b] : T(0);
+          for (int a = 0; a < 6; a++)
 #pragma unroll
             for (int y = 0; y < 6; y++) {
-              T s = 0;
+              T sm = 0;
 #pragma unroll
-              for (int b = 0; b < 6; b++) s += ur[b] * m[b * 6 + y];
-              gf[a * 6 + y] += f * s;
+              for (int b = 0; b < 6; b++) sm += ul[a * 6 + b] * m[b * 6 + y];
+              gf[a * 6 + y] += f * sm;
             }
-          }
         } else if (l1 == 0) {
           // right bulge: inner pair (i+1, l), run l+1..j-1
-          const T f = D.tab[TB_BU + l2] * cdz_p2<T>(sE[l2 - 1] + sE[din] - Ed);
+          const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[l2 - 1] + sE[din] - Ed);
           const int dc = D.d[l + 1], Pc = D.P[l + 1];
+          T q[36], el[36], ur[36];
+#pragma unroll
+          for (int r = 0; r < 36; r++) {
+            q[r] = (r / 6 < dk && r % 6 < dlp) ? D.Qb[(Pk + r / 6) * ld + Pl + r % 6] : T(0);
+            el[r] = D.e[l * 36 + r];
+            ur[r] = (r / 6 < dc && r % 6 < dm) ? D.U[(Pc + r / 6) * ld + Pm + r % 6] : T(0);
+          }
           T m[36];  // m(y, dd) = sum_c e_l(y,c) U[l+1][j-1](c,dd)
 #pragma unroll
           for (int y = 0; y < 6; y++)
 #pragma unroll
             for (int dd = 0; dd < 6; dd++) {
               T a = 0;
-              if (y < dlp && dd < dm)
 #pragma unroll
-                for (int c = 0; c < 6; c++)
-                  if (c < dc) a += D.e[l * 36 + y * 6 + c] * D.U[(Pc + c) * ld + Pm + dd];
+              for (int c = 0; c < 6; c++) a += el[y * 6 + c] * ur[c * 6 + dd];
               m[y * 6 + dd] = a;
             }
 #pragma unroll
-          for (int x = 0; x < 6; x++) {
-            if (x >= dk) continue;
-            T q[6];
-#pragma unroll
-            for (int y = 0; y < 6; y++) q[y] = y < dlp ? D.Qb[(Pk + x) * ld + Pl + y] : T(0);
+          for (int x = 0; x < 6; x++)
 #pragma unroll
             for (int dd = 0; dd < 6; dd++) {
-              T s = 0;
+              T sm = 0;
 #pragma unroll
-              for (int y = 0; y < 6; y++) s += q[y] * m[y * 6 + dd];
-              gf[x * 6 + dd] += f * s;
+              for (int y = 0; y < 6; y++) sm += q[x * 6 + y] * m[y * 6 + dd];
+              gf[x * 6 + dd] += f * sm;
             }
-          }
         } else {
           // interior loop: U[i+1][k-1] . DI[k][l] . U[l+1][j-1]
-          const T f = D.tab[TB_IN + l1 + l2] *
-                      cdz_p2<T>(sE[l1 - 1] + sE[din] + sE[l2 - 1] - Ed);
+          const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[din] + sE[l2 - 1] - Ed);
           const int db = D.d[k - 1], Pb = D.P[k - 1], dc = D.d[l + 1], Pc = D.P[l + 1];
+          T di_[36], ul[36], ur[36];
+#pragma unroll
+          for (int r = 0; r < 36; r++) {
+            di_[r] = (r / 6 < db && r % 6 < dc) ? D.DI[(Pb + r / 6) * ld + Pc + r % 6] : T(0);
+            ul[r] = (r / 6 < d1 && r % 6 < db) ? D.U[(P1 + r / 6) * ld + Pb + r % 6] : T(0);
+            ur[r] = (r / 6 < dc && r % 6 < dm) ? D.U[(Pc + r / 6) * ld + Pm + r % 6] : T(0);
+          }
           T m[36];  // m(b, dd) = sum_c DI[k][l](b,c) U[l+1][j-1](c,dd)
 #pragma unroll
           for (int b = 0; b < 6; b++)
 #pragma unroll
             for (int dd = 0; dd < 6; dd++) {
               T a = 0;
-              if (b < db && dd < dm)
 #pragma unroll
-                for (int c = 0; c < 6; c++)
-                  if (c < dc) a += D.DI[(Pb + b) * ld + Pc + c] * D.U[(Pc + c) * ld + Pm + dd];
+              for (int c = 0; c < 6; c++) a += di_[b * 6 + c] * ur[c * 6 + dd];
               m[b * 6 + dd] = a;
             }
 #pragma unroll
-          for (int a = 0; a < 6; a++) {
-            if (a >= d1) continue;
-            T ul[6];
-#pragma unroll
-            for (int b = 0; b < 6; b++) ul[b] = b < db ? D.U[(Pa + a) * ld + Pb + b] : T(0);
+          for (int a = 0; a < 6; a++)
 #pragma unroll
             for (int dd = 0; dd < 6; dd++) {
-              T s = 0;
+              T sm = 0;
 #pragma unroll
-              for (int b = 0; b < 6; b++) s += ul[b] * m[b * 6 + dd];
-              gf[36 + a * 6 + dd] += f * s;
+              for (int b = 0; b < 6; b++) sm += ul[a * 6 + b] * m[b * 6 + dd];
+              gf[36 + a * 6 + dd] += f * sm;
             }
-          }
         }
       }
-      cdz_block_sum<T, 72>(gf, red, sGF);
+      cdz_block_sum<T, 72>(gf, red, C.gf);
     }
-    // ---- Qb (one thread per slot pair)
-    const int d1 = D.d[i + 1], dm = D.d[j - 1], Pa = D.P[i + 1], Pm = D.P[j - 1];
+    const T *tab = C.tab;
+    // ---- Qb (one thread per slot pair), all operands in LDS
     if (tid < 36) {
       const int s = tid / 6, s2 = tid % 6;
       T qb = 0;
       if (s < di && s2 < dj) {
-        const int t = cdz_ptype(D.nt[i * 6 + s], D.nt[j * 6 + s2]);
+        const int t = cdz_ptype(C.nt[1][s], C.nt[4][s2]);
         if (t >= 0) {
-          const T *ei = D.e + i * 36 + s * 6;     // e_i(s, .)
-          const T *ej = D.e + (j - 1) * 36 + s2;  // e_{j-1}(., s2), stride 6
           const T f2 = cdz_p2<T>(sE[dl - 2] - Ed);
           T acc = 0, hp = 0, st = 0, ml = 0;
-          for (int a = 0; a < d1; a++) {
-            const int na = D.nt[(i + 1) * 6 + a];
-            for (int b = 0; b < dm; b++) {
-              const int nb = D.nt[(j - 1) * 6 + b];
-              const T w = ei[a] * ej[b * 6];
-              if (w == T(0)) continue;
-              const T mmo = D.tab[TB_MM + na * 24 + nb * 6 + t];
-              hp += w * D.U[(Pa + a) * ld + Pm + b] * mmo;
-              acc += w * (sGF[a * 6 + b] + sGF[36 + a * 6 + b] * mmo);
-              ml += w * D.QmX[(Pa + a) * ld + Pm + b];
-              if (dl - 2 >= 4) {
-                const int t2 = cdz_ptype(na, nb);
-                if (t2 >= 0) st += w * D.Qb[(Pa + a) * ld + Pm + b] * D.tab[TB_ST + t * 6 + t2];
-              }
+#pragma unroll
+          for (int a = 0; a < 6; a++) {
+            const int na = C.nt[2][a];
+#pragma unroll
+            for (int b = 0; b < 6; b++) {
+              if (a >= d1 || b >= dm) continue;
+              const int nb = C.nt[3][b];
+              const T w = C.eI[s * 6 + a] * C.eJm1[b * 6 + s2];
+              const T mmo = tab[TB_MM + na * 24 + nb * 6 + t];
+              const int o = a * 6 + b;
+              hp += w * C.Uin[o] * mmo;
+              acc += w * (C.gf[o] + C.gf[36 + o] * mmo);
+              ml += w * C.Xin[o];
+              const int t2 = cdz_ptype(na, nb);
+              if (dl - 2 >= 4 && t2 >= 0) st += w * C.Bin[o] * tab[TB_ST + t * 6 + t2];
             }
           }
-          acc += (hp * D.Bhp[dl - 1] + st + ml * D.tab[TB_MLAB]) * f2;
-          qb = D.v[i * 6 + s] * D.v[j * 6 + s2] * acc;
+          acc += (hp * D.Bhp[dl - 1] + st + ml * tab[TB_MLAB]) * f2;
+          qb = C.vI[s] * C.vJ[s2] * acc;
         }
         D.Qb[(Pi + s) * ld + Pj + s2] = qb;
         vmax = fmaxf(vmax, (float)fabs(qb));
       }
-      sQb[tid] = qb;
+      C.qb[tid] = qb;
       // keep the window sums of this cell for the adjoint (block (i+1, j-1))
       if (s < d1 && s2 < dm) {
-        D.G[(Pa + s) * ld + Pm + s2] = sGF[tid];
-        D.F[(Pa + s) * ld + Pm + s2] = sGF[36 + tid];
+        D.G[(P1 + s) * ld + Pm + s2] = C.gf[tid];
+        D.F[(P1 + s) * ld + Pm + s2] = C.gf[36 + tid];
       }
     }
     __syncthreads();
@@ -412,30 +525,29 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
       const int s = tid / 6, s2 = tid % 6;
       T q1 = 0;
       if (s < di && s2 < dj) {
-        const int dp = D.d[j - 1], Pp = D.P[j - 1];
         T a = 0;
-        for (int t = 0; t < dp; t++) a += D.Qm1[(Pi + s) * ld + Pp + t] * D.e[(j - 1) * 36 + t * 6 + s2];
-        q1 = a * D.v[j * 6 + s2] * D.tab[TB_MLC] * cdz_p2<T>(sE[dl - 1] - Ed) + sQb[tid] * D.tab[TB_MLB];
+#pragma unroll
+        for (int t = 0; t < 6; t++) a += C.M1l[s * 6 + t] * C.eJm1[t * 6 + s2];
+        q1 = a * C.vJ[s2] * tab[TB_MLC] * cdz_p2<T>(sE[dl - 1] - Ed) + C.qb[tid] * tab[TB_MLB];
         D.Qm1[(Pi + s) * ld + Pj + s2] = q1;
         vmax = fmaxf(vmax, (float)fabs(q1));
       }
-      sQm1[tid] = q1;
+      C.qm1[tid] = q1;
       if (i >= 1 && j + 1 < n) {
         const int b = tid / 6, c = tid % 6;
-        if (b < D.d[i - 1] && c < D.d[j + 1]) {
-          const int nb = D.nt[(i - 1) * 6 + b], nc = D.nt[(j + 1) * 6 + c];
+        if (b < C.d[0] && c < C.d[5]) {
+          const int nb = C.nt[0][b], nc = C.nt[5][c];
           T a = 0;
-          for (int x = 0; x < di; x++) {
-            const T ex = D.e[(i - 1) * 36 + b * 6 + x];
-            if (ex == T(0)) continue;
-            for (int y = 0; y < dj; y++) {
-              const T q = sQb[x * 6 + y];
-              if (q == T(0)) continue;
-              const int t2 = cdz_ptype(D.nt[j * 6 + y], D.nt[i * 6 + x]);
-              a += ex * q * D.e[j * 36 + y * 6 + c] * D.tab[TB_MM + nc * 24 + nb * 6 + t2];
+#pragma unroll
+          for (int x = 0; x < 6; x++)
+#pragma unroll
+            for (int y = 0; y < 6; y++) {
+              const T q = C.qb[x * 6 + y];
+              const int t2 = cdz_ptype(C.nt[4][y], C.nt[1][x]);
+              if (q != T(0) && t2 >= 0)
+                a += C.eIm1[b * 6 + x] * q * C.eJ[y * 6 + c] * tab[TB_MM + nc * 24 + nb * 6 + t2];
             }
-          }
-          D.DI[(D.P[i - 1] + b) * ld + D.P[j + 1] + c] = a;
+          D.DI[(C.P[0] + b) * ld + C.P[5] + c] = a;
         }
       }
     }
@@ -443,17 +555,19 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
     // ---- Qm1L, Qm1p, QmX, Qm
     if (tid < 36) {
       const int s = tid / 6, s2 = tid % 6;
-      if (i >= 1 && s < D.d[i - 1] && s2 < dj) {
+      if (i >= 1 && s < C.d[0] && s2 < dj) {
         T a = 0;
-        for (int t = 0; t < di; t++) a += D.e[(i - 1) * 36 + s * 6 + t] * sQm1[t * 6 + s2];
-        D.Qm1Lr[(D.P[i - 1] + s) * ld + Pj + s2] = a;
-        D.Qm1Lt[(Pj + s2) * ld + D.P[i - 1] + s] = a;
+#pragma unroll
+        for (int t = 0; t < 6; t++) a += C.eIm1[s * 6 + t] * C.qm1[t * 6 + s2];
+        D.Qm1Lr[(C.P[0] + s) * ld + Pj + s2] = a;
+        D.Qm1Lt[(Pj + s2) * ld + C.P[0] + s] = a;
       }
       if (s < di && s2 < dj) {
         T a = 0;
-        for (int t = 0; t < d1; t++) a += D.e[i * 36 + s * 6 + t] * D.Qm1p[(Pa + t) * ld + Pj + s2];
-        const T qp = sQm1[tid] + D.tab[TB_MLC] * D.v[i * 6 + s] * cdz_p2<T>(sE[dl - 1] - Ed) * a;
-        const T qx = sSplit[tid];
+#pragma unroll
+        for (int t = 0; t < 6; t++) a += C.eI[s * 6 + t] * C.M1pr[t * 6 + s2];
+        const T qp = C.qm1[tid] + tab[TB_MLC] * C.vI[s] * cdz_p2<T>(sE[dl - 1] - Ed) * a;
+        const T qx = C.split[tid];
         const T qm = qx + qp;
         const long long o = (Pi + s) * ld + Pj + s2;
         D.Qm1p[o] = qp;

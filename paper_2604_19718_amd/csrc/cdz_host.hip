@@ -311,7 +311,9 @@ __global__ void cdz_fwd_diag(DevProb<T> D, int dl);
 
 template <typename T>
 static size_t fwd_shmem(int n) {
-  return ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 72 + 36 + 72 + 36 + 36) * sizeof(T);
+  // exponents, reduction scratch, and the cell stage (see cdz_fwd.hip)
+  const size_t stage = (size_t)(TB_LEN + 4 * 36 + 12 + 6 * 36 + 36 + 72 + 36 + 36) * sizeof(T) + 36 + 48 + 64;
+  return ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 72) * sizeof(T) + stage;
 }
 
 template <typename T>
@@ -322,6 +324,8 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   const int n = D.n;
   hipStream_t st = h->stream;
   const size_t shm = fwd_shmem<T>(n);
+  if (shm > CDZ_MAX_LDS)
+    return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the forward kernel");
   // FP32: a first pass finds the free-energy landscape (prefix exterior
   // partition function), the vertex factors are rescaled by it, and the
   // second pass runs on the rescaled tables.  FP64 has the range for one pass.

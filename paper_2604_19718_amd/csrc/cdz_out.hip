@@ -37,12 +37,42 @@ void adj_carve(size_t &off, char *base, const HostTables &t, DevAdj<T> &A, size_
 template void adj_carve<float>(size_t &, char *, const HostTables &, DevAdj<float> &, size_t);
 template void adj_carve<double>(size_t &, char *, const HostTables &, DevAdj<double> &, size_t);
 
-#define NRUN 29  // run lengths 1..29 inside an interior loop
+#define NRUN 30  // run lengths 1..30: interior-loop runs reach 29, a bulge
+                 // (the other side empty) reaches 30
+
+// LDS stage of one cell of the outside pass (see cdz_fwd.hip for the idea):
+// all small operands of the cell's O(1) adjoint statements, fetched by one
+// parallel load phase, plus the per-cell accumulators of the run pushes.
+template <typename T>
+struct OutStage {
+  T tab[TB_LEN];
+  T eIm1[36], eI[36], eJm1[36], eJ[36];
+  T vIm1[6], vI[6], vJ[6], vJp1[6];
+  T m1pUp[36];   // Qm1p'[i-1][j]
+  T m1Right[36]; // Qm1'[i][j+1]
+  T qbOut[36];   // Qb'[i-1][j+1]
+  T gbOut[36];   // Gb at block (i, j): dressed adjoint of the enclosing pair
+  T ubRight[36]; // U'[i][j+1]
+  T ubl[36], ubr[36];  // pushed run adjoints of [i..j]
+  T acc[72], w[72], qm1pb[36], qm1lb[36], qm1b[36], qbb[36], gb[36], fb[36];
+  T Tl[NRUN * 36], Vl[NRUN * 36];
+  T accL[NRUN * 36], accR[NRUN * 36];
+  double z5[6], z3[6], edm1[36];
+  signed char nt[6][6];
+  int d[6], P[6];
+};
 
 template <typename T>
 static size_t out_shmem(int n) {
-  return ((size_t)(n + 1) * 4 + 15) / 16 * 16 +
-         (size_t)((CDZ_NT / 64) * 72 + 72 + 72 + 6 * 36 + 2 * NRUN * 36) * sizeof(T);
+  return ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 72) * sizeof(T) +
+         sizeof(OutStage<T>) + 64;
+}
+
+template <typename T>
+__device__ __forceinline__ void ostage(T *dst, const T *A, long long ld, int r0, int c0, int dr, int dc,
+                                       int q, bool ok) {
+  const int r = q / 6, c = q % 6;
+  dst[q] = (ok && r < dr && c < dc) ? A[(long long)(r0 + r) * ld + c0 + c] : T(0);
 }
 
 template <typename T>
@@ -52,57 +82,125 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
   const long long ld = D.ld;
   int *sE = reinterpret_cast<int *>(smem_raw);
   T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
-  T *sAcc = red + (CDZ_NT / 64) * 72;  // Qm' (36) | Qm1L' (36)
-  T *sW = sAcc + 72;                   // DI' (36) | bulge part of Qb' (36)
-  T *sQm1pb = sW + 72, *sQm1Lb = sQm1pb + 36, *sQm1b = sQm1Lb + 36;
-  T *sQbb = sQm1b + 36, *sGb = sQbb + 36, *sFb = sGb + 36;
-  T *sT = sFb + 36, *sV = sT + NRUN * 36;
+  OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
   for (int k = tid; k < n; k += CDZ_NT) sE[k] = D.E[k];
-  __syncthreads();
   const int EZ = (int)D.res[2];
   const int i = blockIdx.x, j = i + dl;
-  const int di = D.d[i], dj = D.d[j], Pi = D.P[i], Pj = D.P[j];
-  const T *tab = D.tab;
+  if (tid < 6) {
+    const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
+    const int p = pos[tid];
+    const bool ok = p >= 0 && p < n;
+    C.d[tid] = ok ? D.d[p] : 0;
+    C.P[tid] = ok ? D.P[p] : 0;
+#pragma unroll
+    for (int s = 0; s < 6; s++) C.nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
+  }
+  for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+  __syncthreads();
+  const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
+  const int dim1 = C.d[0], Pim1 = C.P[0], djp1 = C.d[5], Pjp1 = C.P[5];
+  const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
+  const bool hasL = i >= 1, hasR = j + 1 <= n - 1;
+  {
+    const int g = tid / 36, q = tid % 36;
+    switch (g) {
+      case 0:
+        ostage(C.m1pUp, A.Qm1pb, ld, Pim1, Pj, dim1, dj, q, hasL);
+        ostage(C.m1Right, A.Qm1b, ld, Pi, Pjp1, di, djp1, q, hasR);
+        break;
+      case 1:
+        ostage(C.qbOut, A.Qbb, ld, Pim1, Pjp1, dim1, djp1, q, hasL && hasR);
+        ostage(C.gbOut, A.Gb, ld, Pi, Pj, di, dj, q, hasL && hasR);
+        break;
+      case 2:
+        ostage(C.ubRight, A.Ub, ld, Pi, Pjp1, di, djp1, q, hasR);
+        ostage(C.ubl, A.UbL, ld, Pi, Pj, di, dj, q, true);
+        ostage(C.ubr, A.UbR, ld, Pi, Pj, di, dj, q, true);
+        break;
+      case 3:
+        C.eIm1[q] = hasL ? D.e[(i - 1) * 36 + q] : T(0);
+        C.eI[q] = D.e[i * 36 + q];
+        C.eJm1[q] = j >= 1 ? D.e[(j - 1) * 36 + q] : T(0);
+        C.eJ[q] = D.e[j * 36 + q];
+        break;
+      case 4:
+        C.edm1[q] = hasL ? D.ed[(i - 1) * 36 + q] : 0.0;
+        if (q < 6) {
+          C.vIm1[q] = hasL ? D.v[(i - 1) * 6 + q] : T(0);
+          C.vI[q] = D.v[i * 6 + q];
+          C.vJ[q] = D.v[j * 6 + q];
+          C.vJp1[q] = hasR ? D.v[(j + 1) * 6 + q] : T(0);
+          C.z5[q] = hasL ? D.Z5[(i - 1) * 6 + q] : 0.0;
+          C.z3[q] = D.Z3[j * 6 + q];
+        }
+        break;
+    }
+  }
+  __syncthreads();
+  const T *tab = C.tab;
 
   if (dl >= 4) {
     // ---- split gathers: Qm'[i][j] along row i, Qm1L'[i][j] down column j
     {
+      constexpr int UN = sizeof(T) == 4 ? 4 : 2;
       T acc[72];
 #pragma unroll
       for (int r = 0; r < 72; r++) acc[r] = 0;
       if (j + 5 <= n - 1) {
         const int K0 = D.P[j + 5], K1 = D.P[n];
-        for (int k = K0 + tid; k < K1; k += CDZ_NT) {
-          const int p = D.posOf[k];
-          const T f = cdz_p2<T>(sE[dl] + sE[p - j - 1] - sE[p - i]);
-          T a[6], b[6];
+        for (int k0 = K0 + tid; k0 < K1; k0 += UN * CDZ_NT) {
+          T a[UN][6], b[UN][6];
+          int pp[UN];
 #pragma unroll
-          for (int s = 0; s < 6; s++) a[s] = s < di ? A.QmXb[(Pi + s) * ld + k] * f : T(0);
+          for (int u = 0; u < UN; u++) {
+            const int k = k0 + u * CDZ_NT;
+            const bool ok = k < K1;
+            pp[u] = ok ? D.posOf[k] : j + 5;
 #pragma unroll
-          for (int t = 0; t < 6; t++) b[t] = t < dj ? D.Qm1Lr[(Pj + t) * ld + k] : T(0);
+            for (int s = 0; s < 6; s++) a[u][s] = (ok && s < di) ? A.QmXb[(Pi + s) * ld + k] : T(0);
 #pragma unroll
-          for (int s = 0; s < 6; s++)
+            for (int t = 0; t < 6; t++) b[u][t] = (ok && t < dj) ? D.Qm1Lr[(Pj + t) * ld + k] : T(0);
+          }
 #pragma unroll
-            for (int t = 0; t < 6; t++) acc[s * 6 + t] = fma(a[s], b[t], acc[s * 6 + t]);
+          for (int u = 0; u < UN; u++) {
+            const T f = cdz_p2<T>(sE[dl] + sE[pp[u] - j - 1] - sE[pp[u] - i]);
+#pragma unroll
+            for (int s = 0; s < 6; s++) {
+              const T as = a[u][s] * f;
+#pragma unroll
+              for (int t = 0; t < 6; t++) acc[s * 6 + t] = fma(as, b[u][t], acc[s * 6 + t]);
+            }
+          }
         }
       }
       if (i >= 5) {
-        const int dm1 = D.d[i - 1], Pm1 = D.P[i - 1], K1 = D.P[i - 4];
-        for (int k = tid; k < K1; k += CDZ_NT) {
-          const int p = D.posOf[k];
-          const T f = cdz_p2<T>(sE[i - 1 - p] + sE[dl] - sE[j - p]);
-          T a[6], c[6];
+        const int K1 = D.P[i - 4];
+        for (int k0 = tid; k0 < K1; k0 += UN * CDZ_NT) {
+          T a[UN][6], c[UN][6];
+          int pp[UN];
 #pragma unroll
-          for (int b = 0; b < 6; b++) a[b] = b < dm1 ? D.Qmt[(Pm1 + b) * ld + k] * f : T(0);
+          for (int u = 0; u < UN; u++) {
+            const int k = k0 + u * CDZ_NT;
+            const bool ok = k < K1;
+            pp[u] = ok ? D.posOf[k] : 0;
 #pragma unroll
-          for (int s2 = 0; s2 < 6; s2++) c[s2] = s2 < dj ? A.QmXbt[(Pj + s2) * ld + k] : T(0);
+            for (int b = 0; b < 6; b++) a[u][b] = (ok && b < dim1) ? D.Qmt[(Pim1 + b) * ld + k] : T(0);
 #pragma unroll
-          for (int b = 0; b < 6; b++)
+            for (int s2 = 0; s2 < 6; s2++) c[u][s2] = (ok && s2 < dj) ? A.QmXbt[(Pj + s2) * ld + k] : T(0);
+          }
 #pragma unroll
-            for (int s2 = 0; s2 < 6; s2++) acc[36 + b * 6 + s2] = fma(a[b], c[s2], acc[36 + b * 6 + s2]);
+          for (int u = 0; u < UN; u++) {
+            const T f = cdz_p2<T>(sE[i - 1 - pp[u]] + sE[dl] - sE[j - pp[u]]);
+#pragma unroll
+            for (int b = 0; b < 6; b++) {
+              const T ab = a[u][b] * f;
+#pragma unroll
+              for (int s2 = 0; s2 < 6; s2++) acc[36 + b * 6 + s2] = fma(ab, c[u][s2], acc[36 + b * 6 + s2]);
+            }
+          }
         }
       }
-      cdz_block_sum<T, 72>(acc, red, sAcc);
+      cdz_block_sum<T, 72>(acc, red, C.acc);
     }
     // ---- window gathers: DI'[i][j] from enclosing interior loops, and the
     //      bulge part of Qb'[i][j] from enclosing bulges
@@ -119,116 +217,119 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
           const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[dl] + sE[l2 - 1] - sE[dl + l1 + l2 + 2]);
           const int pa = i - l1, da = D.d[pa], Pa = D.P[pa];
           const int pz = j + l2, dz = D.d[pz], Pz = D.P[pz];
-          const int db = D.d[i - 1], Pb = D.P[i - 1], dc = D.d[j + 1], Pc = D.P[j + 1];
+          T ul[36], fbk[36], ur[36];
+#pragma unroll
+          for (int r = 0; r < 36; r++) {
+            const int r0 = r / 6, r1 = r % 6;
+            ul[r] = (r0 < da && r1 < dim1) ? D.U[(Pa + r0) * ld + Pim1 + r1] : T(0);
+            fbk[r] = (r0 < da && r1 < dz) ? A.Fb[(Pa + r0) * ld + Pz + r1] : T(0);
+            ur[r] = (r0 < djp1 && r1 < dz) ? D.U[(Pjp1 + r0) * ld + Pz + r1] : T(0);
+          }
           T m[36];  // m(b, dd) = sum_a U[pa][i-1](a,b) Fb[pa][pz](a,dd)
 #pragma unroll
           for (int b = 0; b < 6; b++)
 #pragma unroll
             for (int dd = 0; dd < 6; dd++) {
-              T s = 0;
-              if (b < db && dd < dz)
-                for (int a = 0; a < da; a++) s += D.U[(Pa + a) * ld + Pb + b] * A.Fb[(Pa + a) * ld + Pz + dd];
-              m[b * 6 + dd] = s;
+              T sm = 0;
+#pragma unroll
+              for (int a = 0; a < 6; a++) sm += ul[a * 6 + b] * fbk[a * 6 + dd];
+              m[b * 6 + dd] = sm;
             }
 #pragma unroll
-          for (int c = 0; c < 6; c++) {
-            if (c >= dc) continue;
-            T ur[6];
+          for (int b = 0; b < 6; b++)
 #pragma unroll
-            for (int dd = 0; dd < 6; dd++) ur[dd] = dd < dz ? D.U[(Pc + c) * ld + Pz + dd] : T(0);
+            for (int c = 0; c < 6; c++) {
+              T sm = 0;
 #pragma unroll
-            for (int b = 0; b < 6; b++) {
-              T s = 0;
-#pragma unroll
-              for (int dd = 0; dd < 6; dd++) s += m[b * 6 + dd] * ur[dd];
-              w[b * 6 + c] += f * s;
+              for (int dd = 0; dd < 6; dd++) sm += m[b * 6 + dd] * ur[c * 6 + dd];
+              w[b * 6 + c] += f * sm;
             }
-          }
         } else if (l2 == 0) {
           // enclosing left bulge (i-l1-1, j+1): run i-l1..i-1, inner pair (i, j)
-          if (i - l1 - 1 < 0 || j + 1 > n - 1) continue;
+          if (i - l1 - 1 < 0 || !hasR) continue;
           const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[dl] - sE[dl + l1 + 2]);
-          const int pa = i - l1, da = D.d[pa], Pa = D.P[pa], db = D.d[i - 1], Pb = D.P[i - 1];
+          const int pa = i - l1, da = D.d[pa], Pa = D.P[pa];
+          T ul[36], g[36];
+#pragma unroll
+          for (int r = 0; r < 36; r++) {
+            const int r0 = r / 6, r1 = r % 6;
+            ul[r] = (r0 < da && r1 < dim1) ? D.U[(Pa + r0) * ld + Pim1 + r1] : T(0);
+            g[r] = (r0 < da && r1 < dj) ? A.Gb[(Pa + r0) * ld + Pj + r1] : T(0);
+          }
           T m[36];  // m(a, x) = sum_b U[pa][i-1](a,b) e_{i-1}(b,x)
 #pragma unroll
           for (int a = 0; a < 6; a++)
 #pragma unroll
             for (int x = 0; x < 6; x++) {
-              T s = 0;
-              if (a < da && x < di)
-                for (int b = 0; b < db; b++) s += D.U[(Pa + a) * ld + Pb + b] * D.e[(i - 1) * 36 + b * 6 + x];
-              m[a * 6 + x] = s;
+              T sm = 0;
+#pragma unroll
+              for (int b = 0; b < 6; b++) sm += ul[a * 6 + b] * C.eIm1[b * 6 + x];
+              m[a * 6 + x] = sm;
             }
 #pragma unroll
-          for (int y = 0; y < 6; y++) {
-            if (y >= dj) continue;
-            T g[6];
+          for (int x = 0; x < 6; x++)
 #pragma unroll
-            for (int a = 0; a < 6; a++) g[a] = a < da ? A.Gb[(Pa + a) * ld + Pj + y] : T(0);
+            for (int y = 0; y < 6; y++) {
+              T sm = 0;
 #pragma unroll
-            for (int x = 0; x < 6; x++) {
-              T s = 0;
-#pragma unroll
-              for (int a = 0; a < 6; a++) s += m[a * 6 + x] * g[a];
-              w[36 + x * 6 + y] += f * s;
+              for (int a = 0; a < 6; a++) sm += m[a * 6 + x] * g[a * 6 + y];
+              w[36 + x * 6 + y] += f * sm;
             }
-          }
         } else {
           // enclosing right bulge (i-1, j+l2+1): inner pair (i, j), run j+1..j+l2
-          if (i < 1 || j + l2 + 1 > n - 1) continue;
+          if (!hasL || j + l2 + 1 > n - 1) continue;
           const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[dl] + sE[l2 - 1] - sE[dl + l2 + 2]);
-          const int pz = j + l2, dz = D.d[pz], Pz = D.P[pz], dc = D.d[j + 1], Pc = D.P[j + 1];
+          const int pz = j + l2, dz = D.d[pz], Pz = D.P[pz];
+          T ur[36], g[36];
+#pragma unroll
+          for (int r = 0; r < 36; r++) {
+            const int r0 = r / 6, r1 = r % 6;
+            ur[r] = (r0 < djp1 && r1 < dz) ? D.U[(Pjp1 + r0) * ld + Pz + r1] : T(0);
+            g[r] = (r0 < di && r1 < dz) ? A.Gb[(Pi + r0) * ld + Pz + r1] : T(0);
+          }
           T m[36];  // m(y, dd) = sum_c e_j(y,c) U[j+1][pz](c,dd)
 #pragma unroll
           for (int y = 0; y < 6; y++)
 #pragma unroll
             for (int dd = 0; dd < 6; dd++) {
-              T s = 0;
-              if (y < dj && dd < dz)
-                for (int c = 0; c < dc; c++) s += D.e[j * 36 + y * 6 + c] * D.U[(Pc + c) * ld + Pz + dd];
-              m[y * 6 + dd] = s;
+              T sm = 0;
+#pragma unroll
+              for (int c = 0; c < 6; c++) sm += C.eJ[y * 6 + c] * ur[c * 6 + dd];
+              m[y * 6 + dd] = sm;
             }
 #pragma unroll
-          for (int x = 0; x < 6; x++) {
-            if (x >= di) continue;
-            T g[6];
-#pragma unroll
-            for (int dd = 0; dd < 6; dd++) g[dd] = dd < dz ? A.Gb[(Pi + x) * ld + Pz + dd] : T(0);
+          for (int x = 0; x < 6; x++)
 #pragma unroll
             for (int y = 0; y < 6; y++) {
-              T s = 0;
+              T sm = 0;
 #pragma unroll
-              for (int dd = 0; dd < 6; dd++) s += g[dd] * m[y * 6 + dd];
-              w[36 + x * 6 + y] += f * s;
+              for (int dd = 0; dd < 6; dd++) sm += g[x * 6 + dd] * m[y * 6 + dd];
+              w[36 + x * 6 + y] += f * sm;
             }
-          }
         }
       }
-      cdz_block_sum<T, 72>(w, red, sW);
+      cdz_block_sum<T, 72>(w, red, C.w);
     }
     const int s = tid / 6, t = tid % 6;
-    // ---- Qm', QmX', Qm1p', Qm1L', DI'
+    // ---- Qm', QmX', Qm1p', Qm1L', DI' (all operands in LDS)
     if (tid < 36) {
       T qlb = 0;
-      if (i >= 1 && s < D.d[i - 1] && t < dj) {
-        qlb = sAcc[36 + tid];
-        A.Qm1Lb[(D.P[i - 1] + s) * ld + Pj + t] = qlb;
+      if (hasL && s < dim1 && t < dj) {
+        qlb = C.acc[36 + tid];
+        A.Qm1Lb[(Pim1 + s) * ld + Pj + t] = qlb;
       }
-      sQm1Lb[tid] = qlb;
-      if (i >= 1 && j + 1 <= n - 1 && s < D.d[i - 1] && t < D.d[j + 1])
-        A.DIb[(D.P[i - 1] + s) * ld + D.P[j + 1] + t] = sW[tid];
+      C.qm1lb[tid] = qlb;
+      if (hasL && hasR && s < dim1 && t < djp1) A.DIb[(Pim1 + s) * ld + Pjp1 + t] = C.w[tid];
       T qpb = 0;
       if (s < di && t < dj) {
-        const T qmb = sAcc[tid];
+        const T qmb = C.acc[tid];
         T qxb = qmb;
-        if (i >= 1 && j + 1 <= n - 1)
-          qxb += tab[TB_MLAB] * cdz_p2<T>(sE[dl] - sE[dl + 2]) * A.Gb[(Pi + s) * ld + Pj + t];
+        if (hasL && hasR) qxb += tab[TB_MLAB] * cdz_p2<T>(sE[dl] - sE[dl + 2]) * C.gbOut[tid];
         qpb = qmb;
-        if (i >= 1) {
-          const int dp = D.d[i - 1], Pp = D.P[i - 1];
+        if (hasL) {
           T a = 0;
-          for (int q = 0; q < dp; q++)
-            a += A.Qm1pb[(Pp + q) * ld + Pj + t] * D.v[(i - 1) * 6 + q] * D.e[(i - 1) * 36 + q * 6 + s];
+#pragma unroll
+          for (int q = 0; q < 6; q++) a += C.m1pUp[q * 6 + t] * C.vIm1[q] * C.eIm1[q * 6 + s];
           qpb += tab[TB_MLC] * cdz_p2<T>(sE[dl] - sE[dl + 1]) * a;
         }
         const long long o = (Pi + s) * ld + Pj + t;
@@ -237,26 +338,25 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         A.QmXbt[(Pj + t) * ld + Pi + s] = qxb;
         A.Qm1pb[o] = qpb;
       }
-      sQm1pb[tid] = qpb;
+      C.qm1pb[tid] = qpb;
     }
     __syncthreads();
     // ---- Qm1'
     if (tid < 36) {
       T q1b = 0;
       if (s < di && t < dj) {
-        q1b = sQm1pb[tid];
-        if (i >= 1)
-          for (int b = 0; b < D.d[i - 1]; b++) q1b += D.e[(i - 1) * 36 + b * 6 + s] * sQm1Lb[b * 6 + t];
-        if (j + 1 <= n - 1) {
-          const int dq = D.d[j + 1], Pq = D.P[j + 1];
+        q1b = C.qm1pb[tid];
+#pragma unroll
+        for (int b = 0; b < 6; b++) q1b += C.eIm1[b * 6 + s] * C.qm1lb[b * 6 + t];
+        if (hasR) {
           T a = 0;
-          for (int q = 0; q < dq; q++)
-            a += A.Qm1b[(Pi + s) * ld + Pq + q] * D.v[(j + 1) * 6 + q] * D.e[j * 36 + t * 6 + q];
+#pragma unroll
+          for (int q = 0; q < 6; q++) a += C.m1Right[s * 6 + q] * C.vJp1[q] * C.eJ[t * 6 + q];
           q1b += tab[TB_MLC] * cdz_p2<T>(sE[dl] - sE[dl + 1]) * a;
         }
         A.Qm1b[(Pi + s) * ld + Pj + t] = q1b;
       }
-      sQm1b[tid] = q1b;
+      C.qm1b[tid] = q1b;
     }
     __syncthreads();
     // ---- Qb'
@@ -264,161 +364,201 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
       const int x = s, y = t;
       T qbb = 0;
       if (x < di && y < dj) {
-        qbb = sQm1b[tid] * tab[TB_MLB] + sW[36 + tid];
-        const int nx = D.nt[i * 6 + x], ny = D.nt[j * 6 + y];
+        qbb = C.qm1b[tid] * tab[TB_MLB] + C.w[36 + tid];
+        const int nx = C.nt[1][x], ny = C.nt[4][y];
         const int tin = cdz_ptype(ny, nx);  // inner pair read in loop order (j, i)
-        if (i >= 1 && j + 1 <= n - 1 && tin >= 0) {
-          for (int b = 0; b < D.d[i - 1]; b++) {
-            const T eb = D.e[(i - 1) * 36 + b * 6 + x];
-            if (eb == T(0)) continue;
-            const int nb = D.nt[(i - 1) * 6 + b];
-            for (int c = 0; c < D.d[j + 1]; c++) {
-              const int nc = D.nt[(j + 1) * 6 + c];
-              qbb += sW[b * 6 + c] * eb * D.e[j * 36 + y * 6 + c] * tab[TB_MM + nc * 24 + nb * 6 + tin];
-            }
-          }
+        if (hasL && hasR && tin >= 0) {
+#pragma unroll
+          for (int b = 0; b < 6; b++)
+#pragma unroll
+            for (int c = 0; c < 6; c++)
+              if (b < dim1 && c < djp1)
+                qbb += C.w[b * 6 + c] * C.eIm1[b * 6 + x] * C.eJ[y * 6 + c] *
+                       tab[TB_MM + C.nt[5][c] * 24 + C.nt[0][b] * 6 + tin];
         }
         {  // exterior loop: prefix before i, suffix after j (FP64)
           double zl = 1.0;
           int G = 0;
-          if (i >= 1) {
+          if (hasL) {
             zl = 0;
-            for (int q = 0; q < D.d[i - 1]; q++) zl += D.Z5[(i - 1) * 6 + q] * D.ed[(i - 1) * 36 + q * 6 + x];
+#pragma unroll
+            for (int q = 0; q < 6; q++) zl += C.z5[q] * C.edm1[q * 6 + x];
             G = D.G5[i - 1];
           }
-          qbb += (T)(zl * D.Z3[j * 6 + y] * ldexp(1.0, G + D.H3[j] + sE[dl] - EZ));
+          qbb += (T)(zl * C.z3[y] * ldexp(1.0, G + D.H3[j] + sE[dl] - EZ));
         }
         const int txy = cdz_ptype(nx, ny);
-        if (i >= 1 && j + 1 <= n - 1 && txy >= 0) {  // stacked under (i-1, j+1)
+        if (hasL && hasR && txy >= 0) {  // stacked under (i-1, j+1)
           const T f2 = cdz_p2<T>(sE[dl] - sE[dl + 2]);
-          const int Pp = D.P[i - 1], Pq = D.P[j + 1];
-          for (int q = 0; q < D.d[i - 1]; q++) {
-            const T eq = D.e[(i - 1) * 36 + q * 6 + x];
-            if (eq == T(0)) continue;
-            for (int r = 0; r < D.d[j + 1]; r++) {
-              const int to = cdz_ptype(D.nt[(i - 1) * 6 + q], D.nt[(j + 1) * 6 + r]);
-              if (to < 0) continue;
-              const T ac = A.Qbb[(Pp + q) * ld + Pq + r] * D.v[(i - 1) * 6 + q] * D.v[(j + 1) * 6 + r];
-              qbb += ac * eq * D.e[j * 36 + y * 6 + r] * tab[TB_ST + to * 6 + txy] * f2;
+#pragma unroll
+          for (int q = 0; q < 6; q++)
+#pragma unroll
+            for (int r = 0; r < 6; r++) {
+              const int to = cdz_ptype(C.nt[0][q], C.nt[5][r]);
+              if (q < dim1 && r < djp1 && to >= 0) {
+                const T ac = C.qbOut[q * 6 + r] * C.vIm1[q] * C.vJp1[r];
+                qbb += ac * C.eIm1[q * 6 + x] * C.eJ[y * 6 + r] * tab[TB_ST + to * 6 + txy] * f2;
+              }
             }
-          }
         }
         A.Qbb[(Pi + x) * ld + Pj + y] = qbb;
       }
-      sQbb[tid] = qbb;
+      C.qbb[tid] = qbb;
     }
     __syncthreads();
     // ---- outer-edge-dressed adjoints of this cell's loop sums, block (i+1, j-1)
-    const int d1 = D.d[i + 1], dm = D.d[j - 1], P1 = D.P[i + 1], Pm = D.P[j - 1];
     if (tid < 36) {
       const int a = s, dd = t;
       T gb = 0, fb = 0;
       if (a < d1 && dd < dm) {
-        const int na = D.nt[(i + 1) * 6 + a], nd = D.nt[(j - 1) * 6 + dd];
-        for (int q = 0; q < di; q++) {
-          const T ea = D.e[i * 36 + q * 6 + a];
-          if (ea == T(0)) continue;
-          for (int r = 0; r < dj; r++) {
-            const int to = cdz_ptype(D.nt[i * 6 + q], D.nt[j * 6 + r]);
-            if (to < 0) continue;
-            const T w = sQbb[q * 6 + r] * D.v[i * 6 + q] * D.v[j * 6 + r] * ea * D.e[(j - 1) * 36 + dd * 6 + r];
-            gb += w;
-            fb += w * tab[TB_MM + na * 24 + nd * 6 + to];
+        const int na = C.nt[2][a], nd = C.nt[3][dd];
+#pragma unroll
+        for (int q = 0; q < 6; q++)
+#pragma unroll
+          for (int r = 0; r < 6; r++) {
+            const int to = cdz_ptype(C.nt[1][q], C.nt[4][r]);
+            if (q < di && r < dj && to >= 0) {
+              const T w = C.qbb[q * 6 + r] * C.vI[q] * C.vJ[r] * C.eI[q * 6 + a] * C.eJm1[dd * 6 + r];
+              gb += w;
+              fb += w * tab[TB_MM + na * 24 + nd * 6 + to];
+            }
           }
-        }
         A.Gb[(P1 + a) * ld + Pm + dd] = gb;
         A.Fb[(P1 + a) * ld + Pm + dd] = fb;
       }
-      sGb[tid] = gb;
-      sFb[tid] = fb;
+      C.gb[tid] = gb;
+      C.fb[tid] = fb;
     }
     __syncthreads();
-    // ---- push the adjoints of this cell's loop runs: left runs (and
-    //      hairpin) into row i+1 of UbL, right runs into column j-1 of UbR
+    // ---- run adjoints of this cell's loops.  T_L(a, c) = sum_dd Fb(a,dd)
+    //      U[j-L][j-1](c,dd); V_L(b, dd) = sum_a U[i+1][i+L](a,b) Fb(a,dd)
     for (int idx = tid; idx < 2 * NRUN * 36; idx += CDZ_NT) {
       const int side = idx / (NRUN * 36), rem = idx % (NRUN * 36), L = rem / 36 + 1, q = rem % 36;
       const int r0 = q / 6, r1 = q % 6;
       T val = 0;
-      if (side == 0) {  // T_L(a, c) = sum_dd Fb(a,dd) U[j-L][j-1](c,dd)
+      if (side == 0) {
         const int pc = j - L;
-        if (pc > i + 1 && r0 < d1 && r1 < D.d[pc]) {
-          const int Pc = D.P[pc];
-          for (int dd = 0; dd < dm; dd++) val += sFb[r0 * 6 + dd] * D.U[(Pc + r1) * ld + Pm + dd];
+        if (pc > i + 1) {
+          const int dc = D.d[pc], Pc = D.P[pc];
+          T u[6];
+#pragma unroll
+          for (int dd = 0; dd < 6; dd++) u[dd] = (r1 < dc && dd < dm) ? D.U[(Pc + r1) * ld + Pm + dd] : T(0);
+#pragma unroll
+          for (int dd = 0; dd < 6; dd++) val += C.fb[r0 * 6 + dd] * u[dd];
         }
-        sT[rem] = val;
-      } else {  // V_L(b, dd) = sum_a U[i+1][i+L](a,b) Fb(a,dd)
+        C.Tl[rem] = val;
+        C.accL[rem] = 0;
+      } else {
         const int pb = i + L;
-        if (pb < j - 1 && r0 < D.d[pb] && r1 < dm) {
-          const int Pb = D.P[pb];
-          for (int a = 0; a < d1; a++) val += D.U[(P1 + a) * ld + Pb + r0] * sFb[a * 6 + r1];
+        if (pb < j - 1) {
+          const int db = D.d[pb], Pb = D.P[pb];
+          T u[6];
+#pragma unroll
+          for (int a = 0; a < 6; a++) u[a] = (a < d1 && r0 < db) ? D.U[(P1 + a) * ld + Pb + r0] : T(0);
+#pragma unroll
+          for (int a = 0; a < 6; a++) val += u[a] * C.fb[a * 6 + r1];
         }
-        sV[rem] = val;
+        C.Vl[rem] = val;
+        C.accR[rem] = 0;
       }
     }
     __syncthreads();
+    // one thread per inner pair (k, l) of the window: interior loops add to
+    // both runs, bulges to their single run (LDS atomics, 29 runs per side)
+    for (int win = 1 + tid; win < CDZ_NWIN; win += CDZ_NT) {
+      int l1, l2;
+      cdz_win(win, l1, l2);
+      const int k = i + 1 + l1, l = j - 1 - l2;
+      if (l - k < 4) continue;
+      const int din = l - k;
+      if (l1 >= 1 && l2 >= 1) {
+        const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[din] + sE[l2 - 1] - sE[dl]);
+        const int db = D.d[k - 1], Pb = D.P[k - 1], dc = D.d[l + 1], Pc = D.P[l + 1];
+        T dI[36];
+#pragma unroll
+        for (int r = 0; r < 36; r++)
+          dI[r] = (r / 6 < db && r % 6 < dc) ? D.DI[(Pb + r / 6) * ld + Pc + r % 6] : T(0);
+        const T *Tq = C.Tl + (l2 - 1) * 36;
+        const T *Vq = C.Vl + (l1 - 1) * 36;
+#pragma unroll
+        for (int a = 0; a < 6; a++)
+#pragma unroll
+          for (int b = 0; b < 6; b++) {
+            T sm = 0;
+#pragma unroll
+            for (int c = 0; c < 6; c++) sm += Tq[a * 6 + c] * dI[b * 6 + c];
+            if (a < d1 && b < db && sm != T(0)) atomicAdd(&C.accL[(l1 - 1) * 36 + a * 6 + b], f * sm);
+          }
+#pragma unroll
+        for (int c = 0; c < 6; c++)
+#pragma unroll
+          for (int dd = 0; dd < 6; dd++) {
+            T sm = 0;
+#pragma unroll
+            for (int b = 0; b < 6; b++) sm += dI[b * 6 + c] * Vq[b * 6 + dd];
+            if (c < dc && dd < dm && sm != T(0)) atomicAdd(&C.accR[(l2 - 1) * 36 + c * 6 + dd], f * sm);
+          }
+      } else if (l2 == 0) {  // left bulge: run i+1..k-1, inner pair (k, j-1)
+        const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[din] - sE[dl]);
+        const int dk = D.d[k], Pk = D.P[k], db = D.d[k - 1];
+        T q[36], ek[36];
+#pragma unroll
+        for (int r = 0; r < 36; r++) {
+          q[r] = (r / 6 < dk && r % 6 < dm) ? D.Qb[(Pk + r / 6) * ld + Pm + r % 6] : T(0);
+          ek[r] = D.e[(k - 1) * 36 + r];
+        }
+#pragma unroll
+        for (int a = 0; a < 6; a++)
+#pragma unroll
+          for (int b = 0; b < 6; b++) {
+            T sm = 0;
+#pragma unroll
+            for (int x = 0; x < 6; x++)
+#pragma unroll
+              for (int y = 0; y < 6; y++) sm += C.gb[a * 6 + y] * ek[b * 6 + x] * q[x * 6 + y];
+            if (a < d1 && b < db && sm != T(0)) atomicAdd(&C.accL[(l1 - 1) * 36 + a * 6 + b], f * sm);
+          }
+      } else {  // right bulge: inner pair (i+1, l), run l+1..j-1
+        const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[l2 - 1] + sE[din] - sE[dl]);
+        const int dL = D.d[l], Pl = D.P[l], dc = D.d[l + 1];
+        T q[36], el[36];
+#pragma unroll
+        for (int r = 0; r < 36; r++) {
+          q[r] = (r / 6 < d1 && r % 6 < dL) ? D.Qb[(P1 + r / 6) * ld + Pl + r % 6] : T(0);
+          el[r] = D.e[l * 36 + r];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; c++)
+#pragma unroll
+          for (int dd = 0; dd < 6; dd++) {
+            T sm = 0;
+#pragma unroll
+            for (int x = 0; x < 6; x++)
+#pragma unroll
+              for (int y = 0; y < 6; y++) sm += C.gb[x * 6 + dd] * q[x * 6 + y] * el[y * 6 + c];
+            if (c < dc && dd < dm && sm != T(0)) atomicAdd(&C.accR[(l2 - 1) * 36 + c * 6 + dd], f * sm);
+          }
+      }
+    }
+    __syncthreads();
+    // write back: left runs (row i+1) and the hairpin run, right runs (column j-1)
     for (int idx = tid; idx < 2 * NRUN * 36; idx += CDZ_NT) {
       const int side = idx / (NRUN * 36), rem = idx % (NRUN * 36), L = rem / 36 + 1, q = rem % 36;
       const int r0 = q / 6, r1 = q % 6;
       if (side == 0) {
-        // left run (i+1 .. i+L), l1 = L, inner pair starts at k = i+L+1
-        const int l1 = L, pe = i + l1, k = pe + 1;
-        if (k + 4 > j - 1 || r0 >= d1 || r1 >= D.d[pe]) continue;
-        const int a = r0, b = r1, Pb = D.P[pe];
-        T acc = 0;
-        for (int l2 = 1; l1 + l2 <= CDZ_MAXLOOP; l2++) {
-          const int l = j - 1 - l2;
-          if (l - k < 4) break;
-          const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[l - k] + sE[l2 - 1] - sE[dl]);
-          const int dc = D.d[l + 1], Pc = D.P[l + 1];
-          T sm = 0;
-          for (int c = 0; c < dc; c++) sm += sT[(l2 - 1) * 36 + a * 6 + c] * D.DI[(Pb + b) * ld + Pc + c];
-          acc += f * sm;
-        }
-        {  // left bulge with inner pair (k, j-1)
-          const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[j - 1 - k] - sE[dl]);
-          const int dk = D.d[k], Pk = D.P[k];
-          T sm = 0;
-          for (int x = 0; x < dk; x++) {
-            const T ex = D.e[(k - 1) * 36 + b * 6 + x];
-            if (ex == T(0)) continue;
-            for (int y = 0; y < dm; y++) sm += sGb[a * 6 + y] * ex * D.Qb[(Pk + x) * ld + Pm + y];
-          }
-          acc += f * sm;
-        }
-        A.UbL[(P1 + a) * ld + Pb + b] += acc;
+        const int pe = i + L;  // left run i+1..pe
+        if (pe + 5 > j - 1 || r0 >= d1 || r1 >= D.d[pe]) continue;
+        A.UbL[(P1 + r0) * ld + D.P[pe] + r1] += C.accL[rem];
       } else {
-        // right run (j-L .. j-1), l2 = L, inner pair ends at l = j-L-1
-        const int l2 = L, ps = j - l2, l = ps - 1;
-        if (l - (i + 1) < 4 || r0 >= D.d[ps] || r1 >= dm) continue;
-        const int c = r0, dd = r1, Pc = D.P[ps];
-        T acc = 0;
-        for (int l1 = 1; l1 + l2 <= CDZ_MAXLOOP; l1++) {
-          const int k = i + 1 + l1;
-          if (l - k < 4) break;
-          const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[l - k] + sE[l2 - 1] - sE[dl]);
-          const int db = D.d[k - 1], Pb = D.P[k - 1];
-          T sm = 0;
-          for (int b = 0; b < db; b++) sm += D.DI[(Pb + b) * ld + Pc + c] * sV[(l1 - 1) * 36 + b * 6 + dd];
-          acc += f * sm;
-        }
-        {  // right bulge with inner pair (i+1, l)
-          const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[l2 - 1] + sE[l - i - 1] - sE[dl]);
-          const int dl_ = D.d[l], Pl = D.P[l];
-          T sm = 0;
-          for (int y = 0; y < dl_; y++) {
-            const T ey = D.e[l * 36 + y * 6 + c];
-            if (ey == T(0)) continue;
-            for (int x = 0; x < d1; x++) sm += sGb[x * 6 + dd] * D.Qb[(P1 + x) * ld + Pl + y] * ey;
-          }
-          acc += f * sm;
-        }
-        A.UbR[(Pc + c) * ld + Pm + dd] += acc;
+        const int ps = j - L;  // right run ps..j-1
+        if (ps - 1 - (i + 1) < 4 || r0 >= D.d[ps] || r1 >= dm) continue;
+        A.UbR[(D.P[ps] + r0) * ld + Pm + r1] += C.accR[rem];
       }
     }
     __syncthreads();
     // hairpin closed by (i, j): its run i+1..j-1 (same row as the left runs)
     if (tid < 36 && s < d1 && t < dm)
-      A.UbL[(P1 + s) * ld + Pm + t] += D.Bhp[dl - 1] * cdz_p2<T>(sE[dl - 2] - sE[dl]) * sFb[tid];
+      A.UbL[(P1 + s) * ld + Pm + t] += D.Bhp[dl - 1] * cdz_p2<T>(sE[dl - 2] - sE[dl]) * C.fb[tid];
   } else if (tid < 36) {
     const int s = tid / 6, t = tid % 6;
     if (s < di && t < dj) {
@@ -431,20 +571,19 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
       A.QmXbt[(Pj + t) * ld + Pi + s] = 0;
     }
   }
-  __syncthreads();
-  // ---- total adjoint of the unpaired run [i..j]
+  // ---- total adjoint of the unpaired run [i..j] (operands staged before the
+  //      pushes above, which only touch runs strictly inside [i+1..j-1])
   if (tid < 36) {
     const int a = tid / 6, c = tid % 6;
     if (a < di && c < dj) {
-      const long long o = (Pi + a) * ld + Pj + c;
-      T u = A.UbL[o] + A.UbR[o];
-      if (j + 1 <= n - 1) {
-        const int dq = D.d[j + 1], Pq = D.P[j + 1];
+      T u = C.ubl[tid] + C.ubr[tid];
+      if (hasR) {
         T sm = 0;
-        for (int b = 0; b < dq; b++) sm += A.Ub[(Pi + a) * ld + Pq + b] * D.e[j * 36 + c * 6 + b] * D.v[(j + 1) * 6 + b];
+#pragma unroll
+        for (int b = 0; b < 6; b++) sm += C.ubRight[a * 6 + b] * C.eJ[c * 6 + b] * C.vJp1[b];
         u += sm * cdz_p2<T>(sE[dl] - sE[dl + 1]);
       }
-      A.Ub[o] = u;
+      A.Ub[(Pi + a) * ld + Pj + c] = u;
     }
   }
 }
@@ -779,10 +918,12 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   const int n = D.n;
   hipStream_t st = h->stream;
   const size_t S2b = (size_t)D.ld * D.ld * sizeof(T);
+  const size_t shm = out_shmem<T>(n);
+  if (shm > CDZ_MAX_LDS)
+    return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the outside kernel");
   HIPCHK(h, hipEventRecord(h->ev[2], st));
   HIPCHK(h, hipMemsetAsync(A.UbL, 0, S2b, st));
   HIPCHK(h, hipMemsetAsync(A.UbR, 0, S2b, st));
-  const size_t shm = out_shmem<T>(n);
   if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
   for (int dl = n - 1; dl >= 0; dl--) {
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));

@@ -191,11 +191,36 @@ __device__ void f_ext(W<T> &w, int j, int t) {
     if (g == 1) return D.d[0];
     return D.d[g - 2] * D.d[g - 1];
   };
-  auto gsum = [&](int g) {
-    double s = 0;
-    const int c = cnt(g);
-    for (int a = 0; a < c; a++) s += alt(g, a);
-    return s;
+  // group totals with every load of a group issued at once
+  auto gsum = [&](int g) -> double {
+    if (g == 0) {
+      double z = 0;
+#pragma unroll
+      for (int s = 0; s < 6; s++) z += D.Z5[(j - 1) * 6 + s] * D.ed[(j - 1) * 36 + s * 6 + t];
+      return z * D.vd[j * 6 + t] * ldexp(1.0, D.G5[j - 1] - Gj);
+    }
+    if (g == 1) {
+      if (j < 4) return 0.0;
+      const int d0 = D.d[0];
+      double z = 0;
+#pragma unroll
+      for (int x = 0; x < 6; x++) z += x < d0 ? Qv(D.Qb, ld, x, Pj + t) : 0.0;
+      return z * ldexp(1.0, D.E[j] - Gj);
+    }
+    const int k = g - 1, dk = D.d[k], Pk = D.P[k];
+    double zl[6], q[6];
+#pragma unroll
+    for (int x = 0; x < 6; x++) {
+      double a = 0;
+#pragma unroll
+      for (int s = 0; s < 6; s++) a += D.Z5[(k - 1) * 6 + s] * D.ed[(k - 1) * 36 + s * 6 + x];
+      zl[x] = a;
+      q[x] = x < dk ? Qv(D.Qb, ld, Pk + x, Pj + t) : 0.0;
+    }
+    double z = 0;
+#pragma unroll
+    for (int x = 0; x < 6; x++) z += zl[x] * q[x];
+    return z * ldexp(1.0, D.G5[k - 1] + D.E[j - k] - Gj);
   };
   auto scan = [&](int g, double run, double target) {
     const int c = cnt(g);
@@ -338,7 +363,18 @@ __device__ void f_pair(W<T> &w, int i, int j, int s, int s2) {
   auto mmo = [&](int a, int b) {
     return (double)tab[TB_MM + D.nt[(i + 1) * 6 + a] * 24 + D.nt[(j - 1) * 6 + b] * 6 + t];
   };
-  // weight of inner-pair group w (window index, (l1,l2)) for the fixed outer slots
+  // weight of inner-pair group w (window index, (l1,l2)) for the fixed outer
+  // slots; each block is loaded whole (predicated) so the loads overlap
+  auto blk = [&](const T *A, int r0, int c0, int dr, int dc, double (&o)[36]) {
+#pragma unroll
+    for (int r = 0; r < 36; r++) o[r] = (r / 6 < dr && r % 6 < dc) ? Qv(A, ld, r0 + r / 6, c0 + r % 6) : 0.0;
+  };
+  double eiv[6], ejv[6];
+#pragma unroll
+  for (int a = 0; a < 6; a++) {
+    eiv[a] = ei(a);
+    ejv[a] = ej(a);
+  }
   auto win_weight = [&](int wi) -> double {
     int l1, l2;
     cdz_win(wi, l1, l2);
@@ -347,49 +383,92 @@ __device__ void f_pair(W<T> &w, int i, int j, int s, int s2) {
     const int din = l - k, dk = D.d[k], dL = D.d[l], Pk = D.P[k], Pl = D.P[l];
     double wsum_ = 0;
     if (l1 == 0 && l2 == 0) {
-      for (int x = 0; x < d1; x++)
-        for (int y = 0; y < dm; y++) {
+      double q[36];
+      blk(D.Qb, Pk, Pl, dk, dL, q);
+#pragma unroll
+      for (int x = 0; x < 6; x++)
+#pragma unroll
+        for (int y = 0; y < 6; y++) {
           const int t2 = cdz_ptype(D.nt[k * 6 + x], D.nt[l * 6 + y]);
-          if (t2 < 0) continue;
-          wsum_ += ei(x) * Qv(D.Qb, ld, Pk + x, Pl + y) * ej(y) * (double)tab[TB_ST + t * 6 + t2];
+          if (t2 >= 0) wsum_ += eiv[x] * q[x * 6 + y] * ejv[y] * (double)tab[TB_ST + t * 6 + t2];
         }
       return wsum_ * f2;
     }
     if (l2 == 0) {
       const int db = D.d[k - 1], Pb = D.P[k - 1];
-      for (int a = 0; a < d1; a++)
-        for (int b = 0; b < db; b++) {
-          const double ua = ei(a) * Qv(D.U, ld, P1 + a, Pb + b);
-          if (ua == 0) continue;
-          for (int x = 0; x < dk; x++)
-            for (int y = 0; y < dL; y++)
-              wsum_ += ua * (double)D.e[(k - 1) * 36 + b * 6 + x] * Qv(D.Qb, ld, Pk + x, Pl + y) * ej(y);
-        }
+      double ul[36], q[36];
+      blk(D.U, P1, Pb, d1, db, ul);
+      blk(D.Qb, Pk, Pl, dk, dL, q);
+      double lft[6], rgt[6];  // sum_a e_i ul, sum_y q e_{j-1}
+#pragma unroll
+      for (int b = 0; b < 6; b++) {
+        double a_ = 0;
+#pragma unroll
+        for (int a = 0; a < 6; a++) a_ += eiv[a] * ul[a * 6 + b];
+        lft[b] = a_;
+      }
+#pragma unroll
+      for (int x = 0; x < 6; x++) {
+        double a_ = 0;
+#pragma unroll
+        for (int y = 0; y < 6; y++) a_ += q[x * 6 + y] * ejv[y];
+        rgt[x] = a_;
+      }
+#pragma unroll
+      for (int b = 0; b < 6; b++)
+#pragma unroll
+        for (int x = 0; x < 6; x++) wsum_ += lft[b] * (double)D.e[(k - 1) * 36 + b * 6 + x] * rgt[x];
       return wsum_ * (double)tab[TB_BU + l1] * ldexp(1.0, D.E[l1 - 1] + D.E[din] - E0);
     }
     if (l1 == 0) {
       const int dc = D.d[l + 1], Pc = D.P[l + 1];
-      for (int x = 0; x < dk; x++)
-        for (int y = 0; y < dL; y++) {
-          const double q = ei(x) * Qv(D.Qb, ld, Pk + x, Pl + y);
-          if (q == 0) continue;
-          for (int c = 0; c < dc; c++)
-            for (int dd = 0; dd < dm; dd++)
-              wsum_ += q * (double)D.e[l * 36 + y * 6 + c] * Qv(D.U, ld, Pc + c, Pm + dd) * ej(dd);
-        }
+      double q[36], ur[36];
+      blk(D.Qb, Pk, Pl, dk, dL, q);
+      blk(D.U, Pc, Pm, dc, dm, ur);
+      double lft[6], rgt[6];  // sum_x e_i q, sum_dd ur e_{j-1}
+#pragma unroll
+      for (int y = 0; y < 6; y++) {
+        double a_ = 0;
+#pragma unroll
+        for (int x = 0; x < 6; x++) a_ += eiv[x] * q[x * 6 + y];
+        lft[y] = a_;
+      }
+#pragma unroll
+      for (int c = 0; c < 6; c++) {
+        double a_ = 0;
+#pragma unroll
+        for (int dd = 0; dd < 6; dd++) a_ += ur[c * 6 + dd] * ejv[dd];
+        rgt[c] = a_;
+      }
+#pragma unroll
+      for (int y = 0; y < 6; y++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) wsum_ += lft[y] * (double)D.e[l * 36 + y * 6 + c] * rgt[c];
       return wsum_ * (double)tab[TB_BU + l2] * ldexp(1.0, D.E[din] + D.E[l2 - 1] - E0);
     }
     const int db = D.d[k - 1], Pb = D.P[k - 1], dc = D.d[l + 1], Pc = D.P[l + 1];
-    for (int a = 0; a < d1; a++)
-      for (int dd = 0; dd < dm; dd++) {
-        const double o = ei(a) * ej(dd) * mmo(a, dd);
-        if (o == 0) continue;
+    double ul[36], dI[36], ur[36];
+    blk(D.U, P1, Pb, d1, db, ul);
+    blk(D.DI, Pb, Pc, db, dc, dI);
+    blk(D.U, Pc, Pm, dc, dm, ur);
+    double m[36];  // m(b, dd) = sum_c DI(b,c) ur(c,dd)
+#pragma unroll
+    for (int b = 0; b < 6; b++)
+#pragma unroll
+      for (int dd = 0; dd < 6; dd++) {
+        double a_ = 0;
+#pragma unroll
+        for (int c = 0; c < 6; c++) a_ += dI[b * 6 + c] * ur[c * 6 + dd];
+        m[b * 6 + dd] = a_;
+      }
+#pragma unroll
+    for (int a = 0; a < 6; a++)
+#pragma unroll
+      for (int dd = 0; dd < 6; dd++) {
+        const double o = eiv[a] * ejv[dd] * (a < d1 && dd < dm ? mmo(a, dd) : 0.0);
         double in = 0;
-        for (int b = 0; b < db; b++) {
-          const double ua = Qv(D.U, ld, P1 + a, Pb + b);
-          if (ua == 0) continue;
-          for (int c = 0; c < dc; c++) in += ua * Qv(D.DI, ld, Pb + b, Pc + c) * Qv(D.U, ld, Pc + c, Pm + dd);
-        }
+#pragma unroll
+        for (int b = 0; b < 6; b++) in += ul[a * 6 + b] * m[b * 6 + dd];
         wsum_ += o * in;
       }
     return wsum_ * (double)tab[TB_IN + l1 + l2] * ldexp(1.0, D.E[l1 - 1] + D.E[din] + D.E[l2 - 1] - E0);
@@ -397,15 +476,22 @@ __device__ void f_pair(W<T> &w, int i, int j, int s, int s2) {
   // decision 1: which loop (group 0 hairpin, 1 + w window, CDZ_NWIN + 1 multiloop)
   auto gsum1 = [&](int g) -> double {
     if (g == 0) {
-      double h = 0;
-      for (int a = 0; a < d1; a++)
-        for (int b = 0; b < dm; b++) h += ei(a) * Qv(D.U, ld, P1 + a, Pm + b) * ej(b) * mmo(a, b);
+      double u[36], h = 0;
+      blk(D.U, P1, Pm, d1, dm, u);
+#pragma unroll
+      for (int a = 0; a < 6; a++)
+#pragma unroll
+        for (int b = 0; b < 6; b++)
+          if (a < d1 && b < dm) h += eiv[a] * u[a * 6 + b] * ejv[b] * mmo(a, b);
       return h * (double)D.Bhp[dl - 1] * f2;
     }
     if (g <= CDZ_NWIN) return win_weight(g - 1);
-    double m = 0;
-    for (int x = 0; x < d1; x++)
-      for (int y = 0; y < dm; y++) m += ei(x) * Qv(D.QmX, ld, P1 + x, Pm + y) * ej(y);
+    double x_[36], m = 0;
+    blk(D.QmX, P1, Pm, d1, dm, x_);
+#pragma unroll
+    for (int x = 0; x < 6; x++)
+#pragma unroll
+      for (int y = 0; y < 6; y++) m += eiv[x] * x_[x * 6 + y] * ejv[y];
     return m * (double)tab[TB_MLAB] * f2;
   };
   auto scan1 = [&](int g, double, double) { return 0; };
@@ -505,11 +591,21 @@ __device__ void f_split(W<T> &w, int i, int j, int s, int s2, bool with_m1p) {
     return Qv(D.Qm, ld, Pi + s, D.P[u - 1] + t) * (double)D.e[(u - 1) * 36 + t * 6 + t2] *
            Qv(D.Qm1, ld, D.P[u] + t2, Pj + s2) * ldexp(1.0, D.E[u - 1 - i] + D.E[j - u] - E0);
   };
-  auto gsum = [&](int g) {
+  auto gsum = [&](int g) -> double {
+    if (g >= nu) return Qv(D.Qm1p, ld, Pi + s, Pj + s2);
+    const int u = i + 5 + g, du1 = D.d[u - 1], du = D.d[u], Pu1 = D.P[u - 1], Pu = D.P[u];
+    double qa[6], qb[6];
+#pragma unroll
+    for (int t = 0; t < 6; t++) {
+      qa[t] = t < du1 ? Qv(D.Qm, ld, Pi + s, Pu1 + t) : 0.0;
+      qb[t] = t < du ? Qv(D.Qm1, ld, Pu + t, Pj + s2) : 0.0;
+    }
     double x = 0;
-    const int c = cnt(g);
-    for (int a = 0; a < c; a++) x += alt(g, a);
-    return x;
+#pragma unroll
+    for (int t = 0; t < 6; t++)
+#pragma unroll
+      for (int t2 = 0; t2 < 6; t2++) x += qa[t] * (double)D.e[(u - 1) * 36 + t * 6 + t2] * qb[t2];
+    return x * ldexp(1.0, D.E[u - 1 - i] + D.E[j - u] - E0);
   };
   auto scan = [&](int g, double run, double target) {
     const int c = cnt(g);

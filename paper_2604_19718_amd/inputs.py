@@ -178,6 +178,19 @@ def interior_rich_energy(seed: int) -> Energy:
     return e
 
 
+def bulge_rich_energy(seed: int) -> Energy:
+    """Stacks and interior loops forbidden, bulges favourable and more so the
+    longer they are, so that helices are built from bulges and the longest
+    bulges carry a visible share of Z (a test model for the bulge terms)."""
+    e = energy_tables(seed)
+    e.stack[:] = math.inf
+    e.interior[:] = math.inf
+    for L in range(1, 31):
+        e.bulge[L] = -1.0 - 0.1 * L
+    e.hairpin[3:] = e.hairpin[3:] - 3.0
+    return e
+
+
 def protein(seed: int, m: int, index: int = 0) -> str:
     r = Stream(seed, TAG_PROTEIN, index)
     return "".join(AA_ORDER[r.randint(20)] for _ in range(m))

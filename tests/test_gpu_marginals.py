@@ -46,3 +46,16 @@ def test_workload_ragged(prec, m):
     ref = oracle.marginals(prob, en)
     got = B.cdz_marginals(B.cdz_create(en, prec), prob)
     _check(got, ref, prec, f"m{m}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("model", ["bulge_rich", "interior_rich"])
+def test_loop_rich_models(prec, model):
+    """Tables under which bulges and interior loops up to the 30-nt window
+    limit carry a visible share of Z, so that a dropped or misplaced long-loop
+    term moves the marginals far beyond the tolerance."""
+    en = getattr(I, f"{model}_energy")(7)
+    prob, _ = I.workload(2, m=40)
+    ref = oracle.marginals(prob, en)
+    got = B.cdz_marginals(B.cdz_create(en, prec), prob)
+    _check(got, ref, prec, model)

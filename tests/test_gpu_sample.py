@@ -40,6 +40,20 @@ def test_fp64_samples_workload_8aa_and_100aa():
         assert mism == 0
 
 
+@pytest.mark.parametrize("model", ["bulge_rich", "interior_rich"])
+def test_fp64_samples_loop_rich_models(model):
+    """Draw for draw under tables where long bulges and interior loops are
+    frequent, so that every window branch of the pair decision is taken."""
+    en = getattr(I, f"{model}_energy")(7)
+    prob, _ = I.workload(2, m=40)
+    seed = I.sampler_seed(2, 1)
+    oc, op = oracle.sample(prob, en, seed, 200)
+    gc, gp = B.cdz_sample(B.cdz_create(en, "fp64"), prob, seed, 200)
+    mism = int(np.sum(np.any(oc != gc, axis=1) | np.any(op != gp, axis=1)))
+    print(model, "mismatching samples", mism, flush=True)
+    assert mism == 0
+
+
 def _joint_tv(cod, pairs, joint):
     N = len(cod)
     cnt = collections.Counter()
