@@ -24,7 +24,8 @@
 
 #define CDZ_NT 256      // threads per workgroup of the cell kernels
 #define CDZ_MAXLOOP 30  // bulge / interior loop size bound
-#define CDZ_MAX_LDS 65536  // dynamic LDS per workgroup the diagonal kernels may ask for
+#define CDZ_NA 27      // interior-loop sizes L = 2..28 kept per cell (the recursion in
+                       // L reads L - 2 <= 28; sizes 29, 30 only feed the cell itself)
 #define CDZ_NWIN 496    // (l1, l2) pairs with l1 + l2 <= 30, including (0, 0)
 
 // Boltzmann table offsets inside DevProb::tab
@@ -52,6 +53,10 @@ struct DevProb {
   const T *Bhp;            // [n] hairpin factor by loop length L (mismatch excluded)
   // forward arrays, S x S each (see header comment)
   T *U, *Qb, *G, *F, *DI, *Qm1, *Qm1Lr, *Qm1Lt, *Qm1p, *QmX, *Qm, *Qmt;
+  // interior-loop sums by loop size: A(i,j,L), L = 2..CDZ_NA+1, for the cell
+  // (i,j) at rows P[i+1].. and columns CDZ_NA*P[j-1] + (L-2)*d[j-1] + ..
+  T *AL;
+  long long ldA;           // CDZ_NA * ld
   int *E;                  // [n + 1] diagonal exponents
   unsigned *maxb;          // [n + 1] float bits of max |entry| per diagonal
   double *Z5;              // [n][6] prefix exterior partition function

@@ -216,9 +216,23 @@ struct CellStage {
   T M1pr[36];  // Qm1p[i+1][j]
   T Ul[36];    // U[i][j-1]
   T split[36], gf[72], qb[36], qm1[36];
+  T eI1[36], eJm2[36], vI1[6], vJm1[6];  // e_{i+1}, e_{j-2}, v_{i+1}, v_{j-1}
   signed char nt[6][6];  // bases of positions i-1, i, i+1, j-1, j, j+1
   int d[6], P[6];
+  int wd[64], wP[64];    // d, P of positions i+1+q ([q]) and j-1-q ([32+q])
 };
+
+// Blocks of 36 values staged for the loops closed by a cell (after the stage)
+#define CDZ_FWD_WBLK 173
+
+template <typename T>
+size_t fwd_lds_bytes(int n) {
+  const size_t head = ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 72) * sizeof(T);
+  const size_t st = (sizeof(CellStage<T>) + 15) / 16 * 16;
+  return head + st + (size_t)CDZ_FWD_WBLK * 36 * sizeof(T);
+}
+template size_t fwd_lds_bytes<float>(int);
+template size_t fwd_lds_bytes<double>(int);
 
 template <typename T>
 __device__ __forceinline__ void stage_block(T *dst, const T *A, long long ld, int r0, int c0, int dr,
@@ -238,6 +252,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
   int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1]
   T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(D.n + 1) * 4 + 15) / 16 * 16);
   CellStage<T> &C = *reinterpret_cast<CellStage<T> *>(red + (CDZ_NT / 64) * 72);
+  T *W = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(CellStage<T>) + 15) / 16 * 16);
   const int n = D.n, tid = threadIdx.x;
   const long long ld = D.ld;
   for (int k = tid; k < dl && k <= n; k += CDZ_NT) sE[k] = D.E[k];
@@ -264,6 +279,13 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
     for (int s = 0; s < 6; s++) C.nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
   }
   for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+  if (tid >= 64 && tid < 128) {
+    const int q = tid - 64;
+    const int p = q < 32 ? i + 1 + q : j - 1 - (q - 32);
+    const bool ok = p >= 0 && p < n;
+    C.wd[q] = ok ? D.d[p] : 0;
+    C.wP[q] = ok ? D.P[p] : 0;
+  }
   __syncthreads();
   const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
   const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
@@ -299,9 +321,13 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
         C.eI[q] = D.e[i * 36 + q];
         C.eJm1[q] = j >= 1 ? D.e[(j - 1) * 36 + q] : T(0);
         C.eJ[q] = D.e[j * 36 + q];
+        C.eI1[q] = i + 1 < n ? D.e[(i + 1) * 36 + q] : T(0);
+        C.eJm2[q] = j >= 2 ? D.e[(j - 2) * 36 + q] : T(0);
         if (q < 6) {
           C.vI[q] = D.v[i * 6 + q];
           C.vJ[q] = D.v[j * 6 + q];
+          C.vI1[q] = i + 1 < n ? D.v[(i + 1) * 6 + q] : T(0);
+          C.vJm1[q] = j >= 1 ? D.v[(j - 1) * 6 + q] : T(0);
         }
         break;
     }
@@ -371,113 +397,176 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
       }
       cdz_block_sum<T, 36>(acc, red, C.split);
     }
-    // ---- bulge and interior window: G (bulges, outer edges not applied),
-    //      F (interior loops, outer edges and outer mismatch not applied);
-    //      indices (a, dd) = slots of positions i+1 and j-1
+    // ---- bulge and interior loops closed by (i, j), indices (a, dd) = slots
+    //      of positions i+1 and j-1, outer edges and outer mismatch not
+    //      applied: G = bulges, F = interior loops.
+    //
+    //      Interior loops use the loop-size recursion (Lyngso's observation,
+    //      valid because the interior-loop energy depends on l1 + l2 and the
+    //      end mismatches only): with A(i,j,L) the sum over inner pairs at
+    //      total loop size L = l1 + l2 of U[i+1][k-1] . DI[k][l] . U[l+1][j-1],
+    //        A(i,j,L) = V . A(i+1,j-1,L-2) . W          (l1, l2 >= 2)
+    //                 + diag v_{i+1} . DI . U[j-L+1][j-1]  (l1 = 1)
+    //                 + U[i+1][i+L-1] . DI . diag v_{j-1}  (l2 = 1, L >= 3)
+    //      with V = v_{i+1} e_{i+1}, W = e_{j-2} v_{j-1}; F = sum_L w_int(L) A.
+    //      Every term needs an inner pair at distance >= 4, i.e. L <= dl - 6.
     {
-      T gf[72];
-#pragma unroll
-      for (int r = 0; r < 72; r++) gf[r] = 0;
-      const T *tab = C.tab;
-      for (int w = 1 + tid; w < CDZ_NWIN; w += CDZ_NT) {
-        int l1, l2;
-        cdz_win(w, l1, l2);
-        const int k = i + 1 + l1, l = j - 1 - l2;
-        if (l - k < 4) continue;
-        const int din = l - k, dk = D.d[k], dlp = D.d[l], Pk = D.P[k], Pl = D.P[l];
-        if (l2 == 0) {
-          // left bulge: run i+1..k-1, inner pair (k, j-1)
-          const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[din] - Ed);
-          const int db = D.d[k - 1], Pb = D.P[k - 1];
-          T q[36], ek[36], ul[36];
-#pragma unroll
-          for (int r = 0; r < 36; r++) {
-            q[r] = (r / 6 < dk && r % 6 < dlp) ? D.Qb[(Pk + r / 6) * ld + Pl + r % 6] : T(0);
-            ek[r] = D.e[(k - 1) * 36 + r];
-            ul[r] = (r / 6 < d1 && r % 6 < db) ? D.U[(P1 + r / 6) * ld + Pb + r % 6] : T(0);
+      const int lmax = min(CDZ_MAXLOOP, dl - 6);
+      T *UR1 = W;              // [l-1] U[i+1][i+l]
+      T *UC1 = W + 30 * 36;    // [l-1] U[j-l][j-1]
+      T *X = W + 60 * 36;      // phase-dependent blocks
+      T *DIrow = X;            // [L-2] DI[i+1][j-L+1]
+      T *DIcol = X + 29 * 36;  // [L-3] DI[i+L-1][j-1]
+      T *AP = X + 57 * 36;     // [L-2] A(i+1,j-1,L), then A(i+1,j-1,L) . W
+      T *AC = X + 84 * 36;     // [L-2] A(i,j,L)
+      const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
+      const int nAP = lmax - 3 > 0 ? lmax - 3 : 0;  // L = 2..lmax-2
+      if (lmax >= 1) {
+        const int n0 = lmax, n1 = 2 * lmax, n2 = n1 + (lmax - 1), n3 = n2 + (lmax >= 3 ? lmax - 2 : 0),
+                  n4 = n3 + nAP;
+        for (int idx = tid; idx < n4 * 36; idx += CDZ_NT) {
+          const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
+          T v = 0;
+          if (b < n0) {  // U[i+1][i+l], l = b + 1
+            if (r < d1 && c < lp_d[b]) v = D.U[(long long)(P1 + r) * ld + lp_P[b] + c];
+            UR1[b * 36 + q] = v;
+          } else if (b < n1) {  // U[j-l][j-1], l = b - n0 + 1
+            const int l = b - n0 + 1;
+            if (r < rp_d[l - 1] && c < dm) v = D.U[(long long)(rp_P[l - 1] + r) * ld + Pm + c];
+            UC1[(l - 1) * 36 + q] = v;
+          } else if (b < n2) {  // DI[i+1][j-L+1], L = b - n1 + 2
+            const int L = b - n1 + 2;
+            if (r < d1 && c < rp_d[L - 2]) v = D.DI[(long long)(P1 + r) * ld + rp_P[L - 2] + c];
+            DIrow[(L - 2) * 36 + q] = v;
+          } else if (b < n3) {  // DI[i+L-1][j-1], L = b - n2 + 3
+            const int L = b - n2 + 3;
+            if (r < lp_d[L - 2] && c < dm) v = D.DI[(long long)(lp_P[L - 2] + r) * ld + Pm + c];
+            DIcol[(L - 3) * 36 + q] = v;
+          } else {  // A(i+1, j-1, L), L = b - n3 + 2
+            const int L = b - n3 + 2;
+            if (r < lp_d[1] && c < rp_d[1])
+              v = D.AL[(long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + (L - 2) * rp_d[1] + c];
+            AP[(L - 2) * 36 + q] = v;
           }
-          T m[36];  // m(b, y) = sum_x e_{k-1}(b,x) Qb[k][l](x,y)
-#pragma unroll
-          for (int b = 0; b < 6; b++)
-#pragma unroll
-            for (int y = 0; y < 6; y++) {
-              T a = 0;
-#pragma unroll
-              for (int x = 0; x < 6; x++) a += ek[b * 6 + x] * q[x * 6 + y];
-              m[b * 6 + y] = a;
-            }
-#pragma unroll
-          for (int a = 0; a < 6; a++)
-#pragma unroll
-            for (int y = 0; y < 6; y++) {
-              T sm = 0;
-#pragma unroll
-              for (int b = 0; b < 6; b++) sm += ul[a * 6 + b] * m[b * 6 + y];
-              gf[a * 6 + y] += f * sm;
-            }
-        } else if (l1 == 0) {
-          // right bulge: inner pair (i+1, l), run l+1..j-1
-          const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[l2 - 1] + sE[din] - Ed);
-          const int dc = D.d[l + 1], Pc = D.P[l + 1];
-          T q[36], el[36], ur[36];
-#pragma unroll
-          for (int r = 0; r < 36; r++) {
-            q[r] = (r / 6 < dk && r % 6 < dlp) ? D.Qb[(Pk + r / 6) * ld + Pl + r % 6] : T(0);
-            el[r] = D.e[l * 36 + r];
-            ur[r] = (r / 6 < dc && r % 6 < dm) ? D.U[(Pc + r / 6) * ld + Pm + r % 6] : T(0);
-          }
-          T m[36];  // m(y, dd) = sum_c e_l(y,c) U[l+1][j-1](c,dd)
-#pragma unroll
-          for (int y = 0; y < 6; y++)
-#pragma unroll
-            for (int dd = 0; dd < 6; dd++) {
-              T a = 0;
-#pragma unroll
-              for (int c = 0; c < 6; c++) a += el[y * 6 + c] * ur[c * 6 + dd];
-              m[y * 6 + dd] = a;
-            }
-#pragma unroll
-          for (int x = 0; x < 6; x++)
-#pragma unroll
-            for (int dd = 0; dd < 6; dd++) {
-              T sm = 0;
-#pragma unroll
-              for (int y = 0; y < 6; y++) sm += q[x * 6 + y] * m[y * 6 + dd];
-              gf[x * 6 + dd] += f * sm;
-            }
-        } else {
-          // interior loop: U[i+1][k-1] . DI[k][l] . U[l+1][j-1]
-          const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[din] + sE[l2 - 1] - Ed);
-          const int db = D.d[k - 1], Pb = D.P[k - 1], dc = D.d[l + 1], Pc = D.P[l + 1];
-          T di_[36], ul[36], ur[36];
-#pragma unroll
-          for (int r = 0; r < 36; r++) {
-            di_[r] = (r / 6 < db && r % 6 < dc) ? D.DI[(Pb + r / 6) * ld + Pc + r % 6] : T(0);
-            ul[r] = (r / 6 < d1 && r % 6 < db) ? D.U[(P1 + r / 6) * ld + Pb + r % 6] : T(0);
-            ur[r] = (r / 6 < dc && r % 6 < dm) ? D.U[(Pc + r / 6) * ld + Pm + r % 6] : T(0);
-          }
-          T m[36];  // m(b, dd) = sum_c DI[k][l](b,c) U[l+1][j-1](c,dd)
-#pragma unroll
-          for (int b = 0; b < 6; b++)
-#pragma unroll
-            for (int dd = 0; dd < 6; dd++) {
-              T a = 0;
-#pragma unroll
-              for (int c = 0; c < 6; c++) a += di_[b * 6 + c] * ur[c * 6 + dd];
-              m[b * 6 + dd] = a;
-            }
-#pragma unroll
-          for (int a = 0; a < 6; a++)
-#pragma unroll
-            for (int dd = 0; dd < 6; dd++) {
-              T sm = 0;
-#pragma unroll
-              for (int b = 0; b < 6; b++) sm += ul[a * 6 + b] * m[b * 6 + dd];
-              gf[36 + a * 6 + dd] += f * sm;
-            }
         }
       }
-      cdz_block_sum<T, 72>(gf, red, C.gf);
+      __syncthreads();
+      // AP <- AP . W (in place: every output is read into registers first)
+      {
+        T t4[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int idx = tid + u * CDZ_NT;
+          t4[u] = 0;
+          if (idx < nAP * 36) {
+            const int b = idx / 36, q = idx % 36, a2 = q / 6, dd = q % 6;
+            T s = 0;
+#pragma unroll
+            for (int d2 = 0; d2 < 6; d2++) s += AP[b * 36 + a2 * 6 + d2] * C.eJm2[d2 * 6 + dd];
+            t4[u] = s * C.vJm1[dd];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int idx = tid + u * CDZ_NT;
+          if (idx < nAP * 36) AP[idx] = t4[u];
+        }
+      }
+      __syncthreads();
+      // A(i,j,L), L = 2..lmax
+      const T frec = cdz_p2<T>(sE[dl >= 2 ? dl - 2 : 0] - Ed);
+      for (int idx = tid; idx < (lmax - 1) * 36; idx += CDZ_NT) {
+        const int L = idx / 36 + 2, q = idx % 36, a = q / 6, dd = q % 6;
+        const T fb = cdz_p2<T>(sE[dl - L - 2] + sE[L - 2] - Ed);
+        T rec = 0, b1 = 0, b2 = 0;
+        if (L >= 4) {
+#pragma unroll
+          for (int a2 = 0; a2 < 6; a2++) rec += C.eI1[a * 6 + a2] * AP[(L - 4) * 36 + a2 * 6 + dd];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; c++) b1 += DIrow[(L - 2) * 36 + a * 6 + c] * UC1[(L - 2) * 36 + c * 6 + dd];
+        if (L >= 3) {
+#pragma unroll
+          for (int b = 0; b < 6; b++) b2 += UR1[(L - 2) * 36 + a * 6 + b] * DIcol[(L - 3) * 36 + b * 6 + dd];
+        }
+        AC[(L - 2) * 36 + q] = C.vI1[a] * (rec * frec + b1 * fb) + b2 * C.vJm1[dd] * fb;
+      }
+      __syncthreads();
+      // keep A(i,j,L), L = 2..CDZ_NA+1, for the cells of diagonal dl + 2 and
+      // the outside pass (zero where no inner pair fits)
+      for (int idx = tid; idx < CDZ_NA * 36; idx += CDZ_NT) {
+        const int L = idx / 36 + 2, q = idx % 36, a = q / 6, dd = q % 6;
+        if (a < d1 && dd < dm)
+          D.AL[(long long)(P1 + a) * D.ldA + (long long)CDZ_NA * Pm + (L - 2) * dm + dd] =
+              L <= lmax ? AC[(L - 2) * 36 + q] : T(0);
+      }
+      if (tid < 36) {
+        T f = 0;
+        for (int L = 2; L <= lmax; L++) f += C.tab[TB_IN + L] * AC[(L - 2) * 36 + tid];
+        C.gf[36 + tid] = f;
+      }
+      __syncthreads();
+      // bulges: left (run i+1..k-1, inner pair (k, j-1)), right (inner pair
+      // (i+1, l), run l+1..j-1), l = 1..lmax; one side after the other, each
+      // thread summing the terms term = g, g + 7, .. of output q
+      T *EB = X, *QB = X + 30 * 36;
+      T *GP = red;  // 7 x 36 partial sums (the reduction scratch is free here)
+      const int q = tid % 36, g = tid / 36, r = q / 6, c = q % 6;
+      T gacc = 0;
+      for (int side = 0; side < 2; side++) {
+        for (int idx = tid; idx < 2 * lmax * 36; idx += CDZ_NT) {
+          const int b = idx / 36, qq = idx % 36, rr = qq / 6, cc = qq % 6;
+          const int l = b % lmax + 1;
+          T v = 0;
+          if (b < lmax) {  // e_{k-1}, k = i+1+l (left) / e_l, l = j-1-l2 (right)
+            v = D.e[(long long)(side == 0 ? i + l : j - 1 - l) * 36 + qq];
+          } else if (side == 0) {  // Qb[i+1+l][j-1]
+            if (rr < lp_d[l] && cc < dm) v = D.Qb[(long long)(lp_P[l] + rr) * ld + Pm + cc];
+          } else {  // Qb[i+1][j-1-l]
+            if (rr < d1 && cc < rp_d[l]) v = D.Qb[(long long)(P1 + rr) * ld + rp_P[l] + cc];
+          }
+          (b < lmax ? EB : QB)[(l - 1) * 36 + qq] = v;
+        }
+        __syncthreads();
+        if (g < 7) {
+          for (int l = g + 1; l <= lmax; l += 7) {
+            const T f = C.tab[TB_BU + l] * cdz_p2<T>(sE[l - 1] + sE[dl - 2 - l] - Ed);
+            const T *ek = EB + (l - 1) * 36, *qk = QB + (l - 1) * 36;
+            T sm = 0;
+            if (side == 0) {  // output (a, y) = (r, c): U[i+1][k-1] e_{k-1} Qb[k][j-1]
+              const T *ul = UR1 + (l - 1) * 36;
+#pragma unroll
+              for (int b = 0; b < 6; b++) {
+                T m = 0;
+#pragma unroll
+                for (int x = 0; x < 6; x++) m += ek[b * 6 + x] * qk[x * 6 + c];
+                sm += ul[r * 6 + b] * m;
+              }
+            } else {  // output (x, dd) = (r, c): Qb[i+1][l] e_l U[l+1][j-1]
+              const T *ur = UC1 + (l - 1) * 36;
+#pragma unroll
+              for (int y = 0; y < 6; y++) {
+                T m = 0;
+#pragma unroll
+                for (int cc = 0; cc < 6; cc++) m += ek[y * 6 + cc] * ur[cc * 6 + c];
+                sm += qk[r * 6 + y] * m;
+              }
+            }
+            gacc += f * sm;
+          }
+        }
+        __syncthreads();
+      }
+      if (g < 7) GP[g * 36 + q] = gacc;
+      __syncthreads();
+      if (tid < 36) {
+        T gs = 0;
+#pragma unroll
+        for (int gg = 0; gg < 7; gg++) gs += GP[gg * 36 + tid];
+        C.gf[tid] = gs;
+      }
+      __syncthreads();
     }
     const T *tab = C.tab;
     // ---- Qb (one thread per slot pair), all operands in LDS

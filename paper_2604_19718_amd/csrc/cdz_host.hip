@@ -130,7 +130,8 @@ extern "C" cdz_status cdz_create(const cdz_energy *energy, const cdz_options *op
     h->opt.hip_stream = nullptr;
   }
   h->stream = reinterpret_cast<hipStream_t>(h->opt.hip_stream);
-  if (hipGetDevice(&h->device) != hipSuccess) {
+  if (hipGetDevice(&h->device) != hipSuccess ||
+      hipDeviceGetAttribute(&h->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess) {
     delete h;
     return CDZ_ERR_HIP;
   }
@@ -282,6 +283,8 @@ static size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A
   T **arrs[] = {&D.U, &D.Qb, &D.G, &D.F, &D.DI, &D.Qm1, &D.Qm1Lr, &D.Qm1Lt,
                 &D.Qm1p, &D.QmX, &D.Qm, &D.Qmt};
   for (T **a : arrs) *a = c.take<T>(base, S2);
+  D.ldA = (long long)CDZ_NA * ld;
+  D.AL = c.take<T>(base, (size_t)CDZ_NA * S2);
   if (adjoint) adj_carve<T>(c.off, base, t, A, S2);
   return c.off + 256;
 }
@@ -309,12 +312,6 @@ static cdz_status upload(cdz_handle *h, const HostTables &t, DevProb<T> &D) {
 template <typename T>
 __global__ void cdz_fwd_diag(DevProb<T> D, int dl);
 
-template <typename T>
-static size_t fwd_shmem(int n) {
-  // exponents, reduction scratch, and the cell stage (see cdz_fwd.hip)
-  const size_t stage = (size_t)(TB_LEN + 4 * 36 + 12 + 6 * 36 + 36 + 72 + 36 + 36) * sizeof(T) + 36 + 48 + 64;
-  return ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 72) * sizeof(T) + stage;
-}
 
 template <typename T>
 __global__ void cdz_rescale(DevProb<T> D);
@@ -323,9 +320,10 @@ template <typename T>
 static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   const int n = D.n;
   hipStream_t st = h->stream;
-  const size_t shm = fwd_shmem<T>(n);
-  if (shm > CDZ_MAX_LDS)
+  const size_t shm = fwd_lds_bytes<T>(n);
+  if (shm > (size_t)h->lds_max)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the forward kernel");
+  HIPCHK(h, hipFuncSetAttribute((const void *)cdz_fwd_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
   // FP32: a first pass finds the free-energy landscape (prefix exterior
   // partition function), the vertex factors are rescaled by it, and the
   // second pass runs on the rescaled tables.  FP64 has the range for one pass.

@@ -36,6 +36,9 @@ struct HostTables {
 template <typename T>
 struct DevAdj {
   T *Qbb, *Qm1b, *Qm1pb, *QmXb, *QmXbt, *Qmb, *Qm1Lb, *DIb, *Gb, *Fb, *Ub, *UbL, *UbR;
+  T *DIbL, *DIbR;  // DI adjoint pushed along row i+1 / column j-1 of the enclosing cells
+  T *ring;         // [3][n][CDZ_NA][36] interior-loop adjoints by size, last three diagonals
+  double *etaV, *etaW;  // [n][36] edge-marginal terms of the size recursion
   double *eta;   // [n][6][6] edge marginals times Z / 2^EZ
   double *pair;  // [n][n] pair probabilities (upper triangle)
   double *out;   // [16] scalars
@@ -49,6 +52,7 @@ struct cdz_handle {
   cdz_options opt;
   hipStream_t stream = nullptr;
   int device = 0;
+  int lds_max = 65536;  // dynamic LDS a workgroup may use on this device
   std::string err;
   void *ws = nullptr;
   size_t ws_bytes = 0;
@@ -81,6 +85,11 @@ inline void store_dev(cdz_handle *h, const DevProb<double> &D, const DevAdj<doub
   h->pd = D;
   h->ad = A;
 }
+
+template <typename T>
+size_t fwd_lds_bytes(int n);  // dynamic LDS of the forward diagonal kernel
+template <typename T>
+size_t out_lds_bytes(int n);  // dynamic LDS of the outside diagonal kernel
 
 cdz_status cdz_fail(cdz_handle *h, cdz_status s, const std::string &msg);
 cdz_status build_tables(cdz_handle *h, int32_t n_aa, const char *aa, const double *theta1,

@@ -28,8 +28,11 @@ void adj_carve(size_t &off, char *base, const HostTables &t, DevAdj<T> &A, size_
     return p;
   };
   T **arrs[] = {&A.Qbb, &A.Qm1b, &A.Qm1pb, &A.QmXb, &A.QmXbt, &A.Qmb, &A.Qm1Lb,
-                &A.DIb, &A.Gb, &A.Fb, &A.Ub, &A.UbL, &A.UbR};
+                &A.DIb, &A.Gb, &A.Fb, &A.Ub, &A.UbL, &A.UbR, &A.DIbL, &A.DIbR};
   for (T **a : arrs) *a = reinterpret_cast<T *>(take(S2 * sizeof(T)));
+  A.ring = reinterpret_cast<T *>(take((size_t)3 * t.n * CDZ_NA * 36 * sizeof(T)));
+  A.etaV = reinterpret_cast<double *>(take((size_t)t.n * 36 * sizeof(double)));
+  A.etaW = reinterpret_cast<double *>(take((size_t)t.n * 36 * sizeof(double)));
   A.eta = reinterpret_cast<double *>(take((size_t)t.n * 36 * sizeof(double)));
   A.pair = reinterpret_cast<double *>(take((size_t)t.n * t.n * sizeof(double)));
   A.out = reinterpret_cast<double *>(take(16 * sizeof(double)));
@@ -37,17 +40,14 @@ void adj_carve(size_t &off, char *base, const HostTables &t, DevAdj<T> &A, size_
 template void adj_carve<float>(size_t &, char *, const HostTables &, DevAdj<float> &, size_t);
 template void adj_carve<double>(size_t &, char *, const HostTables &, DevAdj<double> &, size_t);
 
-#define NRUN 30  // run lengths 1..30: interior-loop runs reach 29, a bulge
-                 // (the other side empty) reaches 30
-
 // LDS stage of one cell of the outside pass (see cdz_fwd.hip for the idea):
 // all small operands of the cell's O(1) adjoint statements, fetched by one
-// parallel load phase, plus the per-cell accumulators of the run pushes.
+// parallel load phase.
 template <typename T>
 struct OutStage {
   T tab[TB_LEN];
-  T eIm1[36], eI[36], eJm1[36], eJ[36];
-  T vIm1[6], vI[6], vJ[6], vJp1[6];
+  T eIm1[36], eI[36], eJm1[36], eJ[36], eI1[36], eJm2[36];
+  T vIm1[6], vI[6], vJ[6], vJp1[6], vI1[6], vJm1[6];
   T m1pUp[36];   // Qm1p'[i-1][j]
   T m1Right[36]; // Qm1'[i][j+1]
   T qbOut[36];   // Qb'[i-1][j+1]
@@ -55,24 +55,37 @@ struct OutStage {
   T ubRight[36]; // U'[i][j+1]
   T ubl[36], ubr[36];  // pushed run adjoints of [i..j]
   T acc[72], w[72], qm1pb[36], qm1lb[36], qm1b[36], qbb[36], gb[36], fb[36];
-  T Tl[NRUN * 36], Vl[NRUN * 36];
-  T accL[NRUN * 36], accR[NRUN * 36];
   double z5[6], z3[6], edm1[36];
   signed char nt[6][6];
   int d[6], P[6];
+  // d, P of positions i+1+q ([q]), j-1-q ([32+q]), i-1-q ([64+q]), j+1+q ([96+q])
+  int wd[128], wP[128];
 };
 
+// Blocks of 36 values for the loop terms of a cell: the adjoints of the
+// interior-loop sums by size (29) and one phase-dependent region (127).
+#define CDZ_OUT_WBLK (29 + 127)
+
 template <typename T>
-static size_t out_shmem(int n) {
-  return ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 72) * sizeof(T) +
-         sizeof(OutStage<T>) + 64;
+size_t out_lds_bytes(int n) {
+  const size_t head = ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 72) * sizeof(T);
+  const size_t st = (sizeof(OutStage<T>) + 15) / 16 * 16;
+  return head + st + (size_t)CDZ_OUT_WBLK * 36 * sizeof(T);
 }
+template size_t out_lds_bytes<float>(int);
+template size_t out_lds_bytes<double>(int);
 
 template <typename T>
 __device__ __forceinline__ void ostage(T *dst, const T *A, long long ld, int r0, int c0, int dr, int dc,
                                        int q, bool ok) {
   const int r = q / 6, c = q % 6;
   dst[q] = (ok && r < dr && c < dc) ? A[(long long)(r0 + r) * ld + c0 + c] : T(0);
+}
+
+// ring of interior-loop adjoints: diagonal dl, cell i, size L (4..30)
+template <typename T>
+__device__ __forceinline__ T *ring_at(const DevAdj<T> &A, int n, int dl, int i, int L) {
+  return A.ring + (((long long)(dl % 3) * n + i) * CDZ_NA + (L - 4)) * 36;
 }
 
 template <typename T>
@@ -83,6 +96,8 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
   int *sE = reinterpret_cast<int *>(smem_raw);
   T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
   OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
+  T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
+  T *X = AB + 29 * 36;
   for (int k = tid; k < n; k += CDZ_NT) sE[k] = D.E[k];
   const int EZ = (int)D.res[2];
   const int i = blockIdx.x, j = i + dl;
@@ -96,11 +111,20 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
     for (int s = 0; s < 6; s++) C.nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
   }
   for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+  if (tid >= 128) {
+    const int q = tid - 128, grp = q / 32, o = q % 32;
+    const int p = grp == 0 ? i + 1 + o : grp == 1 ? j - 1 - o : grp == 2 ? i - 1 - o : j + 1 + o;
+    const bool ok = p >= 0 && p < n;
+    C.wd[q] = ok ? D.d[p] : 0;
+    C.wP[q] = ok ? D.P[p] : 0;
+  }
   __syncthreads();
   const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
   const int dim1 = C.d[0], Pim1 = C.P[0], djp1 = C.d[5], Pjp1 = C.P[5];
   const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
   const bool hasL = i >= 1, hasR = j + 1 <= n - 1;
+  const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
+  const int *ll_d = C.wd + 64, *ll_P = C.wP + 64, *rr_d = C.wd + 96, *rr_P = C.wP + 96;
   {
     const int g = tid / 36, q = tid % 36;
     switch (g) {
@@ -122,6 +146,8 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         C.eI[q] = D.e[i * 36 + q];
         C.eJm1[q] = j >= 1 ? D.e[(j - 1) * 36 + q] : T(0);
         C.eJ[q] = D.e[j * 36 + q];
+        C.eI1[q] = i + 1 < n ? D.e[(i + 1) * 36 + q] : T(0);
+        C.eJm2[q] = j >= 2 ? D.e[(j - 2) * 36 + q] : T(0);
         break;
       case 4:
         C.edm1[q] = hasL ? D.ed[(i - 1) * 36 + q] : 0.0;
@@ -130,16 +156,29 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
           C.vI[q] = D.v[i * 6 + q];
           C.vJ[q] = D.v[j * 6 + q];
           C.vJp1[q] = hasR ? D.v[(j + 1) * 6 + q] : T(0);
+          C.vI1[q] = i + 1 < n ? D.v[(i + 1) * 6 + q] : T(0);
+          C.vJm1[q] = j >= 1 ? D.v[(j - 1) * 6 + q] : T(0);
           C.z5[q] = hasL ? D.Z5[(i - 1) * 6 + q] : 0.0;
           C.z3[q] = D.Z3[j * 6 + q];
         }
         break;
+      case 5: {
+        // adjoint of DI at block (i-1, j+1): pushed by the enclosing loops
+        T v = 0;
+        const int r = q / 6, c = q % 6;
+        if (hasL && hasR && r < dim1 && c < djp1) {
+          const long long o = (long long)(Pim1 + r) * ld + Pjp1 + c;
+          v = A.DIbL[o] + A.DIbR[o];
+        }
+        C.w[q] = v;
+        break;
+      }
     }
   }
   __syncthreads();
   const T *tab = C.tab;
-
   if (dl >= 4) {
+    const int lmax = min(CDZ_MAXLOOP, dl - 6);
     // ---- split gathers: Qm'[i][j] along row i, Qm1L'[i][j] down column j
     {
       constexpr int UN = sizeof(T) == 4 ? 4 : 2;
@@ -202,113 +241,79 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
       }
       cdz_block_sum<T, 72>(acc, red, C.acc);
     }
-    // ---- window gathers: DI'[i][j] from enclosing interior loops, and the
-    //      bulge part of Qb'[i][j] from enclosing bulges
+    // ---- bulges enclosing the pair (i, j): the bulge part of Qb'[i][j].
+    //      Left bulge (i-l1-1, j+1): run i-l1..i-1; right bulge
+    //      (i-1, j+l2+1): run j+1..j+l2.
     {
-      T w[72];
-#pragma unroll
-      for (int r = 0; r < 72; r++) w[r] = 0;
-      for (int win = 1 + tid; win < CDZ_NWIN; win += CDZ_NT) {
-        int l1, l2;
-        cdz_win(win, l1, l2);
-        if (l1 >= 1 && l2 >= 1) {
-          const int I = i - l1 - 1, J = j + l2 + 1;
-          if (I < 0 || J > n - 1) continue;
-          const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[dl] + sE[l2 - 1] - sE[dl + l1 + l2 + 2]);
-          const int pa = i - l1, da = D.d[pa], Pa = D.P[pa];
-          const int pz = j + l2, dz = D.d[pz], Pz = D.P[pz];
-          T ul[36], fbk[36], ur[36];
-#pragma unroll
-          for (int r = 0; r < 36; r++) {
-            const int r0 = r / 6, r1 = r % 6;
-            ul[r] = (r0 < da && r1 < dim1) ? D.U[(Pa + r0) * ld + Pim1 + r1] : T(0);
-            fbk[r] = (r0 < da && r1 < dz) ? A.Fb[(Pa + r0) * ld + Pz + r1] : T(0);
-            ur[r] = (r0 < djp1 && r1 < dz) ? D.U[(Pjp1 + r0) * ld + Pz + r1] : T(0);
+      const int nl = hasR ? min(CDZ_MAXLOOP, i - 1) : 0;
+      const int nr = hasL ? min(CDZ_MAXLOOP, n - 2 - j) : 0;
+      T *Ulc = X, *Gbc = X + 30 * 36, *Urr = X + 60 * 36, *Gbr = X + 90 * 36, *GP = X + 120 * 36;
+      for (int idx = tid; idx < 2 * (nl + nr) * 36; idx += CDZ_NT) {
+        const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
+        T v = 0;
+        if (b < 2 * nl) {
+          const int kind = b / nl, l1 = b % nl + 1, pa = l1 - 1;  // position i - l1
+          if (kind == 0) {  // U[i-l1][i-1]
+            if (r < ll_d[pa] && c < dim1) v = D.U[(long long)(ll_P[pa] + r) * ld + Pim1 + c];
+            Ulc[(l1 - 1) * 36 + q] = v;
+          } else {  // Gb at block (i-l1, j)
+            if (r < ll_d[pa] && c < dj) v = A.Gb[(long long)(ll_P[pa] + r) * ld + Pj + c];
+            Gbc[(l1 - 1) * 36 + q] = v;
           }
-          T m[36];  // m(b, dd) = sum_a U[pa][i-1](a,b) Fb[pa][pz](a,dd)
-#pragma unroll
-          for (int b = 0; b < 6; b++)
-#pragma unroll
-            for (int dd = 0; dd < 6; dd++) {
-              T sm = 0;
-#pragma unroll
-              for (int a = 0; a < 6; a++) sm += ul[a * 6 + b] * fbk[a * 6 + dd];
-              m[b * 6 + dd] = sm;
-            }
-#pragma unroll
-          for (int b = 0; b < 6; b++)
-#pragma unroll
-            for (int c = 0; c < 6; c++) {
-              T sm = 0;
-#pragma unroll
-              for (int dd = 0; dd < 6; dd++) sm += m[b * 6 + dd] * ur[c * 6 + dd];
-              w[b * 6 + c] += f * sm;
-            }
-        } else if (l2 == 0) {
-          // enclosing left bulge (i-l1-1, j+1): run i-l1..i-1, inner pair (i, j)
-          if (i - l1 - 1 < 0 || !hasR) continue;
-          const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[dl] - sE[dl + l1 + 2]);
-          const int pa = i - l1, da = D.d[pa], Pa = D.P[pa];
-          T ul[36], g[36];
-#pragma unroll
-          for (int r = 0; r < 36; r++) {
-            const int r0 = r / 6, r1 = r % 6;
-            ul[r] = (r0 < da && r1 < dim1) ? D.U[(Pa + r0) * ld + Pim1 + r1] : T(0);
-            g[r] = (r0 < da && r1 < dj) ? A.Gb[(Pa + r0) * ld + Pj + r1] : T(0);
-          }
-          T m[36];  // m(a, x) = sum_b U[pa][i-1](a,b) e_{i-1}(b,x)
-#pragma unroll
-          for (int a = 0; a < 6; a++)
-#pragma unroll
-            for (int x = 0; x < 6; x++) {
-              T sm = 0;
-#pragma unroll
-              for (int b = 0; b < 6; b++) sm += ul[a * 6 + b] * C.eIm1[b * 6 + x];
-              m[a * 6 + x] = sm;
-            }
-#pragma unroll
-          for (int x = 0; x < 6; x++)
-#pragma unroll
-            for (int y = 0; y < 6; y++) {
-              T sm = 0;
-#pragma unroll
-              for (int a = 0; a < 6; a++) sm += m[a * 6 + x] * g[a * 6 + y];
-              w[36 + x * 6 + y] += f * sm;
-            }
         } else {
-          // enclosing right bulge (i-1, j+l2+1): inner pair (i, j), run j+1..j+l2
-          if (!hasL || j + l2 + 1 > n - 1) continue;
-          const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[dl] + sE[l2 - 1] - sE[dl + l2 + 2]);
-          const int pz = j + l2, dz = D.d[pz], Pz = D.P[pz];
-          T ur[36], g[36];
-#pragma unroll
-          for (int r = 0; r < 36; r++) {
-            const int r0 = r / 6, r1 = r % 6;
-            ur[r] = (r0 < djp1 && r1 < dz) ? D.U[(Pjp1 + r0) * ld + Pz + r1] : T(0);
-            g[r] = (r0 < di && r1 < dz) ? A.Gb[(Pi + r0) * ld + Pz + r1] : T(0);
+          const int bb = b - 2 * nl, kind = bb / nr, l2 = bb % nr + 1, pz = l2 - 1;  // position j + l2
+          if (kind == 0) {  // U[j+1][j+l2]
+            if (r < djp1 && c < rr_d[pz]) v = D.U[(long long)(Pjp1 + r) * ld + rr_P[pz] + c];
+            Urr[(l2 - 1) * 36 + q] = v;
+          } else {  // Gb at block (i, j+l2)
+            if (r < di && c < rr_d[pz]) v = A.Gb[(long long)(Pi + r) * ld + rr_P[pz] + c];
+            Gbr[(l2 - 1) * 36 + q] = v;
           }
-          T m[36];  // m(y, dd) = sum_c e_j(y,c) U[j+1][pz](c,dd)
-#pragma unroll
-          for (int y = 0; y < 6; y++)
-#pragma unroll
-            for (int dd = 0; dd < 6; dd++) {
-              T sm = 0;
-#pragma unroll
-              for (int c = 0; c < 6; c++) sm += C.eJ[y * 6 + c] * ur[c * 6 + dd];
-              m[y * 6 + dd] = sm;
-            }
-#pragma unroll
-          for (int x = 0; x < 6; x++)
-#pragma unroll
-            for (int y = 0; y < 6; y++) {
-              T sm = 0;
-#pragma unroll
-              for (int dd = 0; dd < 6; dd++) sm += g[x * 6 + dd] * m[y * 6 + dd];
-              w[36 + x * 6 + y] += f * sm;
-            }
         }
       }
-      cdz_block_sum<T, 72>(w, red, C.w);
+      __syncthreads();
+      const int q = tid % 36, g = tid / 36, x = q / 6, y = q % 6;
+      if (g < 7) {
+        T acc = 0;
+        for (int term = g; term < nl + nr; term += 7) {
+          if (term < nl) {
+            const int l1 = term + 1;
+            const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[dl] - sE[dl + l1 + 2]);
+            const T *ul = Ulc + (l1 - 1) * 36, *gg = Gbc + (l1 - 1) * 36;
+            T s = 0;
+#pragma unroll
+            for (int a = 0; a < 6; a++) {
+              T m = 0;
+#pragma unroll
+              for (int b = 0; b < 6; b++) m += ul[a * 6 + b] * C.eIm1[b * 6 + x];
+              s += m * gg[a * 6 + y];
+            }
+            acc += f * s;
+          } else {
+            const int l2 = term - nl + 1;
+            const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[dl] + sE[l2 - 1] - sE[dl + l2 + 2]);
+            const T *ur = Urr + (l2 - 1) * 36, *gg = Gbr + (l2 - 1) * 36;
+            T s = 0;
+#pragma unroll
+            for (int dd = 0; dd < 6; dd++) {
+              T m = 0;
+#pragma unroll
+              for (int c = 0; c < 6; c++) m += C.eJ[y * 6 + c] * ur[c * 6 + dd];
+              s += gg[x * 6 + dd] * m;
+            }
+            acc += f * s;
+          }
+        }
+        GP[g * 36 + q] = acc;
+      }
+      __syncthreads();
+      if (tid < 36) {
+        T s = 0;
+#pragma unroll
+        for (int gg = 0; gg < 7; gg++) s += GP[gg * 36 + tid];
+        C.w[36 + tid] = s;
+      }
+      __syncthreads();
     }
     const int s = tid / 6, t = tid % 6;
     // ---- Qm', QmX', Qm1p', Qm1L', DI' (all operands in LDS)
@@ -429,134 +434,207 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
       C.gb[tid] = gb;
       C.fb[tid] = fb;
     }
-    __syncthreads();
-    // ---- run adjoints of this cell's loops.  T_L(a, c) = sum_dd Fb(a,dd)
-    //      U[j-L][j-1](c,dd); V_L(b, dd) = sum_a U[i+1][i+L](a,b) Fb(a,dd)
-    for (int idx = tid; idx < 2 * NRUN * 36; idx += CDZ_NT) {
-      const int side = idx / (NRUN * 36), rem = idx % (NRUN * 36), L = rem / 36 + 1, q = rem % 36;
-      const int r0 = q / 6, r1 = q % 6;
-      T val = 0;
-      if (side == 0) {
-        const int pc = j - L;
-        if (pc > i + 1) {
-          const int dc = D.d[pc], Pc = D.P[pc];
-          T u[6];
+    // ---- adjoints of the interior-loop sums by size, AB[L-2] = A'(i,j,L):
+    //      from F (F = sum_L w_int(L) A) and, through the size recursion,
+    //      from the enclosing cell (i-1, j+1) at size L + 2 (kept in a ring
+    //      of three diagonals)
+    const bool pull = hasL && hasR && lmax >= 2;
+    {
+      T *APV = X, *TB = X + 27 * 36;
+      const int npull = pull ? min(lmax, 28) - 1 : 0;  // L = 2..min(lmax, 28)
+      for (int idx = tid; idx < npull * 36; idx += CDZ_NT) {
+        const int b = idx / 36, q = idx % 36;
+        APV[idx] = ring_at(A, n, dl + 2, i - 1, b + 4)[q];
+      }
+      __syncthreads();
+      // TB(a, d') = sum_dd A'(i-1,j+1,L+2)(a,dd) e_{j-1}(d',dd) v_j(dd)
+      for (int idx = tid; idx < npull * 36; idx += CDZ_NT) {
+        const int b = idx / 36, q = idx % 36, a = q / 6, d2 = q % 6;
+        T v = 0;
 #pragma unroll
-          for (int dd = 0; dd < 6; dd++) u[dd] = (r1 < dc && dd < dm) ? D.U[(Pc + r1) * ld + Pm + dd] : T(0);
+        for (int dd = 0; dd < 6; dd++) v += APV[b * 36 + a * 6 + dd] * C.eJm1[d2 * 6 + dd] * C.vJ[dd];
+        TB[idx] = v;
+      }
+      __syncthreads();
+      const T frA = pull ? cdz_p2<T>(sE[dl] - sE[dl + 2]) : T(0);
+      for (int idx = tid; idx < 29 * 36; idx += CDZ_NT) {
+        const int L = idx / 36 + 2, q = idx % 36, a2 = q / 6, d2 = q % 6;
+        T v = 0;
+        if (L <= lmax) {
+          v = tab[TB_IN + L] * C.fb[q];
+          if (L - 2 < npull) {
+            T r = 0;
 #pragma unroll
-          for (int dd = 0; dd < 6; dd++) val += C.fb[r0 * 6 + dd] * u[dd];
+            for (int a = 0; a < 6; a++) r += C.vI[a] * C.eI[a * 6 + a2] * TB[(L - 2) * 36 + a * 6 + d2];
+            v += frA * r;
+          }
         }
-        C.Tl[rem] = val;
-        C.accL[rem] = 0;
-      } else {
-        const int pb = i + L;
-        if (pb < j - 1) {
-          const int db = D.d[pb], Pb = D.P[pb];
-          T u[6];
-#pragma unroll
-          for (int a = 0; a < 6; a++) u[a] = (a < d1 && r0 < db) ? D.U[(P1 + a) * ld + Pb + r0] : T(0);
-#pragma unroll
-          for (int a = 0; a < 6; a++) val += u[a] * C.fb[a * 6 + r1];
+        AB[idx] = v;
+        if (L >= 4) ring_at(A, n, dl, i, L)[q] = v;
+      }
+      __syncthreads();
+    }
+    if (lmax >= 2) {
+      // ---- interior loops closed by (i, j): adjoints of the blocks the size
+      //      recursion reads directly (the l1 = 1 and l2 = 1 terms)
+      T *UR1 = X, *UC1 = X + 30 * 36, *DIrow = X + 60 * 36, *DIcol = X + 89 * 36;
+      {
+        const int n0 = lmax, n1 = 2 * lmax, n2 = n1 + (lmax - 1), n3 = n2 + (lmax - 2);
+        for (int idx = tid; idx < n3 * 36; idx += CDZ_NT) {
+          const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
+          T v = 0;
+          if (b < n0) {  // U[i+1][i+l], l = b + 1
+            if (r < d1 && c < lp_d[b]) v = D.U[(long long)(P1 + r) * ld + lp_P[b] + c];
+            UR1[b * 36 + q] = v;
+          } else if (b < n1) {  // U[j-l][j-1]
+            const int l = b - n0 + 1;
+            if (r < rp_d[l - 1] && c < dm) v = D.U[(long long)(rp_P[l - 1] + r) * ld + Pm + c];
+            UC1[(l - 1) * 36 + q] = v;
+          } else if (b < n2) {  // DI[i+1][j-L+1]
+            const int L = b - n1 + 2;
+            if (r < d1 && c < rp_d[L - 2]) v = D.DI[(long long)(P1 + r) * ld + rp_P[L - 2] + c];
+            DIrow[(L - 2) * 36 + q] = v;
+          } else {  // DI[i+L-1][j-1]
+            const int L = b - n2 + 3;
+            if (r < lp_d[L - 2] && c < dm) v = D.DI[(long long)(lp_P[L - 2] + r) * ld + Pm + c];
+            DIcol[(L - 2) * 36 + q] = v;
+          }
         }
-        C.Vl[rem] = val;
-        C.accR[rem] = 0;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < 4 * 29 * 36; idx += CDZ_NT) {
+        const int kind = idx / (29 * 36), rem = idx % (29 * 36), L = rem / 36 + 2, q = rem % 36;
+        const int r = q / 6, c = q % 6;
+        if (L > lmax || (L < 3 && (kind == 1 || kind == 3))) continue;
+        const T fb = cdz_p2<T>(sE[dl - L - 2] + sE[L - 2] - sE[dl]);
+        const T *ab = AB + (L - 2) * 36;
+        T v = 0;
+        if (kind == 0) {  // DI'[i+1][j-L+1](a, c)
+          if (r < d1 && c < rp_d[L - 2]) {
+#pragma unroll
+            for (int dd = 0; dd < 6; dd++) v += ab[r * 6 + dd] * UC1[(L - 2) * 36 + c * 6 + dd];
+            A.DIbL[(long long)(P1 + r) * ld + rp_P[L - 2] + c] += fb * C.vI1[r] * v;
+          }
+        } else if (kind == 1) {  // DI'[i+L-1][j-1](b, dd)
+          if (r < lp_d[L - 2] && c < dm) {
+#pragma unroll
+            for (int a = 0; a < 6; a++) v += UR1[(L - 2) * 36 + a * 6 + r] * ab[a * 6 + c];
+            A.DIbR[(long long)(lp_P[L - 2] + r) * ld + Pm + c] += fb * C.vJm1[c] * v;
+          }
+        } else if (kind == 2) {  // U'[j-L+1][j-1](c, dd), run of L - 1
+          if (r < rp_d[L - 2] && c < dm) {
+#pragma unroll
+            for (int a = 0; a < 6; a++) v += C.vI1[a] * DIrow[(L - 2) * 36 + a * 6 + r] * ab[a * 6 + c];
+            A.UbR[(long long)(rp_P[L - 2] + r) * ld + Pm + c] += fb * v;
+          }
+        } else {  // U'[i+1][i+L-1](a, b), run of L - 1
+          if (r < d1 && c < lp_d[L - 2]) {
+#pragma unroll
+            for (int dd = 0; dd < 6; dd++) v += ab[r * 6 + dd] * C.vJm1[dd] * DIcol[(L - 2) * 36 + c * 6 + dd];
+            A.UbL[(long long)(P1 + r) * ld + lp_P[L - 2] + c] += fb * v;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (lmax >= 4) {
+      // ---- edges e_{i+1} (in V) and e_{j-2} (in W) of the size recursion:
+      //      their share of the edge marginals
+      T *AP = X, *TM = X + 27 * 36, *SM = X + 54 * 36;
+      const int nAP = lmax - 3;  // A(i+1, j-1, L'), L' = 2..lmax-2
+      for (int idx = tid; idx < nAP * 36; idx += CDZ_NT) {
+        const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
+        T v = 0;
+        if (r < lp_d[1] && c < rp_d[1])
+          v = D.AL[(long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + b * rp_d[1] + c];
+        AP[idx] = v;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < nAP * 36; idx += CDZ_NT) {
+        const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
+        T tm = 0, sm = 0;
+#pragma unroll
+        for (int u = 0; u < 6; u++) {
+          tm += AP[b * 36 + r * 6 + u] * C.eJm2[u * 6 + c];
+          sm += C.eI1[r * 6 + u] * AP[b * 36 + u * 6 + c];
+        }
+        TM[idx] = tm * C.vJm1[c];  // (A . W)(a', dd)
+        SM[idx] = C.vI1[r] * sm;   // (V . A)(a, d')
+      }
+      __syncthreads();
+      const T frec = cdz_p2<T>(sE[dl - 2] - sE[dl]);
+      if (tid < 72) {
+        const int q = tid % 36, r = q / 6, c = q % 6;
+        T v = 0;
+        if (tid < 36) {  // e_{i+1}(a, a') with (a, a') = (r, c)
+          for (int L = 4; L <= lmax; L++)
+#pragma unroll
+            for (int dd = 0; dd < 6; dd++) v += AB[(L - 2) * 36 + r * 6 + dd] * TM[(L - 4) * 36 + c * 6 + dd];
+          v *= frec * C.vI1[r] * C.eI1[q];
+          A.etaV[(long long)(i + 1) * 36 + q] += (double)v;
+        } else {  // e_{j-2}(d', dd) with (d', dd) = (r, c)
+          for (int L = 4; L <= lmax; L++)
+#pragma unroll
+            for (int a = 0; a < 6; a++) v += AB[(L - 2) * 36 + a * 6 + c] * SM[(L - 4) * 36 + a * 6 + r];
+          v *= frec * C.eJm2[q] * C.vJm1[c];
+          A.etaW[(long long)(j - 2) * 36 + q] += (double)v;
+        }
+      }
+      __syncthreads();
+    }
+    if (lmax >= 1) {
+      // ---- bulges closed by (i, j): adjoints of their runs. Left bulge
+      //      l1: run i+1..i+l1, inner pair (i+l1+1, j-1); right bulge l2:
+      //      inner pair (i+1, j-1-l2), run j-l2..j-1.
+      T *EL = X, *ER = X + 30 * 36, *QL = X + 60 * 36, *QR = X + 90 * 36;
+      for (int idx = tid; idx < 4 * lmax * 36; idx += CDZ_NT) {
+        const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
+        const int kind = b / lmax, l = b % lmax + 1;
+        T v = 0;
+        if (kind == 0) {
+          v = D.e[(long long)(i + l) * 36 + q];
+        } else if (kind == 1) {
+          v = D.e[(long long)(j - 1 - l) * 36 + q];
+        } else if (kind == 2) {
+          if (r < lp_d[l] && c < dm) v = D.Qb[(long long)(lp_P[l] + r) * ld + Pm + c];
+        } else {
+          if (r < d1 && c < rp_d[l]) v = D.Qb[(long long)(P1 + r) * ld + rp_P[l] + c];
+        }
+        X[(kind * 30 + l - 1) * 36 + q] = v;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < 2 * lmax * 36; idx += CDZ_NT) {
+        const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
+        const int side = b / lmax, l = b % lmax + 1;
+        const T *el = (side == 0 ? EL : ER) + (l - 1) * 36, *qk = (side == 0 ? QL : QR) + (l - 1) * 36;
+        const T f = tab[TB_BU + l] * cdz_p2<T>(sE[l - 1] + sE[dl - 2 - l] - sE[dl]);
+        T v = 0;
+        if (side == 0) {  // U'[i+1][i+l](a, b) = sum_x,y Gb(a,y) e_{k-1}(b,x) Qb[k][j-1](x,y)
+          if (r < d1 && c < lp_d[l - 1]) {
+#pragma unroll
+            for (int x = 0; x < 6; x++) {
+              T m = 0;
+#pragma unroll
+              for (int y = 0; y < 6; y++) m += C.gb[r * 6 + y] * qk[x * 6 + y];
+              v += el[c * 6 + x] * m;
+            }
+            A.UbL[(long long)(P1 + r) * ld + lp_P[l - 1] + c] += f * v;
+          }
+        } else {  // U'[j-l][j-1](c, dd) = sum_x,y Gb(x,dd) Qb[i+1][l](x,y) e_l(y,c)
+          if (r < rp_d[l - 1] && c < dm) {
+#pragma unroll
+            for (int y = 0; y < 6; y++) {
+              T m = 0;
+#pragma unroll
+              for (int x = 0; x < 6; x++) m += C.gb[x * 6 + c] * qk[x * 6 + y];
+              v += m * el[y * 6 + r];
+            }
+            A.UbR[(long long)(rp_P[l - 1] + r) * ld + Pm + c] += f * v;
+          }
+        }
       }
     }
-    __syncthreads();
-    // one thread per inner pair (k, l) of the window: interior loops add to
-    // both runs, bulges to their single run (LDS atomics, 29 runs per side)
-    for (int win = 1 + tid; win < CDZ_NWIN; win += CDZ_NT) {
-      int l1, l2;
-      cdz_win(win, l1, l2);
-      const int k = i + 1 + l1, l = j - 1 - l2;
-      if (l - k < 4) continue;
-      const int din = l - k;
-      if (l1 >= 1 && l2 >= 1) {
-        const T f = tab[TB_IN + l1 + l2] * cdz_p2<T>(sE[l1 - 1] + sE[din] + sE[l2 - 1] - sE[dl]);
-        const int db = D.d[k - 1], Pb = D.P[k - 1], dc = D.d[l + 1], Pc = D.P[l + 1];
-        T dI[36];
-#pragma unroll
-        for (int r = 0; r < 36; r++)
-          dI[r] = (r / 6 < db && r % 6 < dc) ? D.DI[(Pb + r / 6) * ld + Pc + r % 6] : T(0);
-        const T *Tq = C.Tl + (l2 - 1) * 36;
-        const T *Vq = C.Vl + (l1 - 1) * 36;
-#pragma unroll
-        for (int a = 0; a < 6; a++)
-#pragma unroll
-          for (int b = 0; b < 6; b++) {
-            T sm = 0;
-#pragma unroll
-            for (int c = 0; c < 6; c++) sm += Tq[a * 6 + c] * dI[b * 6 + c];
-            if (a < d1 && b < db && sm != T(0)) atomicAdd(&C.accL[(l1 - 1) * 36 + a * 6 + b], f * sm);
-          }
-#pragma unroll
-        for (int c = 0; c < 6; c++)
-#pragma unroll
-          for (int dd = 0; dd < 6; dd++) {
-            T sm = 0;
-#pragma unroll
-            for (int b = 0; b < 6; b++) sm += dI[b * 6 + c] * Vq[b * 6 + dd];
-            if (c < dc && dd < dm && sm != T(0)) atomicAdd(&C.accR[(l2 - 1) * 36 + c * 6 + dd], f * sm);
-          }
-      } else if (l2 == 0) {  // left bulge: run i+1..k-1, inner pair (k, j-1)
-        const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[din] - sE[dl]);
-        const int dk = D.d[k], Pk = D.P[k], db = D.d[k - 1];
-        T q[36], ek[36];
-#pragma unroll
-        for (int r = 0; r < 36; r++) {
-          q[r] = (r / 6 < dk && r % 6 < dm) ? D.Qb[(Pk + r / 6) * ld + Pm + r % 6] : T(0);
-          ek[r] = D.e[(k - 1) * 36 + r];
-        }
-#pragma unroll
-        for (int a = 0; a < 6; a++)
-#pragma unroll
-          for (int b = 0; b < 6; b++) {
-            T sm = 0;
-#pragma unroll
-            for (int x = 0; x < 6; x++)
-#pragma unroll
-              for (int y = 0; y < 6; y++) sm += C.gb[a * 6 + y] * ek[b * 6 + x] * q[x * 6 + y];
-            if (a < d1 && b < db && sm != T(0)) atomicAdd(&C.accL[(l1 - 1) * 36 + a * 6 + b], f * sm);
-          }
-      } else {  // right bulge: inner pair (i+1, l), run l+1..j-1
-        const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[l2 - 1] + sE[din] - sE[dl]);
-        const int dL = D.d[l], Pl = D.P[l], dc = D.d[l + 1];
-        T q[36], el[36];
-#pragma unroll
-        for (int r = 0; r < 36; r++) {
-          q[r] = (r / 6 < d1 && r % 6 < dL) ? D.Qb[(P1 + r / 6) * ld + Pl + r % 6] : T(0);
-          el[r] = D.e[l * 36 + r];
-        }
-#pragma unroll
-        for (int c = 0; c < 6; c++)
-#pragma unroll
-          for (int dd = 0; dd < 6; dd++) {
-            T sm = 0;
-#pragma unroll
-            for (int x = 0; x < 6; x++)
-#pragma unroll
-              for (int y = 0; y < 6; y++) sm += C.gb[x * 6 + dd] * q[x * 6 + y] * el[y * 6 + c];
-            if (c < dc && dd < dm && sm != T(0)) atomicAdd(&C.accR[(l2 - 1) * 36 + c * 6 + dd], f * sm);
-          }
-      }
-    }
-    __syncthreads();
-    // write back: left runs (row i+1) and the hairpin run, right runs (column j-1)
-    for (int idx = tid; idx < 2 * NRUN * 36; idx += CDZ_NT) {
-      const int side = idx / (NRUN * 36), rem = idx % (NRUN * 36), L = rem / 36 + 1, q = rem % 36;
-      const int r0 = q / 6, r1 = q % 6;
-      if (side == 0) {
-        const int pe = i + L;  // left run i+1..pe
-        if (pe + 5 > j - 1 || r0 >= d1 || r1 >= D.d[pe]) continue;
-        A.UbL[(P1 + r0) * ld + D.P[pe] + r1] += C.accL[rem];
-      } else {
-        const int ps = j - L;  // right run ps..j-1
-        if (ps - 1 - (i + 1) < 4 || r0 >= D.d[ps] || r1 >= dm) continue;
-        A.UbR[(D.P[ps] + r0) * ld + Pm + r1] += C.accR[rem];
-      }
-    }
-    __syncthreads();
-    // hairpin closed by (i, j): its run i+1..j-1 (same row as the left runs)
+    // hairpin closed by (i, j): its run i+1..j-1 (block distinct from the runs above)
     if (tid < 36 && s < d1 && t < dm)
       A.UbL[(P1 + s) * ld + Pm + t] += D.Bhp[dl - 1] * cdz_p2<T>(sE[dl - 2] - sE[dl]) * C.fb[tid];
   } else if (tid < 36) {
@@ -868,7 +946,9 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A) {
   }
   double *out = red + (CDZ_NT / 64) * 36;
   cdz_block_sum<double, 36>(acc, red, out);
-  for (int r = tid; r < 36; r += CDZ_NT) A.eta[p * 36 + r] = out[r];
+  // plus the uses of e_p as V (e_{i+1}) and W (e_{j-2}) in the interior-loop
+  // size recursion, accumulated by the outside pass
+  for (int r = tid; r < 36; r += CDZ_NT) A.eta[p * 36 + r] = out[r] + A.etaV[p * 36 + r] + A.etaW[p * 36 + r];
 }
 
 // pair probabilities P[i][j] = r * sum Qb~ Qb'~ over cells with j - i >= 4
@@ -918,12 +998,18 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   const int n = D.n;
   hipStream_t st = h->stream;
   const size_t S2b = (size_t)D.ld * D.ld * sizeof(T);
-  const size_t shm = out_shmem<T>(n);
-  if (shm > CDZ_MAX_LDS)
+  const size_t shm = out_lds_bytes<T>(n);
+  if (shm > (size_t)h->lds_max)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the outside kernel");
+  HIPCHK(h, hipFuncSetAttribute((const void *)cdz_out_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
   HIPCHK(h, hipEventRecord(h->ev[2], st));
+  // accumulators of pushed adjoints start at zero
   HIPCHK(h, hipMemsetAsync(A.UbL, 0, S2b, st));
   HIPCHK(h, hipMemsetAsync(A.UbR, 0, S2b, st));
+  HIPCHK(h, hipMemsetAsync(A.DIbL, 0, S2b, st));
+  HIPCHK(h, hipMemsetAsync(A.DIbR, 0, S2b, st));
+  HIPCHK(h, hipMemsetAsync(A.etaV, 0, (size_t)n * 36 * sizeof(double), st));
+  HIPCHK(h, hipMemsetAsync(A.etaW, 0, (size_t)n * 36 * sizeof(double), st));
   if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
   for (int dl = n - 1; dl >= 0; dl--) {
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
