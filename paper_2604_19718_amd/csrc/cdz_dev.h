@@ -112,22 +112,120 @@ __device__ __forceinline__ float cdz_wave_max(float x) {
   return x;
 }
 
+// Workgroup barrier that orders LDS accesses only: global stores issued
+// before it are not drained (a plain __syncthreads waits for every
+// outstanding store).  Use __syncthreads where global data written by one
+// thread is read by another thread of the workgroup.
+__device__ __forceinline__ void cdz_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// ---- workgroup sums by a reduce-scatter butterfly inside each wavefront.
+// At level k (k = 5..0) every lane pairs with a partner that differs in lane
+// bit k and agrees in the higher bits; the lane with bit k = 0 keeps the
+// first half of its values, the partner the second half, and each adds the
+// partner's copy of the half it keeps.  After six levels a lane holds
+// ceil(R / 64) sums (or none), so R sums cost about R exchanges instead of
+// 6R.  Bits 5 and 4 exchange with v_permlane32_swap / v_permlane16_swap,
+// bits 3..0 with DPP moves (row_ror:8, row_half_mirror, two quad perms);
+// all of them are VALU operations with no LDS round trip.
+__device__ __forceinline__ void cdz_swap_words(unsigned &a, unsigned &b, int level) {
+  if (level == 5) {
+    auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  } else {
+    auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  }
+}
+__device__ __forceinline__ void cdz_swap(float &a, float &b, int level) {
+  unsigned x = __float_as_uint(a), y = __float_as_uint(b);
+  cdz_swap_words(x, y, level);
+  a = __uint_as_float(x);
+  b = __uint_as_float(y);
+}
+__device__ __forceinline__ void cdz_swap(double &a, double &b, int level) {
+  unsigned long long x = (unsigned long long)__double_as_longlong(a), y = (unsigned long long)__double_as_longlong(b);
+  unsigned xl = (unsigned)x, xh = (unsigned)(x >> 32), yl = (unsigned)y, yh = (unsigned)(y >> 32);
+  cdz_swap_words(xl, yl, level);
+  cdz_swap_words(xh, yh, level);
+  a = __longlong_as_double((long long)(((unsigned long long)xh << 32) | xl));
+  b = __longlong_as_double((long long)(((unsigned long long)yh << 32) | yl));
+}
+template <int CTRL>
+__device__ __forceinline__ float cdz_dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double cdz_dpp(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// level 5 / 4: pair sums through the permlane swaps
+template <int LEVEL, typename T, int N>
+__device__ __forceinline__ void cdz_rs_swap(const T (&v)[N], T (&o)[(N + 1) / 2]) {
+  constexpr int H = (N + 1) / 2;
+#pragma unroll
+  for (int q = 0; q < H; q++) {
+    T a = v[q], b = H + q < N ? v[H + q] : T(0);
+    cdz_swap(a, b, LEVEL);
+    o[q] = a + b;
+  }
+}
+// levels 3..0: explicit send / keep through one DPP move per value
+template <int CTRL, typename T, int N>
+__device__ __forceinline__ void cdz_rs_dpp(const T (&v)[N], T (&o)[(N + 1) / 2], bool bit) {
+  constexpr int H = (N + 1) / 2;
+#pragma unroll
+  for (int q = 0; q < H; q++) {
+    const T lo = v[q], hi = H + q < N ? v[H + q] : T(0);
+    const T recv = cdz_dpp<CTRL>(bit ? lo : hi);
+    o[q] = (bit ? hi : lo) + recv;
+  }
+}
+
 // Sum R per-thread values over the workgroup; result in out[0..R) (LDS),
 // visible to all threads after the call.  scratch holds (NT/64) * R values.
 template <typename T, int R>
 __device__ __forceinline__ void cdz_block_sum(T (&v)[R], T *scratch, T *out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int N1 = (R + 1) / 2, N2 = (N1 + 1) / 2, N3 = (N2 + 1) / 2, N4 = (N3 + 1) / 2,
+                N5 = (N4 + 1) / 2, N6 = (N5 + 1) / 2;
+  T a1[N1], a2[N2], a3[N3], a4[N4], a5[N5], a6[N6];
+  cdz_rs_swap<5>(v, a1);
+  cdz_rs_swap<4>(a1, a2);
+  cdz_rs_dpp<0x128>(a2, a3, (lane >> 3) & 1);  // row_ror:8
+  cdz_rs_dpp<0x141>(a3, a4, (lane >> 2) & 1);  // row_half_mirror
+  cdz_rs_dpp<0x1B>(a4, a5, (lane >> 1) & 1);   // quad_perm 3,2,1,0
+  cdz_rs_dpp<0xB1>(a5, a6, lane & 1);          // quad_perm 1,0,3,2
+  // which sums this lane holds: positions base .. base + cnt - 1
+  int base = 0, cnt = R, N = R;
 #pragma unroll
-  for (int r = 0; r < R; r++) {
-    T s = cdz_wave_sum(v[r]);
-    if (lane == 0) scratch[wv * R + r] = s;
+  for (int k = 5; k >= 0; k--) {
+    const int H = (N + 1) / 2;
+    if ((lane >> k) & 1) {
+      base += H;
+      cnt = cnt - H > 0 ? cnt - H : 0;
+    } else {
+      cnt = cnt < H ? cnt : H;
+    }
+    N = H;
   }
-  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < N6; q++)
+    if (q < cnt) scratch[wv * R + base + q] = a6[q];
+  cdz_sync();
   for (int r = threadIdx.x; r < R; r += CDZ_NT) {
     T s = 0;
 #pragma unroll
     for (int w = 0; w < CDZ_NT / 64; w++) s += scratch[w * R + r];
     out[r] = s;
   }
-  __syncthreads();
+  cdz_sync();
 }

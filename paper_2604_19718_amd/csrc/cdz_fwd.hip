@@ -87,23 +87,19 @@ __device__ void exterior_step(const DevProb<T> &D, int dl, const int *sE, double
         const int k = it - 1;  // 1 <= k <= j-4
         const int dk = D.d[k], Pk = D.P[k];
         const double sc = ldexp(1.0, D.G5[k - 1] + sE[j - k] - R);
-        double z[6], zl[6];
+        double z[6];
 #pragma unroll
         for (int s = 0; s < 6; s++) z[s] = D.Z5[(k - 1) * 6 + s];
-#pragma unroll
-        for (int x = 0; x < 6; x++) {
+        // one slot x of k at a time (keeps the register count of the kernel low)
+#pragma unroll 1
+        for (int x = 0; x < dk; x++) {
           double a = 0;
 #pragma unroll
           for (int s = 0; s < 6; s++) a += z[s] * D.ed[(k - 1) * 36 + s * 6 + x];
-          zl[x] = x < dk ? a * sc : 0.0;
-        }
+          a *= sc;
 #pragma unroll
-        for (int t = 0; t < 6; t++) {
-          double a = 0;
-#pragma unroll
-          for (int x = 0; x < 6; x++)
-            if (x < dk && t < dj) a += zl[x] * (double)D.Qb[(Pk + x) * ld + Pj + t];
-          part[t] += a;
+          for (int t = 0; t < 6; t++)
+            if (t < dj) part[t] += a * (double)D.Qb[(Pk + x) * ld + Pj + t];
         }
       }
     }
@@ -115,7 +111,7 @@ __device__ void exterior_step(const DevProb<T> &D, int dl, const int *sE, double
       for (int t = 0; t < 6; t++) D.Z5[j * 6 + t] = t < dj ? ldexp(tot[t], -e) : 0.0;
       D.G5[j] = R + e;
     }
-    __syncthreads();
+    cdz_sync();
   }
   // ---- suffix Z3[p], p = n - 1 - dl
   int p = n - 1 - dl;
@@ -138,7 +134,7 @@ __device__ void exterior_step(const DevProb<T> &D, int dl, const int *sE, double
         double z3[6];
 #pragma unroll
         for (int t = 0; t < 6; t++) z3[t] = D.Z3[jj * 6 + t];
-#pragma unroll
+#pragma unroll 1
         for (int x = 0; x < 6; x++) {
           double a = 0;
 #pragma unroll
@@ -163,7 +159,7 @@ __device__ void exterior_step(const DevProb<T> &D, int dl, const int *sE, double
       for (int s = 0; s < 6; s++) D.Z3[p * 6 + s] = s < dp ? ldexp(tot[s], -e) : 0.0;
       D.H3[p] = R + e;
     }
-    __syncthreads();
+    cdz_sync();
   }
   // ---- totals after the last diagonal
   if (dl == n) {
@@ -256,11 +252,11 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
   const int n = D.n, tid = threadIdx.x;
   const long long ld = D.ld;
   for (int k = tid; k < dl && k <= n; k += CDZ_NT) sE[k] = D.E[k];
-  __syncthreads();
+  cdz_sync();
   const int Ed = choose_exponent(D, dl, sE);
   if (tid == 0) sE[dl] = Ed;
   if (blockIdx.x == 0 && tid == 0) D.E[dl] = Ed;
-  __syncthreads();
+  cdz_sync();
   const int ncell = n - dl > 0 ? n - dl : 0;
   if ((int)blockIdx.x == ncell) {
     exterior_step<T>(D, dl, sE, reinterpret_cast<double *>(red));
@@ -286,7 +282,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
     C.wd[q] = ok ? D.d[p] : 0;
     C.wP[q] = ok ? D.P[p] : 0;
   }
-  __syncthreads();
+  cdz_sync();
   const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
   const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
   {
@@ -332,7 +328,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
         break;
     }
   }
-  __syncthreads();
+  cdz_sync();
   float vmax = 0.f;
 
   // ---- unpaired run U[i][j]
@@ -366,7 +362,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
     //      states of positions i+4 .. j-5 (u - 1 = pos(k)); the stream is
     //      unrolled so that the loads of several k are in flight together
     {
-      constexpr int UN = sizeof(T) == 4 ? 4 : 2;
+      constexpr int UN = sizeof(T) == 4 ? 4 : 1;
       T acc[36];
 #pragma unroll
       for (int r = 0; r < 36; r++) acc[r] = 0;
@@ -450,7 +446,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
           }
         }
       }
-      __syncthreads();
+      cdz_sync();
       // AP <- AP . W (in place: every output is read into registers first)
       {
         T t4[4];
@@ -466,14 +462,14 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
             t4[u] = s * C.vJm1[dd];
           }
         }
-        __syncthreads();
+        cdz_sync();
 #pragma unroll
         for (int u = 0; u < 4; u++) {
           const int idx = tid + u * CDZ_NT;
           if (idx < nAP * 36) AP[idx] = t4[u];
         }
       }
-      __syncthreads();
+      cdz_sync();
       // A(i,j,L), L = 2..lmax
       const T frec = cdz_p2<T>(sE[dl >= 2 ? dl - 2 : 0] - Ed);
       for (int idx = tid; idx < (lmax - 1) * 36; idx += CDZ_NT) {
@@ -492,21 +488,13 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
         }
         AC[(L - 2) * 36 + q] = C.vI1[a] * (rec * frec + b1 * fb) + b2 * C.vJm1[dd] * fb;
       }
-      __syncthreads();
-      // keep A(i,j,L), L = 2..CDZ_NA+1, for the cells of diagonal dl + 2 and
-      // the outside pass (zero where no inner pair fits)
-      for (int idx = tid; idx < CDZ_NA * 36; idx += CDZ_NT) {
-        const int L = idx / 36 + 2, q = idx % 36, a = q / 6, dd = q % 6;
-        if (a < d1 && dd < dm)
-          D.AL[(long long)(P1 + a) * D.ldA + (long long)CDZ_NA * Pm + (L - 2) * dm + dd] =
-              L <= lmax ? AC[(L - 2) * 36 + q] : T(0);
-      }
+      cdz_sync();
       if (tid < 36) {
         T f = 0;
         for (int L = 2; L <= lmax; L++) f += C.tab[TB_IN + L] * AC[(L - 2) * 36 + tid];
         C.gf[36 + tid] = f;
       }
-      __syncthreads();
+      cdz_sync();
       // bulges: left (run i+1..k-1, inner pair (k, j-1)), right (inner pair
       // (i+1, l), run l+1..j-1), l = 1..lmax; one side after the other, each
       // thread summing the terms term = g, g + 7, .. of output q
@@ -528,7 +516,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
           }
           (b < lmax ? EB : QB)[(l - 1) * 36 + qq] = v;
         }
-        __syncthreads();
+        cdz_sync();
         if (g < 7) {
           for (int l = g + 1; l <= lmax; l += 7) {
             const T f = C.tab[TB_BU + l] * cdz_p2<T>(sE[l - 1] + sE[dl - 2 - l] - Ed);
@@ -556,17 +544,26 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
             gacc += f * sm;
           }
         }
-        __syncthreads();
+        cdz_sync();
       }
       if (g < 7) GP[g * 36 + q] = gacc;
-      __syncthreads();
+      cdz_sync();
       if (tid < 36) {
         T gs = 0;
 #pragma unroll
         for (int gg = 0; gg < 7; gg++) gs += GP[gg * 36 + tid];
         C.gf[tid] = gs;
       }
-      __syncthreads();
+      // keep A(i,j,L), L = 2..CDZ_NA+1, for the cells of diagonal dl + 2 and
+      // the outside pass (zero where no inner pair fits); stored after the
+      // loads above so that none of them waits behind these stores
+      for (int idx = tid; idx < CDZ_NA * 36; idx += CDZ_NT) {
+        const int L = idx / 36 + 2, qq = idx % 36, a = qq / 6, dd = qq % 6;
+        if (a < d1 && dd < dm)
+          D.AL[(long long)(P1 + a) * D.ldA + (long long)CDZ_NA * Pm + (L - 2) * dm + dd] =
+              L <= lmax ? AC[(L - 2) * 36 + qq] : T(0);
+      }
+      cdz_sync();
     }
     const T *tab = C.tab;
     // ---- Qb (one thread per slot pair), all operands in LDS
@@ -608,7 +605,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
         D.F[(P1 + s) * ld + Pm + s2] = C.gf[36 + tid];
       }
     }
-    __syncthreads();
+    cdz_sync();
     // ---- Qm1 and DI (Qb dressed as an interior loop's inner pair)
     if (tid < 36) {
       const int s = tid / 6, s2 = tid % 6;
@@ -640,7 +637,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
         }
       }
     }
-    __syncthreads();
+    cdz_sync();
     // ---- Qm1L, Qm1p, QmX, Qm
     if (tid < 36) {
       const int s = tid / 6, s2 = tid % 6;

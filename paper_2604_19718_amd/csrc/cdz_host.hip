@@ -378,6 +378,9 @@ static cdz_status forward_impl(cdz_handle *h, const HostTables &t, bool adjoint)
   memset(&D, 0, sizeof(D));
   memset(&A, 0, sizeof(A));
   const size_t need = carve<T>(nullptr, t, D, A, adjoint);
+  // block offsets inside one S x S array are kept in 32-bit integers
+  if ((unsigned long long)D.ld * (unsigned long long)D.ld > 0x7fffffffull)
+    return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(t.n) + " nt is too long for 32-bit block offsets");
   if (h->opt.mem_budget_bytes && need > h->opt.mem_budget_bytes)
     return cdz_fail(h, CDZ_ERR_BUDGET, "workspace of " + std::to_string(need) + " bytes exceeds the budget");
   if (need > h->ws_bytes) {

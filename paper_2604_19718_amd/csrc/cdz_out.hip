@@ -118,7 +118,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
     C.wd[q] = ok ? D.d[p] : 0;
     C.wP[q] = ok ? D.P[p] : 0;
   }
-  __syncthreads();
+  cdz_sync();
   const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
   const int dim1 = C.d[0], Pim1 = C.P[0], djp1 = C.d[5], Pjp1 = C.P[5];
   const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
@@ -175,13 +175,13 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
       }
     }
   }
-  __syncthreads();
+  cdz_sync();
   const T *tab = C.tab;
   if (dl >= 4) {
     const int lmax = min(CDZ_MAXLOOP, dl - 6);
     // ---- split gathers: Qm'[i][j] along row i, Qm1L'[i][j] down column j
     {
-      constexpr int UN = sizeof(T) == 4 ? 4 : 2;
+      constexpr int UN = 2;
       T acc[72];
 #pragma unroll
       for (int r = 0; r < 72; r++) acc[r] = 0;
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
           }
         }
       }
-      __syncthreads();
+      cdz_sync();
       const int q = tid % 36, g = tid / 36, x = q / 6, y = q % 6;
       if (g < 7) {
         T acc = 0;
@@ -306,14 +306,14 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         }
         GP[g * 36 + q] = acc;
       }
-      __syncthreads();
+      cdz_sync();
       if (tid < 36) {
         T s = 0;
 #pragma unroll
         for (int gg = 0; gg < 7; gg++) s += GP[gg * 36 + tid];
         C.w[36 + tid] = s;
       }
-      __syncthreads();
+      cdz_sync();
     }
     const int s = tid / 6, t = tid % 6;
     // ---- Qm', QmX', Qm1p', Qm1L', DI' (all operands in LDS)
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
       }
       C.qm1pb[tid] = qpb;
     }
-    __syncthreads();
+    cdz_sync();
     // ---- Qm1'
     if (tid < 36) {
       T q1b = 0;
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
       }
       C.qm1b[tid] = q1b;
     }
-    __syncthreads();
+    cdz_sync();
     // ---- Qb'
     if (tid < 36) {
       const int x = s, y = t;
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
       }
       C.qbb[tid] = qbb;
     }
-    __syncthreads();
+    cdz_sync();
     // ---- outer-edge-dressed adjoints of this cell's loop sums, block (i+1, j-1)
     if (tid < 36) {
       const int a = s, dd = t;
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         const int b = idx / 36, q = idx % 36;
         APV[idx] = ring_at(A, n, dl + 2, i - 1, b + 4)[q];
       }
-      __syncthreads();
+      cdz_sync();
       // TB(a, d') = sum_dd A'(i-1,j+1,L+2)(a,dd) e_{j-1}(d',dd) v_j(dd)
       for (int idx = tid; idx < npull * 36; idx += CDZ_NT) {
         const int b = idx / 36, q = idx % 36, a = q / 6, d2 = q % 6;
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         for (int dd = 0; dd < 6; dd++) v += APV[b * 36 + a * 6 + dd] * C.eJm1[d2 * 6 + dd] * C.vJ[dd];
         TB[idx] = v;
       }
-      __syncthreads();
+      cdz_sync();
       const T frA = pull ? cdz_p2<T>(sE[dl] - sE[dl + 2]) : T(0);
       for (int idx = tid; idx < 29 * 36; idx += CDZ_NT) {
         const int L = idx / 36 + 2, q = idx % 36, a2 = q / 6, d2 = q % 6;
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         AB[idx] = v;
         if (L >= 4) ring_at(A, n, dl, i, L)[q] = v;
       }
-      __syncthreads();
+      cdz_sync();
     }
     if (lmax >= 2) {
       // ---- interior loops closed by (i, j): adjoints of the blocks the size
@@ -501,8 +501,18 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
           }
         }
       }
-      __syncthreads();
-      for (int idx = tid; idx < 4 * 29 * 36; idx += CDZ_NT) {
+      cdz_sync();
+      // every target block is updated by exactly one thread; all old values
+      // are fetched first so that the loads are in flight together
+      constexpr int NPT = (4 * 29 * 36 + CDZ_NT - 1) / CDZ_NT;
+      int off[NPT];
+      T val[NPT];
+#pragma unroll
+      for (int m = 0; m < NPT; m++) {
+        const int idx = tid + m * CDZ_NT;
+        off[m] = -1;
+        val[m] = 0;
+        if (idx >= 4 * 29 * 36) continue;
         const int kind = idx / (29 * 36), rem = idx % (29 * 36), L = rem / 36 + 2, q = rem % 36;
         const int r = q / 6, c = q % 6;
         if (L > lmax || (L < 3 && (kind == 1 || kind == 3))) continue;
@@ -513,29 +523,44 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
           if (r < d1 && c < rp_d[L - 2]) {
 #pragma unroll
             for (int dd = 0; dd < 6; dd++) v += ab[r * 6 + dd] * UC1[(L - 2) * 36 + c * 6 + dd];
-            A.DIbL[(long long)(P1 + r) * ld + rp_P[L - 2] + c] += fb * C.vI1[r] * v;
+            off[m] = (P1 + r) * (int)ld + rp_P[L - 2] + c;
+            val[m] = fb * C.vI1[r] * v;
           }
         } else if (kind == 1) {  // DI'[i+L-1][j-1](b, dd)
           if (r < lp_d[L - 2] && c < dm) {
 #pragma unroll
             for (int a = 0; a < 6; a++) v += UR1[(L - 2) * 36 + a * 6 + r] * ab[a * 6 + c];
-            A.DIbR[(long long)(lp_P[L - 2] + r) * ld + Pm + c] += fb * C.vJm1[c] * v;
+            off[m] = (lp_P[L - 2] + r) * (int)ld + Pm + c;
+            val[m] = fb * C.vJm1[c] * v;
           }
         } else if (kind == 2) {  // U'[j-L+1][j-1](c, dd), run of L - 1
           if (r < rp_d[L - 2] && c < dm) {
 #pragma unroll
             for (int a = 0; a < 6; a++) v += C.vI1[a] * DIrow[(L - 2) * 36 + a * 6 + r] * ab[a * 6 + c];
-            A.UbR[(long long)(rp_P[L - 2] + r) * ld + Pm + c] += fb * v;
+            off[m] = (rp_P[L - 2] + r) * (int)ld + Pm + c;
+            val[m] = fb * v;
           }
         } else {  // U'[i+1][i+L-1](a, b), run of L - 1
           if (r < d1 && c < lp_d[L - 2]) {
 #pragma unroll
             for (int dd = 0; dd < 6; dd++) v += ab[r * 6 + dd] * C.vJm1[dd] * DIcol[(L - 2) * 36 + c * 6 + dd];
-            A.UbL[(long long)(P1 + r) * ld + lp_P[L - 2] + c] += fb * v;
+            off[m] = (P1 + r) * (int)ld + lp_P[L - 2] + c;
+            val[m] = fb * v;
           }
         }
       }
-      __syncthreads();
+      auto target = [&](int m) -> T * {
+        const int kind = (tid + m * CDZ_NT) / (29 * 36);
+        T *base = kind == 0 ? A.DIbL : kind == 1 ? A.DIbR : kind == 2 ? A.UbR : A.UbL;
+        return base + off[m];
+      };
+      T old[NPT];
+#pragma unroll
+      for (int m = 0; m < NPT; m++) old[m] = off[m] >= 0 ? *target(m) : T(0);
+#pragma unroll
+      for (int m = 0; m < NPT; m++)
+        if (off[m] >= 0) *target(m) = old[m] + val[m];
+      __syncthreads();  // the bulge pushes below update some of the same runs
     }
     if (lmax >= 4) {
       // ---- edges e_{i+1} (in V) and e_{j-2} (in W) of the size recursion:
@@ -549,7 +574,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
           v = D.AL[(long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + b * rp_d[1] + c];
         AP[idx] = v;
       }
-      __syncthreads();
+      cdz_sync();
       for (int idx = tid; idx < nAP * 36; idx += CDZ_NT) {
         const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
         T tm = 0, sm = 0;
@@ -561,7 +586,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         TM[idx] = tm * C.vJm1[c];  // (A . W)(a', dd)
         SM[idx] = C.vI1[r] * sm;   // (V . A)(a, d')
       }
-      __syncthreads();
+      cdz_sync();
       const T frec = cdz_p2<T>(sE[dl - 2] - sE[dl]);
       if (tid < 72) {
         const int q = tid % 36, r = q / 6, c = q % 6;
@@ -580,7 +605,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
           A.etaW[(long long)(j - 2) * 36 + q] += (double)v;
         }
       }
-      __syncthreads();
+      cdz_sync();
     }
     if (lmax >= 1) {
       // ---- bulges closed by (i, j): adjoints of their runs. Left bulge
@@ -602,8 +627,16 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         }
         X[(kind * 30 + l - 1) * 36 + q] = v;
       }
-      __syncthreads();
-      for (int idx = tid; idx < 2 * lmax * 36; idx += CDZ_NT) {
+      cdz_sync();
+      constexpr int NPB = (2 * 30 * 36 + CDZ_NT - 1) / CDZ_NT;
+      int off[NPB];
+      T val[NPB];
+#pragma unroll
+      for (int m = 0; m < NPB; m++) {
+        const int idx = tid + m * CDZ_NT;
+        off[m] = -1;
+        val[m] = 0;
+        if (idx >= 2 * lmax * 36) continue;
         const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
         const int side = b / lmax, l = b % lmax + 1;
         const T *el = (side == 0 ? EL : ER) + (l - 1) * 36, *qk = (side == 0 ? QL : QR) + (l - 1) * 36;
@@ -613,25 +646,38 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
           if (r < d1 && c < lp_d[l - 1]) {
 #pragma unroll
             for (int x = 0; x < 6; x++) {
-              T m = 0;
+              T mm = 0;
 #pragma unroll
-              for (int y = 0; y < 6; y++) m += C.gb[r * 6 + y] * qk[x * 6 + y];
-              v += el[c * 6 + x] * m;
+              for (int y = 0; y < 6; y++) mm += C.gb[r * 6 + y] * qk[x * 6 + y];
+              v += el[c * 6 + x] * mm;
             }
-            A.UbL[(long long)(P1 + r) * ld + lp_P[l - 1] + c] += f * v;
+            off[m] = (P1 + r) * (int)ld + lp_P[l - 1] + c;
+            val[m] = f * v;
           }
         } else {  // U'[j-l][j-1](c, dd) = sum_x,y Gb(x,dd) Qb[i+1][l](x,y) e_l(y,c)
           if (r < rp_d[l - 1] && c < dm) {
 #pragma unroll
             for (int y = 0; y < 6; y++) {
-              T m = 0;
+              T mm = 0;
 #pragma unroll
-              for (int x = 0; x < 6; x++) m += C.gb[x * 6 + c] * qk[x * 6 + y];
-              v += m * el[y * 6 + r];
+              for (int x = 0; x < 6; x++) mm += C.gb[x * 6 + c] * qk[x * 6 + y];
+              v += mm * el[y * 6 + r];
             }
-            A.UbR[(long long)(rp_P[l - 1] + r) * ld + Pm + c] += f * v;
+            off[m] = (rp_P[l - 1] + r) * (int)ld + Pm + c;
+            val[m] = f * v;
           }
         }
+      }
+      T old[NPB];
+#pragma unroll
+      for (int m = 0; m < NPB; m++) {
+        const bool left = (tid + m * CDZ_NT) / 36 < lmax;
+        old[m] = off[m] >= 0 ? (left ? A.UbL : A.UbR)[off[m]] : T(0);
+      }
+#pragma unroll
+      for (int m = 0; m < NPB; m++) {
+        const bool left = (tid + m * CDZ_NT) / 36 < lmax;
+        if (off[m] >= 0) (left ? A.UbL : A.UbR)[off[m]] = old[m] + val[m];
       }
     }
     // hairpin closed by (i, j): its run i+1..j-1 (block distinct from the runs above)
