@@ -166,6 +166,46 @@ __device__ bool decide(W<T> &w, int G, GS gsum, SC scan, int &gsel, int &asel) {
   return asel >= 0;
 }
 
+// The same decision when the total is already known (the forward pass stored
+// it): the groups are evaluated in order, the first chunk FIRST wide and then
+// 64 at a time, and the walk stops at the chunk where the running sum passes
+// u * total.  Most decisions end in the first few groups.  If rounding leaves
+// the target beyond the last group, the last nonzero group is taken.
+template <typename T, typename GS, typename SC>
+__device__ bool decide_total(W<T> &w, int G, double tot, int first, GS gsum, SC scan, int &gsel, int &asel) {
+  const double u = uniform01(w.S->seed, (uint32_t)w.sid, w.draw++);
+  if (!(tot > 0)) return false;
+  const double target = u * tot;
+  double cum = 0, before = 0;
+  int last_nz = -1;
+  gsel = -1;
+  for (int base = 0; base < G && gsel < 0;) {
+    const int width = base == 0 ? first : 64;
+    const int g = base + w.lane;
+    const bool in = w.lane < width && g < G;
+    const double s = in ? gsum(g) : 0.0;
+    const double incl = wscan(s, w.lane) + cum;
+    const unsigned long long hit = __ballot(in && incl > target);
+    const unsigned long long nz = __ballot(in && s > 0);
+    if (nz) last_nz = base + 63 - __clzll(nz);
+    if (hit) {
+      const int l = __ffsll((long long)hit) - 1;
+      gsel = base + l;
+      before = __shfl(incl - s, l, 64);
+    } else {
+      cum = __shfl(incl, 63, 64);
+    }
+    base += width;
+  }
+  if (gsel < 0) {
+    gsel = last_nz;
+    if (gsel < 0) return false;
+    before = -1.0;
+  }
+  asel = scan(gsel, before, target);
+  return asel >= 0;
+}
+
 // ---- fragment handlers ----------------------------------------------------
 
 template <typename T>
@@ -495,8 +535,11 @@ __device__ void f_pair(W<T> &w, int i, int j, int s, int s2) {
     return m * (double)tab[TB_MLAB] * f2;
   };
   auto scan1 = [&](int g, double, double) { return 0; };
+  // the total over all loops closed by (i, j) is the stored Qb entry without
+  // its two vertex factors; hairpin and stack come first in the order
+  const double tot1 = Qv(D.Qb, ld, D.P[i] + s, D.P[j] + s2) / ((double)D.v[i * 6 + s] * (double)D.v[j * 6 + s2]);
   int g1, a1;
-  if (!decide(w, CDZ_NWIN + 2, gsum1, scan1, g1, a1)) {
+  if (!decide_total(w, CDZ_NWIN + 2, tot1, 2, gsum1, scan1, g1, a1)) {
     w.bad = true;
     return;
   }
