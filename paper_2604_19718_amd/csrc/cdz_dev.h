@@ -112,6 +112,18 @@ __device__ __forceinline__ float cdz_wave_max(float x) {
   return x;
 }
 
+// Cells of one diagonal are assigned to workgroups so that each of the 8
+// XCDs (workgroups are dealt to them in turn, each XCD has its own L2) runs
+// a contiguous range of i: cells with nearby i read each other's rows and
+// runs, which then tend to be in the same L2.  Blocks past the last cell exit.
+#define CDZ_NXCD 8
+__host__ __device__ __forceinline__ int cdz_cells_grid(int ncell) {
+  return (ncell + CDZ_NXCD - 1) / CDZ_NXCD * CDZ_NXCD;
+}
+__device__ __forceinline__ int cdz_cell_of_block(int w, int ncell) {
+  return (w % CDZ_NXCD) * ((ncell + CDZ_NXCD - 1) / CDZ_NXCD) + w / CDZ_NXCD;
+}
+
 // Workgroup barrier that orders LDS accesses only: global stores issued
 // before it are not drained (a plain __syncthreads waits for every
 // outstanding store).  Use __syncthreads where global data written by one

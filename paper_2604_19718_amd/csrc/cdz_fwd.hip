@@ -258,11 +258,12 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
   if (blockIdx.x == 0 && tid == 0) D.E[dl] = Ed;
   cdz_sync();
   const int ncell = n - dl > 0 ? n - dl : 0;
-  if ((int)blockIdx.x == ncell) {
+  if ((int)blockIdx.x == cdz_cells_grid(ncell)) {
     exterior_step<T>(D, dl, sE, reinterpret_cast<double *>(red));
     return;
   }
-  const int i = blockIdx.x, j = i + dl;
+  const int i = cdz_cell_of_block(blockIdx.x, ncell), j = i + dl;
+  if (i >= ncell) return;
 
   // ---- stage: positions i-1, i, i+1, j-1, j, j+1 (clamped; unused when absent)
   if (tid < 6) {

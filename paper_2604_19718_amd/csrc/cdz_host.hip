@@ -337,7 +337,7 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
     for (int dl = 0; dl <= n; dl++) {
       const int ncell = n - dl > 0 ? n - dl : 0;
       if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
-      hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(ncell + 1), dim3(CDZ_NT), shm, st, D, dl);
+      hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(cdz_cells_grid(ncell) + 1), dim3(CDZ_NT), shm, st, D, dl);
       if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
     }
     if (pass + 1 < passes)

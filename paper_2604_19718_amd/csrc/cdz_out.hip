@@ -100,7 +100,8 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
   T *X = AB + 29 * 36;
   for (int k = tid; k < n; k += CDZ_NT) sE[k] = D.E[k];
   const int EZ = (int)D.res[2];
-  const int i = blockIdx.x, j = i + dl;
+  const int i = cdz_cell_of_block(blockIdx.x, n - dl), j = i + dl;
+  if (i >= n - dl) return;
   if (tid < 6) {
     const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
     const int p = pos[tid];
@@ -1059,7 +1060,7 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
   for (int dl = n - 1; dl >= 0; dl--) {
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
-    hipLaunchKernelGGL(cdz_out_diag<T>, dim3(n - dl), dim3(CDZ_NT), shm, st, D, A, dl);
+    hipLaunchKernelGGL(cdz_out_diag<T>, dim3(cdz_cells_grid(n - dl)), dim3(CDZ_NT), shm, st, D, A, dl);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
   }
   HIPCHK(h, hipGetLastError());
