@@ -63,6 +63,7 @@ struct DevProb {
   int *G5;                 // [n]
   double *Z3;              // [n][6] suffix exterior partition function
   int *H3;                 // [n]
+  int *Cl;                 // [n] landscape exponents C[p] (FP32 mode)
   double *res;             // [8] results: log Z (prefix), log Z (suffix), EZ, ...
 };
 

@@ -672,35 +672,135 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
   }
 }
 
-// Per-position scale from a finished forward pass: C[p] = log2 of the prefix
-// exterior partition function Z5[p] (FP64).  Every vertex factor v_p is
-// multiplied by 2^-g_p with g_p = round(C[p]) - round(C[p-1]); each range
-// [i..j] then carries the exact factor 2^-(round C[j] - round C[i-1]), which
-// follows the free-energy landscape of the sequence, so inside and outside
-// values of every cell stay near 1 in the next pass.  res[3] accumulates the
-// total shift sum_p g_p (log Z = log Z~ + res[3] ln 2).
+// ---- FP32: the free-energy landscape of the sequence ---------------------
+// With C[p] = round(log2 Z5[p]) (prefix exterior partition function, C[-1]
+// = 0), multiplying every vertex factor v_p by 2^-(C[p] - C[p-1]) multiplies
+// every quantity over a span [a..b] by the exact power of two
+// 2^-(C[b] - C[a-1]).  Cells of one diagonal then stay within a few octaves
+// of each other, even where strong and weak regions of the sequence differ
+// by more than 2^120 (beyond the FP32 range); probabilities do not change
+// and log Z is restored exactly from sum_p (C[p] - C[p-1]) = C[n-1].
+//
+// The landscape is estimated before the exact pass from a truncated one:
+// the dynamic program over spans <= W only, then the exterior prefix with
+// pairs of span <= W (cdz_exterior_trunc).  Any landscape gives exact
+// results; its quality only decides how far cells spread, which
+// cdz_spread_check verifies after the exact pass.
+
+// Z5[j], j = W..n-1, from pairs (k, j) with j - k <= W (Z5[0..W-1] are the
+// exact values of the truncated pass).  One workgroup, positions in turn.
 template <typename T>
-__global__ void cdz_rescale(DevProb<T> D) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= D.n) return;
-  auto C = [&](int q) -> long long {
-    if (q < 0) return 0;
-    double z = 0;
-    for (int t = 0; t < 6; t++) z += D.Z5[q * 6 + t];
-    return (z > 0 && isfinite(z)) ? llrint(D.G5[q] + log2(z)) : 0;
-  };
-  const long long g = C(p) - C(p - 1);
-  const double f = ldexp(1.0, (int)(-g));
-  double *vd = const_cast<double *>(D.vd);
-  T *v = const_cast<T *>(D.v);
-  for (int s = 0; s < 6; s++) {
-    vd[p * 6 + s] *= f;
-    v[p * 6 + s] = (T)((double)v[p * 6 + s] * f);
+__global__ __launch_bounds__(CDZ_NT) void cdz_exterior_trunc(DevProb<T> D, int W) {
+  __shared__ double red[(CDZ_NT / 64) * 6 + 6];
+  double *tot = red + (CDZ_NT / 64) * 6;
+  const int n = D.n, tid = threadIdx.x;
+  const long long ld = D.ld;
+  for (int j = W; j < n; j++) {
+    const int R = D.G5[j - 1], dj = D.d[j], Pj = D.P[j];
+    double part[6] = {0, 0, 0, 0, 0, 0};
+    const int k0 = j - W > 0 ? j - W : 0;  // first pair start
+    // item 0: j unpaired; item it >= 1: k = k0 + it - 1 pairs j (k <= j - 4)
+    const int nit = 1 + (j - 4 - k0 + 1 > 0 ? j - 4 - k0 + 1 : 0);
+    for (int it = tid; it < nit; it += CDZ_NT) {
+      if (it == 0) {
+        double z[6];
+#pragma unroll
+        for (int q = 0; q < 6; q++) z[q] = D.Z5[(j - 1) * 6 + q];
+#pragma unroll
+        for (int t = 0; t < 6; t++) {
+          double a = 0;
+#pragma unroll
+          for (int q = 0; q < 6; q++) a += z[q] * D.ed[(j - 1) * 36 + q * 6 + t];
+          part[t] += t < dj ? a * D.vd[j * 6 + t] : 0.0;
+        }
+      } else {
+        const int k = k0 + it - 1, dk = D.d[k], Pk = D.P[k];
+        if (k == 0) {
+          const double sc = ldexp(1.0, D.E[j] - R);
+#pragma unroll 1
+          for (int x = 0; x < dk; x++)
+#pragma unroll
+            for (int t = 0; t < 6; t++)
+              if (t < dj) part[t] += (double)D.Qb[x * ld + Pj + t] * sc;
+        } else {
+          const double sc = ldexp(1.0, D.G5[k - 1] + D.E[j - k] - R);
+          double z[6];
+#pragma unroll
+          for (int q = 0; q < 6; q++) z[q] = D.Z5[(k - 1) * 6 + q];
+#pragma unroll 1
+          for (int x = 0; x < dk; x++) {
+            double a = 0;
+#pragma unroll
+            for (int q = 0; q < 6; q++) a += z[q] * D.ed[(k - 1) * 36 + q * 6 + x];
+            a *= sc;
+#pragma unroll
+            for (int t = 0; t < 6; t++)
+              if (t < dj) part[t] += a * (double)D.Qb[(Pk + x) * ld + Pj + t];
+          }
+        }
+      }
+    }
+    cdz_block_sum<double, 6>(part, red, tot);
+    if (tid == 0) {
+      double mx = 0;
+      for (int t = 0; t < 6; t++) mx = fmax(mx, fabs(tot[t]));
+      const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
+      for (int t = 0; t < 6; t++) D.Z5[j * 6 + t] = t < dj ? ldexp(tot[t], -e) : 0.0;
+      D.G5[j] = R + e;
+    }
+    __syncthreads();  // Z5[j], G5[j] are read by every thread at j + 1
   }
-  if (p == D.n - 1) D.res[3] += (double)C(p);
 }
 
-template __global__ void cdz_rescale<float>(DevProb<float>);
-template __global__ void cdz_rescale<double>(DevProb<double>);
+// C[p] from the current Z5, v and vd rescaled by it; res[3] accumulates
+// C[n-1] over the rescalings (log Z = log Z~ + res[3] ln 2).
+template <typename T>
+__global__ __launch_bounds__(1024) void cdz_landscape(DevProb<T> D) {
+  const int n = D.n;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    double z = 0;
+    for (int t = 0; t < 6; t++) z += D.Z5[p * 6 + t];
+    D.Cl[p] = (z > 0 && isfinite(z)) ? (int)llrint(D.G5[p] + log2(z)) : 0;
+  }
+  __syncthreads();  // C is read across threads below (global memory)
+  double *vd = const_cast<double *>(D.vd);
+  T *v = const_cast<T *>(D.v);
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    const int g = D.Cl[p] - (p >= 1 ? D.Cl[p - 1] : 0);
+    for (int s = 0; s < 6; s++) {
+      vd[p * 6 + s] = ldexp(vd[p * 6 + s], -g);
+      v[p * 6 + s] = (T)ldexp((double)v[p * 6 + s], -g);
+    }
+  }
+  if (threadIdx.x == 0) D.res[3] += D.Cl[n - 1];
+}
+
+// After the exact pass: does the weakest cell of a diagonal come within 26
+// octaves of FP32 underflow?  Then res[5] = 1 (the pass is repeated with the
+// landscape of the exact pass).
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_spread_check(DevProb<T> D) {
+  const int dl = blockIdx.x, n = D.n, ncell = n - dl;
+  const long long ld = D.ld;
+  T *const full[6] = {D.U, D.Qb, D.Qm1, D.Qm1p, D.QmX, D.Qm};
+  const T low = (T)ldexp(1.0, -100);
+  bool weak = false;
+  for (int i = threadIdx.x; i < ncell; i += CDZ_NT) {
+    const int j = i + dl, di = D.d[i], dj = D.d[j], Pi = D.P[i], Pj = D.P[j];
+    T m = 0;
+    for (int a = 0; a < 6; a++)
+      for (int r = 0; r < di; r++)
+        for (int c = 0; c < dj; c++) m = fmax(m, fabs(full[a][(long long)(Pi + r) * ld + Pj + c]));
+    weak = weak || (m > T(0) && m < low);
+  }
+  if (__any(weak) && (threadIdx.x & 63) == 0) D.res[5] = 1.0;
+}
+
+template __global__ void cdz_exterior_trunc<float>(DevProb<float>, int);
+template __global__ void cdz_exterior_trunc<double>(DevProb<double>, int);
+template __global__ void cdz_landscape<float>(DevProb<float>);
+template __global__ void cdz_landscape<double>(DevProb<double>);
+template __global__ void cdz_spread_check<float>(DevProb<float>);
+template __global__ void cdz_spread_check<double>(DevProb<double>);
 template __global__ void cdz_fwd_diag<float>(DevProb<float>, int);
 template __global__ void cdz_fwd_diag<double>(DevProb<double>, int);

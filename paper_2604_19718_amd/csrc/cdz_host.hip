@@ -279,6 +279,7 @@ static size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A
   D.G5 = c.take<int>(base, n);
   D.Z3 = c.take<double>(base, (size_t)n * 6);
   D.H3 = c.take<int>(base, n);
+  D.Cl = c.take<int>(base, n);
   D.res = c.take<double>(base, 8);
   T **arrs[] = {&D.U, &D.Qb, &D.G, &D.F, &D.DI, &D.Qm1, &D.Qm1Lr, &D.Qm1Lt,
                 &D.Qm1p, &D.QmX, &D.Qm, &D.Qmt};
@@ -314,7 +315,29 @@ __global__ void cdz_fwd_diag(DevProb<T> D, int dl);
 
 
 template <typename T>
-__global__ void cdz_rescale(DevProb<T> D);
+__global__ void cdz_landscape(DevProb<T> D);
+template <typename T>
+__global__ void cdz_exterior_trunc(DevProb<T> D, int W);
+template <typename T>
+__global__ void cdz_spread_check(DevProb<T> D);
+
+// span limit of the truncated pass that estimates the FP32 landscape
+#define CDZ_LANDSCAPE_SPAN 96
+
+template <typename T>
+static cdz_status forward_pass(cdz_handle *h, DevProb<T> &D, size_t shm, bool timed, int dlmax) {
+  const int n = D.n;
+  hipStream_t st = h->stream;
+  HIPCHK(h, hipMemsetAsync(D.maxb, 0, (n + 1) * sizeof(unsigned), st));
+  for (int dl = 0; dl <= dlmax; dl++) {
+    const int ncell = n - dl > 0 ? n - dl : 0;
+    if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
+    hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(cdz_cells_grid(ncell) + 1), dim3(CDZ_NT), shm, st, D, dl);
+    if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
+  }
+  HIPCHK(h, hipGetLastError());
+  return CDZ_OK;
+}
 
 template <typename T>
 static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
@@ -324,28 +347,41 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   if (shm > (size_t)h->lds_max)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the forward kernel");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_fwd_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-  // FP32: a first pass finds the free-energy landscape (prefix exterior
-  // partition function), the vertex factors are rescaled by it, and the
-  // second pass runs on the rescaled tables.  FP64 has the range for one pass.
-  const int passes = std::is_same<T, float>::value ? 2 : 1;
+  const bool fp32 = std::is_same<T, float>::value;
   HIPCHK(h, hipMemsetAsync(D.res, 0, 8 * sizeof(double), st));
   if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
   HIPCHK(h, hipEventRecord(h->ev[0], st));
-  for (int pass = 0; pass < passes; pass++) {
-    HIPCHK(h, hipMemsetAsync(D.maxb, 0, (n + 1) * sizeof(unsigned), st));
-    const bool timed = h->profiling && pass == passes - 1;
-    for (int dl = 0; dl <= n; dl++) {
-      const int ncell = n - dl > 0 ? n - dl : 0;
-      if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
-      hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(cdz_cells_grid(ncell) + 1), dim3(CDZ_NT), shm, st, D, dl);
-      if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
+  cdz_status s;
+  double res[8];
+  if (fp32) {
+    // FP32: vertex factors rescaled to the free-energy landscape, estimated
+    // from a pass truncated to short spans; then the exact pass, and once
+    // more with the landscape of the exact pass if its cells still spread
+    // too far (see cdz_landscape in cdz_fwd.hip)
+    const int W = n - 1 < CDZ_LANDSCAPE_SPAN ? n - 1 : CDZ_LANDSCAPE_SPAN;
+    s = forward_pass<T>(h, D, shm, false, W);
+    if (s != CDZ_OK) return s;
+    hipLaunchKernelGGL(cdz_exterior_trunc<T>, dim3(1), dim3(CDZ_NT), 0, st, D, W);
+    hipLaunchKernelGGL(cdz_landscape<T>, dim3(1), dim3(1024), 0, st, D);
+    s = forward_pass<T>(h, D, shm, h->profiling, n);
+    if (s != CDZ_OK) return s;
+    hipLaunchKernelGGL(cdz_spread_check<T>, dim3(n), dim3(CDZ_NT), 0, st, D);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(res, D.res, sizeof(res), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    h->landscape_retries = 0;
+    if (res[5] != 0.0) {
+      h->landscape_retries = 1;
+      hipLaunchKernelGGL(cdz_landscape<T>, dim3(1), dim3(1024), 0, st, D);
+      s = forward_pass<T>(h, D, shm, false, n);
+      if (s != CDZ_OK) return s;
     }
-    if (pass + 1 < passes)
-      hipLaunchKernelGGL(cdz_rescale<T>, dim3((n + 255) / 256), dim3(256), 0, st, D);
+  } else {
+    s = forward_pass<T>(h, D, shm, h->profiling, n);
+    if (s != CDZ_OK) return s;
   }
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->ev[1], st));
-  double res[8];
   HIPCHK(h, hipMemcpyAsync(res, D.res, sizeof(res), hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));
   float ms = 0;

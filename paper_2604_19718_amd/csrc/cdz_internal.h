@@ -53,6 +53,7 @@ struct cdz_handle {
   hipStream_t stream = nullptr;
   int device = 0;
   int lds_max = 65536;  // dynamic LDS a workgroup may use on this device
+  int landscape_retries = 0;  // FP32: exact passes repeated for range (last forward)
   std::string err;
   void *ws = nullptr;
   size_t ws_bytes = 0;
