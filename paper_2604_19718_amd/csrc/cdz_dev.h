@@ -125,6 +125,47 @@ __device__ __forceinline__ int cdz_cell_of_block(int w, int ncell) {
   return (w % CDZ_NXCD) * ((ncell + CDZ_NXCD - 1) / CDZ_NXCD) + w / CDZ_NXCD;
 }
 
+// ---- wave-uniform helpers ---------------------------------------------------
+__device__ __forceinline__ int cdz_uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+template <typename T>
+__device__ __forceinline__ const T *cdz_uni(const T *p) {
+  const unsigned long long u = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return reinterpret_cast<const T *>(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int cdz_wave_id() { return cdz_uni((int)(threadIdx.x >> 6)); }
+// orders the LDS accesses of the lanes of one wavefront (reads of a block by
+// some lanes before writes to it by others); LDS serves a wave in order, so
+// this only has to stop the compiler from moving them
+__device__ __forceinline__ void cdz_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Stage blocks of up to 6 x 6 values into LDS (dst[b * 36 + r * 6 + c]), one
+// wavefront per block: the block's source (row-major, stride ld, dr x dc
+// valid entries) is wave-uniform, lane q < 36 moves entry (q / 6, q % 6), so
+// the per-lane work is one load and one LDS store.  src(b, p, dr, dc) fills
+// the source of block b (values it reads must be the same in every lane).
+template <typename T, typename F>
+__device__ __forceinline__ void cdz_stage_blocks(T *dst, int nblk, long long ld, F src) {
+  const int lane = threadIdx.x & 63, r = lane / 6, c = lane % 6;
+  const long long off = (long long)r * ld + c;
+  const int nw = CDZ_NT / 64;
+#pragma unroll 2
+  for (int b = cdz_wave_id(); b < nblk; b += nw) {
+    const T *p;
+    int dr, dc;
+    src(b, p, dr, dc);
+    p = cdz_uni(p);
+    dr = cdz_uni(dr);
+    dc = cdz_uni(dc);
+    const T v = (r < dr && c < dc) ? p[off] : T(0);
+    if (lane < 36) dst[b * 36 + lane] = v;
+  }
+}
+
 // Workgroup barrier that orders LDS accesses only: global stores issued
 // before it are not drained (a plain __syncthreads waits for every
 // outstanding store).  Use __syncthreads where global data written by one

@@ -567,35 +567,44 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
       cdz_sync();
     }
     const T *tab = C.tab;
-    // ---- Qb (one thread per slot pair), all operands in LDS
+    // ---- Qb: thread (a, o) sums the terms of output o = (s, s2) whose slot
+    //      at i+1 is a; the six partial sums are added afterwards
+    if (tid < 216) {
+      const int a = tid / 36, o = tid % 36, s = o / 6, s2 = o % 6;
+      T part = 0;
+      if (s < di && s2 < dj && a < d1) {
+        const int t = cdz_ptype(C.nt[1][s], C.nt[4][s2]);
+        if (t >= 0) {
+          const int na = C.nt[2][a];
+          const T ea = C.eI[s * 6 + a];
+          T acc = 0, hp = 0, st = 0, ml = 0;
+#pragma unroll
+          for (int b = 0; b < 6; b++) {
+            if (b >= dm) continue;
+            const int nb = C.nt[3][b];
+            const T w = ea * C.eJm1[b * 6 + s2];
+            const T mmo = tab[TB_MM + na * 24 + nb * 6 + t];
+            const int o2 = a * 6 + b;
+            hp += w * C.Uin[o2] * mmo;
+            acc += w * (C.gf[o2] + C.gf[36 + o2] * mmo);
+            ml += w * C.Xin[o2];
+            const int t2 = cdz_ptype(na, nb);
+            if (dl - 2 >= 4 && t2 >= 0) st += w * C.Bin[o2] * tab[TB_ST + t * 6 + t2];
+          }
+          part = acc + (hp * D.Bhp[dl - 1] + st + ml * tab[TB_MLAB]) * cdz_p2<T>(sE[dl - 2] - Ed);
+        }
+      }
+      red[a * 36 + o] = part;
+    }
+    cdz_sync();
     if (tid < 36) {
       const int s = tid / 6, s2 = tid % 6;
       T qb = 0;
       if (s < di && s2 < dj) {
-        const int t = cdz_ptype(C.nt[1][s], C.nt[4][s2]);
-        if (t >= 0) {
-          const T f2 = cdz_p2<T>(sE[dl - 2] - Ed);
-          T acc = 0, hp = 0, st = 0, ml = 0;
+        T acc = 0;
 #pragma unroll
-          for (int a = 0; a < 6; a++) {
-            const int na = C.nt[2][a];
-#pragma unroll
-            for (int b = 0; b < 6; b++) {
-              if (a >= d1 || b >= dm) continue;
-              const int nb = C.nt[3][b];
-              const T w = C.eI[s * 6 + a] * C.eJm1[b * 6 + s2];
-              const T mmo = tab[TB_MM + na * 24 + nb * 6 + t];
-              const int o = a * 6 + b;
-              hp += w * C.Uin[o] * mmo;
-              acc += w * (C.gf[o] + C.gf[36 + o] * mmo);
-              ml += w * C.Xin[o];
-              const int t2 = cdz_ptype(na, nb);
-              if (dl - 2 >= 4 && t2 >= 0) st += w * C.Bin[o] * tab[TB_ST + t * 6 + t2];
-            }
-          }
-          acc += (hp * D.Bhp[dl - 1] + st + ml * tab[TB_MLAB]) * f2;
-          qb = C.vI[s] * C.vJ[s2] * acc;
-        }
+        for (int a = 0; a < 6; a++) acc += red[a * 36 + tid];
+        qb = C.vI[s] * C.vJ[s2] * acc;
         D.Qb[(Pi + s) * ld + Pj + s2] = qb;
         vmax = fmaxf(vmax, (float)fabs(qb));
       }
@@ -607,7 +616,8 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
       }
     }
     cdz_sync();
-    // ---- Qm1 and DI (Qb dressed as an interior loop's inner pair)
+    // ---- Qm1, and DI (Qb dressed as an interior loop's inner pair) with
+    //      thread (x, o) summing over the slot y of j for output o = (b, c)
     if (tid < 36) {
       const int s = tid / 6, s2 = tid % 6;
       T q1 = 0;
@@ -620,28 +630,33 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
         vmax = fmaxf(vmax, (float)fabs(q1));
       }
       C.qm1[tid] = q1;
-      if (i >= 1 && j + 1 < n) {
-        const int b = tid / 6, c = tid % 6;
-        if (b < C.d[0] && c < C.d[5]) {
-          const int nb = C.nt[0][b], nc = C.nt[5][c];
-          T a = 0;
+    }
+    const bool hasDI = i >= 1 && j + 1 < n;
+    if (hasDI && tid < 216) {
+      const int x = tid / 36, o = tid % 36, b = o / 6, c = o % 6;
+      T part = 0;
+      if (x < di && b < C.d[0] && c < C.d[5]) {
+        const int nb = C.nt[0][b], nc = C.nt[5][c];
+        const T eb = C.eIm1[b * 6 + x];
 #pragma unroll
-          for (int x = 0; x < 6; x++)
-#pragma unroll
-            for (int y = 0; y < 6; y++) {
-              const T q = C.qb[x * 6 + y];
-              const int t2 = cdz_ptype(C.nt[4][y], C.nt[1][x]);
-              if (q != T(0) && t2 >= 0)
-                a += C.eIm1[b * 6 + x] * q * C.eJ[y * 6 + c] * tab[TB_MM + nc * 24 + nb * 6 + t2];
-            }
-          D.DI[(C.P[0] + b) * ld + C.P[5] + c] = a;
+        for (int y = 0; y < 6; y++) {
+          const T q = C.qb[x * 6 + y];
+          const int t2 = cdz_ptype(C.nt[4][y], C.nt[1][x]);
+          if (q != T(0) && t2 >= 0) part += eb * q * C.eJ[y * 6 + c] * tab[TB_MM + nc * 24 + nb * 6 + t2];
         }
       }
+      red[x * 36 + o] = part;
     }
     cdz_sync();
-    // ---- Qm1L, Qm1p, QmX, Qm
+    // ---- DI, Qm1L, Qm1p, QmX, Qm
     if (tid < 36) {
       const int s = tid / 6, s2 = tid % 6;
+      if (hasDI && s < C.d[0] && s2 < C.d[5]) {
+        T a = 0;
+#pragma unroll
+        for (int x = 0; x < 6; x++) a += red[x * 36 + tid];
+        D.DI[(C.P[0] + s) * ld + C.P[5] + s2] = a;
+      }
       if (i >= 1 && s < C.d[0] && s2 < dj) {
         T a = 0;
 #pragma unroll
