@@ -273,6 +273,26 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         }
       }
       cdz_sync();
+      // per term, once: Ulc . e_{i-1} (left) and e_j . Urr (right), in place
+      {
+        const int lane = tid & 63, r = lane / 6, c = lane % 6;
+        for (int b = cdz_wave_id(); b < nl + nr; b += CDZ_NT / 64) {
+          T *blk = b < nl ? Ulc + b * 36 : Urr + (b - nl) * 36;
+          T v = 0;
+          if (lane < 36) {
+            if (b < nl) {  // (Ulc . e_{i-1})(a, x) = sum_b U[i-l1][i-1](a,b) e_{i-1}(b,x)
+#pragma unroll
+              for (int k = 0; k < 6; k++) v += blk[r * 6 + k] * C.eIm1[k * 6 + c];
+            } else {  // (e_j . Urr)(y, dd) = sum_c e_j(y,c) U[j+1][j+l2](c,dd)
+#pragma unroll
+              for (int k = 0; k < 6; k++) v += C.eJ[r * 6 + k] * blk[k * 6 + c];
+            }
+          }
+          cdz_wave_sync();
+          if (lane < 36) blk[lane] = v;
+        }
+      }
+      cdz_sync();
       const int q = tid % 36, g = tid / 36, x = q / 6, y = q % 6;
       if (g < 7) {
         T acc = 0;
@@ -280,29 +300,19 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
           if (term < nl) {
             const int l1 = term + 1;
             const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[dl] - sE[dl + l1 + 2]);
-            const T *ul = Ulc + (l1 - 1) * 36, *gg = Gbc + (l1 - 1) * 36;
-            T s = 0;
+            const T *m = Ulc + (l1 - 1) * 36, *gg = Gbc + (l1 - 1) * 36;
+            T sm = 0;
 #pragma unroll
-            for (int a = 0; a < 6; a++) {
-              T m = 0;
-#pragma unroll
-              for (int b = 0; b < 6; b++) m += ul[a * 6 + b] * C.eIm1[b * 6 + x];
-              s += m * gg[a * 6 + y];
-            }
-            acc += f * s;
+            for (int a = 0; a < 6; a++) sm += m[a * 6 + x] * gg[a * 6 + y];
+            acc += f * sm;
           } else {
             const int l2 = term - nl + 1;
             const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[dl] + sE[l2 - 1] - sE[dl + l2 + 2]);
-            const T *ur = Urr + (l2 - 1) * 36, *gg = Gbr + (l2 - 1) * 36;
-            T s = 0;
+            const T *m = Urr + (l2 - 1) * 36, *gg = Gbr + (l2 - 1) * 36;
+            T sm = 0;
 #pragma unroll
-            for (int dd = 0; dd < 6; dd++) {
-              T m = 0;
-#pragma unroll
-              for (int c = 0; c < 6; c++) m += C.eJ[y * 6 + c] * ur[c * 6 + dd];
-              s += gg[x * 6 + dd] * m;
-            }
-            acc += f * s;
+            for (int dd = 0; dd < 6; dd++) sm += gg[x * 6 + dd] * m[y * 6 + dd];
+            acc += f * sm;
           }
         }
         GP[g * 36 + q] = acc;
@@ -365,23 +375,42 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
       C.qm1b[tid] = q1b;
     }
     cdz_sync();
-    // ---- Qb'
+    // ---- Qb': thread (b, o) adds the interior-loop terms with outer slot b
+    //      at i-1 and the stack terms with slot b at i-1 of output o = (x, y)
+    if (tid < 216) {
+      const int b = tid / 36, o = tid % 36, x = o / 6, y = o % 6;
+      T part = 0;
+      if (x < di && y < dj && hasL && hasR && b < dim1) {
+        const int nx = C.nt[1][x], ny = C.nt[4][y];
+        const int tin = cdz_ptype(ny, nx);  // inner pair read in loop order (j, i)
+        const T eb = C.eIm1[b * 6 + x];
+        if (tin >= 0) {
+#pragma unroll
+          for (int c = 0; c < 6; c++)
+            if (c < djp1)
+              part += C.w[b * 6 + c] * eb * C.eJ[y * 6 + c] * tab[TB_MM + C.nt[5][c] * 24 + C.nt[0][b] * 6 + tin];
+        }
+        const int txy = cdz_ptype(nx, ny);
+        if (txy >= 0) {  // stacked under (i-1, j+1)
+          const T f2 = cdz_p2<T>(sE[dl] - sE[dl + 2]);
+#pragma unroll
+          for (int r = 0; r < 6; r++) {
+            const int to = cdz_ptype(C.nt[0][b], C.nt[5][r]);
+            if (r < djp1 && to >= 0)
+              part += C.qbOut[b * 6 + r] * C.vIm1[b] * C.vJp1[r] * eb * C.eJ[y * 6 + r] * tab[TB_ST + to * 6 + txy] * f2;
+          }
+        }
+      }
+      red[b * 36 + o] = part;
+    }
+    cdz_sync();
     if (tid < 36) {
       const int x = s, y = t;
       T qbb = 0;
       if (x < di && y < dj) {
         qbb = C.qm1b[tid] * tab[TB_MLB] + C.w[36 + tid];
-        const int nx = C.nt[1][x], ny = C.nt[4][y];
-        const int tin = cdz_ptype(ny, nx);  // inner pair read in loop order (j, i)
-        if (hasL && hasR && tin >= 0) {
 #pragma unroll
-          for (int b = 0; b < 6; b++)
-#pragma unroll
-            for (int c = 0; c < 6; c++)
-              if (b < dim1 && c < djp1)
-                qbb += C.w[b * 6 + c] * C.eIm1[b * 6 + x] * C.eJ[y * 6 + c] *
-                       tab[TB_MM + C.nt[5][c] * 24 + C.nt[0][b] * 6 + tin];
-        }
+        for (int b = 0; b < 6; b++) qbb += red[b * 36 + tid];
         {  // exterior loop: prefix before i, suffix after j (FP64)
           double zl = 1.0;
           int G = 0;
@@ -393,48 +422,49 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
           }
           qbb += (T)(zl * C.z3[y] * ldexp(1.0, G + D.H3[j] + sE[dl] - EZ));
         }
-        const int txy = cdz_ptype(nx, ny);
-        if (hasL && hasR && txy >= 0) {  // stacked under (i-1, j+1)
-          const T f2 = cdz_p2<T>(sE[dl] - sE[dl + 2]);
-#pragma unroll
-          for (int q = 0; q < 6; q++)
-#pragma unroll
-            for (int r = 0; r < 6; r++) {
-              const int to = cdz_ptype(C.nt[0][q], C.nt[5][r]);
-              if (q < dim1 && r < djp1 && to >= 0) {
-                const T ac = C.qbOut[q * 6 + r] * C.vIm1[q] * C.vJp1[r];
-                qbb += ac * C.eIm1[q * 6 + x] * C.eJ[y * 6 + r] * tab[TB_ST + to * 6 + txy] * f2;
-              }
-            }
-        }
         A.Qbb[(Pi + x) * ld + Pj + y] = qbb;
       }
       C.qbb[tid] = qbb;
     }
     cdz_sync();
-    // ---- outer-edge-dressed adjoints of this cell's loop sums, block (i+1, j-1)
+    // ---- outer-edge-dressed adjoints of this cell's loop sums, block (i+1, j-1):
+    //      thread (q, o) sums over the slot r of j for output o = (a, dd)
+    if (tid < 216) {
+      const int q = tid / 36, o = tid % 36, a = o / 6, dd = o % 6;
+      T gb = 0, fb = 0;
+      if (a < d1 && dd < dm && q < di) {
+        const int na = C.nt[2][a], nd = C.nt[3][dd];
+        const T wq = C.vI[q] * C.eI[q * 6 + a];
+#pragma unroll
+        for (int r = 0; r < 6; r++) {
+          const int to = cdz_ptype(C.nt[1][q], C.nt[4][r]);
+          if (r < dj && to >= 0) {
+            const T w = C.qbb[q * 6 + r] * wq * C.vJ[r] * C.eJm1[dd * 6 + r];
+            gb += w;
+            fb += w * tab[TB_MM + na * 24 + nd * 6 + to];
+          }
+        }
+      }
+      X[q * 36 + o] = gb;
+      X[216 + q * 36 + o] = fb;
+    }
+    cdz_sync();
     if (tid < 36) {
       const int a = s, dd = t;
       T gb = 0, fb = 0;
+#pragma unroll
+      for (int q = 0; q < 6; q++) {
+        gb += X[q * 36 + tid];
+        fb += X[216 + q * 36 + tid];
+      }
       if (a < d1 && dd < dm) {
-        const int na = C.nt[2][a], nd = C.nt[3][dd];
-#pragma unroll
-        for (int q = 0; q < 6; q++)
-#pragma unroll
-          for (int r = 0; r < 6; r++) {
-            const int to = cdz_ptype(C.nt[1][q], C.nt[4][r]);
-            if (q < di && r < dj && to >= 0) {
-              const T w = C.qbb[q * 6 + r] * C.vI[q] * C.vJ[r] * C.eI[q * 6 + a] * C.eJm1[dd * 6 + r];
-              gb += w;
-              fb += w * tab[TB_MM + na * 24 + nd * 6 + to];
-            }
-          }
         A.Gb[(P1 + a) * ld + Pm + dd] = gb;
         A.Fb[(P1 + a) * ld + Pm + dd] = fb;
       }
       C.gb[tid] = gb;
       C.fb[tid] = fb;
     }
+    cdz_sync();
     // ---- adjoints of the interior-loop sums by size, AB[L-2] = A'(i,j,L):
     //      from F (F = sum_L w_int(L) A) and, through the size recursion,
     //      from the enclosing cell (i-1, j+1) at size L + 2 (kept in a ring
@@ -629,6 +659,27 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         X[(kind * 30 + l - 1) * 36 + q] = v;
       }
       cdz_sync();
+      // per term, once and in place: R(a, x) = sum_y Gb(a,y) Qb[k][j-1](x,y)
+      // (left) and S(y, dd) = sum_x Qb[i+1][l](x,y) Gb(x,dd) (right)
+      {
+        const int lane = tid & 63, r = lane / 6, c = lane % 6;
+        for (int b = cdz_wave_id(); b < 2 * lmax; b += CDZ_NT / 64) {
+          T *blk = b < lmax ? QL + b * 36 : QR + (b - lmax) * 36;
+          T v = 0;
+          if (lane < 36) {
+            if (b < lmax) {
+#pragma unroll
+              for (int k = 0; k < 6; k++) v += C.gb[r * 6 + k] * blk[c * 6 + k];
+            } else {
+#pragma unroll
+              for (int k = 0; k < 6; k++) v += blk[k * 6 + r] * C.gb[k * 6 + c];
+            }
+          }
+          cdz_wave_sync();
+          if (lane < 36) blk[lane] = v;
+        }
+      }
+      cdz_sync();
       constexpr int NPB = (2 * 30 * 36 + CDZ_NT - 1) / CDZ_NT;
       int off[NPB];
       T val[NPB];
@@ -643,27 +694,17 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
         const T *el = (side == 0 ? EL : ER) + (l - 1) * 36, *qk = (side == 0 ? QL : QR) + (l - 1) * 36;
         const T f = tab[TB_BU + l] * cdz_p2<T>(sE[l - 1] + sE[dl - 2 - l] - sE[dl]);
         T v = 0;
-        if (side == 0) {  // U'[i+1][i+l](a, b) = sum_x,y Gb(a,y) e_{k-1}(b,x) Qb[k][j-1](x,y)
+        if (side == 0) {  // U'[i+1][i+l](a, b) = sum_x e_{k-1}(b,x) R(a,x)
           if (r < d1 && c < lp_d[l - 1]) {
 #pragma unroll
-            for (int x = 0; x < 6; x++) {
-              T mm = 0;
-#pragma unroll
-              for (int y = 0; y < 6; y++) mm += C.gb[r * 6 + y] * qk[x * 6 + y];
-              v += el[c * 6 + x] * mm;
-            }
+            for (int x = 0; x < 6; x++) v += el[c * 6 + x] * qk[r * 6 + x];
             off[m] = (P1 + r) * (int)ld + lp_P[l - 1] + c;
             val[m] = f * v;
           }
-        } else {  // U'[j-l][j-1](c, dd) = sum_x,y Gb(x,dd) Qb[i+1][l](x,y) e_l(y,c)
+        } else {  // U'[j-l][j-1](c, dd) = sum_y e_l(y,c) S(y,dd)
           if (r < rp_d[l - 1] && c < dm) {
 #pragma unroll
-            for (int y = 0; y < 6; y++) {
-              T mm = 0;
-#pragma unroll
-              for (int x = 0; x < 6; x++) mm += C.gb[x * 6 + c] * qk[x * 6 + y];
-              v += mm * el[y * 6 + r];
-            }
+            for (int y = 0; y < 6; y++) v += el[y * 6 + r] * qk[y * 6 + c];
             off[m] = (rp_P[l - 1] + r) * (int)ld + Pm + c;
             val[m] = f * v;
           }
