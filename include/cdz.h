@@ -130,6 +130,49 @@ cdz_status cdz_marginals(cdz_handle *h, const cdz_problem *prob, double *log_z,
 cdz_status cdz_sample(cdz_handle *h, const cdz_problem *prob, uint64_t seed,
                       int32_t n_samples, uint8_t *codons, int32_t *pairs);
 
+/* Batched forms (Section 3a's design problems come in sets of proteins of
+ * uneven length): `count` problems on one handle.  The batch is split, in
+ * order, into chunks whose device workspaces together fit the budget
+ * (options.mem_budget_bytes, else 90% of the free device memory less 1 GiB);
+ * inside a chunk one launch per diagonal index runs that diagonal of every
+ * protein in the chunk.  Each protein's results equal those of the
+ * single-problem call (bit for bit: same kernels, same order of operations).
+ * Outputs are concatenated in batch order; with n_c = 3 * n_aa of problem c,
+ * problem b's block starts at
+ *   log_z      [count]                 b
+ *   pair       n_c * n_c per problem    sum_{c<b} n_c^2
+ *   base       n_c * 4                  4 * sum_{c<b} n_c
+ *   codon      n_aa_c * 6               6 * sum_{c<b} n_aa_c
+ *   codon_pair n_aa_c * 36              36 * sum_{c<b} n_aa_c
+ *   codons     n_samples * n_aa_c       n_samples * sum_{c<b} n_aa_c
+ *   pairs      n_samples * n_c          n_samples * sum_{c<b} n_c
+ * with each block laid out as in the single-problem call.  Problem b's samples
+ * are drawn with key seed + b (the samples cdz_sample gives with that seed).
+ * The handle keeps no forward pass afterwards (cdz_sample / cdz_marginals on
+ * a single problem recompute theirs).  Errors: CDZ_ERR_ARG for count < 0,
+ * null lists or outputs, or n_samples < 0; a problem's validation error is
+ * reported with its index in cdz_last_error; CDZ_ERR_BUDGET when one
+ * protein's workspace alone exceeds mem_budget_bytes (CDZ_ERR_NOMEM without
+ * a budget).  Outputs of problems before a failing chunk are written. */
+
+/* Forward of every problem (log_z may be NULL), the outside pass when any
+ * marginal output is non-NULL, and n_samples samples of each problem when
+ * n_samples > 0 (codons and pairs then required), all in one call. */
+cdz_status cdz_batch(cdz_handle *h, const cdz_problem *probs, int32_t count, int32_t n_samples,
+                     uint64_t seed, double *log_z, double *pair, double *base, double *codon,
+                     double *codon_pair, uint8_t *codons, int32_t *pairs);
+cdz_status cdz_partition_batch(cdz_handle *h, const cdz_problem *probs, int32_t count, double *log_z);
+cdz_status cdz_marginals_batch(cdz_handle *h, const cdz_problem *probs, int32_t count, double *log_z,
+                               double *pair, double *base, double *codon, double *codon_pair);
+cdz_status cdz_sample_batch(cdz_handle *h, const cdz_problem *probs, int32_t count, uint64_t seed,
+                            int32_t n_samples, uint8_t *codons, int32_t *pairs);
+
+/* Device workspace (bytes) that one problem needs in the handle's precision:
+ * forward arrays, plus the outside pass when `adjoint` is non-zero.  The
+ * single-problem calls allocate this much; a batch chunk holds problems whose
+ * sum stays within the budget.  No device work. */
+cdz_status cdz_workspace_bytes(cdz_handle *h, const cdz_problem *prob, int32_t adjoint, size_t *bytes);
+
 /* Device-pointer form of the forward pass for callers that keep the weights
  * on the device (PyTorch): theta1_dev [n_aa][6], theta2_dev [n_aa][6][6] or
  * NULL, doubles in device memory.  log_z is a host pointer.  The stream is the

@@ -21,7 +21,9 @@ STATUS = ["CDZ_OK", "CDZ_ERR_ARG", "CDZ_ERR_PROTEIN", "CDZ_ERR_NUMERIC", "CDZ_ER
           "CDZ_ERR_BUDGET", "CDZ_ERR_HIP", "CDZ_ERR_STATE"]
 EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_sample",
            "cdz_forward_dev", "cdz_backward_dev", "cdz_last_timings", "cdz_reset",
-           "cdz_set_profiling", "cdz_kernel_timings", "cdz_status_string", "cdz_last_error"]
+           "cdz_set_profiling", "cdz_kernel_timings", "cdz_status_string", "cdz_last_error",
+           "cdz_batch", "cdz_partition_batch", "cdz_marginals_batch", "cdz_sample_batch",
+           "cdz_workspace_bytes"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -68,6 +70,17 @@ def lib():
             "cdz_reset": ([vp], ctypes.c_int),
             "cdz_set_profiling": ([vp, ctypes.c_int], ctypes.c_int),
             "cdz_kernel_timings": ([vp, _dp], ctypes.c_int),
+            "cdz_batch": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                           _dp, _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_uint8),
+                           ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "cdz_partition_batch": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_int32, _dp], ctypes.c_int),
+            "cdz_marginals_batch": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_int32, _dp, _dp, _dp, _dp,
+                                     _dp], ctypes.c_int),
+            "cdz_sample_batch": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_int32, ctypes.c_uint64,
+                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8),
+                                  ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "cdz_workspace_bytes": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             if hasattr(L, name):
@@ -150,6 +163,76 @@ def cdz_sample(h: Handle, prob, seed: int, n_samples: int):
                              cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                              pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return cod, pairs
+
+
+class _Batch:
+    """Marshalled problem array of a batch and its output offsets."""
+
+    def __init__(self, probs):
+        self.items = [_Prob(p) for p in probs]
+        self.arr = (cdz_problem * max(1, len(probs)))(*[it.c for it in self.items])
+        self.m = [len(p.prot) for p in probs]
+        self.n = [3 * x for x in self.m]
+
+    def split(self, flat, sizes, shape):
+        out, at = [], 0
+        for k, sz in enumerate(sizes):
+            out.append(flat[at:at + sz].reshape(shape(k)))
+            at += sz
+        return out
+
+
+def cdz_batch(h: Handle, probs, n_samples: int = 0, seed: int = 0, marginals: bool = True) -> dict:
+    """One call over a list of problems: log Z of each, marginals (if asked)
+    and n_samples samples of each (problem b drawn with seed + b).  Outputs
+    are split back into per-problem arrays."""
+    B = _Batch(probs)
+    cnt = len(probs)
+    sn2, sn, sm = sum(x * x for x in B.n), sum(B.n), sum(B.m)
+    logz = np.zeros(max(1, cnt))
+    pair = np.zeros(sn2) if marginals else None
+    base = np.zeros(sn * 4) if marginals else None
+    cod1 = np.zeros(sm * 6) if marginals else None
+    cod2 = np.zeros(sm * 36) if marginals else None
+    sc = np.zeros(max(1, n_samples * sm), np.uint8)
+    sp = np.zeros(max(1, n_samples * sn), np.int32)
+    h.check(lib().cdz_batch(h.ptr, B.arr, cnt, n_samples, ctypes.c_uint64(seed), _arr(logz), _arr(pair),
+                            _arr(base), _arr(cod1), _arr(cod2),
+                            sc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if n_samples else None,
+                            sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if n_samples else None))
+    out = {"logz": logz[:cnt].copy()}
+    if marginals:
+        out["pair"] = B.split(pair, [x * x for x in B.n], lambda k: (B.n[k], B.n[k]))
+        out["base"] = B.split(base, [x * 4 for x in B.n], lambda k: (B.n[k], 4))
+        out["codon"] = B.split(cod1, [x * 6 for x in B.m], lambda k: (B.m[k], 6))
+        out["codon_pair"] = B.split(cod2, [x * 36 for x in B.m], lambda k: (B.m[k], 6, 6))
+    if n_samples:
+        out["codons"] = B.split(sc, [n_samples * x for x in B.m], lambda k: (n_samples, B.m[k]))
+        out["pairs"] = B.split(sp, [n_samples * x for x in B.n], lambda k: (n_samples, B.n[k]))
+    return out
+
+
+def cdz_workspace_bytes(h: Handle, prob, adjoint: bool = True) -> int:
+    p = _Prob(prob)
+    out = ctypes.c_size_t(0)
+    h.check(lib().cdz_workspace_bytes(h.ptr, ctypes.byref(p.c), int(adjoint), ctypes.byref(out)))
+    return int(out.value)
+
+
+def cdz_partition_batch(h: Handle, probs) -> np.ndarray:
+    B = _Batch(probs)
+    out = np.zeros(max(1, len(probs)))
+    h.check(lib().cdz_partition_batch(h.ptr, B.arr, len(probs), _arr(out)))
+    return out[:len(probs)].copy()
+
+
+def cdz_marginals_batch(h: Handle, probs) -> dict:
+    return cdz_batch(h, probs, 0, 0, True)
+
+
+def cdz_sample_batch(h: Handle, probs, seed: int, n_samples: int):
+    r = cdz_batch(h, probs, n_samples, seed, False)
+    return r.get("codons", []), r.get("pairs", [])
 
 
 def cdz_forward_dev(h: Handle, aa: str, theta1_ptr: int, theta2_ptr: int) -> float:

@@ -143,6 +143,20 @@ __device__ __forceinline__ void cdz_wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Batched launches: off[0..count] are prefix sums of the workgroups of each
+// problem (off[0] = 0).  Workgroup blk belongs to the largest b with
+// off[b] <= blk (problems without workgroups are skipped), as its w-th block.
+__device__ __forceinline__ void cdz_batch_locate(const int *off, int count, int blk, int &b, int &w) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  b = cdz_uni(lo);
+  w = cdz_uni(blk - off[lo]);
+}
+
 // Stage blocks of up to 6 x 6 values into LDS (dst[b * 36 + r * 6 + c]), one
 // wavefront per block: the block's source (row-major, stride ld, dr x dc
 // valid entries) is wave-uniform, lane q < 36 moves entry (q / 6, q % 6), so

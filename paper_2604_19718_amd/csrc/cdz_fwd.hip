@@ -242,8 +242,10 @@ __device__ __forceinline__ int win_base(int l1) {  // first window index with th
   return 31 * l1 - l1 * (l1 - 1) / 2;
 }
 
+// One cell (or the exterior step) of diagonal dl; blk is the workgroup's index
+// among the workgroups of this problem's diagonal.
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
+__device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1]
   T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(D.n + 1) * 4 + 15) / 16 * 16);
@@ -255,14 +257,14 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
   cdz_sync();
   const int Ed = choose_exponent(D, dl, sE);
   if (tid == 0) sE[dl] = Ed;
-  if (blockIdx.x == 0 && tid == 0) D.E[dl] = Ed;
+  if (blk == 0 && tid == 0) D.E[dl] = Ed;
   cdz_sync();
   const int ncell = n - dl > 0 ? n - dl : 0;
-  if ((int)blockIdx.x == cdz_cells_grid(ncell)) {
+  if (blk == cdz_cells_grid(ncell)) {
     exterior_step<T>(D, dl, sE, reinterpret_cast<double *>(red));
     return;
   }
-  const int i = cdz_cell_of_block(blockIdx.x, ncell), j = i + dl;
+  const int i = cdz_cell_of_block(blk, ncell), j = i + dl;
   if (i >= ncell) return;
 
   // ---- stage: positions i-1, i, i+1, j-1, j, j+1 (clamped; unused when absent)
@@ -705,7 +707,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
 // Z5[j], j = W..n-1, from pairs (k, j) with j - k <= W (Z5[0..W-1] are the
 // exact values of the truncated pass).  One workgroup, positions in turn.
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_exterior_trunc(DevProb<T> D, int W) {
+__device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) {
   __shared__ double red[(CDZ_NT / 64) * 6 + 6];
   double *tot = red + (CDZ_NT / 64) * 6;
   const int n = D.n, tid = threadIdx.x;
@@ -770,7 +772,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_exterior_trunc(DevProb<T> D, int W
 // C[p] from the current Z5, v and vd rescaled by it; res[3] accumulates
 // C[n-1] over the rescalings (log Z = log Z~ + res[3] ln 2).
 template <typename T>
-__global__ __launch_bounds__(1024) void cdz_landscape(DevProb<T> D) {
+__device__ __forceinline__ void landscape_body(const DevProb<T> &D) {
   const int n = D.n;
   for (int p = threadIdx.x; p < n; p += blockDim.x) {
     double z = 0;
@@ -794,8 +796,8 @@ __global__ __launch_bounds__(1024) void cdz_landscape(DevProb<T> D) {
 // octaves of FP32 underflow?  Then res[5] = 1 (the pass is repeated with the
 // landscape of the exact pass).
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_spread_check(DevProb<T> D) {
-  const int dl = blockIdx.x, n = D.n, ncell = n - dl;
+__device__ __forceinline__ void spread_check_body(const DevProb<T> &D, int dl) {
+  const int n = D.n, ncell = n - dl;
   const long long ld = D.ld;
   T *const full[6] = {D.U, D.Qb, D.Qm1, D.Qm1p, D.QmX, D.Qm};
   const T low = (T)ldexp(1.0, -100);
@@ -811,6 +813,54 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_spread_check(DevProb<T> D) {
   if (__any(weak) && (threadIdx.x & 63) == 0) D.res[5] = 1.0;
 }
 
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
+  fwd_cell<T>(D, dl, blockIdx.x);
+}
+
+// Batched wavefront: one launch runs diagonal dl of every problem of a batch.
+// off[0..count] are the prefix sums of the workgroups per problem for this
+// launch (problems without work on dl have none).
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag_batch(const DevProb<T> *probs, const int *off, int count,
+                                                            int dl) {
+  int b, w;
+  cdz_batch_locate(off, count, blockIdx.x, b, w);
+  const DevProb<T> D = probs[b];
+  fwd_cell<T>(D, dl, w);
+}
+
+// per problem b of a batch: the span-truncated exterior prefix (span W[b]),
+// the landscape, and the spread check over off (n_b workgroups per problem)
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_exterior_trunc_batch(const DevProb<T> *probs, const int *W) {
+  const int b = blockIdx.x;
+  exterior_trunc_body<T>(probs[b], W[b]);
+}
+template <typename T>
+__global__ __launch_bounds__(1024) void cdz_landscape_batch(const DevProb<T> *probs) {
+  landscape_body<T>(probs[blockIdx.x]);
+}
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_spread_check_batch(const DevProb<T> *probs, const int *off, int count) {
+  int b, w;
+  cdz_batch_locate(off, count, blockIdx.x, b, w);
+  spread_check_body<T>(probs[b], w);
+}
+
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_exterior_trunc(DevProb<T> D, int W) {
+  exterior_trunc_body<T>(D, W);
+}
+template <typename T>
+__global__ __launch_bounds__(1024) void cdz_landscape(DevProb<T> D) {
+  landscape_body<T>(D);
+}
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_spread_check(DevProb<T> D) {
+  spread_check_body<T>(D, blockIdx.x);
+}
+
 template __global__ void cdz_exterior_trunc<float>(DevProb<float>, int);
 template __global__ void cdz_exterior_trunc<double>(DevProb<double>, int);
 template __global__ void cdz_landscape<float>(DevProb<float>);
@@ -819,3 +869,11 @@ template __global__ void cdz_spread_check<float>(DevProb<float>);
 template __global__ void cdz_spread_check<double>(DevProb<double>);
 template __global__ void cdz_fwd_diag<float>(DevProb<float>, int);
 template __global__ void cdz_fwd_diag<double>(DevProb<double>, int);
+template __global__ void cdz_fwd_diag_batch<float>(const DevProb<float> *, const int *, int, int);
+template __global__ void cdz_fwd_diag_batch<double>(const DevProb<double> *, const int *, int, int);
+template __global__ void cdz_exterior_trunc_batch<float>(const DevProb<float> *, const int *);
+template __global__ void cdz_exterior_trunc_batch<double>(const DevProb<double> *, const int *);
+template __global__ void cdz_landscape_batch<float>(const DevProb<float> *);
+template __global__ void cdz_landscape_batch<double>(const DevProb<double> *);
+template __global__ void cdz_spread_check_batch<float>(const DevProb<float> *, const int *, int);
+template __global__ void cdz_spread_check_batch<double>(const DevProb<double> *, const int *, int);

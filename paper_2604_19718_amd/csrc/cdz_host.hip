@@ -99,13 +99,6 @@ cdz_status cdz_fail(cdz_handle *h, cdz_status s, const std::string &msg) {
   return s;
 }
 
-#define HIPCHK(h, x)                                                               \
-  do {                                                                             \
-    hipError_t e_ = (x);                                                           \
-    if (e_ != hipSuccess)                                                          \
-      return cdz_fail((h), CDZ_ERR_HIP, std::string(#x " failed: ") + hipGetErrorString(e_)); \
-  } while (0)
-
 extern "C" const char *cdz_status_string(cdz_status s) {
   int k = (int)s;
   return (k >= 0 && k <= 7) ? kStatusText[k] : "unknown status";
@@ -148,6 +141,7 @@ extern "C" void cdz_destroy(cdz_handle *h) {
   if (!h) return;
   if (h->ws) (void)hipFree(h->ws);
   if (h->smp) (void)hipFree(h->smp);
+  if (h->bws) (void)hipFree(h->bws);
   for (auto &ev : h->ev)
     if (ev) (void)hipEventDestroy(ev);
   for (auto &ev : h->pev) (void)hipEventDestroy(ev);
@@ -254,7 +248,7 @@ struct Carver {
 }  // namespace
 
 template <typename T>
-static size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool adjoint) {
+size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool adjoint) {
   Carver c;
   const int n = t.n, S = t.S;
   const long long ld = ((long long)S + 31) / 32 * 32;
@@ -291,7 +285,7 @@ static size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A
 }
 
 template <typename T>
-static cdz_status upload(cdz_handle *h, const HostTables &t, DevProb<T> &D) {
+cdz_status upload(cdz_handle *h, const HostTables &t, DevProb<T> &D) {
   std::vector<T> v(t.v.begin(), t.v.end()), e(t.e.begin(), t.e.end()), tab(t.tab.begin(), t.tab.end()),
       bhp(t.Bhp.begin(), t.Bhp.end());
   hipStream_t st = h->stream;
@@ -309,6 +303,10 @@ static cdz_status upload(cdz_handle *h, const HostTables &t, DevProb<T> &D) {
   HIPCHK(h, hipStreamSynchronize(st));
   return CDZ_OK;
 }
+template size_t carve<float>(char *, const HostTables &, DevProb<float> &, DevAdj<float> &, bool);
+template size_t carve<double>(char *, const HostTables &, DevProb<double> &, DevAdj<double> &, bool);
+template cdz_status upload<float>(cdz_handle *, const HostTables &, DevProb<float> &);
+template cdz_status upload<double>(cdz_handle *, const HostTables &, DevProb<double> &);
 
 template <typename T>
 __global__ void cdz_fwd_diag(DevProb<T> D, int dl);
@@ -321,8 +319,6 @@ __global__ void cdz_exterior_trunc(DevProb<T> D, int W);
 template <typename T>
 __global__ void cdz_spread_check(DevProb<T> D);
 
-// span limit of the truncated pass that estimates the FP32 landscape
-#define CDZ_LANDSCAPE_SPAN 96
 
 template <typename T>
 static cdz_status forward_pass(cdz_handle *h, DevProb<T> &D, size_t shm, bool timed, int dlmax) {

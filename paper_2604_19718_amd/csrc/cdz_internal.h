@@ -59,6 +59,8 @@ struct cdz_handle {
   size_t ws_bytes = 0;
   void *smp = nullptr;  // sampler workspace (stacks, group sums, outputs)
   size_t smp_bytes = 0;
+  void *bws = nullptr;  // batched calls: problem descriptors and launch offset tables
+  size_t bws_bytes = 0;
   hipEvent_t ev[8] = {};
   double times[5] = {0, 0, 0, 0, 0};
   // per-launch event timing of the diagonal kernels (cdz_set_profiling)
@@ -87,12 +89,40 @@ inline void store_dev(cdz_handle *h, const DevProb<double> &D, const DevAdj<doub
   h->ad = A;
 }
 
+// span limit of the truncated pass that estimates the FP32 landscape
+#define CDZ_LANDSCAPE_SPAN 96
+
 template <typename T>
 size_t fwd_lds_bytes(int n);  // dynamic LDS of the forward diagonal kernel
 template <typename T>
 size_t out_lds_bytes(int n);  // dynamic LDS of the outside diagonal kernel
+size_t eta_lds_bytes(int n);  // dynamic LDS of the edge-marginal kernel
+
+// workspace carve (base == nullptr: only the size) and table upload of one problem
+template <typename T>
+size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool adjoint);
+template <typename T>
+cdz_status upload(cdz_handle *h, const HostTables &t, DevProb<T> &D);
+// marginal outputs of one problem from its device edge marginals and pair
+// probabilities (r = 2^EZ / Z~); any output may be NULL
+cdz_status assemble_marginals(cdz_handle *h, const HostTables &t, const double *eta_dev, const double *pair_dev,
+                              double r, double *pair, double *base, double *codon, double *codon_pair);
+
+// N samples of each problem of a batch (problem b with seed + b)
+template <typename T>
+cdz_status sample_batch(cdz_handle *h, const std::vector<DevProb<T>> &Ds, uint64_t seed, int N, uint8_t *codons,
+                        int32_t *pairs);
 
 cdz_status cdz_fail(cdz_handle *h, cdz_status s, const std::string &msg);
+
+// return CDZ_ERR_HIP from the enclosing function when a HIP call fails
+#define HIPCHK(h, x)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (x);                                                                      \
+    if (e_ != hipSuccess)                                                                     \
+      return cdz_fail((h), CDZ_ERR_HIP, std::string(#x " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
 cdz_status build_tables(cdz_handle *h, int32_t n_aa, const char *aa, const double *theta1,
                         const double *theta2, HostTables &t);
 cdz_status ensure_forward(cdz_handle *h, const HostTables &t, bool adjoint);

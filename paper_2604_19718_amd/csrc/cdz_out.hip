@@ -89,7 +89,7 @@ __device__ __forceinline__ T *ring_at(const DevAdj<T> &A, int n, int dl, int i, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A, int dl) {
+__device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A, int dl, int blk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = D.n, tid = threadIdx.x;
   const long long ld = D.ld;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A
   T *X = AB + 29 * 36;
   for (int k = tid; k < n; k += CDZ_NT) sE[k] = D.E[k];
   const int EZ = (int)D.res[2];
-  const int i = cdz_cell_of_block(blockIdx.x, n - dl), j = i + dl;
+  const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
   if (i >= n - dl) return;
   if (tid < 6) {
     const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
@@ -779,9 +779,9 @@ __device__ __forceinline__ T loop_inner(const DevProb<T> &D, int i, int j, int a
 }
 
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A) {
+__device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A, int p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int n = D.n, tid = threadIdx.x, p = blockIdx.x;
+  const int n = D.n, tid = threadIdx.x;
   const long long ld = D.ld;
   int *sE = reinterpret_cast<int *>(smem_raw);
   double *red = reinterpret_cast<double *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
@@ -1039,6 +1039,35 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A) {
   for (int r = tid; r < 36; r += CDZ_NT) A.eta[p * 36 + r] = out[r] + A.etaV[p * 36 + r] + A.etaW[p * 36 + r];
 }
 
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A, int dl) {
+  out_cell<T>(D, A, dl, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A) {
+  eta_edge<T>(D, A, blockIdx.x);
+}
+// batched forms (see cdz_fwd_diag_batch): one launch for diagonal dl / for the
+// edges of every problem of a batch
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_out_diag_batch(const DevProb<T> *probs, const DevAdj<T> *adjs,
+                                                            const int *off, int count, int dl) {
+  int b, w;
+  cdz_batch_locate(off, count, blockIdx.x, b, w);
+  const DevProb<T> D = probs[b];
+  const DevAdj<T> A = adjs[b];
+  out_cell<T>(D, A, dl, w);
+}
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_eta_batch(const DevProb<T> *probs, const DevAdj<T> *adjs,
+                                                       const int *off, int count) {
+  int b, w;
+  cdz_batch_locate(off, count, blockIdx.x, b, w);
+  const DevProb<T> D = probs[b];
+  const DevAdj<T> A = adjs[b];
+  eta_edge<T>(D, A, w);
+}
+
 // pair probabilities P[i][j] = r * sum Qb~ Qb'~ over cells with j - i >= 4
 template <typename T>
 __global__ void cdz_pairprob(DevProb<T> D, DevAdj<T> A, double r) {
@@ -1074,12 +1103,9 @@ __global__ void cdz_grad_theta(const double *eta, const int *d, int m, double sc
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-#define HIPCHK(h, x)                                                                          \
-  do {                                                                                        \
-    hipError_t e_ = (x);                                                                      \
-    if (e_ != hipSuccess)                                                                     \
-      return cdz_fail((h), CDZ_ERR_HIP, std::string(#x " failed: ") + hipGetErrorString(e_)); \
-  } while (0)
+size_t eta_lds_bytes(int n) {
+  return ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 36 + 36) * 8;
+}
 
 template <typename T>
 static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
@@ -1106,7 +1132,7 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   }
   HIPCHK(h, hipGetLastError());
   if (n >= 2) {
-    const size_t shm2 = ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 36 + 36) * 8;
+    const size_t shm2 = eta_lds_bytes(n);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n], st));
     hipLaunchKernelGGL(cdz_eta<T>, dim3(n - 1), dim3(CDZ_NT), shm2, st, D, A);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n + 1], st));
@@ -1155,14 +1181,19 @@ extern "C" cdz_status cdz_marginals(cdz_handle *h, const cdz_problem *prob, doub
   if (s != CDZ_OK) return s;
   s = outside(h);
   if (s != CDZ_OK) return s;
+  if (log_z) *log_z = h->logz;
+  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz_scaled);
+  return assemble_marginals(h, t, eta_dev(h), pair_dev(h), r, pair, base, codon, codon_pair);
+}
+
+cdz_status assemble_marginals(cdz_handle *h, const HostTables &t, const double *eta_dev, const double *pair_dev,
+                              double r, double *pair, double *base, double *codon, double *codon_pair) {
   const int n = t.n, m = t.m;
   std::vector<double> eta((size_t)n * 36);
-  HIPCHK(h, hipMemcpy(eta.data(), eta_dev(h), eta.size() * 8, hipMemcpyDeviceToHost));
-  const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz_scaled);
+  HIPCHK(h, hipMemcpy(eta.data(), eta_dev, eta.size() * 8, hipMemcpyDeviceToHost));
   std::vector<double> cod((size_t)m * 6, 0.0);
   for (int a = 0; a < m; a++)
     for (int c = 0; c < t.d[3 * a]; c++) cod[a * 6 + c] = r * eta[(size_t)(3 * a) * 36 + c * 6 + c];
-  if (log_z) *log_z = h->logz;
   if (codon) memcpy(codon, cod.data(), cod.size() * 8);
   if (codon_pair) {
     for (int k = 0; k < m * 36; k++) codon_pair[k] = 0.0;
@@ -1178,7 +1209,7 @@ extern "C" cdz_status cdz_marginals(cdz_handle *h, const cdz_problem *prob, doub
     }
   }
   if (pair) {
-    HIPCHK(h, hipMemcpy(pair, pair_dev(h), (size_t)n * n * 8, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(pair, pair_dev, (size_t)n * n * 8, hipMemcpyDeviceToHost));
     for (int i = 0; i < n; i++)
       for (int j = i + 1; j < n; j++) pair[(size_t)j * n + i] = pair[(size_t)i * n + j];
     for (int i = 0; i < n; i++) {
@@ -1257,3 +1288,11 @@ extern "C" cdz_status cdz_debug_copy(cdz_handle *h, int which, void *dst, size_t
 
 template __global__ void cdz_out_diag<float>(DevProb<float>, DevAdj<float>, int);
 template __global__ void cdz_out_diag<double>(DevProb<double>, DevAdj<double>, int);
+template __global__ void cdz_out_diag_batch<float>(const DevProb<float> *, const DevAdj<float> *, const int *, int,
+                                                    int);
+template __global__ void cdz_out_diag_batch<double>(const DevProb<double> *, const DevAdj<double> *, const int *,
+                                                     int, int);
+template __global__ void cdz_eta_batch<float>(const DevProb<float> *, const DevAdj<float> *, const int *, int);
+template __global__ void cdz_eta_batch<double>(const DevProb<double> *, const DevAdj<double> *, const int *, int);
+template __global__ void cdz_pairprob<float>(DevProb<float>, DevAdj<float>, double);
+template __global__ void cdz_pairprob<double>(DevProb<double>, DevAdj<double>, double);

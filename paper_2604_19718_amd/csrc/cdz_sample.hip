@@ -718,10 +718,8 @@ __device__ void f_m1p(W<T> &w, int i, int j, int s, int s2) {
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(256) void cdz_sample_kernel(Smp<T> S) {
+__device__ __forceinline__ void sample_one(const Smp<T> &S, int sid) {
   const int lane = threadIdx.x & 63;
-  const int sid = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (sid >= S.nsamp) return;
   const DevProb<T> &D = S.D;
   const int n = D.n, m = D.m;
   W<T> w;
@@ -773,12 +771,19 @@ __global__ __launch_bounds__(256) void cdz_sample_kernel(Smp<T> S) {
   }
 }
 
-#define HIPCHK(h, x)                                                                          \
-  do {                                                                                        \
-    hipError_t e_ = (x);                                                                      \
-    if (e_ != hipSuccess)                                                                     \
-      return cdz_fail((h), CDZ_ERR_HIP, std::string(#x " failed: ") + hipGetErrorString(e_)); \
-  } while (0)
+template <typename T>
+__global__ __launch_bounds__(256) void cdz_sample_kernel(Smp<T> S) {
+  const int sid = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (sid < S.nsamp) sample_one<T>(S, sid);
+}
+
+// many problems in one launch: N samples of each, wavefront g runs sample
+// g % N of problem g / N
+template <typename T>
+__global__ __launch_bounds__(256) void cdz_sample_batch_kernel(const Smp<T> *S, int N, int total) {
+  const int g = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (g < total) sample_one<T>(S[g / N], g % N);
+}
 
 template <typename T>
 static cdz_status run_sample(cdz_handle *h, const DevProb<T> &D, uint64_t seed, int N,
@@ -832,6 +837,87 @@ static cdz_status run_sample(cdz_handle *h, const DevProb<T> &D, uint64_t seed, 
     if (err[k]) return cdz_fail(h, CDZ_ERR_NUMERIC, "sampling failed (sample " + std::to_string(k) + ")");
   return CDZ_OK;
 }
+
+// Samples of a batch of problems whose forward passes are on the device: N per
+// problem, problem b drawn with seed + b (the same samples as cdz_sample of
+// that problem alone with that seed).  Outputs concatenated in batch order.
+template <typename T>
+cdz_status sample_batch(cdz_handle *h, const std::vector<DevProb<T>> &Ds, uint64_t seed, int N, uint8_t *codons,
+                        int32_t *pairs) {
+  const int cnt = (int)Ds.size();
+  if (cnt == 0 || N == 0) return CDZ_OK;
+  std::vector<Smp<T>> S(cnt);
+  std::vector<size_t> need(cnt);
+  size_t tot = (size_t)cnt * sizeof(Smp<T>) + 4096;
+  for (int b = 0; b < cnt; b++) {
+    const int n = Ds[b].n, m = Ds[b].m;
+    S[b].D = Ds[b];
+    S[b].seed = seed + (uint64_t)b;
+    S[b].nsamp = N;
+    S[b].cap = n + 16;
+    S[b].gcap = (n > CDZ_NWIN + 2 ? n : CDZ_NWIN + 2) + 64;
+    need[b] = (size_t)N * S[b].cap * 5 * 4 + (size_t)N * S[b].gcap * 8 + (size_t)N * n + (size_t)N * m +
+              (size_t)N * n * 4 + (size_t)N * 4 + 6 * 256;
+    tot += need[b];
+  }
+  if (tot > h->smp_bytes) {
+    if (h->smp) (void)hipFree(h->smp);
+    h->smp = nullptr;
+    h->smp_bytes = 0;
+    if (hipMalloc(&h->smp, tot) != hipSuccess) {
+      (void)hipGetLastError();
+      return cdz_fail(h, CDZ_ERR_NOMEM, "sampler workspace allocation failed");
+    }
+    h->smp_bytes = tot;
+  }
+  char *p = (char *)h->smp;
+  auto take = [&](size_t bytes) {
+    char *r = p;
+    p += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  Smp<T> *dS = (Smp<T> *)take((size_t)cnt * sizeof(Smp<T>));
+  for (int b = 0; b < cnt; b++) {
+    const int n = Ds[b].n, m = Ds[b].m;
+    S[b].stack = (int *)take((size_t)N * S[b].cap * 5 * 4);
+    S[b].gbuf = (double *)take((size_t)N * S[b].gcap * 8);
+    S[b].state = (signed char *)take((size_t)N * n);
+    S[b].codons = (uint8_t *)take((size_t)N * m);
+    S[b].pairs = (int32_t *)take((size_t)N * n * 4);
+    S[b].err = (int *)take((size_t)N * 4);
+  }
+  hipStream_t st = h->stream;
+  HIPCHK(h, hipMemcpyAsync(dS, S.data(), (size_t)cnt * sizeof(Smp<T>), hipMemcpyHostToDevice, st));
+  const int total = cnt * N;
+  HIPCHK(h, hipEventRecord(h->ev[4], st));
+  hipLaunchKernelGGL(cdz_sample_batch_kernel<T>, dim3((total + 3) / 4), dim3(256), 0, st, dS, N, total);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipEventRecord(h->ev[5], st));
+  std::vector<std::vector<int>> err(cnt, std::vector<int>(N));
+  size_t oc = 0, op = 0;
+  for (int b = 0; b < cnt; b++) {
+    const int n = Ds[b].n, m = Ds[b].m;
+    HIPCHK(h, hipMemcpyAsync(codons + oc, S[b].codons, (size_t)N * m, hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(pairs + op, S[b].pairs, (size_t)N * n * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(err[b].data(), S[b].err, (size_t)N * 4, hipMemcpyDeviceToHost, st));
+    oc += (size_t)N * m;
+    op += (size_t)N * n;
+  }
+  HIPCHK(h, hipStreamSynchronize(st));
+  float ms = 0;
+  HIPCHK(h, hipEventElapsedTime(&ms, h->ev[4], h->ev[5]));
+  h->times[2] += ms;
+  for (int b = 0; b < cnt; b++)
+    for (int k = 0; k < N; k++)
+      if (err[b][k])
+        return cdz_fail(h, CDZ_ERR_NUMERIC, "sampling failed (problem " + std::to_string(b) + ", sample " +
+                                                std::to_string(k) + ")");
+  return CDZ_OK;
+}
+template cdz_status sample_batch<float>(cdz_handle *, const std::vector<DevProb<float>> &, uint64_t, int, uint8_t *,
+                                        int32_t *);
+template cdz_status sample_batch<double>(cdz_handle *, const std::vector<DevProb<double>> &, uint64_t, int,
+                                         uint8_t *, int32_t *);
 
 extern "C" cdz_status cdz_sample(cdz_handle *h, const cdz_problem *prob, uint64_t seed,
                                  int32_t n_samples, uint8_t *codons, int32_t *pairs) {
