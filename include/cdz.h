@@ -96,7 +96,10 @@ typedef struct {
 
 typedef struct {
   cdz_precision prec;
-  size_t mem_budget_bytes; /* 0 = unlimited; otherwise CDZ_ERR_BUDGET above it */
+  size_t mem_budget_bytes; /* 0 = unlimited; else the device workspace stays
+                              within it (memory-bounded form when needed, see
+                              cdz_workspace_bytes), CDZ_ERR_BUDGET below the
+                              minimum                                          */
   void *hip_stream;        /* hipStream_t to run on; NULL = the null stream     */
 } cdz_options;
 
@@ -167,11 +170,25 @@ cdz_status cdz_marginals_batch(cdz_handle *h, const cdz_problem *probs, int32_t 
 cdz_status cdz_sample_batch(cdz_handle *h, const cdz_problem *probs, int32_t count, uint64_t seed,
                             int32_t n_samples, uint8_t *codons, int32_t *pairs);
 
-/* Device workspace (bytes) that one problem needs in the handle's precision:
- * forward arrays, plus the outside pass when `adjoint` is non-zero.  The
- * single-problem calls allocate this much; a batch chunk holds problems whose
- * sum stays within the budget.  No device work. */
-cdz_status cdz_workspace_bytes(cdz_handle *h, const cdz_problem *prob, int32_t adjoint, size_t *bytes);
+/* Device workspace (bytes) that one problem needs in the handle's precision,
+ * for `what`:
+ *   CDZ_WS_FORWARD       forward arrays, all diagonals resident (cdz_partition,
+ *                        cdz_sample without a budget)
+ *   CDZ_WS_MARGINALS     forward + outside, all resident (cdz_marginals
+ *                        without a budget; what each batch member takes)
+ *   CDZ_WS_MARGINALS_MIN the least budget cdz_marginals accepts: forward +
+ *                        outside with the interior-loop sums kept only as
+ *                        checkpoints and one recomputed band of diagonals
+ *                        (or the resident form where that is smaller, as for
+ *                        sequences of about 120 nt and less)
+ *   CDZ_WS_FORWARD_MIN   the least budget cdz_partition / cdz_sample accept:
+ *                        forward with those sums in a ring of 3 diagonals
+ * The single-problem calls use the resident form when it fits
+ * options.mem_budget_bytes (or no budget is set), else the minimum form, whose
+ * results are the same bit for bit; below the minimum they return
+ * CDZ_ERR_BUDGET.  No device work. */
+enum { CDZ_WS_FORWARD = 0, CDZ_WS_MARGINALS = 1, CDZ_WS_MARGINALS_MIN = 2, CDZ_WS_FORWARD_MIN = 3 };
+cdz_status cdz_workspace_bytes(cdz_handle *h, const cdz_problem *prob, int32_t what, size_t *bytes);
 
 /* Device-pointer form of the forward pass for callers that keep the weights
  * on the device (PyTorch): theta1_dev [n_aa][6], theta2_dev [n_aa][6][6] or

@@ -52,6 +52,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime under the same soname as the system
+        # one the library links; whichever is loaded first serves the whole
+        # process, and torch cannot start its device on a runtime other than
+        # its own.  Load torch's first so that one runtime serves both.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         sig = {
@@ -81,6 +89,8 @@ def lib():
                                   ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_workspace_bytes": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+            "cdz_debug_al_k": ([vp], ctypes.c_int),
+            "cdz_debug_force_al_k": ([vp, ctypes.c_int], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             if hasattr(L, name):
@@ -212,10 +222,13 @@ def cdz_batch(h: Handle, probs, n_samples: int = 0, seed: int = 0, marginals: bo
     return out
 
 
-def cdz_workspace_bytes(h: Handle, prob, adjoint: bool = True) -> int:
+CDZ_WS_FORWARD, CDZ_WS_MARGINALS, CDZ_WS_MARGINALS_MIN, CDZ_WS_FORWARD_MIN = 0, 1, 2, 3
+
+
+def cdz_workspace_bytes(h: Handle, prob, what: int = CDZ_WS_MARGINALS) -> int:
     p = _Prob(prob)
     out = ctypes.c_size_t(0)
-    h.check(lib().cdz_workspace_bytes(h.ptr, ctypes.byref(p.c), int(adjoint), ctypes.byref(out)))
+    h.check(lib().cdz_workspace_bytes(h.ptr, ctypes.byref(p.c), int(what), ctypes.byref(out)))
     return int(out.value)
 
 

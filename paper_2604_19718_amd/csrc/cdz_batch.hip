@@ -301,7 +301,7 @@ cdz_status run_batch(cdz_handle *h, const std::vector<HostTables> &tabs, int32_t
     DevAdj<T> A;
     memset(&D, 0, sizeof(D));
     memset(&A, 0, sizeof(A));
-    need[b] = (carve<T>(nullptr, tabs[b], D, A, adjoint) + 255) / 256 * 256;
+    need[b] = (carve<T>(nullptr, tabs[b], D, A, adjoint, CDZ_AL_RESIDENT) + 255) / 256 * 256;
     if ((unsigned long long)D.ld * (unsigned long long)D.ld > 0x7fffffffull)
       return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(tabs[b].n) + " nt is too long for 32-bit block offsets");
     biggest = std::max(biggest, need[b]);
@@ -353,7 +353,7 @@ cdz_status run_batch(cdz_handle *h, const std::vector<HostTables> &tabs, int32_t
       DevAdj<T> A;
       memset(&D, 0, sizeof(D));
       memset(&A, 0, sizeof(A));
-      carve<T>((char *)h->ws + at, tabs[b], D, A, adjoint);
+      carve<T>((char *)h->ws + at, tabs[b], D, A, adjoint, CDZ_AL_RESIDENT);
       at += need[b];
       cdz_status s = upload<T>(h, tabs[b], D);
       if (s != CDZ_OK) return s;
@@ -393,22 +393,30 @@ cdz_status run_batch(cdz_handle *h, const std::vector<HostTables> &tabs, int32_t
 
 }  // namespace
 
-extern "C" cdz_status cdz_workspace_bytes(cdz_handle *h, const cdz_problem *prob, int32_t adjoint, size_t *bytes) {
+extern "C" cdz_status cdz_workspace_bytes(cdz_handle *h, const cdz_problem *prob, int32_t what, size_t *bytes) {
   if (!h) return CDZ_ERR_ARG;
-  if (!prob || !bytes) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
+  if (!prob || !bytes || what < 0 || what > 3) return cdz_fail(h, CDZ_ERR_ARG, "bad argument");
   HostTables t;
   cdz_status s = build_tables(h, prob->n_aa, prob->aa, prob->theta1, prob->theta2, t);
   if (s != CDZ_OK) return s;
-  const bool adj = adjoint != 0;
-  if (h->opt.prec == CDZ_FP64) {
-    DevProb<double> D;
-    DevAdj<double> A;
-    *bytes = (carve<double>(nullptr, t, D, A, adj) + 255) / 256 * 256;
-  } else {
-    DevProb<float> D;
-    DevAdj<float> A;
-    *bytes = (carve<float>(nullptr, t, D, A, adj) + 255) / 256 * 256;
-  }
+  const bool adj = what == CDZ_WS_MARGINALS || what == CDZ_WS_MARGINALS_MIN;
+  const bool least = what == CDZ_WS_MARGINALS_MIN || what == CDZ_WS_FORWARD_MIN;
+  auto size = [&](int alK) -> size_t {
+    size_t b;
+    if (h->opt.prec == CDZ_FP64) {
+      DevProb<double> D;
+      DevAdj<double> A;
+      b = carve<double>(nullptr, t, D, A, adj, alK);
+    } else {
+      DevProb<float> D;
+      DevAdj<float> A;
+      b = carve<float>(nullptr, t, D, A, adj, alK);
+    }
+    return (b + 255) / 256 * 256;
+  };
+  *bytes = size(CDZ_AL_RESIDENT);
+  // short sequences: the resident form can be the smaller one
+  if (least) *bytes = std::min(*bytes, size(adj ? al_best_k(t.n) : 0));
   return CDZ_OK;
 }
 

@@ -57,6 +57,14 @@ struct DevProb {
   // (i,j) at rows P[i+1].. and columns CDZ_NA*P[j-1] + (L-2)*d[j-1] + ..
   T *AL;
   long long ldA;           // CDZ_NA * ld
+  // Memory-bounded form (AL == nullptr): A is kept diagonal-major, a diagonal
+  // being [n][CDZ_NA][36] (cell i at i * CDZ_NA * 36, blocks padded to 6 x 6)
+  // in one of the slots ALs[nslot]; each launch is given the diagonal it
+  // writes (ALw) and the diagonal dl - 2 it reads (ALp).  alK > 0: the outside
+  // pass recomputes bands of alK diagonals from checkpoints (see cdz_host.hip).
+  T *ALs, *ALw;
+  const T *ALp;
+  int alK, alTop, alSlots;
   int *E;                  // [n + 1] diagonal exponents
   unsigned *maxb;          // [n + 1] float bits of max |entry| per diagonal
   double *Z5;              // [n][6] prefix exterior partition function

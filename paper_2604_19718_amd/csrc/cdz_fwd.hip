@@ -242,6 +242,120 @@ __device__ __forceinline__ int win_base(int l1) {  // first window index with th
   return 31 * l1 - l1 * (l1 - 1) / 2;
 }
 
+// Interior-loop sums A(i,j,L), L = 2..lmax, of cell (i, j) into AC by the
+// loop-size recursion, staging on the way UR1 = U[i+1][i+l] and UC1 =
+// U[j-l][j-1] (l = 1..lmax), which the bulge sums of the forward read next.
+// The forward and the recomputation of A for the memory-bounded outside pass
+// both run this code, so they produce the same bits.  A(i+1, j-1, .) comes
+// from D.AL (all diagonals resident) or from D.ALp (diagonal dl - 2, stored
+// diagonal-major).
+template <typename T>
+__device__ __forceinline__ void a_window(const DevProb<T> &D, const CellStage<T> &C, const int *sE, T *W, int i,
+                                         int j, int dl, int lmax, int Ed) {
+  const int tid = threadIdx.x;
+  const long long ld = D.ld;
+  const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
+  T *UR1 = W;              // [l-1] U[i+1][i+l]
+  T *UC1 = W + 30 * 36;    // [l-1] U[j-l][j-1]
+  T *X = W + 60 * 36;      // phase-dependent blocks
+  T *DIrow = X;            // [L-2] DI[i+1][j-L+1]
+  T *DIcol = X + 29 * 36;  // [L-3] DI[i+L-1][j-1]
+  T *AP = X + 57 * 36;     // [L-2] A(i+1,j-1,L), then A(i+1,j-1,L) . W
+  T *AC = X + 84 * 36;     // [L-2] A(i,j,L)
+  const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
+  const int nAP = lmax - 3 > 0 ? lmax - 3 : 0;  // L = 2..lmax-2
+  if (lmax >= 1) {
+    const int n0 = lmax, n1 = 2 * lmax, n2 = n1 + (lmax - 1), n3 = n2 + (lmax >= 3 ? lmax - 2 : 0),
+              n4 = n3 + nAP;
+    for (int idx = tid; idx < n4 * 36; idx += CDZ_NT) {
+      const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
+      T v = 0;
+      if (b < n0) {  // U[i+1][i+l], l = b + 1
+        if (r < d1 && c < lp_d[b]) v = D.U[(long long)(P1 + r) * ld + lp_P[b] + c];
+        UR1[b * 36 + q] = v;
+      } else if (b < n1) {  // U[j-l][j-1], l = b - n0 + 1
+        const int l = b - n0 + 1;
+        if (r < rp_d[l - 1] && c < dm) v = D.U[(long long)(rp_P[l - 1] + r) * ld + Pm + c];
+        UC1[(l - 1) * 36 + q] = v;
+      } else if (b < n2) {  // DI[i+1][j-L+1], L = b - n1 + 2
+        const int L = b - n1 + 2;
+        if (r < d1 && c < rp_d[L - 2]) v = D.DI[(long long)(P1 + r) * ld + rp_P[L - 2] + c];
+        DIrow[(L - 2) * 36 + q] = v;
+      } else if (b < n3) {  // DI[i+L-1][j-1], L = b - n2 + 3
+        const int L = b - n2 + 3;
+        if (r < lp_d[L - 2] && c < dm) v = D.DI[(long long)(lp_P[L - 2] + r) * ld + Pm + c];
+        DIcol[(L - 3) * 36 + q] = v;
+      } else {  // A(i+1, j-1, L), L = b - n3 + 2
+        const int L = b - n3 + 2;
+        if (r < lp_d[1] && c < rp_d[1])
+          v = D.AL ? D.AL[(long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + (L - 2) * rp_d[1] + c]
+                   : D.ALp[(long long)(i + 1) * (CDZ_NA * 36) + (L - 2) * 36 + q];
+        AP[(L - 2) * 36 + q] = v;
+      }
+    }
+  }
+  cdz_sync();
+  // AP <- AP . W (in place: every output is read into registers first)
+  {
+    T t4[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int idx = tid + u * CDZ_NT;
+      t4[u] = 0;
+      if (idx < nAP * 36) {
+        const int b = idx / 36, q = idx % 36, a2 = q / 6, dd = q % 6;
+        T s = 0;
+#pragma unroll
+        for (int d2 = 0; d2 < 6; d2++) s += AP[b * 36 + a2 * 6 + d2] * C.eJm2[d2 * 6 + dd];
+        t4[u] = s * C.vJm1[dd];
+      }
+    }
+    cdz_sync();
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int idx = tid + u * CDZ_NT;
+      if (idx < nAP * 36) AP[idx] = t4[u];
+    }
+  }
+  cdz_sync();
+  // A(i,j,L), L = 2..lmax
+  const T frec = cdz_p2<T>(sE[dl >= 2 ? dl - 2 : 0] - Ed);
+  for (int idx = tid; idx < (lmax - 1) * 36; idx += CDZ_NT) {
+    const int L = idx / 36 + 2, q = idx % 36, a = q / 6, dd = q % 6;
+    const T fb = cdz_p2<T>(sE[dl - L - 2] + sE[L - 2] - Ed);
+    T rec = 0, b1 = 0, b2 = 0;
+    if (L >= 4) {
+#pragma unroll
+      for (int a2 = 0; a2 < 6; a2++) rec += C.eI1[a * 6 + a2] * AP[(L - 4) * 36 + a2 * 6 + dd];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; c++) b1 += DIrow[(L - 2) * 36 + a * 6 + c] * UC1[(L - 2) * 36 + c * 6 + dd];
+    if (L >= 3) {
+#pragma unroll
+      for (int b = 0; b < 6; b++) b2 += UR1[(L - 2) * 36 + a * 6 + b] * DIcol[(L - 3) * 36 + b * 6 + dd];
+    }
+    AC[(L - 2) * 36 + q] = C.vI1[a] * (rec * frec + b1 * fb) + b2 * C.vJm1[dd] * fb;
+  }
+  cdz_sync();
+}
+
+// Store A(i,j,L), L = 2..CDZ_NA+1, of cell (i, j) (zero where no inner pair
+// fits): into D.AL at rows P[i+1].., or, diagonal-major, into D.ALw at cell i
+// (all 36 entries of each block, padding zero).
+template <typename T>
+__device__ __forceinline__ void a_store(const DevProb<T> &D, const CellStage<T> &C, int i, int lmax, const T *AC) {
+  const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
+  for (int idx = threadIdx.x; idx < CDZ_NA * 36; idx += CDZ_NT) {
+    const int L = idx / 36 + 2, qq = idx % 36, a = qq / 6, dd = qq % 6;
+    const T v = (L <= lmax && a < d1 && dd < dm) ? AC[(L - 2) * 36 + qq] : T(0);
+    if (D.AL) {
+      if (a < d1 && dd < dm) D.AL[(long long)(P1 + a) * D.ldA + (long long)CDZ_NA * Pm + (L - 2) * dm + dd] = v;
+    } else {
+      D.ALw[(long long)i * (CDZ_NA * 36) + idx] = v;
+    }
+  }
+}
+
 // One cell (or the exterior step) of diagonal dl; blk is the workgroup's index
 // among the workgroups of this problem's diagonal.
 template <typename T>
@@ -414,84 +528,9 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
       T *UR1 = W;              // [l-1] U[i+1][i+l]
       T *UC1 = W + 30 * 36;    // [l-1] U[j-l][j-1]
       T *X = W + 60 * 36;      // phase-dependent blocks
-      T *DIrow = X;            // [L-2] DI[i+1][j-L+1]
-      T *DIcol = X + 29 * 36;  // [L-3] DI[i+L-1][j-1]
-      T *AP = X + 57 * 36;     // [L-2] A(i+1,j-1,L), then A(i+1,j-1,L) . W
       T *AC = X + 84 * 36;     // [L-2] A(i,j,L)
       const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
-      const int nAP = lmax - 3 > 0 ? lmax - 3 : 0;  // L = 2..lmax-2
-      if (lmax >= 1) {
-        const int n0 = lmax, n1 = 2 * lmax, n2 = n1 + (lmax - 1), n3 = n2 + (lmax >= 3 ? lmax - 2 : 0),
-                  n4 = n3 + nAP;
-        for (int idx = tid; idx < n4 * 36; idx += CDZ_NT) {
-          const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
-          T v = 0;
-          if (b < n0) {  // U[i+1][i+l], l = b + 1
-            if (r < d1 && c < lp_d[b]) v = D.U[(long long)(P1 + r) * ld + lp_P[b] + c];
-            UR1[b * 36 + q] = v;
-          } else if (b < n1) {  // U[j-l][j-1], l = b - n0 + 1
-            const int l = b - n0 + 1;
-            if (r < rp_d[l - 1] && c < dm) v = D.U[(long long)(rp_P[l - 1] + r) * ld + Pm + c];
-            UC1[(l - 1) * 36 + q] = v;
-          } else if (b < n2) {  // DI[i+1][j-L+1], L = b - n1 + 2
-            const int L = b - n1 + 2;
-            if (r < d1 && c < rp_d[L - 2]) v = D.DI[(long long)(P1 + r) * ld + rp_P[L - 2] + c];
-            DIrow[(L - 2) * 36 + q] = v;
-          } else if (b < n3) {  // DI[i+L-1][j-1], L = b - n2 + 3
-            const int L = b - n2 + 3;
-            if (r < lp_d[L - 2] && c < dm) v = D.DI[(long long)(lp_P[L - 2] + r) * ld + Pm + c];
-            DIcol[(L - 3) * 36 + q] = v;
-          } else {  // A(i+1, j-1, L), L = b - n3 + 2
-            const int L = b - n3 + 2;
-            if (r < lp_d[1] && c < rp_d[1])
-              v = D.AL[(long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + (L - 2) * rp_d[1] + c];
-            AP[(L - 2) * 36 + q] = v;
-          }
-        }
-      }
-      cdz_sync();
-      // AP <- AP . W (in place: every output is read into registers first)
-      {
-        T t4[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-          const int idx = tid + u * CDZ_NT;
-          t4[u] = 0;
-          if (idx < nAP * 36) {
-            const int b = idx / 36, q = idx % 36, a2 = q / 6, dd = q % 6;
-            T s = 0;
-#pragma unroll
-            for (int d2 = 0; d2 < 6; d2++) s += AP[b * 36 + a2 * 6 + d2] * C.eJm2[d2 * 6 + dd];
-            t4[u] = s * C.vJm1[dd];
-          }
-        }
-        cdz_sync();
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-          const int idx = tid + u * CDZ_NT;
-          if (idx < nAP * 36) AP[idx] = t4[u];
-        }
-      }
-      cdz_sync();
-      // A(i,j,L), L = 2..lmax
-      const T frec = cdz_p2<T>(sE[dl >= 2 ? dl - 2 : 0] - Ed);
-      for (int idx = tid; idx < (lmax - 1) * 36; idx += CDZ_NT) {
-        const int L = idx / 36 + 2, q = idx % 36, a = q / 6, dd = q % 6;
-        const T fb = cdz_p2<T>(sE[dl - L - 2] + sE[L - 2] - Ed);
-        T rec = 0, b1 = 0, b2 = 0;
-        if (L >= 4) {
-#pragma unroll
-          for (int a2 = 0; a2 < 6; a2++) rec += C.eI1[a * 6 + a2] * AP[(L - 4) * 36 + a2 * 6 + dd];
-        }
-#pragma unroll
-        for (int c = 0; c < 6; c++) b1 += DIrow[(L - 2) * 36 + a * 6 + c] * UC1[(L - 2) * 36 + c * 6 + dd];
-        if (L >= 3) {
-#pragma unroll
-          for (int b = 0; b < 6; b++) b2 += UR1[(L - 2) * 36 + a * 6 + b] * DIcol[(L - 3) * 36 + b * 6 + dd];
-        }
-        AC[(L - 2) * 36 + q] = C.vI1[a] * (rec * frec + b1 * fb) + b2 * C.vJm1[dd] * fb;
-      }
-      cdz_sync();
+      a_window<T>(D, C, sE, W, i, j, dl, lmax, Ed);
       if (tid < 36) {
         T f = 0;
         for (int L = 2; L <= lmax; L++) f += C.tab[TB_IN + L] * AC[(L - 2) * 36 + tid];
@@ -560,12 +599,7 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
       // keep A(i,j,L), L = 2..CDZ_NA+1, for the cells of diagonal dl + 2 and
       // the outside pass (zero where no inner pair fits); stored after the
       // loads above so that none of them waits behind these stores
-      for (int idx = tid; idx < CDZ_NA * 36; idx += CDZ_NT) {
-        const int L = idx / 36 + 2, qq = idx % 36, a = qq / 6, dd = qq % 6;
-        if (a < d1 && dd < dm)
-          D.AL[(long long)(P1 + a) * D.ldA + (long long)CDZ_NA * Pm + (L - 2) * dm + dd] =
-              L <= lmax ? AC[(L - 2) * 36 + qq] : T(0);
-      }
+      a_store<T>(D, C, i, lmax, AC);
       cdz_sync();
     }
     const T *tab = C.tab;
@@ -813,6 +847,48 @@ __device__ __forceinline__ void spread_check_body(const DevProb<T> &D, int dl) {
   if (__any(weak) && (threadIdx.x & 63) == 0) D.res[5] = 1.0;
 }
 
+// Recompute the interior-loop sums A of the cells of diagonal dl (>= 4) into
+// D.ALw, from the stored U, DI and exponents of the final forward pass: the
+// memory-bounded outside pass rebuilds a band of diagonals this way from its
+// checkpoints.  Same LDS layout and window code as the forward.
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_arec_diag(DevProb<T> D, int dl) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1]
+  T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(D.n + 1) * 4 + 15) / 16 * 16);
+  CellStage<T> &C = *reinterpret_cast<CellStage<T> *>(red + (CDZ_NT / 64) * 72);
+  T *W = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(CellStage<T>) + 15) / 16 * 16);
+  const int n = D.n, tid = threadIdx.x, ncell = n - dl;
+  const int i = cdz_cell_of_block(blockIdx.x, ncell), j = i + dl;
+  if (i >= ncell) return;
+  for (int k = tid; k <= dl; k += CDZ_NT) sE[k] = D.E[k];
+  if (tid < 6) {
+    const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
+    const int p = pos[tid];
+    const bool ok = p >= 0 && p < n;
+    C.d[tid] = ok ? D.d[p] : 0;
+    C.P[tid] = ok ? D.P[p] : 0;
+  } else if (tid >= 64 && tid < 128) {
+    const int q = tid - 64;
+    const int p = q < 32 ? i + 1 + q : j - 1 - (q - 32);
+    const bool ok = p >= 0 && p < n;
+    C.wd[q] = ok ? D.d[p] : 0;
+    C.wP[q] = ok ? D.P[p] : 0;
+  } else if (tid >= 128 && tid < 164) {
+    const int q = tid - 128;
+    C.eI1[q] = i + 1 < n ? D.e[(i + 1) * 36 + q] : T(0);
+    C.eJm2[q] = j >= 2 ? D.e[(j - 2) * 36 + q] : T(0);
+    if (q < 6) {
+      C.vI1[q] = i + 1 < n ? D.v[(i + 1) * 6 + q] : T(0);
+      C.vJm1[q] = j >= 1 ? D.v[(j - 1) * 6 + q] : T(0);
+    }
+  }
+  cdz_sync();
+  const int lmax = min(CDZ_MAXLOOP, dl - 6);
+  a_window<T>(D, C, sE, W, i, j, dl, lmax, sE[dl]);
+  a_store<T>(D, C, i, lmax, W + 60 * 36 + 84 * 36);
+}
+
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
   fwd_cell<T>(D, dl, blockIdx.x);
@@ -867,6 +943,8 @@ template __global__ void cdz_landscape<float>(DevProb<float>);
 template __global__ void cdz_landscape<double>(DevProb<double>);
 template __global__ void cdz_spread_check<float>(DevProb<float>);
 template __global__ void cdz_spread_check<double>(DevProb<double>);
+template __global__ void cdz_arec_diag<float>(DevProb<float>, int);
+template __global__ void cdz_arec_diag<double>(DevProb<double>, int);
 template __global__ void cdz_fwd_diag<float>(DevProb<float>, int);
 template __global__ void cdz_fwd_diag<double>(DevProb<double>, int);
 template __global__ void cdz_fwd_diag_batch<float>(const DevProb<float> *, const int *, int, int);

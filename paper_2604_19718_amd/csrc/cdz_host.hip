@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -248,7 +249,7 @@ struct Carver {
 }  // namespace
 
 template <typename T>
-size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool adjoint) {
+size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool adjoint, int alK) {
   Carver c;
   const int n = t.n, S = t.S;
   const long long ld = ((long long)S + 31) / 32 * 32;
@@ -279,7 +280,20 @@ size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool 
                 &D.Qm1p, &D.QmX, &D.Qm, &D.Qmt};
   for (T **a : arrs) *a = c.take<T>(base, S2);
   D.ldA = (long long)CDZ_NA * ld;
-  D.AL = c.take<T>(base, (size_t)CDZ_NA * S2);
+  D.ALw = nullptr;
+  D.ALp = nullptr;
+  D.alK = alK;
+  if (alK == CDZ_AL_RESIDENT) {
+    D.AL = c.take<T>(base, (size_t)CDZ_NA * S2);
+    D.ALs = nullptr;
+    D.alTop = 0;
+    D.alSlots = 0;
+  } else {
+    D.AL = nullptr;
+    D.alTop = al_top(alK, n);
+    D.alSlots = al_slots(alK, n);
+    D.ALs = c.take<T>(base, (size_t)D.alSlots * n * CDZ_NA * 36);
+  }
   if (adjoint) adj_carve<T>(c.off, base, t, A, S2);
   return c.off + 256;
 }
@@ -303,8 +317,20 @@ cdz_status upload(cdz_handle *h, const HostTables &t, DevProb<T> &D) {
   HIPCHK(h, hipStreamSynchronize(st));
   return CDZ_OK;
 }
-template size_t carve<float>(char *, const HostTables &, DevProb<float> &, DevAdj<float> &, bool);
-template size_t carve<double>(char *, const HostTables &, DevProb<double> &, DevAdj<double> &, bool);
+template size_t carve<float>(char *, const HostTables &, DevProb<float> &, DevAdj<float> &, bool, int);
+template size_t carve<double>(char *, const HostTables &, DevProb<double> &, DevAdj<double> &, bool, int);
+
+int al_best_k(int n) {
+  int best = 2, cost = INT_MAX;
+  for (int K = 2; K <= std::max(2, n); K++) {
+    const int c = al_slots(K, n);
+    if (c < cost) {
+      cost = c;
+      best = K;
+    }
+  }
+  return best;
+}
 template cdz_status upload<float>(cdz_handle *, const HostTables &, DevProb<float> &);
 template cdz_status upload<double>(cdz_handle *, const HostTables &, DevProb<double> &);
 
@@ -325,10 +351,15 @@ static cdz_status forward_pass(cdz_handle *h, DevProb<T> &D, size_t shm, bool ti
   const int n = D.n;
   hipStream_t st = h->stream;
   HIPCHK(h, hipMemsetAsync(D.maxb, 0, (n + 1) * sizeof(unsigned), st));
+  DevProb<T> Dl = D;
   for (int dl = 0; dl <= dlmax; dl++) {
     const int ncell = n - dl > 0 ? n - dl : 0;
+    if (!D.AL) {  // diagonal-major A: this diagonal's slot and that of dl - 2
+      Dl.ALw = al_slot_ptr(D, al_slot_fwd(D.alK, D.alTop, dl));
+      Dl.ALp = al_slot_ptr(D, al_slot_fwd(D.alK, D.alTop, dl >= 2 ? dl - 2 : 0));
+    }
     if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
-    hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(cdz_cells_grid(ncell) + 1), dim3(CDZ_NT), shm, st, D, dl);
+    hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(cdz_cells_grid(ncell) + 1), dim3(CDZ_NT), shm, st, Dl, dl);
     if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
   }
   HIPCHK(h, hipGetLastError());
@@ -409,12 +440,25 @@ static cdz_status forward_impl(cdz_handle *h, const HostTables &t, bool adjoint)
   DevAdj<T> A;
   memset(&D, 0, sizeof(D));
   memset(&A, 0, sizeof(A));
-  const size_t need = carve<T>(nullptr, t, D, A, adjoint);
+  // A resident for all diagonals when the budget allows, else the
+  // memory-bounded form (ring; checkpoints and a recomputed band when the
+  // outside pass follows)
+  int alK = CDZ_AL_RESIDENT;
+  size_t need = carve<T>(nullptr, t, D, A, adjoint, alK);
   // block offsets inside one S x S array are kept in 32-bit integers
   if ((unsigned long long)D.ld * (unsigned long long)D.ld > 0x7fffffffull)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(t.n) + " nt is too long for 32-bit block offsets");
-  if (h->opt.mem_budget_bytes && need > h->opt.mem_budget_bytes)
-    return cdz_fail(h, CDZ_ERR_BUDGET, "workspace of " + std::to_string(need) + " bytes exceeds the budget");
+  if (h->al_k_forced >= CDZ_AL_RESIDENT) {
+    alK = h->al_k_forced;
+    if (adjoint && alK == 0) return cdz_fail(h, CDZ_ERR_ARG, "the outside pass needs checkpoints (K > 0)");
+    need = carve<T>(nullptr, t, D, A, adjoint, alK);
+  } else if (h->opt.mem_budget_bytes && need > h->opt.mem_budget_bytes) {
+    alK = adjoint ? al_best_k(t.n) : 0;
+    need = carve<T>(nullptr, t, D, A, adjoint, alK);
+    if (need > h->opt.mem_budget_bytes)
+      return cdz_fail(h, CDZ_ERR_BUDGET, "workspace of " + std::to_string(need) +
+                                             " bytes (checkpointed minimum) exceeds the budget");
+  }
   if (need > h->ws_bytes) {
     if (h->ws) HIPCHK(h, hipFree(h->ws));
     h->ws = nullptr;
@@ -426,7 +470,8 @@ static cdz_status forward_impl(cdz_handle *h, const HostTables &t, bool adjoint)
     }
     h->ws_bytes = need;
   }
-  carve<T>((char *)h->ws, t, D, A, adjoint);
+  carve<T>((char *)h->ws, t, D, A, adjoint, alK);
+  h->al_k = alK;
   cdz_status s = upload<T>(h, t, D);
   if (s != CDZ_OK) return s;
   s = launch_forward<T>(h, D);
@@ -502,3 +547,13 @@ hipError_t prof_reserve(cdz_handle *h, int launches) {
 
 // debug/test hook: log Z computed from the suffix exterior pass of the last forward
 extern "C" double cdz_debug_logz_suffix(const cdz_handle *h) { return h ? h->logz_suffix : NAN; }
+// storage of A in the last forward: -1 all diagonals resident, 0 ring only,
+// K > 0 checkpointed with bands of K diagonals
+extern "C" int cdz_debug_al_k(const cdz_handle *h) { return h ? h->al_k : -2; }
+// force that storage for the following forward passes (-2: chosen by budget)
+extern "C" int cdz_debug_force_al_k(cdz_handle *h, int K) {
+  if (!h || K < -2) return CDZ_ERR_ARG;
+  h->al_k_forced = K;
+  h->have_fwd = false;
+  return CDZ_OK;
+}

@@ -10,6 +10,9 @@
 #include "cdz.h"
 #include "cdz_dev.h"
 
+// alK of carve: the interior-loop sums A of every diagonal stay resident
+#define CDZ_AL_RESIDENT (-1)
+
 // Per-problem host tables (FP64), built before any device work.
 struct HostTables {
   int m = 0, n = 0, S = 0;
@@ -54,6 +57,8 @@ struct cdz_handle {
   int device = 0;
   int lds_max = 65536;  // dynamic LDS a workgroup may use on this device
   int landscape_retries = 0;  // FP32: exact passes repeated for range (last forward)
+  int al_k = CDZ_AL_RESIDENT;  // storage of A chosen for the last forward (see carve)
+  int al_k_forced = -2;        // test hook: storage of A to use regardless of budget (-2: by budget)
   std::string err;
   void *ws = nullptr;
   size_t ws_bytes = 0;
@@ -98,9 +103,34 @@ template <typename T>
 size_t out_lds_bytes(int n);  // dynamic LDS of the outside diagonal kernel
 size_t eta_lds_bytes(int n);  // dynamic LDS of the edge-marginal kernel
 
+// Storage of the interior-loop sums A (alK of carve):
+//   CDZ_AL_RESIDENT (-1): every diagonal in D.AL (block layout)
+//   0                   : diagonal-major ring of 3 diagonals (forward only)
+//   K > 0               : ring, plus checkpoints of diagonals kK-2, kK-1
+//                         (k = 1..top) and a band of K diagonals that the
+//                         outside pass recomputes from them
+inline int al_top(int K, int n) { return K > 0 && n > 3 ? (n - 3) / K : 0; }
+inline int al_slots(int K, int n) { return K > 0 ? 3 + 2 * al_top(K, n) + K : 3; }
+// slot holding diagonal x in the forward passes
+inline int al_slot_fwd(int K, int top, int x) {
+  if (K > 0 && x + 2 >= K) {
+    const int k = (x + 2) / K, r = (x + 2) % K;
+    if (r < 2 && k <= top) return 3 + 2 * (k - 1) + r;
+  }
+  return x % 3;
+}
+// slot holding diagonal x while the outside pass recomputes its band
+inline int al_slot_band(int K, int top, int x) { return 3 + 2 * top + x % K; }
+template <typename T>
+T *al_slot_ptr(const DevProb<T> &D, int slot) {
+  return D.ALs + (size_t)slot * D.n * CDZ_NA * 36;
+}
+// band length with the fewest slots for a sequence of n positions
+int al_best_k(int n);
+
 // workspace carve (base == nullptr: only the size) and table upload of one problem
 template <typename T>
-size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool adjoint);
+size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool adjoint, int alK);
 template <typename T>
 cdz_status upload(cdz_handle *h, const HostTables &t, DevProb<T> &D);
 // marginal outputs of one problem from its device edge marginals and pair

@@ -14,6 +14,7 @@
 // marginals are eta at the edge inside a codon, codon-pair marginals eta at
 // the edge between two codons (equal to d log Z / d theta1 and d theta2),
 // and pair probabilities are sum Qb * Qb' / Z.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -602,7 +603,8 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
         const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
         T v = 0;
         if (r < lp_d[1] && c < rp_d[1])
-          v = D.AL[(long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + b * rp_d[1] + c];
+          v = D.AL ? D.AL[(long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + b * rp_d[1] + c]
+                   : D.ALp[(long long)(i + 1) * (CDZ_NA * 36) + b * 36 + q];
         AP[idx] = v;
       }
       cdz_sync();
@@ -1108,6 +1110,9 @@ size_t eta_lds_bytes(int n) {
 }
 
 template <typename T>
+__global__ void cdz_arec_diag(DevProb<T> D, int dl);
+
+template <typename T>
 static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   const int n = D.n;
   hipStream_t st = h->stream;
@@ -1125,9 +1130,35 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   HIPCHK(h, hipMemsetAsync(A.etaV, 0, (size_t)n * 36 * sizeof(double), st));
   HIPCHK(h, hipMemsetAsync(A.etaW, 0, (size_t)n * 36 * sizeof(double), st));
   if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
+  // memory-bounded form: the cells of diagonal dl read A of diagonal dl - 2
+  // (when dl >= 10); the band of K diagonals holding it is rebuilt from its
+  // two checkpoint diagonals the first time the pass reaches it
+  DevProb<T> Dl = D;
+  int band = -1;
+  const int K = D.alK, top = D.alTop;
+  if (!D.AL) {
+    if (K <= 0) return cdz_fail(h, CDZ_ERR_STATE, "forward kept no checkpoints for the outside pass");
+    const size_t shf = fwd_lds_bytes<T>(n);
+    HIPCHK(h, hipFuncSetAttribute((const void *)cdz_arec_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)shf));
+  }
   for (int dl = n - 1; dl >= 0; dl--) {
+    if (!D.AL && dl >= 10) {
+      const int x = dl - 2, k = x / K;
+      if (k != band) {
+        DevProb<T> Dr = D;
+        for (int y = std::max(4, k * K); y <= x; y++) {
+          Dr.ALw = al_slot_ptr(D, al_slot_band(K, top, y));
+          Dr.ALp = al_slot_ptr(D, y - 2 >= k * K ? al_slot_band(K, top, y - 2) : al_slot_fwd(K, top, y - 2));
+          hipLaunchKernelGGL(cdz_arec_diag<T>, dim3(cdz_cells_grid(n - y)), dim3(CDZ_NT), fwd_lds_bytes<T>(n), st,
+                             Dr, y);
+        }
+        band = k;
+      }
+      Dl.ALp = al_slot_ptr(D, al_slot_band(K, top, x));
+    }
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
-    hipLaunchKernelGGL(cdz_out_diag<T>, dim3(cdz_cells_grid(n - dl)), dim3(CDZ_NT), shm, st, D, A, dl);
+    hipLaunchKernelGGL(cdz_out_diag<T>, dim3(cdz_cells_grid(n - dl)), dim3(CDZ_NT), shm, st, Dl, A, dl);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
   }
   HIPCHK(h, hipGetLastError());

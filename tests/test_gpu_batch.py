@@ -64,7 +64,7 @@ def test_batch_chunked_by_budget(prec):
     seed, N = 5, 4
     h0 = B.cdz_create(en, prec)
     whole = B.cdz_batch(h0, probs, N, seed)
-    need = [B.cdz_workspace_bytes(h0, p, True) for p in probs]
+    need = [B.cdz_workspace_bytes(h0, p, B.CDZ_WS_MARGINALS) for p in probs]
     budget = max(need) + min(need)
     chunks, used = 1, 0
     for x in need:
