@@ -100,6 +100,45 @@ def cpu_baseline(prob, en):
                       f"900-nt protein, {dt:.1f} s"}
 
 
+def extra_workloads(B, I):
+    """The batch of 256 proteins (30..400 residues; forward + outside + 64 samples
+    each, FP32) and the 3900-nt instance (forward + outside, FP32 and FP64; 1000
+    samples FP32), each timed once after one warm-up run, by HIP events."""
+    out = {}
+    probs = []
+    for k in range(256):
+        p, en4 = I.workload(4, index=k)
+        probs.append(p)
+    ns = np.array([p.n for p in probs])
+    cells = float((ns * (ns + 1) // 2).sum())
+    h = B.cdz_create(en4, "fp32")
+    for rep in range(2):
+        B.cdz_batch(h, probs, 64, I.sampler_seed(4), marginals=True)
+    tm = B.cdz_last_timings(h)
+    out["batch256"] = {"dp_cells": cells, "ms_forward": tm[0], "ms_outside": tm[1], "ms_sample": tm[2],
+                       "dp_cells_per_s": cells / ((tm[0] + tm[1]) / 1e3), "dtype": "f32"}
+    print(f"# batch256 {out['batch256']}", file=sys.stderr, flush=True)
+    del h
+    prob5, en5 = I.workload(5)
+    n5 = prob5.n
+    c5 = n5 * (n5 + 1) / 2
+    for prec in ("fp32", "fp64"):
+        h = B.cdz_create(en5, prec)
+        for rep in range(2):
+            B.cdz_reset(h)
+            B.cdz_marginals(h, prob5)
+        tm = B.cdz_last_timings(h)
+        rec = {"dp_cells": c5, "ms_forward": tm[0], "ms_outside": tm[1],
+               "dp_cells_per_s": c5 / ((tm[0] + tm[1]) / 1e3)}
+        if prec == "fp32":
+            B.cdz_sample(h, prob5, I.sampler_seed(5), N_SAMPLES)
+            rec["ms_sample_1000"] = B.cdz_last_timings(h)[2]
+        out[f"3900nt_{prec}"] = rec
+        print(f"# 3900nt {prec} {rec}", file=sys.stderr, flush=True)
+        del h
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +146,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time, once each, the 256-protein batch and the 3900-nt "
+                         "instance (FP32 and FP64) and report them under extra_workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one device copy of 256 MiB first (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
@@ -197,6 +239,8 @@ def main():
         "ms_forward_outside_fp64": ms_fo64, "fp64_over_fp32": None if ms_fo64 is None else ms_fo64 / ms_fo,
         "roofline": roof,
     }
+    if args.extra:
+        res["extra_workloads"] = extra_workloads(B, I)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(prob, en)
     print(json.dumps(res), flush=True)
