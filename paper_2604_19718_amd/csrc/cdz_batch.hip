@@ -263,6 +263,10 @@ cdz_status chunk_outside(cdz_handle *h, Chunk<T> &C) {
                        (const int *)(dev + oO) + Lo.at(dl), cnt, dl);
   }
   HIPCHK(h, hipGetLastError());
+  if (eta_lds_bytes(nmax) > (size_t)h->lds_max)
+    return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(nmax) + " nt exceeds the LDS layout of the edge kernel");
+  HIPCHK(h, hipFuncSetAttribute((const void *)cdz_eta_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)eta_lds_bytes(nmax)));
   if (Le.total(0) > 0)
     hipLaunchKernelGGL(cdz_eta_batch<T>, dim3(Le.total(0)), dim3(CDZ_NT), eta_lds_bytes(nmax), st, dP, dA,
                        (const int *)(dev + oE), cnt);

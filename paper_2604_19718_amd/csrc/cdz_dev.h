@@ -126,6 +126,8 @@ __device__ __forceinline__ float cdz_wave_max(float x) {
 // a contiguous range of i: cells with nearby i read each other's rows and
 // runs, which then tend to be in the same L2.  Blocks past the last cell exit.
 #define CDZ_NXCD 8
+// largest span of the truncated pass that estimates the FP32 landscape
+#define CDZ_SPAN_MAX 96
 __host__ __device__ __forceinline__ int cdz_cells_grid(int ncell) {
   return (ncell + CDZ_NXCD - 1) / CDZ_NXCD * CDZ_NXCD;
 }

@@ -742,12 +742,34 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
 // exact values of the truncated pass).  One workgroup, positions in turn.
 template <typename T>
 __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) {
+  // the recurrence reaches back at most W + 1 positions: Z5, G5, d and P of
+  // positions j - W - 1 .. j live in an LDS ring, the exponents E[0..W] too,
+  // so each step waits on LDS rather than on global memory
+  constexpr int RMAX = CDZ_SPAN_MAX + 2;
   __shared__ double red[(CDZ_NT / 64) * 6 + 6];
+  __shared__ double zr[RMAX * 6];
+  __shared__ int gr[RMAX], dr[RMAX], Pr[RMAX], sE[CDZ_SPAN_MAX + 1];
   double *tot = red + (CDZ_NT / 64) * 6;
-  const int n = D.n, tid = threadIdx.x;
+  const int n = D.n, tid = threadIdx.x, R = W + 2;
   const long long ld = D.ld;
+  if (W > CDZ_SPAN_MAX) {
+    if (tid == 0) D.res[0] = NAN;  // caller error: log Z reports it
+    return;
+  }
+  for (int k = tid; k <= W && k < n; k += CDZ_NT) {
+#pragma unroll
+    for (int q = 0; q < 6; q++) zr[(k % R) * 6 + q] = D.Z5[k * 6 + q];
+    gr[k % R] = D.G5[k];
+    dr[k % R] = D.d[k];
+    Pr[k % R] = D.P[k];
+    sE[k] = D.E[k];
+  }
+  __syncthreads();
   for (int j = W; j < n; j++) {
-    const int R = D.G5[j - 1], dj = D.d[j], Pj = D.P[j];
+    const int sj = j % R, sm1 = (j - 1) % R;
+    const int G = gr[sm1], dj = dr[sj], Pj = Pr[sj];
+    // d, P of position j + 1, loaded now so that the step does not wait on them
+    const int dn = j + 1 < n ? D.d[j + 1] : 0, Pn = j + 1 < n ? D.P[j + 1] : 0;
     double part[6] = {0, 0, 0, 0, 0, 0};
     const int k0 = j - W > 0 ? j - W : 0;  // first pair start
     // item 0: j unpaired; item it >= 1: k = k0 + it - 1 pairs j (k <= j - 4)
@@ -756,7 +778,7 @@ __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) 
       if (it == 0) {
         double z[6];
 #pragma unroll
-        for (int q = 0; q < 6; q++) z[q] = D.Z5[(j - 1) * 6 + q];
+        for (int q = 0; q < 6; q++) z[q] = zr[sm1 * 6 + q];
 #pragma unroll
         for (int t = 0; t < 6; t++) {
           double a = 0;
@@ -765,28 +787,41 @@ __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) 
           part[t] += t < dj ? a * D.vd[j * 6 + t] : 0.0;
         }
       } else {
-        const int k = k0 + it - 1, dk = D.d[k], Pk = D.P[k];
+        const int k = k0 + it - 1, dk = dr[k % R], Pk = Pr[k % R];
         if (k == 0) {
-          const double sc = ldexp(1.0, D.E[j] - R);
+          const double sc = ldexp(1.0, sE[j] - G);
 #pragma unroll 1
           for (int x = 0; x < dk; x++)
 #pragma unroll
             for (int t = 0; t < 6; t++)
               if (t < dj) part[t] += (double)D.Qb[x * ld + Pj + t] * sc;
         } else {
-          const double sc = ldexp(1.0, D.G5[k - 1] + D.E[j - k] - R);
+          // every global operand of the item first (none depends on the
+          // recurrence), then the ring values
+          T qb[6][6];
+          double ev[6][6];
+#pragma unroll
+          for (int x = 0; x < 6; x++)
+#pragma unroll
+            for (int t = 0; t < 6; t++) {
+              qb[x][t] = (x < dk && t < dj) ? D.Qb[(Pk + x) * ld + Pj + t] : T(0);
+              ev[x][t] = x < dk ? D.ed[(k - 1) * 36 + t * 6 + x] : 0.0;  // ev[x][q] = ed(q, x)
+            }
+          const int sk = (k - 1) % R;
+          const double sc = ldexp(1.0, gr[sk] + sE[j - k] - G);
           double z[6];
 #pragma unroll
-          for (int q = 0; q < 6; q++) z[q] = D.Z5[(k - 1) * 6 + q];
-#pragma unroll 1
-          for (int x = 0; x < dk; x++) {
+          for (int q = 0; q < 6; q++) z[q] = zr[sk * 6 + q];
+#pragma unroll
+          for (int x = 0; x < 6; x++) {
+            if (x >= dk) break;
             double a = 0;
 #pragma unroll
-            for (int q = 0; q < 6; q++) a += z[q] * D.ed[(k - 1) * 36 + q * 6 + x];
+            for (int q = 0; q < 6; q++) a += z[q] * ev[x][q];
             a *= sc;
 #pragma unroll
             for (int t = 0; t < 6; t++)
-              if (t < dj) part[t] += a * (double)D.Qb[(Pk + x) * ld + Pj + t];
+              if (t < dj) part[t] += a * (double)qb[x][t];
           }
         }
       }
@@ -796,10 +831,18 @@ __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) 
       double mx = 0;
       for (int t = 0; t < 6; t++) mx = fmax(mx, fabs(tot[t]));
       const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
-      for (int t = 0; t < 6; t++) D.Z5[j * 6 + t] = t < dj ? ldexp(tot[t], -e) : 0.0;
-      D.G5[j] = R + e;
+      for (int t = 0; t < 6; t++) {
+        const double z = t < dj ? ldexp(tot[t], -e) : 0.0;
+        zr[sj * 6 + t] = z;
+        D.Z5[j * 6 + t] = z;
+      }
+      gr[sj] = G + e;
+      D.G5[j] = G + e;
+      // position j + 1 takes the slot of j - W - 1, which no step needs any more
+      dr[(j + 1) % R] = dn;
+      Pr[(j + 1) % R] = Pn;
     }
-    __syncthreads();  // Z5[j], G5[j] are read by every thread at j + 1
+    cdz_sync();  // the ring entries written above are read by every thread at j + 1
   }
 }
 

@@ -95,7 +95,7 @@ inline void store_dev(cdz_handle *h, const DevProb<double> &D, const DevAdj<doub
 }
 
 // span limit of the truncated pass that estimates the FP32 landscape
-#define CDZ_LANDSCAPE_SPAN 96
+#define CDZ_LANDSCAPE_SPAN CDZ_SPAN_MAX
 
 template <typename T>
 size_t fwd_lds_bytes(int n);  // dynamic LDS of the forward diagonal kernel

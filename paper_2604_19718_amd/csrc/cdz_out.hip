@@ -762,55 +762,113 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
 // statements use e_p: row p (edge right after a closing base), row p+1
 // (edge right before a pair / run start), column p+1 and column p.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T loop_inner(const DevProb<T> &D, int i, int j, int a, int dd, int to,
-                                        const int *sE, int dl) {
-  // inner part X(a, dd) of the loop closed by (i, j) for outer pair type to:
-  // sum of hairpin, stack, multiloop, bulge and interior terms with the outer
-  // edges e_i, e_{j-1} removed (units of the cell)
-  const long long ld = D.ld;
-  const long long o = (D.P[i + 1] + a) * ld + D.P[j - 1] + dd;
-  const int na = D.nt[(i + 1) * 6 + a], nd = D.nt[(j - 1) * 6 + dd];
-  const T mm = D.tab[TB_MM + na * 24 + nd * 6 + to];
-  T x = D.Bhp[dl - 1] * D.U[o] * mm + D.tab[TB_MLAB] * D.QmX[o];
-  if (dl - 2 >= 4) {
-    const int t2 = cdz_ptype(na, nd);
-    if (t2 >= 0) x += D.Qb[o] * D.tab[TB_ST + to * 6 + t2];
-  }
-  return x * cdz_p2<T>(sE[dl - 2] - sE[dl]) + D.G[o] + D.F[o] * mm;
-}
-
+// Edge marginals of edge p (between positions p and p+1): the cells whose
+// loops or runs use e_p, i.e. (p+1, j) and (p, j) to the right and (i, p+1),
+// (i, p) to the left, plus the exterior step over the edge.  One workgroup
+// per edge; each wavefront takes one cell at a time and lane q < 36 owns
+// output (u, w) = (q / 6, q % 6), the slots of positions p and p+1.
 template <typename T>
 __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A, int p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int n = D.n, tid = threadIdx.x;
+  const int n = D.n, tid = threadIdx.x, lane = tid & 63, wv = cdz_wave_id();
   const long long ld = D.ld;
+  // LDS: exponents, slot counts and offsets of every position (so that the
+  // loops below issue one level of global loads), then reduction scratch
   int *sE = reinterpret_cast<int *>(smem_raw);
-  double *red = reinterpret_cast<double *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
-  for (int k = tid; k < n; k += CDZ_NT) sE[k] = D.E[k];
+  int *sd = sE + (n + 1), *sP = sd + (n + 1);
+  double *red = reinterpret_cast<double *>(smem_raw + ((size_t)3 * (n + 1) * 4 + 15) / 16 * 16);
+  double *Mw = red + (CDZ_NT / 64) * 36 + wv * 36;  // per-wave bulge partial products
+  T *tab = reinterpret_cast<T *>(red + 2 * (CDZ_NT / 64) * 36);  // [TB_LEN] Boltzmann tables
+  T *Xw = tab + (TB_LEN + 7) / 8 * 8 + wv * 5 * 36;  // per wave: U, QmX, Qb, G, F of an inner block
+  int *Nw = reinterpret_cast<int *>(tab + (TB_LEN + 7) / 8 * 8 + (CDZ_NT / 64) * 5 * 36) + wv * 12;
+  for (int k = tid; k < n; k += CDZ_NT) {
+    sE[k] = D.E[k];
+    sd[k] = D.d[k];
+    sP[k] = D.P[k];
+  }
+  for (int k = tid; k < TB_LEN; k += CDZ_NT) tab[k] = D.tab[k];
   __syncthreads();
   const int EZ = (int)D.res[2];
-  const int dp = D.d[p], dq = D.d[p + 1], Pp = D.P[p], Pq = D.P[p + 1];
+  const int dp = sd[p], dq = sd[p + 1], Pp = sP[p], Pq = sP[p + 1];
   const T *ep = D.e + p * 36;
-  const T *tab = D.tab;
-  double acc[36];
-#pragma unroll
-  for (int r = 0; r < 36; r++) acc[r] = 0;
+  // The wave stages block (i+1, j-1) of the loop closed by (i, j) (lane q =
+  // (a, dd)) and the bases of positions i+1 and j-1; inner(a, dd, to) is then
+  // the inner part of that loop for outer pair type to: hairpin, stack,
+  // multiloop, bulge and interior terms with the outer edges removed, in the
+  // units of the cell (i, j).
+  auto stage_inner = [&](int i, int j) {
+    if (lane < 36) {
+      const int a = lane / 6, dd = lane % 6;
+      const bool ok = a < sd[i + 1] && dd < sd[j - 1];
+      const long long o = (long long)(sP[i + 1] + a) * ld + sP[j - 1] + dd;
+      Xw[lane] = ok ? D.U[o] : T(0);
+      Xw[36 + lane] = ok ? D.QmX[o] : T(0);
+      Xw[72 + lane] = ok ? D.Qb[o] : T(0);
+      Xw[108 + lane] = ok ? D.G[o] : T(0);
+      Xw[144 + lane] = ok ? D.F[o] : T(0);
+    } else if (lane < 48) {
+      const int q = lane - 36;
+      Nw[q] = q < 6 ? D.nt[(i + 1) * 6 + q] : D.nt[(j - 1) * 6 + q - 6];
+    }
+    cdz_wave_sync();
+  };
+  auto inner = [&](int a, int dd, int to, int dl) -> T {
+    const int q = a * 6 + dd, na = Nw[a], nd = Nw[6 + dd];
+    const T mm = tab[TB_MM + na * 24 + nd * 6 + to];
+    T x = D.Bhp[dl - 1] * Xw[q] * mm + tab[TB_MLAB] * Xw[36 + q];
+    if (dl - 2 >= 4) {
+      const int t2 = cdz_ptype(na, nd);
+      if (t2 >= 0) x += Xw[72 + q] * tab[TB_ST + to * 6 + t2];
+    }
+    return x * cdz_p2<T>(sE[dl - 2] - sE[dl]) + Xw[108 + q] + Xw[144 + q] * mm;
+  };
+  const int u = lane / 6, w = lane % 6;
+  const bool own = lane < 36 && u < dp && w < dq;  // this lane's output exists
+  double acc = 0;
   const int nR1 = n - p - 5 > 0 ? n - p - 5 : 0;  // cells (p+1, j), j >= p+5
   const int nR0 = n - p - 4 > 0 ? n - p - 4 : 0;  // cells (p, j), j >= p+4
   const int nC1 = p + 2;                          // cells (i, p+1), i <= p+1
   const int nC0 = p - 3 > 0 ? p - 3 : 0;          // cells (i, p), i <= p-4
-  const int total = nR1 + nR0 + nC1 + nC0 + 1;
-  for (int it = tid; it < total; it += CDZ_NT) {
-    int w = it;
-    if (w < nR1) {
-      // ---- cell (i, j) = (p+1, j): the edge before its first base
-      const int i = p + 1, j = p + 5 + w, dl = j - i, di = dq, dj = D.d[j], Pj = D.P[j];
+  const int total = nR1 + nR0 + nC1 + nC0;
+  for (int it = wv; it < total; it += CDZ_NT / 64) {
+    int k = it;
+    if (k < nR1) {
+      // ---- cell (i, j) = (p+1, j): the edge before its first base;
+      //      output (b, x) = (u, w), x a slot of i
+      const int i = p + 1, j = p + 5 + k, dl = j - i, di = dq, dj = sd[j], Pj = sP[j];
       const long long Pi = Pq;
-      // DI dressing
+      const int b = u, x = w;
       if (j + 1 <= n - 1) {
-        const int dc = D.d[j + 1], Pc = D.P[j + 1];
-        for (int x = 0; x < di; x++)
+        // left bulges with inner pair (i, j): lane (b, y) forms
+        // M(b, y) = sum_l1 f sum_a Gb(a, y) U(a, b) for the wave
+        {
+          const int y = w;
+          T M = 0;
+          if (lane < 36 && b < dp && y < dj) {
+            const int l1max = min(CDZ_MAXLOOP, i - 1);
+#pragma unroll 2
+            for (int l1 = 1; l1 <= l1max; l1++) {
+              const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[dl] - sE[dl + l1 + 2]);
+              const int pa = i - l1, da = sd[pa], Pa = sP[pa];
+              T g[6], uu[6];
+#pragma unroll
+              for (int a = 0; a < 6; a++) {
+                g[a] = a < da ? A.Gb[(Pa + a) * ld + Pj + y] : T(0);
+                uu[a] = a < da ? D.U[(Pa + a) * ld + Pp + b] : T(0);
+              }
+              T sm = 0;
+#pragma unroll
+              for (int a = 0; a < 6; a++)
+                if (a < da) sm += g[a] * uu[a];
+              M += f * sm;
+            }
+          }
+          if (lane < 36) Mw[lane] = (double)M;
+          cdz_wave_sync();
+        }
+        if (own) {
+          // DI dressing
+          const int dc = sd[j + 1], Pc = sP[j + 1];
           for (int y = 0; y < dj; y++) {
             const T qb = D.Qb[(Pi + x) * ld + Pj + y];
             if (qb == T(0)) continue;
@@ -818,163 +876,132 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
             for (int c = 0; c < dc; c++) {
               const T wyc = qb * D.e[j * 36 + y * 6 + c];
               const int nc = D.nt[(j + 1) * 6 + c];
-#pragma unroll
-              for (int b = 0; b < 6; b++)
-                if (b < dp)
-                  acc[b * 6 + x] += (double)(A.DIb[(Pp + b) * ld + Pc + c] * ep[b * 6 + x] * wyc *
-                                             tab[TB_MM + nc * 24 + D.nt[p * 6 + b] * 6 + tin]);
+              acc += (double)(A.DIb[(Pp + b) * ld + Pc + c] * ep[b * 6 + x] * wyc *
+                              tab[TB_MM + nc * 24 + D.nt[p * 6 + b] * 6 + tin]);
             }
           }
-      }
-      // Qm1L dressing
-#pragma unroll
-      for (int b = 0; b < 6; b++)
-        if (b < dp)
-          for (int t = 0; t < di; t++) {
-            T sm = 0;
-            for (int s2 = 0; s2 < dj; s2++) sm += A.Qm1Lb[(Pp + b) * ld + Pj + s2] * D.Qm1[(Pi + t) * ld + Pj + s2];
-            acc[b * 6 + t] += (double)(sm * ep[b * 6 + t]);
-          }
-      // left bulges with inner pair (i, j): M(b, y) = sum_l1 f sum_a Gb(a,y) U(a,b)
-      if (j + 1 <= n - 1) {
-        T M[36];
-#pragma unroll
-        for (int r = 0; r < 36; r++) M[r] = 0;
-        for (int l1 = 1; l1 <= CDZ_MAXLOOP && i - l1 - 1 >= 0; l1++) {
-          const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[dl] - sE[dl + l1 + 2]);
-          const int pa = i - l1, da = D.d[pa], Pa = D.P[pa];
-#pragma unroll
-          for (int b = 0; b < 6; b++)
-#pragma unroll
-            for (int y = 0; y < 6; y++)
-              if (b < dp && y < dj) {
-                T sm = 0;
-                for (int a = 0; a < da; a++) sm += A.Gb[(Pa + a) * ld + Pj + y] * D.U[(Pa + a) * ld + Pp + b];
-                M[b * 6 + y] += f * sm;
-              }
+          // the bulges: sum_y Qb(x, y) M(b, y)
+          T sm = 0;
+          for (int y = 0; y < dj; y++) sm += D.Qb[(Pi + x) * ld + Pj + y] * (T)Mw[b * 6 + y];
+          acc += (double)(sm * ep[b * 6 + x]);
         }
-#pragma unroll
-        for (int b = 0; b < 6; b++)
-#pragma unroll
-          for (int x = 0; x < 6; x++)
-            if (b < dp && x < di) {
-              T sm = 0;
-#pragma unroll
-              for (int y = 0; y < 6; y++)
-                if (y < dj) sm += D.Qb[(Pi + x) * ld + Pj + y] * M[b * 6 + y];
-              acc[b * 6 + x] += (double)(sm * ep[b * 6 + x]);
-            }
+        cdz_wave_sync();
       }
-      // exterior loop: pair (i, j) right after the prefix [0..p]
-      {
+      if (own) {
+        // Qm1L dressing
+        T sm = 0;
+        for (int s2 = 0; s2 < dj; s2++) sm += A.Qm1Lb[(Pp + b) * ld + Pj + s2] * D.Qm1[(Pi + x) * ld + Pj + s2];
+        acc += (double)(sm * ep[b * 6 + x]);
+        // exterior loop: pair (i, j) right after the prefix [0..p]
         const double sc = ldexp(1.0, D.G5[p] + sE[dl] + D.H3[j] - EZ);
-        for (int x = 0; x < di; x++) {
-          double sm = 0;
-          for (int t = 0; t < dj; t++) sm += (double)D.Qb[(Pi + x) * ld + Pj + t] * D.Z3[j * 6 + t];
-          sm *= sc;
-#pragma unroll
-          for (int s = 0; s < 6; s++)
-            if (s < dp) acc[s * 6 + x] += D.Z5[p * 6 + s] * D.ed[p * 36 + s * 6 + x] * sm;
-        }
+        double sz = 0;
+        for (int t = 0; t < dj; t++) sz += (double)D.Qb[(Pi + x) * ld + Pj + t] * D.Z3[j * 6 + t];
+        acc += D.Z5[p * 6 + b] * D.ed[p * 36 + b * 6 + x] * (sz * sc);
       }
       continue;
     }
-    w -= nR1;
-    if (w < nR0) {
-      // ---- cell (p, j): the edge after its first base
-      const int i = p, j = p + 4 + w, dl = j - i, di = dp, dj = D.d[j], Pj = D.P[j];
+    k -= nR1;
+    if (k < nR0) {
+      // ---- cell (p, j): the edge after its first base; output (s, a) = (u, w)
+      const int i = p, j = p + 4 + k, dl = j - i, di = dp, dj = sd[j], Pj = sP[j];
       const long long Pi = Pp;
-      const int dm = D.d[j - 1];
-      for (int s = 0; s < di; s++)
+      const int dm = sd[j - 1], s = u, a = w;
+      stage_inner(i, j);
+      if (own) {
         for (int s2 = 0; s2 < dj; s2++) {
           const int to = cdz_ptype(D.nt[i * 6 + s], D.nt[j * 6 + s2]);
           if (to < 0) continue;
           const T ac = A.Qbb[(Pi + s) * ld + Pj + s2] * D.v[i * 6 + s] * D.v[j * 6 + s2];
-          if (ac == T(0)) continue;
-#pragma unroll
-          for (int a = 0; a < 6; a++)
-            if (a < dq && ep[s * 6 + a] != T(0)) {
-              T sm = 0;
-              for (int dd = 0; dd < dm; dd++)
-                sm += loop_inner<T>(D, i, j, a, dd, to, sE, dl) * D.e[(j - 1) * 36 + dd * 6 + s2];
-              acc[s * 6 + a] += (double)(ac * ep[s * 6 + a] * sm);
-            }
+          if (ac == T(0) || ep[s * 6 + a] == T(0)) continue;
+          T sm = 0;
+          for (int dd = 0; dd < dm; dd++)
+            sm += inner(a, dd, to, dl) * D.e[(j - 1) * 36 + dd * 6 + s2];
+          acc += (double)(ac * ep[s * 6 + a] * sm);
         }
-      // multiloop unpaired prefix base i
-      {
+        // multiloop unpaired prefix base i
         const T f = tab[TB_MLC] * cdz_p2<T>(sE[dl - 1] - sE[dl]);
-#pragma unroll
-        for (int s = 0; s < 6; s++)
-#pragma unroll
-          for (int t = 0; t < 6; t++)
-            if (s < dp && t < dq) {
-              T sm = 0;
-              for (int s2 = 0; s2 < dj; s2++)
-                sm += A.Qm1pb[(Pi + s) * ld + Pj + s2] * D.Qm1p[(Pq + t) * ld + Pj + s2];
-              acc[s * 6 + t] += (double)(sm * f * D.v[i * 6 + s] * ep[s * 6 + t]);
-            }
+        T sm = 0;
+        for (int s2 = 0; s2 < dj; s2++) sm += A.Qm1pb[(Pi + s) * ld + Pj + s2] * D.Qm1p[(Pq + a) * ld + Pj + s2];
+        acc += (double)(sm * f * D.v[i * 6 + s] * ep[s * 6 + a]);
       }
+      cdz_wave_sync();
+      (void)di;
       continue;
     }
-    w -= nR0;
-    if (w < nC1) {
-      // ---- cell (i, p+1): the edge before its last base
-      const int i = w, j = p + 1, dl = j - i, di = D.d[i], dj = dq;
-      const long long Pi = D.P[i], Pj = Pq;
-      if (dl >= 4) {
-        const int d1 = D.d[i + 1];
-        for (int s = 0; s < di; s++)
-          for (int s2 = 0; s2 < dj; s2++) {
+    k -= nR0;
+    if (k < nC1) {
+      // ---- cell (i, p+1): the edge before its last base; output (dd, s2) = (u, w)
+      const int i = k, j = p + 1, dl = j - i, di = sd[i];
+      const long long Pi = sP[i], Pj = Pq;
+      const int dd = u, s2 = w;
+      if (dl >= 4) stage_inner(i, j);
+      if (own && dl >= 4) {
+        const int d1 = sd[i + 1];
+        if (ep[dd * 6 + s2] != T(0)) {
+          for (int s = 0; s < di; s++) {
             const int to = cdz_ptype(D.nt[i * 6 + s], D.nt[j * 6 + s2]);
             if (to < 0) continue;
             const T ac = A.Qbb[(Pi + s) * ld + Pj + s2] * D.v[i * 6 + s] * D.v[j * 6 + s2];
             if (ac == T(0)) continue;
-#pragma unroll
-            for (int dd = 0; dd < 6; dd++)
-              if (dd < dp && ep[dd * 6 + s2] != T(0)) {
-                T sm = 0;
-                for (int a = 0; a < d1; a++)
-                  sm += D.e[i * 36 + s * 6 + a] * loop_inner<T>(D, i, j, a, dd, to, sE, dl);
-                acc[dd * 6 + s2] += (double)(ac * ep[dd * 6 + s2] * sm);
-              }
+            T sm = 0;
+            for (int a = 0; a < d1; a++) sm += D.e[i * 36 + s * 6 + a] * inner(a, dd, to, dl);
+            acc += (double)(ac * ep[dd * 6 + s2] * sm);
           }
+        }
         // multiloop unpaired tail base j
         const T f = tab[TB_MLC] * cdz_p2<T>(sE[dl - 1] - sE[dl]);
-#pragma unroll
-        for (int t = 0; t < 6; t++)
-#pragma unroll
-          for (int s2 = 0; s2 < 6; s2++)
-            if (t < dp && s2 < dq) {
-              T sm = 0;
-              for (int s = 0; s < di; s++) sm += A.Qm1b[(Pi + s) * ld + Pj + s2] * D.Qm1[(Pi + s) * ld + Pp + t];
-              acc[t * 6 + s2] += (double)(sm * f * ep[t * 6 + s2] * D.v[j * 6 + s2]);
-            }
+        T sm = 0;
+        for (int s = 0; s < di; s++) sm += A.Qm1b[(Pi + s) * ld + Pj + s2] * D.Qm1[(Pi + s) * ld + Pp + dd];
+        acc += (double)(sm * f * ep[dd * 6 + s2] * D.v[j * 6 + s2]);
       }
-      if (dl >= 1) {
+      if (dl >= 4) cdz_wave_sync();
+      if (own && dl >= 1) {
         // unpaired run [i..p+1] extended from [i..p]
         const T f = cdz_p2<T>(sE[dl - 1] - sE[dl]);
-#pragma unroll
-        for (int c = 0; c < 6; c++)
-#pragma unroll
-          for (int b = 0; b < 6; b++)
-            if (c < dp && b < dq) {
-              T sm = 0;
-              for (int a = 0; a < di; a++) sm += A.Ub[(Pi + a) * ld + Pj + b] * D.U[(Pi + a) * ld + Pp + c];
-              acc[c * 6 + b] += (double)(sm * f * ep[c * 6 + b] * D.v[j * 6 + b]);
-            }
+        T sm = 0;
+        for (int a = 0; a < di; a++) sm += A.Ub[(Pi + a) * ld + Pj + s2] * D.U[(Pi + a) * ld + Pp + dd];
+        acc += (double)(sm * f * ep[dd * 6 + s2] * D.v[j * 6 + s2]);
       }
       continue;
     }
-    w -= nC1;
-    if (w < nC0) {
-      // ---- cell (i, p): the edge after its last base
-      const int i = w, j = p, dl = j - i, di = D.d[i], dj = dp;
-      const long long Pi = D.P[i], Pj = Pp;
-      // DI dressing
+    k -= nC1;
+    {
+      // ---- cell (i, p): the edge after its last base; output (y, c) = (u, w)
+      const int i = k, j = p, dl = j - i, di = sd[i];
+      const long long Pi = sP[i], Pj = Pp;
       if (i >= 1) {
-        const int db = D.d[i - 1], Pb = D.P[i - 1];
-        for (int x = 0; x < di; x++)
-          for (int y = 0; y < dj; y++) {
+        // right bulges with inner pair (i, p): lane (x, c) forms
+        // M(x, c) = sum_l2 f sum_dd U(c, dd) Gb(x, dd) for the wave
+        {
+          const int x = u, c = w;
+          T M = 0;
+          if (lane < 36 && x < di && c < dq) {
+            const int l2max = min(CDZ_MAXLOOP, n - 2 - p);
+#pragma unroll 2
+            for (int l2 = 1; l2 <= l2max; l2++) {
+              const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[dl] + sE[l2 - 1] - sE[dl + l2 + 2]);
+              const int pz = p + l2, dz = sd[pz], Pz = sP[pz];
+              T uu[6], g[6];
+#pragma unroll
+              for (int q = 0; q < 6; q++) {
+                uu[q] = q < dz ? D.U[(Pq + c) * ld + Pz + q] : T(0);
+                g[q] = q < dz ? A.Gb[(Pi + x) * ld + Pz + q] : T(0);
+              }
+              T sm = 0;
+#pragma unroll
+              for (int q = 0; q < 6; q++)
+                if (q < dz) sm += uu[q] * g[q];
+              M += f * sm;
+            }
+          }
+          if (lane < 36) Mw[lane] = (double)M;
+          cdz_wave_sync();
+        }
+        if (own) {
+          const int y = u, c = w;
+          // DI dressing
+          const int db = sd[i - 1], Pb = sP[i - 1];
+          for (int x = 0; x < di; x++) {
             const T qb = D.Qb[(Pi + x) * ld + Pj + y];
             if (qb == T(0)) continue;
             const int tin = cdz_ptype(D.nt[j * 6 + y], D.nt[i * 6 + x]);
@@ -982,63 +1009,33 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
               const T wb = D.e[(i - 1) * 36 + b * 6 + x] * qb;
               if (wb == T(0)) continue;
               const int nb = D.nt[(i - 1) * 6 + b];
-#pragma unroll
-              for (int c = 0; c < 6; c++)
-                if (c < dq)
-                  acc[y * 6 + c] += (double)(A.DIb[(Pb + b) * ld + Pq + c] * wb * ep[y * 6 + c] *
-                                             tab[TB_MM + D.nt[(p + 1) * 6 + c] * 24 + nb * 6 + tin]);
+              acc += (double)(A.DIb[(Pb + b) * ld + Pq + c] * wb * ep[y * 6 + c] *
+                              tab[TB_MM + D.nt[(p + 1) * 6 + c] * 24 + nb * 6 + tin]);
             }
           }
-      }
-      // right bulges with inner pair (i, p): M(x, c) = sum_l2 f sum_dd U(c,dd) Gb(x,dd)
-      if (i >= 1) {
-        T M[36];
-#pragma unroll
-        for (int r = 0; r < 36; r++) M[r] = 0;
-        for (int l2 = 1; l2 <= CDZ_MAXLOOP && p + l2 + 1 <= n - 1; l2++) {
-          const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[dl] + sE[l2 - 1] - sE[dl + l2 + 2]);
-          const int pz = p + l2, dz = D.d[pz], Pz = D.P[pz];
-#pragma unroll
-          for (int x = 0; x < 6; x++)
-#pragma unroll
-            for (int c = 0; c < 6; c++)
-              if (x < di && c < dq) {
-                T sm = 0;
-                for (int dd = 0; dd < dz; dd++) sm += D.U[(Pq + c) * ld + Pz + dd] * A.Gb[(Pi + x) * ld + Pz + dd];
-                M[x * 6 + c] += f * sm;
-              }
+          // the bulges: sum_x Qb(x, y) M(x, c)
+          T sm = 0;
+          for (int x = 0; x < di; x++) sm += D.Qb[(Pi + x) * ld + Pj + y] * (T)Mw[x * 6 + c];
+          acc += (double)(sm * ep[y * 6 + c]);
         }
-#pragma unroll
-        for (int y = 0; y < 6; y++)
-#pragma unroll
-          for (int c = 0; c < 6; c++)
-            if (y < dj && c < dq) {
-              T sm = 0;
-#pragma unroll
-              for (int x = 0; x < 6; x++)
-                if (x < di) sm += D.Qb[(Pi + x) * ld + Pj + y] * M[x * 6 + c];
-              acc[y * 6 + c] += (double)(sm * ep[y * 6 + c]);
-            }
+        cdz_wave_sync();
       }
-      continue;
-    }
-    // ---- exterior loop: base p+1 unpaired right after the prefix [0..p]
-    {
-      const double sc = ldexp(1.0, D.G5[p] + D.H3[p + 1] - EZ);
-#pragma unroll
-      for (int s = 0; s < 6; s++)
-#pragma unroll
-        for (int t = 0; t < 6; t++)
-          if (s < dp && t < dq)
-            acc[s * 6 + t] += D.Z5[p * 6 + s] * D.ed[p * 36 + s * 6 + t] * D.vd[(p + 1) * 6 + t] *
-                              D.Z3[(p + 1) * 6 + t] * sc;
     }
   }
-  double *out = red + (CDZ_NT / 64) * 36;
-  cdz_block_sum<double, 36>(acc, red, out);
+  // ---- exterior loop: base p+1 unpaired right after the prefix [0..p]
+  if (wv == 0 && own) {
+    const double sc = ldexp(1.0, D.G5[p] + D.H3[p + 1] - EZ);
+    acc += D.Z5[p * 6 + u] * D.ed[p * 36 + u * 6 + w] * D.vd[(p + 1) * 6 + w] * D.Z3[(p + 1) * 6 + w] * sc;
+  }
+  if (lane < 36) red[wv * 36 + lane] = acc;
+  __syncthreads();
   // plus the uses of e_p as V (e_{i+1}) and W (e_{j-2}) in the interior-loop
   // size recursion, accumulated by the outside pass
-  for (int r = tid; r < 36; r += CDZ_NT) A.eta[p * 36 + r] = out[r] + A.etaV[p * 36 + r] + A.etaW[p * 36 + r];
+  if (tid < 36) {
+    double t = 0;
+    for (int v = 0; v < CDZ_NT / 64; v++) t += red[v * 36 + tid];
+    A.eta[p * 36 + tid] = t + A.etaV[p * 36 + tid] + A.etaW[p * 36 + tid];
+  }
 }
 
 template <typename T>
@@ -1106,7 +1103,10 @@ __global__ void cdz_grad_theta(const double *eta, const int *d, int m, double sc
 // Host side
 // ---------------------------------------------------------------------------
 size_t eta_lds_bytes(int n) {
-  return ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 36 + 36) * 8;
+  // d, P, E of every position; reduction and bulge scratch; tables; per-wave
+  // inner blocks and bases
+  return ((size_t)3 * (n + 1) * 4 + 15) / 16 * 16 + (size_t)(2 * (CDZ_NT / 64) * 36) * 8 +
+         ((size_t)(TB_LEN + 7) / 8 * 8 + (CDZ_NT / 64) * 5 * 36) * 8 + (CDZ_NT / 64) * 12 * 4;
 }
 
 template <typename T>
@@ -1164,6 +1164,9 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   HIPCHK(h, hipGetLastError());
   if (n >= 2) {
     const size_t shm2 = eta_lds_bytes(n);
+    if (shm2 > (size_t)h->lds_max)
+      return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the edge kernel");
+    HIPCHK(h, hipFuncSetAttribute((const void *)cdz_eta<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm2));
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n], st));
     hipLaunchKernelGGL(cdz_eta<T>, dim3(n - 1), dim3(CDZ_NT), shm2, st, D, A);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n + 1], st));
