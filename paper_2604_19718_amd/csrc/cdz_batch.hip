@@ -140,7 +140,7 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
   std::vector<int> n(cnt), W(cnt), full(cnt);
   for (int b = 0; b < cnt; b++) {
     n[b] = C.t[b]->n;
-    W[b] = std::min(n[b] - 1, CDZ_LANDSCAPE_SPAN);
+    W[b] = std::min(n[b] - 1, h->span);
     full[b] = n[b];
   }
   const Launches Ltr = fwd_launches(n, W), Lex = fwd_launches(n, full);
@@ -358,6 +358,7 @@ cdz_status run_batch(cdz_handle *h, const std::vector<HostTables> &tabs, int32_t
       memset(&D, 0, sizeof(D));
       memset(&A, 0, sizeof(A));
       carve<T>((char *)h->ws + at, tabs[b], D, A, adjoint, CDZ_AL_RESIDENT);
+      D.lowExp = h->low_exp;
       at += need[b];
       cdz_status s = upload<T>(h, tabs[b], D);
       if (s != CDZ_OK) return s;

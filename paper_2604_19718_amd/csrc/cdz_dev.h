@@ -65,6 +65,7 @@ struct DevProb {
   T *ALs, *ALw;
   const T *ALp;
   int alK, alTop, alSlots;
+  int lowExp;              // FP32 spread check: a cell below 2^-lowExp repeats the pass
   int *E;                  // [n + 1] diagonal exponents
   unsigned *maxb;          // [n + 1] float bits of max |entry| per diagonal
   double *Z5;              // [n][6] prefix exterior partition function
@@ -127,7 +128,7 @@ __device__ __forceinline__ float cdz_wave_max(float x) {
 // runs, which then tend to be in the same L2.  Blocks past the last cell exit.
 #define CDZ_NXCD 8
 // largest span of the truncated pass that estimates the FP32 landscape
-#define CDZ_SPAN_MAX 96
+#define CDZ_SPAN_MAX 512
 __host__ __device__ __forceinline__ int cdz_cells_grid(int ncell) {
   return (ncell + CDZ_NXCD - 1) / CDZ_NXCD * CDZ_NXCD;
 }

@@ -869,15 +869,15 @@ __device__ __forceinline__ void landscape_body(const DevProb<T> &D) {
   if (threadIdx.x == 0) D.res[3] += D.Cl[n - 1];
 }
 
-// After the exact pass: does the weakest cell of a diagonal come within 26
-// octaves of FP32 underflow?  Then res[5] = 1 (the pass is repeated with the
-// landscape of the exact pass).
+// After the exact pass: is the largest entry of some cell of diagonal dl below
+// 2^-lowExp (close to FP32 underflow; the diagonal's top sits near 2^0)?
+// Then res[5] = 1 (the pass is repeated with the landscape of the exact pass).
 template <typename T>
 __device__ __forceinline__ void spread_check_body(const DevProb<T> &D, int dl) {
   const int n = D.n, ncell = n - dl;
   const long long ld = D.ld;
   T *const full[6] = {D.U, D.Qb, D.Qm1, D.Qm1p, D.QmX, D.Qm};
-  const T low = (T)ldexp(1.0, -100);
+  const T low = (T)ldexp(1.0, -D.lowExp);
   bool weak = false;
   for (int i = threadIdx.x; i < ncell; i += CDZ_NT) {
     const int j = i + dl, di = D.d[i], dj = D.d[j], Pi = D.P[i], Pj = D.P[j];

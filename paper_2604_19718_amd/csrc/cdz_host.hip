@@ -280,6 +280,7 @@ size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool 
                 &D.Qm1p, &D.QmX, &D.Qm, &D.Qmt};
   for (T **a : arrs) *a = c.take<T>(base, S2);
   D.ldA = (long long)CDZ_NA * ld;
+  D.lowExp = CDZ_SPREAD_LOW;
   D.ALw = nullptr;
   D.ALp = nullptr;
   D.alK = alK;
@@ -385,7 +386,7 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
     // from a pass truncated to short spans; then the exact pass, and once
     // more with the landscape of the exact pass if its cells still spread
     // too far (see cdz_landscape in cdz_fwd.hip)
-    const int W = n - 1 < CDZ_LANDSCAPE_SPAN ? n - 1 : CDZ_LANDSCAPE_SPAN;
+    const int W = n - 1 < h->span ? n - 1 : h->span;
     s = forward_pass<T>(h, D, shm, false, W);
     if (s != CDZ_OK) return s;
     hipLaunchKernelGGL(cdz_exterior_trunc<T>, dim3(1), dim3(CDZ_NT), 0, st, D, W);
@@ -471,6 +472,7 @@ static cdz_status forward_impl(cdz_handle *h, const HostTables &t, bool adjoint)
     h->ws_bytes = need;
   }
   carve<T>((char *)h->ws, t, D, A, adjoint, alK);
+  D.lowExp = h->low_exp;
   h->al_k = alK;
   cdz_status s = upload<T>(h, t, D);
   if (s != CDZ_OK) return s;
@@ -550,6 +552,22 @@ extern "C" double cdz_debug_logz_suffix(const cdz_handle *h) { return h ? h->log
 // storage of A in the last forward: -1 all diagonals resident, 0 ring only,
 // K > 0 checkpointed with bands of K diagonals
 extern "C" int cdz_debug_al_k(const cdz_handle *h) { return h ? h->al_k : -2; }
+// span of the truncated pass of the FP32 landscape estimate, and the number of
+// exact passes the last forward repeated because cells came too close to
+// FP32 underflow
+extern "C" int cdz_debug_set_span(cdz_handle *h, int W) {
+  if (!h || W < 4 || W > CDZ_SPAN_MAX) return CDZ_ERR_ARG;
+  h->span = W;
+  h->have_fwd = false;
+  return CDZ_OK;
+}
+extern "C" int cdz_debug_landscape_retries(const cdz_handle *h) { return h ? h->landscape_retries : -1; }
+extern "C" int cdz_debug_set_low_exp(cdz_handle *h, int e) {
+  if (!h || e < 1 || e > 140) return CDZ_ERR_ARG;
+  h->low_exp = e;
+  h->have_fwd = false;
+  return CDZ_OK;
+}
 // force that storage for the following forward passes (-2: chosen by budget)
 extern "C" int cdz_debug_force_al_k(cdz_handle *h, int K) {
   if (!h || K < -2) return CDZ_ERR_ARG;

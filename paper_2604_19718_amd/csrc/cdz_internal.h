@@ -12,6 +12,12 @@
 
 // alK of carve: the interior-loop sums A of every diagonal stay resident
 #define CDZ_AL_RESIDENT (-1)
+// default span of the truncated pass that estimates the FP32 landscape
+#define CDZ_LANDSCAPE_SPAN 96
+// FP32 spread check: the exact pass is repeated with its own landscape when
+// the largest entry of some cell falls below 2^-CDZ_SPREAD_LOW (the top of the
+// diagonal sits near 2^0), i.e. within 6 octaves of the smallest normal float
+#define CDZ_SPREAD_LOW 120
 
 // Per-problem host tables (FP64), built before any device work.
 struct HostTables {
@@ -59,6 +65,8 @@ struct cdz_handle {
   int landscape_retries = 0;  // FP32: exact passes repeated for range (last forward)
   int al_k = CDZ_AL_RESIDENT;  // storage of A chosen for the last forward (see carve)
   int al_k_forced = -2;        // test hook: storage of A to use regardless of budget (-2: by budget)
+  int span = CDZ_LANDSCAPE_SPAN;  // span of the truncated landscape pass (FP32)
+  int low_exp = CDZ_SPREAD_LOW;   // spread-check threshold exponent (FP32)
   std::string err;
   void *ws = nullptr;
   size_t ws_bytes = 0;
@@ -93,9 +101,6 @@ inline void store_dev(cdz_handle *h, const DevProb<double> &D, const DevAdj<doub
   h->pd = D;
   h->ad = A;
 }
-
-// span limit of the truncated pass that estimates the FP32 landscape
-#define CDZ_LANDSCAPE_SPAN CDZ_SPAN_MAX
 
 template <typename T>
 size_t fwd_lds_bytes(int n);  // dynamic LDS of the forward diagonal kernel
