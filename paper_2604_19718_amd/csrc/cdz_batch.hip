@@ -140,7 +140,7 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
   std::vector<int> n(cnt), W(cnt), full(cnt);
   for (int b = 0; b < cnt; b++) {
     n[b] = C.t[b]->n;
-    W[b] = std::min(n[b] - 1, h->span);
+    W[b] = landscape_span(n[b], h->span);
     full[b] = n[b];
   }
   const Launches Ltr = fwd_launches(n, W), Lex = fwd_launches(n, full);
@@ -164,7 +164,7 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
   if (fp32) {
     s = fwd_pass<T>(h, dP, (const int *)(dev + oTr), Ltr, shm);
     if (s != CDZ_OK) return s;
-    hipLaunchKernelGGL(cdz_exterior_trunc_batch<T>, dim3(cnt), dim3(CDZ_NT), 0, st, dP, (const int *)(dev + oW));
+    hipLaunchKernelGGL(cdz_exterior_trunc_batch<T>, dim3(cnt), dim3(64), 0, st, dP, (const int *)(dev + oW));
     hipLaunchKernelGGL(cdz_landscape_batch<T>, dim3(cnt), dim3(1024), 0, st, dP);
     for (int b = 0; b < cnt; b++) HIPCHK(h, hipMemsetAsync(C.D[b].maxb, 0, (n[b] + 1) * sizeof(unsigned), st));
     s = fwd_pass<T>(h, dP, (const int *)(dev + oEx), Lex, shm);

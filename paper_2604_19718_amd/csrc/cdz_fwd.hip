@@ -740,23 +740,24 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
 
 // Z5[j], j = W..n-1, from pairs (k, j) with j - k <= W (Z5[0..W-1] are the
 // exact values of the truncated pass).  One workgroup, positions in turn.
+// One wavefront (64 lanes, no workgroup barriers) steps the truncated exterior
+// prefix through j = W..n-1; lanes take the items of a step, a butterfly of
+// lane exchanges sums them, lane 0 renormalises.
 template <typename T>
 __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) {
   // the recurrence reaches back at most W + 1 positions: Z5, G5, d and P of
   // positions j - W - 1 .. j live in an LDS ring, the exponents E[0..W] too,
   // so each step waits on LDS rather than on global memory
   constexpr int RMAX = CDZ_SPAN_MAX + 2;
-  __shared__ double red[(CDZ_NT / 64) * 6 + 6];
   __shared__ double zr[RMAX * 6];
   __shared__ int gr[RMAX], dr[RMAX], Pr[RMAX], sE[CDZ_SPAN_MAX + 1];
-  double *tot = red + (CDZ_NT / 64) * 6;
-  const int n = D.n, tid = threadIdx.x, R = W + 2;
+  const int n = D.n, lane = threadIdx.x, R = W + 2;
   const long long ld = D.ld;
   if (W > CDZ_SPAN_MAX) {
-    if (tid == 0) D.res[0] = NAN;  // caller error: log Z reports it
+    if (lane == 0) D.res[0] = NAN;  // caller error: log Z reports it
     return;
   }
-  for (int k = tid; k <= W && k < n; k += CDZ_NT) {
+  for (int k = lane; k <= W && k < n; k += 64) {
 #pragma unroll
     for (int q = 0; q < 6; q++) zr[(k % R) * 6 + q] = D.Z5[k * 6 + q];
     gr[k % R] = D.G5[k];
@@ -764,7 +765,7 @@ __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) 
     Pr[k % R] = D.P[k];
     sE[k] = D.E[k];
   }
-  __syncthreads();
+  cdz_wave_sync();
   for (int j = W; j < n; j++) {
     const int sj = j % R, sm1 = (j - 1) % R;
     const int G = gr[sm1], dj = dr[sj], Pj = Pr[sj];
@@ -774,7 +775,7 @@ __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) 
     const int k0 = j - W > 0 ? j - W : 0;  // first pair start
     // item 0: j unpaired; item it >= 1: k = k0 + it - 1 pairs j (k <= j - 4)
     const int nit = 1 + (j - 4 - k0 + 1 > 0 ? j - 4 - k0 + 1 : 0);
-    for (int it = tid; it < nit; it += CDZ_NT) {
+    for (int it = lane; it < nit; it += 64) {
       if (it == 0) {
         double z[6];
 #pragma unroll
@@ -826,13 +827,16 @@ __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) 
         }
       }
     }
-    cdz_block_sum<double, 6>(part, red, tot);
-    if (tid == 0) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+      for (int t = 0; t < 6; t++) part[t] += __shfl_xor(part[t], off, 64);
+    if (lane == 0) {
       double mx = 0;
-      for (int t = 0; t < 6; t++) mx = fmax(mx, fabs(tot[t]));
+      for (int t = 0; t < 6; t++) mx = fmax(mx, fabs(part[t]));
       const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
       for (int t = 0; t < 6; t++) {
-        const double z = t < dj ? ldexp(tot[t], -e) : 0.0;
+        const double z = t < dj ? ldexp(part[t], -e) : 0.0;
         zr[sj * 6 + t] = z;
         D.Z5[j * 6 + t] = z;
       }
@@ -842,7 +846,7 @@ __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) 
       dr[(j + 1) % R] = dn;
       Pr[(j + 1) % R] = Pn;
     }
-    cdz_sync();  // the ring entries written above are read by every thread at j + 1
+    cdz_wave_sync();  // lane 0's ring entries are read by every lane at j + 1
   }
 }
 
@@ -952,7 +956,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag_batch(const DevProb<T> *p
 // per problem b of a batch: the span-truncated exterior prefix (span W[b]),
 // the landscape, and the spread check over off (n_b workgroups per problem)
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_exterior_trunc_batch(const DevProb<T> *probs, const int *W) {
+__global__ __launch_bounds__(64) void cdz_exterior_trunc_batch(const DevProb<T> *probs, const int *W) {
   const int b = blockIdx.x;
   exterior_trunc_body<T>(probs[b], W[b]);
 }
@@ -968,7 +972,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_spread_check_batch(const DevProb<T
 }
 
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_exterior_trunc(DevProb<T> D, int W) {
+__global__ __launch_bounds__(64) void cdz_exterior_trunc(DevProb<T> D, int W) {
   exterior_trunc_body<T>(D, W);
 }
 template <typename T>

@@ -386,10 +386,10 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
     // from a pass truncated to short spans; then the exact pass, and once
     // more with the landscape of the exact pass if its cells still spread
     // too far (see cdz_landscape in cdz_fwd.hip)
-    const int W = n - 1 < h->span ? n - 1 : h->span;
+    const int W = landscape_span(n, h->span);
     s = forward_pass<T>(h, D, shm, false, W);
     if (s != CDZ_OK) return s;
-    hipLaunchKernelGGL(cdz_exterior_trunc<T>, dim3(1), dim3(CDZ_NT), 0, st, D, W);
+    hipLaunchKernelGGL(cdz_exterior_trunc<T>, dim3(1), dim3(64), 0, st, D, W);
     hipLaunchKernelGGL(cdz_landscape<T>, dim3(1), dim3(1024), 0, st, D);
     s = forward_pass<T>(h, D, shm, h->profiling, n);
     if (s != CDZ_OK) return s;
@@ -556,7 +556,7 @@ extern "C" int cdz_debug_al_k(const cdz_handle *h) { return h ? h->al_k : -2; }
 // exact passes the last forward repeated because cells came too close to
 // FP32 underflow
 extern "C" int cdz_debug_set_span(cdz_handle *h, int W) {
-  if (!h || W < 4 || W > CDZ_SPAN_MAX) return CDZ_ERR_ARG;
+  if (!h || (W != 0 && W < 4) || W > CDZ_SPAN_MAX) return CDZ_ERR_ARG;
   h->span = W;
   h->have_fwd = false;
   return CDZ_OK;
