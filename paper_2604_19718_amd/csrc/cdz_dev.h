@@ -53,6 +53,7 @@ struct DevProb {
   const T *Bhp;            // [n] hairpin factor by loop length L (mismatch excluded)
   // forward arrays, S x S each (see header comment)
   T *U, *Qb, *G, *F, *DI, *Qm1, *Qm1Lr, *Qm1Lt, *Qm1p, *QmX, *Qm, *Qmt;
+  T *Ut, *DIt;             // U and DI transposed (their column strips read as rows)
   // interior-loop sums by loop size: A(i,j,L), L = 2..CDZ_NA+1, for the cell
   // (i,j) at rows P[i+1].. and columns CDZ_NA*P[j-1] + (L-2)*d[j-1] + ..
   T *AL;

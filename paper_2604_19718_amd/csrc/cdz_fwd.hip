@@ -216,6 +216,7 @@ struct CellStage {
   signed char nt[6][6];  // bases of positions i-1, i, i+1, j-1, j, j+1
   int d[6], P[6];
   int wd[64], wP[64];    // d, P of positions i+1+q ([q]) and j-1-q ([32+q])
+  unsigned char mapL[192], mapR[192];  // state offset -> position index (window staging)
 };
 
 // Blocks of 36 values staged for the loops closed by a cell (after the stage)
@@ -250,7 +251,7 @@ __device__ __forceinline__ int win_base(int l1) {  // first window index with th
 // from D.AL (all diagonals resident) or from D.ALp (diagonal dl - 2, stored
 // diagonal-major).
 template <typename T>
-__device__ __forceinline__ void a_window(const DevProb<T> &D, const CellStage<T> &C, const int *sE, T *W, int i,
+__device__ __forceinline__ void a_window(const DevProb<T> &D, CellStage<T> &C, const int *sE, T *W, int i,
                                          int j, int dl, int lmax, int Ed) {
   const int tid = threadIdx.x;
   const long long ld = D.ld;
@@ -265,32 +266,59 @@ __device__ __forceinline__ void a_window(const DevProb<T> &D, const CellStage<T>
   const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
   const int nAP = lmax - 3 > 0 ? lmax - 3 : 0;  // L = 2..lmax-2
   if (lmax >= 1) {
-    const int n0 = lmax, n1 = 2 * lmax, n2 = n1 + (lmax - 1), n3 = n2 + (lmax >= 3 ? lmax - 2 : 0),
-              n4 = n3 + nAP;
-    for (int idx = tid; idx < n4 * 36; idx += CDZ_NT) {
-      const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
-      T v = 0;
-      if (b < n0) {  // U[i+1][i+l], l = b + 1
-        if (r < d1 && c < lp_d[b]) v = D.U[(long long)(P1 + r) * ld + lp_P[b] + c];
-        UR1[b * 36 + q] = v;
-      } else if (b < n1) {  // U[j-l][j-1], l = b - n0 + 1
-        const int l = b - n0 + 1;
-        if (r < rp_d[l - 1] && c < dm) v = D.U[(long long)(rp_P[l - 1] + r) * ld + Pm + c];
-        UC1[(l - 1) * 36 + q] = v;
-      } else if (b < n2) {  // DI[i+1][j-L+1], L = b - n1 + 2
-        const int L = b - n1 + 2;
-        if (r < d1 && c < rp_d[L - 2]) v = D.DI[(long long)(P1 + r) * ld + rp_P[L - 2] + c];
-        DIrow[(L - 2) * 36 + q] = v;
-      } else if (b < n3) {  // DI[i+L-1][j-1], L = b - n2 + 3
-        const int L = b - n2 + 3;
-        if (r < lp_d[L - 2] && c < dm) v = D.DI[(long long)(lp_P[L - 2] + r) * ld + Pm + c];
-        DIcol[(L - 3) * 36 + q] = v;
-      } else {  // A(i+1, j-1, L), L = b - n3 + 2
-        const int L = b - n3 + 2;
-        if (r < lp_d[1] && c < rp_d[1])
-          v = D.AL ? D.AL[(long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + (L - 2) * rp_d[1] + c]
-                   : D.ALp[(long long)(i + 1) * (CDZ_NA * 36) + (L - 2) * 36 + q];
-        AP[(L - 2) * 36 + q] = v;
+    // Every region is read as contiguous row segments (the column strips
+    // U[j-l][j-1] and DI[i+L-1][j-1] as rows of the transposed arrays), lanes
+    // walking the row so that the loads coalesce; a map from state offset to
+    // position places each value in its 6 x 6 block, zeroed first for the
+    // padding.  Left states: positions i+1.. (lp index q), from lp_P[0];
+    // right states: positions j-lmax..j-1 (rp index q), from rp_P[lmax-1].
+    const int baseL = lp_P[0], baseR = rp_P[lmax - 1];
+    if (tid < 31) {
+      if (tid < lmax)
+        for (int c = 0; c < lp_d[tid]; c++) C.mapL[lp_P[tid] - baseL + c] = (unsigned char)tid;
+    } else if (tid >= 32 && tid < 63) {
+      const int q = tid - 32;
+      if (q < lmax)
+        for (int c = 0; c < rp_d[q]; c++) C.mapR[rp_P[q] - baseR + c] = (unsigned char)q;
+    }
+    {  // clear UR1, UC1, DIrow, DIcol and the AP blocks in use, 16 bytes a store
+      uint4 *w4 = reinterpret_cast<uint4 *>(W);
+      const int n4 = (117 + nAP) * 36 * (int)sizeof(T) / 16;
+      for (int idx = tid; idx < n4; idx += CDZ_NT) w4[idx] = make_uint4(0, 0, 0, 0);
+    }
+    cdz_sync();
+    const int KU = lp_P[lmax] - baseL;                           // end states of U[i+1][i+1..i+lmax]
+    const int KC = rp_P[0] + rp_d[0] - baseR;                    // start states of U[j-lmax..j-1][j-1]
+    const int oD = lmax >= 2 ? rp_P[lmax - 2] - baseR : KC;     // DI[i+1][j-lmax+1..j-1]: suffix of KC
+    const int KD = KC - oD;
+    const int oL = lp_P[1] - baseL;                              // DI[i+2..i+lmax-1][j-1]: part of KU
+    const int KL = lmax >= 3 ? lp_P[lmax - 1] - lp_P[1] : 0;
+    const int dA = lp_d[1], dB = rp_d[1], KA = nAP * dB;         // A(i+1, j-1, L), L = 2..lmax-2
+    const int nU = d1 * KU, nC = dm * KC, nD = d1 * KD, nL = dm * KL;
+    const int nA = D.AL ? dA * KA : nAP * 36;
+    const int e1 = nU, e2 = e1 + nC, e3 = e2 + nD, e4 = e3 + nL;
+    for (int idx = tid; idx < e4 + nA; idx += CDZ_NT) {
+      if (idx < e1) {  // U[i+1][i+l]: row P1 + r of U
+        const int r = idx / KU, k = idx % KU, qq = C.mapL[k], c = k - (lp_P[qq] - baseL);
+        UR1[qq * 36 + r * 6 + c] = D.U[(long long)(P1 + r) * ld + baseL + k];
+      } else if (idx < e2) {  // U[j-l][j-1]: row Pm + c of Ut, l = qq + 1
+        const int t = idx - e1, c = t / KC, k = t % KC, qq = C.mapR[k], r = k - (rp_P[qq] - baseR);
+        UC1[qq * 36 + r * 6 + c] = D.Ut[(long long)(Pm + c) * ld + baseR + k];
+      } else if (idx < e3) {  // DI[i+1][j-L+1]: row P1 + r of DI, L = qq + 2
+        const int t = idx - e2, r = t / KD, k = t % KD + oD, qq = C.mapR[k], c = k - (rp_P[qq] - baseR);
+        DIrow[qq * 36 + r * 6 + c] = D.DI[(long long)(P1 + r) * ld + baseR + k];
+      } else if (idx < e4) {  // DI[i+L-1][j-1]: row Pm + c of DIt, L = qq + 2
+        const int t = idx - e3, c = t / KL, k = t % KL + oL, qq = C.mapL[k], r = k - (lp_P[qq] - baseL);
+        DIcol[(qq - 1) * 36 + r * 6 + c] = D.DIt[(long long)(Pm + c) * ld + baseL + k];
+      } else {
+        const int t = idx - e4;
+        if (D.AL) {
+          const int r = t / KA, k = t % KA;
+          AP[(k / dB) * 36 + r * 6 + k % dB] =
+              D.AL[(long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + k];
+        } else {
+          AP[t] = D.ALp[(long long)(i + 1) * (CDZ_NA * 36) + t];
+        }
       }
     }
   }
@@ -462,6 +490,7 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
         u = a * C.vJ[t] * cdz_p2<T>(sE[dl - 1] - Ed);
       }
       D.U[(Pi + s) * ld + Pj + t] = u;
+      D.Ut[(Pj + t) * ld + Pi + s] = u;
       vmax = fmaxf(vmax, (float)fabs(u));
       if (dl < 4) {
         const long long o = (Pi + s) * ld + Pj + t;
@@ -692,6 +721,7 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
 #pragma unroll
         for (int x = 0; x < 6; x++) a += red[x * 36 + tid];
         D.DI[(C.P[0] + s) * ld + C.P[5] + s2] = a;
+        D.DIt[(C.P[5] + s2) * ld + C.P[0] + s] = a;
       }
       if (i >= 1 && s < C.d[0] && s2 < dj) {
         T a = 0;
