@@ -53,7 +53,7 @@ struct DevProb {
   const T *Bhp;            // [n] hairpin factor by loop length L (mismatch excluded)
   // forward arrays, S x S each (see header comment)
   T *U, *Qb, *G, *F, *DI, *Qm1, *Qm1Lr, *Qm1Lt, *Qm1p, *QmX, *Qm, *Qmt;
-  T *Ut, *DIt;             // U and DI transposed (their column strips read as rows)
+  T *Ut, *DIt, *Qbt;       // U, DI and Qb transposed (their column strips read as rows)
   // interior-loop sums by loop size: A(i,j,L), L = 2..CDZ_NA+1, for the cell
   // (i,j) at rows P[i+1].. and columns CDZ_NA*P[j-1] + (L-2)*d[j-1] + ..
   T *AL;
@@ -200,6 +200,24 @@ __device__ __forceinline__ void cdz_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Maps from a state offset to the position index of the loop window of cell
+// (i, j): mapL[k] = q for the states of position i+1+q (q = 0..lmax, offsets
+// from lp_P[0]); mapR[k] = q for the states of position j-1-q (q = 0..lmax,
+// offsets from rp_P[lmax]).  lp_* / rp_* hold d and P of those positions.
+// Threads 0..30 and 32..62 write; the caller synchronises before reading.
+__device__ __forceinline__ void cdz_window_maps(unsigned char *mapL, unsigned char *mapR, const int *lp_d,
+                                                const int *lp_P, const int *rp_d, const int *rp_P, int lmax) {
+  const int tid = threadIdx.x;
+  if (tid < 31) {
+    if (tid <= lmax)
+      for (int c = 0; c < lp_d[tid]; c++) mapL[lp_P[tid] - lp_P[0] + c] = (unsigned char)tid;
+  } else if (tid >= 32 && tid < 63) {
+    const int q = tid - 32;
+    if (q <= lmax)
+      for (int c = 0; c < rp_d[q]; c++) mapR[rp_P[q] - rp_P[lmax] + c] = (unsigned char)q;
+  }
 }
 
 // ---- workgroup sums by a reduce-scatter butterfly inside each wavefront.

@@ -272,15 +272,8 @@ __device__ __forceinline__ void a_window(const DevProb<T> &D, CellStage<T> &C, c
     // position places each value in its 6 x 6 block, zeroed first for the
     // padding.  Left states: positions i+1.. (lp index q), from lp_P[0];
     // right states: positions j-lmax..j-1 (rp index q), from rp_P[lmax-1].
-    const int baseL = lp_P[0], baseR = rp_P[lmax - 1];
-    if (tid < 31) {
-      if (tid < lmax)
-        for (int c = 0; c < lp_d[tid]; c++) C.mapL[lp_P[tid] - baseL + c] = (unsigned char)tid;
-    } else if (tid >= 32 && tid < 63) {
-      const int q = tid - 32;
-      if (q < lmax)
-        for (int c = 0; c < rp_d[q]; c++) C.mapR[rp_P[q] - baseR + c] = (unsigned char)q;
-    }
+    const int baseL = lp_P[0], baseR = rp_P[lmax];
+    cdz_window_maps(C.mapL, C.mapR, lp_d, lp_P, rp_d, rp_P, lmax);
     {  // clear UR1, UC1, DIrow, DIcol and the AP blocks in use, 16 bytes a store
       uint4 *w4 = reinterpret_cast<uint4 *>(W);
       const int n4 = (117 + nAP) * 36 * (int)sizeof(T) / 16;
@@ -288,9 +281,10 @@ __device__ __forceinline__ void a_window(const DevProb<T> &D, CellStage<T> &C, c
     }
     cdz_sync();
     const int KU = lp_P[lmax] - baseL;                           // end states of U[i+1][i+1..i+lmax]
-    const int KC = rp_P[0] + rp_d[0] - baseR;                    // start states of U[j-lmax..j-1][j-1]
-    const int oD = lmax >= 2 ? rp_P[lmax - 2] - baseR : KC;     // DI[i+1][j-lmax+1..j-1]: suffix of KC
-    const int KD = KC - oD;
+    const int endR = rp_P[0] + rp_d[0] - baseR;                  // right map: positions j-1-lmax..j-1
+    const int oC = rp_P[lmax - 1] - baseR, KC = endR - oC;       // start states of U[j-lmax..j-1][j-1]
+    const int oD = lmax >= 2 ? rp_P[lmax - 2] - baseR : endR;    // DI[i+1][j-lmax+1..j-1]
+    const int KD = endR - oD;
     const int oL = lp_P[1] - baseL;                              // DI[i+2..i+lmax-1][j-1]: part of KU
     const int KL = lmax >= 3 ? lp_P[lmax - 1] - lp_P[1] : 0;
     const int dA = lp_d[1], dB = rp_d[1], KA = nAP * dB;         // A(i+1, j-1, L), L = 2..lmax-2
@@ -302,7 +296,7 @@ __device__ __forceinline__ void a_window(const DevProb<T> &D, CellStage<T> &C, c
         const int r = idx / KU, k = idx % KU, qq = C.mapL[k], c = k - (lp_P[qq] - baseL);
         UR1[qq * 36 + r * 6 + c] = D.U[(long long)(P1 + r) * ld + baseL + k];
       } else if (idx < e2) {  // U[j-l][j-1]: row Pm + c of Ut, l = qq + 1
-        const int t = idx - e1, c = t / KC, k = t % KC, qq = C.mapR[k], r = k - (rp_P[qq] - baseR);
+        const int t = idx - e1, c = t / KC, k = t % KC + oC, qq = C.mapR[k], r = k - (rp_P[qq] - baseR);
         UC1[qq * 36 + r * 6 + c] = D.Ut[(long long)(Pm + c) * ld + baseR + k];
       } else if (idx < e3) {  // DI[i+1][j-L+1]: row P1 + r of DI, L = qq + 2
         const int t = idx - e2, r = t / KD, k = t % KD + oD, qq = C.mapR[k], c = k - (rp_P[qq] - baseR);
@@ -495,6 +489,7 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
       if (dl < 4) {
         const long long o = (Pi + s) * ld + Pj + t;
         D.Qb[o] = 0;
+        D.Qbt[(Pj + t) * ld + Pi + s] = 0;
         D.Qm1[o] = 0;
         D.Qm1p[o] = 0;
         D.QmX[o] = 0;
@@ -574,18 +569,28 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
       const int q = tid % 36, g = tid / 36, r = q / 6, c = q % 6;
       T gacc = 0;
       for (int side = 0; side < 2; side++) {
+        // e blocks (contiguous in D.e), then the Qb blocks of the inner pairs,
+        // the left side's column strip as contiguous rows of Qbt placed by the
+        // window map, into blocks cleared first
         for (int idx = tid; idx < 2 * lmax * 36; idx += CDZ_NT) {
-          const int b = idx / 36, qq = idx % 36, rr = qq / 6, cc = qq % 6;
-          const int l = b % lmax + 1;
-          T v = 0;
-          if (b < lmax) {  // e_{k-1}, k = i+1+l (left) / e_l, l = j-1-l2 (right)
-            v = D.e[(long long)(side == 0 ? i + l : j - 1 - l) * 36 + qq];
-          } else if (side == 0) {  // Qb[i+1+l][j-1]
-            if (rr < lp_d[l] && cc < dm) v = D.Qb[(long long)(lp_P[l] + rr) * ld + Pm + cc];
-          } else {  // Qb[i+1][j-1-l]
-            if (rr < d1 && cc < rp_d[l]) v = D.Qb[(long long)(P1 + rr) * ld + rp_P[l] + cc];
+          const int b = idx / 36, qq = idx % 36, l = b % lmax + 1;
+          if (b < lmax)  // e_{k-1}, k = i+1+l (left) / e_l, l = j-1-l2 (right)
+            EB[(l - 1) * 36 + qq] = D.e[(long long)(side == 0 ? i + l : j - 1 - l) * 36 + qq];
+          else
+            QB[(l - 1) * 36 + qq] = 0;
+        }
+        cdz_sync();
+        if (side == 0) {  // Qb[i+1+l][j-1](x, c) = Qbt row Pm + c, states of positions i+2..i+1+lmax
+          const int o = lp_P[1] - lp_P[0], K = lp_P[lmax + 1] - lp_P[1];
+          for (int idx = tid; idx < dm * K; idx += CDZ_NT) {
+            const int c = idx / K, k = idx % K + o, l = C.mapL[k], x = k - (lp_P[l] - lp_P[0]);
+            QB[(l - 1) * 36 + x * 6 + c] = D.Qbt[(long long)(Pm + c) * ld + lp_P[0] + k];
           }
-          (b < lmax ? EB : QB)[(l - 1) * 36 + qq] = v;
+        } else {  // Qb[i+1][j-1-l]
+          for (int idx = tid; idx < lmax * 36; idx += CDZ_NT) {
+            const int b = idx / 36, qq = idx % 36, rr = qq / 6, cc = qq % 6, l = b + 1;
+            if (rr < d1 && cc < rp_d[l]) QB[(l - 1) * 36 + qq] = D.Qb[(long long)(P1 + rr) * ld + rp_P[l] + cc];
+          }
         }
         cdz_sync();
         if (g < 7) {
@@ -671,6 +676,7 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
         for (int a = 0; a < 6; a++) acc += red[a * 36 + tid];
         qb = C.vI[s] * C.vJ[s2] * acc;
         D.Qb[(Pi + s) * ld + Pj + s2] = qb;
+        D.Qbt[(Pj + s2) * ld + Pi + s] = qb;
         vmax = fmaxf(vmax, (float)fabs(qb));
       }
       C.qb[tid] = qb;

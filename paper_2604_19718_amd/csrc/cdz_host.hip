@@ -277,7 +277,7 @@ size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool 
   D.Cl = c.take<int>(base, n);
   D.res = c.take<double>(base, 8);
   T **arrs[] = {&D.U, &D.Qb, &D.G, &D.F, &D.DI, &D.Qm1, &D.Qm1Lr, &D.Qm1Lt,
-                &D.Qm1p, &D.QmX, &D.Qm, &D.Qmt, &D.Ut, &D.DIt};
+                &D.Qm1p, &D.QmX, &D.Qm, &D.Qmt, &D.Ut, &D.DIt, &D.Qbt};
   for (T **a : arrs) *a = c.take<T>(base, S2);
   D.ldA = (long long)CDZ_NA * ld;
   D.lowExp = CDZ_SPREAD_LOW;

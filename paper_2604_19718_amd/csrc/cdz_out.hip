@@ -61,6 +61,7 @@ struct OutStage {
   int d[6], P[6];
   // d, P of positions i+1+q ([q]), j-1-q ([32+q]), i-1-q ([64+q]), j+1+q ([96+q])
   int wd[128], wP[128];
+  unsigned char mapL[192], mapR[192];  // state offset -> position index (window staging)
 };
 
 // Blocks of 36 values for the loop terms of a cell: the adjoints of the
@@ -511,25 +512,34 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       //      recursion reads directly (the l1 = 1 and l2 = 1 terms)
       T *UR1 = X, *UC1 = X + 30 * 36, *DIrow = X + 60 * 36, *DIcol = X + 89 * 36;
       {
-        const int n0 = lmax, n1 = 2 * lmax, n2 = n1 + (lmax - 1), n3 = n2 + (lmax - 2);
-        for (int idx = tid; idx < n3 * 36; idx += CDZ_NT) {
-          const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
-          T v = 0;
-          if (b < n0) {  // U[i+1][i+l], l = b + 1
-            if (r < d1 && c < lp_d[b]) v = D.U[(long long)(P1 + r) * ld + lp_P[b] + c];
-            UR1[b * 36 + q] = v;
-          } else if (b < n1) {  // U[j-l][j-1]
-            const int l = b - n0 + 1;
-            if (r < rp_d[l - 1] && c < dm) v = D.U[(long long)(rp_P[l - 1] + r) * ld + Pm + c];
-            UC1[(l - 1) * 36 + q] = v;
-          } else if (b < n2) {  // DI[i+1][j-L+1]
-            const int L = b - n1 + 2;
-            if (r < d1 && c < rp_d[L - 2]) v = D.DI[(long long)(P1 + r) * ld + rp_P[L - 2] + c];
-            DIrow[(L - 2) * 36 + q] = v;
-          } else {  // DI[i+L-1][j-1]
-            const int L = b - n2 + 3;
-            if (r < lp_d[L - 2] && c < dm) v = D.DI[(long long)(lp_P[L - 2] + r) * ld + Pm + c];
-            DIcol[(L - 2) * 36 + q] = v;
+        // the forward's window staging: contiguous rows (U, DI, and their
+        // transposes for the column strips), placed by state-to-position maps
+        // into blocks cleared first for the padding
+        const int baseL = lp_P[0], baseR = rp_P[lmax];
+        cdz_window_maps(C.mapL, C.mapR, lp_d, lp_P, rp_d, rp_P, lmax);
+        uint4 *w4 = reinterpret_cast<uint4 *>(X);
+        for (int idx = tid; idx < 118 * 36 * (int)sizeof(T) / 16; idx += CDZ_NT) w4[idx] = make_uint4(0, 0, 0, 0);
+        cdz_sync();
+        const int KU = lp_P[lmax] - baseL;                        // end states of U[i+1][i+1..i+lmax]
+        const int endR = rp_P[0] + rp_d[0] - baseR;               // right map: positions j-1-lmax..j-1
+        const int oC = rp_P[lmax - 1] - baseR, KC = endR - oC;    // start states of U[j-lmax..j-1][j-1]
+        const int oD = rp_P[lmax - 2] - baseR, KD = endR - oD;    // DI[i+1][j-lmax+1..j-1]
+        const int oL = lp_P[1] - baseL;                           // DI[i+2..i+lmax-1][j-1]
+        const int KL = lmax >= 3 ? lp_P[lmax - 1] - lp_P[1] : 0;
+        const int e1 = d1 * KU, e2 = e1 + dm * KC, e3 = e2 + d1 * KD, e4 = e3 + dm * KL;
+        for (int idx = tid; idx < e4; idx += CDZ_NT) {
+          if (idx < e1) {  // U[i+1][i+l]: row P1 + r of U
+            const int r = idx / KU, k = idx % KU, qq = C.mapL[k], c = k - (lp_P[qq] - baseL);
+            UR1[qq * 36 + r * 6 + c] = D.U[(long long)(P1 + r) * ld + baseL + k];
+          } else if (idx < e2) {  // U[j-l][j-1]: row Pm + c of Ut, l = qq + 1
+            const int t = idx - e1, c = t / KC, k = t % KC + oC, qq = C.mapR[k], r = k - (rp_P[qq] - baseR);
+            UC1[qq * 36 + r * 6 + c] = D.Ut[(long long)(Pm + c) * ld + baseR + k];
+          } else if (idx < e3) {  // DI[i+1][j-L+1]: row P1 + r of DI, L = qq + 2
+            const int t = idx - e2, r = t / KD, k = t % KD + oD, qq = C.mapR[k], c = k - (rp_P[qq] - baseR);
+            DIrow[qq * 36 + r * 6 + c] = D.DI[(long long)(P1 + r) * ld + baseR + k];
+          } else {  // DI[i+L-1][j-1]: row Pm + c of DIt, L = qq + 2
+            const int t = idx - e3, c = t / KL, k = t % KL + oL, qq = C.mapL[k], r = k - (lp_P[qq] - baseL);
+            DIcol[qq * 36 + r * 6 + c] = D.DIt[(long long)(Pm + c) * ld + baseL + k];
           }
         }
       }
@@ -645,20 +655,31 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       //      l1: run i+1..i+l1, inner pair (i+l1+1, j-1); right bulge l2:
       //      inner pair (i+1, j-1-l2), run j-l2..j-1.
       T *EL = X, *ER = X + 30 * 36, *QL = X + 60 * 36, *QR = X + 90 * 36;
+      // e blocks (contiguous in D.e); the Qb blocks of the inner pairs, the
+      // left column strip as contiguous rows of Qbt placed by the window map,
+      // into blocks cleared first
+      cdz_window_maps(C.mapL, C.mapR, lp_d, lp_P, rp_d, rp_P, lmax);
       for (int idx = tid; idx < 4 * lmax * 36; idx += CDZ_NT) {
-        const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
+        const int b = idx / 36, q = idx % 36;
         const int kind = b / lmax, l = b % lmax + 1;
         T v = 0;
-        if (kind == 0) {
-          v = D.e[(long long)(i + l) * 36 + q];
-        } else if (kind == 1) {
-          v = D.e[(long long)(j - 1 - l) * 36 + q];
-        } else if (kind == 2) {
-          if (r < lp_d[l] && c < dm) v = D.Qb[(long long)(lp_P[l] + r) * ld + Pm + c];
-        } else {
-          if (r < d1 && c < rp_d[l]) v = D.Qb[(long long)(P1 + r) * ld + rp_P[l] + c];
-        }
+        if (kind == 0) v = D.e[(long long)(i + l) * 36 + q];
+        else if (kind == 1) v = D.e[(long long)(j - 1 - l) * 36 + q];
         X[(kind * 30 + l - 1) * 36 + q] = v;
+      }
+      cdz_sync();
+      {
+        const int oq = lp_P[1] - lp_P[0], KQ = lp_P[lmax + 1] - lp_P[1];  // positions i+2..i+1+lmax
+        const int e1 = dm * KQ;
+        for (int idx = tid; idx < e1 + lmax * 36; idx += CDZ_NT) {
+          if (idx < e1) {  // Qb[i+1+l][j-1](x, c): row Pm + c of Qbt
+            const int c = idx / KQ, k = idx % KQ + oq, l = C.mapL[k], x = k - (lp_P[l] - lp_P[0]);
+            QL[(l - 1) * 36 + x * 6 + c] = D.Qbt[(long long)(Pm + c) * ld + lp_P[0] + k];
+          } else {  // Qb[i+1][j-1-l], by blocks
+            const int t = idx - e1, b = t / 36, qq = t % 36, r = qq / 6, c = qq % 6, l = b + 1;
+            if (r < d1 && c < rp_d[l]) QR[(l - 1) * 36 + qq] = D.Qb[(long long)(P1 + r) * ld + rp_P[l] + c];
+          }
+        }
       }
       cdz_sync();
       // per term, once and in place: R(a, x) = sum_y Gb(a,y) Qb[k][j-1](x,y)
