@@ -220,6 +220,37 @@ __device__ __forceinline__ void cdz_window_maps(unsigned char *mapL, unsigned ch
   }
 }
 
+// Copy nblk consecutive 36-value blocks (nblk <= 30) from global src to LDS
+// dst, in order or with the block order reversed; every thread issues all of
+// its loads before its first store.
+template <typename T>
+__device__ __forceinline__ void cdz_copy_blocks(T *dst, const T *src, int nblk, bool rev) {
+  constexpr int NV = (30 * 36 + CDZ_NT - 1) / CDZ_NT;
+  const int count = nblk * 36;
+  T v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    const int f = (int)threadIdx.x + k * CDZ_NT;
+    v[k] = f < count ? src[f] : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    const int f = (int)threadIdx.x + k * CDZ_NT;
+    if (f < count) {
+      const int b = f / 36;
+      dst[(rev ? nblk - 1 - b : b) * 36 + f % 36] = v[k];
+    }
+  }
+}
+
+// Zero nblk 36-value blocks at dst (16-byte aligned), 16 bytes a store.
+template <typename T>
+__device__ __forceinline__ void cdz_zero_blocks(T *dst, int nblk) {
+  uint4 *w4 = reinterpret_cast<uint4 *>(dst);
+  const int n4 = nblk * 36 * (int)sizeof(T) / 16;
+  for (int f = threadIdx.x; f < n4; f += CDZ_NT) w4[f] = make_uint4(0, 0, 0, 0);
+}
+
 // ---- workgroup sums by a reduce-scatter butterfly inside each wavefront.
 // At level k (k = 5..0) every lane pairs with a partner that differs in lane
 // bit k and agrees in the higher bits; the lane with bit k = 0 keeps the

@@ -572,13 +572,11 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
         // e blocks (contiguous in D.e), then the Qb blocks of the inner pairs,
         // the left side's column strip as contiguous rows of Qbt placed by the
         // window map, into blocks cleared first
-        for (int idx = tid; idx < 2 * lmax * 36; idx += CDZ_NT) {
-          const int b = idx / 36, qq = idx % 36, l = b % lmax + 1;
-          if (b < lmax)  // e_{k-1}, k = i+1+l (left) / e_l, l = j-1-l2 (right)
-            EB[(l - 1) * 36 + qq] = D.e[(long long)(side == 0 ? i + l : j - 1 - l) * 36 + qq];
-          else
-            QB[(l - 1) * 36 + qq] = 0;
-        }
+        // e_{k-1}, k = i+1+l (left: positions i+1..i+lmax) / e_l, l = j-1-l2
+        // (right: positions j-2 down to j-1-lmax), block l-1
+        if (side == 0) cdz_copy_blocks<T>(EB, D.e + (long long)(i + 1) * 36, lmax, false);
+        else cdz_copy_blocks<T>(EB, D.e + (long long)(j - 1 - lmax) * 36, lmax, true);
+        cdz_zero_blocks<T>(QB, lmax);
         cdz_sync();
         if (side == 0) {  // Qb[i+1+l][j-1](x, c) = Qbt row Pm + c, states of positions i+2..i+1+lmax
           const int o = lp_P[1] - lp_P[0], K = lp_P[lmax + 1] - lp_P[1];

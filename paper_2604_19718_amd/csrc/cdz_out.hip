@@ -659,14 +659,10 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       // left column strip as contiguous rows of Qbt placed by the window map,
       // into blocks cleared first
       cdz_window_maps(C.mapL, C.mapR, lp_d, lp_P, rp_d, rp_P, lmax);
-      for (int idx = tid; idx < 4 * lmax * 36; idx += CDZ_NT) {
-        const int b = idx / 36, q = idx % 36;
-        const int kind = b / lmax, l = b % lmax + 1;
-        T v = 0;
-        if (kind == 0) v = D.e[(long long)(i + l) * 36 + q];
-        else if (kind == 1) v = D.e[(long long)(j - 1 - l) * 36 + q];
-        X[(kind * 30 + l - 1) * 36 + q] = v;
-      }
+      cdz_copy_blocks<T>(EL, D.e + (long long)(i + 1) * 36, lmax, false);       // e_{i+l}
+      cdz_copy_blocks<T>(ER, D.e + (long long)(j - 1 - lmax) * 36, lmax, true);  // e_{j-1-l}
+      cdz_zero_blocks<T>(QL, lmax);
+      cdz_zero_blocks<T>(QR, lmax);
       cdz_sync();
       {
         const int oq = lp_P[1] - lp_P[0], KQ = lp_P[lmax + 1] - lp_P[1];  // positions i+2..i+1+lmax
