@@ -243,6 +243,50 @@ __device__ __forceinline__ void cdz_copy_blocks(T *dst, const T *src, int nblk, 
   }
 }
 
+// Copy count ints from global src to LDS dst (both 16-byte aligned) with
+// 16-byte loads, up to 4 of them in flight per thread.
+__device__ __forceinline__ void cdz_copy_ints(int *dst, const int *src, int count) {
+  const int n4 = count / 4;
+  const int4 *s4 = reinterpret_cast<const int4 *>(src);
+  int4 *d4 = reinterpret_cast<int4 *>(dst);
+  for (int base = 0; base < n4; base += 4 * CDZ_NT) {
+    int4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int f = base + (int)threadIdx.x + k * CDZ_NT;
+      v[k] = f < n4 ? s4[f] : make_int4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int f = base + (int)threadIdx.x + k * CDZ_NT;
+      if (f < n4) d4[f] = v[k];
+    }
+  }
+  for (int f = 4 * n4 + (int)threadIdx.x; f < count; f += CDZ_NT) dst[f] = src[f];
+}
+
+// Stage count LDS entries: loc(f, d) returns the global address of entry f
+// (nullptr: the entry is zero) and sets its index d in dst.  Each thread
+// issues NV loads before its stores, so their latencies overlap.
+template <int NV, typename T, typename L>
+__device__ __forceinline__ void cdz_stage_nv(T *dst, int count, L loc) {
+  for (int base = 0; base < count; base += NV * CDZ_NT) {
+    T v[NV];
+    int di[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      const int f = base + (int)threadIdx.x + k * CDZ_NT;
+      const T *p = nullptr;
+      di[k] = -1;
+      if (f < count) p = loc(f, di[k]);
+      v[k] = p ? *p : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < NV; k++)
+      if (di[k] >= 0) dst[di[k]] = v[k];
+  }
+}
+
 // Zero nblk 36-value blocks at dst (16-byte aligned), 16 bytes a store.
 template <typename T>
 __device__ __forceinline__ void cdz_zero_blocks(T *dst, int nblk) {

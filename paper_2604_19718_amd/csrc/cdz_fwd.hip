@@ -291,30 +291,37 @@ __device__ __forceinline__ void a_window(const DevProb<T> &D, CellStage<T> &C, c
     const int nU = d1 * KU, nC = dm * KC, nD = d1 * KD, nL = dm * KL;
     const int nA = D.AL ? dA * KA : nAP * 36;
     const int e1 = nU, e2 = e1 + nC, e3 = e2 + nD, e4 = e3 + nL;
-    for (int idx = tid; idx < e4 + nA; idx += CDZ_NT) {
+    // W offsets: UR1 0, UC1 30*36, DIrow 60*36, DIcol 89*36, AP 117*36
+    cdz_stage_nv<4, T>(W, e4 + nA, [&](int idx, int &d) -> const T * {
       if (idx < e1) {  // U[i+1][i+l]: row P1 + r of U
         const int r = idx / KU, k = idx % KU, qq = C.mapL[k], c = k - (lp_P[qq] - baseL);
-        UR1[qq * 36 + r * 6 + c] = D.U[(long long)(P1 + r) * ld + baseL + k];
-      } else if (idx < e2) {  // U[j-l][j-1]: row Pm + c of Ut, l = qq + 1
-        const int t = idx - e1, c = t / KC, k = t % KC + oC, qq = C.mapR[k], r = k - (rp_P[qq] - baseR);
-        UC1[qq * 36 + r * 6 + c] = D.Ut[(long long)(Pm + c) * ld + baseR + k];
-      } else if (idx < e3) {  // DI[i+1][j-L+1]: row P1 + r of DI, L = qq + 2
-        const int t = idx - e2, r = t / KD, k = t % KD + oD, qq = C.mapR[k], c = k - (rp_P[qq] - baseR);
-        DIrow[qq * 36 + r * 6 + c] = D.DI[(long long)(P1 + r) * ld + baseR + k];
-      } else if (idx < e4) {  // DI[i+L-1][j-1]: row Pm + c of DIt, L = qq + 2
-        const int t = idx - e3, c = t / KL, k = t % KL + oL, qq = C.mapL[k], r = k - (lp_P[qq] - baseL);
-        DIcol[(qq - 1) * 36 + r * 6 + c] = D.DIt[(long long)(Pm + c) * ld + baseL + k];
-      } else {
-        const int t = idx - e4;
-        if (D.AL) {
-          const int r = t / KA, k = t % KA;
-          AP[(k / dB) * 36 + r * 6 + k % dB] =
-              D.AL[(long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + k];
-        } else {
-          AP[t] = D.ALp[(long long)(i + 1) * (CDZ_NA * 36) + t];
-        }
+        d = qq * 36 + r * 6 + c;
+        return D.U + (long long)(P1 + r) * ld + baseL + k;
       }
-    }
+      if (idx < e2) {  // U[j-l][j-1]: row Pm + c of Ut, l = qq + 1
+        const int t = idx - e1, c = t / KC, k = t % KC + oC, qq = C.mapR[k], r = k - (rp_P[qq] - baseR);
+        d = (30 + qq) * 36 + r * 6 + c;
+        return D.Ut + (long long)(Pm + c) * ld + baseR + k;
+      }
+      if (idx < e3) {  // DI[i+1][j-L+1]: row P1 + r of DI, L = qq + 2
+        const int t = idx - e2, r = t / KD, k = t % KD + oD, qq = C.mapR[k], c = k - (rp_P[qq] - baseR);
+        d = (60 + qq) * 36 + r * 6 + c;
+        return D.DI + (long long)(P1 + r) * ld + baseR + k;
+      }
+      if (idx < e4) {  // DI[i+L-1][j-1]: row Pm + c of DIt, L = qq + 2
+        const int t = idx - e3, c = t / KL, k = t % KL + oL, qq = C.mapL[k], r = k - (lp_P[qq] - baseL);
+        d = (89 + qq - 1) * 36 + r * 6 + c;
+        return D.DIt + (long long)(Pm + c) * ld + baseL + k;
+      }
+      const int t = idx - e4;
+      if (D.AL) {
+        const int r = t / KA, k = t % KA;
+        d = (117 + k / dB) * 36 + r * 6 + k % dB;
+        return D.AL + (long long)(lp_P[1] + r) * D.ldA + (long long)CDZ_NA * rp_P[1] + k;
+      }
+      d = 117 * 36 + t;
+      return D.ALp + (long long)(i + 1) * (CDZ_NA * 36) + t;
+    });
   }
   cdz_sync();
   // AP <- AP . W (in place: every output is read into registers first)
@@ -389,7 +396,7 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
   T *W = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(CellStage<T>) + 15) / 16 * 16);
   const int n = D.n, tid = threadIdx.x;
   const long long ld = D.ld;
-  for (int k = tid; k < dl && k <= n; k += CDZ_NT) sE[k] = D.E[k];
+  cdz_copy_ints(sE, D.E, dl < n + 1 ? dl : n + 1);
   cdz_sync();
   const int Ed = choose_exponent(D, dl, sE);
   if (tid == 0) sE[dl] = Ed;

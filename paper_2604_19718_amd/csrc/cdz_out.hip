@@ -100,7 +100,7 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
   OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
   T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
   T *X = AB + 29 * 36;
-  for (int k = tid; k < n; k += CDZ_NT) sE[k] = D.E[k];
+  cdz_copy_ints(sE, D.E, n);
   const int EZ = (int)D.res[2];
   const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
   if (i >= n - dl) return;
@@ -251,29 +251,24 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       const int nl = hasR ? min(CDZ_MAXLOOP, i - 1) : 0;
       const int nr = hasL ? min(CDZ_MAXLOOP, n - 2 - j) : 0;
       T *Ulc = X, *Gbc = X + 30 * 36, *Urr = X + 60 * 36, *Gbr = X + 90 * 36, *GP = X + 120 * 36;
-      for (int idx = tid; idx < 2 * (nl + nr) * 36; idx += CDZ_NT) {
+      // X offsets: Ulc 0, Gbc 30*36, Urr 60*36, Gbr 90*36
+      cdz_stage_nv<3, T>(X, 2 * (nl + nr) * 36, [&](int idx, int &d) -> const T * {
         const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
-        T v = 0;
         if (b < 2 * nl) {
           const int kind = b / nl, l1 = b % nl + 1, pa = l1 - 1;  // position i - l1
-          if (kind == 0) {  // U[i-l1][i-1]
-            if (r < ll_d[pa] && c < dim1) v = D.U[(long long)(ll_P[pa] + r) * ld + Pim1 + c];
-            Ulc[(l1 - 1) * 36 + q] = v;
-          } else {  // Gb at block (i-l1, j)
-            if (r < ll_d[pa] && c < dj) v = A.Gb[(long long)(ll_P[pa] + r) * ld + Pj + c];
-            Gbc[(l1 - 1) * 36 + q] = v;
-          }
-        } else {
-          const int bb = b - 2 * nl, kind = bb / nr, l2 = bb % nr + 1, pz = l2 - 1;  // position j + l2
-          if (kind == 0) {  // U[j+1][j+l2]
-            if (r < djp1 && c < rr_d[pz]) v = D.U[(long long)(Pjp1 + r) * ld + rr_P[pz] + c];
-            Urr[(l2 - 1) * 36 + q] = v;
-          } else {  // Gb at block (i, j+l2)
-            if (r < di && c < rr_d[pz]) v = A.Gb[(long long)(Pi + r) * ld + rr_P[pz] + c];
-            Gbr[(l2 - 1) * 36 + q] = v;
-          }
+          d = (kind * 30 + l1 - 1) * 36 + q;
+          if (kind == 0)  // U[i-l1][i-1]
+            return (r < ll_d[pa] && c < dim1) ? D.U + (long long)(ll_P[pa] + r) * ld + Pim1 + c : nullptr;
+          // Gb at block (i-l1, j)
+          return (r < ll_d[pa] && c < dj) ? A.Gb + (long long)(ll_P[pa] + r) * ld + Pj + c : nullptr;
         }
-      }
+        const int bb = b - 2 * nl, kind = bb / nr, l2 = bb % nr + 1, pz = l2 - 1;  // position j + l2
+        d = ((2 + kind) * 30 + l2 - 1) * 36 + q;
+        if (kind == 0)  // U[j+1][j+l2]
+          return (r < djp1 && c < rr_d[pz]) ? D.U + (long long)(Pjp1 + r) * ld + rr_P[pz] + c : nullptr;
+        // Gb at block (i, j+l2)
+        return (r < di && c < rr_d[pz]) ? A.Gb + (long long)(Pi + r) * ld + rr_P[pz] + c : nullptr;
+      });
       cdz_sync();
       // per term, once: Ulc . e_{i-1} (left) and e_j . Urr (right), in place
       {
@@ -527,21 +522,28 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
         const int oL = lp_P[1] - baseL;                           // DI[i+2..i+lmax-1][j-1]
         const int KL = lmax >= 3 ? lp_P[lmax - 1] - lp_P[1] : 0;
         const int e1 = d1 * KU, e2 = e1 + dm * KC, e3 = e2 + d1 * KD, e4 = e3 + dm * KL;
-        for (int idx = tid; idx < e4; idx += CDZ_NT) {
+        // X offsets: UR1 0, UC1 30*36, DIrow 60*36, DIcol 89*36
+        cdz_stage_nv<3, T>(X, e4, [&](int idx, int &d) -> const T * {
           if (idx < e1) {  // U[i+1][i+l]: row P1 + r of U
             const int r = idx / KU, k = idx % KU, qq = C.mapL[k], c = k - (lp_P[qq] - baseL);
-            UR1[qq * 36 + r * 6 + c] = D.U[(long long)(P1 + r) * ld + baseL + k];
-          } else if (idx < e2) {  // U[j-l][j-1]: row Pm + c of Ut, l = qq + 1
-            const int t = idx - e1, c = t / KC, k = t % KC + oC, qq = C.mapR[k], r = k - (rp_P[qq] - baseR);
-            UC1[qq * 36 + r * 6 + c] = D.Ut[(long long)(Pm + c) * ld + baseR + k];
-          } else if (idx < e3) {  // DI[i+1][j-L+1]: row P1 + r of DI, L = qq + 2
-            const int t = idx - e2, r = t / KD, k = t % KD + oD, qq = C.mapR[k], c = k - (rp_P[qq] - baseR);
-            DIrow[qq * 36 + r * 6 + c] = D.DI[(long long)(P1 + r) * ld + baseR + k];
-          } else {  // DI[i+L-1][j-1]: row Pm + c of DIt, L = qq + 2
-            const int t = idx - e3, c = t / KL, k = t % KL + oL, qq = C.mapL[k], r = k - (lp_P[qq] - baseL);
-            DIcol[qq * 36 + r * 6 + c] = D.DIt[(long long)(Pm + c) * ld + baseL + k];
+            d = qq * 36 + r * 6 + c;
+            return D.U + (long long)(P1 + r) * ld + baseL + k;
           }
-        }
+          if (idx < e2) {  // U[j-l][j-1]: row Pm + c of Ut, l = qq + 1
+            const int t = idx - e1, c = t / KC, k = t % KC + oC, qq = C.mapR[k], r = k - (rp_P[qq] - baseR);
+            d = (30 + qq) * 36 + r * 6 + c;
+            return D.Ut + (long long)(Pm + c) * ld + baseR + k;
+          }
+          if (idx < e3) {  // DI[i+1][j-L+1]: row P1 + r of DI, L = qq + 2
+            const int t = idx - e2, r = t / KD, k = t % KD + oD, qq = C.mapR[k], c = k - (rp_P[qq] - baseR);
+            d = (60 + qq) * 36 + r * 6 + c;
+            return D.DI + (long long)(P1 + r) * ld + baseR + k;
+          }
+          // DI[i+L-1][j-1]: row Pm + c of DIt, L = qq + 2
+          const int t = idx - e3, c = t / KL, k = t % KL + oL, qq = C.mapL[k], r = k - (lp_P[qq] - baseL);
+          d = (89 + qq) * 36 + r * 6 + c;
+          return D.DIt + (long long)(Pm + c) * ld + baseL + k;
+        });
       }
       cdz_sync();
       // every target block is updated by exactly one thread; all old values
@@ -1066,7 +1068,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A) {
 // batched forms (see cdz_fwd_diag_batch): one launch for diagonal dl / for the
 // edges of every problem of a batch
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_out_diag_batch(const DevProb<T> *probs, const DevAdj<T> *adjs,
+__global__ __launch_bounds__(CDZ_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void cdz_out_diag_batch(const DevProb<T> *probs, const DevAdj<T> *adjs,
                                                             const int *off, int count, int dl) {
   int b, w;
   cdz_batch_locate(off, count, blockIdx.x, b, w);
