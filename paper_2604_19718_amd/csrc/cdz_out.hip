@@ -549,48 +549,25 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       // every target block is updated by exactly one thread; all old values
       // are fetched first so that the loads are in flight together
       constexpr int NPT = (4 * 29 * 36 + CDZ_NT - 1) / CDZ_NT;
+      // targets first, so that the old values are in flight while the pushed
+      // values are formed from LDS
       int off[NPT];
-      T val[NPT];
 #pragma unroll
       for (int m = 0; m < NPT; m++) {
         const int idx = tid + m * CDZ_NT;
         off[m] = -1;
-        val[m] = 0;
         if (idx >= 4 * 29 * 36) continue;
         const int kind = idx / (29 * 36), rem = idx % (29 * 36), L = rem / 36 + 2, q = rem % 36;
         const int r = q / 6, c = q % 6;
         if (L > lmax || (L < 3 && (kind == 1 || kind == 3))) continue;
-        const T fb = cdz_p2<T>(sE[dl - L - 2] + sE[L - 2] - sE[dl]);
-        const T *ab = AB + (L - 2) * 36;
-        T v = 0;
         if (kind == 0) {  // DI'[i+1][j-L+1](a, c)
-          if (r < d1 && c < rp_d[L - 2]) {
-#pragma unroll
-            for (int dd = 0; dd < 6; dd++) v += ab[r * 6 + dd] * UC1[(L - 2) * 36 + c * 6 + dd];
-            off[m] = (P1 + r) * (int)ld + rp_P[L - 2] + c;
-            val[m] = fb * C.vI1[r] * v;
-          }
+          if (r < d1 && c < rp_d[L - 2]) off[m] = (P1 + r) * (int)ld + rp_P[L - 2] + c;
         } else if (kind == 1) {  // DI'[i+L-1][j-1](b, dd)
-          if (r < lp_d[L - 2] && c < dm) {
-#pragma unroll
-            for (int a = 0; a < 6; a++) v += UR1[(L - 2) * 36 + a * 6 + r] * ab[a * 6 + c];
-            off[m] = (lp_P[L - 2] + r) * (int)ld + Pm + c;
-            val[m] = fb * C.vJm1[c] * v;
-          }
+          if (r < lp_d[L - 2] && c < dm) off[m] = (lp_P[L - 2] + r) * (int)ld + Pm + c;
         } else if (kind == 2) {  // U'[j-L+1][j-1](c, dd), run of L - 1
-          if (r < rp_d[L - 2] && c < dm) {
-#pragma unroll
-            for (int a = 0; a < 6; a++) v += C.vI1[a] * DIrow[(L - 2) * 36 + a * 6 + r] * ab[a * 6 + c];
-            off[m] = (rp_P[L - 2] + r) * (int)ld + Pm + c;
-            val[m] = fb * v;
-          }
+          if (r < rp_d[L - 2] && c < dm) off[m] = (rp_P[L - 2] + r) * (int)ld + Pm + c;
         } else {  // U'[i+1][i+L-1](a, b), run of L - 1
-          if (r < d1 && c < lp_d[L - 2]) {
-#pragma unroll
-            for (int dd = 0; dd < 6; dd++) v += ab[r * 6 + dd] * C.vJm1[dd] * DIcol[(L - 2) * 36 + c * 6 + dd];
-            off[m] = (P1 + r) * (int)ld + lp_P[L - 2] + c;
-            val[m] = fb * v;
-          }
+          if (r < d1 && c < lp_d[L - 2]) off[m] = (P1 + r) * (int)ld + lp_P[L - 2] + c;
         }
       }
       auto target = [&](int m) -> T * {
@@ -602,8 +579,33 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
 #pragma unroll
       for (int m = 0; m < NPT; m++) old[m] = off[m] >= 0 ? *target(m) : T(0);
 #pragma unroll
-      for (int m = 0; m < NPT; m++)
-        if (off[m] >= 0) *target(m) = old[m] + val[m];
+      for (int m = 0; m < NPT; m++) {
+        if (off[m] < 0) continue;
+        const int idx = tid + m * CDZ_NT;
+        const int kind = idx / (29 * 36), rem = idx % (29 * 36), L = rem / 36 + 2, q = rem % 36;
+        const int r = q / 6, c = q % 6;
+        const T fb = cdz_p2<T>(sE[dl - L - 2] + sE[L - 2] - sE[dl]);
+        const T *ab = AB + (L - 2) * 36;
+        T v = 0, val;
+        if (kind == 0) {
+#pragma unroll
+          for (int dd = 0; dd < 6; dd++) v += ab[r * 6 + dd] * UC1[(L - 2) * 36 + c * 6 + dd];
+          val = fb * C.vI1[r] * v;
+        } else if (kind == 1) {
+#pragma unroll
+          for (int a = 0; a < 6; a++) v += UR1[(L - 2) * 36 + a * 6 + r] * ab[a * 6 + c];
+          val = fb * C.vJm1[c] * v;
+        } else if (kind == 2) {
+#pragma unroll
+          for (int a = 0; a < 6; a++) v += C.vI1[a] * DIrow[(L - 2) * 36 + a * 6 + r] * ab[a * 6 + c];
+          val = fb * v;
+        } else {
+#pragma unroll
+          for (int dd = 0; dd < 6; dd++) v += ab[r * 6 + dd] * C.vJm1[dd] * DIcol[(L - 2) * 36 + c * 6 + dd];
+          val = fb * v;
+        }
+        *target(m) = old[m] + val;
+      }
       __syncthreads();  // the bulge pushes below update some of the same runs
     }
     if (lmax >= 4) {
@@ -702,33 +704,19 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       }
       cdz_sync();
       constexpr int NPB = (2 * 30 * 36 + CDZ_NT - 1) / CDZ_NT;
+      // targets first (their old values in flight while the pushes are formed)
       int off[NPB];
-      T val[NPB];
 #pragma unroll
       for (int m = 0; m < NPB; m++) {
         const int idx = tid + m * CDZ_NT;
         off[m] = -1;
-        val[m] = 0;
         if (idx >= 2 * lmax * 36) continue;
         const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
         const int side = b / lmax, l = b % lmax + 1;
-        const T *el = (side == 0 ? EL : ER) + (l - 1) * 36, *qk = (side == 0 ? QL : QR) + (l - 1) * 36;
-        const T f = tab[TB_BU + l] * cdz_p2<T>(sE[l - 1] + sE[dl - 2 - l] - sE[dl]);
-        T v = 0;
-        if (side == 0) {  // U'[i+1][i+l](a, b) = sum_x e_{k-1}(b,x) R(a,x)
-          if (r < d1 && c < lp_d[l - 1]) {
-#pragma unroll
-            for (int x = 0; x < 6; x++) v += el[c * 6 + x] * qk[r * 6 + x];
-            off[m] = (P1 + r) * (int)ld + lp_P[l - 1] + c;
-            val[m] = f * v;
-          }
-        } else {  // U'[j-l][j-1](c, dd) = sum_y e_l(y,c) S(y,dd)
-          if (r < rp_d[l - 1] && c < dm) {
-#pragma unroll
-            for (int y = 0; y < 6; y++) v += el[y * 6 + r] * qk[y * 6 + c];
-            off[m] = (rp_P[l - 1] + r) * (int)ld + Pm + c;
-            val[m] = f * v;
-          }
+        if (side == 0) {  // U'[i+1][i+l](a, b)
+          if (r < d1 && c < lp_d[l - 1]) off[m] = (P1 + r) * (int)ld + lp_P[l - 1] + c;
+        } else {  // U'[j-l][j-1](c, dd)
+          if (r < rp_d[l - 1] && c < dm) off[m] = (rp_P[l - 1] + r) * (int)ld + Pm + c;
         }
       }
       T old[NPB];
@@ -739,8 +727,21 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       }
 #pragma unroll
       for (int m = 0; m < NPB; m++) {
-        const bool left = (tid + m * CDZ_NT) / 36 < lmax;
-        if (off[m] >= 0) (left ? A.UbL : A.UbR)[off[m]] = old[m] + val[m];
+        if (off[m] < 0) continue;
+        const int idx = tid + m * CDZ_NT;
+        const int b = idx / 36, q = idx % 36, r = q / 6, c = q % 6;
+        const int side = b / lmax, l = b % lmax + 1;
+        const T *el = (side == 0 ? EL : ER) + (l - 1) * 36, *qk = (side == 0 ? QL : QR) + (l - 1) * 36;
+        const T f = tab[TB_BU + l] * cdz_p2<T>(sE[l - 1] + sE[dl - 2 - l] - sE[dl]);
+        T v = 0;
+        if (side == 0) {  // U'[i+1][i+l](a, b) = sum_x e_{k-1}(b,x) R(a,x)
+#pragma unroll
+          for (int x = 0; x < 6; x++) v += el[c * 6 + x] * qk[r * 6 + x];
+        } else {  // U'[j-l][j-1](c, dd) = sum_y e_l(y,c) S(y,dd)
+#pragma unroll
+          for (int y = 0; y < 6; y++) v += el[y * 6 + r] * qk[y * 6 + c];
+        }
+        (side == 0 ? A.UbL : A.UbR)[off[m]] = old[m] + f * v;
       }
     }
     // hairpin closed by (i, j): its run i+1..j-1 (block distinct from the runs above)
