@@ -110,13 +110,6 @@ __device__ __forceinline__ void cdz_win(int w, int &l1, int &l2) {
   l2 = w - base;
 }
 
-template <typename T>
-__device__ __forceinline__ T cdz_wave_sum(T x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
 __device__ __forceinline__ float cdz_wave_max(float x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
@@ -167,29 +160,6 @@ __device__ __forceinline__ void cdz_batch_locate(const int *off, int count, int 
   }
   b = cdz_uni(lo);
   w = cdz_uni(blk - off[lo]);
-}
-
-// Stage blocks of up to 6 x 6 values into LDS (dst[b * 36 + r * 6 + c]), one
-// wavefront per block: the block's source (row-major, stride ld, dr x dc
-// valid entries) is wave-uniform, lane q < 36 moves entry (q / 6, q % 6), so
-// the per-lane work is one load and one LDS store.  src(b, p, dr, dc) fills
-// the source of block b (values it reads must be the same in every lane).
-template <typename T, typename F>
-__device__ __forceinline__ void cdz_stage_blocks(T *dst, int nblk, long long ld, F src) {
-  const int lane = threadIdx.x & 63, r = lane / 6, c = lane % 6;
-  const long long off = (long long)r * ld + c;
-  const int nw = CDZ_NT / 64;
-#pragma unroll 2
-  for (int b = cdz_wave_id(); b < nblk; b += nw) {
-    const T *p;
-    int dr, dc;
-    src(b, p, dr, dc);
-    p = cdz_uni(p);
-    dr = cdz_uni(dr);
-    dc = cdz_uni(dc);
-    const T v = (r < dr && c < dc) ? p[off] : T(0);
-    if (lane < 36) dst[b * 36 + lane] = v;
-  }
 }
 
 // Workgroup barrier that orders LDS accesses only: global stores issued

@@ -238,11 +238,6 @@ __device__ __forceinline__ void stage_block(T *dst, const T *A, long long ld, in
   dst[q] = (r < dr && c < dc) ? A[(long long)(r0 + r) * ld + c0 + c] : T(0);
 }
 
-template <typename T>
-__device__ __forceinline__ int win_base(int l1) {  // first window index with this l1
-  return 31 * l1 - l1 * (l1 - 1) / 2;
-}
-
 // Interior-loop sums A(i,j,L), L = 2..lmax, of cell (i, j) into AC by the
 // loop-size recursion, staging on the way UR1 = U[i+1][i+l] and UC1 =
 // U[j-l][j-1] (l = 1..lmax), which the bulge sums of the forward read next.
@@ -782,18 +777,27 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
 // Z5[j], j = W..n-1, from pairs (k, j) with j - k <= W (Z5[0..W-1] are the
 // exact values of the truncated pass).  One workgroup, positions in turn.
 // One wavefront (64 lanes, no workgroup barriers) steps the truncated exterior
-// prefix through j = W..n-1; lanes take the items of a step, a butterfly of
-// lane exchanges sums them, lane 0 renormalises.
+// prefix through j = W..n-1:
+//   Z5[j] = A[j] v_j  +  sum_{k = max(0, j-W)}^{j-4} 2^(..) A[k] Qb[k][j],
+//   A[k] = Z5[k-1] e_{k-1}  (A[0] = the unit row),
+// lanes take the pair items k of a step, a butterfly of lane exchanges sums
+// them, lane 0 renormalises, and lanes 0..5 form A[j+1] once Z5[j] is known
+// (each A is used by up to W steps).  Qb[k][j] is read from Qbt, where the
+// items of a step lie along one row.
 template <typename T>
 __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) {
-  // the recurrence reaches back at most W + 1 positions: Z5, G5, d and P of
-  // positions j - W - 1 .. j live in an LDS ring, the exponents E[0..W] too,
-  // so each step waits on LDS rather than on global memory
-  constexpr int RMAX = CDZ_SPAN_MAX + 2;
-  __shared__ double zr[RMAX * 6];
+  // the recurrence reaches back at most W + 1 positions: Z5, G5, A, d and P
+  // of positions j - W - 1 .. j live in an LDS ring, the exponents E[0..W]
+  // too, so each step waits on LDS rather than on global memory.  The ring
+  // holds 64 positions more, and the new Z5, G5 go to global memory 64
+  // positions at a time (a store in every step would hold up the next step's
+  // loads, which complete in order behind it).
+  constexpr int RMAX = CDZ_SPAN_MAX + 2 + 64;
+  __shared__ double zr[RMAX * 6], ar[RMAX * 6];
   __shared__ int gr[RMAX], dr[RMAX], Pr[RMAX], sE[CDZ_SPAN_MAX + 1];
-  const int n = D.n, lane = threadIdx.x, R = W + 2;
+  const int n = D.n, lane = threadIdx.x, R = W + 2 + 64;
   const long long ld = D.ld;
+  int flushed = W;  // positions W.. not yet written to D.Z5 / D.G5
   if (W > CDZ_SPAN_MAX) {
     if (lane == 0) D.res[0] = NAN;  // caller error: log Z reports it
     return;
@@ -807,67 +811,99 @@ __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) 
     sE[k] = D.E[k];
   }
   cdz_wave_sync();
-  for (int j = W; j < n; j++) {
+  for (int k = 1 + lane; k <= W && k < n; k += 64) {  // A of positions 1..W
+#pragma unroll
+    for (int x = 0; x < 6; x++) {
+      double a = 0;
+#pragma unroll
+      for (int q = 0; q < 6; q++) a += zr[((k - 1) % R) * 6 + q] * D.ed[(k - 1) * 36 + q * 6 + x];
+      ar[(k % R) * 6 + x] = a;
+    }
+  }
+  cdz_wave_sync();
+  // The global operands of a step do not depend on the recurrence: those of
+  // step j + 1 (the Qb of this lane's first item, v_{j+1}, e_{j+1}) are
+  // issued at the start of step j into the other of two operand sets and
+  // waited on at j + 1; d and P enter the ring 64 positions ahead of the
+  // steps (slot p % R of position p is free once step p - R + W + 1 has
+  // passed, as R = W + 66).  The items k of step jj
+  // are k0 .. jj - 4, k0 = max(0, jj - W); the loads of a lane without an
+  // item, or outside the item's states, read a valid element in its place
+  // and are masked where they are used.
+  struct Ops {
+    T q[6][6];
+    int dk, ok;
+    double v, e[6];
+  };
+  auto load_qb = [&](T(&q)[6][6], int Pj, int dj, int k) __attribute__((always_inline)) {
+    const int dk = dr[k % R], Pk = Pr[k % R];
+#pragma unroll
+    for (int t = 0; t < 6; t++)
+#pragma unroll
+      for (int x = 0; x < 6; x++) {
+        const int tc = t < dj ? t : dj - 1, xc = x < dk ? x : dk - 1;
+        q[x][t] = D.Qbt[(Pj + tc) * ld + Pk + xc];
+      }
+  };
+  auto issue = [&](int jj, int djj, int Pjj, Ops &o) __attribute__((always_inline)) {
+    const int k0 = jj - W > 0 ? jj - W : 0, k = k0 + lane;
+    o.ok = k <= jj - 4;
+    const int kc = o.ok ? k : k0;
+    o.dk = o.ok ? dr[kc % R] : 0;
+    load_qb(o.q, Pjj, djj, kc);
+    const int ls = lane < 6 ? lane : 0;
+    o.v = D.vd[jj * 6 + ls];
+#pragma unroll
+    for (int c = 0; c < 6; c++) o.e[c] = D.ed[jj * 36 + c * 6 + ls];
+  };
+  auto step = [&](int j, const Ops &cur, Ops &nxt) __attribute__((always_inline)) {
     const int sj = j % R, sm1 = (j - 1) % R;
-    const int G = gr[sm1], dj = dr[sj], Pj = Pr[sj];
-    // d, P of position j + 1, loaded now so that the step does not wait on them
-    const int dn = j + 1 < n ? D.d[j + 1] : 0, Pn = j + 1 < n ? D.P[j + 1] : 0;
+    if ((j - W) % 64 == 0) {  // d, P of positions j + 1 .. j + 64 into the ring
+      const int p = j + 1 + lane;
+      if (p < n) {
+        dr[p % R] = D.d[p];
+        Pr[p % R] = D.P[p];
+      }
+      cdz_wave_sync();
+    }
+    const int G = gr[sm1], dj = dr[sj];
+    // every step issues the same loads (the count of loads in flight stays
+    // fixed); the last one loads a set for position n - 1 that is not used
+    const int jn = j + 1 < n ? j + 1 : j;
+    issue(jn, dr[jn % R], Pr[jn % R], nxt);
     double part[6] = {0, 0, 0, 0, 0, 0};
     const int k0 = j - W > 0 ? j - W : 0;  // first pair start
-    // item 0: j unpaired; item it >= 1: k = k0 + it - 1 pairs j (k <= j - 4)
-    const int nit = 1 + (j - 4 - k0 + 1 > 0 ? j - 4 - k0 + 1 : 0);
-    for (int it = lane; it < nit; it += 64) {
-      if (it == 0) {
-        double z[6];
+    const int nk = j - 4 - k0 + 1 > 0 ? j - 4 - k0 + 1 : 0;  // pair items k = k0..j-4
+    auto add_item = [&](int k, int dk, const T(&q)[6][6]) __attribute__((always_inline)) {
+      double a[6];
+      if (k == 0) {
+        const double sc = ldexp(1.0, sE[j] - G);
 #pragma unroll
-        for (int q = 0; q < 6; q++) z[q] = zr[sm1 * 6 + q];
-#pragma unroll
-        for (int t = 0; t < 6; t++) {
-          double a = 0;
-#pragma unroll
-          for (int q = 0; q < 6; q++) a += z[q] * D.ed[(j - 1) * 36 + q * 6 + t];
-          part[t] += t < dj ? a * D.vd[j * 6 + t] : 0.0;
-        }
+        for (int x = 0; x < 6; x++) a[x] = sc;
       } else {
-        const int k = k0 + it - 1, dk = dr[k % R], Pk = Pr[k % R];
-        if (k == 0) {
-          const double sc = ldexp(1.0, sE[j] - G);
-#pragma unroll 1
-          for (int x = 0; x < dk; x++)
+        const double sc = ldexp(1.0, gr[(k - 1) % R] + sE[j - k] - G);
 #pragma unroll
-            for (int t = 0; t < 6; t++)
-              if (t < dj) part[t] += (double)D.Qb[x * ld + Pj + t] * sc;
-        } else {
-          // every global operand of the item first (none depends on the
-          // recurrence), then the ring values
-          T qb[6][6];
-          double ev[6][6];
-#pragma unroll
-          for (int x = 0; x < 6; x++)
-#pragma unroll
-            for (int t = 0; t < 6; t++) {
-              qb[x][t] = (x < dk && t < dj) ? D.Qb[(Pk + x) * ld + Pj + t] : T(0);
-              ev[x][t] = x < dk ? D.ed[(k - 1) * 36 + t * 6 + x] : 0.0;  // ev[x][q] = ed(q, x)
-            }
-          const int sk = (k - 1) % R;
-          const double sc = ldexp(1.0, gr[sk] + sE[j - k] - G);
-          double z[6];
-#pragma unroll
-          for (int q = 0; q < 6; q++) z[q] = zr[sk * 6 + q];
-#pragma unroll
-          for (int x = 0; x < 6; x++) {
-            if (x >= dk) break;
-            double a = 0;
-#pragma unroll
-            for (int q = 0; q < 6; q++) a += z[q] * ev[x][q];
-            a *= sc;
-#pragma unroll
-            for (int t = 0; t < 6; t++)
-              if (t < dj) part[t] += a * (double)qb[x][t];
-          }
-        }
+        for (int x = 0; x < 6; x++) a[x] = ar[(k % R) * 6 + x] * sc;
       }
+#pragma unroll
+      for (int x = 0; x < 6; x++) {
+        if (x >= dk) break;
+#pragma unroll
+        for (int t = 0; t < 6; t++)
+          if (t < dj) part[t] += a[x] * (double)q[x][t];
+      }
+    };
+    if (cur.ok) add_item(k0 + lane, cur.dk, cur.q);
+    for (int it = lane + 64; it < nk; it += 64) {  // spans above 67: items beyond the first 64
+      const int k = k0 + it;
+      T q[6][6];
+      load_qb(q, Pr[sj], dj, k);
+      add_item(k, dr[k % R], q);
     }
+    // j unpaired: lane t adds A[j](t) v_j(t)
+#pragma unroll
+    for (int t = 0; t < 6; t++)
+      if (t == lane && t < dj) part[t] += ar[sj * 6 + t] * cur.v;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
 #pragma unroll
@@ -876,18 +912,32 @@ __device__ __forceinline__ void exterior_trunc_body(const DevProb<T> &D, int W) 
       double mx = 0;
       for (int t = 0; t < 6; t++) mx = fmax(mx, fabs(part[t]));
       const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
-      for (int t = 0; t < 6; t++) {
-        const double z = t < dj ? ldexp(part[t], -e) : 0.0;
-        zr[sj * 6 + t] = z;
-        D.Z5[j * 6 + t] = z;
-      }
+      for (int t = 0; t < 6; t++) zr[sj * 6 + t] = t < dj ? ldexp(part[t], -e) : 0.0;
       gr[sj] = G + e;
-      D.G5[j] = G + e;
-      // position j + 1 takes the slot of j - W - 1, which no step needs any more
-      dr[(j + 1) % R] = dn;
-      Pr[(j + 1) % R] = Pn;
     }
-    cdz_wave_sync();  // lane 0's ring entries are read by every lane at j + 1
+    cdz_wave_sync();  // Z5[j] is read by lanes 0..5 below, the ring at j + 1
+    if (lane < 6 && j + 1 < n) {  // A[j+1](x = lane) = sum_q Z5[j](q) e_j(q, x)
+      double a = 0;
+#pragma unroll
+      for (int q = 0; q < 6; q++) a += zr[sj * 6 + q] * cur.e[q];
+      ar[((j + 1) % R) * 6 + lane] = a;
+    }
+    if (j - flushed == 63 || j == n - 1) {
+      const int p = flushed + lane;
+      if (p <= j) {
+#pragma unroll
+        for (int t = 0; t < 6; t++) D.Z5[p * 6 + t] = zr[(p % R) * 6 + t];
+        D.G5[p] = gr[p % R];
+      }
+      flushed = j + 1;
+    }
+    cdz_wave_sync();  // A[j+1] is read at j + 1
+  };
+  Ops o0, o1;
+  if (W < n) issue(W, dr[W % R], Pr[W % R], o0);
+  for (int j = W; j < n; j += 2) {  // two steps per turn: the operand sets swap roles
+    step(j, o0, o1);
+    if (j + 1 < n) step(j + 1, o1, o0);
   }
 }
 
