@@ -84,6 +84,7 @@ template <typename T>
 struct W {  // per-wave state
   const Smp<T> *S;
   int sid, lane, top;
+  int hk, hi, hj, hs, ht;  // top entry of the stack, held in registers (hk < 0: none)
   uint32_t draw;
   int *stk;
   double *gb;
@@ -97,21 +98,27 @@ __device__ __forceinline__ double Qv(const T *A, long long ld, int r, int c) {
   return (double)A[(long long)r * ld + c];
 }
 
-// Stack entries, slots and partners are written by every lane with the same
-// (wave-uniform) value, so each lane later reads back its own store.
+// The top entry of the stack is held in registers (depth first, the fragment
+// pushed last is taken next, so most pushes never reach memory); a push moves
+// the entry held before it to the stack in memory.  Stack entries, slots and
+// partners are written by every lane with the same (wave-uniform) value, so
+// each lane later reads back its own store.
 template <typename T>
 __device__ __forceinline__ void push(W<T> &w, int kind, int i, int j, int s, int t) {
-  if (w.top >= w.S->cap) {
-    w.bad = true;
-    return;
+  if (w.hk >= 0) {
+    if (w.top >= w.S->cap) {
+      w.bad = true;
+      return;
+    }
+    int *e = w.stk + 5 * w.top;
+    e[0] = w.hk;
+    e[1] = w.hi;
+    e[2] = w.hj;
+    e[3] = w.hs;
+    e[4] = w.ht;
+    w.top++;
   }
-  int *e = w.stk + 5 * w.top;
-  e[0] = kind;
-  e[1] = i;
-  e[2] = j;
-  e[3] = s;
-  e[4] = t;
-  w.top++;
+  w.hk = kind, w.hi = i, w.hj = j, w.hs = s, w.ht = t;
 }
 
 template <typename T>
@@ -125,7 +132,7 @@ __device__ __forceinline__ void set_state(W<T> &w, int p, int s) {
 // returns the index of the chosen alternative (wave-uniform).  Returns false
 // if every weight vanished.
 template <typename T, typename GS, typename SC>
-__device__ bool decide(W<T> &w, int G, GS gsum, SC scan, int &gsel, int &asel) {
+__device__ __forceinline__ bool decide(W<T> &w, int G, GS gsum, SC scan, int &gsel, int &asel) {
   const double u = uniform01(w.S->seed, (uint32_t)w.sid, w.draw++);
   double tot = 0;
   for (int base = 0; base < G; base += 64) {
@@ -172,7 +179,7 @@ __device__ bool decide(W<T> &w, int G, GS gsum, SC scan, int &gsel, int &asel) {
 // u * total.  Most decisions end in the first few groups.  If rounding leaves
 // the target beyond the last group, the last nonzero group is taken.
 template <typename T, typename GS, typename SC>
-__device__ bool decide_total(W<T> &w, int G, double tot, int first, GS gsum, SC scan, int &gsel, int &asel) {
+__device__ __forceinline__ bool decide_total(W<T> &w, int G, double tot, int first, GS gsum, SC scan, int &gsel, int &asel) {
   const double u = uniform01(w.S->seed, (uint32_t)w.sid, w.draw++);
   if (!(tot > 0)) return false;
   const double target = u * tot;
@@ -209,7 +216,7 @@ __device__ bool decide_total(W<T> &w, int G, double tot, int first, GS gsum, SC 
 // ---- fragment handlers ----------------------------------------------------
 
 template <typename T>
-__device__ void f_ext(W<T> &w, int j, int t) {
+__device__ __forceinline__ void f_ext(W<T> &w, int j, int t) {
   const DevProb<T> &D = w.S->D;
   const long long ld = D.ld;
   set_state(w, j, t);
@@ -292,7 +299,7 @@ __device__ void f_ext(W<T> &w, int j, int t) {
 }
 
 template <typename T>
-__device__ void f_run(W<T> &w, int p, int q, int a, int b) {
+__device__ __forceinline__ void f_run(W<T> &w, int p, int q, int a, int b) {
   const DevProb<T> &D = w.S->D;
   const long long ld = D.ld;
   const int cp = p / 3, cq = q / 3;
@@ -332,7 +339,7 @@ __device__ void f_run(W<T> &w, int p, int q, int a, int b) {
 
 // generic small decision: alternatives a = 0..count-1 (a single group)
 template <typename T, typename F>
-__device__ int small_decide(W<T> &w, int count, F alt) {
+__device__ __forceinline__ int small_decide(W<T> &w, int count, F alt) {
   auto gsum = [&](int) {
     double s = 0;
     for (int a = 0; a < count; a++) s += alt(a);
@@ -360,7 +367,7 @@ __device__ int small_decide(W<T> &w, int count, F alt) {
 
 // grouped decision: groups g = 0..G-1, alternatives a = 0..A-1 in each
 template <typename T, typename F>
-__device__ bool grid_decide(W<T> &w, int G, int A, F alt, int &g, int &a) {
+__device__ __forceinline__ bool grid_decide(W<T> &w, int G, int A, F alt, int &g, int &a) {
   auto gsum = [&](int gg) {
     double s = 0;
     for (int x = 0; x < A; x++) s += alt(gg, x);
@@ -386,7 +393,7 @@ __device__ bool grid_decide(W<T> &w, int G, int A, F alt, int &g, int &a) {
 }
 
 template <typename T>
-__device__ void f_pair(W<T> &w, int i, int j, int s, int s2) {
+__device__ __forceinline__ void f_pair(W<T> &w, int i, int j, int s, int s2) {
   const DevProb<T> &D = w.S->D;
   const long long ld = D.ld;
   const T *tab = D.tab;
@@ -621,7 +628,7 @@ __device__ void f_pair(W<T> &w, int i, int j, int s, int s2) {
 }
 
 template <typename T>
-__device__ void f_split(W<T> &w, int i, int j, int s, int s2, bool with_m1p) {
+__device__ __forceinline__ void f_split(W<T> &w, int i, int j, int s, int s2, bool with_m1p) {
   const DevProb<T> &D = w.S->D;
   const long long ld = D.ld;
   const int dl = j - i, Pi = D.P[i], Pj = D.P[j], E0 = D.E[dl];
@@ -678,7 +685,7 @@ __device__ void f_split(W<T> &w, int i, int j, int s, int s2, bool with_m1p) {
 }
 
 template <typename T>
-__device__ void f_m1(W<T> &w, int i, int j, int s, int s2) {
+__device__ __forceinline__ void f_m1(W<T> &w, int i, int j, int s, int s2) {
   const DevProb<T> &D = w.S->D;
   const long long ld = D.ld;
   set_state(w, i, s);
@@ -697,7 +704,7 @@ __device__ void f_m1(W<T> &w, int i, int j, int s, int s2) {
 }
 
 template <typename T>
-__device__ void f_m1p(W<T> &w, int i, int j, int s, int s2) {
+__device__ __forceinline__ void f_m1p(W<T> &w, int i, int j, int s, int s2) {
   const DevProb<T> &D = w.S->D;
   const long long ld = D.ld;
   set_state(w, i, s);
@@ -727,6 +734,7 @@ __device__ __forceinline__ void sample_one(const Smp<T> &S, int sid) {
   w.sid = sid;
   w.lane = lane;
   w.top = 0;
+  w.hk = -1;
   w.draw = 0;
   w.bad = false;
   w.stk = S.stack + (size_t)sid * S.cap * 5;
@@ -745,10 +753,16 @@ __device__ __forceinline__ void sample_one(const Smp<T> &S, int sid) {
     if (t >= 0) push(w, F_EXT, n - 1, 0, t, 0);
   }
   // depth-first traversal; every wave ends when its stack is empty or on error
-  while (w.top > 0 && !w.bad) {
-    w.top--;
-    const int *e = w.stk + 5 * w.top;
-    const int kind = e[0], i = e[1], j = e[2], s = e[3], t = e[4];
+  while ((w.hk >= 0 || w.top > 0) && !w.bad) {
+    int kind, i, j, s, t;
+    if (w.hk >= 0) {
+      kind = w.hk, i = w.hi, j = w.hj, s = w.hs, t = w.ht;
+      w.hk = -1;
+    } else {
+      w.top--;
+      const int *e = w.stk + 5 * w.top;
+      kind = e[0], i = e[1], j = e[2], s = e[3], t = e[4];
+    }
     switch (kind) {
       case F_EXT: f_ext(w, i, s); break;
       case F_B: f_pair(w, i, j, s, t); break;
