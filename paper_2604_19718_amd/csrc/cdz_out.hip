@@ -887,35 +887,65 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
           cdz_wave_sync();
         }
         if (own) {
-          // DI dressing
+          // DI dressing (every operand of a loop over at most 6 slots is
+          // loaded before the loop, absent slots as 0, so the loads overlap)
           const int dc = sd[j + 1], Pc = sP[j + 1];
-          for (int y = 0; y < dj; y++) {
-            const T qb = D.Qb[(Pi + x) * ld + Pj + y];
-            if (qb == T(0)) continue;
-            const int tin = cdz_ptype(D.nt[j * 6 + y], D.nt[i * 6 + x]);
-            for (int c = 0; c < dc; c++) {
-              const T wyc = qb * D.e[j * 36 + y * 6 + c];
-              const int nc = D.nt[(j + 1) * 6 + c];
-              acc += (double)(A.DIb[(Pp + b) * ld + Pc + c] * ep[b * 6 + x] * wyc *
-                              tab[TB_MM + nc * 24 + D.nt[p * 6 + b] * 6 + tin]);
+          const T epx = ep[b * 6 + x];
+          const int nix = D.nt[i * 6 + x], npb = D.nt[p * 6 + b];
+          T qbr[6], dib[6];
+          int ntj[6], ncr[6];
+#pragma unroll
+          for (int y = 0; y < 6; y++) {
+            qbr[y] = y < dj ? D.Qb[(Pi + x) * ld + Pj + y] : T(0);
+            ntj[y] = y < dj ? D.nt[j * 6 + y] : 0;
+            dib[y] = y < dc ? A.DIb[(Pp + b) * ld + Pc + y] : T(0);
+            ncr[y] = y < dc ? D.nt[(j + 1) * 6 + y] : 0;
+          }
+#pragma unroll
+          for (int y = 0; y < 6; y++) {
+            if (y >= dj || qbr[y] == T(0)) continue;
+            const int tin = cdz_ptype(ntj[y], nix);
+            T er[6];
+#pragma unroll
+            for (int c = 0; c < 6; c++) er[c] = c < dc ? D.e[j * 36 + y * 6 + c] : T(0);
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+              if (c >= dc) break;
+              const T wyc = qbr[y] * er[c];
+              acc += (double)(dib[c] * epx * wyc * tab[TB_MM + ncr[c] * 24 + npb * 6 + tin]);
             }
           }
           // the bulges: sum_y Qb(x, y) M(b, y)
           T sm = 0;
-          for (int y = 0; y < dj; y++) sm += D.Qb[(Pi + x) * ld + Pj + y] * (T)Mw[b * 6 + y];
-          acc += (double)(sm * ep[b * 6 + x]);
+#pragma unroll
+          for (int y = 0; y < 6; y++)
+            if (y < dj) sm += qbr[y] * (T)Mw[b * 6 + y];
+          acc += (double)(sm * epx);
         }
         cdz_wave_sync();
       }
       if (own) {
+        T lb[6], q1[6], qb[6];
+        double z3[6];
+#pragma unroll
+        for (int s2 = 0; s2 < 6; s2++) {
+          lb[s2] = s2 < dj ? A.Qm1Lb[(Pp + b) * ld + Pj + s2] : T(0);
+          q1[s2] = s2 < dj ? D.Qm1[(Pi + x) * ld + Pj + s2] : T(0);
+          qb[s2] = s2 < dj ? D.Qb[(Pi + x) * ld + Pj + s2] : T(0);
+          z3[s2] = s2 < dj ? D.Z3[j * 6 + s2] : 0.0;
+        }
         // Qm1L dressing
         T sm = 0;
-        for (int s2 = 0; s2 < dj; s2++) sm += A.Qm1Lb[(Pp + b) * ld + Pj + s2] * D.Qm1[(Pi + x) * ld + Pj + s2];
+#pragma unroll
+        for (int s2 = 0; s2 < 6; s2++)
+          if (s2 < dj) sm += lb[s2] * q1[s2];
         acc += (double)(sm * ep[b * 6 + x]);
         // exterior loop: pair (i, j) right after the prefix [0..p]
         const double sc = ldexp(1.0, D.G5[p] + sE[dl] + D.H3[j] - EZ);
         double sz = 0;
-        for (int t = 0; t < dj; t++) sz += (double)D.Qb[(Pi + x) * ld + Pj + t] * D.Z3[j * 6 + t];
+#pragma unroll
+        for (int t = 0; t < 6; t++)
+          if (t < dj) sz += (double)qb[t] * z3[t];
         acc += D.Z5[p * 6 + b] * D.ed[p * 36 + b * 6 + x] * (sz * sc);
       }
       continue;
@@ -928,21 +958,38 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
       const int dm = sd[j - 1], s = u, a = w;
       stage_inner(i, j);
       if (own) {
-        for (int s2 = 0; s2 < dj; s2++) {
-          const int to = cdz_ptype(D.nt[i * 6 + s], D.nt[j * 6 + s2]);
-          if (to < 0) continue;
-          const T ac = A.Qbb[(Pi + s) * ld + Pj + s2] * D.v[i * 6 + s] * D.v[j * 6 + s2];
-          if (ac == T(0) || ep[s * 6 + a] == T(0)) continue;
+        const T eps = ep[s * 6 + a], vis = D.v[i * 6 + s];
+        const int nis = D.nt[i * 6 + s];
+        T ac[6], mp[6], qp[6];
+        int ntj[6];
+#pragma unroll
+        for (int s2 = 0; s2 < 6; s2++) {
+          ntj[s2] = s2 < dj ? D.nt[j * 6 + s2] : 0;
+          ac[s2] = s2 < dj ? A.Qbb[(Pi + s) * ld + Pj + s2] * vis * D.v[j * 6 + s2] : T(0);
+          mp[s2] = s2 < dj ? A.Qm1pb[(Pi + s) * ld + Pj + s2] : T(0);
+          qp[s2] = s2 < dj ? D.Qm1p[(Pq + a) * ld + Pj + s2] : T(0);
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 6; s2++) {
+          if (s2 >= dj) break;
+          const int to = cdz_ptype(nis, ntj[s2]);
+          if (to < 0 || ac[s2] == T(0) || eps == T(0)) continue;
+          T em[6];
+#pragma unroll
+          for (int dd = 0; dd < 6; dd++) em[dd] = dd < dm ? D.e[(j - 1) * 36 + dd * 6 + s2] : T(0);
           T sm = 0;
-          for (int dd = 0; dd < dm; dd++)
-            sm += inner(a, dd, to, dl) * D.e[(j - 1) * 36 + dd * 6 + s2];
-          acc += (double)(ac * ep[s * 6 + a] * sm);
+#pragma unroll
+          for (int dd = 0; dd < 6; dd++)
+            if (dd < dm) sm += inner(a, dd, to, dl) * em[dd];
+          acc += (double)(ac[s2] * eps * sm);
         }
         // multiloop unpaired prefix base i
         const T f = tab[TB_MLC] * cdz_p2<T>(sE[dl - 1] - sE[dl]);
         T sm = 0;
-        for (int s2 = 0; s2 < dj; s2++) sm += A.Qm1pb[(Pi + s) * ld + Pj + s2] * D.Qm1p[(Pq + a) * ld + Pj + s2];
-        acc += (double)(sm * f * D.v[i * 6 + s] * ep[s * 6 + a]);
+#pragma unroll
+        for (int s2 = 0; s2 < 6; s2++)
+          if (s2 < dj) sm += mp[s2] * qp[s2];
+        acc += (double)(sm * f * vis * eps);
       }
       cdz_wave_sync();
       (void)di;
@@ -955,32 +1002,57 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
       const long long Pi = sP[i], Pj = Pq;
       const int dd = u, s2 = w;
       if (dl >= 4) stage_inner(i, j);
+      const T eps = own ? ep[dd * 6 + s2] : T(0), vjs = own ? D.v[j * 6 + s2] : T(0);
       if (own && dl >= 4) {
-        const int d1 = sd[i + 1];
-        if (ep[dd * 6 + s2] != T(0)) {
-          for (int s = 0; s < di; s++) {
-            const int to = cdz_ptype(D.nt[i * 6 + s], D.nt[j * 6 + s2]);
-            if (to < 0) continue;
-            const T ac = A.Qbb[(Pi + s) * ld + Pj + s2] * D.v[i * 6 + s] * D.v[j * 6 + s2];
-            if (ac == T(0)) continue;
+        const int d1 = sd[i + 1], njs = D.nt[j * 6 + s2];
+        T ac[6], mb[6], q1[6];
+        int nti[6];
+#pragma unroll
+        for (int s = 0; s < 6; s++) {
+          nti[s] = s < di ? D.nt[i * 6 + s] : 0;
+          ac[s] = s < di ? A.Qbb[(Pi + s) * ld + Pj + s2] * D.v[i * 6 + s] * vjs : T(0);
+          mb[s] = s < di ? A.Qm1b[(Pi + s) * ld + Pj + s2] : T(0);
+          q1[s] = s < di ? D.Qm1[(Pi + s) * ld + Pp + dd] : T(0);
+        }
+        if (eps != T(0)) {
+#pragma unroll
+          for (int s = 0; s < 6; s++) {
+            if (s >= di) break;
+            const int to = cdz_ptype(nti[s], njs);
+            if (to < 0 || ac[s] == T(0)) continue;
+            T ei[6];
+#pragma unroll
+            for (int a = 0; a < 6; a++) ei[a] = a < d1 ? D.e[i * 36 + s * 6 + a] : T(0);
             T sm = 0;
-            for (int a = 0; a < d1; a++) sm += D.e[i * 36 + s * 6 + a] * inner(a, dd, to, dl);
-            acc += (double)(ac * ep[dd * 6 + s2] * sm);
+#pragma unroll
+            for (int a = 0; a < 6; a++)
+              if (a < d1) sm += ei[a] * inner(a, dd, to, dl);
+            acc += (double)(ac[s] * eps * sm);
           }
         }
         // multiloop unpaired tail base j
         const T f = tab[TB_MLC] * cdz_p2<T>(sE[dl - 1] - sE[dl]);
         T sm = 0;
-        for (int s = 0; s < di; s++) sm += A.Qm1b[(Pi + s) * ld + Pj + s2] * D.Qm1[(Pi + s) * ld + Pp + dd];
-        acc += (double)(sm * f * ep[dd * 6 + s2] * D.v[j * 6 + s2]);
+#pragma unroll
+        for (int s = 0; s < 6; s++)
+          if (s < di) sm += mb[s] * q1[s];
+        acc += (double)(sm * f * eps * vjs);
       }
       if (dl >= 4) cdz_wave_sync();
       if (own && dl >= 1) {
         // unpaired run [i..p+1] extended from [i..p]
         const T f = cdz_p2<T>(sE[dl - 1] - sE[dl]);
+        T ub[6], uu[6];
+#pragma unroll
+        for (int a = 0; a < 6; a++) {
+          ub[a] = a < di ? A.Ub[(Pi + a) * ld + Pj + s2] : T(0);
+          uu[a] = a < di ? D.U[(Pi + a) * ld + Pp + dd] : T(0);
+        }
         T sm = 0;
-        for (int a = 0; a < di; a++) sm += A.Ub[(Pi + a) * ld + Pj + s2] * D.U[(Pi + a) * ld + Pp + dd];
-        acc += (double)(sm * f * ep[dd * 6 + s2] * D.v[j * 6 + s2]);
+#pragma unroll
+        for (int a = 0; a < 6; a++)
+          if (a < di) sm += ub[a] * uu[a];
+        acc += (double)(sm * f * eps * vjs);
       }
       continue;
     }
@@ -1021,22 +1093,38 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
           const int y = u, c = w;
           // DI dressing
           const int db = sd[i - 1], Pb = sP[i - 1];
-          for (int x = 0; x < di; x++) {
-            const T qb = D.Qb[(Pi + x) * ld + Pj + y];
-            if (qb == T(0)) continue;
-            const int tin = cdz_ptype(D.nt[j * 6 + y], D.nt[i * 6 + x]);
-            for (int b = 0; b < db; b++) {
-              const T wb = D.e[(i - 1) * 36 + b * 6 + x] * qb;
+          const T epc = ep[y * 6 + c];
+          const int njy = D.nt[j * 6 + y], nqc = D.nt[(p + 1) * 6 + c];
+          T qbc[6], dib[6];
+          int nti[6], nbr[6];
+#pragma unroll
+          for (int x = 0; x < 6; x++) {
+            qbc[x] = x < di ? D.Qb[(Pi + x) * ld + Pj + y] : T(0);
+            nti[x] = x < di ? D.nt[i * 6 + x] : 0;
+            dib[x] = x < db ? A.DIb[(Pb + x) * ld + Pq + c] : T(0);
+            nbr[x] = x < db ? D.nt[(i - 1) * 6 + x] : 0;
+          }
+#pragma unroll
+          for (int x = 0; x < 6; x++) {
+            if (x >= di || qbc[x] == T(0)) continue;
+            const int tin = cdz_ptype(njy, nti[x]);
+            T eb[6];
+#pragma unroll
+            for (int b = 0; b < 6; b++) eb[b] = b < db ? D.e[(i - 1) * 36 + b * 6 + x] : T(0);
+#pragma unroll
+            for (int b = 0; b < 6; b++) {
+              if (b >= db) break;
+              const T wb = eb[b] * qbc[x];
               if (wb == T(0)) continue;
-              const int nb = D.nt[(i - 1) * 6 + b];
-              acc += (double)(A.DIb[(Pb + b) * ld + Pq + c] * wb * ep[y * 6 + c] *
-                              tab[TB_MM + D.nt[(p + 1) * 6 + c] * 24 + nb * 6 + tin]);
+              acc += (double)(dib[b] * wb * epc * tab[TB_MM + nqc * 24 + nbr[b] * 6 + tin]);
             }
           }
           // the bulges: sum_x Qb(x, y) M(x, c)
           T sm = 0;
-          for (int x = 0; x < di; x++) sm += D.Qb[(Pi + x) * ld + Pj + y] * (T)Mw[x * 6 + c];
-          acc += (double)(sm * ep[y * 6 + c]);
+#pragma unroll
+          for (int x = 0; x < 6; x++)
+            if (x < di) sm += qbc[x] * (T)Mw[x * 6 + c];
+          acc += (double)(sm * epc);
         }
         cdz_wave_sync();
       }
