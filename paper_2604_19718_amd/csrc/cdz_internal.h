@@ -47,12 +47,14 @@ struct HostTables {
 //   UbL, UbR                    : run adjoints pushed by enclosing loops, by
 //                                 row (left runs, hairpins) and by column
 //                                 (right runs), so no two cells of one
-//                                 diagonal write the same element
+//                                 diagonal write the same element; UbR is
+//                                 stored transposed, so that the column a
+//                                 cell pushes along is a contiguous row
 //   Ub                          : total adjoint of the unpaired runs
 template <typename T>
 struct DevAdj {
   T *Qbb, *Qm1b, *Qm1pb, *QmXb, *QmXbt, *Qmb, *Qm1Lb, *DIb, *Gb, *Fb, *Ub, *UbL, *UbR;
-  T *DIbL, *DIbR;  // DI adjoint pushed along row i+1 / column j-1 of the enclosing cells
+  T *DIbL, *DIbR;  // DI adjoint pushed along row i+1 / column j-1 of the enclosing cells (DIbR transposed)
   T *ring;         // [3][n][CDZ_NA][36] interior-loop adjoints by size, last three diagonals
   double *etaV, *etaW;  // [n][36] edge-marginal terms of the size recursion
   double *eta;   // [n][6][6] edge marginals times Z / 2^EZ

@@ -83,6 +83,13 @@ __device__ __forceinline__ void ostage(T *dst, const T *A, long long ld, int r0,
   const int r = q / 6, c = q % 6;
   dst[q] = (ok && r < dr && c < dc) ? A[(long long)(r0 + r) * ld + c0 + c] : T(0);
 }
+// the same block from an array stored transposed (element (r, c) at [c][r])
+template <typename T>
+__device__ __forceinline__ void ostage_t(T *dst, const T *At, long long ld, int r0, int c0, int dr, int dc,
+                                         int q, bool ok) {
+  const int r = q / 6, c = q % 6;
+  dst[q] = (ok && r < dr && c < dc) ? At[(long long)(c0 + c) * ld + r0 + r] : T(0);
+}
 
 // ring of interior-loop adjoints: diagonal dl, cell i, size L (4..30)
 template <typename T>
@@ -142,7 +149,7 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       case 2:
         ostage(C.ubRight, A.Ub, ld, Pi, Pjp1, di, djp1, q, hasR);
         ostage(C.ubl, A.UbL, ld, Pi, Pj, di, dj, q, true);
-        ostage(C.ubr, A.UbR, ld, Pi, Pj, di, dj, q, true);
+        ostage_t(C.ubr, A.UbR, ld, Pi, Pj, di, dj, q, true);
         break;
       case 3:
         C.eIm1[q] = hasL ? D.e[(i - 1) * 36 + q] : T(0);
@@ -170,8 +177,8 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
         T v = 0;
         const int r = q / 6, c = q % 6;
         if (hasL && hasR && r < dim1 && c < djp1) {
-          const long long o = (long long)(Pim1 + r) * ld + Pjp1 + c;
-          v = A.DIbL[o] + A.DIbR[o];
+          const long long o = (long long)(Pim1 + r) * ld + Pjp1 + c, ot = (long long)(Pjp1 + c) * ld + Pim1 + r;
+          v = A.DIbL[o] + A.DIbR[ot];
         }
         C.w[q] = v;
         break;
@@ -562,10 +569,10 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
         if (L > lmax || (L < 3 && (kind == 1 || kind == 3))) continue;
         if (kind == 0) {  // DI'[i+1][j-L+1](a, c)
           if (r < d1 && c < rp_d[L - 2]) off[m] = (P1 + r) * (int)ld + rp_P[L - 2] + c;
-        } else if (kind == 1) {  // DI'[i+L-1][j-1](b, dd)
-          if (r < lp_d[L - 2] && c < dm) off[m] = (lp_P[L - 2] + r) * (int)ld + Pm + c;
-        } else if (kind == 2) {  // U'[j-L+1][j-1](c, dd), run of L - 1
-          if (r < rp_d[L - 2] && c < dm) off[m] = (rp_P[L - 2] + r) * (int)ld + Pm + c;
+        } else if (kind == 1) {  // DI'[i+L-1][j-1](b, dd), DIbR stored transposed
+          if (r < lp_d[L - 2] && c < dm) off[m] = (Pm + c) * (int)ld + lp_P[L - 2] + r;
+        } else if (kind == 2) {  // U'[j-L+1][j-1](c, dd), run of L - 1, UbR stored transposed
+          if (r < rp_d[L - 2] && c < dm) off[m] = (Pm + c) * (int)ld + rp_P[L - 2] + r;
         } else {  // U'[i+1][i+L-1](a, b), run of L - 1
           if (r < d1 && c < lp_d[L - 2]) off[m] = (P1 + r) * (int)ld + lp_P[L - 2] + c;
         }
@@ -715,8 +722,8 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
         const int side = b / lmax, l = b % lmax + 1;
         if (side == 0) {  // U'[i+1][i+l](a, b)
           if (r < d1 && c < lp_d[l - 1]) off[m] = (P1 + r) * (int)ld + lp_P[l - 1] + c;
-        } else {  // U'[j-l][j-1](c, dd)
-          if (r < rp_d[l - 1] && c < dm) off[m] = (rp_P[l - 1] + r) * (int)ld + Pm + c;
+        } else {  // U'[j-l][j-1](c, dd), UbR stored transposed
+          if (r < rp_d[l - 1] && c < dm) off[m] = (Pm + c) * (int)ld + rp_P[l - 1] + r;
         }
       }
       T old[NPB];
@@ -1400,7 +1407,8 @@ extern "C" cdz_status cdz_backward_dev(cdz_handle *h, double grad_logz, double *
 
 // Diagnostic copy of one workspace array of the last pass to the host:
 // which = 0..11 forward (U Qb G F DI Qm1 Qm1Lr Qm1Lt Qm1p QmX Qm Qmt),
-// 12..24 adjoint (Qbb Qm1b Qm1pb QmXb QmXbt Qmb Qm1Lb DIb Gb Fb Ub UbL UbR),
+// 12..24 adjoint (Qbb Qm1b Qm1pb QmXb QmXbt Qmb Qm1Lb DIb Gb Fb Ub UbL UbR; UbR
+// transposed),
 // 25 diagonal exponents (int32, n + 1).  Element type is the handle's
 // precision; ld x ld elements.
 template <typename T>
