@@ -264,8 +264,8 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
         if (b < 2 * nl) {
           const int kind = b / nl, l1 = b % nl + 1, pa = l1 - 1;  // position i - l1
           d = (kind * 30 + l1 - 1) * 36 + q;
-          if (kind == 0)  // U[i-l1][i-1]
-            return (r < ll_d[pa] && c < dim1) ? D.U + (long long)(ll_P[pa] + r) * ld + Pim1 + c : nullptr;
+          if (kind == 0)  // U[i-l1][i-1], a column strip read along a row of Ut
+            return (r < ll_d[pa] && c < dim1) ? D.Ut + (long long)(Pim1 + c) * ld + ll_P[pa] + r : nullptr;
           // Gb at block (i-l1, j)
           return (r < ll_d[pa] && c < dj) ? A.Gb + (long long)(ll_P[pa] + r) * ld + Pj + c : nullptr;
         }
@@ -881,7 +881,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
 #pragma unroll
               for (int a = 0; a < 6; a++) {
                 g[a] = a < da ? A.Gb[(Pa + a) * ld + Pj + y] : T(0);
-                uu[a] = a < da ? D.U[(Pa + a) * ld + Pp + b] : T(0);
+                uu[a] = a < da ? D.Ut[(Pp + b) * ld + Pa + a] : T(0);  // U(Pa + a, Pp + b)
               }
               T sm = 0;
 #pragma unroll
