@@ -1,0 +1,93 @@
+#!/usr/bin/env python3
+"""Write the stored oracle values that the full-size GPU parity tests compare
+against.  Calls only ``oracle/`` (and the seeded input generator); no value
+here comes from the HIP path.
+
+  oracle_workload2_300nt.npz   100 residues, codon + codon-pair weights
+  oracle_workload3_900nt.npz   300 residues, codon + codon-pair weights
+      logz, pair_upper (P[i][j] for j >= i, row-major upper triangle with the
+      diagonal = probability of being unpaired), base [n][4], codon [m][6],
+      codon_pair [m][6][6]
+  oracle_workload4_1197nt.npz  the longest member of the 256-protein batch
+      (index 189, 399 residues): logz only
+
+Each file also records the sha256 of the oracle sources it was computed
+with.  The 900-nt marginals take about two minutes on 8 cores.
+
+Usage: python tests/golden/make_oracle_goldens.py [--only 2|3|4]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_2604_19718_amd import inputs as I  # noqa: E402
+
+BATCH_LONGEST = 189  # member of workload 4 with the most residues (399)
+
+
+def oracle_sha256() -> str:
+    h = hashlib.sha256()
+    for f in ("oracle.c", "seqmcc.c"):
+        with open(os.path.join(ROOT, "oracle", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def path_for(k: int) -> str:
+    return os.path.join(HERE, {2: "oracle_workload2_300nt.npz", 3: "oracle_workload3_900nt.npz",
+                               4: "oracle_workload4_1197nt.npz"}[k])
+
+
+def write(k: int) -> None:
+    if k == 4:
+        prob, en = I.workload(4, index=BATCH_LONGEST)
+        t0 = time.time()
+        lz = oracle.logz(prob, en)
+        np.savez_compressed(path_for(k), logz=np.float64(lz), n=prob.n, index=BATCH_LONGEST,
+                            oracle_sha256=oracle_sha256())
+        print(f"workload 4[{BATCH_LONGEST}] n={prob.n} logz={lz!r} {time.time() - t0:.1f}s", flush=True)
+        return
+    prob, en = I.workload(k)
+    t0 = time.time()
+    r = oracle.marginals(prob, en)
+    iu = np.triu_indices(prob.n)
+    np.savez_compressed(path_for(k), logz=np.float64(r["logz"]), pair_upper=r["pair"][iu],
+                        base=r["base"], codon=r["codon"], codon_pair=r["codon_pair"], n=prob.n,
+                        oracle_sha256=oracle_sha256())
+    print(f"workload {k} n={prob.n} logz={r['logz']!r} {time.time() - t0:.1f}s", flush=True)
+
+
+def load(k: int) -> dict:
+    """The stored values of workload k; the pair matrix is rebuilt symmetric."""
+    z = np.load(path_for(k), allow_pickle=False)
+    out = {key: z[key] for key in z.files}
+    out["logz"] = float(out["logz"])
+    if "pair_upper" in out:
+        n = int(out["n"])
+        P = np.zeros((n, n))
+        iu = np.triu_indices(n)
+        P[iu] = out["pair_upper"]
+        P = P + np.triu(P, 1).T
+        out["pair"] = P
+    return out
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", type=int, choices=[2, 3, 4])
+    a = ap.parse_args()
+    oracle.build(force=False)
+    for k in ([a.only] if a.only else [2, 3, 4]):
+        write(k)

@@ -45,6 +45,7 @@ def test_workload_300nt(prec, m):
     ref = oracle.logz(prob, en)
     h = B.cdz_create(en, prec)
     got = B.cdz_partition(h, prob)
-    suffix = B.lib().cdz_debug_logz_suffix(h.ptr) if hasattr(B.lib(), "cdz_debug_logz_suffix") else got
-    print(prec, m, got, ref, got - ref, flush=True)
+    suffix = B.lib().cdz_debug_logz_suffix(h.ptr)
+    print(prec, m, got, suffix, ref, got - ref, flush=True)
     assert _rel(got, ref) <= TOL[prec]
+    assert _rel(suffix, ref) <= TOL[prec]

@@ -1,7 +1,9 @@
 """The 900-nt workload (300 residues, codon + codon-pair weights) in the
-launch configuration bench.py times: log Z against the oracle, FP32-scaled
-marginals against FP64, gradients against central finite differences, and
-invariants that hold at any size."""
+launch configuration bench.py times: log Z and all four marginals element by
+element against the FP64 oracle (stored by tests/golden/make_oracle_goldens.py,
+which calls only the oracle), the 1000 FP32 samples against the oracle's pair
+and codon probabilities, gradients against central finite differences, and
+properties the host-side assembly of the marginals cannot force."""
 import numpy as np
 import pytest
 
@@ -9,50 +11,75 @@ import oracle
 from paper_2604_19718_amd import binding as B
 from paper_2604_19718_amd import inputs as I
 
+from golden.make_oracle_goldens import load as load_golden
+
 pytestmark = pytest.mark.gpu
+
+# spec tolerances: log Z relative, marginals absolute
+TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-6, 1e-5)}
 
 
 @pytest.fixture(scope="module")
 def full():
     prob, en = I.workload(3)
-    ref_lz = oracle.logz(prob, en)
+    ref = load_golden(3)
+    assert int(ref["n"]) == prob.n
     h32, h64 = B.cdz_create(en, "fp32"), B.cdz_create(en, "fp64")
     m32 = B.cdz_marginals(h32, prob)
     m64 = B.cdz_marginals(h64, prob)
-    return prob, en, ref_lz, h32, h64, m32, m64
+    return prob, en, ref, h32, h64, m32, m64
 
 
-def test_logz_900nt(full):
-    prob, en, ref_lz, h32, h64, m32, m64 = full
-    print("log Z oracle", ref_lz, "fp64", m64["logz"], "fp32", m32["logz"], flush=True)
-    assert abs(m64["logz"] - ref_lz) <= 1e-12 * abs(ref_lz)
-    assert abs(m32["logz"] - ref_lz) <= 1e-6 * abs(ref_lz)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_logz_900nt(full, prec):
+    prob, en, ref, h32, h64, m32, m64 = full
+    h, mm = (h64, m64) if prec == "fp64" else (h32, m32)
+    tl, _ = TOL[prec]
+    suffix = B.lib().cdz_debug_logz_suffix(h.ptr)
+    print(prec, "log Z", mm["logz"], "suffix", suffix, "oracle", ref["logz"], flush=True)
+    assert abs(mm["logz"] - ref["logz"]) <= tl * abs(ref["logz"])
+    # the suffix exterior loop is an independent sum over the same arrays
+    assert abs(suffix - ref["logz"]) <= tl * abs(ref["logz"])
 
 
-def test_fp32_marginals_match_fp64_900nt(full):
-    prob, en, ref_lz, h32, h64, m32, m64 = full
-    for k in ("pair", "base", "codon", "codon_pair"):
-        err = np.abs(m32[k] - m64[k]).max()
-        print(k, "fp32 vs fp64 max abs", err, flush=True)
-        assert err <= 1e-5
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("key", ["pair", "base", "codon", "codon_pair"])
+def test_marginals_against_oracle_900nt(full, prec, key):
+    prob, en, ref, h32, h64, m32, m64 = full
+    mm = m64 if prec == "fp64" else m32
+    _, ta = TOL[prec]
+    err = np.abs(mm[key] - ref[key])
+    print(prec, key, "max abs err vs oracle", err.max(), "at", np.unravel_index(err.argmax(), err.shape),
+          flush=True)
+    assert err.max() <= ta
 
 
-def test_invariants_900nt(full):
-    prob, en, ref_lz, h32, h64, m32, m64 = full
-    for mm in (m32, m64):
-        P = mm["pair"]
-        assert np.abs(P - P.T).max() == 0
-        assert np.abs(mm["codon"].sum(1) - 1).max() < 1e-5
-        assert np.abs(mm["base"].sum(1) - 1).max() < 1e-5
-        cp = mm["codon_pair"]
-        assert np.abs(cp[1:].sum(2) - mm["codon"][:-1]).max() < 1e-5
-        assert np.abs(cp[1:].sum(1) - mm["codon"][1:]).max() < 1e-5
-        assert P.min() > -1e-6
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_unforced_properties_900nt(full, prec):
+    """Properties that the host assembly does not impose: every computed pair
+    probability (upper triangle, straight from the device) is >= 0 and the
+    unpaired probability 1 - sum_j P_ij lies in [0, 1]; codon marginals of
+    each residue sum to 1 and the codon-pair marginals of edge a-1|a
+    marginalise to the codon marginals of both residues (three different
+    device adjoints)."""
+    prob, en, ref, h32, h64, m32, m64 = full
+    mm = m64 if prec == "fp64" else m32
+    _, ta = TOL[prec]
+    P = mm["pair"]
+    iu = np.triu_indices(prob.n, 1)
+    assert P[iu].min() >= -ta
+    d = np.diag(P)
+    assert d.min() >= -ta and d.max() <= 1 + ta
+    assert np.abs(mm["codon"].sum(1) - 1).max() <= ta
+    cp = mm["codon_pair"]
+    assert np.abs(cp[1:].sum(2) - mm["codon"][:-1]).max() <= ta
+    assert np.abs(cp[1:].sum(1) - mm["codon"][1:]).max() <= ta
 
 
 def test_codon_marginals_against_clamped_oracle_900nt(full):
     """Two codon marginals by their definition: a clamped partition function."""
-    prob, en, ref_lz, h32, h64, m32, m64 = full
+    prob, en, ref, h32, h64, m32, m64 = full
+    ref_lz = ref["logz"]
     rng = np.random.default_rng(3)
     for _ in range(2):
         a = int(rng.integers(prob.m))
@@ -71,7 +98,7 @@ def test_codon_marginals_against_clamped_oracle_900nt(full):
 
 
 def test_finite_differences_900nt_fp64(full):
-    prob, en, ref_lz, h32, h64, m32, m64 = full
+    prob, en, ref, h32, h64, m32, m64 = full
     rng = np.random.default_rng(int(I.Stream(1003, I.TAG_FD).u64() % 2**32))
     hh = 1e-4
     for _ in range(32):
@@ -98,13 +125,16 @@ def test_finite_differences_900nt_fp64(full):
 
 
 def test_samples_900nt(full):
-    prob, en, ref_lz, h32, h64, m32, m64 = full
+    """1000 FP32 samples: every pair table is a valid structure of allowed
+    pairs, and the sampled codon, pair and unpaired frequencies agree with the
+    oracle's probabilities (5 sigma plus 3 counts of slack for rare events,
+    whose counts are discrete)."""
+    prob, en, ref, h32, h64, m32, m64 = full
     N = 1000
     cod, pairs = B.cdz_sample(h32, prob, I.sampler_seed(3), N)
     assert cod.shape == (N, prob.m) and pairs.shape == (N, prob.n)
     n = prob.n
-    # every pair table is a valid non-crossing structure of allowed pairs
-    for k in range(0, N, 50):
+    for k in range(N):
         pt = pairs[k]
         stack = []
         for i in range(n):
@@ -113,6 +143,7 @@ def test_samples_900nt(full):
                 continue
             assert pt[j] == i
             if j > i:
+                assert j - i >= 4
                 stack.append(j)
             else:
                 assert stack and stack[-1] == i
@@ -120,6 +151,25 @@ def test_samples_900nt(full):
     freq = np.zeros((prob.m, 6))
     for a in range(prob.m):
         freq[a] = np.bincount(cod[:, a], minlength=6)[:6] / N
-    p = np.clip(m32["codon"], 0, 1)
-    # 5 sigma plus 3 counts of slack: rare codons (N p << 1) are discrete
+    p = np.clip(ref["codon"], 0, 1)
     assert np.all(np.abs(freq - p) <= 5 * np.sqrt(p * (1 - p) / N) + 3.0 / N)
+    # pair frequencies (diagonal: unpaired) against the oracle's pair matrix
+    F = np.zeros((n, n))
+    rows = np.repeat(np.arange(n)[None, :], N, 0)
+    part = np.where(pairs >= 0, pairs, rows)
+    np.add.at(F, (rows.ravel(), part.ravel()), 1.0)
+    F /= N
+    Pr = np.clip(ref["pair"], 0, 1)
+    dev = np.abs(F - Pr) - (5 * np.sqrt(Pr * (1 - Pr) / N) + 3.0 / N)
+    print("pair frequency: worst excess", dev.max(), flush=True)
+    assert dev.max() <= 0
+    # pair types are allowed at the sampled codons: the base of each
+    # position follows from its residue's sampled codon
+    base = np.array([[oracle.slot_base(prob.prot[p // 3], int(cod[k, p // 3]), p % 3) for p in range(n)]
+                     for k in range(0, N, 100)])
+    ok = {(0, 3), (3, 0), (1, 2), (2, 1), (2, 3), (3, 2)}
+    for r, k in enumerate(range(0, N, 100)):
+        for i in range(n):
+            j = pairs[k, i]
+            if j > i:
+                assert (base[r, i], base[r, j]) in ok
