@@ -68,7 +68,7 @@ typedef enum {
  *                       + mismatch[b(l+1)][b(k-1)][type(l,k)]
  *   multiloop: ml_a + ml_b*(inner branches + 1) + ml_c*(unpaired bases)
  *   exterior loop: 0.  Hairpins need >= 3 unpaired bases; no pseudoknots.
- * The record is 199 doubles in exactly this field order. */
+ * The record is 229 doubles (36 + 3*31 + 96 + 4) in exactly this field order. */
 typedef struct {
   double stack[6][6];
   double hairpin[31];
@@ -94,6 +94,9 @@ typedef struct {
   const double *theta2;
 } cdz_problem;
 
+/* There is no autotuning option: every cell of every diagonal runs the same
+ * work shape (one workgroup per cell, a fixed number of waves per SIMD), so
+ * no tile or schedule choice is left to search. */
 typedef struct {
   cdz_precision prec;
   size_t mem_budget_bytes; /* 0 = unlimited; else the device workspace stays
@@ -133,8 +136,8 @@ cdz_status cdz_marginals(cdz_handle *h, const cdz_problem *prob, double *log_z,
 cdz_status cdz_sample(cdz_handle *h, const cdz_problem *prob, uint64_t seed,
                       int32_t n_samples, uint8_t *codons, int32_t *pairs);
 
-/* Batched forms (Section 3a's design problems come in sets of proteins of
- * uneven length): `count` problems on one handle.  The batch is split, in
+/* Batched forms (batching is this library's own; the paper treats one
+ * protein at a time): `count` problems of uneven length on one handle.  The batch is split, in
  * order, into chunks whose device workspaces together fit the budget
  * (options.mem_budget_bytes, else 90% of the free device memory less 1 GiB);
  * inside a chunk one launch per diagonal index runs that diagonal of every
@@ -191,16 +194,23 @@ enum { CDZ_WS_FORWARD = 0, CDZ_WS_MARGINALS = 1, CDZ_WS_MARGINALS_MIN = 2, CDZ_W
 cdz_status cdz_workspace_bytes(cdz_handle *h, const cdz_problem *prob, int32_t what, size_t *bytes);
 
 /* Device-pointer form of the forward pass for callers that keep the weights
- * on the device (PyTorch): theta1_dev [n_aa][6], theta2_dev [n_aa][6][6] or
+ * on the device (PyTorch), whose reverse mode (cdz_backward_dev) gives the
+ * codon marginals as d log Z / d theta (Section 4c, eq. codon-marginal: the
+ * codon probability is the derivative of log Z with respect to the log weight
+ * on the codon's middle base).  theta1_dev [n_aa][6], theta2_dev [n_aa][6][6] or
  * NULL, doubles in device memory.  log_z is a host pointer.  The stream is the
  * handle's stream. */
 cdz_status cdz_forward_dev(cdz_handle *h, int32_t n_aa, const char *aa,
                            const double *theta1_dev, const double *theta2_dev,
                            double *log_z);
 
-/* Adjoint of cdz_forward_dev: writes d(log Z)/d theta1 [n_aa][6] and
- * d(log Z)/d theta2 [n_aa][6][6] (device doubles; theta2 grad may be NULL),
- * each scaled by grad_logz.  Needs the forward of the same problem. */
+/* Adjoint of cdz_forward_dev (Section 4c, eq. codon-marginal): writes
+ * d(log Z)/d theta1 [n_aa][6] and d(log Z)/d theta2 [n_aa][6][6] (device
+ * doubles; theta2 grad may be NULL), each scaled by grad_logz, for the
+ * problem of the forward pass the handle holds now (a later call on another
+ * problem replaces it: call cdz_forward_dev again first, which is free when
+ * the handle already holds that problem).  CDZ_ERR_STATE without a forward
+ * pass; CDZ_ERR_NUMERIC if the adjoint left the floating-point range. */
 cdz_status cdz_backward_dev(cdz_handle *h, double grad_logz, double *dtheta1_dev,
                             double *dtheta2_dev);
 

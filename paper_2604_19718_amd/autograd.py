@@ -24,16 +24,22 @@ class CdzLogZ(torch.autograd.Function):
         t2 = None if theta2 is None else theta2.detach().to(torch.float64).contiguous()
         logz = B.cdz_forward_dev(handle, aa, t1.data_ptr(), 0 if t2 is None else t2.data_ptr())
         ctx.handle = handle
-        ctx.has_t2 = t2 is not None
-        ctx.m = len(aa)
+        ctx.aa = aa
+        # the weights of this node: the handle keeps only its last forward
+        # pass, which another apply() may have replaced before backward runs
+        ctx.t1 = t1.clone()
+        ctx.t2 = None if t2 is None else t2.clone()
         ctx.dev = theta1.device
         return torch.tensor(logz, dtype=torch.float64, device=theta1.device)
 
     @staticmethod
     def backward(ctx, grad):
-        m = ctx.m
+        m = len(ctx.aa)
+        t2 = ctx.t2
+        # make the handle hold this node's forward pass (free when it already does)
+        B.cdz_forward_dev(ctx.handle, ctx.aa, ctx.t1.data_ptr(), 0 if t2 is None else t2.data_ptr())
         d1 = torch.empty((m, 6), dtype=torch.float64, device=ctx.dev)
-        d2 = torch.empty((m, 6, 6), dtype=torch.float64, device=ctx.dev) if ctx.has_t2 else None
+        d2 = torch.empty((m, 6, 6), dtype=torch.float64, device=ctx.dev) if t2 is not None else None
         B.cdz_backward_dev(ctx.handle, float(grad), d1.data_ptr(), 0 if d2 is None else d2.data_ptr())
         return d1, d2, None, None
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libcdz.so")
 
 CDZ_FP32_SCALED = 0
 CDZ_FP64 = 1
+ENERGY_LEN = 229  # doubles in the cdz_energy record
 STATUS = ["CDZ_OK", "CDZ_ERR_ARG", "CDZ_ERR_PROTEIN", "CDZ_ERR_NUMERIC", "CDZ_ERR_NOMEM",
           "CDZ_ERR_BUDGET", "CDZ_ERR_HIP", "CDZ_ERR_STATE"]
 EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_sample",
@@ -89,8 +90,14 @@ def lib():
                                   ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_workspace_bytes": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+            # test hooks of include/cdz_debug.h
             "cdz_debug_al_k": ([vp], ctypes.c_int),
             "cdz_debug_force_al_k": ([vp, ctypes.c_int], ctypes.c_int),
+            "cdz_debug_set_span": ([vp, ctypes.c_int], ctypes.c_int),
+            "cdz_debug_landscape_retries": ([vp], ctypes.c_int),
+            "cdz_debug_set_low_exp": ([vp, ctypes.c_int], ctypes.c_int),
+            "cdz_debug_copy": ([vp, ctypes.c_int, vp, ctypes.c_size_t,
+                                ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             if hasattr(L, name):
@@ -135,8 +142,10 @@ class Handle:
 
 
 def cdz_create(energy, prec: str = "fp32", mem_budget_bytes: int = 0, stream: int = 0) -> Handle:
-    """energy: an object with .packed() (199 doubles in cdz_energy order)."""
+    """energy: an object with .packed() (229 doubles in cdz_energy order)."""
     buf = np.ascontiguousarray(energy.packed(), np.float64)
+    if buf.shape != (ENERGY_LEN,):
+        raise ValueError(f"energy record must be {ENERGY_LEN} doubles, got shape {buf.shape}")
     opts = cdz_options(CDZ_FP64 if prec == "fp64" else CDZ_FP32_SCALED, mem_budget_bytes,
                        ctypes.c_void_p(stream) if stream else None)
     out = ctypes.c_void_p()

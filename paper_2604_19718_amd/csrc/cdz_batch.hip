@@ -169,18 +169,26 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
     for (int b = 0; b < cnt; b++) HIPCHK(h, hipMemsetAsync(C.D[b].maxb, 0, (n[b] + 1) * sizeof(unsigned), st));
     s = fwd_pass<T>(h, dP, (const int *)(dev + oEx), Lex, shm);
     if (s != CDZ_OK) return s;
-    hipLaunchKernelGGL(cdz_spread_check_batch<T>, dim3(Lsp.total(0)), dim3(CDZ_NT), 0, st, dP,
-                       (const int *)(dev + oSp), cnt);
     HIPCHK(h, hipGetLastError());
-    for (int b = 0; b < cnt; b++)
-      HIPCHK(h, hipMemcpyAsync(&C.res[(size_t)b * 8], C.D[b].res, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(h, hipStreamSynchronize(st));
-    // problems whose cells came too close to FP32 underflow: landscape of the
-    // exact pass, then the exact pass once more
+  } else {
+    s = fwd_pass<T>(h, dP, (const int *)(dev + oEx), Lex, shm);
+    if (s != CDZ_OK) return s;
+  }
+  // range check of every exact pass: flags res[5] (weak cell), res[6]
+  // (non-finite entry); FP32 problems with weak cells repeat the pass once
+  // with the landscape of the exact pass and are checked again
+  hipLaunchKernelGGL(cdz_spread_check_batch<T>, dim3(Lsp.total(0)), dim3(CDZ_NT), 0, st, dP,
+                     (const int *)(dev + oSp), cnt);
+  HIPCHK(h, hipGetLastError());
+  for (int b = 0; b < cnt; b++)
+    HIPCHK(h, hipMemcpyAsync(&C.res[(size_t)b * 8], C.D[b].res, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  h->landscape_retries = 0;
+  if (fp32) {
     std::vector<DevProb<T>> R;
     std::vector<int> rn;
     for (int b = 0; b < cnt; b++)
-      if (C.res[(size_t)b * 8 + 5] != 0.0) {
+      if (C.res[(size_t)b * 8 + 5] != 0.0 && C.res[(size_t)b * 8 + 6] == 0.0) {
         R.push_back(C.D[b]);
         rn.push_back(n[b]);
       }
@@ -188,21 +196,25 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
     if (!R.empty()) {
       const int rc = (int)R.size();
       const Launches Lr = fwd_launches(rn, rn);
+      const Launches Lrs(rc, 1, [&](int k, int) { return rn[k]; });
       Meta mr;
       const size_t rP = mr.put(R.data(), rc * sizeof(DevProb<T>));
       const size_t rO = mr.put(Lr.off.data(), Lr.off.size() * sizeof(int));
+      const size_t rS = mr.put(Lrs.off.data(), Lrs.off.size() * sizeof(int));
       s = meta_upload(h, mr, &dev);
       if (s != CDZ_OK) return s;
       const DevProb<T> *dR = (const DevProb<T> *)(dev + rP);
       hipLaunchKernelGGL(cdz_landscape_batch<T>, dim3(rc), dim3(1024), 0, st, dR);
-      for (int k = 0; k < rc; k++) HIPCHK(h, hipMemsetAsync(R[k].maxb, 0, (rn[k] + 1) * sizeof(unsigned), st));
+      for (int k = 0; k < rc; k++) {
+        HIPCHK(h, hipMemsetAsync(R[k].maxb, 0, (rn[k] + 1) * sizeof(unsigned), st));
+        HIPCHK(h, hipMemsetAsync(R[k].res + 5, 0, 2 * sizeof(double), st));
+      }
       s = fwd_pass<T>(h, dR, (const int *)(dev + rO), Lr, shm);
       if (s != CDZ_OK) return s;
+      hipLaunchKernelGGL(cdz_spread_check_batch<T>, dim3(Lrs.total(0)), dim3(CDZ_NT), 0, st, dR,
+                         (const int *)(dev + rS), rc);
+      HIPCHK(h, hipGetLastError());
     }
-  } else {
-    h->landscape_retries = 0;
-    s = fwd_pass<T>(h, dP, (const int *)(dev + oEx), Lex, shm);
-    if (s != CDZ_OK) return s;
   }
   HIPCHK(h, hipEventRecord(h->ev[1], st));
   for (int b = 0; b < cnt; b++)
@@ -213,6 +225,13 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
   h->times[0] += ms;
   for (int b = 0; b < cnt; b++) {
     const double *r = &C.res[(size_t)b * 8];
+    if (r[6] != 0.0)
+      return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite entries in the forward pass of a batch member (" +
+                                              std::string(fp32 ? "FP32-scaled" : "FP64") + " range exceeded)");
+    if (r[5] != 0.0)
+      return cdz_fail(h, CDZ_ERR_NUMERIC, "cells of the forward pass of a batch member fell below 2^-" +
+                                              std::to_string(C.D[b].lowExp) + " (" +
+                                              std::string(fp32 ? "FP32-scaled" : "FP64") + " range exceeded)");
     if (!std::isfinite(r[0]) || !std::isfinite(r[1]))
       return cdz_fail(h, CDZ_ERR_NUMERIC, "log Z not finite (scaling out of range)");
   }
@@ -358,7 +377,7 @@ cdz_status run_batch(cdz_handle *h, const std::vector<HostTables> &tabs, int32_t
       memset(&D, 0, sizeof(D));
       memset(&A, 0, sizeof(A));
       carve<T>((char *)h->ws + at, tabs[b], D, A, adjoint, CDZ_AL_RESIDENT);
-      D.lowExp = h->low_exp;
+      D.lowExp = spread_low(h->low_exp, sizeof(T) == 4);
       at += need[b];
       cdz_status s = upload<T>(h, tabs[b], D);
       if (s != CDZ_OK) return s;

@@ -66,7 +66,8 @@ struct DevProb {
   T *ALs, *ALw;
   const T *ALp;
   int alK, alTop, alSlots;
-  int lowExp;              // FP32 spread check: a cell below 2^-lowExp repeats the pass
+  int lowExp;              // range check: a cell whose largest entry is below 2^-lowExp
+                           // (zero included) is too weak (FP32: the pass is repeated once)
   int *E;                  // [n + 1] diagonal exponents
   unsigned *maxb;          // [n + 1] float bits of max |entry| per diagonal
   double *Z5;              // [n][6] prefix exterior partition function
@@ -74,7 +75,9 @@ struct DevProb {
   double *Z3;              // [n][6] suffix exterior partition function
   int *H3;                 // [n]
   int *Cl;                 // [n] landscape exponents C[p] (FP32 mode)
-  double *res;             // [8] results: log Z (prefix), log Z (suffix), EZ, ...
+  double *res;             // [8] results: [0] log Z~ (prefix), [1] log Z~ (suffix), [2] EZ,
+                           // [3] landscape exponent sum, [5] weak cell found, [6] non-finite
+                           // entry found (range check flags)
 };
 
 __device__ __forceinline__ int cdz_ptype(int x, int y) {
@@ -86,16 +89,21 @@ __device__ __forceinline__ int cdz_ptype(int x, int y) {
   return t == 15 ? -1 : t;
 }
 
+// 2^e as a scale factor between diagonals.  Below the smallest subnormal the
+// factor is 0 (the term is then below the precision of the cell it feeds,
+// whose top sits near 2^0).  Above the largest finite power the factor is
+// +inf, never a clamped value: the cell becomes non-finite, which the range
+// check after the pass reports as CDZ_ERR_NUMERIC instead of a wrong sum.
 template <typename T>
 __device__ __forceinline__ T cdz_p2(int e);
 template <>
 __device__ __forceinline__ float cdz_p2<float>(int e) {
-  e = e > 127 ? 127 : e;
+  if (e > 127) return __int_as_float(0x7f800000);
   return e < -149 ? 0.0f : ldexpf(1.0f, e);
 }
 template <>
 __device__ __forceinline__ double cdz_p2<double>(int e) {
-  e = e > 1023 ? 1023 : e;
+  if (e > 1023) return __longlong_as_double(0x7ff0000000000000ll);
   return e < -1074 ? 0.0 : ldexp(1.0, e);
 }
 

@@ -571,9 +571,10 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
       const int q = tid % 36, g = tid / 36, r = q / 6, c = q % 6;
       T gacc = 0;
       for (int side = 0; side < 2; side++) {
-        // e blocks (contiguous in D.e), then the Qb blocks of the inner pairs,
-        // the left side's column strip as contiguous rows of Qbt placed by the
-        // window map, into blocks cleared first
+        // e blocks (contiguous in D.e), then the Qb blocks of the inner pairs:
+        // the left side's column strip as contiguous rows of Qbt, the right
+        // side's row strip as one contiguous row segment of Qb, each placed by
+        // the window map of its side into blocks cleared first
         // e_{k-1}, k = i+1+l (left: positions i+1..i+lmax) / e_l, l = j-1-l2
         // (right: positions j-2 down to j-1-lmax), block l-1
         if (side == 0) cdz_copy_blocks<T>(EB, D.e + (long long)(i + 1) * 36, lmax, false);
@@ -586,10 +587,12 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
             const int c = idx / K, k = idx % K + o, l = C.mapL[k], x = k - (lp_P[l] - lp_P[0]);
             QB[(l - 1) * 36 + x * 6 + c] = D.Qbt[(long long)(Pm + c) * ld + lp_P[0] + k];
           }
-        } else {  // Qb[i+1][j-1-l]
-          for (int idx = tid; idx < lmax * 36; idx += CDZ_NT) {
-            const int b = idx / 36, qq = idx % 36, rr = qq / 6, cc = qq % 6, l = b + 1;
-            if (rr < d1 && cc < rp_d[l]) QB[(l - 1) * 36 + qq] = D.Qb[(long long)(P1 + rr) * ld + rp_P[l] + cc];
+        } else if (lmax >= 1) {  // Qb[i+1][j-1-l] = row P1 + r of Qb, states of positions
+                                 // j-1-lmax..j-2, placed by the right window map
+          const int baseR = rp_P[lmax], K = rp_P[1] + rp_d[1] - baseR;
+          for (int idx = tid; idx < d1 * K; idx += CDZ_NT) {
+            const int r = idx / K, k = idx % K, l = C.mapR[k], c = k - (rp_P[l] - baseR);
+            QB[(l - 1) * 36 + r * 6 + c] = D.Qb[(long long)(P1 + r) * ld + baseR + k];
           }
         }
         cdz_sync();
@@ -964,25 +967,33 @@ __device__ __forceinline__ void landscape_body(const DevProb<T> &D) {
   if (threadIdx.x == 0) D.res[3] += D.Cl[n - 1];
 }
 
-// After the exact pass: is the largest entry of some cell of diagonal dl below
-// 2^-lowExp (close to FP32 underflow; the diagonal's top sits near 2^0)?
-// Then res[5] = 1 (the pass is repeated with the landscape of the exact pass).
+// Range check after the exact pass, over the cells of diagonal dl:
+//   res[5] = 1 if the largest entry of some cell lies below 2^-lowExp, zero
+//          included (the unpaired run U of every cell is positive in exact
+//          arithmetic, so an all-zero cell has underflowed); FP32 then
+//          repeats the pass once with the landscape of the exact pass
+//   res[6] = 1 if some entry is not finite (a scale factor overflowed)
 template <typename T>
 __device__ __forceinline__ void spread_check_body(const DevProb<T> &D, int dl) {
   const int n = D.n, ncell = n - dl;
   const long long ld = D.ld;
   T *const full[6] = {D.U, D.Qb, D.Qm1, D.Qm1p, D.QmX, D.Qm};
   const T low = (T)ldexp(1.0, -D.lowExp);
-  bool weak = false;
+  bool weak = false, bad = false;
   for (int i = threadIdx.x; i < ncell; i += CDZ_NT) {
     const int j = i + dl, di = D.d[i], dj = D.d[j], Pi = D.P[i], Pj = D.P[j];
     T m = 0;
     for (int a = 0; a < 6; a++)
       for (int r = 0; r < di; r++)
-        for (int c = 0; c < dj; c++) m = fmax(m, fabs(full[a][(long long)(Pi + r) * ld + Pj + c]));
-    weak = weak || (m > T(0) && m < low);
+        for (int c = 0; c < dj; c++) {
+          const T x = fabs(full[a][(long long)(Pi + r) * ld + Pj + c]);
+          bad = bad || !isfinite(x);
+          m = fmax(m, x);
+        }
+    weak = weak || !(m >= low);
   }
   if (__any(weak) && (threadIdx.x & 63) == 0) D.res[5] = 1.0;
+  if (__any(bad) && (threadIdx.x & 63) == 0) D.res[6] = 1.0;
 }
 
 // Recompute the interior-loop sums A of the cells of diagonal dl (>= 4) into

@@ -100,6 +100,10 @@ cdz_status cdz_fail(cdz_handle *h, cdz_status s, const std::string &msg) {
   return s;
 }
 
+// the ABI record is 229 doubles: stack 36, hairpin/bulge/interior 3 x 31,
+// mismatch 96, ml_a ml_b ml_c extrap 4
+static_assert(sizeof(cdz_energy) == 229 * sizeof(double), "cdz_energy must be 229 doubles");
+
 extern "C" const char *cdz_status_string(cdz_status s) {
   int k = (int)s;
   return (k >= 0 && k <= 7) ? kStatusText[k] : "unknown status";
@@ -280,7 +284,7 @@ size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool 
                 &D.Qm1p, &D.QmX, &D.Qm, &D.Qmt, &D.Ut, &D.DIt, &D.Qbt};
   for (T **a : arrs) *a = c.take<T>(base, S2);
   D.ldA = (long long)CDZ_NA * ld;
-  D.lowExp = CDZ_SPREAD_LOW;
+  D.lowExp = spread_low(0, sizeof(T) == 4);
   D.ALw = nullptr;
   D.ALp = nullptr;
   D.alK = alK;
@@ -381,6 +385,17 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   HIPCHK(h, hipEventRecord(h->ev[0], st));
   cdz_status s;
   double res[8];
+  // range check of the exact pass: flags res[5] (weak cell) and res[6]
+  // (non-finite entry), read back into res
+  auto range_check = [&]() -> cdz_status {
+    HIPCHK(h, hipMemsetAsync(D.res + 5, 0, 2 * sizeof(double), st));
+    hipLaunchKernelGGL(cdz_spread_check<T>, dim3(n), dim3(CDZ_NT), 0, st, D);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(res, D.res, sizeof(res), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    return CDZ_OK;
+  };
+  h->landscape_retries = 0;
   if (fp32) {
     // FP32: vertex factors rescaled to the free-energy landscape, estimated
     // from a pass truncated to short spans; then the exact pass, and once
@@ -393,21 +408,27 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
     hipLaunchKernelGGL(cdz_landscape<T>, dim3(1), dim3(1024), 0, st, D);
     s = forward_pass<T>(h, D, shm, h->profiling, n);
     if (s != CDZ_OK) return s;
-    hipLaunchKernelGGL(cdz_spread_check<T>, dim3(n), dim3(CDZ_NT), 0, st, D);
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipMemcpyAsync(res, D.res, sizeof(res), hipMemcpyDeviceToHost, st));
-    HIPCHK(h, hipStreamSynchronize(st));
-    h->landscape_retries = 0;
-    if (res[5] != 0.0) {
+    if ((s = range_check()) != CDZ_OK) return s;
+    if (res[5] != 0.0 && res[6] == 0.0) {
       h->landscape_retries = 1;
       hipLaunchKernelGGL(cdz_landscape<T>, dim3(1), dim3(1024), 0, st, D);
       s = forward_pass<T>(h, D, shm, false, n);
       if (s != CDZ_OK) return s;
+      if ((s = range_check()) != CDZ_OK) return s;
     }
   } else {
     s = forward_pass<T>(h, D, shm, h->profiling, n);
     if (s != CDZ_OK) return s;
+    if ((s = range_check()) != CDZ_OK) return s;
   }
+  if (res[6] != 0.0)
+    return cdz_fail(h, CDZ_ERR_NUMERIC, std::string("non-finite entries in the forward pass (") +
+                                            (fp32 ? "FP32-scaled" : "FP64") + " range exceeded)");
+  if (res[5] != 0.0)
+    return cdz_fail(h, CDZ_ERR_NUMERIC, std::string("cells of the forward pass fell below 2^-") +
+                                            std::to_string(D.lowExp) +
+                                            (fp32 ? " after the landscape was repeated (FP32 range exceeded)"
+                                                  : " (FP64 range exceeded)"));
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->ev[1], st));
   HIPCHK(h, hipMemcpyAsync(res, D.res, sizeof(res), hipMemcpyDeviceToHost, st));
@@ -472,7 +493,7 @@ static cdz_status forward_impl(cdz_handle *h, const HostTables &t, bool adjoint)
     h->ws_bytes = need;
   }
   carve<T>((char *)h->ws, t, D, A, adjoint, alK);
-  D.lowExp = h->low_exp;
+  D.lowExp = spread_low(h->low_exp, sizeof(T) == 4);
   h->al_k = alK;
   cdz_status s = upload<T>(h, t, D);
   if (s != CDZ_OK) return s;
@@ -563,7 +584,7 @@ extern "C" int cdz_debug_set_span(cdz_handle *h, int W) {
 }
 extern "C" int cdz_debug_landscape_retries(const cdz_handle *h) { return h ? h->landscape_retries : -1; }
 extern "C" int cdz_debug_set_low_exp(cdz_handle *h, int e) {
-  if (!h || e < 1 || e > 140) return CDZ_ERR_ARG;
+  if (!h || e < 0 || e > 1074) return CDZ_ERR_ARG;
   h->low_exp = e;
   h->have_fwd = false;
   return CDZ_OK;

@@ -21,10 +21,15 @@ inline int landscape_span(int n, int fixed) {
   if (fixed <= 0) W = W < 16 ? 16 : W > CDZ_LANDSCAPE_SPAN ? CDZ_LANDSCAPE_SPAN : W;
   return W < n - 1 ? W : n - 1;
 }
-// FP32 spread check: the exact pass is repeated with its own landscape when
-// the largest entry of some cell falls below 2^-CDZ_SPREAD_LOW (the top of the
-// diagonal sits near 2^0), i.e. within 6 octaves of the smallest normal float
+// Range check after the exact pass.  FP32: the pass is repeated once with its
+// own landscape when the largest entry of some cell falls below
+// 2^-CDZ_SPREAD_LOW (the top of the diagonal sits near 2^0), i.e. within 6
+// octaves of the smallest normal float; still weak after that, or any entry
+// not finite, the call returns CDZ_ERR_NUMERIC.  FP64 has no landscape: a
+// cell below 2^-CDZ_SPREAD_LOW_FP64 or a non-finite entry is an error.
 #define CDZ_SPREAD_LOW 120
+#define CDZ_SPREAD_LOW_FP64 1020
+inline int spread_low(int set, bool fp32) { return set > 0 ? set : fp32 ? CDZ_SPREAD_LOW : CDZ_SPREAD_LOW_FP64; }
 
 // Per-problem host tables (FP64), built before any device work.
 struct HostTables {
@@ -75,7 +80,7 @@ struct cdz_handle {
   int al_k = CDZ_AL_RESIDENT;  // storage of A chosen for the last forward (see carve)
   int al_k_forced = -2;        // test hook: storage of A to use regardless of budget (-2: by budget)
   int span = 0;                   // fixed span of the truncated landscape pass (0: by length)
-  int low_exp = CDZ_SPREAD_LOW;   // spread-check threshold exponent (FP32)
+  int low_exp = 0;                // range-check threshold exponent (0: by precision, spread_low)
   std::string err;
   void *ws = nullptr;
   size_t ws_bytes = 0;

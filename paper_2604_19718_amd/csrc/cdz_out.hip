@@ -667,8 +667,9 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       //      inner pair (i+1, j-1-l2), run j-l2..j-1.
       T *EL = X, *ER = X + 30 * 36, *QL = X + 60 * 36, *QR = X + 90 * 36;
       // e blocks (contiguous in D.e); the Qb blocks of the inner pairs, the
-      // left column strip as contiguous rows of Qbt placed by the window map,
-      // into blocks cleared first
+      // left column strip as contiguous rows of Qbt and the right row strip as
+      // one contiguous segment of a row of Qb, placed by the window maps into
+      // blocks cleared first
       cdz_window_maps(C.mapL, C.mapR, lp_d, lp_P, rp_d, rp_P, lmax);
       cdz_copy_blocks<T>(EL, D.e + (long long)(i + 1) * 36, lmax, false);       // e_{i+l}
       cdz_copy_blocks<T>(ER, D.e + (long long)(j - 1 - lmax) * 36, lmax, true);  // e_{j-1-l}
@@ -677,14 +678,15 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       cdz_sync();
       {
         const int oq = lp_P[1] - lp_P[0], KQ = lp_P[lmax + 1] - lp_P[1];  // positions i+2..i+1+lmax
+        const int baseR = rp_P[lmax], KR = rp_P[1] + rp_d[1] - baseR;     // positions j-1-lmax..j-2
         const int e1 = dm * KQ;
-        for (int idx = tid; idx < e1 + lmax * 36; idx += CDZ_NT) {
+        for (int idx = tid; idx < e1 + d1 * KR; idx += CDZ_NT) {
           if (idx < e1) {  // Qb[i+1+l][j-1](x, c): row Pm + c of Qbt
             const int c = idx / KQ, k = idx % KQ + oq, l = C.mapL[k], x = k - (lp_P[l] - lp_P[0]);
             QL[(l - 1) * 36 + x * 6 + c] = D.Qbt[(long long)(Pm + c) * ld + lp_P[0] + k];
-          } else {  // Qb[i+1][j-1-l], by blocks
-            const int t = idx - e1, b = t / 36, qq = t % 36, r = qq / 6, c = qq % 6, l = b + 1;
-            if (r < d1 && c < rp_d[l]) QR[(l - 1) * 36 + qq] = D.Qb[(long long)(P1 + r) * ld + rp_P[l] + c];
+          } else {  // Qb[i+1][j-1-l](r, c): row P1 + r of Qb
+            const int t = idx - e1, r = t / KR, k = t % KR, l = C.mapR[k], c = k - (rp_P[l] - baseR);
+            QR[(l - 1) * 36 + r * 6 + c] = D.Qb[(long long)(P1 + r) * ld + baseR + k];
           }
         }
       }
@@ -1340,6 +1342,8 @@ cdz_status assemble_marginals(cdz_handle *h, const HostTables &t, const double *
   const int n = t.n, m = t.m;
   std::vector<double> eta((size_t)n * 36);
   HIPCHK(h, hipMemcpy(eta.data(), eta_dev, eta.size() * 8, hipMemcpyDeviceToHost));
+  for (double x : eta)
+    if (!std::isfinite(x)) return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite edge marginals (outside pass out of range)");
   std::vector<double> cod((size_t)m * 6, 0.0);
   for (int a = 0; a < m; a++)
     for (int c = 0; c < t.d[3 * a]; c++) cod[a * 6 + c] = r * eta[(size_t)(3 * a) * 36 + c * 6 + c];
@@ -1359,6 +1363,10 @@ cdz_status assemble_marginals(cdz_handle *h, const HostTables &t, const double *
   }
   if (pair) {
     HIPCHK(h, hipMemcpy(pair, pair_dev, (size_t)n * n * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; i++)
+      for (int j = i + 1; j < n; j++)
+        if (!std::isfinite(pair[(size_t)i * n + j]))
+          return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite pair probabilities (outside pass out of range)");
     for (int i = 0; i < n; i++)
       for (int j = i + 1; j < n; j++) pair[(size_t)j * n + i] = pair[(size_t)i * n + j];
     for (int i = 0; i < n; i++) {
@@ -1397,6 +1405,13 @@ extern "C" cdz_status cdz_backward_dev(cdz_handle *h, double grad_logz, double *
   if (!h->have_fwd || !h->fwd_adjoint) return cdz_fail(h, CDZ_ERR_STATE, "no forward pass to differentiate");
   cdz_status s = outside(h);
   if (s != CDZ_OK) return s;
+  {
+    std::vector<double> eta((size_t)h->tables.n * 36);
+    HIPCHK(h, hipMemcpy(eta.data(), eta_dev(h), eta.size() * 8, hipMemcpyDeviceToHost));
+    for (double x : eta)
+      if (!std::isfinite(x))
+        return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite edge marginals (outside pass out of range)");
+  }
   const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz_scaled);
   hipLaunchKernelGGL(cdz_grad_theta, dim3(h->tables.m), dim3(64), 0, h->stream, eta_dev(h), d_dev(h),
                      h->tables.m, grad_logz * r, dtheta1_dev, dtheta2_dev);

@@ -8,8 +8,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "cdz.h")).read()
+def _declared(header="cdz.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(cdz_[a-z_0-9]+)\s*\(", src)))
 
@@ -27,8 +27,25 @@ def test_library_exports_every_declared_symbol():
     if not os.path.exists(B.LIB_PATH):
         pytest.skip("libcdz.so not built (run __graft_entry__.build())")
     L = ctypes.CDLL(B.LIB_PATH)
-    missing = [n for n in _declared() if not hasattr(L, n)]
+    missing = [n for n in _declared() + _declared("cdz_debug.h") if not hasattr(L, n)]
     assert not missing, missing
+
+
+def test_every_exported_symbol_is_declared():
+    """No undeclared entry points: each exported cdz_* symbol of the library is
+    declared in include/cdz.h (product) or include/cdz_debug.h (test hooks)."""
+    import subprocess
+    from paper_2604_19718_amd import binding as B
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libcdz.so not built (run __graft_entry__.build())")
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = sorted({ln.split()[-1] for ln in out.splitlines()
+                       if ln.split() and ln.split()[-1].startswith("cdz_") and " T " in ln})
+    declared = set(_declared()) | set(_declared("cdz_debug.h"))
+    undeclared = [n for n in exported if n not in declared]
+    assert not undeclared, undeclared
+    assert not set(_declared()) & set(_declared("cdz_debug.h"))
 
 
 def test_binding_names_match_the_abi():

@@ -67,3 +67,21 @@ def test_backward_without_forward_is_a_state_error():
     with pytest.raises(B.CdzError) as e:
         B.cdz_backward_dev(h, 1.0, d.data_ptr(), 0)
     assert e.value.status == 7
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_two_nodes_on_one_handle(prec):
+    """Two log Z nodes of different proteins on one handle, summed: the
+    handle keeps only the last forward pass, yet each node's gradient is its
+    own protein's codon and codon-pair marginals."""
+    pa, en = I.workload(2, m=30)
+    pb = I.Problem(I.protein(77, 24), I.theta1(77, I.protein(77, 24)), I.theta2(77, I.protein(77, 24)))
+    h = make_handle(en, prec)
+    a1, a2 = _t(pa.theta1), _t(pa.theta2)
+    b1, b2 = _t(pb.theta1), _t(pb.theta2)
+    (CdzLogZ.apply(a1, a2, h, pa.prot) + CdzLogZ.apply(b1, b2, h, pb.prot)).backward()
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    for p, g1, g2 in ((pa, a1, a2), (pb, b1, b2)):
+        ref = oracle.marginals(p, en)
+        assert np.abs(g1.grad.cpu().numpy() - ref["codon"]).max() <= tol
+        assert np.abs(g2.grad.cpu().numpy() - ref["codon_pair"]).max() <= tol
