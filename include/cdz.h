@@ -136,6 +136,23 @@ cdz_status cdz_marginals(cdz_handle *h, const cdz_problem *prob, double *log_z,
 cdz_status cdz_sample(cdz_handle *h, const cdz_problem *prob, uint64_t seed,
                       int32_t n_samples, uint8_t *codons, int32_t *pairs);
 
+/* cdz_sample for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same samples as cdz_sample with the same seed, drawn from the forward pass
+ * the handle already holds for this problem (CDZ_ERR_STATE otherwise: call
+ * cdz_partition or cdz_marginals on it first).  It allocates nothing: the
+ * sampler's device workspace is one fixed array of 32 MiB per device, held
+ * until the process ends, which needs per call
+ *   n_samples * (20 (n + 16) + 8 (max(n, 498) + 64) + 5 n + n_aa + 4) + 1536
+ * bytes (n = 3 n_aa; 1000 samples of 900 nt take 30.8 MB); a call needing
+ * more returns CDZ_ERR_BUDGET before any device work.  All calls on one
+ * device share that array and the next call overwrites it: calls that
+ * overlap on one device (other streams, handles or threads) race, and the
+ * caller must serialise them.  codons and pairs are host buffers laid out as
+ * in cdz_sample. */
+cdz_status cdz_sample_noalloc(cdz_handle *h, const cdz_problem *prob, uint64_t seed,
+                              int32_t n_samples, uint8_t *codons, int32_t *pairs);
+
 /* Batched forms (batching is this library's own; the paper treats one
  * protein at a time): `count` problems of uneven length on one handle.  The batch is split, in
  * order, into chunks whose device workspaces together fit the budget

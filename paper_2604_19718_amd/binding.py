@@ -20,7 +20,7 @@ CDZ_FP64 = 1
 ENERGY_LEN = 229  # doubles in the cdz_energy record
 STATUS = ["CDZ_OK", "CDZ_ERR_ARG", "CDZ_ERR_PROTEIN", "CDZ_ERR_NUMERIC", "CDZ_ERR_NOMEM",
           "CDZ_ERR_BUDGET", "CDZ_ERR_HIP", "CDZ_ERR_STATE"]
-EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_sample",
+EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_sample", "cdz_sample_noalloc",
            "cdz_forward_dev", "cdz_backward_dev", "cdz_last_timings", "cdz_reset",
            "cdz_set_profiling", "cdz_kernel_timings", "cdz_status_string", "cdz_last_error",
            "cdz_batch", "cdz_partition_batch", "cdz_marginals_batch", "cdz_sample_batch",
@@ -70,6 +70,8 @@ def lib():
             "cdz_marginals": ([vp, ctypes.POINTER(cdz_problem), _dp, _dp, _dp, _dp, _dp], ctypes.c_int),
             "cdz_sample": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_uint64, ctypes.c_int32,
                             ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "cdz_sample_noalloc": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_uint64, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_forward_dev": ([vp, ctypes.c_int32, ctypes.c_char_p, vp, vp, _dp], ctypes.c_int),
             "cdz_backward_dev": ([vp, ctypes.c_double, vp, vp], ctypes.c_int),
             "cdz_last_timings": ([vp, _dp], ctypes.c_int),
@@ -181,6 +183,17 @@ def cdz_sample(h: Handle, prob, seed: int, n_samples: int):
     h.check(lib().cdz_sample(h.ptr, ctypes.byref(p.c), ctypes.c_uint64(seed), n_samples,
                              cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                              pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return cod, pairs
+
+
+def cdz_sample_noalloc(h: Handle, prob, seed: int, n_samples: int):
+    p = _Prob(prob)
+    m, n = len(prob.prot), 3 * len(prob.prot)
+    cod = np.zeros((n_samples, m), np.uint8)
+    pairs = np.zeros((n_samples, n), np.int32)
+    h.check(lib().cdz_sample_noalloc(h.ptr, ctypes.byref(p.c), ctypes.c_uint64(seed), n_samples,
+                                     cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                     pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return cod, pairs
 
 

@@ -138,6 +138,11 @@ extern "C" cdz_status cdz_create(const cdz_energy *energy, const cdz_options *op
       delete h;
       return CDZ_ERR_HIP;
     }
+  // device address of the fixed scratch of cdz_sample_noalloc on this device
+  if (!noalloc_scratch(h->device)) {
+    delete h;
+    return CDZ_ERR_HIP;
+  }
   *out = h;
   return CDZ_OK;
 }

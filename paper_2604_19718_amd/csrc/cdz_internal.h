@@ -164,6 +164,13 @@ cdz_status sample_batch(cdz_handle *h, const std::vector<DevProb<T>> &Ds, uint64
 
 cdz_status cdz_fail(cdz_handle *h, cdz_status s, const std::string &msg);
 
+// Scratch of cdz_sample_noalloc: a file-scope device array of
+// CDZ_NOALLOC_SCRATCH_BYTES in cdz_sample.hip.  noalloc_scratch(dev) returns
+// its device address on device dev (resolved once per device with dev
+// current, by cdz_create), or nullptr if the address cannot be obtained.
+#define CDZ_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+void *noalloc_scratch(int device);
+
 // return CDZ_ERR_HIP from the enclosing function when a HIP call fails
 #define HIPCHK(h, x)                                                                          \
   do {                                                                                        \

@@ -23,6 +23,9 @@
 #include <cmath>
 #include <cstring>
 
+#include <map>
+#include <mutex>
+
 #include "cdz_internal.h"
 
 namespace {
@@ -799,19 +802,55 @@ __global__ __launch_bounds__(256) void cdz_sample_batch_kernel(const Smp<T> *S, 
   if (g < total) sample_one<T>(S[g / N], g % N);
 }
 
+// Device scratch of cdz_sample_noalloc, one copy per device for the life of
+// the process.  Host code never uses this name as an address: the per-device
+// address comes from hipGetSymbolAddress (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[CDZ_NOALLOC_SCRATCH_BYTES];
+
+void *noalloc_scratch(int device) {
+  static std::mutex mu;
+  static std::map<int, void *> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != device) return nullptr;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  addr[device] = ptr;
+  return ptr;
+}
+
+// bytes of sampler workspace for N samples of a sequence of n positions, m
+// residues (stacks, group sums, slots, codons, pairs, flags; 256-byte aligned)
+static size_t sample_ws_bytes(int n, int m, int N, int &cap, int &gcap) {
+  cap = n + 16;
+  gcap = (n > CDZ_NWIN + 2 ? n : CDZ_NWIN + 2) + 64;
+  return (size_t)N * cap * 5 * 4 + (size_t)N * gcap * 8 + (size_t)N * n + (size_t)N * m +
+         (size_t)N * n * 4 + (size_t)N * 4 + 6 * 256;
+}
+
+// ws == nullptr: the handle's workspace (grown with hipMalloc as needed);
+// else a caller-provided device buffer of ws_bytes (nothing is allocated)
 template <typename T>
 static cdz_status run_sample(cdz_handle *h, const DevProb<T> &D, uint64_t seed, int N,
-                             uint8_t *codons, int32_t *pairs) {
+                             uint8_t *codons, int32_t *pairs, char *ws = nullptr, size_t ws_bytes = 0) {
   const int n = D.n, m = D.m;
   Smp<T> S;
   S.D = D;
   S.seed = seed;
   S.nsamp = N;
-  S.cap = n + 16;
-  S.gcap = (n > CDZ_NWIN + 2 ? n : CDZ_NWIN + 2) + 64;
-  const size_t need = (size_t)N * S.cap * 5 * 4 + (size_t)N * S.gcap * 8 + (size_t)N * n +
-                      (size_t)N * m + (size_t)N * n * 4 + (size_t)N * 4 + 4096;
-  if (need > h->smp_bytes) {
+  const size_t need = sample_ws_bytes(n, m, N, S.cap, S.gcap);
+  if (ws) {
+    if (need > ws_bytes)
+      return cdz_fail(h, CDZ_ERR_BUDGET, std::to_string(N) + " samples of " + std::to_string(n) +
+                                             " nt need " + std::to_string(need) +
+                                             " bytes of scratch, above the " + std::to_string(ws_bytes) +
+                                             " bytes of cdz_sample_noalloc");
+  } else if (need > h->smp_bytes) {
     if (h->smp) (void)hipFree(h->smp);
     h->smp = nullptr;
     h->smp_bytes = 0;
@@ -821,7 +860,7 @@ static cdz_status run_sample(cdz_handle *h, const DevProb<T> &D, uint64_t seed, 
     }
     h->smp_bytes = need;
   }
-  char *p = (char *)h->smp;
+  char *p = ws ? ws : (char *)h->smp;
   auto take = [&](size_t b) {
     char *r = p;
     p += (b + 255) / 256 * 256;
@@ -932,6 +971,27 @@ template cdz_status sample_batch<float>(cdz_handle *, const std::vector<DevProb<
                                         int32_t *);
 template cdz_status sample_batch<double>(cdz_handle *, const std::vector<DevProb<double>> &, uint64_t, int,
                                          uint8_t *, int32_t *);
+
+// cdz_sample without device allocation: the forward pass must already be in
+// the handle, and the sampler's workspace is the fixed per-device scratch.
+extern "C" cdz_status cdz_sample_noalloc(cdz_handle *h, const cdz_problem *prob, uint64_t seed,
+                                         int32_t n_samples, uint8_t *codons, int32_t *pairs) {
+  if (!h || !prob) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
+  if (n_samples < 0) return cdz_fail(h, CDZ_ERR_ARG, "n_samples < 0");
+  if (n_samples > 0 && (!codons || !pairs)) return cdz_fail(h, CDZ_ERR_ARG, "null output");
+  HostTables t;
+  cdz_status s = build_tables(h, prob->n_aa, prob->aa, prob->theta1, prob->theta2, t);
+  if (s != CDZ_OK) return s;
+  if (!h->have_fwd || h->fwd_key != t.key)
+    return cdz_fail(h, CDZ_ERR_STATE, "cdz_sample_noalloc needs the forward pass of this problem in the handle "
+                                      "(call cdz_partition or cdz_marginals first)");
+  char *ws = (char *)noalloc_scratch(h->device);
+  if (!ws) return cdz_fail(h, CDZ_ERR_HIP, "scratch address of this device is not available");
+  if (n_samples == 0) return CDZ_OK;
+  return h->opt.prec == CDZ_FP64
+             ? run_sample<double>(h, h->pd, seed, n_samples, codons, pairs, ws, CDZ_NOALLOC_SCRATCH_BYTES)
+             : run_sample<float>(h, h->pf, seed, n_samples, codons, pairs, ws, CDZ_NOALLOC_SCRATCH_BYTES);
+}
 
 extern "C" cdz_status cdz_sample(cdz_handle *h, const cdz_problem *prob, uint64_t seed,
                                  int32_t n_samples, uint8_t *codons, int32_t *pairs) {
