@@ -581,7 +581,7 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
         else cdz_copy_blocks<T>(EB, D.e + (long long)(j - 1 - lmax) * 36, lmax, true);
         cdz_zero_blocks<T>(QB, lmax);
         cdz_sync();
-        if (side == 0) {  // Qb[i+1+l][j-1](x, c) = Qbt row Pm + c, states of positions i+2..i+1+lmax
+        if (side == 0 && lmax >= 1) {  // Qb[i+1+l][j-1](x, c) = Qbt row Pm + c, states of positions i+2..i+1+lmax
           const int o = lp_P[1] - lp_P[0], K = lp_P[lmax + 1] - lp_P[1];
           for (int idx = tid; idx < dm * K; idx += CDZ_NT) {
             const int c = idx / K, k = idx % K + o, l = C.mapL[k], x = k - (lp_P[l] - lp_P[0]);
