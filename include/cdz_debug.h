@@ -43,6 +43,12 @@ int cdz_debug_set_span(cdz_handle *h, int W);
  * within the range-check threshold; -1 for a null handle. */
 int cdz_debug_landscape_retries(const cdz_handle *h);
 
+/* Binary exponent of the largest entry of the weakest cell in the first
+ * and in the final range check of the last single-problem forward pass (the
+ * two differ when the FP32 pass was repeated; -1100 stands for a cell that is
+ * entirely zero).  CDZ_ERR_ARG for null arguments. */
+int cdz_debug_weakest(const cdz_handle *h, int *first, int *final_);
+
 /* Range-check threshold exponent e: a cell whose largest entry is below 2^-e
  * is too weak (0 = the default of the precision: 120 in FP32, 1020 in FP64).
  * Accepts 0..1074, else CDZ_ERR_ARG. */

@@ -98,6 +98,7 @@ def lib():
             "cdz_debug_set_span": ([vp, ctypes.c_int], ctypes.c_int),
             "cdz_debug_landscape_retries": ([vp], ctypes.c_int),
             "cdz_debug_set_low_exp": ([vp, ctypes.c_int], ctypes.c_int),
+            "cdz_debug_weakest": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "cdz_debug_copy": ([vp, ctypes.c_int, vp, ctypes.c_size_t,
                                 ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
         }

@@ -27,6 +27,8 @@ __global__ void cdz_fwd_diag_batch(const DevProb<T> *probs, const int *off, int 
 template <typename T>
 __global__ void cdz_exterior_trunc_batch(const DevProb<T> *probs, const int *W);
 template <typename T>
+__global__ void cdz_exterior_scan_batch(const DevProb<T> *probs, const int *W, const int *jend, int per);
+template <typename T>
 __global__ void cdz_landscape_batch(const DevProb<T> *probs);
 template <typename T>
 __global__ void cdz_spread_check_batch(const DevProb<T> *probs, const int *off, int count);
@@ -119,9 +121,7 @@ cdz_status fwd_pass(cdz_handle *h, const DevProb<T> *dP, const int *dOff, const 
 Launches fwd_launches(const std::vector<int> &n, const std::vector<int> &dlmax) {
   int nl = 0;
   for (int x : dlmax) nl = std::max(nl, x + 1);
-  return Launches((int)n.size(), nl, [&](int b, int dl) {
-    return dl <= dlmax[b] ? cdz_cells_grid(std::max(0, n[b] - dl)) + 1 : 0;
-  });
+  return Launches((int)n.size(), nl, [&](int b, int t) { return t <= dlmax[b] ? fwd_nblocks(n[b], t) : 0; });
 }
 
 // Forward passes of every problem of the chunk (the sequence of the
@@ -137,17 +137,25 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(nmax) + " nt exceeds the LDS layout of the forward kernel");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_fwd_diag_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)shm));
-  std::vector<int> n(cnt), W(cnt), full(cnt);
+  if (scan_lds_bytes(nmax) > (size_t)h->lds_max)
+    return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(nmax) + " nt exceeds the LDS layout of the exterior scan");
+  HIPCHK(h, hipFuncSetAttribute((const void *)cdz_exterior_scan_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)scan_lds_bytes(nmax)));
+  std::vector<int> n(cnt), W(cnt), full(cnt), Wm1(cnt), nm1(cnt);
   for (int b = 0; b < cnt; b++) {
     n[b] = C.t[b]->n;
     W[b] = landscape_span(n[b], h->span);
     full[b] = n[b];
+    Wm1[b] = W[b] - 1;  // truncated pass: prefix scan of the first W positions
+    nm1[b] = n[b] - 1;  // exact pass: pairs of every span, every position
   }
   const Launches Ltr = fwd_launches(n, W), Lex = fwd_launches(n, full);
   const Launches Lsp(cnt, 1, [&](int b, int) { return n[b]; });
   Meta m;
   const size_t oP = m.put(C.D.data(), cnt * sizeof(DevProb<T>));
   const size_t oW = m.put(W.data(), cnt * sizeof(int));
+  const size_t oWm1 = m.put(Wm1.data(), cnt * sizeof(int));
+  const size_t oNm1 = m.put(nm1.data(), cnt * sizeof(int));
   const size_t oTr = m.put(Ltr.off.data(), Ltr.off.size() * sizeof(int));
   const size_t oEx = m.put(Lex.off.data(), Lex.off.size() * sizeof(int));
   const size_t oSp = m.put(Lsp.off.data(), Lsp.off.size() * sizeof(int));
@@ -159,14 +167,20 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
   for (int b = 0; b < cnt; b++) {
     HIPCHK(h, hipMemsetAsync(C.D[b].res, 0, 8 * sizeof(double), st));
     HIPCHK(h, hipMemsetAsync(C.D[b].maxb, 0, (n[b] + 1) * sizeof(unsigned), st));
+    HIPCHK(h, hipMemsetAsync(C.D[b].E, 0, (n[b] + 1) * sizeof(int), st));
   }
   C.res.assign((size_t)cnt * 8, 0.0);
   if (fp32) {
     s = fwd_pass<T>(h, dP, (const int *)(dev + oTr), Ltr, shm);
     if (s != CDZ_OK) return s;
+    hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(cnt), dim3(CDZ_NT), scan_lds_bytes(nmax), st, dP,
+                       (const int *)(dev + oW), (const int *)(dev + oWm1), 1);
     hipLaunchKernelGGL(cdz_exterior_trunc_batch<T>, dim3(cnt), dim3(64), 0, st, dP, (const int *)(dev + oW));
     hipLaunchKernelGGL(cdz_landscape_batch<T>, dim3(cnt), dim3(1024), 0, st, dP);
-    for (int b = 0; b < cnt; b++) HIPCHK(h, hipMemsetAsync(C.D[b].maxb, 0, (n[b] + 1) * sizeof(unsigned), st));
+    for (int b = 0; b < cnt; b++) {
+      HIPCHK(h, hipMemsetAsync(C.D[b].maxb, 0, (n[b] + 1) * sizeof(unsigned), st));
+      HIPCHK(h, hipMemsetAsync(C.D[b].E, 0, (n[b] + 1) * sizeof(int), st));
+    }
     s = fwd_pass<T>(h, dP, (const int *)(dev + oEx), Lex, shm);
     if (s != CDZ_OK) return s;
     HIPCHK(h, hipGetLastError());
@@ -174,6 +188,8 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
     s = fwd_pass<T>(h, dP, (const int *)(dev + oEx), Lex, shm);
     if (s != CDZ_OK) return s;
   }
+  hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(2 * cnt), dim3(CDZ_NT), scan_lds_bytes(nmax), st, dP,
+                     (const int *)(dev + oNm1), (const int *)(dev + oNm1), 2);
   // range check of every exact pass: flags res[5] (weak cell), res[6]
   // (non-finite entry); FP32 problems with weak cells repeat the pass once
   // with the landscape of the exact pass and are checked again
@@ -201,16 +217,22 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
       const size_t rP = mr.put(R.data(), rc * sizeof(DevProb<T>));
       const size_t rO = mr.put(Lr.off.data(), Lr.off.size() * sizeof(int));
       const size_t rS = mr.put(Lrs.off.data(), Lrs.off.size() * sizeof(int));
+      std::vector<int> rm1(rc);
+      for (int k = 0; k < rc; k++) rm1[k] = rn[k] - 1;
+      const size_t rN = mr.put(rm1.data(), rc * sizeof(int));
       s = meta_upload(h, mr, &dev);
       if (s != CDZ_OK) return s;
       const DevProb<T> *dR = (const DevProb<T> *)(dev + rP);
       hipLaunchKernelGGL(cdz_landscape_batch<T>, dim3(rc), dim3(1024), 0, st, dR);
       for (int k = 0; k < rc; k++) {
         HIPCHK(h, hipMemsetAsync(R[k].maxb, 0, (rn[k] + 1) * sizeof(unsigned), st));
-        HIPCHK(h, hipMemsetAsync(R[k].res + 5, 0, 2 * sizeof(double), st));
+        HIPCHK(h, hipMemsetAsync(R[k].E, 0, (rn[k] + 1) * sizeof(int), st));
+        HIPCHK(h, hipMemsetAsync(R[k].res + 5, 0, 3 * sizeof(double), st));
       }
       s = fwd_pass<T>(h, dR, (const int *)(dev + rO), Lr, shm);
       if (s != CDZ_OK) return s;
+      hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(2 * rc), dim3(CDZ_NT), scan_lds_bytes(nmax), st, dR,
+                         (const int *)(dev + rN), (const int *)(dev + rN), 2);
       hipLaunchKernelGGL(cdz_spread_check_batch<T>, dim3(Lrs.total(0)), dim3(CDZ_NT), 0, st, dR,
                          (const int *)(dev + rS), rc);
       HIPCHK(h, hipGetLastError());

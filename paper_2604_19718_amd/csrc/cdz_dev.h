@@ -69,8 +69,10 @@ struct DevProb {
   int lowExp;              // range check: a cell whose largest entry is below 2^-lowExp
                            // (zero included) is too weak (FP32: the pass is repeated once)
   int *E;                  // [n + 1] diagonal exponents
+  int *EX;                 // [n + 5] provisional exponents of the split sums (forward)
   unsigned *maxb;          // [n + 1] float bits of max |entry| per diagonal
   double *Z5;              // [n][6] prefix exterior partition function
+  double *A5;              // [n][6] A[k] = Z5[k-1] e_{k-1} (prefix scan)
   int *G5;                 // [n]
   double *Z3;              // [n][6] suffix exterior partition function
   int *H3;                 // [n]
@@ -133,6 +135,29 @@ __device__ __forceinline__ float cdz_wave_max(float x) {
 #define CDZ_SPAN_MAX 512
 __host__ __device__ __forceinline__ int cdz_cells_grid(int ncell) {
   return (ncell + CDZ_NXCD - 1) / CDZ_NXCD * CDZ_NXCD;
+}
+// 16-byte rounding of LDS region sizes
+__host__ __device__ constexpr size_t lds_al(size_t b) { return (b + 15) / 16 * 16; }
+// dynamic LDS of the exterior scans: exponents, slot counts, offsets and the
+// running exponents of n + 1 positions, then FP64 reduction scratch and sums
+__host__ __device__ constexpr size_t scan_lds_bytes(int n) {
+  return lds_al((size_t)4 * (n + 1) * 4) + (4 * 6 + 8) * sizeof(double);
+}
+
+// Workgroups of forward launch t (t = 0..n-1) of a sequence of n positions,
+// in block order: window sums of diagonal t+1, bulge sums of diagonal t+1
+// (both for 4 <= t+1 < n), split of diagonal t+4 (9 <= t+4 < n), finish of
+// diagonal t.
+__host__ __device__ __forceinline__ void fwd_ranges(int n, int t, int r[4]) {
+  r[0] = t + 1 >= 4 && t + 1 < n ? cdz_cells_grid(n - t - 1) : 0;
+  r[1] = r[0];
+  r[2] = t + 4 >= 9 && t + 4 < n ? cdz_cells_grid(n - t - 4) : 0;
+  r[3] = t < n ? cdz_cells_grid(n - t) : 0;
+}
+__host__ __device__ __forceinline__ int fwd_nblocks(int n, int t) {
+  int r[4];
+  fwd_ranges(n, t, r);
+  return r[0] + r[1] + r[2] + r[3];
 }
 __device__ __forceinline__ int cdz_cell_of_block(int w, int ncell) {
   return (w % CDZ_NXCD) * ((ncell + CDZ_NXCD - 1) / CDZ_NXCD) + w / CDZ_NXCD;

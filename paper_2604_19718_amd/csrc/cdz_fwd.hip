@@ -17,184 +17,11 @@
 // inner pair of an interior loop), Qm1L (Qm1 with its left edge, in row and
 // column orientation), Qmt (Qm transposed), and G/F (the bulge and interior
 // loop sums of the cell, kept for the adjoint).
+#include <algorithm>
+
 #include "cdz_dev.h"
 
 namespace {
-
-template <typename T>
-__device__ int choose_exponent(const DevProb<T> &D, int dl, const int *sE) {
-  if (dl == 0) return 0;
-  float m1 = __uint_as_float(D.maxb[dl - 1]);
-  if (dl >= 2) {
-    float m2 = __uint_as_float(D.maxb[dl - 2]);
-    if (m1 > 0.f && m2 > 0.f) {
-      double L1 = sE[dl - 1] + log2((double)m1);
-      double L2 = sE[dl - 2] + log2((double)m2);
-      double slope = fmin(fmax(L1 - L2, -16.0), 16.0);
-      return (int)rint(L1 + slope);
-    }
-  }
-  if (m1 > 0.f) return (int)rint(sE[dl - 1] + log2((double)m1));
-  return sE[dl - 1];
-}
-
-// FP64 exterior loop, one step each way:
-//   Z5[j](t) = prefix [0..j] with slot t at j
-//   Z3[p](s) = suffix [p+1..n-1] given slot s at p, edge e_p included
-// Every term is evaluated by its own thread with fully unrolled slot loops,
-// so the loads of a step are issued together.
-template <typename T>
-__device__ void exterior_step(const DevProb<T> &D, int dl, const int *sE, double *red) {
-  const int n = D.n, tid = threadIdx.x;
-  const long long ld = D.ld;
-  double *tot = red + (CDZ_NT / 64) * 6;
-  // ---- prefix Z5[j], j = dl - 1
-  int j = dl - 1;
-  if (j == 0) {
-    if (tid < 6) D.Z5[tid] = tid < D.d[0] ? D.vd[tid] : 0.0;
-    if (tid == 0) D.G5[0] = 0;
-  } else if (j > 0 && j < n) {
-    const int R = D.G5[j - 1], dj = D.d[j], Pj = D.P[j];
-    double part[6] = {0, 0, 0, 0, 0, 0};
-    // item 0: j unpaired; item 1: 0 pairs j; item k >= 2: (k-1) pairs j
-    const int nit = j >= 3 ? j - 2 : 1;  // item 0 always; items 1.. need j >= 4
-    for (int it = tid; it < nit; it += CDZ_NT) {
-      if (it == 0) {
-        double z[6];
-#pragma unroll
-        for (int s = 0; s < 6; s++) z[s] = D.Z5[(j - 1) * 6 + s];
-#pragma unroll
-        for (int t = 0; t < 6; t++) {
-          double a = 0;
-#pragma unroll
-          for (int s = 0; s < 6; s++) a += z[s] * D.ed[(j - 1) * 36 + s * 6 + t];
-          part[t] += t < dj ? a * D.vd[j * 6 + t] : 0.0;
-        }
-      } else if (it == 1) {
-        if (j >= 4) {
-          const double sc = ldexp(1.0, sE[j] - R);
-          const int d0 = D.d[0];
-#pragma unroll
-          for (int t = 0; t < 6; t++) {
-            double a = 0;
-#pragma unroll
-            for (int x = 0; x < 6; x++)
-              if (x < d0 && t < dj) a += (double)D.Qb[x * ld + Pj + t];
-            part[t] += a * sc;
-          }
-        }
-      } else {
-        const int k = it - 1;  // 1 <= k <= j-4
-        const int dk = D.d[k], Pk = D.P[k];
-        const double sc = ldexp(1.0, D.G5[k - 1] + sE[j - k] - R);
-        double z[6];
-#pragma unroll
-        for (int s = 0; s < 6; s++) z[s] = D.Z5[(k - 1) * 6 + s];
-        // one slot x of k at a time (keeps the register count of the kernel low)
-#pragma unroll 1
-        for (int x = 0; x < dk; x++) {
-          double a = 0;
-#pragma unroll
-          for (int s = 0; s < 6; s++) a += z[s] * D.ed[(k - 1) * 36 + s * 6 + x];
-          a *= sc;
-#pragma unroll
-          for (int t = 0; t < 6; t++)
-            if (t < dj) part[t] += a * (double)D.Qb[(Pk + x) * ld + Pj + t];
-        }
-      }
-    }
-    cdz_block_sum<double, 6>(part, red, tot);
-    if (tid == 0) {
-      double mx = 0;
-      for (int t = 0; t < 6; t++) mx = fmax(mx, fabs(tot[t]));
-      const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
-      for (int t = 0; t < 6; t++) D.Z5[j * 6 + t] = t < dj ? ldexp(tot[t], -e) : 0.0;
-      D.G5[j] = R + e;
-    }
-    cdz_sync();
-  }
-  // ---- suffix Z3[p], p = n - 1 - dl
-  int p = n - 1 - dl;
-  if (p == n - 1) {
-    if (tid < 6) D.Z3[p * 6 + tid] = tid < D.d[p] ? 1.0 : 0.0;
-    if (tid == 0) D.H3[p] = 0;
-  } else if (p >= 0) {
-    const int R = D.H3[p + 1], dp = D.d[p], d1 = D.d[p + 1], P1 = D.P[p + 1];
-    double part[6] = {0, 0, 0, 0, 0, 0};
-    // item 0: p+1 unpaired; item it >= 1: p+1 pairs jj = p + 4 + it
-    const int nit = n - 5 - p >= 0 ? n - 4 - p : 1;  // item 0 always
-    for (int it = tid; it < nit; it += CDZ_NT) {
-      double w[6];
-      if (it == 0) {
-#pragma unroll
-        for (int t = 0; t < 6; t++) w[t] = D.vd[(p + 1) * 6 + t] * D.Z3[(p + 1) * 6 + t];
-      } else {
-        const int jj = p + 4 + it, dq = D.d[jj], Pq = D.P[jj];
-        const double sc = ldexp(1.0, sE[jj - p - 1] + D.H3[jj] - R);
-        double z3[6];
-#pragma unroll
-        for (int t = 0; t < 6; t++) z3[t] = D.Z3[jj * 6 + t];
-#pragma unroll 1
-        for (int x = 0; x < 6; x++) {
-          double a = 0;
-#pragma unroll
-          for (int t = 0; t < 6; t++)
-            if (x < d1 && t < dq) a += (double)D.Qb[(P1 + x) * ld + Pq + t] * z3[t];
-          w[x] = a * sc;
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < 6; s++) {
-        double a = 0;
-#pragma unroll
-        for (int x = 0; x < 6; x++) a += D.ed[p * 36 + s * 6 + x] * w[x];
-        part[s] += s < dp ? a : 0.0;
-      }
-    }
-    cdz_block_sum<double, 6>(part, red, tot);
-    if (tid == 0) {
-      double mx = 0;
-      for (int s = 0; s < 6; s++) mx = fmax(mx, fabs(tot[s]));
-      const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
-      for (int s = 0; s < 6; s++) D.Z3[p * 6 + s] = s < dp ? ldexp(tot[s], -e) : 0.0;
-      D.H3[p] = R + e;
-    }
-    cdz_sync();
-  }
-  // ---- totals after the last diagonal
-  if (dl == n) {
-    double part[2] = {0, 0};
-    const int nit = n >= 4 ? n - 3 : 1;  // item 0 always
-    for (int it = tid; it < nit; it += CDZ_NT) {
-      if (it == 0) {
-        double a = 0;
-#pragma unroll
-        for (int s = 0; s < 6; s++) a += D.vd[s] * D.Z3[s];
-        part[0] += a;
-      } else {
-        const int jj = 3 + it, dq = D.d[jj], Pq = D.P[jj], d0 = D.d[0];
-        double a = 0;
-#pragma unroll
-        for (int x = 0; x < 6; x++)
-#pragma unroll
-          for (int t = 0; t < 6; t++)
-            if (x < d0 && t < dq) a += (double)D.Qb[x * ld + Pq + t] * D.Z3[jj * 6 + t];
-        part[0] += a * ldexp(1.0, sE[jj] + D.H3[jj] - D.H3[0]);
-      }
-    }
-    cdz_block_sum<double, 2>(part, red, tot);
-    if (tid == 0) {
-      double z5 = 0;
-      for (int t = 0; t < 6; t++) z5 += D.Z5[(n - 1) * 6 + t];
-      const double L2 = 0.6931471805599453094;
-      const double lz5 = log(z5) + D.G5[n - 1] * L2;
-      const double lz3 = log(tot[0]) + D.H3[0] * L2;
-      D.res[0] = lz5;
-      D.res[1] = lz3;
-      D.res[2] = rint(lz5 / L2);  // EZ, the adjoint scale exponent
-    }
-  }
-}
 
 }  // namespace
 
@@ -219,24 +46,14 @@ struct CellStage {
   unsigned char mapL[192], mapR[192];  // state offset -> position index (window staging)
 };
 
-// Blocks of 36 values staged for the loops closed by a cell (after the stage)
+// Blocks of 36 values of the window kind (a_window: runs U[i+1][i+l] 30,
+// U[j-l][j-1] 30, DI strips 29 + 28, A of the inner cell 27, A of the cell
+// for L = 2..30 29) and of the bulge kind (runs 2 x 30, edges 2 x 30, inner
+// pairs 2 x 30)
 #define CDZ_FWD_WBLK 173
+#define CDZ_BUL_BLK 180
 
-template <typename T>
-size_t fwd_lds_bytes(int n) {
-  const size_t head = ((size_t)(n + 1) * 4 + 15) / 16 * 16 + (size_t)((CDZ_NT / 64) * 72) * sizeof(T);
-  const size_t st = (sizeof(CellStage<T>) + 15) / 16 * 16;
-  return head + st + (size_t)CDZ_FWD_WBLK * 36 * sizeof(T);
-}
-template size_t fwd_lds_bytes<float>(int);
-template size_t fwd_lds_bytes<double>(int);
 
-template <typename T>
-__device__ __forceinline__ void stage_block(T *dst, const T *A, long long ld, int r0, int c0, int dr,
-                                            int dc, int q) {
-  const int r = q / 6, c = q % 6;
-  dst[q] = (r < dr && c < dc) ? A[(long long)(r0 + r) * ld + c0 + c] : T(0);
-}
 
 // Interior-loop sums A(i,j,L), L = 2..lmax, of cell (i, j) into AC by the
 // loop-size recursion, staging on the way UR1 = U[i+1][i+l] and UC1 =
@@ -380,291 +197,452 @@ __device__ __forceinline__ void a_store(const DevProb<T> &D, const CellStage<T> 
   }
 }
 
-// One cell (or the exterior step) of diagonal dl; blk is the workgroup's index
-// among the workgroups of this problem's diagonal.
-template <typename T>
-__device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1]
-  T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(D.n + 1) * 4 + 15) / 16 * 16);
-  CellStage<T> &C = *reinterpret_cast<CellStage<T> *>(red + (CDZ_NT / 64) * 72);
-  T *W = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(CellStage<T>) + 15) / 16 * 16);
-  const int n = D.n, tid = threadIdx.x;
-  const long long ld = D.ld;
-  cdz_copy_ints(sE, D.E, dl < n + 1 ? dl : n + 1);
-  cdz_sync();
-  const int Ed = choose_exponent(D, dl, sE);
-  if (tid == 0) sE[dl] = Ed;
-  if (blk == 0 && tid == 0) D.E[dl] = Ed;
-  cdz_sync();
-  const int ncell = n - dl > 0 ? n - dl : 0;
-  if (blk == cdz_cells_grid(ncell)) {
-    exterior_step<T>(D, dl, sE, reinterpret_cast<double *>(red));
-    return;
-  }
-  const int i = cdz_cell_of_block(blk, ncell), j = i + dl;
-  if (i >= ncell) return;
+// ---------------------------------------------------------------------------
+// One launch per step t = 0..n.  The work of a diagonal is split by what it
+// reads, and each piece runs in the earliest launch where its inputs are
+// final, as its own workgroups; the pieces of one launch never read each
+// other's results:
+//   window   (diagonal t+1)  interior-loop sums by size A(i,j,L) and F: reads
+//                            U, DI and A of diagonals <= t-1
+//   bulges   (diagonal t+1)  bulge sums G: reads Qb of diagonals <= t-2
+//   split    (diagonal t+4)  QmX, the O(n) multiloop split: reads Qm and Qm1L
+//                            of diagonals <= t-1; stored under a provisional
+//                            exponent EX[t+4] that the finish converts
+//   finish   (diagonal t)    U, Qb, Qm1, DI, Qm1L, Qm1p, QmX, Qm of every cell:
+//                            O(1) blocks of diagonals t-1, t-2 and the sums
+//                            above
+// The FP64 exterior loops run after the last launch (exterior_scan_body).
+// Exponents.  E[t+1] and EX[t+4] are chosen in launch t from the maxima of
+// the last complete diagonals, extrapolated; every workgroup of the launch
+// that needs them computes the same values and the first finish workgroup
+// stores them.  E[0] = 0 (set by the host).
+// ---------------------------------------------------------------------------
 
-  // ---- stage: positions i-1, i, i+1, j-1, j, j+1 (clamped; unused when absent)
+// Exponent for diagonal `target`, chosen in launch t (t >= 0): the log2 of
+// the largest entry of diagonal t-1, extrapolated with the growth per
+// diagonal averaged over diagonals t-5..t-1 (over t-2..t-1 early on), so that
+// the short, irregular diagonals at the start do not make it overshoot
+template <typename T>
+__device__ __forceinline__ int exponent_ahead(const DevProb<T> &D, int t, int target) {
+  if (t <= 0) return 0;
+  const int E1 = D.E[t - 1];
+  const float m1 = __uint_as_float(D.maxb[t - 1]);
+  if (!(m1 > 0.f)) return E1;
+  const double L1 = E1 + log2((double)m1);
+  double slope = 0;
+  const int back = t >= 5 ? 4 : t >= 2 ? 1 : 0;
+  if (back > 0) {
+    const float mb = __uint_as_float(D.maxb[t - 1 - back]);
+    if (mb > 0.f) slope = fmin(fmax((L1 - (D.E[t - 1 - back] + log2((double)mb))) / back, -16.0), 16.0);
+  }
+  return (int)rint(L1 + (target - (t - 1)) * slope);
+}
+
+// LDS of the finish: every operand of the O(1) recurrences of a cell
+template <typename T>
+struct FinStage {
+  T tab[TB_LEN];
+  T eIm1[36], eI[36], eJm1[36], eJ[36];  // edge factors e_{i-1}, e_i, e_{j-1}, e_j
+  T vI[6], vJ[6];
+  T Uin[36], Xin[36], Bin[36];  // U, QmX, Qb of (i+1, j-1)
+  T M1l[36];                    // Qm1[i][j-1]
+  T M1pr[36];                   // Qm1p[i+1][j]
+  T Ul[36];                     // U[i][j-1]
+  T G[36], F[36];               // bulge and interior sums of the cell (block (i+1, j-1))
+  T X[36];                      // split sum of the cell, provisional exponent
+  T qb[36], qm1[36];
+  signed char nt[6][6];  // bases of positions i-1, i, i+1, j-1, j, j+1
+  int d[6], P[6];
+};
+
+// LDS of the bulge sums of a cell
+struct BulStage {
+  int d[6], P[6];
+  int wd[64], wP[64];  // d, P of positions i+1+q ([q]) and j-1-q ([32+q])
+  unsigned char mapL[192], mapR[192];
+};
+
+// LDS layouts of the workgroup kinds, byte offsets from the start of the
+// dynamic LDS.  The kernels carve their LDS with these and the launch size
+// (fwd_lds_bytes) is the largest end among them, so the two cannot drift.
+__host__ __device__ constexpr size_t lds_se(int n) { return lds_al((size_t)(n + 1) * 4); }  // E[0..n]
+template <typename T>
+struct WinLayout {  // window kind and the outside's recomputation of A
+  static __host__ __device__ size_t stage(int n) { return lds_se(n); }
+  static __host__ __device__ size_t blocks(int n) { return stage(n) + lds_al(sizeof(CellStage<T>)); }
+  static __host__ __device__ size_t end(int n) { return blocks(n) + (size_t)CDZ_FWD_WBLK * 36 * sizeof(T); }
+};
+template <typename T>
+struct BulLayout {  // bulge kind: exponents, stage, 32 bulge weights, blocks
+  static __host__ __device__ size_t stage(int n) { return lds_se(n); }
+  static __host__ __device__ size_t weights(int n) { return stage(n) + lds_al(sizeof(BulStage)); }
+  static __host__ __device__ size_t blocks(int n) { return weights(n) + 32 * sizeof(T); }
+  static __host__ __device__ size_t end(int n) { return blocks(n) + (size_t)CDZ_BUL_BLK * 36 * sizeof(T); }
+};
+template <typename T>
+struct SplLayout {  // split kind: exponents, reduction scratch, 36 sums
+  static __host__ __device__ size_t red(int n) { return lds_se(n); }
+  static __host__ __device__ size_t out(int n) { return red(n) + (CDZ_NT / 64) * 36 * sizeof(T); }
+  static __host__ __device__ size_t end(int n) { return out(n) + 36 * sizeof(T); }
+};
+template <typename T>
+struct FinLayout {  // finish kind: 216 partial sums, stage
+  static __host__ __device__ size_t stage(int) { return lds_al(216 * sizeof(T)); }
+  static __host__ __device__ size_t end(int n) { return stage(n) + sizeof(FinStage<T>); }
+};
+
+template <typename T>
+__device__ __forceinline__ void stage_block(T *dst, const T *A, long long ld, int r0, int c0, int dr,
+                                            int dc, int q) {
+  const int r = q / 6, c = q % 6;
+  dst[q] = (r < dr && c < dc) ? A[(long long)(r0 + r) * ld + c0 + c] : T(0);
+}
+
+// positions i-1, i, i+1, j-1, j, j+1 (d = 0, P = 0 where absent), by threads 0..5
+template <typename T>
+__device__ __forceinline__ void load_positions(const DevProb<T> &D, int i, int j, int *d, int *P,
+                                               signed char (*nt)[6]) {
+  const int tid = threadIdx.x, n = D.n;
   if (tid < 6) {
     const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
     const int p = pos[tid];
     const bool ok = p >= 0 && p < n;
-    C.d[tid] = ok ? D.d[p] : 0;
-    C.P[tid] = ok ? D.P[p] : 0;
+    d[tid] = ok ? D.d[p] : 0;
+    P[tid] = ok ? D.P[p] : 0;
+    if (nt)
 #pragma unroll
-    for (int s = 0; s < 6; s++) C.nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
+      for (int s = 0; s < 6; s++) nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
   }
-  for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+}
+// window positions i+1+q ([q]) and j-1-q ([32+q]), q = 0..31, by threads 64..127
+template <typename T>
+__device__ __forceinline__ void load_window_positions(const DevProb<T> &D, int i, int j, int *wd, int *wP) {
+  const int tid = threadIdx.x, n = D.n;
   if (tid >= 64 && tid < 128) {
     const int q = tid - 64;
     const int p = q < 32 ? i + 1 + q : j - 1 - (q - 32);
     const bool ok = p >= 0 && p < n;
-    C.wd[q] = ok ? D.d[p] : 0;
-    C.wP[q] = ok ? D.P[p] : 0;
+    wd[q] = ok ? D.d[p] : 0;
+    wP[q] = ok ? D.P[p] : 0;
+  }
+}
+
+// ---- window: A(i,j,L) and F of the cells of diagonal dl (launch dl - 1)
+template <typename T>
+__device__ __forceinline__ void fwd_window(const DevProb<T> &D, int t, int dl, int blk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1]
+  CellStage<T> &C = *reinterpret_cast<CellStage<T> *>(smem_raw + WinLayout<T>::stage(D.n));
+  T *W = reinterpret_cast<T *>(smem_raw + WinLayout<T>::blocks(D.n));
+  const int n = D.n, tid = threadIdx.x, ncell = n - dl;
+  const int i = cdz_cell_of_block(blk, ncell), j = i + dl;
+  if (i >= ncell) return;
+  const int Ed = exponent_ahead(D, t, dl);
+  cdz_copy_ints(sE, D.E, dl);  // E[0..dl-1]; E[dl] below
+  load_positions(D, i, j, C.d, C.P, (signed char(*)[6]) nullptr);
+  load_window_positions(D, i, j, C.wd, C.wP);
+  if (tid >= 128 && tid < 164) {
+    const int q = tid - 128;
+    C.eI1[q] = i + 1 < n ? D.e[(i + 1) * 36 + q] : T(0);
+    C.eJm2[q] = j >= 2 ? D.e[(j - 2) * 36 + q] : T(0);
+    if (q < 6) {
+      C.vI1[q] = i + 1 < n ? D.v[(i + 1) * 6 + q] : T(0);
+      C.vJm1[q] = j >= 1 ? D.v[(j - 1) * 6 + q] : T(0);
+    }
+  } else if (tid >= 164 && tid < 164 + 31) {
+    C.tab[TB_IN + tid - 164] = D.tab[TB_IN + tid - 164];
+  }
+  if (tid == 0) sE[dl] = Ed;
+  cdz_sync();
+  const int lmax = min(CDZ_MAXLOOP, dl - 6);
+  a_window<T>(D, C, sE, W, i, j, dl, lmax, Ed);
+  T *AC = W + 60 * 36 + 84 * 36;
+  if (tid < 36) {
+    const int a = tid / 6, dd = tid % 6;
+    T f = 0;
+    for (int L = 2; L <= lmax; L++) f += C.tab[TB_IN + L] * AC[(L - 2) * 36 + tid];
+    if (a < C.d[2] && dd < C.d[3]) D.F[(long long)(C.P[2] + a) * D.ld + C.P[3] + dd] = f;
+  }
+  // keep A(i,j,L), L = 2..CDZ_NA+1, for the cells of diagonal dl + 2 and the
+  // outside pass (zero where no inner pair fits)
+  a_store<T>(D, C, i, lmax, AC);
+}
+
+// ---- bulges: G of the cells of diagonal dl (launch dl - 1).  Left bulge l:
+//      run i+1..k-1, inner pair (k, j-1), k = i+1+l; right bulge l: inner pair
+//      (i+1, l'), run l'+1..j-1, l' = j-1-l; l = 1..lmax.  The edge between
+//      run and inner pair is folded into one side per term first (M below), so
+//      each term is two 6x6x6 products.
+template <typename T>
+__device__ __forceinline__ void fwd_bulges(const DevProb<T> &D, int t, int dl, int blk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1]
+  BulStage &C = *reinterpret_cast<BulStage *>(smem_raw + BulLayout<T>::stage(D.n));
+  T *tb = reinterpret_cast<T *>(smem_raw + BulLayout<T>::weights(D.n));  // bulge weights by length
+  T *X = reinterpret_cast<T *>(smem_raw + BulLayout<T>::blocks(D.n));
+  T *UR1 = X, *UC1 = X + 30 * 36, *EL = X + 60 * 36, *ER = X + 90 * 36, *QL = X + 120 * 36, *QR = X + 150 * 36;
+  T *GP = UR1;  // 7 x 36 partial sums, after the products have used UR1
+  const int n = D.n, tid = threadIdx.x, ncell = n - dl;
+  const long long ld = D.ld;
+  const int i = cdz_cell_of_block(blk, ncell), j = i + dl;
+  if (i >= ncell) return;
+  const int Ed = exponent_ahead(D, t, dl);
+  const int lmax = min(CDZ_MAXLOOP, dl - 6);
+  cdz_copy_ints(sE, D.E, dl);
+  load_positions(D, i, j, C.d, C.P, (signed char(*)[6]) nullptr);
+  load_window_positions(D, i, j, C.wd, C.wP);
+  if (tid >= 128 && tid < 128 + 31) tb[tid - 128] = D.tab[TB_BU + tid - 128];
+  cdz_sync();
+  const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
+  T g = 0;
+  if (lmax >= 1) {
+    const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
+    cdz_window_maps(C.mapL, C.mapR, lp_d, lp_P, rp_d, rp_P, lmax);
+    {  // clear the blocks the staging places values into (padding stays zero)
+      uint4 *w4 = reinterpret_cast<uint4 *>(X);
+      const int n4 = 180 * 36 * (int)sizeof(T) / 16;
+      for (int idx = tid; idx < n4; idx += CDZ_NT) w4[idx] = make_uint4(0, 0, 0, 0);
+    }
+    cdz_sync();
+    // one staging round: e blocks (contiguous in D.e), the two runs, the two
+    // inner-pair strips, each a set of contiguous row segments placed by the
+    // window maps
+    cdz_copy_blocks<T>(EL, D.e + (long long)(i + 1) * 36, lmax, false);       // e_{i+l}
+    cdz_copy_blocks<T>(ER, D.e + (long long)(j - 1 - lmax) * 36, lmax, true);  // e_{j-1-l}
+    const int baseL = lp_P[0], baseR = rp_P[lmax];
+    const int KU = lp_P[lmax] - baseL;                        // U[i+1][i+1..i+lmax]: row P1 + r of U
+    const int endR = rp_P[0] + rp_d[0] - baseR;
+    const int oC = rp_P[lmax - 1] - baseR, KC = endR - oC;    // U[j-lmax..j-1][j-1]: row Pm + c of Ut
+    const int oq = lp_P[1] - baseL, KQ = lp_P[lmax + 1] - lp_P[1];  // Qb[i+2..i+1+lmax][j-1]: rows of Qbt
+    const int KR = rp_P[1] + rp_d[1] - baseR;                 // Qb[i+1][j-1-lmax..j-2]: row P1 + r of Qb
+    const int e1 = d1 * KU, e2 = e1 + dm * KC, e3 = e2 + dm * KQ, e4 = e3 + d1 * KR;
+    cdz_stage_nv<3, T>(X, e4, [&](int idx, int &d) -> const T * {
+      if (idx < e1) {  // U[i+1][i+l](r, c), block l - 1
+        const int r = idx / KU, k = idx % KU, q = C.mapL[k], c = k - (lp_P[q] - baseL);
+        d = q * 36 + r * 6 + c;
+        return D.U + (long long)(P1 + r) * ld + baseL + k;
+      }
+      if (idx < e2) {  // U[j-l][j-1](r, c), block 30 + l - 1
+        const int s = idx - e1, c = s / KC, k = s % KC + oC, q = C.mapR[k], r = k - (rp_P[q] - baseR);
+        d = (30 + q) * 36 + r * 6 + c;
+        return D.Ut + (long long)(Pm + c) * ld + baseR + k;
+      }
+      if (idx < e3) {  // Qb[i+1+l][j-1](x, c), block 120 + l - 1
+        const int s = idx - e2, c = s / KQ, k = s % KQ + oq, l = C.mapL[k], x = k - (lp_P[l] - baseL);
+        d = (120 + l - 1) * 36 + x * 6 + c;
+        return D.Qbt + (long long)(Pm + c) * ld + baseL + k;
+      }
+      // Qb[i+1][j-1-l](r, c), block 150 + l - 1
+      const int s = idx - e3, r = s / KR, k = s % KR, l = C.mapR[k], c = k - (rp_P[l] - baseR);
+      d = (150 + l - 1) * 36 + r * 6 + c;
+      return D.Qb + (long long)(P1 + r) * ld + baseR + k;
+    });
+    cdz_sync();
+    // per term, in place: left M = e_{k-1} . Qb[k][j-1] (into EL), right
+    // M = e_{l'} . U[l'+1][j-1] (into ER); a wave per term
+    {
+      const int lane = tid & 63, r = lane / 6, c = lane % 6;
+      for (int b = cdz_wave_id(); b < 2 * lmax; b += CDZ_NT / 64) {
+        const bool left = b < lmax;
+        const int l = (left ? b : b - lmax) + 1;
+        T *ek = (left ? EL : ER) + (l - 1) * 36;
+        const T *o = left ? QL + (l - 1) * 36 : UC1 + (l - 1) * 36;
+        T v = 0;
+        if (lane < 36) {
+#pragma unroll
+          for (int x = 0; x < 6; x++) v += ek[r * 6 + x] * o[x * 6 + c];
+        }
+        cdz_wave_sync();
+        if (lane < 36) ek[lane] = v;
+      }
+    }
+    cdz_sync();
+    // G(a, c) = sum_l f_l (sum_b U[i+1][i+l](a,b) M_l(b,c) + sum_y Qb[i+1][l'](a,y) M'_l(y,c));
+    // thread (grp, q) sums the terms grp, grp + 7, .. of output q
+    const int q = tid % 36, grp = tid / 36, a = q / 6, c = q % 6;
+    if (grp < 7) {
+      for (int term = grp; term < 2 * lmax; term += 7) {
+        const bool left = term < lmax;
+        const int l = (left ? term : term - lmax) + 1;
+        const T f = tb[l] * cdz_p2<T>(sE[l - 1] + sE[dl - 2 - l] - Ed);
+        const T *u = left ? UR1 + (l - 1) * 36 : QR + (l - 1) * 36;
+        const T *mm = (left ? EL : ER) + (l - 1) * 36;
+        T sm = 0;
+#pragma unroll
+        for (int b = 0; b < 6; b++) sm += u[a * 6 + b] * mm[b * 6 + c];
+        g += f * sm;
+      }
+    }
+    cdz_sync();  // UR1 is reused for the partial sums
+    if (grp < 7) GP[grp * 36 + q] = g;
+    cdz_sync();
+    if (tid < 36) {
+      g = 0;
+#pragma unroll
+      for (int gg = 0; gg < 7; gg++) g += GP[gg * 36 + tid];
+    }
+  }
+  if (tid < 36) {
+    const int a = tid / 6, c = tid % 6;
+    if (a < d1 && c < dm) D.G[(long long)(P1 + a) * ld + Pm + c] = g;
+  }
+}
+
+// ---- split: QmX[i][j] = sum_k Qm[i][k] f(k) Qm1Lt[j][k], k over the states of
+//      positions i+4 .. j-5 (u - 1 = pos(k)), for the cells of diagonal dl
+//      (launch dl - 4), stored as true * 2^-EX[dl]
+template <typename T>
+__device__ __forceinline__ void fwd_split(const DevProb<T> &D, int t, int dl, int blk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1]
+  T *red = reinterpret_cast<T *>(smem_raw + SplLayout<T>::red(D.n));
+  T *out = reinterpret_cast<T *>(smem_raw + SplLayout<T>::out(D.n));
+  const int n = D.n, tid = threadIdx.x, ncell = n - dl;
+  const long long ld = D.ld;
+  const int i = cdz_cell_of_block(blk, ncell), j = i + dl;
+  if (i >= ncell) return;
+  const int EX = exponent_ahead(D, t, dl);
+  const int di = D.d[i], dj = D.d[j], Pi = D.P[i], Pj = D.P[j];
+  const int K0 = D.P[i + 4], K1 = D.P[j - 4];
+  cdz_copy_ints(sE, D.E, dl - 4);  // spans 0..dl-5
+  cdz_sync();
+  constexpr int UN = sizeof(T) == 4 ? 4 : 1;
+  T acc[36];
+#pragma unroll
+  for (int r = 0; r < 36; r++) acc[r] = 0;
+  for (int k0 = K0 + tid; k0 < K1; k0 += UN * CDZ_NT) {
+    T a[UN][6], b[UN][6];
+    int pp[UN];
+#pragma unroll
+    for (int u = 0; u < UN; u++) {
+      const int k = k0 + u * CDZ_NT;
+      const bool ok = k < K1;
+      pp[u] = ok ? D.posOf[k] : i + 4;
+#pragma unroll
+      for (int s = 0; s < 6; s++) a[u][s] = (ok && s < di) ? D.Qm[(Pi + s) * ld + k] : T(0);
+#pragma unroll
+      for (int c = 0; c < 6; c++) b[u][c] = (ok && c < dj) ? D.Qm1Lt[(Pj + c) * ld + k] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < UN; u++) {
+      const T f = cdz_p2<T>(sE[pp[u] - i] + sE[j - pp[u] - 1] - EX);
+#pragma unroll
+      for (int s = 0; s < 6; s++) {
+        const T as = a[u][s] * f;
+#pragma unroll
+        for (int c = 0; c < 6; c++) acc[s * 6 + c] = fma(as, b[u][c], acc[s * 6 + c]);
+      }
+    }
+  }
+  cdz_block_sum<T, 36>(acc, red, out);
+  if (tid < 36) {
+    const int s = tid / 6, c = tid % 6;
+    if (s < di && c < dj) D.QmX[(long long)(Pi + s) * ld + Pj + c] = out[tid];
+  }
+}
+
+// ---- finish: the O(1) recurrences of the cells of diagonal dl (launch dl)
+template <typename T>
+__device__ __forceinline__ void fwd_finish(const DevProb<T> &D, int dl, int blk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *red = reinterpret_cast<T *>(smem_raw);  // 216 partial sums
+  FinStage<T> &C = *reinterpret_cast<FinStage<T> *>(smem_raw + FinLayout<T>::stage(D.n));
+  const int n = D.n, tid = threadIdx.x, ncell = n - dl;
+  const long long ld = D.ld;
+  const int i = cdz_cell_of_block(blk, ncell), j = i + dl;
+  if (i >= ncell) return;
+  const int Ed = D.E[dl];
+  const int E1 = dl >= 1 ? D.E[dl - 1] : 0, E2 = dl >= 2 ? D.E[dl - 2] : 0;
+  const int EXd = dl >= 9 ? D.EX[dl] : 0;
+  const T hp = dl >= 4 ? D.Bhp[dl - 1] : T(0);
+  // round 1: positions, tables, edge and vertex factors (indexed by position)
+  load_positions(D, i, j, C.d, C.P, C.nt);
+  for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+  if (tid >= 32 && tid < 32 + 144) {
+    const int w = (tid - 32) / 36, q = (tid - 32) % 36;
+    const int p = w == 0 ? i - 1 : w == 1 ? i : w == 2 ? j - 1 : j;
+    T *dst = w == 0 ? C.eIm1 : w == 1 ? C.eI : w == 2 ? C.eJm1 : C.eJ;
+    dst[q] = (p >= 0 && p < n) ? D.e[p * 36 + q] : T(0);
+  } else if (tid >= 176 && tid < 188) {
+    const int q = tid - 176;
+    if (q < 6) C.vI[q] = D.v[i * 6 + q];
+    else C.vJ[q - 6] = D.v[j * 6 + q - 6];
   }
   cdz_sync();
   const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
   const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
-  {
-    const int g = tid / 36, q = tid % 36;
+  // round 2: the blocks of the cell's neighbours and its loop and split sums
+  for (int idx = tid; idx < 9 * 36; idx += CDZ_NT) {
+    const int g = idx / 36, q = idx % 36;
     switch (g) {
-      case 0:
-        if (dl >= 2) stage_block(C.Uin, D.U, ld, P1, Pm, d1, dm, q);
-        else C.Uin[q] = 0;
-        break;
-      case 1:
-        if (dl >= 2) stage_block(C.Xin, D.QmX, ld, P1, Pm, d1, dm, q);
-        else C.Xin[q] = 0;
-        break;
-      case 2:
-        if (dl >= 2) stage_block(C.Bin, D.Qb, ld, P1, Pm, d1, dm, q);
-        else C.Bin[q] = 0;
-        break;
-      case 3:
-        if (dl >= 1) stage_block(C.M1l, D.Qm1, ld, Pi, Pm, di, dm, q);
-        else C.M1l[q] = 0;
-        break;
-      case 4:
-        if (dl >= 1) stage_block(C.M1pr, D.Qm1p, ld, P1, Pj, d1, dj, q);
-        else C.M1pr[q] = 0;
-        break;
-      case 5:
-        if (dl >= 1) stage_block(C.Ul, D.U, ld, Pi, Pm, di, dm, q);
-        else C.Ul[q] = 0;
-        break;
-      case 6:
-        C.eIm1[q] = i >= 1 ? D.e[(i - 1) * 36 + q] : T(0);
-        C.eI[q] = D.e[i * 36 + q];
-        C.eJm1[q] = j >= 1 ? D.e[(j - 1) * 36 + q] : T(0);
-        C.eJ[q] = D.e[j * 36 + q];
-        C.eI1[q] = i + 1 < n ? D.e[(i + 1) * 36 + q] : T(0);
-        C.eJm2[q] = j >= 2 ? D.e[(j - 2) * 36 + q] : T(0);
-        if (q < 6) {
-          C.vI[q] = D.v[i * 6 + q];
-          C.vJ[q] = D.v[j * 6 + q];
-          C.vI1[q] = i + 1 < n ? D.v[(i + 1) * 6 + q] : T(0);
-          C.vJm1[q] = j >= 1 ? D.v[(j - 1) * 6 + q] : T(0);
-        }
-        break;
+      case 0: if (dl >= 2) stage_block(C.Uin, D.U, ld, P1, Pm, d1, dm, q); else C.Uin[q] = 0; break;
+      case 1: if (dl >= 2) stage_block(C.Xin, D.QmX, ld, P1, Pm, d1, dm, q); else C.Xin[q] = 0; break;
+      case 2: if (dl >= 2) stage_block(C.Bin, D.Qb, ld, P1, Pm, d1, dm, q); else C.Bin[q] = 0; break;
+      case 3: if (dl >= 1) stage_block(C.M1l, D.Qm1, ld, Pi, Pm, di, dm, q); else C.M1l[q] = 0; break;
+      case 4: if (dl >= 1) stage_block(C.M1pr, D.Qm1p, ld, P1, Pj, d1, dj, q); else C.M1pr[q] = 0; break;
+      case 5: if (dl >= 1) stage_block(C.Ul, D.U, ld, Pi, Pm, di, dm, q); else C.Ul[q] = 0; break;
+      case 6: if (dl >= 4) stage_block(C.G, D.G, ld, P1, Pm, d1, dm, q); else C.G[q] = 0; break;
+      case 7: if (dl >= 4) stage_block(C.F, D.F, ld, P1, Pm, d1, dm, q); else C.F[q] = 0; break;
+      case 8: if (dl >= 9) stage_block(C.X, D.QmX, ld, Pi, Pj, di, dj, q); else C.X[q] = 0; break;
+      default: break;
     }
   }
   cdz_sync();
   float vmax = 0.f;
-
-  // ---- unpaired run U[i][j]
+  const T *tab = C.tab;
+  // ---- unpaired run U[i][j]; Qb partial sums: thread (a, o) takes the terms
+  //      of output o = (s, s2) whose slot at i+1 is a
   if (tid < 36) {
-    const int s = tid / 6, t = tid % 6;
-    if (s < di && t < dj) {
+    const int s = tid / 6, c = tid % 6;
+    if (s < di && c < dj) {
       T u = 0;
       if (dl == 0) {
-        u = (s == t) ? C.vI[s] : T(0);
+        u = (s == c) ? C.vI[s] : T(0);
       } else {
         T a = 0;
 #pragma unroll
-        for (int c = 0; c < 6; c++) a += C.Ul[s * 6 + c] * C.eJm1[c * 6 + t];
-        u = a * C.vJ[t] * cdz_p2<T>(sE[dl - 1] - Ed);
+        for (int x = 0; x < 6; x++) a += C.Ul[s * 6 + x] * C.eJm1[x * 6 + c];
+        u = a * C.vJ[c] * cdz_p2<T>(E1 - Ed);
       }
-      D.U[(Pi + s) * ld + Pj + t] = u;
-      D.Ut[(Pj + t) * ld + Pi + s] = u;
+      D.U[(Pi + s) * ld + Pj + c] = u;
+      D.Ut[(Pj + c) * ld + Pi + s] = u;
       vmax = fmaxf(vmax, (float)fabs(u));
       if (dl < 4) {
-        const long long o = (Pi + s) * ld + Pj + t;
+        const long long o = (Pi + s) * ld + Pj + c;
         D.Qb[o] = 0;
-        D.Qbt[(Pj + t) * ld + Pi + s] = 0;
+        D.Qbt[(Pj + c) * ld + Pi + s] = 0;
         D.Qm1[o] = 0;
         D.Qm1p[o] = 0;
         D.QmX[o] = 0;
         D.Qm[o] = 0;
-        D.Qmt[(Pj + t) * ld + Pi + s] = 0;
+        D.Qmt[(Pj + c) * ld + Pi + s] = 0;
       }
     }
   }
   if (dl >= 4) {
-    // ---- split: QmX[i][j] = sum_k Qm[i][k] f(k) Qm1Lt[j][k], k over the
-    //      states of positions i+4 .. j-5 (u - 1 = pos(k)); the stream is
-    //      unrolled so that the loads of several k are in flight together
-    {
-      constexpr int UN = sizeof(T) == 4 ? 4 : 1;
-      T acc[36];
-#pragma unroll
-      for (int r = 0; r < 36; r++) acc[r] = 0;
-      const int K0 = D.P[i + 4], K1 = D.P[j - 4];
-      for (int k0 = K0 + tid; k0 < K1; k0 += UN * CDZ_NT) {
-        T a[UN][6], b[UN][6];
-        int pp[UN];
-#pragma unroll
-        for (int u = 0; u < UN; u++) {
-          const int k = k0 + u * CDZ_NT;
-          const bool ok = k < K1;
-          pp[u] = ok ? D.posOf[k] : i + 4;
-#pragma unroll
-          for (int s = 0; s < 6; s++) a[u][s] = (ok && s < di) ? D.Qm[(Pi + s) * ld + k] : T(0);
-#pragma unroll
-          for (int t = 0; t < 6; t++) b[u][t] = (ok && t < dj) ? D.Qm1Lt[(Pj + t) * ld + k] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < UN; u++) {
-          const T f = cdz_p2<T>(sE[pp[u] - i] + sE[j - pp[u] - 1] - Ed);
-#pragma unroll
-          for (int s = 0; s < 6; s++) {
-            const T as = a[u][s] * f;
-#pragma unroll
-            for (int t = 0; t < 6; t++) acc[s * 6 + t] = fma(as, b[u][t], acc[s * 6 + t]);
-          }
-        }
-      }
-      cdz_block_sum<T, 36>(acc, red, C.split);
-    }
-    // ---- bulge and interior loops closed by (i, j), indices (a, dd) = slots
-    //      of positions i+1 and j-1, outer edges and outer mismatch not
-    //      applied: G = bulges, F = interior loops.
-    //
-    //      Interior loops use the loop-size recursion (Lyngso's observation,
-    //      valid because the interior-loop energy depends on l1 + l2 and the
-    //      end mismatches only): with A(i,j,L) the sum over inner pairs at
-    //      total loop size L = l1 + l2 of U[i+1][k-1] . DI[k][l] . U[l+1][j-1],
-    //        A(i,j,L) = V . A(i+1,j-1,L-2) . W          (l1, l2 >= 2)
-    //                 + diag v_{i+1} . DI . U[j-L+1][j-1]  (l1 = 1)
-    //                 + U[i+1][i+L-1] . DI . diag v_{j-1}  (l2 = 1, L >= 3)
-    //      with V = v_{i+1} e_{i+1}, W = e_{j-2} v_{j-1}; F = sum_L w_int(L) A.
-    //      Every term needs an inner pair at distance >= 4, i.e. L <= dl - 6.
-    {
-      const int lmax = min(CDZ_MAXLOOP, dl - 6);
-      T *UR1 = W;              // [l-1] U[i+1][i+l]
-      T *UC1 = W + 30 * 36;    // [l-1] U[j-l][j-1]
-      T *X = W + 60 * 36;      // phase-dependent blocks
-      T *AC = X + 84 * 36;     // [L-2] A(i,j,L)
-      const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
-      a_window<T>(D, C, sE, W, i, j, dl, lmax, Ed);
-      if (tid < 36) {
-        T f = 0;
-        for (int L = 2; L <= lmax; L++) f += C.tab[TB_IN + L] * AC[(L - 2) * 36 + tid];
-        C.gf[36 + tid] = f;
-      }
-      cdz_sync();
-      // bulges: left (run i+1..k-1, inner pair (k, j-1)), right (inner pair
-      // (i+1, l), run l+1..j-1), l = 1..lmax; one side after the other, each
-      // thread summing the terms term = g, g + 7, .. of output q
-      T *EB = X, *QB = X + 30 * 36;
-      T *GP = red;  // 7 x 36 partial sums (the reduction scratch is free here)
-      const int q = tid % 36, g = tid / 36, r = q / 6, c = q % 6;
-      T gacc = 0;
-      for (int side = 0; side < 2; side++) {
-        // e blocks (contiguous in D.e), then the Qb blocks of the inner pairs:
-        // the left side's column strip as contiguous rows of Qbt, the right
-        // side's row strip as one contiguous row segment of Qb, each placed by
-        // the window map of its side into blocks cleared first
-        // e_{k-1}, k = i+1+l (left: positions i+1..i+lmax) / e_l, l = j-1-l2
-        // (right: positions j-2 down to j-1-lmax), block l-1
-        if (side == 0) cdz_copy_blocks<T>(EB, D.e + (long long)(i + 1) * 36, lmax, false);
-        else cdz_copy_blocks<T>(EB, D.e + (long long)(j - 1 - lmax) * 36, lmax, true);
-        cdz_zero_blocks<T>(QB, lmax);
-        cdz_sync();
-        if (side == 0 && lmax >= 1) {  // Qb[i+1+l][j-1](x, c) = Qbt row Pm + c, states of positions i+2..i+1+lmax
-          const int o = lp_P[1] - lp_P[0], K = lp_P[lmax + 1] - lp_P[1];
-          for (int idx = tid; idx < dm * K; idx += CDZ_NT) {
-            const int c = idx / K, k = idx % K + o, l = C.mapL[k], x = k - (lp_P[l] - lp_P[0]);
-            QB[(l - 1) * 36 + x * 6 + c] = D.Qbt[(long long)(Pm + c) * ld + lp_P[0] + k];
-          }
-        } else if (lmax >= 1) {  // Qb[i+1][j-1-l] = row P1 + r of Qb, states of positions
-                                 // j-1-lmax..j-2, placed by the right window map
-          const int baseR = rp_P[lmax], K = rp_P[1] + rp_d[1] - baseR;
-          for (int idx = tid; idx < d1 * K; idx += CDZ_NT) {
-            const int r = idx / K, k = idx % K, l = C.mapR[k], c = k - (rp_P[l] - baseR);
-            QB[(l - 1) * 36 + r * 6 + c] = D.Qb[(long long)(P1 + r) * ld + baseR + k];
-          }
-        }
-        cdz_sync();
-        if (g < 7) {
-          for (int l = g + 1; l <= lmax; l += 7) {
-            const T f = C.tab[TB_BU + l] * cdz_p2<T>(sE[l - 1] + sE[dl - 2 - l] - Ed);
-            const T *ek = EB + (l - 1) * 36, *qk = QB + (l - 1) * 36;
-            T sm = 0;
-            if (side == 0) {  // output (a, y) = (r, c): U[i+1][k-1] e_{k-1} Qb[k][j-1]
-              const T *ul = UR1 + (l - 1) * 36;
-#pragma unroll
-              for (int b = 0; b < 6; b++) {
-                T m = 0;
-#pragma unroll
-                for (int x = 0; x < 6; x++) m += ek[b * 6 + x] * qk[x * 6 + c];
-                sm += ul[r * 6 + b] * m;
-              }
-            } else {  // output (x, dd) = (r, c): Qb[i+1][l] e_l U[l+1][j-1]
-              const T *ur = UC1 + (l - 1) * 36;
-#pragma unroll
-              for (int y = 0; y < 6; y++) {
-                T m = 0;
-#pragma unroll
-                for (int cc = 0; cc < 6; cc++) m += ek[y * 6 + cc] * ur[cc * 6 + c];
-                sm += qk[r * 6 + y] * m;
-              }
-            }
-            gacc += f * sm;
-          }
-        }
-        cdz_sync();
-      }
-      if (g < 7) GP[g * 36 + q] = gacc;
-      cdz_sync();
-      if (tid < 36) {
-        T gs = 0;
-#pragma unroll
-        for (int gg = 0; gg < 7; gg++) gs += GP[gg * 36 + tid];
-        C.gf[tid] = gs;
-      }
-      // keep A(i,j,L), L = 2..CDZ_NA+1, for the cells of diagonal dl + 2 and
-      // the outside pass (zero where no inner pair fits); stored after the
-      // loads above so that none of them waits behind these stores
-      a_store<T>(D, C, i, lmax, AC);
-      cdz_sync();
-    }
-    const T *tab = C.tab;
-    // ---- Qb: thread (a, o) sums the terms of output o = (s, s2) whose slot
-    //      at i+1 is a; the six partial sums are added afterwards
     if (tid < 216) {
       const int a = tid / 36, o = tid % 36, s = o / 6, s2 = o % 6;
       T part = 0;
       if (s < di && s2 < dj && a < d1) {
-        const int t = cdz_ptype(C.nt[1][s], C.nt[4][s2]);
-        if (t >= 0) {
+        const int ty = cdz_ptype(C.nt[1][s], C.nt[4][s2]);
+        if (ty >= 0) {
           const int na = C.nt[2][a];
           const T ea = C.eI[s * 6 + a];
-          T acc = 0, hp = 0, st = 0, ml = 0;
+          T acc = 0, hpa = 0, st = 0, ml = 0;
 #pragma unroll
           for (int b = 0; b < 6; b++) {
             if (b >= dm) continue;
             const int nb = C.nt[3][b];
             const T w = ea * C.eJm1[b * 6 + s2];
-            const T mmo = tab[TB_MM + na * 24 + nb * 6 + t];
+            const T mmo = tab[TB_MM + na * 24 + nb * 6 + ty];
             const int o2 = a * 6 + b;
-            hp += w * C.Uin[o2] * mmo;
-            acc += w * (C.gf[o2] + C.gf[36 + o2] * mmo);
+            hpa += w * C.Uin[o2] * mmo;
+            acc += w * (C.G[o2] + C.F[o2] * mmo);
             ml += w * C.Xin[o2];
             const int t2 = cdz_ptype(na, nb);
-            if (dl - 2 >= 4 && t2 >= 0) st += w * C.Bin[o2] * tab[TB_ST + t * 6 + t2];
+            if (dl - 2 >= 4 && t2 >= 0) st += w * C.Bin[o2] * tab[TB_ST + ty * 6 + t2];
           }
-          part = acc + (hp * D.Bhp[dl - 1] + st + ml * tab[TB_MLAB]) * cdz_p2<T>(sE[dl - 2] - Ed);
+          part = acc + (hpa * hp + st + ml * tab[TB_MLAB]) * cdz_p2<T>(E2 - Ed);
         }
       }
       red[a * 36 + o] = part;
@@ -672,7 +650,7 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
     cdz_sync();
     if (tid < 36) {
       const int s = tid / 6, s2 = tid % 6;
-      T qb = 0;
+      T qb = 0, q1 = 0;
       if (s < di && s2 < dj) {
         T acc = 0;
 #pragma unroll
@@ -681,30 +659,19 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
         D.Qb[(Pi + s) * ld + Pj + s2] = qb;
         D.Qbt[(Pj + s2) * ld + Pi + s] = qb;
         vmax = fmaxf(vmax, (float)fabs(qb));
-      }
-      C.qb[tid] = qb;
-      // keep the window sums of this cell for the adjoint (block (i+1, j-1))
-      if (s < d1 && s2 < dm) {
-        D.G[(P1 + s) * ld + Pm + s2] = C.gf[tid];
-        D.F[(P1 + s) * ld + Pm + s2] = C.gf[36 + tid];
-      }
-    }
-    cdz_sync();
-    // ---- Qm1, and DI (Qb dressed as an interior loop's inner pair) with
-    //      thread (x, o) summing over the slot y of j for output o = (b, c)
-    if (tid < 36) {
-      const int s = tid / 6, s2 = tid % 6;
-      T q1 = 0;
-      if (s < di && s2 < dj) {
         T a = 0;
 #pragma unroll
-        for (int t = 0; t < 6; t++) a += C.M1l[s * 6 + t] * C.eJm1[t * 6 + s2];
-        q1 = a * C.vJ[s2] * tab[TB_MLC] * cdz_p2<T>(sE[dl - 1] - Ed) + C.qb[tid] * tab[TB_MLB];
+        for (int x = 0; x < 6; x++) a += C.M1l[s * 6 + x] * C.eJm1[x * 6 + s2];
+        q1 = a * C.vJ[s2] * tab[TB_MLC] * cdz_p2<T>(E1 - Ed) + qb * tab[TB_MLB];
         D.Qm1[(Pi + s) * ld + Pj + s2] = q1;
         vmax = fmaxf(vmax, (float)fabs(q1));
       }
+      C.qb[tid] = qb;
       C.qm1[tid] = q1;
     }
+    cdz_sync();
+    // ---- DI (Qb dressed as an interior loop's inner pair), thread (x, o)
+    //      summing over the slot y of j for output o = (b, c)
     const bool hasDI = i >= 1 && j + 1 < n;
     if (hasDI && tid < 216) {
       const int x = tid / 36, o = tid % 36, b = o / 6, c = o % 6;
@@ -722,7 +689,7 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
       red[x * 36 + o] = part;
     }
     cdz_sync();
-    // ---- DI, Qm1L, Qm1p, QmX, Qm
+    // ---- DI, Qm1L, Qm1p, QmX (split sum converted to E[dl]), Qm
     if (tid < 36) {
       const int s = tid / 6, s2 = tid % 6;
       if (hasDI && s < C.d[0] && s2 < C.d[5]) {
@@ -735,16 +702,16 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
       if (i >= 1 && s < C.d[0] && s2 < dj) {
         T a = 0;
 #pragma unroll
-        for (int t = 0; t < 6; t++) a += C.eIm1[s * 6 + t] * C.qm1[t * 6 + s2];
+        for (int x = 0; x < 6; x++) a += C.eIm1[s * 6 + x] * C.qm1[x * 6 + s2];
         D.Qm1Lr[(C.P[0] + s) * ld + Pj + s2] = a;
         D.Qm1Lt[(Pj + s2) * ld + C.P[0] + s] = a;
       }
       if (s < di && s2 < dj) {
         T a = 0;
 #pragma unroll
-        for (int t = 0; t < 6; t++) a += C.eI[s * 6 + t] * C.M1pr[t * 6 + s2];
-        const T qp = C.qm1[tid] + tab[TB_MLC] * C.vI[s] * cdz_p2<T>(sE[dl - 1] - Ed) * a;
-        const T qx = C.split[tid];
+        for (int x = 0; x < 6; x++) a += C.eI[s * 6 + x] * C.M1pr[x * 6 + s2];
+        const T qp = C.qm1[tid] + tab[TB_MLC] * C.vI[s] * cdz_p2<T>(E1 - Ed) * a;
+        const T qx = dl >= 9 ? C.X[tid] * cdz_p2<T>(EXd - Ed) : T(0);
         const T qm = qx + qp;
         const long long o = (Pi + s) * ld + Pj + s2;
         D.Qm1p[o] = qp;
@@ -755,10 +722,230 @@ __device__ __forceinline__ void fwd_cell(const DevProb<T> &D, int dl, int blk) {
       }
     }
   }
-  // ---- per-diagonal maximum for the next exponents
+  // ---- per-diagonal maximum for the exponents of later diagonals
   if (tid < 64) {
     vmax = fminf(cdz_wave_max(vmax), 3.0e38f);
     if (tid == 0 && vmax > 0.f) atomicMax(&D.maxb[dl], __float_as_uint(vmax));
+  }
+}
+
+// One workgroup of launch t; w is its index among this problem's workgroups
+template <typename T>
+__device__ __forceinline__ void fwd_block(const DevProb<T> &D, int t, int w) {
+  int r[4];
+  fwd_ranges(D.n, t, r);
+  if (w < r[0]) {
+    fwd_window<T>(D, t, t + 1, w);
+    return;
+  }
+  w -= r[0];
+  if (w < r[1]) {
+    fwd_bulges<T>(D, t, t + 1, w);
+    return;
+  }
+  w -= r[1];
+  if (w < r[2]) {
+    fwd_split<T>(D, t, t + 4, w);
+    return;
+  }
+  w -= r[2];
+  if (w < r[3]) {
+    if (w == 0 && threadIdx.x == 0) {  // the exponents chosen in this launch
+      if (t + 1 <= D.n) D.E[t + 1] = exponent_ahead(D, t, t + 1);
+      D.EX[t + 4] = exponent_ahead(D, t, t + 4);
+    }
+    fwd_finish<T>(D, t, w);
+  }
+}
+
+// dynamic LDS of a forward launch: the largest of its workgroup kinds
+template <typename T>
+size_t fwd_lds_bytes(int n) {
+  return std::max(std::max(WinLayout<T>::end(n), BulLayout<T>::end(n)),
+                  std::max(SplLayout<T>::end(n), FinLayout<T>::end(n)));
+}
+template size_t fwd_lds_bytes<float>(int);
+template size_t fwd_lds_bytes<double>(int);
+
+// ---------------------------------------------------------------------------
+// FP64 exterior loops, after the diagonal launches, as two scans over
+// positions (eq. complex-logq: the exterior loop sums the pairs that close
+// it, with nothing between them):
+//   prefix   Z5[j](t) = Z5[j-1] e_{j-1} v_j (t)                 j unpaired
+//                     + sum_{k>=1} 2^(..) A[k] Qb[k][j](., t)    k pairs j
+//                     + 2^(..) sum_x Qb[0][j](x, t)              0 pairs j
+//            A[k] = Z5[k-1] e_{k-1};  log Z = ln sum_t Z5[n-1](t)
+//   suffix   Z3[p](s) = sum_x e_p(s, x) w(x),
+//            w(x) = v_{p+1}(x) Z3[p+1](x) + sum_jj 2^(..) Qb[p+1][jj](x, .) Z3[jj]
+// Each step reads pairs of every span up to the step's position, so it runs
+// once every diagonal is final.  One workgroup per direction: the pair items
+// of a step are spread over its threads and summed, thread 0 renormalises
+// (Z5[j] = true 2^-G5[j] with the largest entry in [1, 2), likewise Z3/H3).
+// Pairs are limited to spans <= W (the truncated pass of the FP32 landscape
+// estimate); the prefix stops after position jend.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, int jend, int dir) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = D.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1] diagonal exponents
+  int *sd = sE + (n + 1), *sP = sd + (n + 1);   // [n + 1] slot counts and offsets
+  int *sX = sP + (n + 1);                       // [n + 1] G5 (prefix) or H3 (suffix)
+  double *red = reinterpret_cast<double *>(smem_raw + lds_al((size_t)4 * (n + 1) * 4));  // [4][6]
+  double *tot = red + 24;                                                                 // [8]
+  const long long ld = D.ld;
+  for (int k = tid; k <= n; k += CDZ_NT) {
+    sE[k] = D.E[k];
+    sd[k] = k < n ? D.d[k] : 0;
+    sP[k] = D.P[k];
+  }
+  __syncthreads();
+  // workgroup sum of six values per thread into tot[0..5]
+  auto sum6 = [&](double(&v)[6]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+      for (int t = 0; t < 6; t++) v[t] += __shfl_xor(v[t], off, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int t = 0; t < 6; t++) red[wv * 6 + t] = v[t];
+    __syncthreads();
+    if (tid < 6) {
+      double s = 0;
+#pragma unroll
+      for (int w = 0; w < CDZ_NT / 64; w++) s += red[w * 6 + tid];
+      tot[tid] = s;
+    }
+    __syncthreads();
+  };
+  const double L2 = 0.6931471805599453094;
+  if (dir == 0) {
+    for (int j = 0; j <= jend; j++) {
+      const int dj = sd[j], Pj = sP[j];
+      const int R = j >= 1 ? sX[j - 1] : 0;
+      double part[6] = {0, 0, 0, 0, 0, 0};
+      if (j == 0) {
+        if (tid < 6) part[tid] = tid < dj ? D.vd[tid] : 0.0;
+      } else {
+        if (tid < 6 && tid < dj) part[tid] = D.A5[j * 6 + tid] * D.vd[j * 6 + tid];
+        const int k0 = j - W > 0 ? j - W : 0, nk = j - 4 - k0 + 1;
+        for (int it = tid; it < nk; it += CDZ_NT) {
+          const int k = k0 + it, dk = sd[k], Pk = sP[k];
+          double a[6];
+          if (k == 0) {
+            const double sc = ldexp(1.0, sE[j] - R);
+#pragma unroll
+            for (int x = 0; x < 6; x++) a[x] = sc;
+          } else {
+            const double sc = ldexp(1.0, sX[k - 1] + sE[j - k] - R);
+#pragma unroll
+            for (int x = 0; x < 6; x++) a[x] = D.A5[k * 6 + x] * sc;
+          }
+#pragma unroll
+          for (int t = 0; t < 6; t++) {
+            if (t >= dj) break;
+            double s = 0;
+#pragma unroll
+            for (int x = 0; x < 6; x++)
+              if (x < dk) s += a[x] * (double)D.Qbt[(long long)(Pj + t) * ld + Pk + x];
+            part[t] += s;
+          }
+        }
+      }
+      sum6(part);
+      if (tid == 0) {
+        double mx = 0;
+        for (int t = 0; t < 6; t++) mx = fmax(mx, fabs(tot[t]));
+        const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
+        for (int t = 0; t < 6; t++) {
+          const double z = t < dj ? ldexp(tot[t], -e) : 0.0;
+          tot[t] = z;
+          D.Z5[j * 6 + t] = z;
+        }
+        sX[j] = R + e;
+        D.G5[j] = R + e;
+      }
+      __syncthreads();
+      if (tid < 6 && j + 1 < n) {  // A[j+1](x) = sum_q Z5[j](q) e_j(q, x)
+        double a = 0;
+#pragma unroll
+        for (int q = 0; q < 6; q++) a += tot[q] * D.ed[j * 36 + q * 6 + tid];
+        D.A5[(j + 1) * 6 + tid] = a;
+      }
+      __syncthreads();
+    }
+    if (tid == 0 && jend == n - 1) {
+      double z5 = 0;
+      for (int t = 0; t < 6; t++) z5 += D.Z5[(n - 1) * 6 + t];
+      const double lz5 = log(z5) + sX[n - 1] * L2;
+      D.res[0] = lz5;
+      D.res[2] = rint(lz5 / L2);  // EZ, the adjoint scale exponent
+    }
+    return;
+  }
+  // ---- suffix
+  for (int p = n - 1; p >= 0; p--) {
+    const int dp = sd[p];
+    if (p == n - 1) {
+      if (tid < 6) D.Z3[p * 6 + tid] = tid < dp ? 1.0 : 0.0;
+      if (tid == 0) {
+        sX[p] = 0;
+        D.H3[p] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const int R = sX[p + 1], d1 = sd[p + 1], P1 = sP[p + 1];
+    double w[6] = {0, 0, 0, 0, 0, 0};
+    if (tid < 6 && tid < d1) w[tid] = D.vd[(p + 1) * 6 + tid] * D.Z3[(p + 1) * 6 + tid];
+    const int j1 = p + 1 + W < n - 1 ? p + 1 + W : n - 1, nj = j1 - (p + 5) + 1;
+    for (int it = tid; it < nj; it += CDZ_NT) {
+      const int jj = p + 5 + it, dq = sd[jj], Pq = sP[jj];
+      const double sc = ldexp(1.0, sE[jj - p - 1] + sX[jj] - R);
+      double z3[6];
+#pragma unroll
+      for (int t = 0; t < 6; t++) z3[t] = D.Z3[jj * 6 + t] * sc;
+#pragma unroll
+      for (int x = 0; x < 6; x++) {
+        if (x >= d1) break;
+        double s = 0;
+#pragma unroll
+        for (int t = 0; t < 6; t++)
+          if (t < dq) s += (double)D.Qb[(long long)(P1 + x) * ld + Pq + t] * z3[t];
+        w[x] += s;
+      }
+    }
+    sum6(w);
+    if (tid == 0) {
+      double z[6], mx = 0;
+      for (int s = 0; s < 6; s++) {
+        double a = 0;
+        for (int x = 0; x < 6; x++) a += D.ed[p * 36 + s * 6 + x] * tot[x];
+        z[s] = s < dp ? a : 0.0;
+        mx = fmax(mx, fabs(z[s]));
+      }
+      const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
+      for (int s = 0; s < 6; s++) D.Z3[p * 6 + s] = ldexp(z[s], -e);
+      sX[p] = R + e;
+      D.H3[p] = R + e;
+    }
+    __syncthreads();
+  }
+  // total from the suffix: position 0 unpaired, or 0 pairs jj
+  {
+    double part[6] = {0, 0, 0, 0, 0, 0};
+    if (tid == 0)
+      for (int s = 0; s < 6; s++) part[0] += D.vd[s] * D.Z3[s];
+    const int d0 = sd[0];
+    for (int jj = 4 + tid; jj < n; jj += CDZ_NT) {
+      const int dq = sd[jj], Pq = sP[jj];
+      double a = 0;
+      for (int x = 0; x < d0; x++)
+        for (int t = 0; t < dq; t++) a += (double)D.Qb[(long long)x * ld + Pq + t] * D.Z3[jj * 6 + t];
+      part[0] += a * ldexp(1.0, sE[jj] + sX[jj] - sX[0]);
+    }
+    sum6(part);
+    if (tid == 0) D.res[1] = log(tot[0]) + sX[0] * L2;
   }
 }
 
@@ -973,6 +1160,7 @@ __device__ __forceinline__ void landscape_body(const DevProb<T> &D) {
 //          arithmetic, so an all-zero cell has underflowed); FP32 then
 //          repeats the pass once with the landscape of the exact pass
 //   res[6] = 1 if some entry is not finite (a scale factor overflowed)
+//   res[7] (as an int) = -(binary exponent) of the weakest cell's largest entry
 template <typename T>
 __device__ __forceinline__ void spread_check_body(const DevProb<T> &D, int dl) {
   const int n = D.n, ncell = n - dl;
@@ -980,6 +1168,7 @@ __device__ __forceinline__ void spread_check_body(const DevProb<T> &D, int dl) {
   T *const full[6] = {D.U, D.Qb, D.Qm1, D.Qm1p, D.QmX, D.Qm};
   const T low = (T)ldexp(1.0, -D.lowExp);
   bool weak = false, bad = false;
+  int deep = 0;  // -(binary exponent) of the weakest cell maximum seen, 1100 for a zero cell
   for (int i = threadIdx.x; i < ncell; i += CDZ_NT) {
     const int j = i + dl, di = D.d[i], dj = D.d[j], Pi = D.P[i], Pj = D.P[j];
     T m = 0;
@@ -991,9 +1180,14 @@ __device__ __forceinline__ void spread_check_body(const DevProb<T> &D, int dl) {
           m = fmax(m, x);
         }
     weak = weak || !(m >= low);
+    deep = max(deep, m > T(0) && isfinite(m) ? -ilogb(m) : (m > T(0) ? 0 : 1100));
   }
   if (__any(weak) && (threadIdx.x & 63) == 0) D.res[5] = 1.0;
   if (__any(bad) && (threadIdx.x & 63) == 0) D.res[6] = 1.0;
+  // res[7] holds an int: the largest -(exponent) over all cells (memset to 0)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) deep = max(deep, __shfl_xor(deep, o, 64));
+  if ((threadIdx.x & 63) == 0 && deep > 0) atomicMax(reinterpret_cast<int *>(D.res + 7), deep);
 }
 
 // Recompute the interior-loop sums A of the cells of diagonal dl (>= 4) into
@@ -1003,10 +1197,10 @@ __device__ __forceinline__ void spread_check_body(const DevProb<T> &D, int dl) {
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_arec_diag(DevProb<T> D, int dl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  // the LDS layout of the window kind of the forward (fwd_window)
   int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1]
-  T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(D.n + 1) * 4 + 15) / 16 * 16);
-  CellStage<T> &C = *reinterpret_cast<CellStage<T> *>(red + (CDZ_NT / 64) * 72);
-  T *W = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(CellStage<T>) + 15) / 16 * 16);
+  CellStage<T> &C = *reinterpret_cast<CellStage<T> *>(smem_raw + WinLayout<T>::stage(D.n));
+  T *W = reinterpret_cast<T *>(smem_raw + WinLayout<T>::blocks(D.n));
   const int n = D.n, tid = threadIdx.x, ncell = n - dl;
   const int i = cdz_cell_of_block(blockIdx.x, ncell), j = i + dl;
   if (i >= ncell) return;
@@ -1039,8 +1233,8 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_arec_diag(DevProb<T> D, int dl) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int dl) {
-  fwd_cell<T>(D, dl, blockIdx.x);
+__global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int t) {
+  fwd_block<T>(D, t, blockIdx.x);
 }
 
 // Batched wavefront: one launch runs diagonal dl of every problem of a batch.
@@ -1052,7 +1246,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag_batch(const DevProb<T> *p
   int b, w;
   cdz_batch_locate(off, count, blockIdx.x, b, w);
   const DevProb<T> D = probs[b];
-  fwd_cell<T>(D, dl, w);
+  fwd_block<T>(D, dl, w);
 }
 
 // per problem b of a batch: the span-truncated exterior prefix (span W[b]),
@@ -1074,6 +1268,16 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_spread_check_batch(const DevProb<T
 }
 
 template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_exterior_scan(DevProb<T> D, int W, int jend) {
+  exterior_scan_body<T>(D, W, jend, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_exterior_scan_batch(const DevProb<T> *probs, const int *W,
+                                                                 const int *jend, int per) {
+  const int b = blockIdx.x / per;
+  exterior_scan_body<T>(probs[b], W[b], jend[b], blockIdx.x % per);
+}
+template <typename T>
 __global__ __launch_bounds__(64) void cdz_exterior_trunc(DevProb<T> D, int W) {
   exterior_trunc_body<T>(D, W);
 }
@@ -1086,6 +1290,10 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_spread_check(DevProb<T> D) {
   spread_check_body<T>(D, blockIdx.x);
 }
 
+template __global__ void cdz_exterior_scan<float>(DevProb<float>, int, int);
+template __global__ void cdz_exterior_scan<double>(DevProb<double>, int, int);
+template __global__ void cdz_exterior_scan_batch<float>(const DevProb<float> *, const int *, const int *, int);
+template __global__ void cdz_exterior_scan_batch<double>(const DevProb<double> *, const int *, const int *, int);
 template __global__ void cdz_exterior_trunc<float>(DevProb<float>, int);
 template __global__ void cdz_exterior_trunc<double>(DevProb<double>, int);
 template __global__ void cdz_landscape<float>(DevProb<float>);

@@ -278,8 +278,10 @@ size_t carve(char *base, const HostTables &t, DevProb<T> &D, DevAdj<T> &A, bool 
   D.tab = c.take<T>(base, TB_LEN);
   D.Bhp = c.take<T>(base, n);
   D.E = c.take<int>(base, n + 1);
+  D.EX = c.take<int>(base, n + 5);
   D.maxb = c.take<unsigned>(base, n + 1);
   D.Z5 = c.take<double>(base, (size_t)n * 6);
+  D.A5 = c.take<double>(base, (size_t)n * 6);
   D.G5 = c.take<int>(base, n);
   D.Z3 = c.take<double>(base, (size_t)n * 6);
   D.H3 = c.take<int>(base, n);
@@ -353,6 +355,8 @@ __global__ void cdz_landscape(DevProb<T> D);
 template <typename T>
 __global__ void cdz_exterior_trunc(DevProb<T> D, int W);
 template <typename T>
+__global__ void cdz_exterior_scan(DevProb<T> D, int W, int jend);
+template <typename T>
 __global__ void cdz_spread_check(DevProb<T> D);
 
 
@@ -361,17 +365,24 @@ static cdz_status forward_pass(cdz_handle *h, DevProb<T> &D, size_t shm, bool ti
   const int n = D.n;
   hipStream_t st = h->stream;
   HIPCHK(h, hipMemsetAsync(D.maxb, 0, (n + 1) * sizeof(unsigned), st));
+  HIPCHK(h, hipMemsetAsync(D.E, 0, (n + 1) * sizeof(int), st));  // E[0] = 0
   DevProb<T> Dl = D;
-  for (int dl = 0; dl <= dlmax; dl++) {
-    const int ncell = n - dl > 0 ? n - dl : 0;
-    if (!D.AL) {  // diagonal-major A: this diagonal's slot and that of dl - 2
-      Dl.ALw = al_slot_ptr(D, al_slot_fwd(D.alK, D.alTop, dl));
-      Dl.ALp = al_slot_ptr(D, al_slot_fwd(D.alK, D.alTop, dl >= 2 ? dl - 2 : 0));
+  for (int t = 0; t <= dlmax && t < n; t++) {
+    if (!D.AL) {  // diagonal-major A: the window sums of launch t write diagonal t+1 and read t-1
+      Dl.ALw = al_slot_ptr(D, al_slot_fwd(D.alK, D.alTop, t + 1));
+      Dl.ALp = al_slot_ptr(D, al_slot_fwd(D.alK, D.alTop, t >= 1 ? t - 1 : 0));
     }
-    if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
-    hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(cdz_cells_grid(ncell) + 1), dim3(CDZ_NT), shm, st, Dl, dl);
-    if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
+    if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * t], st));
+    hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(fwd_nblocks(n, t)), dim3(CDZ_NT), shm, st, Dl, t);
+    if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * t + 1], st));
   }
+  // exterior loops over the finished diagonals: the exact pass runs the
+  // prefix and suffix scans (log Z twice); the truncated pass of the FP32
+  // landscape the prefix of its first W positions (cdz_exterior_trunc goes on)
+  if (dlmax >= n - 1)
+    hipLaunchKernelGGL(cdz_exterior_scan<T>, dim3(2), dim3(CDZ_NT), scan_lds_bytes(n), st, D, n - 1, n - 1);
+  else
+    hipLaunchKernelGGL(cdz_exterior_scan<T>, dim3(1), dim3(CDZ_NT), scan_lds_bytes(n), st, D, dlmax, dlmax - 1);
   HIPCHK(h, hipGetLastError());
   return CDZ_OK;
 }
@@ -384,6 +395,10 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   if (shm > (size_t)h->lds_max)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the forward kernel");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_fwd_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  if (scan_lds_bytes(n) > (size_t)h->lds_max)
+    return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the exterior scan");
+  HIPCHK(h, hipFuncSetAttribute((const void *)cdz_exterior_scan<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)scan_lds_bytes(n)));
   const bool fp32 = std::is_same<T, float>::value;
   HIPCHK(h, hipMemsetAsync(D.res, 0, 8 * sizeof(double), st));
   if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
@@ -392,12 +407,17 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   double res[8];
   // range check of the exact pass: flags res[5] (weak cell) and res[6]
   // (non-finite entry), read back into res
+  int checks = 0;
   auto range_check = [&]() -> cdz_status {
-    HIPCHK(h, hipMemsetAsync(D.res + 5, 0, 2 * sizeof(double), st));
+    HIPCHK(h, hipMemsetAsync(D.res + 5, 0, 3 * sizeof(double), st));
     hipLaunchKernelGGL(cdz_spread_check<T>, dim3(n), dim3(CDZ_NT), 0, st, D);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipMemcpyAsync(res, D.res, sizeof(res), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
+    int deep = 0;
+    memcpy(&deep, &res[7], sizeof(int));
+    (checks++ == 0 ? h->weakest_first : h->weakest_final) = -deep;
+    h->weakest_final = -deep;
     return CDZ_OK;
   };
   h->landscape_retries = 0;
@@ -443,13 +463,13 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   h->times[0] = ms;
   if (h->profiling) {
     double tot = 0;
-    for (int dl = 0; dl <= n; dl++) {
+    for (int dl = 0; dl < n; dl++) {
       float k = 0;
       HIPCHK(h, hipEventElapsedTime(&k, h->pev[2 * dl], h->pev[2 * dl + 1]));
       tot += k;
     }
     h->prof_fwd_ms = tot;
-    h->prof_fwd_launches = n + 1;
+    h->prof_fwd_launches = n;
   }
   if (!std::isfinite(res[0]) || !std::isfinite(res[1]))
     return cdz_fail(h, CDZ_ERR_NUMERIC, "log Z not finite (scaling out of range)");
@@ -588,6 +608,12 @@ extern "C" int cdz_debug_set_span(cdz_handle *h, int W) {
   return CDZ_OK;
 }
 extern "C" int cdz_debug_landscape_retries(const cdz_handle *h) { return h ? h->landscape_retries : -1; }
+extern "C" int cdz_debug_weakest(const cdz_handle *h, int *first, int *final_) {
+  if (!h || !first || !final_) return CDZ_ERR_ARG;
+  *first = h->weakest_first;
+  *final_ = h->weakest_final;
+  return CDZ_OK;
+}
 extern "C" int cdz_debug_set_low_exp(cdz_handle *h, int e) {
   if (!h || e < 0 || e > 1074) return CDZ_ERR_ARG;
   h->low_exp = e;

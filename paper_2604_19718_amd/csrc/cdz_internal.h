@@ -81,6 +81,7 @@ struct cdz_handle {
   int al_k_forced = -2;        // test hook: storage of A to use regardless of budget (-2: by budget)
   int span = 0;                   // fixed span of the truncated landscape pass (0: by length)
   int low_exp = 0;                // range-check threshold exponent (0: by precision, spread_low)
+  int weakest_first = 0, weakest_final = 0;  // binary exponent of the weakest cell: first and last range check
   std::string err;
   void *ws = nullptr;
   size_t ws_bytes = 0;

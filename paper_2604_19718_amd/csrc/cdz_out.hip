@@ -1337,13 +1337,23 @@ extern "C" cdz_status cdz_marginals(cdz_handle *h, const cdz_problem *prob, doub
   return assemble_marginals(h, t, eta_dev(h), pair_dev(h), r, pair, base, codon, codon_pair);
 }
 
+// the edge marginals the outside pass writes (edges p = 0..n-2, slots below
+// d[p] x d[p+1]; the padding of each 6 x 6 block is never written) are finite
+static bool edge_marginals_finite(const HostTables &t, const std::vector<double> &eta) {
+  for (int p = 0; p + 1 < t.n; p++)
+    for (int u = 0; u < t.d[p]; u++)
+      for (int w = 0; w < t.d[p + 1]; w++)
+        if (!std::isfinite(eta[(size_t)p * 36 + u * 6 + w])) return false;
+  return true;
+}
+
 cdz_status assemble_marginals(cdz_handle *h, const HostTables &t, const double *eta_dev, const double *pair_dev,
                               double r, double *pair, double *base, double *codon, double *codon_pair) {
   const int n = t.n, m = t.m;
   std::vector<double> eta((size_t)n * 36);
   HIPCHK(h, hipMemcpy(eta.data(), eta_dev, eta.size() * 8, hipMemcpyDeviceToHost));
-  for (double x : eta)
-    if (!std::isfinite(x)) return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite edge marginals (outside pass out of range)");
+  if (!edge_marginals_finite(t, eta))
+    return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite edge marginals (outside pass out of range)");
   std::vector<double> cod((size_t)m * 6, 0.0);
   for (int a = 0; a < m; a++)
     for (int c = 0; c < t.d[3 * a]; c++) cod[a * 6 + c] = r * eta[(size_t)(3 * a) * 36 + c * 6 + c];
@@ -1408,9 +1418,8 @@ extern "C" cdz_status cdz_backward_dev(cdz_handle *h, double grad_logz, double *
   {
     std::vector<double> eta((size_t)h->tables.n * 36);
     HIPCHK(h, hipMemcpy(eta.data(), eta_dev(h), eta.size() * 8, hipMemcpyDeviceToHost));
-    for (double x : eta)
-      if (!std::isfinite(x))
-        return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite edge marginals (outside pass out of range)");
+    if (!edge_marginals_finite(h->tables, eta))
+      return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite edge marginals (outside pass out of range)");
   }
   const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz_scaled);
   hipLaunchKernelGGL(cdz_grad_theta, dim3(h->tables.m), dim3(64), 0, h->stream, eta_dev(h), d_dev(h),
