@@ -272,7 +272,7 @@ cdz_status chunk_outside(cdz_handle *h, Chunk<T> &C) {
                                 (int)shm));
   std::vector<int> n(cnt);
   for (int b = 0; b < cnt; b++) n[b] = C.t[b]->n;
-  const Launches Lo(cnt, nmax, [&](int b, int dl) { return dl <= n[b] - 1 ? cdz_cells_grid(n[b] - dl) : 0; });
+  const Launches Lo(cnt, nmax, [&](int b, int dl) { return dl <= n[b] - 1 ? out_nblocks(n[b], dl) : 0; });
   const Launches Le(cnt, 1, [&](int b, int) { return n[b] >= 2 ? n[b] - 1 : 0; });
   Meta m;
   const size_t oP = m.put(C.D.data(), cnt * sizeof(DevProb<T>));
@@ -292,6 +292,8 @@ cdz_status chunk_outside(cdz_handle *h, Chunk<T> &C) {
     const size_t S2b = (size_t)D.ld * D.ld * sizeof(T);
     HIPCHK(h, hipMemsetAsync(A.UbL, 0, S2b, st));
     HIPCHK(h, hipMemsetAsync(A.UbR, 0, S2b, st));
+    HIPCHK(h, hipMemsetAsync(A.UbL2, 0, S2b, st));
+    HIPCHK(h, hipMemsetAsync(A.UbR2, 0, S2b, st));
     HIPCHK(h, hipMemsetAsync(A.DIbL, 0, S2b, st));
     HIPCHK(h, hipMemsetAsync(A.DIbR, 0, S2b, st));
     HIPCHK(h, hipMemsetAsync(A.etaV, 0, (size_t)n[b] * 36 * sizeof(double), st));

@@ -27,6 +27,7 @@
 #define CDZ_NA 27      // interior-loop sizes L = 2..28 kept per cell (the recursion in
                        // L reads L - 2 <= 28; sizes 29, 30 only feed the cell itself)
 #define CDZ_NWIN 496    // (l1, l2) pairs with l1 + l2 <= 30, including (0, 0)
+#define CDZ_NRING 29    // interior-loop adjoints by size kept per cell by the outside pass (L = 2..30)
 
 // Boltzmann table offsets inside DevProb::tab
 #define TB_ST 0      // stack [6][6]
@@ -158,6 +159,23 @@ __host__ __device__ __forceinline__ int fwd_nblocks(int n, int t) {
   int r[4];
   fwd_ranges(n, t, r);
   return r[0] + r[1] + r[2] + r[3];
+}
+// Workgroups of outside launch t (t = n-1..0), in block order: interior-loop
+// pushes of diagonal t+1 (8 <= t+1 < n), bulge pushes of diagonal t+1
+// (7 <= t+1 < n), bulge gathers of diagonal t-1 (4 <= t-1 <= n-2), split
+// gathers of diagonal t-4 (4 <= t-4 <= n-5), finish of diagonal t.
+__host__ __device__ __forceinline__ void out_ranges(int n, int t, int r[5]) {
+  const int a = t + 1, b = t - 1, c = t - 4;
+  r[0] = a >= 8 && a <= n - 1 ? cdz_cells_grid(n - a) : 0;
+  r[1] = a >= 7 && a <= n - 1 ? cdz_cells_grid(n - a) : 0;
+  r[2] = b >= 4 && b <= n - 2 ? cdz_cells_grid(n - b) : 0;
+  r[3] = c >= 4 && c <= n - 5 ? cdz_cells_grid(n - c) : 0;
+  r[4] = t >= 0 && t <= n - 1 ? cdz_cells_grid(n - t) : 0;
+}
+__host__ __device__ __forceinline__ int out_nblocks(int n, int t) {
+  int r[5];
+  out_ranges(n, t, r);
+  return r[0] + r[1] + r[2] + r[3] + r[4];
 }
 __device__ __forceinline__ int cdz_cell_of_block(int w, int ncell) {
   return (w % CDZ_NXCD) * ((ncell + CDZ_NXCD - 1) / CDZ_NXCD) + w / CDZ_NXCD;

@@ -59,8 +59,9 @@ struct HostTables {
 template <typename T>
 struct DevAdj {
   T *Qbb, *Qm1b, *Qm1pb, *QmXb, *QmXbt, *Qmb, *Qm1Lb, *DIb, *Gb, *Fb, *Ub, *UbL, *UbR;
+  T *UbL2, *UbR2;  // run adjoints pushed by bulges (by row, and by column stored transposed)
   T *DIbL, *DIbR;  // DI adjoint pushed along row i+1 / column j-1 of the enclosing cells (DIbR transposed)
-  T *ring;         // [3][n][CDZ_NA][36] interior-loop adjoints by size, last three diagonals
+  T *ring;         // [3][n][CDZ_NRING][36] interior-loop adjoints by size, last three diagonals
   double *etaV, *etaW;  // [n][36] edge-marginal terms of the size recursion
   double *eta;   // [n][6][6] edge marginals times Z / 2^EZ
   double *pair;  // [n][n] pair probabilities (upper triangle)

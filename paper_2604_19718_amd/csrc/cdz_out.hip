@@ -28,10 +28,10 @@ void adj_carve(size_t &off, char *base, const HostTables &t, DevAdj<T> &A, size_
     off += bytes;
     return p;
   };
-  T **arrs[] = {&A.Qbb, &A.Qm1b, &A.Qm1pb, &A.QmXb, &A.QmXbt, &A.Qmb, &A.Qm1Lb,
-                &A.DIb, &A.Gb, &A.Fb, &A.Ub, &A.UbL, &A.UbR, &A.DIbL, &A.DIbR};
+  T **arrs[] = {&A.Qbb, &A.Qm1b, &A.Qm1pb, &A.QmXb, &A.QmXbt, &A.Qmb, &A.Qm1Lb, &A.DIb, &A.Gb,
+                &A.Fb, &A.Ub, &A.UbL, &A.UbR, &A.UbL2, &A.UbR2, &A.DIbL, &A.DIbR};
   for (T **a : arrs) *a = reinterpret_cast<T *>(take(S2 * sizeof(T)));
-  A.ring = reinterpret_cast<T *>(take((size_t)3 * t.n * CDZ_NA * 36 * sizeof(T)));
+  A.ring = reinterpret_cast<T *>(take((size_t)3 * t.n * CDZ_NRING * 36 * sizeof(T)));
   A.etaV = reinterpret_cast<double *>(take((size_t)t.n * 36 * sizeof(double)));
   A.etaW = reinterpret_cast<double *>(take((size_t)t.n * 36 * sizeof(double)));
   A.eta = reinterpret_cast<double *>(take((size_t)t.n * 36 * sizeof(double)));
@@ -54,7 +54,8 @@ struct OutStage {
   T qbOut[36];   // Qb'[i-1][j+1]
   T gbOut[36];   // Gb at block (i, j): dressed adjoint of the enclosing pair
   T ubRight[36]; // U'[i][j+1]
-  T ubl[36], ubr[36];  // pushed run adjoints of [i..j]
+  T ubl[36], ubr[36];  // run adjoints of [i..j] pushed by interior loops and hairpins
+  T ubl2[36], ubr2[36];  // run adjoints of [i..j] pushed by bulges
   T acc[72], w[72], qm1pb[36], qm1lb[36], qm1b[36], qbb[36], gb[36], fb[36];
   double z5[6], z3[6], edm1[36];
   signed char nt[6][6];
@@ -91,14 +92,36 @@ __device__ __forceinline__ void ostage_t(T *dst, const T *At, long long ld, int 
   dst[q] = (ok && r < dr && c < dc) ? At[(long long)(c0 + c) * ld + r0 + r] : T(0);
 }
 
-// ring of interior-loop adjoints: diagonal dl, cell i, size L (4..30)
+// ring of interior-loop adjoints: diagonal dl, cell i, size L (2..30)
 template <typename T>
 __device__ __forceinline__ T *ring_at(const DevAdj<T> &A, int n, int dl, int i, int L) {
-  return A.ring + (((long long)(dl % 3) * n + i) * CDZ_NA + (L - 4)) * 36;
+  return A.ring + (((long long)(dl % 3) * n + i) * CDZ_NRING + (L - 2)) * 36;
 }
 
+// ---------------------------------------------------------------------------
+// One launch per step t = n-1..0.  The adjoint of a cell is split by what it
+// reads, and each piece runs as its own workgroups in the launch where its
+// inputs are final (adjoints flow from longer to shorter spans); the pieces
+// of one launch never read each other's results:
+//   interior pushes (diagonal t+1)  the size-recursion boundary terms of the
+//                                   cell's interior loops: DI' and run
+//                                   adjoints pushed to shorter spans, and the
+//                                   edge terms of V and W (eta)
+//   bulge pushes    (diagonal t+1)  run adjoints of the cell's bulges, into
+//                                   their own accumulators (UbL2, UbR2)
+//   bulge gathers   (diagonal t-1)  the part of Qb' from the enclosing bulges
+//                                   (reads Gb of spans >= t+1)
+//   split gathers   (diagonal t-4)  Qm' and Qm1L' (read QmX' of spans >= t+1)
+//   finish          (diagonal t)    the O(1) adjoint statements, Qb' (with the
+//                                   gathered parts), Gb, Fb, the adjoints of
+//                                   the interior-loop sums by size (ring),
+//                                   the hairpin run push, the run total Ub
+// ---------------------------------------------------------------------------
+
+// ---- split gathers of the cells of diagonal dl (launch dl + 4): Qm'[i][j]
+//      and Qm1L'[i-1][j], complete (no other statement reaches them)
 template <typename T>
-__device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A, int dl, int blk) {
+__device__ __forceinline__ void out_split(const DevProb<T> &D, const DevAdj<T> &A, int dl, int blk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = D.n, tid = threadIdx.x;
   const long long ld = D.ld;
@@ -135,60 +158,6 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
   const bool hasL = i >= 1, hasR = j + 1 <= n - 1;
   const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
   const int *ll_d = C.wd + 64, *ll_P = C.wP + 64, *rr_d = C.wd + 96, *rr_P = C.wP + 96;
-  {
-    const int g = tid / 36, q = tid % 36;
-    switch (g) {
-      case 0:
-        ostage(C.m1pUp, A.Qm1pb, ld, Pim1, Pj, dim1, dj, q, hasL);
-        ostage(C.m1Right, A.Qm1b, ld, Pi, Pjp1, di, djp1, q, hasR);
-        break;
-      case 1:
-        ostage(C.qbOut, A.Qbb, ld, Pim1, Pjp1, dim1, djp1, q, hasL && hasR);
-        ostage(C.gbOut, A.Gb, ld, Pi, Pj, di, dj, q, hasL && hasR);
-        break;
-      case 2:
-        ostage(C.ubRight, A.Ub, ld, Pi, Pjp1, di, djp1, q, hasR);
-        ostage(C.ubl, A.UbL, ld, Pi, Pj, di, dj, q, true);
-        ostage_t(C.ubr, A.UbR, ld, Pi, Pj, di, dj, q, true);
-        break;
-      case 3:
-        C.eIm1[q] = hasL ? D.e[(i - 1) * 36 + q] : T(0);
-        C.eI[q] = D.e[i * 36 + q];
-        C.eJm1[q] = j >= 1 ? D.e[(j - 1) * 36 + q] : T(0);
-        C.eJ[q] = D.e[j * 36 + q];
-        C.eI1[q] = i + 1 < n ? D.e[(i + 1) * 36 + q] : T(0);
-        C.eJm2[q] = j >= 2 ? D.e[(j - 2) * 36 + q] : T(0);
-        break;
-      case 4:
-        C.edm1[q] = hasL ? D.ed[(i - 1) * 36 + q] : 0.0;
-        if (q < 6) {
-          C.vIm1[q] = hasL ? D.v[(i - 1) * 6 + q] : T(0);
-          C.vI[q] = D.v[i * 6 + q];
-          C.vJ[q] = D.v[j * 6 + q];
-          C.vJp1[q] = hasR ? D.v[(j + 1) * 6 + q] : T(0);
-          C.vI1[q] = i + 1 < n ? D.v[(i + 1) * 6 + q] : T(0);
-          C.vJm1[q] = j >= 1 ? D.v[(j - 1) * 6 + q] : T(0);
-          C.z5[q] = hasL ? D.Z5[(i - 1) * 6 + q] : 0.0;
-          C.z3[q] = D.Z3[j * 6 + q];
-        }
-        break;
-      case 5: {
-        // adjoint of DI at block (i-1, j+1): pushed by the enclosing loops
-        T v = 0;
-        const int r = q / 6, c = q % 6;
-        if (hasL && hasR && r < dim1 && c < djp1) {
-          const long long o = (long long)(Pim1 + r) * ld + Pjp1 + c, ot = (long long)(Pjp1 + c) * ld + Pim1 + r;
-          v = A.DIbL[o] + A.DIbR[ot];
-        }
-        C.w[q] = v;
-        break;
-      }
-    }
-  }
-  cdz_sync();
-  const T *tab = C.tab;
-  if (dl >= 4) {
-    const int lmax = min(CDZ_MAXLOOP, dl - 6);
     // ---- split gathers: Qm'[i][j] along row i, Qm1L'[i][j] down column j
     {
       constexpr int UN = 2;
@@ -251,6 +220,59 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       }
       cdz_block_sum<T, 72>(acc, red, C.acc);
     }
+  if (tid < 36) {
+    const int s = tid / 6, t = tid % 6;
+    if (s < di && t < dj) A.Qmb[(Pi + s) * ld + Pj + t] = C.acc[tid];
+    if (hasL && s < dim1 && t < dj) A.Qm1Lb[(Pim1 + s) * ld + Pj + t] = C.acc[36 + tid];
+  }
+}
+
+// ---- bulge gathers of the cells of diagonal dl (launch dl + 1): the part of
+//      Qb'[i][j] from the bulges that enclose (i, j), into Qbb (completed by
+//      the finish of the cell)
+template <typename T>
+__device__ __forceinline__ void out_bulge_gather(const DevProb<T> &D, const DevAdj<T> &A, int dl, int blk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = D.n, tid = threadIdx.x;
+  const long long ld = D.ld;
+  int *sE = reinterpret_cast<int *>(smem_raw);
+  T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
+  OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
+  T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
+  T *X = AB + 29 * 36;
+  cdz_copy_ints(sE, D.E, n);
+  const int EZ = (int)D.res[2];
+  const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
+  if (i >= n - dl) return;
+  if (tid < 6) {
+    const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
+    const int p = pos[tid];
+    const bool ok = p >= 0 && p < n;
+    C.d[tid] = ok ? D.d[p] : 0;
+    C.P[tid] = ok ? D.P[p] : 0;
+#pragma unroll
+    for (int s = 0; s < 6; s++) C.nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
+  }
+  for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+  if (tid >= 128) {
+    const int q = tid - 128, grp = q / 32, o = q % 32;
+    const int p = grp == 0 ? i + 1 + o : grp == 1 ? j - 1 - o : grp == 2 ? i - 1 - o : j + 1 + o;
+    const bool ok = p >= 0 && p < n;
+    C.wd[q] = ok ? D.d[p] : 0;
+    C.wP[q] = ok ? D.P[p] : 0;
+  }
+  if (tid < 36) {
+    C.eIm1[tid] = i >= 1 ? D.e[(i - 1) * 36 + tid] : T(0);
+    C.eJ[tid] = D.e[j * 36 + tid];
+  }
+  cdz_sync();
+  const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
+  const int dim1 = C.d[0], Pim1 = C.P[0], djp1 = C.d[5], Pjp1 = C.P[5];
+  const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
+  const bool hasL = i >= 1, hasR = j + 1 <= n - 1;
+  const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
+  const int *ll_d = C.wd + 64, *ll_P = C.wP + 64, *rr_d = C.wd + 96, *rr_P = C.wP + 96;
+  const T *tab = C.tab;
     // ---- bulges enclosing the pair (i, j): the bulge part of Qb'[i][j].
     //      Left bulge (i-l1-1, j+1): run i-l1..i-1; right bulge
     //      (i-1, j+l2+1): run j+1..j+l2.
@@ -330,6 +352,119 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       }
       cdz_sync();
     }
+  if (tid < 36) {
+    const int s = tid / 6, t = tid % 6;
+    if (s < di && t < dj) A.Qbb[(Pi + s) * ld + Pj + t] = C.w[36 + tid];
+  }
+}
+
+// ---- finish of the cells of diagonal dl (launch dl)
+template <typename T>
+__device__ __forceinline__ void out_finish(const DevProb<T> &D, const DevAdj<T> &A, int dl, int blk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = D.n, tid = threadIdx.x;
+  const long long ld = D.ld;
+  int *sE = reinterpret_cast<int *>(smem_raw);
+  T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
+  OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
+  T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
+  T *X = AB + 29 * 36;
+  cdz_copy_ints(sE, D.E, n);
+  const int EZ = (int)D.res[2];
+  const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
+  if (i >= n - dl) return;
+  if (tid < 6) {
+    const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
+    const int p = pos[tid];
+    const bool ok = p >= 0 && p < n;
+    C.d[tid] = ok ? D.d[p] : 0;
+    C.P[tid] = ok ? D.P[p] : 0;
+#pragma unroll
+    for (int s = 0; s < 6; s++) C.nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
+  }
+  for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+  if (tid >= 128) {
+    const int q = tid - 128, grp = q / 32, o = q % 32;
+    const int p = grp == 0 ? i + 1 + o : grp == 1 ? j - 1 - o : grp == 2 ? i - 1 - o : j + 1 + o;
+    const bool ok = p >= 0 && p < n;
+    C.wd[q] = ok ? D.d[p] : 0;
+    C.wP[q] = ok ? D.P[p] : 0;
+  }
+  cdz_sync();
+  const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
+  const int dim1 = C.d[0], Pim1 = C.P[0], djp1 = C.d[5], Pjp1 = C.P[5];
+  const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
+  const bool hasL = i >= 1, hasR = j + 1 <= n - 1;
+  const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
+  const int *ll_d = C.wd + 64, *ll_P = C.wP + 64, *rr_d = C.wd + 96, *rr_P = C.wP + 96;
+  {
+    for (int idx = tid; idx < 8 * 36; idx += CDZ_NT) {
+    const int g = idx / 36, q = idx % 36;
+    switch (g) {
+      case 0:
+        ostage(C.m1pUp, A.Qm1pb, ld, Pim1, Pj, dim1, dj, q, hasL);
+        ostage(C.m1Right, A.Qm1b, ld, Pi, Pjp1, di, djp1, q, hasR);
+        break;
+      case 1:
+        ostage(C.qbOut, A.Qbb, ld, Pim1, Pjp1, dim1, djp1, q, hasL && hasR);
+        ostage(C.gbOut, A.Gb, ld, Pi, Pj, di, dj, q, hasL && hasR);
+        break;
+      case 2:
+        ostage(C.ubRight, A.Ub, ld, Pi, Pjp1, di, djp1, q, hasR);
+        ostage(C.ubl, A.UbL, ld, Pi, Pj, di, dj, q, true);
+        ostage_t(C.ubr, A.UbR, ld, Pi, Pj, di, dj, q, true);
+        break;
+      case 3:
+        C.eIm1[q] = hasL ? D.e[(i - 1) * 36 + q] : T(0);
+        C.eI[q] = D.e[i * 36 + q];
+        C.eJm1[q] = j >= 1 ? D.e[(j - 1) * 36 + q] : T(0);
+        C.eJ[q] = D.e[j * 36 + q];
+        C.eI1[q] = i + 1 < n ? D.e[(i + 1) * 36 + q] : T(0);
+        C.eJm2[q] = j >= 2 ? D.e[(j - 2) * 36 + q] : T(0);
+        break;
+      case 4:
+        C.edm1[q] = hasL ? D.ed[(i - 1) * 36 + q] : 0.0;
+        if (q < 6) {
+          C.vIm1[q] = hasL ? D.v[(i - 1) * 6 + q] : T(0);
+          C.vI[q] = D.v[i * 6 + q];
+          C.vJ[q] = D.v[j * 6 + q];
+          C.vJp1[q] = hasR ? D.v[(j + 1) * 6 + q] : T(0);
+          C.vI1[q] = i + 1 < n ? D.v[(i + 1) * 6 + q] : T(0);
+          C.vJm1[q] = j >= 1 ? D.v[(j - 1) * 6 + q] : T(0);
+          C.z5[q] = hasL ? D.Z5[(i - 1) * 6 + q] : 0.0;
+          C.z3[q] = D.Z3[j * 6 + q];
+        }
+        break;
+      case 5: {
+        // adjoint of DI at block (i-1, j+1): pushed by the enclosing loops
+        T v = 0;
+        const int r = q / 6, c = q % 6;
+        if (hasL && hasR && r < dim1 && c < djp1) {
+          const long long o = (long long)(Pim1 + r) * ld + Pjp1 + c, ot = (long long)(Pjp1 + c) * ld + Pim1 + r;
+          v = A.DIbL[o] + A.DIbR[ot];
+        }
+        C.w[q] = v;
+        break;
+      }
+      case 6: {  // split gathers of the cell, stored by out_split (diagonals 4..n-5)
+        const bool sp = dl >= 4 && dl <= n - 5;
+        ostage(C.acc, A.Qmb, ld, Pi, Pj, di, dj, q, sp);
+        ostage(C.acc + 36, A.Qm1Lb, ld, Pim1, Pj, dim1, dj, q, sp && hasL);
+        break;
+      }
+      case 7:  // bulge part of Qb' (out_bulge_gather, diagonals 4..n-2); bulge-pushed runs
+        ostage(C.w + 36, A.Qbb, ld, Pi, Pj, di, dj, q, dl >= 4 && dl <= n - 2);
+        ostage(C.ubl2, A.UbL2, ld, Pi, Pj, di, dj, q, true);
+        ostage_t(C.ubr2, A.UbR2, ld, Pi, Pj, di, dj, q, true);
+        break;
+    }
+    }
+  }
+
+  cdz_sync();
+  const T *tab = C.tab;
+  if (dl >= 4) {
+    const int lmax = min(CDZ_MAXLOOP, dl - 6);
     const int s = tid / 6, t = tid % 6;
     // ---- Qm', QmX', Qm1p', Qm1L', DI' (all operands in LDS)
     if (tid < 36) {
@@ -505,10 +640,94 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
           }
         }
         AB[idx] = v;
-        if (L >= 4) ring_at(A, n, dl, i, L)[q] = v;
+        ring_at(A, n, dl, i, L)[q] = v;
       }
       cdz_sync();
     }
+    // hairpin closed by (i, j): its run i+1..j-1 (block distinct from the runs above)
+    if (tid < 36 && s < d1 && t < dm)
+      A.UbL[(P1 + s) * ld + Pm + t] += D.Bhp[dl - 1] * cdz_p2<T>(sE[dl - 2] - sE[dl]) * C.fb[tid];
+  } else if (tid < 36) {
+    const int s = tid / 6, t = tid % 6;
+    if (s < di && t < dj) {
+      const long long o = (Pi + s) * ld + Pj + t;
+      A.Qbb[o] = 0;
+      A.Qm1b[o] = 0;
+      A.Qm1pb[o] = 0;
+      A.QmXb[o] = 0;
+      A.Qmb[o] = 0;
+      A.QmXbt[(Pj + t) * ld + Pi + s] = 0;
+    }
+  }
+  // ---- total adjoint of the unpaired run [i..j]: the runs pushed into by
+  //      enclosing interior loops (UbL, UbR), bulges (UbL2, UbR2) and
+  //      hairpins (UbL), and the run extended by j + 1
+  if (tid < 36) {
+    const int a = tid / 6, c = tid % 6;
+    if (a < di && c < dj) {
+      T u = C.ubl[tid] + C.ubr[tid] + C.ubl2[tid] + C.ubr2[tid];
+      if (hasR) {
+        T sm = 0;
+#pragma unroll
+        for (int b = 0; b < 6; b++) sm += C.ubRight[a * 6 + b] * C.eJ[c * 6 + b] * C.vJp1[b];
+        u += sm * cdz_p2<T>(sE[dl] - sE[dl + 1]);
+      }
+      A.Ub[(Pi + a) * ld + Pj + c] = u;
+    }
+  }
+}
+
+
+// ---- interior-loop pushes of the cells of diagonal dl (launch dl - 1), from
+//      the adjoints by size that the finish of the cell left in the ring
+template <typename T>
+__device__ __forceinline__ void out_int_push(const DevProb<T> &D, const DevAdj<T> &A, int dl, int blk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = D.n, tid = threadIdx.x;
+  const long long ld = D.ld;
+  int *sE = reinterpret_cast<int *>(smem_raw);
+  T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
+  OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
+  T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
+  T *X = AB + 29 * 36;
+  cdz_copy_ints(sE, D.E, n);
+  const int EZ = (int)D.res[2];
+  const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
+  if (i >= n - dl) return;
+  if (tid < 6) {
+    const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
+    const int p = pos[tid];
+    const bool ok = p >= 0 && p < n;
+    C.d[tid] = ok ? D.d[p] : 0;
+    C.P[tid] = ok ? D.P[p] : 0;
+#pragma unroll
+    for (int s = 0; s < 6; s++) C.nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
+  }
+  for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+  if (tid >= 128) {
+    const int q = tid - 128, grp = q / 32, o = q % 32;
+    const int p = grp == 0 ? i + 1 + o : grp == 1 ? j - 1 - o : grp == 2 ? i - 1 - o : j + 1 + o;
+    const bool ok = p >= 0 && p < n;
+    C.wd[q] = ok ? D.d[p] : 0;
+    C.wP[q] = ok ? D.P[p] : 0;
+  }
+  if (tid < 36) {
+    C.eI1[tid] = i + 1 < n ? D.e[(i + 1) * 36 + tid] : T(0);
+    C.eJm2[tid] = j >= 2 ? D.e[(j - 2) * 36 + tid] : T(0);
+    if (tid < 6) {
+      C.vI1[tid] = i + 1 < n ? D.v[(i + 1) * 6 + tid] : T(0);
+      C.vJm1[tid] = j >= 1 ? D.v[(j - 1) * 6 + tid] : T(0);
+    }
+  }
+  const int lmax = min(CDZ_MAXLOOP, dl - 6);
+  for (int idx = tid; idx < (lmax - 1) * 36; idx += CDZ_NT) AB[idx] = ring_at(A, n, dl, i, idx / 36 + 2)[idx % 36];
+  cdz_sync();
+  const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
+  const int dim1 = C.d[0], Pim1 = C.P[0], djp1 = C.d[5], Pjp1 = C.P[5];
+  const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
+  const bool hasL = i >= 1, hasR = j + 1 <= n - 1;
+  const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
+  const int *ll_d = C.wd + 64, *ll_P = C.wP + 64, *rr_d = C.wd + 96, *rr_P = C.wP + 96;
     if (lmax >= 2) {
       // ---- interior loops closed by (i, j): adjoints of the blocks the size
       //      recursion reads directly (the l1 = 1 and l2 = 1 terms)
@@ -661,6 +880,54 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
       }
       cdz_sync();
     }
+}
+
+// ---- bulge pushes of the cells of diagonal dl (launch dl - 1): run adjoints
+//      of the bulges closed by (i, j), from the cell's Gb, into UbL2 / UbR2
+template <typename T>
+__device__ __forceinline__ void out_bulge_push(const DevProb<T> &D, const DevAdj<T> &A, int dl, int blk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = D.n, tid = threadIdx.x;
+  const long long ld = D.ld;
+  int *sE = reinterpret_cast<int *>(smem_raw);
+  T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
+  OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
+  T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
+  T *X = AB + 29 * 36;
+  cdz_copy_ints(sE, D.E, n);
+  const int EZ = (int)D.res[2];
+  const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
+  if (i >= n - dl) return;
+  if (tid < 6) {
+    const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
+    const int p = pos[tid];
+    const bool ok = p >= 0 && p < n;
+    C.d[tid] = ok ? D.d[p] : 0;
+    C.P[tid] = ok ? D.P[p] : 0;
+#pragma unroll
+    for (int s = 0; s < 6; s++) C.nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
+  }
+  for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+  if (tid >= 128) {
+    const int q = tid - 128, grp = q / 32, o = q % 32;
+    const int p = grp == 0 ? i + 1 + o : grp == 1 ? j - 1 - o : grp == 2 ? i - 1 - o : j + 1 + o;
+    const bool ok = p >= 0 && p < n;
+    C.wd[q] = ok ? D.d[p] : 0;
+    C.wP[q] = ok ? D.P[p] : 0;
+  }
+  {
+    const int P1g = D.P[i + 1], Pmg = D.P[j - 1], d1g = D.d[i + 1], dmg = D.d[j - 1];
+    if (tid < 36) ostage(C.gb, A.Gb, ld, P1g, Pmg, d1g, dmg, tid, true);
+  }
+  cdz_sync();
+  const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
+  const int dim1 = C.d[0], Pim1 = C.P[0], djp1 = C.d[5], Pjp1 = C.P[5];
+  const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
+  const bool hasL = i >= 1, hasR = j + 1 <= n - 1;
+  const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
+  const int *ll_d = C.wd + 64, *ll_P = C.wP + 64, *rr_d = C.wd + 96, *rr_P = C.wP + 96;
+  const T *tab = C.tab;
+  const int lmax = min(CDZ_MAXLOOP, dl - 6);
     if (lmax >= 1) {
       // ---- bulges closed by (i, j): adjoints of their runs. Left bulge
       //      l1: run i+1..i+l1, inner pair (i+l1+1, j-1); right bulge l2:
@@ -732,7 +999,7 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
 #pragma unroll
       for (int m = 0; m < NPB; m++) {
         const bool left = (tid + m * CDZ_NT) / 36 < lmax;
-        old[m] = off[m] >= 0 ? (left ? A.UbL : A.UbR)[off[m]] : T(0);
+        old[m] = off[m] >= 0 ? (left ? A.UbL2 : A.UbR2)[off[m]] : T(0);
       }
 #pragma unroll
       for (int m = 0; m < NPB; m++) {
@@ -750,40 +1017,39 @@ __device__ __forceinline__ void out_cell(const DevProb<T> &D, const DevAdj<T> &A
 #pragma unroll
           for (int y = 0; y < 6; y++) v += el[y * 6 + r] * qk[y * 6 + c];
         }
-        (side == 0 ? A.UbL : A.UbR)[off[m]] = old[m] + f * v;
+        (side == 0 ? A.UbL2 : A.UbR2)[off[m]] = old[m] + f * v;
       }
     }
-    // hairpin closed by (i, j): its run i+1..j-1 (block distinct from the runs above)
-    if (tid < 36 && s < d1 && t < dm)
-      A.UbL[(P1 + s) * ld + Pm + t] += D.Bhp[dl - 1] * cdz_p2<T>(sE[dl - 2] - sE[dl]) * C.fb[tid];
-  } else if (tid < 36) {
-    const int s = tid / 6, t = tid % 6;
-    if (s < di && t < dj) {
-      const long long o = (Pi + s) * ld + Pj + t;
-      A.Qbb[o] = 0;
-      A.Qm1b[o] = 0;
-      A.Qm1pb[o] = 0;
-      A.QmXb[o] = 0;
-      A.Qmb[o] = 0;
-      A.QmXbt[(Pj + t) * ld + Pi + s] = 0;
-    }
-  }
-  // ---- total adjoint of the unpaired run [i..j] (operands staged before the
-  //      pushes above, which only touch runs strictly inside [i+1..j-1])
-  if (tid < 36) {
-    const int a = tid / 6, c = tid % 6;
-    if (a < di && c < dj) {
-      T u = C.ubl[tid] + C.ubr[tid];
-      if (hasR) {
-        T sm = 0;
-#pragma unroll
-        for (int b = 0; b < 6; b++) sm += C.ubRight[a * 6 + b] * C.eJ[c * 6 + b] * C.vJp1[b];
-        u += sm * cdz_p2<T>(sE[dl] - sE[dl + 1]);
-      }
-      A.Ub[(Pi + a) * ld + Pj + c] = u;
-    }
-  }
 }
+
+// One workgroup of outside launch t; w is its index among this problem's workgroups
+template <typename T>
+__device__ __forceinline__ void out_block(const DevProb<T> &D, const DevAdj<T> &A, int t, int w) {
+  int r[5];
+  out_ranges(D.n, t, r);
+  if (w < r[0]) {
+    out_int_push<T>(D, A, t + 1, w);
+    return;
+  }
+  w -= r[0];
+  if (w < r[1]) {
+    out_bulge_push<T>(D, A, t + 1, w);
+    return;
+  }
+  w -= r[1];
+  if (w < r[2]) {
+    out_bulge_gather<T>(D, A, t - 1, w);
+    return;
+  }
+  w -= r[2];
+  if (w < r[3]) {
+    out_split<T>(D, A, t - 4, w);
+    return;
+  }
+  w -= r[3];
+  out_finish<T>(D, A, t, w);
+}
+
 
 // ---------------------------------------------------------------------------
 // Edge marginals: one workgroup per backbone edge p (between p and p+1)
@@ -1157,7 +1423,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
 
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A, int dl) {
-  out_cell<T>(D, A, dl, blockIdx.x);
+  out_block<T>(D, A, dl, blockIdx.x);
 }
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A) {
@@ -1172,7 +1438,7 @@ __global__ __launch_bounds__(CDZ_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T
   cdz_batch_locate(off, count, blockIdx.x, b, w);
   const DevProb<T> D = probs[b];
   const DevAdj<T> A = adjs[b];
-  out_cell<T>(D, A, dl, w);
+  out_block<T>(D, A, dl, w);
 }
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_eta_batch(const DevProb<T> *probs, const DevAdj<T> *adjs,
@@ -1242,14 +1508,17 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   // accumulators of pushed adjoints start at zero
   HIPCHK(h, hipMemsetAsync(A.UbL, 0, S2b, st));
   HIPCHK(h, hipMemsetAsync(A.UbR, 0, S2b, st));
+  HIPCHK(h, hipMemsetAsync(A.UbL2, 0, S2b, st));
+  HIPCHK(h, hipMemsetAsync(A.UbR2, 0, S2b, st));
   HIPCHK(h, hipMemsetAsync(A.DIbL, 0, S2b, st));
   HIPCHK(h, hipMemsetAsync(A.DIbR, 0, S2b, st));
   HIPCHK(h, hipMemsetAsync(A.etaV, 0, (size_t)n * 36 * sizeof(double), st));
   HIPCHK(h, hipMemsetAsync(A.etaW, 0, (size_t)n * 36 * sizeof(double), st));
   if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
-  // memory-bounded form: the cells of diagonal dl read A of diagonal dl - 2
-  // (when dl >= 10); the band of K diagonals holding it is rebuilt from its
-  // two checkpoint diagonals the first time the pass reaches it
+  // memory-bounded form: the interior pushes of diagonal t + 1 (launch t)
+  // read A of diagonal t - 1 (when t + 1 >= 10); the band of K diagonals
+  // holding it is rebuilt from its two checkpoint diagonals the first time
+  // the pass reaches it
   DevProb<T> Dl = D;
   int band = -1;
   const int K = D.alK, top = D.alTop;
@@ -1260,8 +1529,8 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
                                   (int)shf));
   }
   for (int dl = n - 1; dl >= 0; dl--) {
-    if (!D.AL && dl >= 10) {
-      const int x = dl - 2, k = x / K;
+    if (!D.AL && dl + 1 >= 10 && dl + 1 <= n - 1) {
+      const int x = dl - 1, k = x / K;
       if (k != band) {
         DevProb<T> Dr = D;
         for (int y = std::max(4, k * K); y <= x; y++) {
@@ -1275,7 +1544,7 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
       Dl.ALp = al_slot_ptr(D, al_slot_band(K, top, x));
     }
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
-    hipLaunchKernelGGL(cdz_out_diag<T>, dim3(cdz_cells_grid(n - dl)), dim3(CDZ_NT), shm, st, Dl, A, dl);
+    hipLaunchKernelGGL(cdz_out_diag<T>, dim3(out_nblocks(n, dl)), dim3(CDZ_NT), shm, st, Dl, A, dl);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
   }
   HIPCHK(h, hipGetLastError());
