@@ -161,21 +161,23 @@ __host__ __device__ __forceinline__ int fwd_nblocks(int n, int t) {
   return r[0] + r[1] + r[2] + r[3];
 }
 // Workgroups of outside launch t (t = n-1..0), in block order: interior-loop
-// pushes of diagonal t+1 (8 <= t+1 < n), bulge pushes of diagonal t+1
-// (7 <= t+1 < n), bulge gathers of diagonal t-1 (4 <= t-1 <= n-2), split
-// gathers of diagonal t-4 (4 <= t-4 <= n-5), finish of diagonal t.
-__host__ __device__ __forceinline__ void out_ranges(int n, int t, int r[5]) {
+// pushes of diagonal t+1 (8 <= t+1 < n), edge terms of the size recursion of
+// diagonal t+1 (10 <= t+1 < n), bulge pushes of diagonal t+1 (7 <= t+1 < n),
+// bulge gathers of diagonal t-1 (4 <= t-1 <= n-2), split gathers of diagonal
+// t-4 (4 <= t-4 <= n-5), finish of diagonal t.
+__host__ __device__ __forceinline__ void out_ranges(int n, int t, int r[6]) {
   const int a = t + 1, b = t - 1, c = t - 4;
   r[0] = a >= 8 && a <= n - 1 ? cdz_cells_grid(n - a) : 0;
-  r[1] = a >= 7 && a <= n - 1 ? cdz_cells_grid(n - a) : 0;
-  r[2] = b >= 4 && b <= n - 2 ? cdz_cells_grid(n - b) : 0;
-  r[3] = c >= 4 && c <= n - 5 ? cdz_cells_grid(n - c) : 0;
-  r[4] = t >= 0 && t <= n - 1 ? cdz_cells_grid(n - t) : 0;
+  r[1] = a >= 10 && a <= n - 1 ? cdz_cells_grid(n - a) : 0;
+  r[2] = a >= 7 && a <= n - 1 ? cdz_cells_grid(n - a) : 0;
+  r[3] = b >= 4 && b <= n - 2 ? cdz_cells_grid(n - b) : 0;
+  r[4] = c >= 4 && c <= n - 5 ? cdz_cells_grid(n - c) : 0;
+  r[5] = t >= 0 && t <= n - 1 ? cdz_cells_grid(n - t) : 0;
 }
 __host__ __device__ __forceinline__ int out_nblocks(int n, int t) {
-  int r[5];
+  int r[6];
   out_ranges(n, t, r);
-  return r[0] + r[1] + r[2] + r[3] + r[4];
+  return r[0] + r[1] + r[2] + r[3] + r[4] + r[5];
 }
 __device__ __forceinline__ int cdz_cell_of_block(int w, int ncell) {
   return (w % CDZ_NXCD) * ((ncell + CDZ_NXCD - 1) / CDZ_NXCD) + w / CDZ_NXCD;
@@ -262,6 +264,17 @@ __device__ __forceinline__ void cdz_copy_blocks(T *dst, const T *src, int nblk, 
       dst[(rev ? nblk - 1 - b : b) * 36 + f % 36] = v[k];
     }
   }
+}
+
+// Exponents of the diagonals a cell's statements read, into sE at their own
+// indices: E[0..31] (short spans: loops of up to 30 unpaired bases) and
+// E[c-w .. c+w] (around the cell's diagonal c), both below m; other entries
+// of sE are not written.
+__device__ __forceinline__ void cdz_copy_exponents(int *sE, const int *E, int m, int c, int w) {
+  const int lo = m < 32 ? m : 32;
+  const int a = c - w > lo ? c - w : lo, b = c + w + 1 < m ? c + w + 1 : m;
+  for (int k = threadIdx.x; k < lo; k += CDZ_NT) sE[k] = E[k];
+  for (int k = a + (int)threadIdx.x; k < b; k += CDZ_NT) sE[k] = E[k];
 }
 
 // Copy count ints from global src to LDS dst (both 16-byte aligned) with

@@ -338,7 +338,7 @@ __device__ __forceinline__ void fwd_window(const DevProb<T> &D, int t, int dl, i
   const int i = cdz_cell_of_block(blk, ncell), j = i + dl;
   if (i >= ncell) return;
   const int Ed = exponent_ahead(D, t, dl);
-  cdz_copy_ints(sE, D.E, dl);  // E[0..dl-1]; E[dl] below
+  cdz_copy_exponents(sE, D.E, dl, dl, 34);  // the spans the window reads; E[dl] below
   load_positions(D, i, j, C.d, C.P, (signed char(*)[6]) nullptr);
   load_window_positions(D, i, j, C.wd, C.wP);
   if (tid >= 128 && tid < 164) {
@@ -388,7 +388,7 @@ __device__ __forceinline__ void fwd_bulges(const DevProb<T> &D, int t, int dl, i
   if (i >= ncell) return;
   const int Ed = exponent_ahead(D, t, dl);
   const int lmax = min(CDZ_MAXLOOP, dl - 6);
-  cdz_copy_ints(sE, D.E, dl);
+  cdz_copy_exponents(sE, D.E, dl, dl, 34);  // the spans the bulges read
   load_positions(D, i, j, C.d, C.P, (signed char(*)[6]) nullptr);
   load_window_positions(D, i, j, C.wd, C.wP);
   if (tid >= 128 && tid < 128 + 31) tb[tid - 128] = D.tab[TB_BU + tid - 128];

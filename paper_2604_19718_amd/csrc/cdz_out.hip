@@ -105,8 +105,9 @@ __device__ __forceinline__ T *ring_at(const DevAdj<T> &A, int n, int dl, int i, 
 // of one launch never read each other's results:
 //   interior pushes (diagonal t+1)  the size-recursion boundary terms of the
 //                                   cell's interior loops: DI' and run
-//                                   adjoints pushed to shorter spans, and the
-//                                   edge terms of V and W (eta)
+//                                   adjoints pushed to shorter spans
+//   edge terms      (diagonal t+1)  the uses of e_{i+1} and e_{j-2} inside the
+//                                   size recursion (eta)
 //   bulge pushes    (diagonal t+1)  run adjoints of the cell's bulges, into
 //                                   their own accumulators (UbL2, UbR2)
 //   bulge gathers   (diagonal t-1)  the part of Qb' from the enclosing bulges
@@ -240,7 +241,7 @@ __device__ __forceinline__ void out_bulge_gather(const DevProb<T> &D, const DevA
   OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
   T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
   T *X = AB + 29 * 36;
-  cdz_copy_ints(sE, D.E, n);
+  cdz_copy_exponents(sE, D.E, n, dl, 34);
   const int EZ = (int)D.res[2];
   const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
   if (i >= n - dl) return;
@@ -369,7 +370,7 @@ __device__ __forceinline__ void out_finish(const DevProb<T> &D, const DevAdj<T> 
   OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
   T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
   T *X = AB + 29 * 36;
-  cdz_copy_ints(sE, D.E, n);
+  cdz_copy_exponents(sE, D.E, n, dl, 34);
   const int EZ = (int)D.res[2];
   const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
   if (i >= n - dl) return;
@@ -690,7 +691,7 @@ __device__ __forceinline__ void out_int_push(const DevProb<T> &D, const DevAdj<T
   OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
   T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
   T *X = AB + 29 * 36;
-  cdz_copy_ints(sE, D.E, n);
+  cdz_copy_exponents(sE, D.E, n, dl, 34);
   const int EZ = (int)D.res[2];
   const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
   if (i >= n - dl) return;
@@ -834,6 +835,59 @@ __device__ __forceinline__ void out_int_push(const DevProb<T> &D, const DevAdj<T
       }
       __syncthreads();  // the bulge pushes below update some of the same runs
     }
+}
+
+// ---- edge terms of the size recursion of the cells of diagonal dl (launch
+//      dl - 1): the uses of e_{i+1} in V and e_{j-2} in W, from the cell's
+//      adjoints by size (ring) and A of the inner cell, into etaV / etaW
+template <typename T>
+__device__ __forceinline__ void out_edge_terms(const DevProb<T> &D, const DevAdj<T> &A, int dl, int blk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = D.n, tid = threadIdx.x;
+  const long long ld = D.ld;
+  int *sE = reinterpret_cast<int *>(smem_raw);
+  T *red = reinterpret_cast<T *>(smem_raw + ((size_t)(n + 1) * 4 + 15) / 16 * 16);
+  OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
+  T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
+  T *X = AB + 29 * 36;
+  cdz_copy_exponents(sE, D.E, n, dl, 34);
+  const int EZ = (int)D.res[2];
+  const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
+  if (i >= n - dl) return;
+  if (tid < 6) {
+    const int pos[6] = {i - 1, i, i + 1, j - 1, j, j + 1};
+    const int p = pos[tid];
+    const bool ok = p >= 0 && p < n;
+    C.d[tid] = ok ? D.d[p] : 0;
+    C.P[tid] = ok ? D.P[p] : 0;
+#pragma unroll
+    for (int s = 0; s < 6; s++) C.nt[tid][s] = ok ? D.nt[p * 6 + s] : (signed char)-1;
+  }
+  for (int q = tid; q < TB_LEN; q += CDZ_NT) C.tab[q] = D.tab[q];
+  if (tid >= 128) {
+    const int q = tid - 128, grp = q / 32, o = q % 32;
+    const int p = grp == 0 ? i + 1 + o : grp == 1 ? j - 1 - o : grp == 2 ? i - 1 - o : j + 1 + o;
+    const bool ok = p >= 0 && p < n;
+    C.wd[q] = ok ? D.d[p] : 0;
+    C.wP[q] = ok ? D.P[p] : 0;
+  }
+  if (tid < 36) {
+    C.eI1[tid] = i + 1 < n ? D.e[(i + 1) * 36 + tid] : T(0);
+    C.eJm2[tid] = j >= 2 ? D.e[(j - 2) * 36 + tid] : T(0);
+    if (tid < 6) {
+      C.vI1[tid] = i + 1 < n ? D.v[(i + 1) * 6 + tid] : T(0);
+      C.vJm1[tid] = j >= 1 ? D.v[(j - 1) * 6 + tid] : T(0);
+    }
+  }
+  const int lmax = min(CDZ_MAXLOOP, dl - 6);
+  for (int idx = tid; idx < (lmax - 1) * 36; idx += CDZ_NT) AB[idx] = ring_at(A, n, dl, i, idx / 36 + 2)[idx % 36];
+  cdz_sync();
+  const int di = C.d[1], dj = C.d[4], Pi = C.P[1], Pj = C.P[4];
+  const int dim1 = C.d[0], Pim1 = C.P[0], djp1 = C.d[5], Pjp1 = C.P[5];
+  const int d1 = C.d[2], dm = C.d[3], P1 = C.P[2], Pm = C.P[3];
+  const bool hasL = i >= 1, hasR = j + 1 <= n - 1;
+  const int *lp_d = C.wd, *lp_P = C.wP, *rp_d = C.wd + 32, *rp_P = C.wP + 32;
+  const int *ll_d = C.wd + 64, *ll_P = C.wP + 64, *rr_d = C.wd + 96, *rr_P = C.wP + 96;
     if (lmax >= 4) {
       // ---- edges e_{i+1} (in V) and e_{j-2} (in W) of the size recursion:
       //      their share of the edge marginals
@@ -894,7 +948,7 @@ __device__ __forceinline__ void out_bulge_push(const DevProb<T> &D, const DevAdj
   OutStage<T> &C = *reinterpret_cast<OutStage<T> *>(red + (CDZ_NT / 64) * 72);
   T *AB = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(&C) + (sizeof(OutStage<T>) + 15) / 16 * 16);
   T *X = AB + 29 * 36;
-  cdz_copy_ints(sE, D.E, n);
+  cdz_copy_exponents(sE, D.E, n, dl, 34);
   const int EZ = (int)D.res[2];
   const int i = cdz_cell_of_block(blk, n - dl), j = i + dl;
   if (i >= n - dl) return;
@@ -1025,7 +1079,7 @@ __device__ __forceinline__ void out_bulge_push(const DevProb<T> &D, const DevAdj
 // One workgroup of outside launch t; w is its index among this problem's workgroups
 template <typename T>
 __device__ __forceinline__ void out_block(const DevProb<T> &D, const DevAdj<T> &A, int t, int w) {
-  int r[5];
+  int r[6];
   out_ranges(D.n, t, r);
   if (w < r[0]) {
     out_int_push<T>(D, A, t + 1, w);
@@ -1033,20 +1087,25 @@ __device__ __forceinline__ void out_block(const DevProb<T> &D, const DevAdj<T> &
   }
   w -= r[0];
   if (w < r[1]) {
-    out_bulge_push<T>(D, A, t + 1, w);
+    out_edge_terms<T>(D, A, t + 1, w);
     return;
   }
   w -= r[1];
   if (w < r[2]) {
-    out_bulge_gather<T>(D, A, t - 1, w);
+    out_bulge_push<T>(D, A, t + 1, w);
     return;
   }
   w -= r[2];
   if (w < r[3]) {
-    out_split<T>(D, A, t - 4, w);
+    out_bulge_gather<T>(D, A, t - 1, w);
     return;
   }
   w -= r[3];
+  if (w < r[4]) {
+    out_split<T>(D, A, t - 4, w);
+    return;
+  }
+  w -= r[4];
   out_finish<T>(D, A, t, w);
 }
 
