@@ -75,17 +75,22 @@ def algorithmic_bytes_out(d: np.ndarray, w: int) -> float:
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cdz_out_diag_float_900nt_traffic.md")
 
 
-def source_sha256() -> str:
-    """Hash of the kernel sources (the key under which traffic counters were taken)."""
-    import glob
+# the sources each diagonal kernel is compiled from
+KERNEL_SOURCES = {
+    "out": ["paper_2604_19718_amd/csrc/cdz_out.hip", "paper_2604_19718_amd/csrc/cdz_internal.h",
+            "paper_2604_19718_amd/csrc/cdz_dev.h", "include/cdz.h"],
+    "fwd": ["paper_2604_19718_amd/csrc/cdz_fwd.hip", "paper_2604_19718_amd/csrc/cdz_dev.h"],
+}
+
+
+def source_sha256(kernel: str = "out") -> str:
+    """Hash of the sources a diagonal kernel is compiled from (the key under which
+    its traffic counters were taken)."""
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2604_19718_amd", "csrc", "*.hip")) +
-                   glob.glob(os.path.join(ROOT, "paper_2604_19718_amd", "csrc", "*.h")) +
-                   [os.path.join(ROOT, "include", "cdz.h")])
-    for f in files:
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for rel in KERNEL_SOURCES[kernel]:
+        h.update(os.path.basename(rel).encode())
+        with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 

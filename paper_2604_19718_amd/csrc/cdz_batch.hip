@@ -173,7 +173,7 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
   if (fp32) {
     s = fwd_pass<T>(h, dP, (const int *)(dev + oTr), Ltr, shm);
     if (s != CDZ_OK) return s;
-    hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(cnt), dim3(CDZ_NT), scan_lds_bytes(nmax), st, dP,
+    hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(cnt), dim3(CDZ_SCAN_NT), scan_lds_bytes(nmax), st, dP,
                        (const int *)(dev + oW), (const int *)(dev + oWm1), 1);
     hipLaunchKernelGGL(cdz_exterior_trunc_batch<T>, dim3(cnt), dim3(64), 0, st, dP, (const int *)(dev + oW));
     hipLaunchKernelGGL(cdz_landscape_batch<T>, dim3(cnt), dim3(1024), 0, st, dP);
@@ -188,7 +188,7 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
     s = fwd_pass<T>(h, dP, (const int *)(dev + oEx), Lex, shm);
     if (s != CDZ_OK) return s;
   }
-  hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(2 * cnt), dim3(CDZ_NT), scan_lds_bytes(nmax), st, dP,
+  hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(2 * cnt), dim3(CDZ_SCAN_NT), scan_lds_bytes(nmax), st, dP,
                      (const int *)(dev + oNm1), (const int *)(dev + oNm1), 2);
   // range check of every exact pass: flags res[5] (weak cell), res[6]
   // (non-finite entry); FP32 problems with weak cells repeat the pass once
@@ -231,7 +231,7 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
       }
       s = fwd_pass<T>(h, dR, (const int *)(dev + rO), Lr, shm);
       if (s != CDZ_OK) return s;
-      hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(2 * rc), dim3(CDZ_NT), scan_lds_bytes(nmax), st, dR,
+      hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(2 * rc), dim3(CDZ_SCAN_NT), scan_lds_bytes(nmax), st, dR,
                          (const int *)(dev + rN), (const int *)(dev + rN), 2);
       hipLaunchKernelGGL(cdz_spread_check_batch<T>, dim3(Lrs.total(0)), dim3(CDZ_NT), 0, st, dR,
                          (const int *)(dev + rS), rc);

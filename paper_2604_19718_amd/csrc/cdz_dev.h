@@ -141,8 +141,9 @@ __host__ __device__ __forceinline__ int cdz_cells_grid(int ncell) {
 __host__ __device__ constexpr size_t lds_al(size_t b) { return (b + 15) / 16 * 16; }
 // dynamic LDS of the exterior scans: exponents, slot counts, offsets and the
 // running exponents of n + 1 positions, then FP64 reduction scratch and sums
+#define CDZ_SCAN_NT 1024  // threads per workgroup of the exterior scans
 __host__ __device__ constexpr size_t scan_lds_bytes(int n) {
-  return lds_al((size_t)4 * (n + 1) * 4) + (4 * 6 + 8) * sizeof(double);
+  return lds_al((size_t)4 * (n + 1) * 4) + ((CDZ_SCAN_NT / 64) * 6 + 8) * sizeof(double);
 }
 
 // Workgroups of forward launch t (t = 0..n-1) of a sequence of n positions,
@@ -397,9 +398,11 @@ __device__ __forceinline__ void cdz_rs_dpp(const T (&v)[N], T (&o)[(N + 1) / 2],
   }
 }
 
-// Sum R per-thread values over the workgroup; result in out[0..R) (LDS),
-// visible to all threads after the call.  scratch holds (NT/64) * R values.
-template <typename T, int R>
+// Sum R per-thread values over the workgroup of NT threads; result in
+// out[0..R) (LDS), visible to all threads after the call.  scratch holds
+// (NT/64) * R values.  GLOBAL makes the first barrier a full one, so that
+// global stores issued before the call are visible to the workgroup after it.
+template <typename T, int R, int NT = CDZ_NT, bool GLOBAL = false>
 __device__ __forceinline__ void cdz_block_sum(T (&v)[R], T *scratch, T *out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   constexpr int N1 = (R + 1) / 2, N2 = (N1 + 1) / 2, N3 = (N2 + 1) / 2, N4 = (N3 + 1) / 2,
@@ -427,11 +430,14 @@ __device__ __forceinline__ void cdz_block_sum(T (&v)[R], T *scratch, T *out) {
 #pragma unroll
   for (int q = 0; q < N6; q++)
     if (q < cnt) scratch[wv * R + base + q] = a6[q];
-  cdz_sync();
-  for (int r = threadIdx.x; r < R; r += CDZ_NT) {
+  if constexpr (GLOBAL)
+    __syncthreads();
+  else
+    cdz_sync();
+  for (int r = threadIdx.x; r < R; r += NT) {
     T s = 0;
 #pragma unroll
-    for (int w = 0; w < CDZ_NT / 64; w++) s += scratch[w * R + r];
+    for (int w = 0; w < NT / 64; w++) s += scratch[w * R + r];
     out[r] = s;
   }
   cdz_sync();

@@ -784,52 +784,64 @@ template size_t fwd_lds_bytes<double>(int);
 // Pairs are limited to spans <= W (the truncated pass of the FP32 landscape
 // estimate); the prefix stops after position jend.
 // ---------------------------------------------------------------------------
+// Both recurrences are sequential in the position; each step's pair terms
+// (up to W of them) are spread over the CDZ_SCAN_NT threads, one pair per
+// thread at the workload sizes, so a step costs one round of loads and one
+// workgroup sum.  The per-step factors v and e are fetched a step ahead by
+// the threads that use them, and every thread derives the step's exponent
+// from the sums, so no extra barrier orders it.
 template <typename T>
 __device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, int jend, int dir) {
+  constexpr int NT = CDZ_SCAN_NT;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int n = D.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = D.n, tid = threadIdx.x;
   int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1] diagonal exponents
   int *sd = sE + (n + 1), *sP = sd + (n + 1);   // [n + 1] slot counts and offsets
   int *sX = sP + (n + 1);                       // [n + 1] G5 (prefix) or H3 (suffix)
-  double *red = reinterpret_cast<double *>(smem_raw + lds_al((size_t)4 * (n + 1) * 4));  // [4][6]
-  double *tot = red + 24;                                                                 // [8]
+  double *red = reinterpret_cast<double *>(smem_raw + lds_al((size_t)4 * (n + 1) * 4));  // [NT/64][6]
+  double *tot = red + (NT / 64) * 6;                                                      // [6]
   const long long ld = D.ld;
-  for (int k = tid; k <= n; k += CDZ_NT) {
+  for (int k = tid; k <= n; k += NT) {
     sE[k] = D.E[k];
     sd[k] = k < n ? D.d[k] : 0;
     sP[k] = D.P[k];
   }
   __syncthreads();
-  // workgroup sum of six values per thread into tot[0..5]
-  auto sum6 = [&](double(&v)[6]) __attribute__((always_inline)) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-      for (int t = 0; t < 6; t++) v[t] += __shfl_xor(v[t], off, 64);
-    if (lane == 0)
-#pragma unroll
-      for (int t = 0; t < 6; t++) red[wv * 6 + t] = v[t];
-    __syncthreads();
-    if (tid < 6) {
-      double s = 0;
-#pragma unroll
-      for (int w = 0; w < CDZ_NT / 64; w++) s += red[w * 6 + tid];
-      tot[tid] = s;
-    }
-    __syncthreads();
-  };
   const double L2 = 0.6931471805599453094;
+  // exponent of the largest of six sums (0 for all zero or non-finite)
+  auto step_exponent = [&](int cnt) __attribute__((always_inline)) {
+    double mx = 0;
+#pragma unroll
+    for (int t = 0; t < 6; t++)
+      if (t < cnt) mx = fmax(mx, fabs(tot[t]));
+    return (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
+  };
   if (dir == 0) {
+    // thread x < 6: column x of e_j, v_j(x) and A[j](x)
+    double ecol[6] = {0, 0, 0, 0, 0, 0}, vx = 0, ax = 0;
+    if (tid < 6) {
+      vx = D.vd[tid];
+#pragma unroll
+      for (int q = 0; q < 6; q++) ecol[q] = D.ed[q * 6 + tid];
+    }
+    int R = 0;  // exponent of Z5[j-1]
     for (int j = 0; j <= jend; j++) {
       const int dj = sd[j], Pj = sP[j];
-      const int R = j >= 1 ? sX[j - 1] : 0;
+      double enx[6] = {0, 0, 0, 0, 0, 0}, vnx = 0;
+      if (tid < 6 && j + 1 < n) {
+        vnx = D.vd[(j + 1) * 6 + tid];
+#pragma unroll
+        for (int q = 0; q < 6; q++) enx[q] = D.ed[(j + 1) * 36 + q * 6 + tid];
+      }
       double part[6] = {0, 0, 0, 0, 0, 0};
-      if (j == 0) {
-        if (tid < 6) part[tid] = tid < dj ? D.vd[tid] : 0.0;
-      } else {
-        if (tid < 6 && tid < dj) part[tid] = D.A5[j * 6 + tid] * D.vd[j * 6 + tid];
+      // position j unpaired: A[j](x) v_j(x) (A[0] = 1)
+      const double own = j == 0 ? vx : ax * vx;
+#pragma unroll
+      for (int x = 0; x < 6; x++)
+        if (x == tid && x < dj) part[x] = own;
+      if (j >= 4) {  // j paired with k: A[k] Qb(k, j), Qb read along rows of Qbt
         const int k0 = j - W > 0 ? j - W : 0, nk = j - 4 - k0 + 1;
-        for (int it = tid; it < nk; it += CDZ_NT) {
+        for (int it = tid; it < nk; it += NT) {
           const int k = k0 + it, dk = sd[k], Pk = sP[k];
           double a[6];
           if (k == 0) {
@@ -844,36 +856,44 @@ __device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, i
 #pragma unroll
           for (int t = 0; t < 6; t++) {
             if (t >= dj) break;
-            double s = 0;
+            double sm = 0;
 #pragma unroll
             for (int x = 0; x < 6; x++)
-              if (x < dk) s += a[x] * (double)D.Qbt[(long long)(Pj + t) * ld + Pk + x];
-            part[t] += s;
+              if (x < dk) sm += a[x] * (double)D.Qbt[(long long)(Pj + t) * ld + Pk + x];
+            part[t] += sm;
           }
         }
       }
-      sum6(part);
+      // the full first barrier makes the A[.] stored a step earlier visible
+      cdz_block_sum<double, 6, NT, true>(part, red, tot);
+      const int e = step_exponent(dj);
+      R += e;
       if (tid == 0) {
-        double mx = 0;
-        for (int t = 0; t < 6; t++) mx = fmax(mx, fabs(tot[t]));
-        const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
-        for (int t = 0; t < 6; t++) {
-          const double z = t < dj ? ldexp(tot[t], -e) : 0.0;
-          tot[t] = z;
-          D.Z5[j * 6 + t] = z;
-        }
-        sX[j] = R + e;
-        D.G5[j] = R + e;
+        sX[j] = R;
+        D.G5[j] = R;
       }
-      __syncthreads();
-      if (tid < 6 && j + 1 < n) {  // A[j+1](x) = sum_q Z5[j](q) e_j(q, x)
-        double a = 0;
+      if (tid < 6) {
+        double z[6];
 #pragma unroll
-        for (int q = 0; q < 6; q++) a += tot[q] * D.ed[j * 36 + q * 6 + tid];
-        D.A5[(j + 1) * 6 + tid] = a;
+        for (int q = 0; q < 6; q++) z[q] = q < dj ? ldexp(tot[q], -e) : 0.0;
+        double zt = 0;
+#pragma unroll
+        for (int q = 0; q < 6; q++)
+          if (q == tid) zt = z[q];
+        D.Z5[j * 6 + tid] = zt;
+        if (j + 1 < n) {  // A[j+1](x) = sum_q Z5[j](q) e_j(q, x)
+          double acc = 0;
+#pragma unroll
+          for (int q = 0; q < 6; q++) acc += z[q] * ecol[q];
+          ax = acc;
+          D.A5[(j + 1) * 6 + tid] = acc;
+        }
+#pragma unroll
+        for (int q = 0; q < 6; q++) ecol[q] = enx[q];
+        vx = vnx;
       }
-      __syncthreads();
     }
+    __syncthreads();
     if (tid == 0 && jend == n - 1) {
       double z5 = 0;
       for (int t = 0; t < 6; t++) z5 += D.Z5[(n - 1) * 6 + t];
@@ -883,23 +903,41 @@ __device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, i
     }
     return;
   }
-  // ---- suffix
-  for (int p = n - 1; p >= 0; p--) {
-    const int dp = sd[p];
-    if (p == n - 1) {
-      if (tid < 6) D.Z3[p * 6 + tid] = tid < dp ? 1.0 : 0.0;
-      if (tid == 0) {
-        sX[p] = 0;
-        D.H3[p] = 0;
-      }
-      __syncthreads();
-      continue;
+  // ---- suffix.  Thread s < 6: row s of e_p, v_{p+1}(s) and Z3[p+1](s).
+  double erow[6] = {0, 0, 0, 0, 0, 0}, vs = 0, zs = 0;
+  const int dlast = sd[n - 1];
+  if (tid < 6) {
+    zs = tid < dlast ? 1.0 : 0.0;
+    D.Z3[(n - 1) * 6 + tid] = zs;
+    vs = D.vd[(n - 1) * 6 + tid];
+    if (n >= 2) {
+#pragma unroll
+      for (int x = 0; x < 6; x++) erow[x] = D.ed[(n - 2) * 36 + tid * 6 + x];
     }
-    const int R = sX[p + 1], d1 = sd[p + 1], P1 = sP[p + 1];
+  }
+  if (tid == 0) {
+    sX[n - 1] = 0;
+    D.H3[n - 1] = 0;
+  }
+  int R = 0;  // exponent of Z3[p+1]
+  for (int p = n - 2; p >= 0; p--) {
+    const int dp = sd[p], d1 = sd[p + 1], P1 = sP[p + 1];
+    double enx[6] = {0, 0, 0, 0, 0, 0}, vnx = 0;
+    if (tid < 6) {
+      vnx = D.vd[p * 6 + tid];
+      if (p >= 1) {
+#pragma unroll
+        for (int x = 0; x < 6; x++) enx[x] = D.ed[(p - 1) * 36 + tid * 6 + x];
+      }
+    }
+    // w(x) over the slots x of position p+1: p+1 unpaired, or paired with jj
     double w[6] = {0, 0, 0, 0, 0, 0};
-    if (tid < 6 && tid < d1) w[tid] = D.vd[(p + 1) * 6 + tid] * D.Z3[(p + 1) * 6 + tid];
+    const double own = vs * zs;
+#pragma unroll
+    for (int x = 0; x < 6; x++)
+      if (x == tid && x < d1) w[x] = own;
     const int j1 = p + 1 + W < n - 1 ? p + 1 + W : n - 1, nj = j1 - (p + 5) + 1;
-    for (int it = tid; it < nj; it += CDZ_NT) {
+    for (int it = tid; it < nj; it += NT) {
       const int jj = p + 5 + it, dq = sd[jj], Pq = sP[jj];
       const double sc = ldexp(1.0, sE[jj - p - 1] + sX[jj] - R);
       double z3[6];
@@ -908,43 +946,58 @@ __device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, i
 #pragma unroll
       for (int x = 0; x < 6; x++) {
         if (x >= d1) break;
-        double s = 0;
+        double sm = 0;
 #pragma unroll
         for (int t = 0; t < 6; t++)
-          if (t < dq) s += (double)D.Qb[(long long)(P1 + x) * ld + Pq + t] * z3[t];
-        w[x] += s;
+          if (t < dq) sm += (double)D.Qb[(long long)(P1 + x) * ld + Pq + t] * z3[t];
+        w[x] += sm;
       }
     }
-    sum6(w);
-    if (tid == 0) {
-      double z[6], mx = 0;
-      for (int s = 0; s < 6; s++) {
-        double a = 0;
-        for (int x = 0; x < 6; x++) a += D.ed[p * 36 + s * 6 + x] * tot[x];
-        z[s] = s < dp ? a : 0.0;
-        mx = fmax(mx, fabs(z[s]));
-      }
-      const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
-      for (int s = 0; s < 6; s++) D.Z3[p * 6 + s] = ldexp(z[s], -e);
-      sX[p] = R + e;
-      D.H3[p] = R + e;
+    cdz_block_sum<double, 6, NT, true>(w, red, tot);
+    // Z3[p](s) = sum_x e_p(s, x) w(x): every thread forms all six for the exponent
+    double mx = 0, zown = 0;
+    if (tid < 64) {  // the first wavefront: lane s < 6 holds row s
+      double z = 0;
+#pragma unroll
+      for (int x = 0; x < 6; x++) z += erow[x] * tot[x];
+      z = tid < dp ? z : 0.0;
+      zown = z;
+      mx = fabs(z);
+#pragma unroll
+      for (int off = 4; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+      if (tid == 0) red[0] = mx;  // published for the other wavefronts below
     }
     __syncthreads();
+    mx = red[0];
+    const int e = (mx > 0 && isfinite(mx)) ? ilogb(mx) : 0;
+    R += e;
+    if (tid == 0) {
+      sX[p] = R;
+      D.H3[p] = R;
+    }
+    if (tid < 6) {
+      zs = ldexp(zown, -e);
+      D.Z3[p * 6 + tid] = zs;
+#pragma unroll
+      for (int x = 0; x < 6; x++) erow[x] = enx[x];
+      vs = vnx;
+    }
   }
+  __syncthreads();
   // total from the suffix: position 0 unpaired, or 0 pairs jj
   {
     double part[6] = {0, 0, 0, 0, 0, 0};
     if (tid == 0)
       for (int s = 0; s < 6; s++) part[0] += D.vd[s] * D.Z3[s];
     const int d0 = sd[0];
-    for (int jj = 4 + tid; jj < n; jj += CDZ_NT) {
+    for (int jj = 4 + tid; jj < n; jj += NT) {
       const int dq = sd[jj], Pq = sP[jj];
       double a = 0;
       for (int x = 0; x < d0; x++)
         for (int t = 0; t < dq; t++) a += (double)D.Qb[(long long)x * ld + Pq + t] * D.Z3[jj * 6 + t];
       part[0] += a * ldexp(1.0, sE[jj] + sX[jj] - sX[0]);
     }
-    sum6(part);
+    cdz_block_sum<double, 6, NT, true>(part, red, tot);
     if (tid == 0) D.res[1] = log(tot[0]) + sX[0] * L2;
   }
 }
@@ -1268,11 +1321,11 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_spread_check_batch(const DevProb<T
 }
 
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_exterior_scan(DevProb<T> D, int W, int jend) {
+__global__ __launch_bounds__(CDZ_SCAN_NT) void cdz_exterior_scan(DevProb<T> D, int W, int jend) {
   exterior_scan_body<T>(D, W, jend, blockIdx.x);
 }
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_exterior_scan_batch(const DevProb<T> *probs, const int *W,
+__global__ __launch_bounds__(CDZ_SCAN_NT) void cdz_exterior_scan_batch(const DevProb<T> *probs, const int *W,
                                                                  const int *jend, int per) {
   const int b = blockIdx.x / per;
   exterior_scan_body<T>(probs[b], W[b], jend[b], blockIdx.x % per);

@@ -380,9 +380,9 @@ static cdz_status forward_pass(cdz_handle *h, DevProb<T> &D, size_t shm, bool ti
   // prefix and suffix scans (log Z twice); the truncated pass of the FP32
   // landscape the prefix of its first W positions (cdz_exterior_trunc goes on)
   if (dlmax >= n - 1)
-    hipLaunchKernelGGL(cdz_exterior_scan<T>, dim3(2), dim3(CDZ_NT), scan_lds_bytes(n), st, D, n - 1, n - 1);
+    hipLaunchKernelGGL(cdz_exterior_scan<T>, dim3(2), dim3(CDZ_SCAN_NT), scan_lds_bytes(n), st, D, n - 1, n - 1);
   else
-    hipLaunchKernelGGL(cdz_exterior_scan<T>, dim3(1), dim3(CDZ_NT), scan_lds_bytes(n), st, D, dlmax, dlmax - 1);
+    hipLaunchKernelGGL(cdz_exterior_scan<T>, dim3(1), dim3(CDZ_SCAN_NT), scan_lds_bytes(n), st, D, dlmax, dlmax - 1);
   HIPCHK(h, hipGetLastError());
   return CDZ_OK;
 }
