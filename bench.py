@@ -136,7 +136,7 @@ def cpu_baseline(prob, en):
 
 def extra_workloads(B, I):
     """The batch of 256 proteins (30..400 residues; forward + outside + 64 samples
-    each, FP32) and the 3900-nt instance (forward + outside, FP32 and FP64; 1000
+    each, FP32; with direct launches and replayed hipGraphs) and the 3900-nt instance (forward + outside, FP32 and FP64; 1000
     samples FP32), each timed once after one warm-up run, by HIP events."""
     out = {}
     probs = []
@@ -146,12 +146,22 @@ def extra_workloads(B, I):
     ns = np.array([p.n for p in probs])
     cells = float((ns * (ns + 1) // 2).sum())
     h = B.cdz_create(en4, "fp32")
-    for rep in range(2):
-        B.cdz_batch(h, probs, 64, I.sampler_seed(4), marginals=True)
-    tm = B.cdz_last_timings(h)
-    out["batch256"] = {"dp_cells": cells, "ms_forward": tm[0], "ms_outside": tm[1], "ms_sample": tm[2],
-                       "dp_cells_per_s": cells / ((tm[0] + tm[1]) / 1e3), "dtype": "f32"}
-    print(f"# batch256 {out['batch256']}", file=sys.stderr, flush=True)
+    import ctypes
+    for graphs in (1, 0):
+        # hipGraphs (the launch-grouping tuner's trial runs capture their own
+        # graphs; the timed run replays the settled one), then direct launches
+        B.lib().cdz_debug_set_graphs(h.ptr, graphs)
+        for rep in range(5 if graphs else 1):
+            B.cdz_batch(h, probs, 64, I.sampler_seed(4), marginals=True)
+        tm = B.cdz_last_timings(h)
+        c, r = ctypes.c_int(0), ctypes.c_int(0)
+        B.lib().cdz_debug_graph_counts(h.ptr, ctypes.byref(c), ctypes.byref(r))
+        rec = {"dp_cells": cells, "ms_forward": tm[0], "ms_outside": tm[1], "ms_sample": tm[2],
+               "dp_cells_per_s": cells / ((tm[0] + tm[1]) / 1e3), "dtype": "f32",
+               "launches": "graph replay" if graphs else "direct", "graph_captures": c.value,
+               "graph_replays": r.value}
+        out["batch256_graphs" if graphs else "batch256"] = rec
+        print(f"# batch256 {rec}", file=sys.stderr, flush=True)
     del h
     prob5, en5 = I.workload(5)
     n5 = prob5.n
@@ -183,6 +193,8 @@ def main():
     ap.add_argument("--extra", action="store_true",
                     help="also time, once each, the 256-protein batch and the 3900-nt "
                          "instance (FP32 and FP64) and report them under extra_workloads")
+    ap.add_argument("--no-freq", dest="freq", action="store_false",
+                    help="skip timing frequency matching (Section S4e) on the same protein")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one device copy of 256 MiB first (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
@@ -268,6 +280,21 @@ def main():
                 "unit": "GB/s", "frac": fwd_ach / HBM_PEAK_GBS, "launches": fl, "avg_launch_ms": fwd_avg,
                 "algorithmic_bytes_per_launch": bytes_fwd / fl}
 
+    # frequency matching (Section S4e) on the same protein, FP32: target bonuses
+    # those its codon weights were drawn from, r_tol 0.002, unlimited history
+    freq = None
+    if args.freq:
+        ft = I.bonus_targets(I.config_seed(3))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fb, ferr, fok = B.cdz_match_frequencies(h32, prob, ft, r_tol=0.002, max_eval=30, history=-1)
+        torch.cuda.synchronize()
+        fms = (time.perf_counter() - t0) * 1e3
+        freq = {"evaluations": len(ferr), "converged": fok, "final_error": float(ferr[-1]),
+                "r_tol": 0.002, "ms_total": fms, "ms_per_evaluation": fms / len(ferr),
+                "errors": [float(e) for e in ferr]}
+        print(f"# frequency matching {len(ferr)} evaluations {fms:.1f} ms", file=sys.stderr, flush=True)
+
     res = {
         "metric": "DP cells/s + ms per forward+outside at 900 nt, FP32-scaled vs FP64, one GPU",
         "value": value, "unit": "DP cells/s", "n_gpus": 1, "steps": args.steps,
@@ -283,6 +310,8 @@ def main():
         "roofline": roof,
         "roofline_forward": roof_fwd,
     }
+    if freq is not None:
+        res["frequency_matching"] = freq
     if args.extra:
         res["extra_workloads"] = extra_workloads(B, I)
     if not args.no_cpu:

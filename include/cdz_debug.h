@@ -54,6 +54,24 @@ int cdz_debug_weakest(const cdz_handle *h, int *first, int *final_);
  * Accepts 0..1074, else CDZ_ERR_ARG. */
 int cdz_debug_set_low_exp(cdz_handle *h, int e);
 
+/* Batched calls run each chunk's forward passes (up to the range check) and
+ * its outside pass as hipGraphs, captured the first time a chunk's launch
+ * sequence is seen and replayed when it recurs.  on = 0 launches every kernel
+ * directly instead (for timing the two); CDZ_ERR_ARG for a null handle. */
+int cdz_debug_set_graphs(cdz_handle *h, int on);
+
+/* Captures and replays of those graphs in the last batched call. */
+int cdz_debug_graph_counts(const cdz_handle *h, int *captures, int *replays);
+
+/* Launch grouping of the diagonal kernels: a launch whose pieces of work (the
+ * workgroup kinds of the forward and outside passes) would take at least wg
+ * workgroups runs fused, one workgroup per cell index doing every kind in
+ * turn; wg = 0 fuses every launch, wg = -1 returns the choice to the
+ * library's tuner (which times candidate thresholds on the first passes of
+ * each class of pass).  Results are the same either way.  CDZ_ERR_ARG for
+ * wg < -1. */
+int cdz_debug_set_fuse(cdz_handle *h, int wg);
+
 /* Copy one workspace array of the last pass to host memory dst (bytes long):
  * which = 0..11 forward arrays (U Qb G F DI Qm1 Qm1Lr Qm1Lt Qm1p QmX Qm Qmt),
  * 12..24 adjoints (Qbb Qm1b Qm1pb QmXb QmXbt Qmb Qm1Lb DIb Gb Fb Ub UbL UbR),

@@ -26,7 +26,7 @@ Algorithm AA with unit mixing): with history m_k = min(m, k),
     gamma = argmin || r_k - DR gamma ||_2,
     x_{k+1} = g_k - DG gamma.
 m = 0 is the plain fixed-point iteration; m < 0 keeps the whole history (the
-paper's runs had no history limit).
+paper's runs had no history limit); m_k never exceeds the dimension of x.
 """
 from __future__ import annotations
 
@@ -102,6 +102,7 @@ def anderson(g: Callable[[np.ndarray], np.ndarray], x0: np.ndarray, tol: float, 
         rs.append(r)
         gs.append(gx)
         mk = k if history < 0 else min(history, k)
+        mk = min(mk, x.size)  # no more differences than dimensions
         if mk == 0:
             x = gx
             continue
@@ -109,7 +110,7 @@ def anderson(g: Callable[[np.ndarray], np.ndarray], x0: np.ndarray, tol: float, 
         DG = np.stack([gs[i + 1] - gs[i] for i in range(k - mk, k)], axis=1)
         gamma = np.linalg.lstsq(DR, r, rcond=None)[0]
         x = gx - DG @ gamma
-    return x, errs, False
+    return xs[-1], errs, False
 
 
 def match_frequencies(prob, energy, f_target: np.ndarray, r_tol: float = 0.002,

@@ -24,7 +24,7 @@ EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_s
            "cdz_forward_dev", "cdz_backward_dev", "cdz_last_timings", "cdz_reset",
            "cdz_set_profiling", "cdz_kernel_timings", "cdz_status_string", "cdz_last_error",
            "cdz_batch", "cdz_partition_batch", "cdz_marginals_batch", "cdz_sample_batch",
-           "cdz_workspace_bytes"]
+           "cdz_workspace_bytes", "cdz_match_frequencies"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -92,12 +92,19 @@ def lib():
                                   ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_workspace_bytes": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+            "cdz_match_frequencies": ([vp, ctypes.POINTER(cdz_problem), _dp, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.c_int32, _dp, _dp, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             # test hooks of include/cdz_debug.h
             "cdz_debug_al_k": ([vp], ctypes.c_int),
             "cdz_debug_force_al_k": ([vp, ctypes.c_int], ctypes.c_int),
             "cdz_debug_set_span": ([vp, ctypes.c_int], ctypes.c_int),
             "cdz_debug_landscape_retries": ([vp], ctypes.c_int),
             "cdz_debug_set_low_exp": ([vp, ctypes.c_int], ctypes.c_int),
+            "cdz_debug_set_graphs": ([vp, ctypes.c_int], ctypes.c_int),
+            "cdz_debug_set_fuse": ([vp, ctypes.c_int], ctypes.c_int),
+            "cdz_debug_graph_counts": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+                                       ctypes.c_int),
             "cdz_debug_weakest": ([vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "cdz_debug_copy": ([vp, ctypes.c_int, vp, ctypes.c_size_t,
                                 ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
@@ -185,6 +192,23 @@ def cdz_sample(h: Handle, prob, seed: int, n_samples: int):
                              cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                              pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return cod, pairs
+
+
+def cdz_match_frequencies(h: Handle, prob, f_target: np.ndarray, r_tol: float = 0.002,
+                          max_eval: int = 30, history: int = -1):
+    """Codon bonuses f [26][6] whose ensemble codon frequencies match those of
+    independent codon choice with f_target; returns (f, errors per evaluation,
+    converged)."""
+    p = _Prob(prob)
+    ft = np.ascontiguousarray(f_target, dtype=np.float64).reshape(26 * 6)
+    f = np.zeros(26 * 6)
+    err = np.zeros(max(int(max_eval), 1))
+    n_eval = ctypes.c_int32(0)
+    conv = ctypes.c_int32(0)
+    h.check(lib().cdz_match_frequencies(h.ptr, ctypes.byref(p.c), _arr(ft), float(r_tol), int(max_eval),
+                                        int(history), _arr(f), _arr(err), ctypes.byref(n_eval),
+                                        ctypes.byref(conv)))
+    return f.reshape(26, 6), err[: n_eval.value].copy(), bool(conv.value)
 
 
 def cdz_sample_noalloc(h: Handle, prob, seed: int, n_samples: int):

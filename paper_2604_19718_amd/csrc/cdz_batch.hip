@@ -25,6 +25,8 @@
 template <typename T>
 __global__ void cdz_fwd_diag_batch(const DevProb<T> *probs, const int *off, int count, int dl);
 template <typename T>
+__global__ void cdz_fwd_diag_batch_fused(const DevProb<T> *probs, const int *off, int count, int dl);
+template <typename T>
 __global__ void cdz_exterior_trunc_batch(const DevProb<T> *probs, const int *W);
 template <typename T>
 __global__ void cdz_exterior_scan_batch(const DevProb<T> *probs, const int *W, const int *jend, int per);
@@ -36,13 +38,92 @@ template <typename T>
 __global__ void cdz_out_diag_batch(const DevProb<T> *probs, const DevAdj<T> *adjs, const int *off, int count,
                                    int dl);
 template <typename T>
+__global__ void cdz_out_diag_batch_fused(const DevProb<T> *probs, const DevAdj<T> *adjs, const int *off, int count,
+                                         int dl);
+template <typename T>
 __global__ void cdz_eta_batch(const DevProb<T> *probs, const DevAdj<T> *adjs, const int *off, int count);
 template <typename T>
 __global__ void cdz_pairprob(DevProb<T> D, DevAdj<T> A, double r);
 
+// Clears of a chunk's per-problem buffers, as kernels, so that a captured
+// sequence holds kernel nodes only.  cdz_clear_fwd: maxb and E of problem
+// blockIdx.x, and its scalars res[0..8) when `all`.
+template <typename T>
+__global__ __launch_bounds__(256) void cdz_clear_fwd(const DevProb<T> *probs, int all) {
+  const DevProb<T> D = probs[blockIdx.x];
+  for (int k = threadIdx.x; k <= D.n; k += 256) {
+    D.maxb[k] = 0u;
+    D.E[k] = 0;
+  }
+  if (all && threadIdx.x < 8) D.res[threadIdx.x] = 0.0;
+}
+
+// cdz_clear_out: the accumulators of pushed adjoints (six S x S arrays and
+// the two per-edge FP64 arrays) of problem blockIdx.x / per, share
+// blockIdx.x % per; every array starts 256-byte aligned and is a multiple of
+// 16 bytes long.
+template <typename T>
+__global__ __launch_bounds__(256) void cdz_clear_out(const DevProb<T> *probs, const DevAdj<T> *adjs, int per) {
+  const int b = blockIdx.x / per, part = blockIdx.x % per;
+  const DevProb<T> D = probs[b];
+  const DevAdj<T> A = adjs[b];
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  const size_t q = (size_t)D.ld * D.ld * sizeof(T) / 16, qe = (size_t)D.n * 36 * sizeof(double) / 16;
+  uint4 *arr[6] = {(uint4 *)A.UbL, (uint4 *)A.UbR, (uint4 *)A.UbL2, (uint4 *)A.UbR2, (uint4 *)A.DIbL,
+                   (uint4 *)A.DIbR};
+  const size_t step = (size_t)per * 256, first = (size_t)part * 256 + threadIdx.x;
+#pragma unroll 1
+  for (int a = 0; a < 6; a++)
+    for (size_t k = first; k < q; k += step) arr[a][k] = z;
+  for (size_t k = first; k < qe; k += step) {
+    ((uint4 *)A.etaV)[k] = z;
+    ((uint4 *)A.etaW)[k] = z;
+  }
+}
+
 namespace {
 
 const double kLn2 = 0.6931471805599453094;
+
+// Enqueue `record(stream)` on the handle's stream through a hipGraph: the
+// sequence is captured (on a stream of its own, where nothing runs) the first
+// time `key` is seen and replayed on later calls with the same key.  record
+// may launch kernels only (no memsets, copies or synchronisation).  With
+// graphs switched off it runs directly on the handle's stream.
+template <typename F>
+cdz_status graph_run(cdz_handle *h, const std::string &key, F record) {
+  if (!h->use_graphs) return record(h->stream);
+  for (auto &g : h->graphs)
+    if (g.key == key) {
+      HIPCHK(h, hipGraphLaunch(g.x, h->stream));
+      h->graph_replays++;
+      return CDZ_OK;
+    }
+  if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  const cdz_status s = record(h->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (s != CDZ_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return s != CDZ_OK ? s : cdz_fail(h, CDZ_ERR_HIP, std::string("stream capture failed: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return cdz_fail(h, CDZ_ERR_HIP, std::string("graph instantiation failed: ") + hipGetErrorString(ei));
+  }
+  if (h->graphs.size() >= 16) {  // a small cache: drop the oldest
+    (void)hipGraphExecDestroy(h->graphs.front().x);
+    (void)hipGraphDestroy(h->graphs.front().g);
+    h->graphs.erase(h->graphs.begin());
+  }
+  h->graphs.push_back({key, g, x});
+  h->graph_captures++;
+  HIPCHK(h, hipGraphLaunch(x, h->stream));
+  return CDZ_OK;
+}
 
 // Host image of the small descriptor buffer of one phase (problem records and
 // launch offset tables), uploaded to the handle's batch buffer in one copy.
@@ -58,15 +139,30 @@ struct Meta {
 
 // Offsets of a sequence of launches over `count` problems: launch l gives
 // problem b wg(b, l) workgroups; its table is the count + 1 prefix sums.
+// With a grouping function wg(b, l, fused) and a threshold, launch l runs
+// fused when its unfused workgroups reach the threshold (fused[l]).
 struct Launches {
   int count = 0, nl = 0;
-  std::vector<int> off;  // [nl][count + 1]
+  std::vector<int> off;      // [nl][count + 1]
+  std::vector<char> fused;  // [nl]
   template <typename F>
-  Launches(int count_, int nl_, F wg) : count(count_), nl(nl_), off((size_t)nl_ * (count_ + 1)) {
+  Launches(int count_, int nl_, F wg) : count(count_), nl(nl_), off((size_t)nl_ * (count_ + 1)), fused(nl_, 0) {
     for (int l = 0; l < nl; l++) {
       int *o = &off[(size_t)l * (count + 1)];
       o[0] = 0;
       for (int b = 0; b < count; b++) o[b + 1] = o[b] + wg(b, l);
+    }
+  }
+  template <typename F>
+  Launches(int count_, int nl_, F wg, int fuse_wg)
+      : count(count_), nl(nl_), off((size_t)nl_ * (count_ + 1)), fused(nl_, 0) {
+    for (int l = 0; l < nl; l++) {
+      long long split = 0;
+      for (int b = 0; b < count; b++) split += wg(b, l, false);
+      fused[l] = split >= fuse_wg;
+      int *o = &off[(size_t)l * (count + 1)];
+      o[0] = 0;
+      for (int b = 0; b < count; b++) o[b + 1] = o[b] + wg(b, l, fused[l] != 0);
     }
   }
   int total(int l) const { return off[(size_t)l * (count + 1) + count]; }
@@ -91,6 +187,17 @@ cdz_status meta_upload(cdz_handle *h, const Meta &m, char **dev) {
   return CDZ_OK;
 }
 
+// key of a captured sequence: phase, precision, the descriptor buffer and
+// workspace it points into, and the descriptor image itself
+std::string graph_key(const cdz_handle *h, const char *phase, size_t tsize, const Meta &m) {
+  std::string k(phase);
+  const void *ptrs[2] = {h->bws, h->ws};
+  k.append(reinterpret_cast<const char *>(&tsize), sizeof(tsize));
+  k.append(reinterpret_cast<const char *>(ptrs), sizeof(ptrs));
+  k.append(m.img.data(), m.img.size());
+  return k;
+}
+
 template <typename T>
 struct Chunk {
   std::vector<const HostTables *> t;
@@ -107,21 +214,27 @@ struct Chunk {
 
 // forward diagonals 0..dlmax[b] of the listed problems (dP: their records)
 template <typename T>
-cdz_status fwd_pass(cdz_handle *h, const DevProb<T> *dP, const int *dOff, const Launches &L, size_t shm) {
+cdz_status fwd_pass(cdz_handle *h, hipStream_t st, const DevProb<T> *dP, const int *dOff, const Launches &L,
+                    size_t shm) {
   for (int l = 0; l < L.nl; l++) {
     const int tot = L.total(l);
     if (tot == 0) continue;
-    hipLaunchKernelGGL(cdz_fwd_diag_batch<T>, dim3(tot), dim3(CDZ_NT), shm, h->stream, dP, dOff + L.at(l),
-                       L.count, l);
+    if (L.fused[l])
+      hipLaunchKernelGGL(cdz_fwd_diag_batch_fused<T>, dim3(tot), dim3(CDZ_NT), shm, st, dP, dOff + L.at(l), L.count,
+                         l);
+    else
+      hipLaunchKernelGGL(cdz_fwd_diag_batch<T>, dim3(tot), dim3(CDZ_NT), shm, st, dP, dOff + L.at(l), L.count, l);
   }
   HIPCHK(h, hipGetLastError());
   return CDZ_OK;
 }
 
-Launches fwd_launches(const std::vector<int> &n, const std::vector<int> &dlmax) {
+Launches fwd_launches(const std::vector<int> &n, const std::vector<int> &dlmax, int fuse_wg) {
   int nl = 0;
   for (int x : dlmax) nl = std::max(nl, x + 1);
-  return Launches((int)n.size(), nl, [&](int b, int t) { return t <= dlmax[b] ? fwd_nblocks(n[b], t) : 0; });
+  return Launches(
+      (int)n.size(), nl, [&](int b, int t, bool fu) { return t <= dlmax[b] ? fwd_nblocks(n[b], t, fu) : 0; },
+      fuse_wg);
 }
 
 // Forward passes of every problem of the chunk (the sequence of the
@@ -137,6 +250,8 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(nmax) + " nt exceeds the LDS layout of the forward kernel");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_fwd_diag_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)shm));
+  HIPCHK(h, hipFuncSetAttribute((const void *)cdz_fwd_diag_batch_fused<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm));
   if (scan_lds_bytes(nmax) > (size_t)h->lds_max)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(nmax) + " nt exceeds the LDS layout of the exterior scan");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_exterior_scan_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -149,7 +264,19 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
     Wm1[b] = W[b] - 1;  // truncated pass: prefix scan of the first W positions
     nm1[b] = n[b] - 1;  // exact pass: pairs of every span, every position
   }
-  const Launches Ltr = fwd_launches(n, W), Lex = fwd_launches(n, full);
+  long long wmax = 0;
+  {
+    int nl = 0;
+    for (int x : n) nl = std::max(nl, x);
+    for (int t = 0; t < nl; t++) {
+      long long w = 0;
+      for (int b = 0; b < cnt; b++) w += t < n[b] ? fwd_nblocks(n[b], t) : 0;
+      wmax = std::max(wmax, w);
+    }
+  }
+  const uint64_t tkey = tune_key(0, true, sizeof(T), wmax);
+  tune_begin(h, tkey);
+  const Launches Ltr = fwd_launches(n, W, h->fuse_wg), Lex = fwd_launches(n, full, h->fuse_wg);
   const Launches Lsp(cnt, 1, [&](int b, int) { return n[b]; });
   Meta m;
   const size_t oP = m.put(C.D.data(), cnt * sizeof(DevProb<T>));
@@ -164,37 +291,32 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
   if (s != CDZ_OK) return s;
   const DevProb<T> *dP = (const DevProb<T> *)(dev + oP);
   HIPCHK(h, hipEventRecord(h->ev[0], st));
-  for (int b = 0; b < cnt; b++) {
-    HIPCHK(h, hipMemsetAsync(C.D[b].res, 0, 8 * sizeof(double), st));
-    HIPCHK(h, hipMemsetAsync(C.D[b].maxb, 0, (n[b] + 1) * sizeof(unsigned), st));
-    HIPCHK(h, hipMemsetAsync(C.D[b].E, 0, (n[b] + 1) * sizeof(int), st));
-  }
   C.res.assign((size_t)cnt * 8, 0.0);
-  if (fp32) {
-    s = fwd_pass<T>(h, dP, (const int *)(dev + oTr), Ltr, shm);
-    if (s != CDZ_OK) return s;
-    hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(cnt), dim3(CDZ_SCAN_NT), scan_lds_bytes(nmax), st, dP,
-                       (const int *)(dev + oW), (const int *)(dev + oWm1), 1);
-    hipLaunchKernelGGL(cdz_exterior_trunc_batch<T>, dim3(cnt), dim3(64), 0, st, dP, (const int *)(dev + oW));
-    hipLaunchKernelGGL(cdz_landscape_batch<T>, dim3(cnt), dim3(1024), 0, st, dP);
-    for (int b = 0; b < cnt; b++) {
-      HIPCHK(h, hipMemsetAsync(C.D[b].maxb, 0, (n[b] + 1) * sizeof(unsigned), st));
-      HIPCHK(h, hipMemsetAsync(C.D[b].E, 0, (n[b] + 1) * sizeof(int), st));
+  // the passes up to the range check: captured once per chunk image, replayed after
+  s = graph_run(h, graph_key(h, "forward", sizeof(T), m), [&](hipStream_t gs) -> cdz_status {
+    hipLaunchKernelGGL(cdz_clear_fwd<T>, dim3(cnt), dim3(256), 0, gs, dP, 1);
+    if (fp32) {
+      cdz_status s2 = fwd_pass<T>(h, gs, dP, (const int *)(dev + oTr), Ltr, shm);
+      if (s2 != CDZ_OK) return s2;
+      hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(cnt), dim3(CDZ_SCAN_NT), scan_lds_bytes(nmax), gs, dP,
+                         (const int *)(dev + oW), (const int *)(dev + oWm1), 1);
+      hipLaunchKernelGGL(cdz_exterior_trunc_batch<T>, dim3(cnt), dim3(64), 0, gs, dP, (const int *)(dev + oW));
+      hipLaunchKernelGGL(cdz_landscape_batch<T>, dim3(cnt), dim3(1024), 0, gs, dP);
+      hipLaunchKernelGGL(cdz_clear_fwd<T>, dim3(cnt), dim3(256), 0, gs, dP, 0);
     }
-    s = fwd_pass<T>(h, dP, (const int *)(dev + oEx), Lex, shm);
-    if (s != CDZ_OK) return s;
+    cdz_status s2 = fwd_pass<T>(h, gs, dP, (const int *)(dev + oEx), Lex, shm);
+    if (s2 != CDZ_OK) return s2;
+    hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(2 * cnt), dim3(CDZ_SCAN_NT), scan_lds_bytes(nmax), gs, dP,
+                       (const int *)(dev + oNm1), (const int *)(dev + oNm1), 2);
+    // range check of every exact pass: flags res[5] (weak cell), res[6]
+    // (non-finite entry); FP32 problems with weak cells repeat the pass once
+    // with the landscape of the exact pass and are checked again
+    hipLaunchKernelGGL(cdz_spread_check_batch<T>, dim3(Lsp.total(0)), dim3(CDZ_NT), 0, gs, dP,
+                       (const int *)(dev + oSp), cnt);
     HIPCHK(h, hipGetLastError());
-  } else {
-    s = fwd_pass<T>(h, dP, (const int *)(dev + oEx), Lex, shm);
-    if (s != CDZ_OK) return s;
-  }
-  hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(2 * cnt), dim3(CDZ_SCAN_NT), scan_lds_bytes(nmax), st, dP,
-                     (const int *)(dev + oNm1), (const int *)(dev + oNm1), 2);
-  // range check of every exact pass: flags res[5] (weak cell), res[6]
-  // (non-finite entry); FP32 problems with weak cells repeat the pass once
-  // with the landscape of the exact pass and are checked again
-  hipLaunchKernelGGL(cdz_spread_check_batch<T>, dim3(Lsp.total(0)), dim3(CDZ_NT), 0, st, dP,
-                     (const int *)(dev + oSp), cnt);
+    return CDZ_OK;
+  });
+  if (s != CDZ_OK) return s;
   HIPCHK(h, hipGetLastError());
   for (int b = 0; b < cnt; b++)
     HIPCHK(h, hipMemcpyAsync(&C.res[(size_t)b * 8], C.D[b].res, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -211,7 +333,7 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
     h->landscape_retries = (int)R.size();
     if (!R.empty()) {
       const int rc = (int)R.size();
-      const Launches Lr = fwd_launches(rn, rn);
+      const Launches Lr = fwd_launches(rn, rn, h->fuse_wg);
       const Launches Lrs(rc, 1, [&](int k, int) { return rn[k]; });
       Meta mr;
       const size_t rP = mr.put(R.data(), rc * sizeof(DevProb<T>));
@@ -229,7 +351,7 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
         HIPCHK(h, hipMemsetAsync(R[k].E, 0, (rn[k] + 1) * sizeof(int), st));
         HIPCHK(h, hipMemsetAsync(R[k].res + 5, 0, 3 * sizeof(double), st));
       }
-      s = fwd_pass<T>(h, dR, (const int *)(dev + rO), Lr, shm);
+      s = fwd_pass<T>(h, st, dR, (const int *)(dev + rO), Lr, shm);
       if (s != CDZ_OK) return s;
       hipLaunchKernelGGL(cdz_exterior_scan_batch<T>, dim3(2 * rc), dim3(CDZ_SCAN_NT), scan_lds_bytes(nmax), st, dR,
                          (const int *)(dev + rN), (const int *)(dev + rN), 2);
@@ -245,6 +367,7 @@ cdz_status chunk_forward(cdz_handle *h, Chunk<T> &C) {
   float ms = 0;
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
   h->times[0] += ms;
+  if (h->landscape_retries == 0) tune_end(h, tkey, ms);
   for (int b = 0; b < cnt; b++) {
     const double *r = &C.res[(size_t)b * 8];
     if (r[6] != 0.0)
@@ -270,9 +393,21 @@ cdz_status chunk_outside(cdz_handle *h, Chunk<T> &C) {
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(nmax) + " nt exceeds the LDS layout of the outside kernel");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_out_diag_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)shm));
+  HIPCHK(h, hipFuncSetAttribute((const void *)cdz_out_diag_batch_fused<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm));
   std::vector<int> n(cnt);
   for (int b = 0; b < cnt; b++) n[b] = C.t[b]->n;
-  const Launches Lo(cnt, nmax, [&](int b, int dl) { return dl <= n[b] - 1 ? out_nblocks(n[b], dl) : 0; });
+  long long wmax = 0;
+  for (int t = 0; t < nmax; t++) {
+    long long w = 0;
+    for (int b = 0; b < cnt; b++) w += t < n[b] ? out_nblocks(n[b], t) : 0;
+    wmax = std::max(wmax, w);
+  }
+  const uint64_t tkey = tune_key(1, true, sizeof(T), wmax);
+  tune_begin(h, tkey);
+  const Launches Lo(
+      cnt, nmax, [&](int b, int dl, bool fu) { return dl <= n[b] - 1 ? out_nblocks(n[b], dl, fu) : 0; },
+      h->fuse_wg);
   const Launches Le(cnt, 1, [&](int b, int) { return n[b] >= 2 ? n[b] - 1 : 0; });
   Meta m;
   const size_t oP = m.put(C.D.data(), cnt * sizeof(DevProb<T>));
@@ -284,47 +419,48 @@ cdz_status chunk_outside(cdz_handle *h, Chunk<T> &C) {
   if (s != CDZ_OK) return s;
   const DevProb<T> *dP = (const DevProb<T> *)(dev + oP);
   const DevAdj<T> *dA = (const DevAdj<T> *)(dev + oA);
-  HIPCHK(h, hipEventRecord(h->ev[2], st));
-  for (int b = 0; b < cnt; b++) {
-    // accumulators of pushed adjoints start at zero
-    const DevProb<T> &D = C.D[b];
-    const DevAdj<T> &A = C.A[b];
-    const size_t S2b = (size_t)D.ld * D.ld * sizeof(T);
-    HIPCHK(h, hipMemsetAsync(A.UbL, 0, S2b, st));
-    HIPCHK(h, hipMemsetAsync(A.UbR, 0, S2b, st));
-    HIPCHK(h, hipMemsetAsync(A.UbL2, 0, S2b, st));
-    HIPCHK(h, hipMemsetAsync(A.UbR2, 0, S2b, st));
-    HIPCHK(h, hipMemsetAsync(A.DIbL, 0, S2b, st));
-    HIPCHK(h, hipMemsetAsync(A.DIbR, 0, S2b, st));
-    HIPCHK(h, hipMemsetAsync(A.etaV, 0, (size_t)n[b] * 36 * sizeof(double), st));
-    HIPCHK(h, hipMemsetAsync(A.etaW, 0, (size_t)n[b] * 36 * sizeof(double), st));
-  }
-  for (int dl = nmax - 1; dl >= 0; dl--) {
-    const int tot = Lo.total(dl);
-    if (tot == 0) continue;
-    hipLaunchKernelGGL(cdz_out_diag_batch<T>, dim3(tot), dim3(CDZ_NT), shm, st, dP, dA,
-                       (const int *)(dev + oO) + Lo.at(dl), cnt, dl);
-  }
-  HIPCHK(h, hipGetLastError());
   if (eta_lds_bytes(nmax) > (size_t)h->lds_max)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(nmax) + " nt exceeds the LDS layout of the edge kernel");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_eta_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)eta_lds_bytes(nmax)));
-  if (Le.total(0) > 0)
-    hipLaunchKernelGGL(cdz_eta_batch<T>, dim3(Le.total(0)), dim3(CDZ_NT), eta_lds_bytes(nmax), st, dP, dA,
-                       (const int *)(dev + oE), cnt);
+  std::vector<double> sc(cnt);
   for (int b = 0; b < cnt; b++) {
     const double *r = &C.res[(size_t)b * 8];
-    const double sc = std::exp(r[2] * kLn2 - r[0]);
-    const long long nn = (long long)n[b] * n[b];
-    hipLaunchKernelGGL(cdz_pairprob<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, C.D[b], C.A[b], sc);
+    sc[b] = std::exp(r[2] * kLn2 - r[0]);
   }
-  HIPCHK(h, hipGetLastError());
+  m.put(sc.data(), cnt * sizeof(double));  // part of the key: pairprob takes the scale by value
+  HIPCHK(h, hipEventRecord(h->ev[2], st));
+  s = graph_run(h, graph_key(h, "outside", sizeof(T), m), [&](hipStream_t gs) -> cdz_status {
+    // accumulators of pushed adjoints start at zero
+    hipLaunchKernelGGL(cdz_clear_out<T>, dim3(cnt * 64), dim3(256), 0, gs, dP, dA, 64);
+    for (int dl = nmax - 1; dl >= 0; dl--) {
+      const int tot = Lo.total(dl);
+      if (tot == 0) continue;
+      if (Lo.fused[dl])
+        hipLaunchKernelGGL(cdz_out_diag_batch_fused<T>, dim3(tot), dim3(CDZ_NT), shm, gs, dP, dA,
+                           (const int *)(dev + oO) + Lo.at(dl), cnt, dl);
+      else
+        hipLaunchKernelGGL(cdz_out_diag_batch<T>, dim3(tot), dim3(CDZ_NT), shm, gs, dP, dA,
+                           (const int *)(dev + oO) + Lo.at(dl), cnt, dl);
+    }
+    if (Le.total(0) > 0)
+      hipLaunchKernelGGL(cdz_eta_batch<T>, dim3(Le.total(0)), dim3(CDZ_NT), eta_lds_bytes(nmax), gs, dP, dA,
+                         (const int *)(dev + oE), cnt);
+    for (int b = 0; b < cnt; b++) {
+      const long long nn = (long long)n[b] * n[b];
+      hipLaunchKernelGGL(cdz_pairprob<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, gs, C.D[b], C.A[b],
+                         sc[b]);
+    }
+    HIPCHK(h, hipGetLastError());
+    return CDZ_OK;
+  });
+  if (s != CDZ_OK) return s;
   HIPCHK(h, hipEventRecord(h->ev[3], st));
   HIPCHK(h, hipStreamSynchronize(st));
   float ms = 0;
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
   h->times[1] += ms;
+  tune_end(h, tkey, ms);
   return CDZ_OK;
 }
 
@@ -377,6 +513,7 @@ cdz_status run_batch(cdz_handle *h, const std::vector<HostTables> &tabs, int32_t
   }
   int start = 0;
   int retries = 0;
+  h->graph_captures = h->graph_replays = 0;
   while (start < count) {
     // greedy chunk [start, stop): as many problems as the budget holds
     int stop = start;

@@ -156,9 +156,13 @@ __host__ __device__ __forceinline__ void fwd_ranges(int n, int t, int r[4]) {
   r[2] = t + 4 >= 9 && t + 4 < n ? cdz_cells_grid(n - t - 4) : 0;
   r[3] = t < n ? cdz_cells_grid(n - t) : 0;
 }
-__host__ __device__ __forceinline__ int fwd_nblocks(int n, int t) {
+// Workgroups of the launch: one per piece of work (split), or, fused, one
+// per cell index running every kind that has that block in turn (the kinds
+// of a launch never read each other's results, so any order is the same)
+__host__ __device__ __forceinline__ int fwd_nblocks(int n, int t, bool fused = false) {
   int r[4];
   fwd_ranges(n, t, r);
+  if (fused) return max(max(r[0], r[1]), max(r[2], r[3]));
   return r[0] + r[1] + r[2] + r[3];
 }
 // Workgroups of outside launch t (t = n-1..0), in block order: interior-loop
@@ -175,9 +179,10 @@ __host__ __device__ __forceinline__ void out_ranges(int n, int t, int r[6]) {
   r[4] = c >= 4 && c <= n - 5 ? cdz_cells_grid(n - c) : 0;
   r[5] = t >= 0 && t <= n - 1 ? cdz_cells_grid(n - t) : 0;
 }
-__host__ __device__ __forceinline__ int out_nblocks(int n, int t) {
+__host__ __device__ __forceinline__ int out_nblocks(int n, int t, bool fused = false) {
   int r[6];
   out_ranges(n, t, r);
+  if (fused) return max(max(max(r[0], r[1]), max(r[2], r[3])), max(r[4], r[5]));
   return r[0] + r[1] + r[2] + r[3] + r[4] + r[5];
 }
 __device__ __forceinline__ int cdz_cell_of_block(int w, int ncell) {

@@ -729,32 +729,43 @@ __device__ __forceinline__ void fwd_finish(const DevProb<T> &D, int dl, int blk)
   }
 }
 
-// One workgroup of launch t; w is its index among this problem's workgroups
-template <typename T>
+// One workgroup of launch t; w is its index among this problem's workgroups.
+// Split (FUSED false): the kinds' blocks are numbered one kind after the
+// other and the workgroup runs one of them.  Fused: it runs block w of every
+// kind that has one, in turn (LDS is reused, hence the barriers).  The two
+// are separate kernels, so each holds one copy of every kind.
+template <typename T, bool FUSED>
 __device__ __forceinline__ void fwd_block(const DevProb<T> &D, int t, int w) {
-  int r[4];
+  int r[4], wk[4];
   fwd_ranges(D.n, t, r);
-  if (w < r[0]) {
-    fwd_window<T>(D, t, t + 1, w);
-    return;
+  int base = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int x = FUSED ? w : w - base;
+    wk[k] = x >= 0 && x < r[k] ? x : -1;
+    base += r[k];
   }
-  w -= r[0];
-  if (w < r[1]) {
-    fwd_bulges<T>(D, t, t + 1, w);
-    return;
+  if (wk[0] >= 0) {
+    fwd_window<T>(D, t, t + 1, wk[0]);
+    if (FUSED) __syncthreads();
+    else return;
   }
-  w -= r[1];
-  if (w < r[2]) {
-    fwd_split<T>(D, t, t + 4, w);
-    return;
+  if (wk[1] >= 0) {
+    fwd_bulges<T>(D, t, t + 1, wk[1]);
+    if (FUSED) __syncthreads();
+    else return;
   }
-  w -= r[2];
-  if (w < r[3]) {
-    if (w == 0 && threadIdx.x == 0) {  // the exponents chosen in this launch
+  if (wk[2] >= 0) {
+    fwd_split<T>(D, t, t + 4, wk[2]);
+    if (FUSED) __syncthreads();
+    else return;
+  }
+  if (wk[3] >= 0) {
+    if (wk[3] == 0 && threadIdx.x == 0) {  // the exponents chosen in this launch
       if (t + 1 <= D.n) D.E[t + 1] = exponent_ahead(D, t, t + 1);
       D.EX[t + 4] = exponent_ahead(D, t, t + 4);
     }
-    fwd_finish<T>(D, t, w);
+    fwd_finish<T>(D, t, wk[3]);
   }
 }
 
@@ -1287,7 +1298,11 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_arec_diag(DevProb<T> D, int dl) {
 
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag(DevProb<T> D, int t) {
-  fwd_block<T>(D, t, blockIdx.x);
+  fwd_block<T, false>(D, t, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag_fused(DevProb<T> D, int t) {
+  fwd_block<T, true>(D, t, blockIdx.x);
 }
 
 // Batched wavefront: one launch runs diagonal dl of every problem of a batch.
@@ -1299,7 +1314,15 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag_batch(const DevProb<T> *p
   int b, w;
   cdz_batch_locate(off, count, blockIdx.x, b, w);
   const DevProb<T> D = probs[b];
-  fwd_block<T>(D, dl, w);
+  fwd_block<T, false>(D, dl, w);
+}
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_fwd_diag_batch_fused(const DevProb<T> *probs, const int *off,
+                                                                  int count, int dl) {
+  int b, w;
+  cdz_batch_locate(off, count, blockIdx.x, b, w);
+  const DevProb<T> D = probs[b];
+  fwd_block<T, true>(D, dl, w);
 }
 
 // per problem b of a batch: the span-truncated exterior prefix (span W[b]),
@@ -1357,8 +1380,12 @@ template __global__ void cdz_arec_diag<float>(DevProb<float>, int);
 template __global__ void cdz_arec_diag<double>(DevProb<double>, int);
 template __global__ void cdz_fwd_diag<float>(DevProb<float>, int);
 template __global__ void cdz_fwd_diag<double>(DevProb<double>, int);
+template __global__ void cdz_fwd_diag_fused<float>(DevProb<float>, int);
+template __global__ void cdz_fwd_diag_fused<double>(DevProb<double>, int);
 template __global__ void cdz_fwd_diag_batch<float>(const DevProb<float> *, const int *, int, int);
 template __global__ void cdz_fwd_diag_batch<double>(const DevProb<double> *, const int *, int, int);
+template __global__ void cdz_fwd_diag_batch_fused<float>(const DevProb<float> *, const int *, int, int);
+template __global__ void cdz_fwd_diag_batch_fused<double>(const DevProb<double> *, const int *, int, int);
 template __global__ void cdz_exterior_trunc_batch<float>(const DevProb<float> *, const int *);
 template __global__ void cdz_exterior_trunc_batch<double>(const DevProb<double> *, const int *);
 template __global__ void cdz_landscape_batch<float>(const DevProb<float> *);

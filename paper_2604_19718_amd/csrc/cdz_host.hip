@@ -152,11 +152,18 @@ extern "C" void cdz_destroy(cdz_handle *h) {
   if (h->ws) (void)hipFree(h->ws);
   if (h->smp) (void)hipFree(h->smp);
   if (h->bws) (void)hipFree(h->bws);
+  for (auto &g : h->graphs) {
+    if (g.x) (void)hipGraphExecDestroy(g.x);
+    if (g.g) (void)hipGraphDestroy(g.g);
+  }
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (auto &ev : h->ev)
     if (ev) (void)hipEventDestroy(ev);
   for (auto &ev : h->pev) (void)hipEventDestroy(ev);
   delete h;
 }
+
+int codon_count(unsigned char letter) { return letter < 128 ? code_table().count[letter] : 0; }
 
 // ---------------------------------------------------------------------------
 // Problem tables
@@ -348,6 +355,8 @@ template cdz_status upload<double>(cdz_handle *, const HostTables &, DevProb<dou
 
 template <typename T>
 __global__ void cdz_fwd_diag(DevProb<T> D, int dl);
+template <typename T>
+__global__ void cdz_fwd_diag_fused(DevProb<T> D, int dl);
 
 
 template <typename T>
@@ -373,7 +382,10 @@ static cdz_status forward_pass(cdz_handle *h, DevProb<T> &D, size_t shm, bool ti
       Dl.ALp = al_slot_ptr(D, al_slot_fwd(D.alK, D.alTop, t >= 1 ? t - 1 : 0));
     }
     if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * t], st));
-    hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(fwd_nblocks(n, t)), dim3(CDZ_NT), shm, st, Dl, t);
+    if (fwd_nblocks(n, t) >= h->fuse_wg)
+      hipLaunchKernelGGL(cdz_fwd_diag_fused<T>, dim3(fwd_nblocks(n, t, true)), dim3(CDZ_NT), shm, st, Dl, t);
+    else
+      hipLaunchKernelGGL(cdz_fwd_diag<T>, dim3(fwd_nblocks(n, t)), dim3(CDZ_NT), shm, st, Dl, t);
     if (timed) HIPCHK(h, hipEventRecord(h->pev[2 * t + 1], st));
   }
   // exterior loops over the finished diagonals: the exact pass runs the
@@ -395,11 +407,17 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   if (shm > (size_t)h->lds_max)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the forward kernel");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_fwd_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  HIPCHK(h, hipFuncSetAttribute((const void *)cdz_fwd_diag_fused<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm));
   if (scan_lds_bytes(n) > (size_t)h->lds_max)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the exterior scan");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_exterior_scan<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)scan_lds_bytes(n)));
   const bool fp32 = std::is_same<T, float>::value;
+  long long wmax = 0;
+  for (int t = 0; t < n; t++) wmax = std::max<long long>(wmax, fwd_nblocks(n, t));
+  const uint64_t tkey = tune_key(0, false, sizeof(T), wmax);
+  tune_begin(h, tkey);
   HIPCHK(h, hipMemsetAsync(D.res, 0, 8 * sizeof(double), st));
   if (h->profiling) HIPCHK(h, prof_reserve(h, n + 1));
   HIPCHK(h, hipEventRecord(h->ev[0], st));
@@ -461,6 +479,7 @@ static cdz_status launch_forward(cdz_handle *h, DevProb<T> &D) {
   float ms = 0;
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
   h->times[0] = ms;
+  if (!h->profiling && h->landscape_retries == 0) tune_end(h, tkey, ms);
   if (h->profiling) {
     double tot = 0;
     for (int dl = 0; dl < n; dl++) {
@@ -619,6 +638,47 @@ extern "C" int cdz_debug_set_low_exp(cdz_handle *h, int e) {
   h->low_exp = e;
   h->have_fwd = false;
   return CDZ_OK;
+}
+extern "C" int cdz_debug_set_graphs(cdz_handle *h, int on) {
+  if (!h) return CDZ_ERR_ARG;
+  h->use_graphs = on != 0;
+  return CDZ_OK;
+}
+extern "C" int cdz_debug_graph_counts(const cdz_handle *h, int *captures, int *replays) {
+  if (!h || !captures || !replays) return CDZ_ERR_ARG;
+  *captures = h->graph_captures;
+  *replays = h->graph_replays;
+  return CDZ_OK;
+}
+extern "C" int cdz_debug_set_fuse(cdz_handle *h, int wg) {
+  if (!h || wg < -1) return CDZ_ERR_ARG;
+  h->fuse_fixed = wg;
+  return CDZ_OK;
+}
+
+namespace {
+const int kFuseCand[3] = {1 << 30, 16384, 4096};
+}
+uint64_t tune_key(int pass, bool batch, size_t tsize, long long max_split_wg) {
+  int b = 0;
+  while (b < 62 && (2ll << b) <= max_split_wg) b++;
+  return (uint64_t)pass | (uint64_t)batch << 1 | (uint64_t)(tsize == 8) << 2 | (uint64_t)b << 3;
+}
+int tune_begin(cdz_handle *h, uint64_t key) {
+  if (h->fuse_fixed >= 0) return h->fuse_wg = h->fuse_fixed;
+  const cdz_handle::Tune &t = h->tune[key];
+  if (t.tried < 0) return h->fuse_wg = kFuseCand[0];
+  if (t.tried < 3) return h->fuse_wg = kFuseCand[t.tried];
+  int best = 0;
+  for (int k = 1; k < 3; k++)
+    if (t.ms[k] < t.ms[best]) best = k;
+  return h->fuse_wg = kFuseCand[best];
+}
+void tune_end(cdz_handle *h, uint64_t key, float ms) {
+  if (h->fuse_fixed >= 0) return;
+  cdz_handle::Tune &t = h->tune[key];
+  if (t.tried < 0) t.tried = 0;
+  else if (t.tried < 3) t.ms[t.tried++] = ms;
 }
 // force that storage for the following forward passes (-2: chosen by budget)
 extern "C" int cdz_debug_force_al_k(cdz_handle *h, int K) {

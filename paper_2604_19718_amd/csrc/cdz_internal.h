@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -90,6 +91,31 @@ struct cdz_handle {
   size_t smp_bytes = 0;
   void *bws = nullptr;  // batched calls: problem descriptors and launch offset tables
   size_t bws_bytes = 0;
+  // captured launch sequences of batch chunks (hipGraph), keyed by the
+  // descriptor image and phase they were captured for; replayed when a key
+  // recurs (the image holds every device pointer and launch table, so equal
+  // keys mean identical launches)
+  struct Graph {
+    std::string key;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+  };
+  std::vector<Graph> graphs;
+  hipStream_t cap_stream = nullptr;  // stream the sequences are captured on (never run)
+  bool use_graphs = true;
+  // launch grouping: a diagonal launch whose pieces of work would take at
+  // least fuse_wg workgroups runs fused (one workgroup per cell index doing
+  // every kind in turn) instead of one workgroup per piece.  fuse_wg is set
+  // per pass: the caller's fixed threshold (fuse_fixed >= 0), or the choice
+  // of the tuner for the pass's class (tune_begin / tune_end)
+  int fuse_wg = 1 << 30;
+  int fuse_fixed = -1;
+  struct Tune {
+    int tried = -1;  // -1: the first (warm-up) pass is not timed
+    float ms[3] = {0, 0, 0};
+  };
+  std::map<uint64_t, Tune> tune;
+  int graph_captures = 0, graph_replays = 0;  // of the last batched call
   hipEvent_t ev[8] = {};
   double times[5] = {0, 0, 0, 0, 0};
   // per-launch event timing of the diagonal kernels (cdz_set_profiling)
@@ -183,5 +209,14 @@ void *noalloc_scratch(int device);
 
 cdz_status build_tables(cdz_handle *h, int32_t n_aa, const char *aa, const double *theta1,
                         const double *theta2, HostTables &t);
+// Launch-grouping tuner.  A class of passes is (forward or outside, single
+// problem or batch, precision, log2 of the largest launch's workgroup count
+// when split).  Its first pass runs split and is not timed; the next three
+// run with the candidate thresholds (never fused, fused from 16384 and from
+// 4096 workgroups) and are timed; later passes use the fastest.  Results do
+// not depend on the choice.
+uint64_t tune_key(int pass, bool batch, size_t tsize, long long max_split_wg);
+int tune_begin(cdz_handle *h, uint64_t key);  // threshold for this pass (also set in fuse_wg)
+void tune_end(cdz_handle *h, uint64_t key, float ms);
 cdz_status ensure_forward(cdz_handle *h, const HostTables &t, bool adjoint);
 hipError_t prof_reserve(cdz_handle *h, int launches);

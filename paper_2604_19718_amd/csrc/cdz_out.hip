@@ -1077,36 +1077,45 @@ __device__ __forceinline__ void out_bulge_push(const DevProb<T> &D, const DevAdj
 }
 
 // One workgroup of outside launch t; w is its index among this problem's workgroups
-template <typename T>
+template <typename T, bool FUSED>
 __device__ __forceinline__ void out_block(const DevProb<T> &D, const DevAdj<T> &A, int t, int w) {
-  int r[6];
+  // split: one block of one kind (kinds numbered in turn); fused: block w of
+  // every kind that has one, in turn (LDS is reused); separate kernels
+  int r[6], wk[6];
   out_ranges(D.n, t, r);
-  if (w < r[0]) {
-    out_int_push<T>(D, A, t + 1, w);
-    return;
+  int base = 0;
+#pragma unroll
+  for (int k = 0; k < 6; k++) {
+    const int x = FUSED ? w : w - base;
+    wk[k] = x >= 0 && x < r[k] ? x : -1;
+    base += r[k];
   }
-  w -= r[0];
-  if (w < r[1]) {
-    out_edge_terms<T>(D, A, t + 1, w);
-    return;
+  if (wk[0] >= 0) {
+    out_int_push<T>(D, A, t + 1, wk[0]);
+    if (FUSED) __syncthreads();
+    else return;
   }
-  w -= r[1];
-  if (w < r[2]) {
-    out_bulge_push<T>(D, A, t + 1, w);
-    return;
+  if (wk[1] >= 0) {
+    out_edge_terms<T>(D, A, t + 1, wk[1]);
+    if (FUSED) __syncthreads();
+    else return;
   }
-  w -= r[2];
-  if (w < r[3]) {
-    out_bulge_gather<T>(D, A, t - 1, w);
-    return;
+  if (wk[2] >= 0) {
+    out_bulge_push<T>(D, A, t + 1, wk[2]);
+    if (FUSED) __syncthreads();
+    else return;
   }
-  w -= r[3];
-  if (w < r[4]) {
-    out_split<T>(D, A, t - 4, w);
-    return;
+  if (wk[3] >= 0) {
+    out_bulge_gather<T>(D, A, t - 1, wk[3]);
+    if (FUSED) __syncthreads();
+    else return;
   }
-  w -= r[4];
-  out_finish<T>(D, A, t, w);
+  if (wk[4] >= 0) {
+    out_split<T>(D, A, t - 4, wk[4]);
+    if (FUSED) __syncthreads();
+    else return;
+  }
+  if (wk[5] >= 0) out_finish<T>(D, A, t, wk[5]);
 }
 
 
@@ -1482,7 +1491,11 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
 
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag(DevProb<T> D, DevAdj<T> A, int dl) {
-  out_block<T>(D, A, dl, blockIdx.x);
+  out_block<T, false>(D, A, dl, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) void cdz_out_diag_fused(DevProb<T> D, DevAdj<T> A, int dl) {
+  out_block<T, true>(D, A, dl, blockIdx.x);
 }
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A) {
@@ -1497,7 +1510,16 @@ __global__ __launch_bounds__(CDZ_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T
   cdz_batch_locate(off, count, blockIdx.x, b, w);
   const DevProb<T> D = probs[b];
   const DevAdj<T> A = adjs[b];
-  out_block<T>(D, A, dl, w);
+  out_block<T, false>(D, A, dl, w);
+}
+template <typename T>
+__global__ __launch_bounds__(CDZ_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void cdz_out_diag_batch_fused(const DevProb<T> *probs, const DevAdj<T> *adjs,
+                                                            const int *off, int count, int dl) {
+  int b, w;
+  cdz_batch_locate(off, count, blockIdx.x, b, w);
+  const DevProb<T> D = probs[b];
+  const DevAdj<T> A = adjs[b];
+  out_block<T, true>(D, A, dl, w);
 }
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_eta_batch(const DevProb<T> *probs, const DevAdj<T> *adjs,
@@ -1563,6 +1585,12 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   if (shm > (size_t)h->lds_max)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the outside kernel");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_out_diag<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  HIPCHK(h, hipFuncSetAttribute((const void *)cdz_out_diag_fused<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm));
+  long long wmax = 0;
+  for (int t = 0; t < n; t++) wmax = std::max<long long>(wmax, out_nblocks(n, t));
+  const uint64_t tkey = tune_key(1, false, sizeof(T), wmax);
+  tune_begin(h, tkey);
   HIPCHK(h, hipEventRecord(h->ev[2], st));
   // accumulators of pushed adjoints start at zero
   HIPCHK(h, hipMemsetAsync(A.UbL, 0, S2b, st));
@@ -1603,7 +1631,11 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
       Dl.ALp = al_slot_ptr(D, al_slot_band(K, top, x));
     }
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl], st));
-    hipLaunchKernelGGL(cdz_out_diag<T>, dim3(out_nblocks(n, dl)), dim3(CDZ_NT), shm, st, Dl, A, dl);
+    const bool fu = out_nblocks(n, dl) >= h->fuse_wg;
+    if (fu)
+      hipLaunchKernelGGL(cdz_out_diag_fused<T>, dim3(out_nblocks(n, dl, true)), dim3(CDZ_NT), shm, st, Dl, A, dl);
+    else
+      hipLaunchKernelGGL(cdz_out_diag<T>, dim3(out_nblocks(n, dl)), dim3(CDZ_NT), shm, st, Dl, A, dl);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * dl + 1], st));
   }
   HIPCHK(h, hipGetLastError());
@@ -1625,6 +1657,7 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   float ms = 0;
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
   h->times[1] = ms;
+  if (!h->profiling) tune_end(h, tkey, ms);
   if (h->profiling) {
     double tot = 0;
     for (int dl = 0; dl < n; dl++) {
@@ -1790,10 +1823,16 @@ extern "C" cdz_status cdz_debug_copy(cdz_handle *h, int which, void *dst, size_t
 
 template __global__ void cdz_out_diag<float>(DevProb<float>, DevAdj<float>, int);
 template __global__ void cdz_out_diag<double>(DevProb<double>, DevAdj<double>, int);
+template __global__ void cdz_out_diag_fused<float>(DevProb<float>, DevAdj<float>, int);
+template __global__ void cdz_out_diag_fused<double>(DevProb<double>, DevAdj<double>, int);
 template __global__ void cdz_out_diag_batch<float>(const DevProb<float> *, const DevAdj<float> *, const int *, int,
                                                     int);
 template __global__ void cdz_out_diag_batch<double>(const DevProb<double> *, const DevAdj<double> *, const int *,
                                                      int, int);
+template __global__ void cdz_out_diag_batch_fused<float>(const DevProb<float> *, const DevAdj<float> *, const int *,
+                                                          int, int);
+template __global__ void cdz_out_diag_batch_fused<double>(const DevProb<double> *, const DevAdj<double> *,
+                                                           const int *, int, int);
 template __global__ void cdz_eta_batch<float>(const DevProb<float> *, const DevAdj<float> *, const int *, int);
 template __global__ void cdz_eta_batch<double>(const DevProb<double> *, const DevAdj<double> *, const int *, int);
 template __global__ void cdz_pairprob<float>(DevProb<float>, DevAdj<float>, double);

@@ -211,6 +211,17 @@ def theta1(seed: int, prot: str, sigma: float = 0.5, index: int = 0) -> np.ndarr
     return out
 
 
+def bonus_targets(seed: int, sigma: float = 0.5, index: int = 0) -> np.ndarray:
+    """Target codon bonuses [26][6] (row = letter - 'A', column = slot): the
+    per-codon-type weights theta1 draws, exponentiated, so that theta1 of any
+    protein under the same seed is log of these at its residues' codons."""
+    r = Stream(seed, TAG_THETA1, index)
+    out = np.zeros((26, MAX_SLOTS))
+    for (a, s) in _codon_types():
+        out[ord(a) - 65, s] = math.exp(r.gauss(sigma))
+    return out
+
+
 def theta2(seed: int, prot: str, sigma: float = 0.3, index: int = 0) -> np.ndarray:
     """Position-level log codon-pair weights [m][6][6]; row a couples codon
     a-1 (first index) with codon a (second index); row 0 is zero."""

@@ -11,10 +11,17 @@ here comes from the HIP path.
   oracle_workload4_1197nt.npz  the longest member of the 256-protein batch
       (index 189, 399 residues): logz only
 
-Each file also records the sha256 of the oracle sources it was computed
-with.  The 900-nt marginals take about two minutes on 8 cores.
+  oracle_freqmatch_workload2_300nt.npz, oracle_freqmatch_workload3_900nt.npz
+      frequency matching (Section S4e) of workloads 2 and 3 with the target
+      bonuses their codon weights were drawn from (inputs.bonus_targets),
+      r_tol 0.002, unlimited Anderson history, at most 30 evaluations:
+      errors per evaluation, the final bonuses f [26][6], converged
 
-Usage: python tests/golden/make_oracle_goldens.py [--only 2|3|4]
+Each file also records the sha256 of the oracle sources it was computed
+with.  The 900-nt marginals take about two minutes on 8 cores, so the 900-nt
+frequency matching about half an hour.
+
+Usage: python tests/golden/make_oracle_goldens.py [--only 2|3|4] [--freq 2|3]
 """
 from __future__ import annotations
 
@@ -37,9 +44,12 @@ from paper_2604_19718_amd import inputs as I  # noqa: E402
 BATCH_LONGEST = 189  # member of workload 4 with the most residues (399)
 
 
-def oracle_sha256() -> str:
+FREQ = dict(r_tol=0.002, history=-1, max_eval=30)
+
+
+def oracle_sha256(files=("oracle.c", "seqmcc.c")) -> str:
     h = hashlib.sha256()
-    for f in ("oracle.c", "seqmcc.c"):
+    for f in files:
         with open(os.path.join(ROOT, "oracle", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -48,6 +58,28 @@ def oracle_sha256() -> str:
 def path_for(k: int) -> str:
     return os.path.join(HERE, {2: "oracle_workload2_300nt.npz", 3: "oracle_workload3_900nt.npz",
                                4: "oracle_workload4_1197nt.npz"}[k])
+
+
+def freq_path_for(k: int) -> str:
+    return os.path.join(HERE, {2: "oracle_freqmatch_workload2_300nt.npz",
+                               3: "oracle_freqmatch_workload3_900nt.npz"}[k])
+
+
+def write_freq(k: int) -> None:
+    from oracle import freqmatch as FM
+    prob, en = I.workload(k)
+    ft = I.bonus_targets(I.config_seed(k))
+    t0 = time.time()
+    f, errs, ok = FM.match_frequencies(prob, en, ft, **FREQ)
+    np.savez_compressed(freq_path_for(k), f=f, errs=np.array(errs), converged=ok, n=prob.n,
+                        oracle_sha256=oracle_sha256(("oracle.c", "seqmcc.c", "freqmatch.py")), **FREQ)
+    print(f"freq workload {k} n={prob.n} evals={len(errs)} converged={ok} errs={errs} "
+          f"{time.time() - t0:.1f}s", flush=True)
+
+
+def load_freq(k: int) -> dict:
+    z = np.load(freq_path_for(k), allow_pickle=False)
+    return {key: z[key] for key in z.files}
 
 
 def write(k: int) -> None:
@@ -87,7 +119,11 @@ def load(k: int) -> dict:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--only", type=int, choices=[2, 3, 4])
+    ap.add_argument("--freq", type=int, choices=[2, 3])
     a = ap.parse_args()
     oracle.build(force=False)
-    for k in ([a.only] if a.only else [2, 3, 4]):
-        write(k)
+    if a.freq:
+        write_freq(a.freq)
+    else:
+        for k in ([a.only] if a.only else [2, 3, 4]):
+            write(k)

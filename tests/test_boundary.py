@@ -1,5 +1,6 @@
 """Boundary checks that need no GPU: the C-ABI library loads and exports
-every entry point declared in include/cdz.h; the binding has no fallback."""
+every entry point declared in include/cdz.h and include/cdz_freq.h (product)
+and include/cdz_debug.h (test hooks); the binding has no fallback."""
 import os
 import re
 
@@ -8,7 +9,12 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared(header="cdz.h"):
+PRODUCT_HEADERS = ("cdz.h", "cdz_freq.h")
+
+
+def _declared(header=None):
+    if header is None:
+        return sorted(set(n for h in PRODUCT_HEADERS for n in _declared(h)))
     src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(cdz_[a-z_0-9]+)\s*\(", src)))
@@ -33,7 +39,11 @@ def test_library_exports_every_declared_symbol():
 
 def test_every_exported_symbol_is_declared():
     """No undeclared entry points: each exported cdz_* symbol of the library is
-    declared in include/cdz.h (product) or include/cdz_debug.h (test hooks)."""
+    declared in a product header or in include/cdz_debug.h (test hooks), and
+    every header under include/ is one of those."""
+    import glob
+    assert sorted(os.path.basename(p) for p in glob.glob(os.path.join(ROOT, "include", "*.h"))) == \
+        sorted(PRODUCT_HEADERS + ("cdz_debug.h",))
     import subprocess
     from paper_2604_19718_amd import binding as B
     if not os.path.exists(B.LIB_PATH):
