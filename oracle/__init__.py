@@ -20,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["oracle.c", "seqmcc.c"]
+_SOURCES = ["oracle.c", "seqmcc.c", "mfe.c"]
 _lib = None
 
 
@@ -83,6 +83,10 @@ def _configure(L):
                                      ctypes.c_int, ctypes.POINTER(ctypes.c_uint8),
                                      ctypes.POINTER(ctypes.c_int32)]
             L.orc_sample.restype = ctypes.c_int
+        if hasattr(L, "orc_mfe"):
+            L.orc_mfe.argtypes = [ctypes.c_int, ctypes.c_char_p, d, d, d, d, ctypes.POINTER(ctypes.c_uint8),
+                                  ctypes.POINTER(ctypes.c_int32)]
+            L.orc_mfe.restype = ctypes.c_int
         if hasattr(L, "orc_philox_u01"):
             L.orc_philox_u01.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
             L.orc_philox_u01.restype = ctypes.c_double
@@ -148,6 +152,23 @@ def sample(prob, energy, seed: int, nsamp: int):
     if rc != 0:
         raise RuntimeError(f"oracle orc_sample failed ({rc})")
     return cod, pairs
+
+
+def mfe(prob, energy, traceback: bool = True):
+    """Minimum free energy (kT) over codon sequences and structures
+    (mfe.c), and one minimising state: codon slots [m] (uint8) and the pair
+    table [n] (-1 unpaired), or (mfe, None, None)."""
+    m, aa, t1, t2 = _prep(prob)
+    en = energy.packed()
+    out = np.zeros(1)
+    cod = np.zeros(m, np.uint8) if traceback else None
+    pairs = np.zeros(3 * m, np.int32) if traceback else None
+    rc = lib().orc_mfe(m, aa, _dp(t1), _dp(t2), _dp(en), _dp(out),
+                       None if cod is None else cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                       None if pairs is None else pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if rc != 0:
+        raise RuntimeError(f"oracle orc_mfe failed ({rc})")
+    return float(out[0]), cod, pairs
 
 
 def philox_u01(seed: int, sample_id: int, draw: int) -> float:
