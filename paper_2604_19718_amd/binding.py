@@ -24,7 +24,7 @@ EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_s
            "cdz_forward_dev", "cdz_backward_dev", "cdz_last_timings", "cdz_reset",
            "cdz_set_profiling", "cdz_kernel_timings", "cdz_status_string", "cdz_last_error",
            "cdz_batch", "cdz_partition_batch", "cdz_marginals_batch", "cdz_sample_batch",
-           "cdz_workspace_bytes", "cdz_match_frequencies"]
+           "cdz_workspace_bytes", "cdz_match_frequencies", "cdz_mfe"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -92,6 +92,8 @@ def lib():
                                   ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_workspace_bytes": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+            "cdz_mfe": ([vp, ctypes.POINTER(cdz_problem), _dp, ctypes.POINTER(ctypes.c_uint8),
+                         ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_match_frequencies": ([vp, ctypes.POINTER(cdz_problem), _dp, ctypes.c_double, ctypes.c_int32,
                                        ctypes.c_int32, _dp, _dp, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -192,6 +194,21 @@ def cdz_sample(h: Handle, prob, seed: int, n_samples: int):
                              cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                              pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return cod, pairs
+
+
+def cdz_mfe(h: Handle, prob, traceback: bool = True):
+    """Minimum free energy (kT) over codon sequences and structures, and one
+    minimising state: (mfe, codon slots [n_aa] uint8, pair table [n] int32),
+    or (mfe, None, None) without the traceback."""
+    p = _Prob(prob)
+    m = len(prob.prot)
+    out = np.zeros(1)
+    cod = np.zeros(m, np.uint8) if traceback else None
+    pairs = np.zeros(3 * m, np.int32) if traceback else None
+    h.check(lib().cdz_mfe(h.ptr, ctypes.byref(p.c), _arr(out),
+                          None if cod is None else cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                          None if pairs is None else pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return float(out[0]), cod, pairs
 
 
 def cdz_match_frequencies(h: Handle, prob, f_target: np.ndarray, r_tol: float = 0.002,

@@ -1,0 +1,827 @@
+// cdz_mfe.hip -- minimum free energy over codon sequences and structures
+// (Section 4d; the (min, +) algebra of SI S2c), with an argmin traceback.
+//
+// The recursions are those of the partition function with every sum over
+// decompositions replaced by a minimum and every product of factors by a sum
+// of energies (kT): a vertex carries -theta1 on the middle base of a codon,
+// an edge inside a codon 0 (same slot) or +inf, an edge across a codon
+// boundary -theta2, a loop its energy; +inf marks what cannot occur.  The
+// entries are FP64 n x n arrays of 6 x 6 blocks (cell (i, j) at
+// ((i n + j) * 36), slot of i by slot of j): the unpaired run U, the pair Qb,
+// the interior-loop inner pair DI (Qb[i][j] with the edges to i-1, j+1 and the
+// inner mismatch), one multiloop branch Qm1, a branch after an unpaired prefix
+// Qm1p, two or more branches QmX, and Qm = min(QmX, Qm1p).
+//
+// One launch per anti-diagonal, one 256-thread workgroup per cell.  A cell
+// enumerates its bulge and interior windows (l1 + l2 <= 30) directly:
+// threads take (slot a of i+1, slot dd of j-1) and a seventh of the windows,
+// with the run blocks of both window sides staged in LDS.  Every quantity is
+// added in one fixed order, so the traceback, which evaluates the same
+// expressions, finds exactly the values the forward pass kept.
+//
+// The argmin traceback runs in one workgroup: a stack of fragments in device
+// memory, each decision's alternatives evaluated by all threads and reduced to
+// the first of smallest value in the documented order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cdz_internal.h"
+#include "cdz_mfe.h"
+
+namespace {
+
+constexpr int MT = 256;  // threads per workgroup
+constexpr int MAXW = 30;
+
+struct MfeDev {
+  int n;
+  const int *d;           // [n] slots of the residue of position p
+  const signed char *nt;  // [n][6] base under slot s
+  const double *v;        // [n][6] vertex energy
+  const double *e;        // [n][36] edge energy p -> p+1
+  const double *hp;       // [n + 1] hairpin energy by unpaired length (+inf below 3)
+  const double *stack;    // [6][6]
+  const double *bulge, *interior;  // [31]
+  const double *mm;       // [4][4][6]
+  double ml_ab, ml_b, ml_c;  // multiloop closing (a + b), per branch, per unpaired base
+  double *U, *Qb, *DI, *Qm1, *Qm1p, *QmX, *Qm;
+  double *Z5;   // [n][6]
+  int *slot;    // [n]
+  int *pt;      // [n]
+  int *stk;     // [cap][5]
+  int cap;
+  double *out;  // [1] minimum
+  int *err;     // [1] traceback stack overflow
+};
+
+__device__ __forceinline__ double *blk(double *A, int n, int i, int j) { return A + ((size_t)i * n + j) * 36; }
+__device__ __forceinline__ const double *cblk(const double *A, int n, int i, int j) {
+  return A + ((size_t)i * n + j) * 36;
+}
+__device__ __forceinline__ int bpair(int x, int y) {  // AU CG GC UA GU UG = 0..5, -1 if none
+  const int code = x * 4 + y;
+  switch (code) {
+    case 3: return 0;   // A-U
+    case 6: return 1;   // C-G
+    case 9: return 2;   // G-C
+    case 12: return 3;  // U-A
+    case 11: return 4;  // G-U
+    case 14: return 5;  // U-G
+  }
+  return -1;
+}
+__device__ __forceinline__ double E(const MfeDev &D, int p, int s, int t) { return D.e[p * 36 + s * 6 + t]; }
+__device__ __forceinline__ int NT(const MfeDev &D, int p, int s) { return D.nt[p * 6 + s]; }
+__device__ __forceinline__ double MM(const MfeDev &D, int x, int y, int t) { return D.mm[(x * 4 + y) * 6 + t]; }
+
+// (l1, l2) of window index w = l1 * 31 + l2, valid when l1 + l2 <= 30, not
+// both zero, and the inner pair spans at least 4 (l1 + l2 <= dl - 6)
+__device__ __forceinline__ bool window_of(int w, int dl, int &l1, int &l2) {
+  l1 = w / 31;
+  l2 = w % 31;
+  return l1 + l2 <= MAXW && (l1 | l2) != 0 && l1 + l2 <= dl - 6;
+}
+
+// per window, at outer slots (a of i+1, dd of j-1): the minimum over the
+// parts' inner slots, plus the loop energy; no outer edges, no outer mismatch
+__device__ double window_value(const MfeDev &D, int i, int j, int l1, int l2, int a, int dd, const double *ul,
+                               const double *ur) {
+  const int n = D.n, k = i + 1 + l1, l = j - 1 - l2;
+  double best = INFINITY;
+  if (l2 == 0) {  // left bulge: run i+1..k-1 (ul), pair (k, j-1)
+    const double *q = cblk(D.Qb, n, k, j - 1);
+    for (int b = 0; b < D.d[k - 1]; b++)
+      for (int x = 0; x < D.d[k]; x++) best = fmin(best, ul[a * 6 + b] + E(D, k - 1, b, x) + q[x * 6 + dd]);
+    return D.bulge[l1] + best;
+  }
+  if (l1 == 0) {  // right bulge: pair (i+1, l), run l+1..j-1 (ur)
+    const double *q = cblk(D.Qb, n, i + 1, l);
+    for (int y = 0; y < D.d[l]; y++)
+      for (int c = 0; c < D.d[l + 1]; c++) best = fmin(best, q[a * 6 + y] + E(D, l, y, c) + ur[c * 6 + dd]);
+    return D.bulge[l2] + best;
+  }
+  const double *di = cblk(D.DI, n, k, l);  // interior loop
+  for (int c = 0; c < D.d[l + 1]; c++) {
+    double T = INFINITY;
+    for (int b = 0; b < D.d[k - 1]; b++) T = fmin(T, ul[a * 6 + b] + di[b * 6 + c]);
+    best = fmin(best, T + ur[c * 6 + dd]);
+  }
+  return D.interior[l1 + l2] + best;
+}
+
+__device__ __forceinline__ double hairpin_term(const MfeDev &D, int i, int j, int s, int s2, int t, int a, int b) {
+  return E(D, i, s, a) + cblk(D.U, D.n, i + 1, j - 1)[a * 6 + b] + E(D, j - 1, b, s2) +
+         MM(D, NT(D, i + 1, a), NT(D, j - 1, b), t);
+}
+__device__ __forceinline__ double stack_term(const MfeDev &D, int i, int j, int s, int s2, int t, int x, int y) {
+  const double q = cblk(D.Qb, D.n, i + 1, j - 1)[x * 6 + y];
+  if (q == INFINITY) return INFINITY;
+  const int t2 = bpair(NT(D, i + 1, x), NT(D, j - 1, y));
+  return E(D, i, s, x) + q + E(D, j - 1, y, s2) + D.stack[t * 6 + t2];
+}
+__device__ __forceinline__ double ml_term(const MfeDev &D, int i, int j, int s, int s2, int x, int y) {
+  return E(D, i, s, x) + cblk(D.QmX, D.n, i + 1, j - 1)[x * 6 + y] + E(D, j - 1, y, s2);
+}
+__device__ __forceinline__ double di_term(const MfeDev &D, const double *qb, int i, int j, int b, int c, int x,
+                                          int y) {
+  const double q = qb[x * 6 + y];
+  if (q == INFINITY) return INFINITY;
+  const int t2 = bpair(NT(D, j, y), NT(D, i, x));
+  return E(D, i - 1, b, x) + q + E(D, j, y, c) + MM(D, NT(D, j + 1, c), NT(D, i - 1, b), t2);
+}
+__device__ __forceinline__ double outer_term(const MfeDev &D, int i, int j, int s, int s2, int a, int dd,
+                                             double w) {
+  return E(D, i, s, a) + E(D, j - 1, dd, s2) + w;
+}
+
+__global__ __launch_bounds__(256) void mfe_fill(double *p, size_t count) {
+  for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < count; k += (size_t)gridDim.x * 256) p[k] = INFINITY;
+}
+
+__global__ __launch_bounds__(64) void mfe_init_runs(MfeDev D) {
+  const int p = blockIdx.x, a = threadIdx.x;
+  if (a < D.d[p]) blk(D.U, D.n, p, p)[a * 6 + a] = D.v[p * 6 + a];
+}
+
+// cell (i, i + dl), dl >= 1
+__global__ __launch_bounds__(MT) void mfe_diag(MfeDev D, int dl) {
+  __shared__ double sUL[MAXW][36], sUR[MAXW][36];  // U[i+1][i+l1], U[j-l2][j-1], l = 1..30
+  __shared__ double sW[7][3][36];                  // window minima per thread group
+  __shared__ double sG[3][36], sQb[36], sQ1p[36];
+  __shared__ double sSp[MT / 64][36];
+  const int n = D.n, i = blockIdx.x, j = i + dl, tid = threadIdx.x;
+  if (j >= n) return;
+  // unpaired run [i..j]
+  if (tid < 36) {
+    const int a = tid / 6, b = tid % 6;
+    if (a < D.d[i] && b < D.d[j]) {
+      const double *ul = cblk(D.U, n, i, j - 1);
+      double best = INFINITY;
+      for (int c = 0; c < D.d[j - 1]; c++) best = fmin(best, ul[a * 6 + c] + E(D, j - 1, c, b));
+      blk(D.U, n, i, j)[tid] = best + D.v[j * 6 + b];
+    }
+  }
+  if (dl < 4) return;
+  // ---- bulge and interior windows: minima GL (left bulges), GR (right), FI (interior)
+  for (int q = tid; q < MAXW * 36; q += MT) {
+    const int r = q / 36, x = q % 36, l = r + 1;
+    sUL[r][x] = i + l <= n - 1 ? cblk(D.U, n, i + 1, i + l)[x] : INFINITY;
+    sUR[r][x] = j - l >= 0 ? cblk(D.U, n, j - l, j - 1)[x] : INFINITY;
+  }
+  __syncthreads();
+  {
+    const int q = tid % 36, g = tid / 36, a = q / 6, dd = q % 6;
+    double mL = INFINITY, mR = INFINITY, mI = INFINITY;
+    if (g < 7 && a < D.d[i + 1] && dd < D.d[j - 1]) {
+      for (int w = g; w < 31 * 31; w += 7) {
+        int l1, l2;
+        if (!window_of(w, dl, l1, l2)) continue;
+        const double *ul = l1 > 0 ? sUL[l1 - 1] : nullptr, *ur = l2 > 0 ? sUR[l2 - 1] : nullptr;
+        const double val = window_value(D, i, j, l1, l2, a, dd, ul, ur);
+        if (l2 == 0) mL = fmin(mL, val);
+        else if (l1 == 0) mR = fmin(mR, val);
+        else mI = fmin(mI, val);
+      }
+    }
+    if (g < 7) {
+      sW[g][0][q] = mL;
+      sW[g][1][q] = mR;
+      sW[g][2][q] = mI;
+    }
+  }
+  __syncthreads();
+  if (tid < 3 * 36) {
+    const int k = tid / 36, q = tid % 36;
+    double m = INFINITY;
+    for (int g = 0; g < 7; g++) m = fmin(m, sW[g][k][q]);
+    sG[k][q] = m;
+  }
+  __syncthreads();
+  // ---- the pair (i, j)
+  if (tid < 36) {
+    const int s = tid / 6, s2 = tid % 6;
+    double qb = INFINITY;
+    const int t = s < D.d[i] && s2 < D.d[j] ? bpair(NT(D, i, s), NT(D, j, s2)) : -1;
+    if (t >= 0) {
+      double h = INFINITY;
+      for (int a = 0; a < D.d[i + 1]; a++)
+        for (int b = 0; b < D.d[j - 1]; b++) h = fmin(h, hairpin_term(D, i, j, s, s2, t, a, b));
+      double acc = fmin(INFINITY, D.hp[j - i - 1] + h);
+      if ((j - 1) - (i + 1) >= 4)
+        for (int x = 0; x < D.d[i + 1]; x++)
+          for (int y = 0; y < D.d[j - 1]; y++) acc = fmin(acc, stack_term(D, i, j, s, s2, t, x, y));
+      for (int a = 0; a < D.d[i + 1]; a++)
+        for (int dd = 0; dd < D.d[j - 1]; dd++) {
+          const int q = a * 6 + dd;
+          acc = fmin(acc, outer_term(D, i, j, s, s2, a, dd,
+                                     fmin(fmin(sG[0][q], sG[1][q]),
+                                          sG[2][q] + MM(D, NT(D, i + 1, a), NT(D, j - 1, dd), t))));
+        }
+      double mlv = INFINITY;
+      for (int x = 0; x < D.d[i + 1]; x++)
+        for (int y = 0; y < D.d[j - 1]; y++) mlv = fmin(mlv, ml_term(D, i, j, s, s2, x, y));
+      acc = fmin(acc, D.ml_ab + mlv);
+      qb = D.v[i * 6 + s] + D.v[j * 6 + s2] + acc;
+      blk(D.Qb, n, i, j)[tid] = qb;
+    }
+    sQb[tid] = qb;
+  }
+  __syncthreads();
+  if (tid < 36) {
+    const int a = tid / 6, b = tid % 6;
+    // DI[i][j](b', c'): (i, j) as the inner pair of an interior loop
+    if (i >= 1 && j + 1 < n && a < D.d[i - 1] && b < D.d[j + 1]) {
+      double best = INFINITY;
+      for (int x = 0; x < D.d[i]; x++)
+        for (int y = 0; y < D.d[j]; y++) best = fmin(best, di_term(D, sQb, i, j, a, b, x, y));
+      blk(D.DI, n, i, j)[tid] = best;
+    }
+    // one branch with an unpaired tail, then with an unpaired prefix
+    const int s = a, s2 = b;
+    double q1p = INFINITY;
+    if (s < D.d[i] && s2 < D.d[j]) {
+      const double *q1l = cblk(D.Qm1, n, i, j - 1), *q1pr = cblk(D.Qm1p, n, i + 1, j);
+      double tail = INFINITY;
+      for (int t = 0; t < D.d[j - 1]; t++) tail = fmin(tail, q1l[s * 6 + t] + E(D, j - 1, t, s2));
+      const double q1 = fmin(sQb[tid] + D.ml_b, tail + D.v[j * 6 + s2] + D.ml_c);
+      blk(D.Qm1, n, i, j)[tid] = q1;
+      double pre = INFINITY;
+      for (int t = 0; t < D.d[i + 1]; t++) pre = fmin(pre, E(D, i, s, t) + q1pr[t * 6 + s2]);
+      q1p = fmin(q1, D.v[i * 6 + s] + D.ml_c + pre);
+      blk(D.Qm1p, n, i, j)[tid] = q1p;
+    }
+    sQ1p[tid] = q1p;
+  }
+  // ---- two or more branches: the split over u (threads over u)
+  double part[36];
+#pragma unroll
+  for (int q = 0; q < 36; q++) part[q] = INFINITY;
+  const int di = D.d[i], dj = D.d[j];
+  for (int u = i + 5 + tid; u <= j - 4; u += MT) {
+    const double *qm = cblk(D.Qm, n, i, u - 1), *q1 = cblk(D.Qm1, n, u, j);
+    const int du1 = D.d[u - 1], du = D.d[u];
+    for (int t = 0; t < du1; t++)
+      for (int t2 = 0; t2 < du; t2++) {
+        const double et = E(D, u - 1, t, t2);
+        double qv[6];
+#pragma unroll
+        for (int s2 = 0; s2 < 6; s2++) qv[s2] = s2 < dj ? q1[t2 * 6 + s2] : INFINITY;
+#pragma unroll
+        for (int s = 0; s < 6; s++)
+          if (s < di) {
+            const double ae = qm[s * 6 + t] + et;
+#pragma unroll
+            for (int s2 = 0; s2 < 6; s2++) part[s * 6 + s2] = fmin(part[s * 6 + s2], ae + qv[s2]);
+          }
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < 36; q++) {
+    double m = part[q];
+    for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+    part[q] = m;
+  }
+  if ((tid & 63) == 0)
+    for (int q = 0; q < 36; q++) sSp[tid >> 6][q] = part[q];
+  __syncthreads();
+  if (tid < 36) {
+    const int s = tid / 6, s2 = tid % 6;
+    if (s < di && s2 < dj) {
+      double x = INFINITY;
+      for (int w = 0; w < MT / 64; w++) x = fmin(x, sSp[w][tid]);
+      blk(D.QmX, n, i, j)[tid] = x;
+      blk(D.Qm, n, i, j)[tid] = fmin(x, sQ1p[tid]);
+    }
+  }
+}
+
+// first-of-smallest reduction over a workgroup: (value, order index); an
+// alternative of value +inf is never chosen
+struct Pick {
+  double v;
+  int idx;
+};
+__device__ __forceinline__ bool better(double v, int idx, const Pick &p) {
+  return v < p.v || (v == p.v && v != INFINITY && idx < p.idx);
+}
+__device__ Pick pick_reduce(Pick p, double *sv, int *si) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  sv[tid] = p.v;
+  si[tid] = p.idx;
+  __syncthreads();
+  for (int w = MT / 2; w >= 1; w >>= 1) {
+    if (tid < w) {
+      const double ov = sv[tid + w];
+      const int oi = si[tid + w];
+      if (better(ov, oi, Pick{sv[tid], si[tid]})) {
+        sv[tid] = ov;
+        si[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const Pick r{sv[0], si[0]};
+  __syncthreads();
+  return r;
+}
+
+// exterior prefix: Z5[j](t) over the structures of [0..j] with slot t at j
+__global__ __launch_bounds__(MT) void mfe_exterior(MfeDev D) {
+  __shared__ double sP[MT / 64][6];
+  const int n = D.n, tid = threadIdx.x;
+  if (tid < 6) D.Z5[tid] = tid < D.d[0] ? D.v[tid] : INFINITY;
+  __syncthreads();
+  for (int j = 1; j < n; j++) {
+    // k pairs j, k = 1..j-4: minima over (k, slot of k-1, slot of k) per slot t of j
+    double part[6];
+#pragma unroll
+    for (int t = 0; t < 6; t++) part[t] = INFINITY;
+    const int nk = j >= 5 ? (j - 4) * 36 : 0, dj = D.d[j];
+    for (int q = tid; q < nk; q += MT) {
+      const int k = 1 + q / 36, s = (q % 36) / 6, x = q % 6;
+      if (s >= D.d[k - 1] || x >= D.d[k]) continue;
+      const double ze = D.Z5[(k - 1) * 6 + s] + E(D, k - 1, s, x);
+      const double *qb = cblk(D.Qb, n, k, j);
+#pragma unroll
+      for (int t = 0; t < 6; t++)
+        if (t < dj) part[t] = fmin(part[t], ze + qb[x * 6 + t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 6; t++)
+      for (int off = 32; off >= 1; off >>= 1) part[t] = fmin(part[t], __shfl_xor(part[t], off, 64));
+    if ((tid & 63) == 0)
+      for (int t = 0; t < 6; t++) sP[tid >> 6][t] = part[t];
+    __syncthreads();
+    if (tid < 6) {
+      const int t = tid;
+      double best = INFINITY;
+      if (t < dj) {
+        double un = INFINITY;
+        for (int s = 0; s < D.d[j - 1]; s++) un = fmin(un, D.Z5[(j - 1) * 6 + s] + E(D, j - 1, s, t));
+        best = un + D.v[j * 6 + t];
+        if (j >= 4)
+          for (int x = 0; x < D.d[0]; x++) best = fmin(best, cblk(D.Qb, n, 0, j)[x * 6 + t]);
+        for (int w = 0; w < MT / 64; w++) best = fmin(best, sP[w][t]);
+      }
+      D.Z5[j * 6 + t] = best;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double m = INFINITY;
+    for (int t = 0; t < D.d[n - 1]; t++) m = fmin(m, D.Z5[(n - 1) * 6 + t]);
+    D.out[0] = m;
+  }
+}
+
+enum { K_EXT = 0, K_PAIR, K_RUN, K_QM1, K_QM1P, K_QM, K_QMX };
+
+// ---- argmin traceback, one workgroup
+__global__ __launch_bounds__(MT) void mfe_traceback(MfeDev D) {
+  __shared__ double sv[MT];
+  __shared__ int si[MT];
+  __shared__ int top;
+  __shared__ int frag[5];
+  const int n = D.n, tid = threadIdx.x;
+  auto push = [&](int kind, int i, int j, int s, int s2) {  // thread 0 only
+    if (top >= D.cap) {
+      D.err[0] = 1;
+      return;
+    }
+    int *f = D.stk + top * 5;
+    f[0] = kind;
+    f[1] = i;
+    f[2] = j;
+    f[3] = s;
+    f[4] = s2;
+    top++;
+  };
+  if (tid == 0) {
+    top = 0;
+    D.err[0] = 0;
+    int bt = -1;
+    double bv = INFINITY;
+    for (int t = 0; t < D.d[n - 1]; t++)
+      if (D.Z5[(n - 1) * 6 + t] < bv) {
+        bv = D.Z5[(n - 1) * 6 + t];
+        bt = t;
+      }
+    push(K_EXT, n - 1, 0, bt, 0);
+  }
+  for (int p = tid; p < n; p += MT) {
+    D.slot[p] = -1;
+    D.pt[p] = -1;
+  }
+  __syncthreads();
+  while (true) {
+    if (tid == 0) {
+      if (top > 0 && D.err[0] == 0) {
+        top--;
+        for (int k = 0; k < 5; k++) frag[k] = D.stk[top * 5 + k];
+      } else {
+        frag[0] = -1;
+      }
+    }
+    __syncthreads();
+    const int kind = frag[0], i = frag[1], j = frag[2], s = frag[3], s2 = frag[4];
+    __syncthreads();
+    if (kind < 0) break;
+    if (kind == K_EXT) {
+      // exterior at (j = i here, slot s): j unpaired [s'], 0 pairs j [100 + x], k pairs j [1000 + ...]
+      const int jj = i, t = s;
+      if (tid == 0) D.slot[jj] = t;
+      if (jj == 0) continue;
+      Pick p{INFINITY, 0x7fffffff};
+      const int nk = jj >= 5 ? (jj - 4) * 36 : 0;
+      for (int q = tid; q < nk; q += MT) {
+        const int k = 1 + q / 36, sp = (q % 36) / 6, x = q % 6;
+        if (sp >= D.d[k - 1] || x >= D.d[k]) continue;
+        const double val = D.Z5[(k - 1) * 6 + sp] + E(D, k - 1, sp, x) + cblk(D.Qb, n, k, jj)[x * 6 + t];
+        const int idx = 1000 + (k * 6 + sp) * 6 + x;
+        if (better(val, idx, p)) p = Pick{val, idx};
+      }
+      if (tid == 0) {
+        for (int sp = 0; sp < D.d[jj - 1]; sp++) {
+          const double val = (D.Z5[(jj - 1) * 6 + sp] + E(D, jj - 1, sp, t)) + D.v[jj * 6 + t];
+          if (better(val, sp, p)) p = Pick{val, sp};
+        }
+        if (jj >= 4)
+          for (int x = 0; x < D.d[0]; x++) {
+            const double val = cblk(D.Qb, n, 0, jj)[x * 6 + t];
+            if (better(val, 100 + x, p)) p = Pick{val, 100 + x};
+          }
+      }
+      p = pick_reduce(p, sv, si);
+      if (tid == 0) {
+        if (p.v == INFINITY) {
+          D.err[0] = 2;  // no finite alternative: the stored minimum cannot be reproduced
+        } else if (p.idx < 100) {
+          push(K_EXT, jj - 1, 0, p.idx, 0);
+        } else if (p.idx < 1000) {
+          push(K_PAIR, 0, jj, p.idx - 100, t);
+        } else {
+          const int r = p.idx - 1000, x = r % 6, sp = (r / 6) % 6, k = r / 36;
+          push(K_EXT, k - 1, 0, sp, 0);
+          push(K_PAIR, k, jj, x, t);
+        }
+      }
+    } else if (kind == K_RUN) {
+      if (tid == 0) {
+        D.slot[j] = s2;
+        if (i != j) {
+          const double *ul = cblk(D.U, n, i, j - 1);
+          int bc = -1;
+          double bv = INFINITY;
+          for (int c = 0; c < D.d[j - 1]; c++) {
+            const double val = ul[s * 6 + c] + E(D, j - 1, c, s2);
+            if (val < bv) {
+              bv = val;
+              bc = c;
+            }
+          }
+          if (bc < 0) D.err[0] = 2;
+          else push(K_RUN, i, j - 1, s, bc);
+        }
+      }
+    } else if (kind == K_PAIR) {
+      if (tid == 0) {
+        D.slot[i] = s;
+        D.slot[j] = s2;
+        D.pt[i] = j;
+        D.pt[j] = i;
+      }
+      const int t = bpair(NT(D, i, s), NT(D, j, s2)), dl = j - i;
+      // level 1: hairpin [0], stack [1], windows [2 + l1 * 31 + l2], multiloop [2000]
+      Pick p{INFINITY, 0x7fffffff};
+      for (int w = tid; w < 31 * 31; w += MT) {
+        int l1, l2;
+        if (!window_of(w, dl, l1, l2)) continue;
+        const double *ul = l1 > 0 ? cblk(D.U, n, i + 1, i + l1) : nullptr;
+        const double *ur = l2 > 0 ? cblk(D.U, n, j - l2, j - 1) : nullptr;
+        double best = INFINITY;
+        for (int a = 0; a < D.d[i + 1]; a++)
+          for (int dd = 0; dd < D.d[j - 1]; dd++) {
+            double wv = window_value(D, i, j, l1, l2, a, dd, ul, ur);
+            if (l1 > 0 && l2 > 0) wv = wv + MM(D, NT(D, i + 1, a), NT(D, j - 1, dd), t);
+            best = fmin(best, outer_term(D, i, j, s, s2, a, dd, wv));
+          }
+        if (better(best, 2 + w, p)) p = Pick{best, 2 + w};
+      }
+      if (tid == 0) {
+        double h = INFINITY;
+        for (int a = 0; a < D.d[i + 1]; a++)
+          for (int b = 0; b < D.d[j - 1]; b++) h = fmin(h, hairpin_term(D, i, j, s, s2, t, a, b));
+        const double hv = D.hp[j - i - 1] + h;
+        if (better(hv, 0, p)) p = Pick{hv, 0};
+        if ((j - 1) - (i + 1) >= 4) {
+          double st = INFINITY;
+          for (int x = 0; x < D.d[i + 1]; x++)
+            for (int y = 0; y < D.d[j - 1]; y++) st = fmin(st, stack_term(D, i, j, s, s2, t, x, y));
+          if (better(st, 1, p)) p = Pick{st, 1};
+        }
+        double mlv = INFINITY;
+        for (int x = 0; x < D.d[i + 1]; x++)
+          for (int y = 0; y < D.d[j - 1]; y++) mlv = fmin(mlv, ml_term(D, i, j, s, s2, x, y));
+        const double mv = D.ml_ab + mlv;
+        if (better(mv, 2000, p)) p = Pick{mv, 2000};
+      }
+      p = pick_reduce(p, sv, si);
+      if (tid == 0 && p.v == INFINITY) D.err[0] = 2;
+      if (tid == 0 && p.v != INFINITY) {
+        auto first6 = [&](auto f, int da, int db) {  // first (x, y) of smallest f(x, y); -1 if none
+          int bi = -1;
+          double bv = INFINITY;
+          for (int x = 0; x < da; x++)
+            for (int y = 0; y < db; y++) {
+              const double val = f(x, y);
+              if (val < bv) {
+                bv = val;
+                bi = x * 6 + y;
+              }
+            }
+          if (bi < 0) D.err[0] = 2;
+          return bi < 0 ? 0 : bi;
+        };
+        if (p.idx == 0) {
+          const int c = first6([&](int a, int b) { return hairpin_term(D, i, j, s, s2, t, a, b); }, D.d[i + 1],
+                               D.d[j - 1]);
+          push(K_RUN, i + 1, j - 1, c / 6, c % 6);
+        } else if (p.idx == 1) {
+          const int c = first6([&](int x, int y) { return stack_term(D, i, j, s, s2, t, x, y); }, D.d[i + 1],
+                               D.d[j - 1]);
+          push(K_PAIR, i + 1, j - 1, c / 6, c % 6);
+        } else if (p.idx == 2000) {
+          const int c = first6([&](int x, int y) { return ml_term(D, i, j, s, s2, x, y); }, D.d[i + 1],
+                               D.d[j - 1]);
+          push(K_QMX, i + 1, j - 1, c / 6, c % 6);
+        } else {
+          const int w = p.idx - 2, l1 = w / 31, l2 = w % 31, k = i + 1 + l1, l = j - 1 - l2;
+          const double *ul = l1 > 0 ? cblk(D.U, n, i + 1, i + l1) : nullptr;
+          const double *ur = l2 > 0 ? cblk(D.U, n, j - l2, j - 1) : nullptr;
+          const int c = first6(
+              [&](int a, int dd) {
+                double wv = window_value(D, i, j, l1, l2, a, dd, ul, ur);
+                if (l1 > 0 && l2 > 0) wv = wv + MM(D, NT(D, i + 1, a), NT(D, j - 1, dd), t);
+                return outer_term(D, i, j, s, s2, a, dd, wv);
+              },
+              D.d[i + 1], D.d[j - 1]);
+          const int a = c / 6, dd = c % 6;
+          if (l2 == 0) {  // left bulge: (b, x)
+            const double *q = cblk(D.Qb, n, k, j - 1);
+            const int g = first6([&](int b, int x) { return ul[a * 6 + b] + E(D, k - 1, b, x) + q[x * 6 + dd]; },
+                                 D.d[k - 1], D.d[k]);
+            push(K_RUN, i + 1, k - 1, a, g / 6);
+            push(K_PAIR, k, j - 1, g % 6, dd);
+          } else if (l1 == 0) {  // right bulge: (y, c)
+            const double *q = cblk(D.Qb, n, i + 1, l);
+            const int g = first6([&](int y, int cc) { return q[a * 6 + y] + E(D, l, y, cc) + ur[cc * 6 + dd]; },
+                                 D.d[l], D.d[l + 1]);
+            push(K_PAIR, i + 1, l, a, g / 6);
+            push(K_RUN, l + 1, j - 1, g % 6, dd);
+          } else {  // interior: c, then b, then the inner pair's slots
+            const double *di = cblk(D.DI, n, k, l);
+            int cc = -1;
+            double bv = INFINITY;
+            for (int c2 = 0; c2 < D.d[l + 1]; c2++) {
+              double T = INFINITY;
+              for (int b = 0; b < D.d[k - 1]; b++) T = fmin(T, ul[a * 6 + b] + di[b * 6 + c2]);
+              const double val = T + ur[c2 * 6 + dd];
+              if (val < bv) {
+                bv = val;
+                cc = c2;
+              }
+            }
+            if (cc < 0) {
+              D.err[0] = 2;
+              cc = 0;
+            }
+            int bb = -1;
+            bv = INFINITY;
+            for (int b = 0; b < D.d[k - 1]; b++) {
+              const double val = ul[a * 6 + b] + di[b * 6 + cc];
+              if (val < bv) {
+                bv = val;
+                bb = b;
+              }
+            }
+            if (bb < 0) {
+              D.err[0] = 2;
+              bb = 0;
+            }
+            const double *qk = cblk(D.Qb, n, k, l);
+            const int g = first6([&](int x, int y) { return di_term(D, qk, k, l, bb, cc, x, y); }, D.d[k], D.d[l]);
+            push(K_RUN, i + 1, k - 1, a, bb);
+            push(K_PAIR, k, l, g / 6, g % 6);
+            push(K_RUN, l + 1, j - 1, cc, dd);
+          }
+        }
+      }
+    } else if (kind == K_QM || kind == K_QMX) {
+      Pick p{INFINITY, 0x7fffffff};
+      for (int u = i + 5 + tid; u <= j - 4; u += MT) {
+        const double *qm = cblk(D.Qm, n, i, u - 1), *q1 = cblk(D.Qm1, n, u, j);
+        for (int t = 0; t < D.d[u - 1]; t++)
+          for (int t2 = 0; t2 < D.d[u]; t2++) {
+            const double val = qm[s * 6 + t] + E(D, u - 1, t, t2) + q1[t2 * 6 + s2];
+            const int idx = (u * 6 + t) * 6 + t2;
+            if (better(val, idx, p)) p = Pick{val, idx};
+          }
+      }
+      if (tid == 0 && kind == K_QM) {  // the one-branch form, last in order
+        const double val = cblk(D.Qm1p, n, i, j)[s * 6 + s2];
+        if (better(val, 0x7ffffffe, p)) p = Pick{val, 0x7ffffffe};
+      }
+      p = pick_reduce(p, sv, si);
+      if (tid == 0) {
+        if (p.v == INFINITY) {
+          D.err[0] = 2;
+        } else if (p.idx == 0x7ffffffe) {
+          push(K_QM1P, i, j, s, s2);
+        } else {
+          const int t2 = p.idx % 6, t = (p.idx / 6) % 6, u = p.idx / 36;
+          push(K_QM, i, u - 1, s, t);
+          push(K_QM1, u, j, t2, s2);
+        }
+      }
+    } else if (kind == K_QM1) {
+      if (tid == 0) {
+        double bv = cblk(D.Qb, n, i, j)[s * 6 + s2] + D.ml_b;
+        int bi = -2;
+        for (int t = 0; t < D.d[j - 1]; t++) {
+          const double val = (cblk(D.Qm1, n, i, j - 1)[s * 6 + t] + E(D, j - 1, t, s2)) + D.v[j * 6 + s2] + D.ml_c;
+          if (val < bv) {
+            bv = val;
+            bi = t;
+          }
+        }
+        if (bi == -2) {
+          push(K_PAIR, i, j, s, s2);
+        } else {
+          D.slot[j] = s2;
+          push(K_QM1, i, j - 1, s, bi);
+        }
+      }
+    } else if (kind == K_QM1P) {
+      if (tid == 0) {
+        double bv = cblk(D.Qm1, n, i, j)[s * 6 + s2];
+        int bi = -2;
+        for (int t = 0; t < D.d[i + 1]; t++) {
+          const double val = D.v[i * 6 + s] + D.ml_c + (E(D, i, s, t) + cblk(D.Qm1p, n, i + 1, j)[t * 6 + s2]);
+          if (val < bv) {
+            bv = val;
+            bi = t;
+          }
+        }
+        if (bi == -2) {
+          push(K_QM1, i, j, s, s2);
+        } else {
+          D.slot[i] = s;
+          push(K_QM1P, i + 1, j, bi, s2);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" cdz_status cdz_mfe(cdz_handle *h, const cdz_problem *prob, double *mfe, uint8_t *codons, int32_t *pairs) {
+  if (!h || !prob || !mfe) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
+  HostTables t;
+  cdz_status st = build_tables(h, prob->n_aa, prob->aa, prob->theta1, prob->theta2, t);
+  if (st != CDZ_OK) return st;
+  const int n = t.n, m = t.m;
+  const double inf = INFINITY;
+  // energies: vertices, edges, hairpins by length, loop tables
+  std::vector<double> v((size_t)n * 6, 0.0), e((size_t)n * 36, inf), hp(n + 1, inf);
+  std::vector<signed char> nt((size_t)n * 6, 0);
+  for (int p = 0; p < n; p++) {
+    for (int s = 0; s < t.d[p]; s++) {
+      nt[p * 6 + s] = (signed char)t.nt[p * 6 + s];
+      if (p % 3 == 1 && prob->theta1) v[p * 6 + s] = -prob->theta1[(p / 3) * 6 + s];
+    }
+    if (p + 1 < n)
+      for (int s = 0; s < t.d[p]; s++)
+        for (int u = 0; u < t.d[p + 1]; u++) {
+          if (p % 3 != 2) e[(size_t)p * 36 + s * 6 + u] = s == u ? 0.0 : inf;
+          else e[(size_t)p * 36 + s * 6 + u] = prob->theta2 ? -prob->theta2[((p / 3 + 1) * 6 + s) * 6 + u] : 0.0;
+        }
+  }
+  const cdz_energy &En = h->en;
+  for (int L = 3; L <= n; L++) hp[L] = L <= 30 ? En.hairpin[L] : En.hairpin[30] + En.extrap * std::log((double)L / 30.0);
+  // device workspace: tables, then the seven arrays
+  const size_t cell = (size_t)n * n * 36;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = (off + 255) / 256 * 256;
+    off = at + bytes;
+    return at;
+  };
+  const size_t oD = take(n * sizeof(int)), oNt = take(nt.size()), oV = take(v.size() * 8), oE = take(e.size() * 8),
+               oHp = take(hp.size() * 8), oSt = take(36 * 8), oBu = take(31 * 8), oIn = take(31 * 8),
+               oMm = take(96 * 8), oZ5 = take((size_t)n * 6 * 8), oSl = take((size_t)n * 4), oPt = take((size_t)n * 4),
+               oStk = take((size_t)(4 * n + 16) * 5 * 4), oOut = take(8), oErr = take(4);
+  size_t oArr[7];
+  for (int k = 0; k < 7; k++) oArr[k] = take(cell * 8);
+  DevBuf ws;
+  if (hipMalloc(&ws.p, off) != hipSuccess) {
+    (void)hipGetLastError();
+    ws.p = nullptr;
+    return cdz_fail(h, CDZ_ERR_NOMEM, "MFE workspace of " + std::to_string(off) + " bytes");
+  }
+  char *base = (char *)ws.p;
+  hipStream_t sm = h->stream;
+  std::vector<int> dvec(t.d.begin(), t.d.end());
+  std::vector<double> tabs(36 + 31 + 31 + 96);
+  memcpy(tabs.data(), En.stack, 36 * 8);
+  memcpy(tabs.data() + 36, En.bulge, 31 * 8);
+  memcpy(tabs.data() + 67, En.interior, 31 * 8);
+  memcpy(tabs.data() + 98, En.mismatch, 96 * 8);
+  HIPCHK(h, hipMemcpyAsync(base + oD, dvec.data(), n * sizeof(int), hipMemcpyHostToDevice, sm));
+  HIPCHK(h, hipMemcpyAsync(base + oNt, nt.data(), nt.size(), hipMemcpyHostToDevice, sm));
+  HIPCHK(h, hipMemcpyAsync(base + oV, v.data(), v.size() * 8, hipMemcpyHostToDevice, sm));
+  HIPCHK(h, hipMemcpyAsync(base + oE, e.data(), e.size() * 8, hipMemcpyHostToDevice, sm));
+  HIPCHK(h, hipMemcpyAsync(base + oHp, hp.data(), hp.size() * 8, hipMemcpyHostToDevice, sm));
+  HIPCHK(h, hipMemcpyAsync(base + oSt, tabs.data(), 36 * 8, hipMemcpyHostToDevice, sm));
+  HIPCHK(h, hipMemcpyAsync(base + oBu, tabs.data() + 36, 31 * 8, hipMemcpyHostToDevice, sm));
+  HIPCHK(h, hipMemcpyAsync(base + oIn, tabs.data() + 67, 31 * 8, hipMemcpyHostToDevice, sm));
+  HIPCHK(h, hipMemcpyAsync(base + oMm, tabs.data() + 98, 96 * 8, hipMemcpyHostToDevice, sm));
+  MfeDev D;
+  D.n = n;
+  D.d = (const int *)(base + oD);
+  D.nt = (const signed char *)(base + oNt);
+  D.v = (const double *)(base + oV);
+  D.e = (const double *)(base + oE);
+  D.hp = (const double *)(base + oHp);
+  D.stack = (const double *)(base + oSt);
+  D.bulge = (const double *)(base + oBu);
+  D.interior = (const double *)(base + oIn);
+  D.mm = (const double *)(base + oMm);
+  D.ml_ab = En.ml_a + En.ml_b;
+  D.ml_b = En.ml_b;
+  D.ml_c = En.ml_c;
+  double **arr[7] = {&D.U, &D.Qb, &D.DI, &D.Qm1, &D.Qm1p, &D.QmX, &D.Qm};
+  for (int k = 0; k < 7; k++) *arr[k] = (double *)(base + oArr[k]);
+  D.Z5 = (double *)(base + oZ5);
+  D.slot = (int *)(base + oSl);
+  D.pt = (int *)(base + oPt);
+  D.stk = (int *)(base + oStk);
+  D.cap = 4 * n + 16;
+  D.out = (double *)(base + oOut);
+  D.err = (int *)(base + oErr);
+  HIPCHK(h, hipEventRecord(h->ev[4], sm));
+  for (int k = 0; k < 7; k++) hipLaunchKernelGGL(mfe_fill, dim3(2048), dim3(256), 0, sm, *arr[k], cell);
+  hipLaunchKernelGGL(mfe_init_runs, dim3(n), dim3(64), 0, sm, D);
+  for (int dl = 1; dl < n; dl++) hipLaunchKernelGGL(mfe_diag, dim3(n - dl), dim3(MT), 0, sm, D, dl);
+  hipLaunchKernelGGL(mfe_exterior, dim3(1), dim3(MT), 0, sm, D);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipEventRecord(h->ev[5], sm));
+  if (codons || pairs) hipLaunchKernelGGL(mfe_traceback, dim3(1), dim3(MT), 0, sm, D);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipEventRecord(h->ev[6], sm));
+  double res = 0;
+  int err = 0;
+  std::vector<int> slot(n), pt(n);
+  HIPCHK(h, hipMemcpyAsync(&res, D.out, 8, hipMemcpyDeviceToHost, sm));
+  if (codons || pairs) {
+    HIPCHK(h, hipMemcpyAsync(&err, D.err, 4, hipMemcpyDeviceToHost, sm));
+    HIPCHK(h, hipMemcpyAsync(slot.data(), D.slot, n * 4, hipMemcpyDeviceToHost, sm));
+    HIPCHK(h, hipMemcpyAsync(pt.data(), D.pt, n * 4, hipMemcpyDeviceToHost, sm));
+  }
+  HIPCHK(h, hipStreamSynchronize(sm));
+  float ms = 0;
+  HIPCHK(h, hipEventElapsedTime(&ms, h->ev[4], h->ev[5]));
+  h->times[0] = ms;
+  if (codons || pairs) {
+    HIPCHK(h, hipEventElapsedTime(&ms, h->ev[5], h->ev[6]));
+    h->times[2] = ms;
+  }
+  *mfe = res;
+  if (!std::isfinite(res)) return cdz_fail(h, CDZ_ERR_NUMERIC, "minimum free energy not finite");
+  if (codons || pairs) {
+    if (err == 1) return cdz_fail(h, CDZ_ERR_STATE, "traceback stack overflow");
+    if (err) return cdz_fail(h, CDZ_ERR_STATE, "traceback found no alternative reproducing the minimum");
+    for (int a = 0; a < m; a++) {
+      const int s = slot[3 * a];
+      if (s < 0 || slot[3 * a + 1] != s || slot[3 * a + 2] != s)
+        return cdz_fail(h, CDZ_ERR_STATE, "traceback left an inconsistent codon at residue " + std::to_string(a));
+      if (codons) codons[a] = (uint8_t)s;
+    }
+    if (pairs)
+      for (int p = 0; p < n; p++) pairs[p] = pt[p];
+  }
+  return CDZ_OK;
+}

@@ -17,11 +17,15 @@ here comes from the HIP path.
       r_tol 0.002, unlimited Anderson history, at most 30 evaluations:
       errors per evaluation, the final bonuses f [26][6], converged
 
+  oracle_mfe_workload2_300nt.npz, oracle_mfe_workload3_900nt.npz
+      minimum free energy (Section 4d) of workloads 2 and 3 and the state the
+      oracle's traceback returns: mfe, codons [m], pairs [n]
+
 Each file also records the sha256 of the oracle sources it was computed
 with.  The 900-nt marginals take about two minutes on 8 cores, so the 900-nt
 frequency matching about half an hour.
 
-Usage: python tests/golden/make_oracle_goldens.py [--only 2|3|4] [--freq 2|3]
+Usage: python tests/golden/make_oracle_goldens.py [--only 2|3|4] [--freq 2|3] [--mfe 2|3]
 """
 from __future__ import annotations
 
@@ -82,6 +86,24 @@ def load_freq(k: int) -> dict:
     return {key: z[key] for key in z.files}
 
 
+def mfe_path_for(k: int) -> str:
+    return os.path.join(HERE, {2: "oracle_mfe_workload2_300nt.npz", 3: "oracle_mfe_workload3_900nt.npz"}[k])
+
+
+def write_mfe(k: int) -> None:
+    prob, en = I.workload(k)
+    t0 = time.time()
+    mfe, cod, pairs = oracle.mfe(prob, en)
+    np.savez_compressed(mfe_path_for(k), mfe=np.float64(mfe), codons=cod, pairs=pairs, n=prob.n,
+                        oracle_sha256=oracle_sha256(("mfe.c",)))
+    print(f"mfe workload {k} n={prob.n} mfe={mfe!r} {time.time() - t0:.1f}s", flush=True)
+
+
+def load_mfe(k: int) -> dict:
+    z = np.load(mfe_path_for(k), allow_pickle=False)
+    return {key: z[key] for key in z.files}
+
+
 def write(k: int) -> None:
     if k == 4:
         prob, en = I.workload(4, index=BATCH_LONGEST)
@@ -120,9 +142,12 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--only", type=int, choices=[2, 3, 4])
     ap.add_argument("--freq", type=int, choices=[2, 3])
+    ap.add_argument("--mfe", type=int, choices=[2, 3])
     a = ap.parse_args()
     oracle.build(force=False)
-    if a.freq:
+    if a.mfe:
+        write_mfe(a.mfe)
+    elif a.freq:
         write_freq(a.freq)
     else:
         for k in ([a.only] if a.only else [2, 3, 4]):

@@ -1,5 +1,5 @@
 """Boundary checks that need no GPU: the C-ABI library loads and exports
-every entry point declared in include/cdz.h and include/cdz_freq.h (product)
+every entry point declared in include/cdz.h, cdz_freq.h and cdz_mfe.h (product)
 and include/cdz_debug.h (test hooks); the binding has no fallback."""
 import os
 import re
@@ -9,7 +9,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-PRODUCT_HEADERS = ("cdz.h", "cdz_freq.h")
+PRODUCT_HEADERS = ("cdz.h", "cdz_freq.h", "cdz_mfe.h")
 
 
 def _declared(header=None):
