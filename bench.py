@@ -72,6 +72,46 @@ def algorithmic_bytes_out(d: np.ndarray, w: int) -> float:
     return tot * w
 
 
+FP64_ALU_PEAK_TOPS = 78.6 / 2  # FP64 vector adds or minima per second (TOP/s): half the FMA flop rate
+
+
+def algorithmic_ops_mfe(d: np.ndarray) -> float:
+    """(min, +) operations of the MFE diagonal kernel, summed over all cells
+    (each add and each minimum counted once): for every cell (i, j) with
+    j - i >= 4, each bulge window (run, edge, inner pair: two adds and a
+    minimum per inner slot pair, one add for the loop energy) and interior
+    window (per slot c of l+1: an add and a minimum per slot of k-1, then an
+    add and a minimum; one add for the energy) at every outer slot pair
+    (a, dd), and the split (two adds and a minimum per (s, s2, t, t2) over
+    u = i+5..j-4).  The O(1) terms of the pair and branch blocks are left out."""
+    n = len(d)
+    dz = np.concatenate([d, [0]])
+    # per u: d_{u-1} d_u, prefix-summed
+    du = np.concatenate([[0], d[:-1] * d[1:]])  # du[u] = d[u-1] d[u] for u >= 1
+    Pu = np.concatenate([[0], np.cumsum(du)])   # Pu[x] = sum_{u < x} du[u]
+    tot = 0.0
+    for dl in range(4, n):
+        i = np.arange(0, n - dl)
+        j = i + dl
+        outer = d[i + 1] * d[j - 1]
+        for l1 in range(0, 31):
+            for l2 in range(0, 31 - l1):
+                if (l1 == 0 and l2 == 0) or l1 + l2 > dl - 6:
+                    continue
+                k, l = i + 1 + l1, j - 1 - l2
+                if l2 == 0:
+                    per = dz[k - 1] * dz[k] * 3 + 1
+                elif l1 == 0:
+                    per = dz[l] * dz[l + 1] * 3 + 1
+                else:
+                    per = dz[l + 1] * (dz[k - 1] * 2 + 2) + 1
+                tot += float(np.sum(outer * per))
+        if dl >= 9:
+            K = Pu[j - 3] - Pu[i + 5]  # u = i+5..j-4
+            tot += float(np.sum(d[i] * d[j] * K * 3))
+    return tot
+
+
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cdz_out_diag_float_900nt_traffic.md")
 
 
@@ -193,6 +233,8 @@ def main():
     ap.add_argument("--extra", action="store_true",
                     help="also time, once each, the 256-protein batch and the 3900-nt "
                          "instance (FP32 and FP64) and report them under extra_workloads")
+    ap.add_argument("--no-mfe", dest="mfe", action="store_false",
+                    help="skip timing the minimum free energy and its traceback on the same protein")
     ap.add_argument("--no-freq", dest="freq", action="store_false",
                     help="skip timing frequency matching (Section S4e) on the same protein")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -295,6 +337,21 @@ def main():
                 "errors": [float(e) for e in ferr]}
         print(f"# frequency matching {len(ferr)} evaluations {fms:.1f} ms", file=sys.stderr, flush=True)
 
+    # minimum free energy with argmin traceback (Section 4d), FP64, same protein
+    mfe = None
+    if args.mfe:
+        B.cdz_mfe(h64, prob)  # warm-up
+        v_mfe, _, _ = B.cdz_mfe(h64, prob)
+        tm = B.cdz_last_timings(h64)
+        ops = algorithmic_ops_mfe(d)
+        ach = ops / (tm[0] / 1e3) / 1e12
+        mfe = {"mfe_kT": v_mfe, "dtype": "f64", "ms_forward": tm[0], "ms_traceback": tm[2],
+               "roofline": {"kernel": "mfe_diag", "bound": "alu", "achieved": ach,
+                            "peak": FP64_ALU_PEAK_TOPS, "unit": "TOP/s (FP64 add or min)",
+                            "frac": ach / FP64_ALU_PEAK_TOPS, "ops": ops,
+                            "note": "ops / forward time (fills, runs and exterior included)"}}
+        print(f"# mfe {v_mfe:.4f} kT forward {tm[0]:.1f} ms traceback {tm[2]:.1f} ms", file=sys.stderr, flush=True)
+
     res = {
         "metric": "DP cells/s + ms per forward+outside at 900 nt, FP32-scaled vs FP64, one GPU",
         "value": value, "unit": "DP cells/s", "n_gpus": 1, "steps": args.steps,
@@ -312,6 +369,8 @@ def main():
     }
     if freq is not None:
         res["frequency_matching"] = freq
+    if mfe is not None:
+        res["mfe"] = mfe
     if args.extra:
         res["extra_workloads"] = extra_workloads(B, I)
     if not args.no_cpu:
