@@ -86,6 +86,36 @@ __device__ __forceinline__ bool window_of(int w, int dl, int &l1, int &l2) {
   return l1 + l2 <= MAXW && (l1 | l2) != 0 && l1 + l2 <= dl - 6;
 }
 
+// interior windows (l1, l2 >= 1, l1 + l2 <= 30) in enumeration order
+struct WinTab {
+  unsigned char l1[435], l2[435];
+};
+constexpr WinTab make_wintab() {
+  WinTab t{};
+  int m = 0;
+  for (int a = 1; a <= MAXW - 1; a++)
+    for (int b = 1; a + b <= MAXW; b++) {
+      t.l1[m] = (unsigned char)a;
+      t.l2[m] = (unsigned char)b;
+      m++;
+    }
+  return t;
+}
+__constant__ WinTab kWin = make_wintab();
+constexpr int NIW = 435;  // interior windows
+constexpr int CH = 32;    // interior windows staged per round
+
+// dynamic LDS of mfe_diag (doubles): runs of both window sides, the bulges'
+// inner pairs and edges, a chunk of interior inner pairs, then the window
+// minima per thread group and the small blocks of the cell
+struct MfeLds {
+  static constexpr int UL = 0, UR = UL + MAXW * 36, QL = UR + MAXW * 36, QR = QL + MAXW * 36, EL = QR + MAXW * 36,
+                       ER = EL + MAXW * 36, DI = ER + MAXW * 36, W = DI + CH * 36, G = W + 7 * 3 * 36,
+                       QB = G + 3 * 36, Q1P = QB + 36, SP = Q1P + 36, SM = SP + 6 * 36, MMT = SM + 10 * 36,
+                       END = MMT + 96 + 36;
+  static constexpr size_t bytes = (size_t)END * sizeof(double);
+};
+
 // per window, at outer slots (a of i+1, dd of j-1): the minimum over the
 // parts' inner slots, plus the loop energy; no outer edges, no outer mismatch
 __device__ double window_value(const MfeDev &D, int i, int j, int l1, int l2, int a, int dd, const double *ul,
@@ -149,10 +179,22 @@ __global__ __launch_bounds__(64) void mfe_init_runs(MfeDev D) {
 
 // cell (i, i + dl), dl >= 1
 __global__ __launch_bounds__(MT) void mfe_diag(MfeDev D, int dl) {
-  __shared__ double sUL[MAXW][36], sUR[MAXW][36];  // U[i+1][i+l1], U[j-l2][j-1], l = 1..30
-  __shared__ double sW[7][3][36];                  // window minima per thread group
-  __shared__ double sG[3][36], sQb[36], sQ1p[36];
-  __shared__ double sSp[MT / 64][36];
+  extern __shared__ __align__(16) double lds[];
+  double(*sUL)[36] = reinterpret_cast<double(*)[36]>(lds + MfeLds::UL);  // U[i+1][i+l], l = 1..30
+  double(*sUR)[36] = reinterpret_cast<double(*)[36]>(lds + MfeLds::UR);  // U[j-l][j-1]
+  double(*sQL)[36] = reinterpret_cast<double(*)[36]>(lds + MfeLds::QL);  // Qb[i+1+l][j-1] (left bulge l)
+  double(*sQR)[36] = reinterpret_cast<double(*)[36]>(lds + MfeLds::QR);  // Qb[i+1][j-1-l] (right bulge l)
+  double(*sEL)[36] = reinterpret_cast<double(*)[36]>(lds + MfeLds::EL);  // e_{i+l}
+  double(*sER)[36] = reinterpret_cast<double(*)[36]>(lds + MfeLds::ER);  // e_{j-1-l}
+  double(*sDI)[36] = reinterpret_cast<double(*)[36]>(lds + MfeLds::DI);  // DI of a chunk of interior windows
+  double(*sW)[3][36] = reinterpret_cast<double(*)[3][36]>(lds + MfeLds::W);
+  double(*sG)[36] = reinterpret_cast<double(*)[36]>(lds + MfeLds::G);
+  double *sQb = lds + MfeLds::QB, *sQ1p = lds + MfeLds::Q1P;
+  double(*sSp)[36] = reinterpret_cast<double(*)[36]>(lds + MfeLds::SP);  // split minima per wavefront
+  // the cell's small blocks: 0 U[i+1][j-1], 1 e_i, 2 e_{j-1}, 3 Qb[i+1][j-1], 4 QmX[i+1][j-1], 5 e_{i-1},
+  // 6 e_j, 7 Qm1[i][j-1], 8 Qm1p[i+1][j]; then the mismatch and stack tables
+  double(*sB)[36] = reinterpret_cast<double(*)[36]>(lds + MfeLds::SM);
+  double *sMM = lds + MfeLds::MMT, *sST = sMM + 96;
   const int n = D.n, i = blockIdx.x, j = i + dl, tid = threadIdx.x;
   if (j >= n) return;
   // unpaired run [i..j]
@@ -171,27 +213,84 @@ __global__ __launch_bounds__(MT) void mfe_diag(MfeDev D, int dl) {
     const int r = q / 36, x = q % 36, l = r + 1;
     sUL[r][x] = i + l <= n - 1 ? cblk(D.U, n, i + 1, i + l)[x] : INFINITY;
     sUR[r][x] = j - l >= 0 ? cblk(D.U, n, j - l, j - 1)[x] : INFINITY;
+    sQL[r][x] = i + 1 + l <= j - 1 ? cblk(D.Qb, n, i + 1 + l, j - 1)[x] : INFINITY;
+    sQR[r][x] = j - 1 - l >= i + 1 ? cblk(D.Qb, n, i + 1, j - 1 - l)[x] : INFINITY;
+    sEL[r][x] = i + l <= n - 2 ? D.e[(size_t)(i + l) * 36 + x] : INFINITY;
+    sER[r][x] = j - 1 - l >= 0 ? D.e[(size_t)(j - 1 - l) * 36 + x] : INFINITY;
+  }
+  for (int q = tid; q < 9 * 36 + 96 + 36; q += MT) {
+    const int r = q / 36, x = q % 36;
+    double val = INFINITY;
+    if (q >= 9 * 36) {
+      const int z = q - 9 * 36;
+      val = z < 96 ? D.mm[z] : D.stack[z - 96];
+      sMM[z] = val;
+      continue;
+    }
+    switch (r) {
+      case 0: val = cblk(D.U, n, i + 1, j - 1)[x]; break;
+      case 1: val = D.e[(size_t)i * 36 + x]; break;
+      case 2: val = D.e[(size_t)(j - 1) * 36 + x]; break;
+      case 3: val = cblk(D.Qb, n, i + 1, j - 1)[x]; break;
+      case 4: val = cblk(D.QmX, n, i + 1, j - 1)[x]; break;
+      case 5: val = i >= 1 ? D.e[(size_t)(i - 1) * 36 + x] : INFINITY; break;
+      case 6: val = j + 1 < n ? D.e[(size_t)j * 36 + x] : INFINITY; break;
+      case 7: val = cblk(D.Qm1, n, i, j - 1)[x]; break;
+      case 8: val = cblk(D.Qm1p, n, i + 1, j)[x]; break;
+    }
+    sB[r][x] = val;
   }
   __syncthreads();
-  {
-    const int q = tid % 36, g = tid / 36, a = q / 6, dd = q % 6;
-    double mL = INFINITY, mR = INFINITY, mI = INFINITY;
-    if (g < 7 && a < D.d[i + 1] && dd < D.d[j - 1]) {
-      for (int w = g; w < 31 * 31; w += 7) {
-        int l1, l2;
-        if (!window_of(w, dl, l1, l2)) continue;
-        const double *ul = l1 > 0 ? sUL[l1 - 1] : nullptr, *ur = l2 > 0 ? sUR[l2 - 1] : nullptr;
-        const double val = window_value(D, i, j, l1, l2, a, dd, ul, ur);
-        if (l2 == 0) mL = fmin(mL, val);
-        else if (l1 == 0) mR = fmin(mR, val);
-        else mI = fmin(mI, val);
+  const int q = tid % 36, g = tid / 36, a = q / 6, dd = q % 6;
+  const bool act = g < 7 && a < D.d[i + 1] && dd < D.d[j - 1];
+  double mL = INFINITY, mR = INFINITY, mI = INFINITY;
+  if (act) {
+    // bulges: the same sums as window_value, from the staged blocks
+    for (int l = 1 + g; l <= MAXW && l <= dl - 6; l += 7) {
+      const int k = i + 1 + l, r = l - 1;
+      double best = INFINITY;
+      for (int b = 0; b < D.d[k - 1]; b++)
+        for (int x = 0; x < D.d[k]; x++) best = fmin(best, sUL[r][a * 6 + b] + sEL[r][b * 6 + x] + sQL[r][x * 6 + dd]);
+      mL = fmin(mL, D.bulge[l] + best);
+      const int lr = j - 1 - l;
+      best = INFINITY;
+      for (int y = 0; y < D.d[lr]; y++)
+        for (int c = 0; c < D.d[lr + 1]; c++) best = fmin(best, sQR[r][a * 6 + y] + sER[r][y * 6 + c] + sUR[r][c * 6 + dd]);
+      mR = fmin(mR, D.bulge[l] + best);
+    }
+  }
+  // interior windows, CH at a time: stage their DI blocks, then reduce
+  for (int c0 = 0; c0 < NIW; c0 += CH) {
+    __syncthreads();
+    for (int z = tid; z < CH * 36; z += MT) {
+      const int m = c0 + z / 36, x = z % 36;
+      double val = INFINITY;
+      if (m < NIW) {
+        const int l1 = kWin.l1[m], l2 = kWin.l2[m];
+        if (l1 + l2 <= dl - 6) val = cblk(D.DI, n, i + 1 + l1, j - 1 - l2)[x];
       }
+      sDI[z / 36][x] = val;
     }
-    if (g < 7) {
-      sW[g][0][q] = mL;
-      sW[g][1][q] = mR;
-      sW[g][2][q] = mI;
-    }
+    __syncthreads();
+    if (act)
+      for (int mm = g; mm < CH && c0 + mm < NIW; mm += 7) {
+        const int m = c0 + mm, l1 = kWin.l1[m], l2 = kWin.l2[m];
+        if (l1 + l2 > dl - 6) continue;
+        const int k = i + 1 + l1, l = j - 1 - l2;
+        const double *ul = sUL[l1 - 1], *ur = sUR[l2 - 1], *di = sDI[mm];
+        double best = INFINITY;
+        for (int c = 0; c < D.d[l + 1]; c++) {
+          double T = INFINITY;
+          for (int b = 0; b < D.d[k - 1]; b++) T = fmin(T, ul[a * 6 + b] + di[b * 6 + c]);
+          best = fmin(best, T + ur[c * 6 + dd]);
+        }
+        mI = fmin(mI, D.interior[l1 + l2] + best);
+      }
+  }
+  if (g < 7) {
+    sW[g][0][q] = mL;
+    sW[g][1][q] = mR;
+    sW[g][2][q] = mI;
   }
   __syncthreads();
   if (tid < 3 * 36) {
@@ -201,29 +300,42 @@ __global__ __launch_bounds__(MT) void mfe_diag(MfeDev D, int dl) {
     sG[k][q] = m;
   }
   __syncthreads();
-  // ---- the pair (i, j)
+  // ---- the pair (i, j), from the staged blocks (the same sums as hairpin_term,
+  // stack_term, outer_term and ml_term)
+  const int di = D.d[i], dj = D.d[j], d1 = D.d[i + 1], dm = D.d[j - 1];
   if (tid < 36) {
     const int s = tid / 6, s2 = tid % 6;
     double qb = INFINITY;
-    const int t = s < D.d[i] && s2 < D.d[j] ? bpair(NT(D, i, s), NT(D, j, s2)) : -1;
+    const int t = s < di && s2 < dj ? bpair(NT(D, i, s), NT(D, j, s2)) : -1;
     if (t >= 0) {
+      int n1[6], nm[6];
+      for (int a = 0; a < 6; a++) {
+        n1[a] = a < d1 ? NT(D, i + 1, a) : 0;
+        nm[a] = a < dm ? NT(D, j - 1, a) : 0;
+      }
+      const double *eI = sB[1], *eJ = sB[2], *u = sB[0], *qin = sB[3], *qx = sB[4];
       double h = INFINITY;
-      for (int a = 0; a < D.d[i + 1]; a++)
-        for (int b = 0; b < D.d[j - 1]; b++) h = fmin(h, hairpin_term(D, i, j, s, s2, t, a, b));
+      for (int a = 0; a < d1; a++)
+        for (int b = 0; b < dm; b++)
+          h = fmin(h, eI[s * 6 + a] + u[a * 6 + b] + eJ[b * 6 + s2] + sMM[(n1[a] * 4 + nm[b]) * 6 + t]);
       double acc = fmin(INFINITY, D.hp[j - i - 1] + h);
       if ((j - 1) - (i + 1) >= 4)
-        for (int x = 0; x < D.d[i + 1]; x++)
-          for (int y = 0; y < D.d[j - 1]; y++) acc = fmin(acc, stack_term(D, i, j, s, s2, t, x, y));
-      for (int a = 0; a < D.d[i + 1]; a++)
-        for (int dd = 0; dd < D.d[j - 1]; dd++) {
+        for (int x = 0; x < d1; x++)
+          for (int y = 0; y < dm; y++) {
+            const double qq = qin[x * 6 + y];
+            if (qq == INFINITY) continue;
+            const int t2 = bpair(n1[x], nm[y]);
+            acc = fmin(acc, eI[s * 6 + x] + qq + eJ[y * 6 + s2] + sST[t * 6 + t2]);
+          }
+      for (int a = 0; a < d1; a++)
+        for (int dd = 0; dd < dm; dd++) {
           const int q = a * 6 + dd;
-          acc = fmin(acc, outer_term(D, i, j, s, s2, a, dd,
-                                     fmin(fmin(sG[0][q], sG[1][q]),
-                                          sG[2][q] + MM(D, NT(D, i + 1, a), NT(D, j - 1, dd), t))));
+          acc = fmin(acc, eI[s * 6 + a] + eJ[dd * 6 + s2] +
+                              fmin(fmin(sG[0][q], sG[1][q]), sG[2][q] + sMM[(n1[a] * 4 + nm[dd]) * 6 + t]));
         }
       double mlv = INFINITY;
-      for (int x = 0; x < D.d[i + 1]; x++)
-        for (int y = 0; y < D.d[j - 1]; y++) mlv = fmin(mlv, ml_term(D, i, j, s, s2, x, y));
+      for (int x = 0; x < d1; x++)
+        for (int y = 0; y < dm; y++) mlv = fmin(mlv, eI[s * 6 + x] + qx[x * 6 + y] + eJ[y * 6 + s2]);
       acc = fmin(acc, D.ml_ab + mlv);
       qb = D.v[i * 6 + s] + D.v[j * 6 + s2] + acc;
       blk(D.Qb, n, i, j)[tid] = qb;
@@ -233,34 +345,41 @@ __global__ __launch_bounds__(MT) void mfe_diag(MfeDev D, int dl) {
   __syncthreads();
   if (tid < 36) {
     const int a = tid / 6, b = tid % 6;
-    // DI[i][j](b', c'): (i, j) as the inner pair of an interior loop
+    // DI[i][j](b', c'): (i, j) as the inner pair of an interior loop (di_term)
     if (i >= 1 && j + 1 < n && a < D.d[i - 1] && b < D.d[j + 1]) {
+      const double *eL = sB[5], *eR = sB[6];
+      const int nl = NT(D, i - 1, a), nr = NT(D, j + 1, b);
       double best = INFINITY;
-      for (int x = 0; x < D.d[i]; x++)
-        for (int y = 0; y < D.d[j]; y++) best = fmin(best, di_term(D, sQb, i, j, a, b, x, y));
+      for (int x = 0; x < di; x++)
+        for (int y = 0; y < dj; y++) {
+          const double qq = sQb[x * 6 + y];
+          if (qq == INFINITY) continue;
+          const int t2 = bpair(NT(D, j, y), NT(D, i, x));
+          best = fmin(best, eL[a * 6 + x] + qq + eR[y * 6 + b] + sMM[(nr * 4 + nl) * 6 + t2]);
+        }
       blk(D.DI, n, i, j)[tid] = best;
     }
     // one branch with an unpaired tail, then with an unpaired prefix
     const int s = a, s2 = b;
     double q1p = INFINITY;
-    if (s < D.d[i] && s2 < D.d[j]) {
-      const double *q1l = cblk(D.Qm1, n, i, j - 1), *q1pr = cblk(D.Qm1p, n, i + 1, j);
+    if (s < di && s2 < dj) {
+      const double *q1l = sB[7], *q1pr = sB[8], *eI = sB[1], *eJ = sB[2];
       double tail = INFINITY;
-      for (int t = 0; t < D.d[j - 1]; t++) tail = fmin(tail, q1l[s * 6 + t] + E(D, j - 1, t, s2));
+      for (int t = 0; t < dm; t++) tail = fmin(tail, q1l[s * 6 + t] + eJ[t * 6 + s2]);
       const double q1 = fmin(sQb[tid] + D.ml_b, tail + D.v[j * 6 + s2] + D.ml_c);
       blk(D.Qm1, n, i, j)[tid] = q1;
       double pre = INFINITY;
-      for (int t = 0; t < D.d[i + 1]; t++) pre = fmin(pre, E(D, i, s, t) + q1pr[t * 6 + s2]);
+      for (int t = 0; t < d1; t++) pre = fmin(pre, eI[s * 6 + t] + q1pr[t * 6 + s2]);
       q1p = fmin(q1, D.v[i * 6 + s] + D.ml_c + pre);
       blk(D.Qm1p, n, i, j)[tid] = q1p;
     }
     sQ1p[tid] = q1p;
   }
-  // ---- two or more branches: the split over u (threads over u)
+  // ---- two or more branches: the split over u = i+5..j-4, threads over u
+  // (each thread all 36 outputs for its u), then minima across the workgroup
   double part[36];
 #pragma unroll
   for (int q = 0; q < 36; q++) part[q] = INFINITY;
-  const int di = D.d[i], dj = D.d[j];
   for (int u = i + 5 + tid; u <= j - 4; u += MT) {
     const double *qm = cblk(D.Qm, n, i, u - 1), *q1 = cblk(D.Qm1, n, u, j);
     const int du1 = D.d[u - 1], du = D.d[u];
@@ -785,7 +904,9 @@ extern "C" cdz_status cdz_mfe(cdz_handle *h, const cdz_problem *prob, double *mf
   HIPCHK(h, hipEventRecord(h->ev[4], sm));
   for (int k = 0; k < 7; k++) hipLaunchKernelGGL(mfe_fill, dim3(2048), dim3(256), 0, sm, *arr[k], cell);
   hipLaunchKernelGGL(mfe_init_runs, dim3(n), dim3(64), 0, sm, D);
-  for (int dl = 1; dl < n; dl++) hipLaunchKernelGGL(mfe_diag, dim3(n - dl), dim3(MT), 0, sm, D, dl);
+  HIPCHK(h, hipFuncSetAttribute((const void *)mfe_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)MfeLds::bytes));
+  for (int dl = 1; dl < n; dl++) hipLaunchKernelGGL(mfe_diag, dim3(n - dl), dim3(MT), MfeLds::bytes, sm, D, dl);
   hipLaunchKernelGGL(mfe_exterior, dim3(1), dim3(MT), 0, sm, D);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->ev[5], sm));
