@@ -456,19 +456,31 @@ __global__ __launch_bounds__(MT) void mfe_exterior(MfeDev D) {
   if (tid < 6) D.Z5[tid] = tid < D.d[0] ? D.v[tid] : INFINITY;
   __syncthreads();
   for (int j = 1; j < n; j++) {
-    // k pairs j, k = 1..j-4: minima over (k, slot of k-1, slot of k) per slot t of j
+    // k pairs j, k = 1..j-4: minima over (k, slot of k-1, slot of k) per slot
+    // t of j; a thread takes whole k, all its operands loaded at once (entries
+    // beyond a position's slots are +inf and drop out of the minima)
     double part[6];
 #pragma unroll
     for (int t = 0; t < 6; t++) part[t] = INFINITY;
-    const int nk = j >= 5 ? (j - 4) * 36 : 0, dj = D.d[j];
-    for (int q = tid; q < nk; q += MT) {
-      const int k = 1 + q / 36, s = (q % 36) / 6, x = q % 6;
-      if (s >= D.d[k - 1] || x >= D.d[k]) continue;
-      const double ze = D.Z5[(k - 1) * 6 + s] + E(D, k - 1, s, x);
-      const double *qb = cblk(D.Qb, n, k, j);
+    const int dj = D.d[j];
+    for (int k = 1 + tid; k <= j - 4; k += MT) {
+      const double *z = D.Z5 + (k - 1) * 6, *eb = D.e + (size_t)(k - 1) * 36, *qb = cblk(D.Qb, n, k, j);
+      double zz[6], ee[36], qq[36];
 #pragma unroll
-      for (int t = 0; t < 6; t++)
-        if (t < dj) part[t] = fmin(part[t], ze + qb[x * 6 + t]);
+      for (int q = 0; q < 6; q++) zz[q] = z[q];
+#pragma unroll
+      for (int q = 0; q < 36; q++) {
+        ee[q] = eb[q];
+        qq[q] = qb[q];
+      }
+#pragma unroll
+      for (int s = 0; s < 6; s++)
+#pragma unroll
+        for (int x = 0; x < 6; x++) {
+          const double ze = zz[s] + ee[s * 6 + x];
+#pragma unroll
+          for (int t = 0; t < 6; t++) part[t] = fmin(part[t], ze + qq[x * 6 + t]);
+        }
     }
 #pragma unroll
     for (int t = 0; t < 6; t++)
@@ -556,13 +568,24 @@ __global__ __launch_bounds__(MT) void mfe_traceback(MfeDev D) {
       if (tid == 0) D.slot[jj] = t;
       if (jj == 0) continue;
       Pick p{INFINITY, 0x7fffffff};
-      const int nk = jj >= 5 ? (jj - 4) * 36 : 0;
-      for (int q = tid; q < nk; q += MT) {
-        const int k = 1 + q / 36, sp = (q % 36) / 6, x = q % 6;
-        if (sp >= D.d[k - 1] || x >= D.d[k]) continue;
-        const double val = D.Z5[(k - 1) * 6 + sp] + E(D, k - 1, sp, x) + cblk(D.Qb, n, k, jj)[x * 6 + t];
-        const int idx = 1000 + (k * 6 + sp) * 6 + x;
-        if (better(val, idx, p)) p = Pick{val, idx};
+      for (int k = 1 + tid; k <= jj - 4; k += MT) {  // whole k per thread, (s, x) ascending
+        const double *z = D.Z5 + (k - 1) * 6, *eb = D.e + (size_t)(k - 1) * 36, *qb = cblk(D.Qb, n, k, jj);
+        double zz[6], ee[36], qq[6];
+#pragma unroll
+        for (int q = 0; q < 6; q++) {
+          zz[q] = z[q];
+          qq[q] = qb[q * 6 + t];
+        }
+#pragma unroll
+        for (int q = 0; q < 36; q++) ee[q] = eb[q];
+#pragma unroll
+        for (int sp = 0; sp < 6; sp++)
+#pragma unroll
+          for (int x = 0; x < 6; x++) {
+            const double val = zz[sp] + ee[sp * 6 + x] + qq[x];
+            const int idx = 1000 + (k * 6 + sp) * 6 + x;
+            if (better(val, idx, p)) p = Pick{val, idx};
+          }
       }
       if (tid == 0) {
         for (int sp = 0; sp < D.d[jj - 1]; sp++) {
