@@ -87,6 +87,11 @@ def _configure(L):
             L.orc_mfe.argtypes = [ctypes.c_int, ctypes.c_char_p, d, d, d, d, ctypes.POINTER(ctypes.c_uint8),
                                   ctypes.POINTER(ctypes.c_int32)]
             L.orc_mfe.restype = ctypes.c_int
+        if hasattr(L, "orc_subopt"):
+            L.orc_subopt.argtypes = [ctypes.c_int, ctypes.c_char_p, d, d, d, ctypes.c_double, ctypes.c_int, d, d,
+                                     ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int)]
+            L.orc_subopt.restype = ctypes.c_int
         if hasattr(L, "orc_philox_u01"):
             L.orc_philox_u01.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
             L.orc_philox_u01.restype = ctypes.c_double
@@ -169,6 +174,26 @@ def mfe(prob, energy, traceback: bool = True):
     if rc != 0:
         raise RuntimeError(f"oracle orc_mfe failed ({rc})")
     return float(out[0]), cod, pairs
+
+
+def subopt(prob, energy, gap: float, max_states: int = 10000):
+    """Every state within gap (kT) of the MFE (mfe.c, depth-first order):
+    (mfe, energies [k], codons [k, m] uint8, pairs [k, n] int32, complete),
+    complete False when more than max_states states exist."""
+    m, aa, t1, t2 = _prep(prob)
+    en = energy.packed()
+    out = np.zeros(1)
+    energies = np.zeros(max(max_states, 1))
+    cod = np.zeros((max(max_states, 1), m), np.uint8)
+    pairs = np.zeros((max(max_states, 1), 3 * m), np.int32)
+    cnt = ctypes.c_int(0)
+    rc = lib().orc_subopt(m, aa, _dp(t1), _dp(t2), _dp(en), float(gap), int(max_states), _dp(out), _dp(energies),
+                          cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                          pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(cnt))
+    if rc < 0:
+        raise RuntimeError(f"oracle orc_subopt failed ({rc})")
+    k = cnt.value
+    return float(out[0]), energies[:k].copy(), cod[:k].copy(), pairs[:k].copy(), rc == 0
 
 
 def philox_u01(seed: int, sample_id: int, draw: int) -> float:

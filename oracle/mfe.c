@@ -619,3 +619,385 @@ int orc_mfe(int m, const char *aa, const double *theta1, const double *theta2, c
   mfe_free(&F);
   return rc;
 }
+
+/* ---- suboptimal enumeration (SI S4d) ------------------------------------
+ * Every state (codon assignment, structure) whose energy is at most
+ * MFE + gap, by depth-first search over the same decisions as the argmin
+ * traceback.  A partial state is a stack of pending fragments and a bound:
+ * the energy decided so far plus the minimum (the DP value) of every pending
+ * fragment.  Expanding a fragment f by an alternative a of value V(a) (its
+ * own energy plus the DP values of the fragments it leaves) gives the bound
+ * (bound - value(f)) + V(a); alternatives whose bound exceeds the threshold
+ * MFE + gap + 1e-9 max(1, |MFE|) are dropped, the others are tried in the
+ * traceback's order.  Inside a pair decision the alternatives are refined
+ * level by level (loop type, window, outer slots, inner slots) and a level is
+ * skipped when its minimum already exceeds the threshold.  A complete state's
+ * energy is its final bound.  States come out in depth-first order. */
+
+typedef struct {
+  double V;
+  int nsub;
+  Frag sub[3];
+  int nas;
+  int as[3][3]; /* assignments: position, slot, partner (-1 unpaired) */
+} Alt;
+
+/* One level per expanded fragment.  Levels below share the pending stack and
+ * may take fragments off it below flen0; each puts its own back when it is
+ * left, so the stack a level sees is restored before its next alternative. */
+typedef struct {
+  Frag f;
+  int flen0;    /* pending stack length after f was taken off */
+  double b0;    /* bound before f was expanded */
+  size_t a0, na, next;
+} Level;
+
+typedef struct {
+  const Mfe *F;
+  double thr;
+  Alt *alts;
+  size_t nalts, capalts;
+  Level *lv;
+  int nlv, caplv;
+  Frag *pend;
+  int npend, cappend;
+  int *slot, *pt;
+} Sub;
+
+static double frag_value(const Mfe *F, const Frag *f) {
+  const int n = F->n;
+  switch (f->kind) {
+    case K_EXT: return F->Z5[f->i * MS + f->s];
+    case K_PAIR: return C(F->Qb, f->i, f->j)[f->s * 6 + f->s2];
+    case K_RUN: return C(F->U, f->i, f->j)[f->s * 6 + f->s2];
+    case K_QM1: return C(F->Qm1, f->i, f->j)[f->s * 6 + f->s2];
+    case K_QM1P: return C(F->Qm1p, f->i, f->j)[f->s * 6 + f->s2];
+    case K_QM: return C(F->Qm, f->i, f->j)[f->s * 6 + f->s2];
+    default: return C(F->QmX, f->i, f->j)[f->s * 6 + f->s2]; /* K_QM + 10 */
+  }
+}
+
+static int alt_push(Sub *S, double V, double base) {
+  if (!(base + V <= S->thr)) return 0;
+  if (S->nalts == S->capalts) {
+    S->capalts = S->capalts ? 2 * S->capalts : 1024;
+    S->alts = realloc(S->alts, S->capalts * sizeof(Alt));
+    if (!S->alts) return -1;
+  }
+  Alt *a = &S->alts[S->nalts++];
+  a->V = V;
+  a->nsub = 0;
+  a->nas = 0;
+  return 1;
+}
+static Alt *alt_last(Sub *S) { return &S->alts[S->nalts - 1]; }
+static void alt_sub(Alt *a, int kind, int i, int j, int s, int s2) { a->sub[a->nsub++] = (Frag){kind, i, j, s, s2}; }
+static void alt_as(Alt *a, int p, int s, int partner) {
+  a->as[a->nas][0] = p;
+  a->as[a->nas][1] = s;
+  a->as[a->nas][2] = partner;
+  a->nas++;
+}
+
+/* alternatives of fragment f, given base = bound - value(f) */
+static int sub_alternatives(Sub *S, const Frag *f, double base) {
+  const Mfe *F = S->F;
+  const int i = f->i, j = f->j, s = f->s, s2 = f->s2;
+  int r;
+  if (f->kind == K_EXT) {
+    const int jj = i, t = s;
+    if (jj == 0) {
+      if ((r = alt_push(S, F->Z5[t], base)) < 0) return r;
+      if (r) alt_as(alt_last(S), 0, t, -1);
+      return 0;
+    }
+    for (int sp = 0; sp < F->d[jj - 1]; sp++) {
+      if ((r = alt_push(S, (F->Z5[(jj - 1) * MS + sp] + F->e[jj - 1][sp][t]) + F->v[jj][t], base)) < 0) return r;
+      if (r) {
+        alt_as(alt_last(S), jj, t, -1);
+        alt_sub(alt_last(S), K_EXT, jj - 1, 0, sp, 0);
+      }
+    }
+    if (jj >= 4)
+      for (int x = 0; x < F->d[0]; x++) {
+        if ((r = alt_push(S, C(F->Qb, 0, jj)[x * 6 + t], base)) < 0) return r;
+        if (r) alt_sub(alt_last(S), K_PAIR, 0, jj, x, t);
+      }
+    for (int k = 1; k <= jj - 4; k++)
+      for (int sp = 0; sp < F->d[k - 1]; sp++)
+        for (int x = 0; x < F->d[k]; x++) {
+          if ((r = alt_push(S, ext_pair_term(F, k, jj, sp, x, t), base)) < 0) return r;
+          if (r) {
+            alt_sub(alt_last(S), K_EXT, k - 1, 0, sp, 0);
+            alt_sub(alt_last(S), K_PAIR, k, jj, x, t);
+          }
+        }
+    return 0;
+  }
+  if (f->kind == K_RUN) {
+    if (i == j) {
+      if ((r = alt_push(S, C(F->U, i, i)[s * 6 + s2], base)) < 0) return r;
+      if (r) alt_as(alt_last(S), i, s2, -1);
+      return 0;
+    }
+    for (int c = 0; c < F->d[j - 1]; c++) {
+      if ((r = alt_push(S, (C(F->U, i, j - 1)[s * 6 + c] + F->e[j - 1][c][s2]) + F->v[j][s2], base)) < 0) return r;
+      if (r) {
+        alt_as(alt_last(S), j, s2, -1);
+        alt_sub(alt_last(S), K_RUN, i, j - 1, s, c);
+      }
+    }
+    return 0;
+  }
+  if (f->kind == K_QM1) {
+    if ((r = alt_push(S, C(F->Qb, i, j)[s * 6 + s2] + F->E->ml_b, base)) < 0) return r;
+    if (r) alt_sub(alt_last(S), K_PAIR, i, j, s, s2);
+    for (int t = 0; t < F->d[j - 1]; t++) {
+      if ((r = alt_push(S, (C(F->Qm1, i, j - 1)[s * 6 + t] + F->e[j - 1][t][s2]) + F->v[j][s2] + F->E->ml_c,
+                        base)) < 0)
+        return r;
+      if (r) {
+        alt_as(alt_last(S), j, s2, -1);
+        alt_sub(alt_last(S), K_QM1, i, j - 1, s, t);
+      }
+    }
+    return 0;
+  }
+  if (f->kind == K_QM1P) {
+    if ((r = alt_push(S, C(F->Qm1, i, j)[s * 6 + s2], base)) < 0) return r;
+    if (r) alt_sub(alt_last(S), K_QM1, i, j, s, s2);
+    for (int t = 0; t < F->d[i + 1]; t++) {
+      if ((r = alt_push(S, F->v[i][s] + F->E->ml_c + (F->e[i][s][t] + C(F->Qm1p, i + 1, j)[t * 6 + s2]), base)) < 0)
+        return r;
+      if (r) {
+        alt_as(alt_last(S), i, s, -1);
+        alt_sub(alt_last(S), K_QM1P, i + 1, j, t, s2);
+      }
+    }
+    return 0;
+  }
+  if (f->kind == K_QM || f->kind == K_QM + 10) {
+    for (int u = i + 5; u <= j - 4; u++)
+      for (int t = 0; t < F->d[u - 1]; t++)
+        for (int t2 = 0; t2 < F->d[u]; t2++) {
+          if ((r = alt_push(S, split_term(F, i, j, u, s, s2, t, t2), base)) < 0) return r;
+          if (r) {
+            alt_sub(alt_last(S), K_QM, i, u - 1, s, t);
+            alt_sub(alt_last(S), K_QM1, u, j, t2, s2);
+          }
+        }
+    if (f->kind == K_QM) {
+      if ((r = alt_push(S, C(F->Qm1p, i, j)[s * 6 + s2], base)) < 0) return r;
+      if (r) alt_sub(alt_last(S), K_QM1P, i, j, s, s2);
+    }
+    return 0;
+  }
+  /* K_PAIR: value(f) = Qb = (v_i + v_j) + acc; each alternative's value is
+   * (v_i + v_j) + its term of acc */
+  const double vv = F->v[i][s] + F->v[j][s2];
+  const int t = bpair(F->nt[i][s], F->nt[j][s2]);
+#define PAIR_AS(a)               \
+  do {                           \
+    alt_as((a), i, s, j);        \
+    alt_as((a), j, s2, i);       \
+  } while (0)
+  {
+    const double bh = e_hairpin(F, j - i - 1);
+    for (int a = 0; a < F->d[i + 1]; a++)
+      for (int b = 0; b < F->d[j - 1]; b++) {
+        if ((r = alt_push(S, vv + (bh + hairpin_term(F, i, j, s, s2, t, a, b)), base)) < 0) return r;
+        if (r) {
+          PAIR_AS(alt_last(S));
+          alt_sub(alt_last(S), K_RUN, i + 1, j - 1, a, b);
+        }
+      }
+  }
+  if ((j - 1) - (i + 1) >= 4)
+    for (int x = 0; x < F->d[i + 1]; x++)
+      for (int y = 0; y < F->d[j - 1]; y++) {
+        if ((r = alt_push(S, vv + stack_term(F, i, j, s, s2, t, x, y), base)) < 0) return r;
+        if (r) {
+          PAIR_AS(alt_last(S));
+          alt_sub(alt_last(S), K_PAIR, i + 1, j - 1, x, y);
+        }
+      }
+  double W[6][6];
+  for (int l1 = 0; l1 <= MAXL; l1++)
+    for (int l2 = 0; l1 + l2 <= MAXL; l2++) {
+      if (!window_ok(i, j, l1, l2)) continue;
+      const int k = i + 1 + l1, l = j - 1 - l2;
+      window_block(F, i, j, l1, l2, W);
+      for (int a = 0; a < F->d[i + 1]; a++)
+        for (int dd = 0; dd < F->d[j - 1]; dd++) {
+          const int inter = l1 > 0 && l2 > 0;
+          const double mm = inter ? outer_mm(F, i, j, t, a, dd) : 0.0;
+          const double wv = inter ? W[a][dd] + mm : W[a][dd];
+          if (!(base + (vv + outer_term(F, i, j, s, s2, a, dd, wv)) <= S->thr)) continue;
+          if (l2 == 0) {
+            for (int b = 0; b < F->d[k - 1]; b++)
+              for (int x = 0; x < F->d[k]; x++) {
+                const double w = F->E->bulge[l1] + lbulge_term(F, i, k, j, a, b, x, dd);
+                if ((r = alt_push(S, vv + outer_term(F, i, j, s, s2, a, dd, w), base)) < 0) return r;
+                if (r) {
+                  PAIR_AS(alt_last(S));
+                  alt_sub(alt_last(S), K_RUN, i + 1, k - 1, a, b);
+                  alt_sub(alt_last(S), K_PAIR, k, j - 1, x, dd);
+                }
+              }
+          } else if (l1 == 0) {
+            for (int y = 0; y < F->d[l]; y++)
+              for (int c = 0; c < F->d[l + 1]; c++) {
+                const double w = F->E->bulge[l2] + rbulge_term(F, i, l, j, a, y, c, dd);
+                if ((r = alt_push(S, vv + outer_term(F, i, j, s, s2, a, dd, w), base)) < 0) return r;
+                if (r) {
+                  PAIR_AS(alt_last(S));
+                  alt_sub(alt_last(S), K_PAIR, i + 1, l, a, y);
+                  alt_sub(alt_last(S), K_RUN, l + 1, j - 1, c, dd);
+                }
+              }
+          } else {
+            for (int c = 0; c < F->d[l + 1]; c++)
+              for (int b = 0; b < F->d[k - 1]; b++) {
+                const double di = C(F->DI, k, l)[b * 6 + c];
+                const double wbc = F->E->interior[l1 + l2] +
+                                   ((C(F->U, i + 1, k - 1)[a * 6 + b] + di) + C(F->U, l + 1, j - 1)[c * 6 + dd]);
+                if (!(base + (vv + outer_term(F, i, j, s, s2, a, dd, wbc + mm)) <= S->thr)) continue;
+                for (int x = 0; x < F->d[k]; x++)
+                  for (int y = 0; y < F->d[l]; y++) {
+                    const double dt = di_term(F, k, l, b, c, x, y);
+                    const double w = F->E->interior[l1 + l2] +
+                                     ((C(F->U, i + 1, k - 1)[a * 6 + b] + dt) + C(F->U, l + 1, j - 1)[c * 6 + dd]);
+                    if ((r = alt_push(S, vv + outer_term(F, i, j, s, s2, a, dd, w + mm), base)) < 0) return r;
+                    if (r) {
+                      PAIR_AS(alt_last(S));
+                      alt_sub(alt_last(S), K_RUN, i + 1, k - 1, a, b);
+                      alt_sub(alt_last(S), K_PAIR, k, l, x, y);
+                      alt_sub(alt_last(S), K_RUN, l + 1, j - 1, c, dd);
+                    }
+                  }
+              }
+          }
+        }
+    }
+  for (int x = 0; x < F->d[i + 1]; x++)
+    for (int y = 0; y < F->d[j - 1]; y++) {
+      if ((r = alt_push(S, vv + (F->E->ml_a + F->E->ml_b + ml_term(F, i, j, s, s2, x, y)), base)) < 0) return r;
+      if (r) {
+        PAIR_AS(alt_last(S));
+        alt_sub(alt_last(S), K_QM + 10, i + 1, j - 1, x, y);
+      }
+    }
+#undef PAIR_AS
+  return 0;
+}
+
+/* All states within gap >= 0 of the MFE (at most max_states): energies[k],
+ * codons[k][m], pairs[k][n] in depth-first order; *count states.  Returns 0,
+ * 1 if more than max_states states exist (the first max_states are given),
+ * < 0 on bad input (a negative or NaN gap among them: the single argmin is
+ * orc_mfe's), allocation failure or an inconsistent state. */
+int orc_subopt(int m, const char *aa, const double *theta1, const double *theta2, const double *energy, double gap,
+               int max_states, double *mfe, double *energies, uint8_t *codons, int32_t *pairs, int *count) {
+  if (m < 1 || !aa || !energy || !mfe || !count || max_states < 0 || !(gap >= 0)) return -1;
+  Mfe F;
+  int rc = mfe_build(&F, m, aa, theta1, theta2, (const MfeEnergy *)energy);
+  *count = 0;
+  if (rc != 0) {
+    mfe_free(&F);
+    return rc;
+  }
+  *mfe = forward(&F);
+  const int n = F.n;
+  Sub S;
+  memset(&S, 0, sizeof(S));
+  S.F = &F;
+  S.thr = *mfe + gap + 1e-9 * fmax(1.0, fabs(*mfe));
+  S.caplv = 4 * n + 16;
+  S.cappend = 4 * n + 16;
+  S.lv = malloc(S.caplv * sizeof(Level));
+  S.pend = malloc(S.cappend * sizeof(Frag));
+  S.slot = malloc(n * sizeof(int));
+  S.pt = malloc(n * sizeof(int));
+  if (!S.lv || !S.pend || !S.slot || !S.pt) rc = -1;
+  /* root level: the slot of the last position */
+  if (rc == 0) {
+    S.lv[0].f = (Frag){-1, 0, 0, 0, 0};
+    S.lv[0].flen0 = 0;
+    S.lv[0].b0 = 0.0;
+    S.lv[0].a0 = 0;
+    for (int t = 0; t < F.d[n - 1]; t++) {
+      const int r = alt_push(&S, F.Z5[(n - 1) * MS + t], 0.0);
+      if (r < 0) {
+        rc = -1;
+        break;
+      }
+      if (r) alt_sub(alt_last(&S), K_EXT, n - 1, 0, t, 0);
+    }
+    S.lv[0].na = S.nalts;
+    S.lv[0].next = 0;
+    S.nlv = 1;
+  }
+  while (rc == 0 && S.nlv > 0) {
+    Level *L = &S.lv[S.nlv - 1];
+    if (L->next == L->na) { /* backtrack: put the expanded fragment back where it was taken from */
+#ifndef PLANT_SUBOPT_NO_RESTORE
+      if (L->f.kind >= 0) S.pend[L->flen0] = L->f;
+#endif
+      S.nalts = L->a0;
+      S.nlv--;
+      continue;
+    }
+    const Alt *a = &S.alts[L->a0 + L->next++];
+    S.npend = L->flen0;
+    for (int q = 0; q < a->nas; q++) {
+      S.slot[a->as[q][0]] = a->as[q][1];
+      S.pt[a->as[q][0]] = a->as[q][2];
+    }
+    for (int q = 0; q < a->nsub; q++) S.pend[S.npend++] = a->sub[q];
+    const double bound = L->f.kind < 0 ? a->V : (L->b0 - frag_value(&F, &L->f)) + a->V;
+    if (S.npend == 0) { /* complete */
+      if (*count >= max_states) {
+        rc = 1;
+        break;
+      }
+      if (energies) energies[*count] = bound;
+      int ok = 1;
+      for (int aa2 = 0; aa2 < m; aa2++) {
+        const int sl = S.slot[3 * aa2];
+        if (sl < 0 || S.slot[3 * aa2 + 1] != sl || S.slot[3 * aa2 + 2] != sl) ok = 0;
+        if (codons) codons[(size_t)*count * m + aa2] = (uint8_t)sl;
+      }
+      if (pairs)
+        for (int p = 0; p < n; p++) pairs[(size_t)*count * n + p] = S.pt[p];
+      if (!ok) {
+        rc = -3;
+        break;
+      }
+      (*count)++;
+      continue;
+    }
+    if (S.nlv == S.caplv) {
+      rc = -1;
+      break;
+    }
+    const Frag f = S.pend[--S.npend];
+    Level *N = &S.lv[S.nlv++];
+    N->f = f;
+    N->flen0 = S.npend;
+    N->b0 = bound;
+    N->a0 = S.nalts;
+    if (sub_alternatives(&S, &f, bound - frag_value(&F, &f)) < 0) {
+      rc = -1;
+      break;
+    }
+    N->na = S.nalts - N->a0;
+    N->next = 0;
+  }
+  free(S.alts);
+  free(S.lv);
+  free(S.pend);
+  free(S.slot);
+  free(S.pt);
+  mfe_free(&F);
+  return rc;
+}
