@@ -20,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["oracle.c", "seqmcc.c", "mfe.c"]
+_SOURCES = ["oracle.c", "seqmcc.c", "mfe.c", "tensor.c"]
 _lib = None
 
 
@@ -87,6 +87,11 @@ def _configure(L):
             L.orc_mfe.argtypes = [ctypes.c_int, ctypes.c_char_p, d, d, d, d, ctypes.POINTER(ctypes.c_uint8),
                                   ctypes.POINTER(ctypes.c_int32)]
             L.orc_mfe.restype = ctypes.c_int
+        if hasattr(L, "orc_tensor_logz"):
+            L.orc_tensor_logz.argtypes = [ctypes.c_int, ctypes.c_char_p, d, ctypes.c_int, ctypes.c_int, d, d, d, d, d]
+            L.orc_tensor_logz.restype = ctypes.c_int
+            L.orc_tensor_dims.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
+            L.orc_tensor_dims.restype = ctypes.c_int
         if hasattr(L, "orc_subopt"):
             L.orc_subopt.argtypes = [ctypes.c_int, ctypes.c_char_p, d, d, d, ctypes.c_double, ctypes.c_int, d, d,
                                      ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
@@ -194,6 +199,31 @@ def subopt(prob, energy, gap: float, max_states: int = 10000):
         raise RuntimeError(f"oracle orc_subopt failed ({rc})")
     k = cnt.value
     return float(out[0]), energies[:k].copy(), cod[:k].copy(), pairs[:k].copy(), rc == 0
+
+
+def tensor_logz(prob, model):
+    """log Z of the tensor-based model summed over the protein's codon
+    sequences (tensor.c) and the prefix values log Z(first a residues),
+    a = 1..m.  Codon bonuses theta1 (if any) weight the middle cores."""
+    m, aa, t1, _ = _prep(prob)
+    V = np.ascontiguousarray(model.V, np.float64)
+    B = np.ascontiguousarray(model.B, np.float64)
+    S = np.ascontiguousarray(model.S, np.float64)
+    out = np.zeros(1)
+    pre = np.zeros(m)
+    rc = lib().orc_tensor_logz(m, aa, _dp(t1), model.gamma, model.xi, _dp(V), _dp(B), _dp(S), _dp(out), _dp(pre))
+    if rc != 0:
+        raise RuntimeError(f"oracle orc_tensor_logz failed ({rc})")
+    return float(out[0]), pre
+
+
+def tensor_dims(prot: str) -> np.ndarray:
+    """Bond dimensions Sigma_p, p = 0..n, of the single-codon tensor train."""
+    sig = np.zeros(3 * len(prot) + 1, np.int32)
+    rc = lib().orc_tensor_dims(len(prot), prot.encode(), sig.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if rc != 0:
+        raise RuntimeError(f"oracle orc_tensor_dims failed ({rc})")
+    return sig
 
 
 def philox_u01(seed: int, sample_id: int, draw: int) -> float:

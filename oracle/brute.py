@@ -156,3 +156,107 @@ def count_structures(prob, code: dict) -> int:
         seq = "".join(code[ch][s] for ch, s in zip(prob.prot, c))
         tot += len(structures(seq))
     return tot
+
+
+# ---- tensor-based model (SI S2b, eq. general-model) ------------------------
+
+def all_structures(n: int):
+    """All non-crossing structures on n positions whose hairpins have at least
+    3 unpaired bases, whatever the bases (the tensor model's B decides which
+    pairs carry weight)."""
+
+    @lru_cache(maxsize=None)
+    def rec(i, j):
+        if i > j:
+            return [()]
+        out = list(rec(i + 1, j))
+        for k in range(i + 4, j + 1):
+            for inner in rec(i + 1, k - 1):
+                for rest in rec(k + 1, j):
+                    out.append(((i, k),) + inner + rest)
+        return out
+
+    return rec(0, n - 1)
+
+
+def tensor_structure_weight(seq: str, pairs, model) -> float:
+    """Boltzmann weight of one (sequence, structure) under a tensor model:
+    the sum over one rank index per pair of the product over loops of
+    Tr[S x (matrices along the loop)] -- V for an unpaired base, B_{x,y} for
+    a base x paired to the loop's next base y.  The exterior loop is read
+    from the 5' end; a loop closed by (i, j) from the closing pair's 3' side,
+    B_{seq[j], seq[i]}, then the bases i+1 .. j-1 at that level."""
+    b = [BASES.index(ch) for ch in seq]
+    n = len(seq)
+    pt = [-1] * n
+    for i, j in pairs:
+        pt[i], pt[j] = j, i
+    g = model.gamma
+    total = 0.0
+    for rhos in itertools.product(range(model.xi), repeat=len(pairs)):
+        rho = {}
+        for (i, j), r in zip(pairs, rhos):
+            rho[i] = rho[j] = r
+
+        def walk(start, end, M):
+            p = start
+            while p < end:
+                q = pt[p]
+                if q < 0:
+                    M = M @ model.V[b[p]]
+                    p += 1
+                else:
+                    M = M @ model.B[rho[p], b[p], b[q]]
+                    p = q + 1
+            return M
+
+        w = np.trace(model.S @ walk(0, n, np.eye(g)))
+        for i, j in pairs:
+            w *= np.trace(model.S @ walk(i + 1, j, model.B[rho[i], b[j], b[i]]))
+        total += w
+    return float(total)
+
+
+def tensor_brute_logz(prob, model, code: dict) -> float:
+    """log of sum over codon assignments c and all structures of
+    exp(sum_a theta1[a][c_a]) * tensor_structure_weight."""
+    prot = prob.prot
+    n = 3 * len(prot)
+    sts = all_structures(n)
+    Z = 0.0
+    for c in itertools.product(*[range(len(code[ch])) for ch in prot]):
+        seq = "".join(code[ch][s] for ch, s in zip(prot, c))
+        lw = sum(prob.theta1[a][s] for a, s in enumerate(c)) if prob.theta1 is not None else 0.0
+        Z += math.exp(lw) * sum(tensor_structure_weight(seq, st, model) for st in sts)
+    return math.log(Z)
+
+
+def tensor_fixed_logz(seq: str, model) -> float:
+    """log Z of one fixed sequence by the recursion of SI S2c (eq.
+    complicated-pf): Q[i][j+1] = Q[i][j] V_j + sum_k sum_rho Q[i][k]
+    B_{k,j} Tr[S B_{j,k} Q[k+1][j]], Q[i][i] = I, Z = Tr[S Q[0][n]]; each
+    Q[i][j] carries a scale so that long sequences stay in range."""
+    b = [BASES.index(ch) for ch in seq]
+    n = len(seq)
+    g = model.gamma
+    Q = {}
+    L = {}  # log scale of Q[i][j]
+    for i in range(n + 1):
+        Q[i, i] = np.eye(g)
+        L[i, i] = 0.0
+    for d in range(1, n + 1):
+        for i in range(0, n - d + 1):
+            j1 = i + d  # Q[i][j1] with j = j1 - 1 the new last base
+            j = j1 - 1
+            terms = [(Q[i, j] @ model.V[b[j]], L[i, j])]
+            for k in range(i, j - 3):
+                for r in range(model.xi):
+                    t = np.trace(model.S @ model.B[r, b[j], b[k]] @ Q[k + 1, j])
+                    if t != 0.0:
+                        terms.append((Q[i, k] @ model.B[r, b[k], b[j]] * t, L[i, k] + L[k + 1, j]))
+            mx = max(l for _, l in terms)
+            M = sum(x * math.exp(l - mx) for x, l in terms)
+            s = np.abs(M).max()
+            Q[i, j1] = M / s
+            L[i, j1] = mx + math.log(s)
+    return math.log(np.trace(model.S @ Q[0, n])) + L[0, n]

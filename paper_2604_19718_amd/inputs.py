@@ -17,9 +17,13 @@ available, so amino acids are uniform and the energy tables synthetic):
   log w ~ N(0, 0.3^2) per ordered pair of sense-codon types, both expanded to
   the protein's positions (the soft constraints of Section 3a).
 
+Tensor-model workload (Sections 3b-3c; the paper's trained (nu=3, mu=3,
+xi=1) parameters are not available, so V, B and S are synthetic with the same
+shapes: gamma = nu * mu = 9, rank xi = 1; see :func:`tensor_model`).
+
 Random streams: SplitMix64 sub-streams keyed by (master seed, tag, index) with
 tags 0 protein, 1 energy tables, 2 codon weights, 3 codon-pair weights,
-4 sampler key, 5 finite-difference index choice.  Uniforms take the top 53
+4 sampler key, 5 finite-difference index choice, 6 tensor-model parameters.  Uniforms take the top 53
 bits; Gaussians use Box-Muller.
 """
 from __future__ import annotations
@@ -38,7 +42,7 @@ AA_DEGENERACY = dict(zip(AA_ORDER, [4, 6, 2, 2, 2, 2, 2, 4, 2, 3,
                                     6, 2, 1, 2, 4, 6, 4, 1, 2, 4]))
 MAX_SLOTS = 6
 
-TAG_PROTEIN, TAG_ENERGY, TAG_THETA1, TAG_THETA2, TAG_SAMPLER, TAG_FD = range(6)
+TAG_PROTEIN, TAG_ENERGY, TAG_THETA1, TAG_THETA2, TAG_SAMPLER, TAG_FD, TAG_TENSOR = range(7)
 _MASK64 = (1 << 64) - 1
 
 
@@ -279,3 +283,56 @@ def workload(k: int, m: Optional[int] = None, index: int = 0):
 
 def sampler_seed(k: int, index: int = 0) -> int:
     return Stream(config_seed(k), TAG_SAMPLER, index).u64()
+
+
+# ---- tensor-based structure model (synthetic parameters) -------------------
+
+PAIRABLE = {(0, 3): 1.0, (3, 0): 1.0, (1, 2): 1.6, (2, 1): 1.6, (2, 3): 0.6, (3, 2): 0.6}
+
+
+@dataclass
+class TensorModel:
+    """Parameters of a tensor-based secondary-structure model: V[4][g][g]
+    per unpaired base, B[xi][4][4][g][g] per side of a pair (first index the
+    base of that side, second its partner; zero for bases that do not pair),
+    S[g][g] for the weighted trace.  Bases A=0, C=1, G=2, U=3."""
+    V: np.ndarray
+    B: np.ndarray
+    S: np.ndarray
+
+    @property
+    def gamma(self) -> int:
+        return self.V.shape[1]
+
+    @property
+    def xi(self) -> int:
+        return self.B.shape[0]
+
+
+def tensor_model(seed: int, gamma: int = 9, xi: int = 1, pair: float = 1.0, index: int = 0) -> TensorModel:
+    """Synthetic non-negative parameters with the trained model's shapes.
+
+    V_b: entries U(0.2, 1), each row then divided by its sum (row-stochastic,
+    so spectral radius 1, the normalisation the paper applies to its V).
+    B_{x,y}: for the six pairing combinations (AU, UA, CG, GC, GU, UG),
+    entries U(0, 1) * strength(x, y) * pair / gamma (GC 1.6, AU 1.0, GU 0.6);
+    zero otherwise.  S: entries U(0.5, 1.5) / gamma."""
+    r = Stream(seed, TAG_TENSOR, index)
+    V = np.array([[[r.uniform_ab(0.2, 1.0) for _ in range(gamma)] for _ in range(gamma)] for _ in range(4)])
+    V /= V.sum(axis=2, keepdims=True)
+    B = np.zeros((xi, 4, 4, gamma, gamma))
+    for rho in range(xi):
+        for (x, y), st in PAIRABLE.items():
+            B[rho, x, y] = np.array([[r.uniform() * st * pair / gamma for _ in range(gamma)]
+                                     for _ in range(gamma)])
+    S = np.array([[r.uniform_ab(0.5, 1.5) / gamma for _ in range(gamma)] for _ in range(gamma)])
+    return TensorModel(V, B, S)
+
+
+def tensor_workload(k: int, m: Optional[int] = None):
+    """(Problem, TensorModel) for the tensor-model workload k: the protein and
+    codon bonuses of workload k (no codon-pair weights: the single-codon
+    tensor train carries per-codon bonuses only) and synthetic (9, 1) model
+    parameters."""
+    prob, _ = workload(k, m)
+    return Problem(prob.prot, prob.theta1, None), tensor_model(config_seed(k))
