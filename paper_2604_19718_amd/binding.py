@@ -24,7 +24,7 @@ EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_s
            "cdz_forward_dev", "cdz_backward_dev", "cdz_last_timings", "cdz_reset",
            "cdz_set_profiling", "cdz_kernel_timings", "cdz_status_string", "cdz_last_error",
            "cdz_batch", "cdz_partition_batch", "cdz_marginals_batch", "cdz_sample_batch",
-           "cdz_workspace_bytes", "cdz_match_frequencies", "cdz_mfe"]
+           "cdz_workspace_bytes", "cdz_match_frequencies", "cdz_mfe", "cdz_tensor_logz"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -37,6 +37,10 @@ class cdz_problem(ctypes.Structure):
 class cdz_options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("mem_budget_bytes", ctypes.c_size_t),
                 ("hip_stream", ctypes.c_void_p)]
+
+
+class cdz_tensor_model(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_int32), ("xi", ctypes.c_int32), ("V", _dp), ("B", _dp), ("S", _dp)]
 
 
 class CdzError(RuntimeError):
@@ -92,6 +96,8 @@ def lib():
                                   ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_workspace_bytes": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+            "cdz_tensor_logz": ([vp, ctypes.POINTER(cdz_tensor_model), ctypes.POINTER(cdz_problem), _dp, _dp],
+                                ctypes.c_int),
             "cdz_mfe": ([vp, ctypes.POINTER(cdz_problem), _dp, ctypes.POINTER(ctypes.c_uint8),
                          ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_match_frequencies": ([vp, ctypes.POINTER(cdz_problem), _dp, ctypes.c_double, ctypes.c_int32,
@@ -209,6 +215,21 @@ def cdz_mfe(h: Handle, prob, traceback: bool = True):
                           None if cod is None else cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                           None if pairs is None else pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return float(out[0]), cod, pairs
+
+
+def cdz_tensor_logz(h: Handle, model, prob):
+    """log Z of prob (theta2 must be None) under a tensor-based model
+    (``inputs.TensorModel``) in the handle's precision, and the prefix values
+    log Z(first a residues), a = 1..n_aa."""
+    p = _Prob(prob)
+    V = np.ascontiguousarray(model.V, np.float64)
+    Bm = np.ascontiguousarray(model.B, np.float64)
+    S = np.ascontiguousarray(model.S, np.float64)
+    md = cdz_tensor_model(model.gamma, model.xi, _arr(V), _arr(Bm), _arr(S))
+    out = np.zeros(1)
+    pre = np.zeros(len(prob.prot))
+    h.check(lib().cdz_tensor_logz(h.ptr, ctypes.byref(md), ctypes.byref(p.c), _arr(out), _arr(pre)))
+    return float(out[0]), pre
 
 
 def cdz_match_frequencies(h: Handle, prob, f_target: np.ndarray, r_tol: float = 0.002,

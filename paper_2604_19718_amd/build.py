@@ -7,7 +7,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["cdz_host.hip", "cdz_fwd.hip", "cdz_out.hip", "cdz_sample.hip", "cdz_batch.hip", "cdz_freq.hip", "cdz_mfe.hip"]
+SOURCES = ["cdz_host.hip", "cdz_fwd.hip", "cdz_out.hip", "cdz_sample.hip", "cdz_batch.hip", "cdz_freq.hip", "cdz_mfe.hip",
+           "cdz_tensor.hip"]
 OUT = os.path.join(HERE, "libcdz.so")
 
 

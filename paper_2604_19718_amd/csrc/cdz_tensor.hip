@@ -1,0 +1,585 @@
+// cdz_tensor.hip -- sequence-summed free energy of a tensor-based structure
+// model (Sections 3b-3c; SI S2b-S2c; Alg. fast-pf of SI S4a).
+//
+// Q is one dense row-major matrix of the flattened blocks: position p owns
+// gamma * Sigma_p consecutive rows and columns starting at off[p] (sigma-major,
+// then zeta).  Upper blocks Q_{i,j} (i < j) hold the scaled open-loop sums,
+// diagonal blocks the identity, and row block j, left of the diagonal, the
+// fold of column j transposed: row off[j] + c, column off[k] + r holds entry
+// (r, c) of E_{k,j}, the element spanning [k, j) (the lower triangle of
+// eq. dp-short).  Both operands of the propagation are therefore read along
+// contiguous rows.
+//
+// Column j takes two launches:
+//   tz_fold (j)  one wave per k < j: finishes column j-1 (sums the split-K
+//                partials, divides by the column's power of two, writes the
+//                blocks back) and builds E_{k,j} -- a pair (k, j-1) folds the
+//                block Q_{k+1,j-1} it has just finished (eq. design-fold), the
+//                last element is the unpaired base, elements of two or three
+//                bases are zero.
+//   tz_prop (j)  Y_{[0:j), j} = sum_k Q_{[0:j), k} E_{k,j} on the matrix cores
+//                (v_mfma 16x16x4, FP32 or FP64): one wave per 64 rows and
+//                2048-wide chunk of k, triangular (a tile starts at the first
+//                block its rows own), partial sums to a side buffer.
+// Scaling: column j is divided by h_{j-1} = 2^e, e the binary exponent of the
+// largest entry of its row-0 block, so the prefix block stays in [1, 2);
+// E_{k,j} of a pair is divided by h_k (the inner block carries the factors of
+// k+1 .. j-2 only).  log Z = log Tr[S Q_{0,n}] + ln 2 * sum of the exponents,
+// and at each codon boundary j = 3a the same gives log Z of the first a
+// residues.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cdz_internal.h"
+#include "cdz_tensor.h"
+
+hipError_t prof_reserve(cdz_handle *h, int launches);
+
+namespace {
+
+constexpr int TZ_KC = 2048;  // k chunk of one propagation wave
+constexpr int TZ_TM = 64;    // rows of one propagation tile (four 16-row MFMA tiles)
+constexpr int TZ_WMAX = 64;  // widest column block gamma * Sigma (gamma <= 16, Sigma <= 4)
+constexpr int TZ_FT = 256;   // fold workgroup: four waves, one k each
+
+template <typename T>
+struct Mf;
+template <>
+struct Mf<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  typedef float ld_t __attribute__((ext_vector_type(4)));
+  static constexpr int VEC = 4;  // k values per 16-byte load
+  static __device__ inline acc_t mac(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of output element v of a lane in k-group q
+  static __device__ inline int drow(int q, int v) { return 4 * q + v; }
+};
+template <>
+struct Mf<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  typedef double ld_t __attribute__((ext_vector_type(2)));
+  static constexpr int VEC = 2;
+  static __device__ inline acc_t mac(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int drow(int q, int v) { return q + 4 * v; }
+};
+
+template <typename T>
+struct TzDev {
+  int n, g, xi;
+  int ld;                       // row stride of Q (elements)
+  int prow;                     // rows of one chunk of P
+  const int *sig;               // [n+1] train dimensions
+  const int *off;               // [n+1] first row/column of each position
+  const int *rstart;            // [rows] off[] of the position owning the row
+  const int *tile_kmin;         // [tiles] rstart of the tile's first row
+  const int *chunk_tiles;       // [chunks] number of tiles whose first chunk is <= c
+  const unsigned char *bmask;   // [n] bit phi set if core p is nonzero for base phi
+  const T *tc;                  // [n][4][4][4] train cores: p, base, sigma_a, sigma_b
+  const T *V;                   // [4][g][g]
+  const T *B;                   // [xi][4][4][g][g]
+  const T *SB;                  // [xi][4][4][g][g]: S B[rho][x][y]
+  const T *S;                   // [g][g]
+  unsigned pairmask;            // bit 4x+y: B[rho][x][y] nonzero for some rho
+  T *Q;                         // [rows][ld]
+  T *P;                         // [chunks][prow][TZ_WMAX] split-K partial sums
+  int *colexp;                  // [n+1] exponent of each column's factor
+  double *ptr;                  // [m] Tr[S Q_{0,3a}] (scaled) at codon boundaries
+};
+
+// ---- propagation: Y_{[0:j), j} on the matrix cores ----------------------
+// Lane layout of v_mfma_*_16x16x4 (one block): A row i, k-group q at lane
+// i + 16q; B column c, k-group q at lane c + 16q; output column c at lane
+// c + 16q, element v holding row 4q + v (f32) or q + 4v (f64).  Each lane loads VEC consecutive k of its row
+// (16 bytes) and feeds them to VEC successive instructions, so instruction s
+// multiplies k = k0 + VEC q + s for q = 0..3 -- the same set for A and B.
+template <typename T>
+__global__ __launch_bounds__(64) void tz_prop(TzDev<T> D, int j, int ntiles, int nchunks) {
+  using M = Mf<T>;
+  constexpr int VEC = M::VEC, KS = 4 * VEC;
+  int b = blockIdx.x, c = 0;
+  for (; c < nchunks - 1; c++) {  // chunk-major: chunk c holds the tiles that reach it
+    const int cnt = min(ntiles, D.chunk_tiles[c]);
+    if (b < cnt) break;
+    b -= cnt;
+  }
+  const int t = b;
+  const int R = D.off[j], w = D.g * D.sig[j], ntn = (w + 15) >> 4;
+  const int lane = threadIdx.x, li = lane & 15, q = lane >> 4;
+  const int r0 = t * TZ_TM;
+  const int kb = max(c * TZ_KC, D.tile_kmin[t]) & ~(KS - 1);
+  const int ke = min((c + 1) * TZ_KC, R);
+  int kst[4];
+  const T *arow[4];
+#pragma unroll
+  for (int m = 0; m < 4; m++) {
+    const int row = r0 + 16 * m + li;
+    kst[m] = row < R ? D.rstart[row] : INT_MAX;
+    arow[m] = D.Q + (size_t)row * D.ld;
+  }
+  const T *brow[4];
+  bool bok[4];
+#pragma unroll
+  for (int nn = 0; nn < 4; nn++) {
+    const int col = 16 * nn + li;
+    bok[nn] = col < w;
+    brow[nn] = D.Q + (size_t)(R + col) * D.ld;
+  }
+  typename M::acc_t acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; m++)
+#pragma unroll
+    for (int nn = 0; nn < 4; nn++) acc[m][nn] = typename M::acc_t{0, 0, 0, 0};
+  for (int k0 = kb; k0 < ke; k0 += KS) {
+    const int kk = k0 + VEC * q;
+    typename M::ld_t a[4], bv[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) a[m] = *reinterpret_cast<const typename M::ld_t *>(arow[m] + kk);
+#pragma unroll
+    for (int nn = 0; nn < 4; nn++)
+      if (nn < ntn) bv[nn] = *reinterpret_cast<const typename M::ld_t *>(brow[nn] + kk);
+#pragma unroll
+    for (int s = 0; s < VEC; s++) {
+      const int k = kk + s;
+      T av[4], bs[4];
+#pragma unroll
+      for (int m = 0; m < 4; m++) av[m] = (k >= kst[m] && k < ke) ? a[m][s] : T(0);
+#pragma unroll
+      for (int nn = 0; nn < 4; nn++) bs[nn] = (nn < ntn && bok[nn] && k < ke) ? bv[nn][s] : T(0);
+#pragma unroll
+      for (int nn = 0; nn < 4; nn++)
+        if (nn < ntn)
+#pragma unroll
+          for (int m = 0; m < 4; m++) acc[m][nn] = M::mac(av[m], bs[nn], acc[m][nn]);
+    }
+  }
+  T *P = D.P + (size_t)c * D.prow * TZ_WMAX;
+#pragma unroll
+  for (int m = 0; m < 4; m++)
+#pragma unroll
+    for (int nn = 0; nn < 4; nn++)
+      if (nn < ntn)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int row = r0 + 16 * m + M::drow(q, v), col = 16 * nn + li;
+          if (row < R && col < w) P[(size_t)row * TZ_WMAX + col] = acc[m][nn][v];
+        }
+}
+
+// sum of the partials of row r, column col of the last propagated column
+template <typename T>
+__device__ inline T col_sum(const TzDev<T> &D, int r, int col, int nchunks) {
+  const int cf = D.tile_kmin[r / TZ_TM] / TZ_KC;
+  T y = T(0);
+  for (int c = cf; c < nchunks; c++) y += D.P[((size_t)c * D.prow + r) * TZ_WMAX + col];
+  return y;
+}
+
+__device__ inline int exp_of(double x) {
+  int e;
+  (void)frexp(x, &e);
+  return e - 1;  // x in [2^(e-1), 2^e)
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+template <typename T>
+__device__ inline T wave_max(T v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// exponent of column jc's factor: binary exponent of the largest entry of its
+// row-0 block (rows 0..g-1), summed from the partials (one wave)
+template <typename T>
+__device__ inline int column_exponent(const TzDev<T> &D, int jc, int nchunks) {
+  const int w = D.g * D.sig[jc];
+  T mx = T(0);
+  for (int e = threadIdx.x & 63; e < D.g * w; e += 64) mx = max(mx, col_sum(D, e / w, e % w, nchunks));
+  mx = wave_max(mx);
+  return exp_of((double)mx);
+}
+
+// ---- fold: finish column j-1, build row block j --------------------------
+template <typename T>
+__global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_prev) {
+  extern __shared__ __align__(16) unsigned char tz_lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = D.g, xi = D.xi, G4 = 4 * g;
+  const int qi = blockIdx.x * 4 + wave;  // item: block row qi of column j-1, element k = qi - 1
+  T *Xs = reinterpret_cast<T *>(tz_lds) + (size_t)wave * (G4 * G4 + 2 * xi * 256);
+  T *ts = Xs + G4 * G4;  // [xi][4 phi_l][4 phi_k][4][4]
+  T *Us = ts + xi * 256; // [xi][4 phi_k][4 phi_l][4][4]
+  __shared__ int e_prev;
+  if (wave == 0) {
+    const int e = j >= 2 ? column_exponent(D, j - 1, nchunks_prev) : 0;
+    if (lane == 0) {
+      e_prev = e;
+      if (blockIdx.x == 0 && j >= 2) D.colexp[j - 1] = e;
+    }
+  }
+  __syncthreads();
+  const bool live = qi < j;
+  const int wp = g * D.sig[j - 1];  // width of column j-1
+  // 1. finish block row qi of column j-1
+  if (live && qi < j - 1) {
+    const int r0 = D.off[qi], rows = g * D.sig[qi];
+    const size_t cbase = (size_t)D.off[j - 1];
+    for (int e = lane; e < rows * wp; e += 64) {
+      const int rr = e / wp, col = e % wp;
+      const T x = ldexp(col_sum(D, r0 + rr, col, nchunks_prev), -e_prev);
+      D.Q[(size_t)(r0 + rr) * D.ld + cbase + col] = x;
+      Xs[rr * wp + col] = x;
+    }
+    if (qi == 0 && (j - 1) % 3 == 0) {  // codon boundary: Sigma = 1, a g x g block
+      T tr = T(0);
+      for (int e = lane; e < g * g; e += 64) {
+        const int x = e / g, y = e % g;
+        tr += D.S[x * g + y] * ldexp(col_sum(D, y, x, nchunks_prev), -e_prev);
+      }
+      tr = wave_sum(tr);
+      if (lane == 0) D.ptr[(j - 1) / 3 - 1] = (double)tr;
+    }
+  }
+  __syncthreads();
+  const int k = qi - 1, l = j - 1;
+  const bool pair = live && qi >= 1 && l - k >= 4;
+  const int sk = pair ? D.sig[k] : 0, sb = pair ? D.sig[k + 1] : 0, se = pair ? D.sig[l] : 0, sj = D.sig[j];
+  // 2a. t[rho][phi_l][phi_k][sigma_b][sigma_e] = Tr[S B_{phi_l, phi_k} X^{sigma_b, sigma_e}]
+  if (pair) {
+    for (int e = lane; e < xi * 256; e += 64) {
+      const int rho = e >> 8, pl = (e >> 6) & 3, pk = (e >> 4) & 3, b = (e >> 2) & 3, ee = e & 3;
+      T acc = T(0);
+      if (b < sb && ee < se && ((D.pairmask >> (4 * pk + pl)) & 1) && ((D.bmask[k] >> pk) & 1) &&
+          ((D.bmask[l] >> pl) & 1)) {
+        const T *sbm = D.SB + ((((size_t)rho * 4 + pl) * 4 + pk) * g) * g;
+        for (int x = 0; x < g; x++)
+          for (int y = 0; y < g; y++) acc += sbm[x * g + y] * Xs[(b * g + y) * wp + ee * g + x];
+      }
+      ts[e] = acc;
+    }
+  }
+  __syncthreads();
+  // 2b. U[rho][phi_k][phi_l][sigma_k][sigma_j] = (T_k t T_l)[sigma_k][sigma_j]
+  if (pair) {
+    for (int e = lane; e < xi * 256; e += 64) {
+      const int rho = e >> 8, pk = (e >> 6) & 3, pl = (e >> 4) & 3, a = (e >> 2) & 3, cc = e & 3;
+      T u = T(0);
+      if (a < sk && cc < sj)
+        for (int b = 0; b < sb; b++)
+          for (int ee = 0; ee < se; ee++)
+            u += D.tc[(((size_t)k * 4 + pk) * 4 + a) * 4 + b] * ts[(((rho * 4 + pl) * 4 + pk) * 4 + b) * 4 + ee] *
+                 D.tc[(((size_t)l * 4 + pl) * 4 + ee) * 4 + cc];
+      Us[e] = u;
+    }
+  }
+  __syncthreads();
+  // 2c. E_{k,j} = 2^-e_k sum_{rho, phi_k, phi_l} U (x) B_{phi_k, phi_l}, stored transposed
+  if (live && qi >= 1) {
+    const int rows = g * D.sig[k], wj = g * sj;
+    const size_t rbase = (size_t)D.off[j], cbase = (size_t)D.off[k];
+    const int ek = pair ? D.colexp[k + 1] : 0;
+    for (int e = lane; e < rows * wj; e += 64) {
+      const int rr = e % rows, cc = e / rows;  // consecutive lanes along the stored row
+      const int a = rr / g, za = rr % g, s2 = cc / g, zb = cc % g;
+      T f = T(0);
+      if (pair) {
+        for (int rho = 0; rho < xi; rho++)
+          for (int pk = 0; pk < 4; pk++)
+            for (int pl = 0; pl < 4; pl++)
+              if ((D.pairmask >> (4 * pk + pl)) & 1)
+                f += Us[(((rho * 4 + pk) * 4 + pl) * 4 + a) * 4 + s2] *
+                     D.B[((((size_t)rho * 4 + pk) * 4 + pl) * g + za) * g + zb];
+        f = ldexp(f, -ek);
+      }
+      D.Q[(rbase + cc) * D.ld + cbase + rr] = f;
+    }
+  }
+  // 3. the unpaired base j-1
+  if (live && qi == j - 1) {
+    const int sa = D.sig[j - 1], rows = g * sa, wj = g * sj;
+    const size_t rbase = (size_t)D.off[j], cbase = (size_t)D.off[j - 1];
+    for (int e = lane; e < rows * wj; e += 64) {
+      const int rr = e % rows, cc = e / rows;
+      const int a = rr / g, za = rr % g, s2 = cc / g, zb = cc % g;
+      T f = T(0);
+      for (int phi = 0; phi < 4; phi++)
+        f += D.tc[(((size_t)(j - 1) * 4 + phi) * 4 + a) * 4 + s2] * D.V[(phi * g + za) * g + zb];
+      D.Q[(rbase + cc) * D.ld + cbase + rr] = f;
+    }
+  }
+}
+
+// after the last column: its exponent and Tr[S Q_{0,n}] (one wave)
+template <typename T>
+__global__ __launch_bounds__(64) void tz_final(TzDev<T> D, int nchunks) {
+  const int n = D.n, g = D.g;
+  const int e = column_exponent(D, n, nchunks);
+  T tr = T(0);
+  for (int q = threadIdx.x; q < g * g; q += 64) {
+    const int x = q / g, y = q % g;
+    tr += D.S[x * g + y] * ldexp(col_sum(D, y, x, nchunks), -e);
+  }
+  tr = wave_sum(tr);
+  if (threadIdx.x == 0) {
+    D.colexp[n] = e;
+    D.ptr[n / 3 - 1] = (double)tr;
+  }
+}
+
+// Q = identity (the diagonal blocks), zero elsewhere
+template <typename T>
+__global__ void tz_init(T *Q, size_t rows, size_t ld, size_t N) {
+  const size_t tot = rows * ld;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / ld, c = e % ld;
+    Q[e] = (r == c && r < N) ? T(1) : T(0);
+  }
+}
+
+// device workspace released when the call returns (hipFree waits for the device)
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+struct TzHost {
+  int n = 0, m = 0, N = 0, rows = 0, ld = 0, tiles = 0, chunks = 0;
+  std::vector<int> sig, off, rstart, tile_kmin, chunk_tiles;
+  std::vector<unsigned char> bmask;
+  std::vector<double> tc;  // [n][4][4][4]
+};
+
+int nchunks_of(const TzHost &H, int j) { return (H.off[j] + TZ_KC - 1) / TZ_KC; }
+int ntiles_of(const TzHost &H, int j) { return (H.off[j] + TZ_TM - 1) / TZ_TM; }
+int prop_grid(const TzHost &H, int j) {
+  const int nt = ntiles_of(H, j), nc = nchunks_of(H, j);
+  int tot = 0;
+  for (int c = 0; c < nc; c++) tot += c == nc - 1 ? nt : std::min(nt, H.chunk_tiles[c]);
+  return tot;
+}
+
+template <typename T>
+cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md, double *log_z, double *prefix) {
+  const int n = H.n, m = H.m, g = md->gamma, xi = md->xi;
+  std::vector<T> V((size_t)4 * g * g), B((size_t)xi * 16 * g * g), SB(B.size()), S((size_t)g * g), tc(H.tc.size());
+  for (size_t q = 0; q < V.size(); q++) V[q] = (T)md->V[q];
+  for (size_t q = 0; q < B.size(); q++) B[q] = (T)md->B[q];
+  for (size_t q = 0; q < S.size(); q++) S[q] = (T)md->S[q];
+  for (size_t q = 0; q < tc.size(); q++) tc[q] = (T)H.tc[q];
+  unsigned pairmask = 0;
+  for (int rho = 0; rho < xi; rho++)
+    for (int xy = 0; xy < 16; xy++) {
+      const double *b = md->B + ((size_t)rho * 16 + xy) * g * g;
+      bool nz = false;
+      for (int q = 0; q < g * g; q++) nz |= b[q] != 0.0;
+      if (nz) pairmask |= 1u << xy;
+      for (int x = 0; x < g; x++)
+        for (int y = 0; y < g; y++) {
+          double acc = 0.0;
+          for (int z = 0; z < g; z++) acc += md->S[x * g + z] * b[z * g + y];
+          SB[((size_t)rho * 16 + xy) * g * g + x * g + y] = (T)acc;
+        }
+    }
+  // workspace
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t p = (at + 255) / 256 * 256;
+    at = p + bytes;
+    return p;
+  };
+  const size_t oQ = take((size_t)H.rows * H.ld * sizeof(T)),
+               oP = take((size_t)H.chunks * H.rows * TZ_WMAX * sizeof(T)), oSig = take((n + 1) * 4),
+               oOff = take((n + 1) * 4), oRs = take((size_t)H.rows * 4), oTk = take((size_t)H.tiles * 4),
+               oCt = take((size_t)H.chunks * 4), oBm = take(n), oTc = take(tc.size() * sizeof(T)),
+               oV = take(V.size() * sizeof(T)), oB = take(B.size() * sizeof(T)), oSB = take(SB.size() * sizeof(T)),
+               oS = take(S.size() * sizeof(T)), oCe = take((n + 1) * 4), oPt = take((size_t)m * 8);
+  DevBuf ws;
+  if (hipMalloc(&ws.p, at) != hipSuccess) {
+    (void)hipGetLastError();
+    ws.p = nullptr;
+    return cdz_fail(h, CDZ_ERR_NOMEM, "tensor-model workspace of " + std::to_string(at) + " bytes");
+  }
+  char *base = (char *)ws.p;
+  hipStream_t st = h->stream;
+  auto up = [&](size_t o, const void *src, size_t bytes) {
+    return hipMemcpyAsync(base + o, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  HIPCHK(h, up(oSig, H.sig.data(), (n + 1) * 4));
+  HIPCHK(h, up(oOff, H.off.data(), (n + 1) * 4));
+  HIPCHK(h, up(oRs, H.rstart.data(), (size_t)H.rows * 4));
+  HIPCHK(h, up(oTk, H.tile_kmin.data(), (size_t)H.tiles * 4));
+  HIPCHK(h, up(oCt, H.chunk_tiles.data(), (size_t)H.chunks * 4));
+  HIPCHK(h, up(oBm, H.bmask.data(), n));
+  HIPCHK(h, up(oTc, tc.data(), tc.size() * sizeof(T)));
+  HIPCHK(h, up(oV, V.data(), V.size() * sizeof(T)));
+  HIPCHK(h, up(oB, B.data(), B.size() * sizeof(T)));
+  HIPCHK(h, up(oSB, SB.data(), SB.size() * sizeof(T)));
+  HIPCHK(h, up(oS, S.data(), S.size() * sizeof(T)));
+  TzDev<T> D;
+  D.n = n;
+  D.g = g;
+  D.xi = xi;
+  D.ld = H.ld;
+  D.prow = H.rows;
+  D.sig = (const int *)(base + oSig);
+  D.off = (const int *)(base + oOff);
+  D.rstart = (const int *)(base + oRs);
+  D.tile_kmin = (const int *)(base + oTk);
+  D.chunk_tiles = (const int *)(base + oCt);
+  D.bmask = (const unsigned char *)(base + oBm);
+  D.tc = (const T *)(base + oTc);
+  D.V = (const T *)(base + oV);
+  D.B = (const T *)(base + oB);
+  D.SB = (const T *)(base + oSB);
+  D.S = (const T *)(base + oS);
+  D.pairmask = pairmask;
+  D.Q = (T *)(base + oQ);
+  D.P = (T *)(base + oP);
+  D.colexp = (int *)(base + oCe);
+  D.ptr = (double *)(base + oPt);
+  const size_t fold_lds = (size_t)4 * (16 * g * g + 2 * xi * 256) * sizeof(T);
+  if ((int)fold_lds > h->lds_max) return cdz_fail(h, CDZ_ERR_ARG, "gamma too large for the fold's LDS");
+  if (h->profiling) HIPCHK(h, prof_reserve(h, n));
+  HIPCHK(h, hipEventRecord(h->ev[0], st));
+  tz_init<T><<<2048, 256, 0, st>>>(D.Q, (size_t)H.rows, (size_t)H.ld, (size_t)H.N);
+  for (int j = 1; j <= n; j++) {
+    const int fgrid = (j + 3) / 4;
+    tz_fold<T><<<fgrid, TZ_FT, fold_lds, st>>>(D, j, j >= 2 ? nchunks_of(H, j - 1) : 0);
+    if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * (j - 1)], st));
+    tz_prop<T><<<prop_grid(H, j), 64, 0, st>>>(D, j, ntiles_of(H, j), nchunks_of(H, j));
+    if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * (j - 1) + 1], st));
+  }
+  tz_final<T><<<1, 64, 0, st>>>(D, nchunks_of(H, n));
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipEventRecord(h->ev[1], st));
+  std::vector<double> ptr(m);
+  std::vector<int> ce(n + 1);
+  HIPCHK(h, hipMemcpyAsync(ptr.data(), base + oPt, (size_t)m * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipMemcpyAsync(ce.data(), base + oCe, (n + 1) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  float ms = 0;
+  HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+  h->times[0] = ms;
+  h->times[1] = h->times[2] = 0;
+  h->times[3] = 0;
+  h->times[4] = n;
+  if (h->profiling) {
+    double tot = 0;
+    for (int j = 0; j < n; j++) {
+      float k = 0;
+      HIPCHK(h, hipEventElapsedTime(&k, h->pev[2 * j], h->pev[2 * j + 1]));
+      tot += k;
+    }
+    h->times[3] = tot / n;
+  }
+  const double L2 = 0.6931471805599453094;
+  long esum = 0;
+  for (int a = 0; a < m; a++) {
+    for (int col = 3 * a + 1; col <= 3 * a + 3; col++) esum += ce[col];
+    const double lz = std::log(ptr[a]) + L2 * (double)esum;
+    if (!(ptr[a] > 0.0) || !std::isfinite(lz))
+      return cdz_fail(h, CDZ_ERR_NUMERIC, "tensor-model prefix " + std::to_string(a) + " not finite");
+    if (prefix) prefix[a] = lz;
+    if (a == m - 1) *log_z = lz;
+  }
+  return CDZ_OK;
+}
+
+}  // namespace
+
+extern "C" cdz_status cdz_tensor_logz(cdz_handle *h, const cdz_tensor_model *md, const cdz_problem *prob,
+                                      double *log_z, double *prefix) {
+  if (!h || !md || !prob || !log_z) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
+  if (prob->theta2) return cdz_fail(h, CDZ_ERR_ARG, "the single-codon train takes no codon-pair weights");
+  const int g = md->gamma, xi = md->xi;
+  if (g < 1 || g > 16 || xi < 1 || xi > 4 || !md->V || !md->B || !md->S)
+    return cdz_fail(h, CDZ_ERR_ARG, "tensor model: gamma in 1..16, xi in 1..4, V, B, S given");
+  auto ok = [](const double *p, size_t cnt) {
+    for (size_t q = 0; q < cnt; q++)
+      if (!(p[q] >= 0.0) || !std::isfinite(p[q])) return false;
+    return true;
+  };
+  if (!ok(md->V, (size_t)4 * g * g) || !ok(md->B, (size_t)xi * 16 * g * g) || !ok(md->S, (size_t)g * g))
+    return cdz_fail(h, CDZ_ERR_NUMERIC, "tensor model entries must be finite and non-negative");
+  HostTables t;
+  cdz_status s = build_tables(h, prob->n_aa, prob->aa, prob->theta1, nullptr, t);
+  if (s != CDZ_OK) return s;
+  TzHost H;
+  H.m = t.m;
+  H.n = t.n;
+  const int n = H.n;
+  H.sig.assign(n + 1, 1);
+  H.tc.assign((size_t)n * 64, 0.0);
+  H.bmask.assign(n, 0);
+  auto TC = [&](int p, int phi, int a, int b) -> double & { return H.tc[(((size_t)p * 4 + phi) * 4 + a) * 4 + b]; };
+  // single-codon train (eq. single-tt): core 3a selects the first base,
+  // core 3a+1 the codon (first base, middle base, third base) with its bonus,
+  // core 3a+2 the third base
+  for (int a = 0; a < H.m; a++) {
+    const int p = 3 * a, d = t.d[p];
+    int first[4], third[4], nf = 0, nth = 0;
+    for (int b = 0; b < 4; b++) {
+      bool hf = false, ht = false;
+      for (int s2 = 0; s2 < d; s2++) {
+        hf |= t.nt[p * 6 + s2] == b;
+        ht |= t.nt[(p + 2) * 6 + s2] == b;
+      }
+      if (hf) first[nf++] = b;
+      if (ht) third[nth++] = b;
+    }
+    H.sig[p] = 1;
+    H.sig[p + 1] = nf;
+    H.sig[p + 2] = nth;
+    for (int x = 0; x < nf; x++) TC(p, first[x], 0, x) = 1.0;
+    for (int s2 = 0; s2 < d; s2++) {
+      const int b0 = t.nt[p * 6 + s2], b1 = t.nt[(p + 1) * 6 + s2], b2 = t.nt[(p + 2) * 6 + s2];
+      int x = 0, y = 0;
+      while (first[x] != b0) x++;
+      while (third[y] != b2) y++;
+      const double th = prob->theta1 ? prob->theta1[a * 6 + s2] : 0.0;
+      if (!std::isfinite(th)) return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite codon bonus");
+      TC(p + 1, b1, x, y) += std::exp(th);
+    }
+    for (int y = 0; y < nth; y++) TC(p + 2, third[y], y, 0) = 1.0;
+  }
+  for (int p = 0; p < n; p++)
+    for (int phi = 0; phi < 4; phi++)
+      for (int q = 0; q < 16; q++)
+        if (H.tc[((size_t)p * 4 + phi) * 16 + q] != 0.0) H.bmask[p] |= (unsigned char)(1u << phi);
+  H.off.assign(n + 1, 0);
+  int o = 0;
+  for (int p = 0; p <= n; p++) {
+    H.off[p] = o;
+    o += g * H.sig[p];
+  }
+  H.N = o;
+  H.rows = (H.N + TZ_WMAX + TZ_TM - 1) / TZ_TM * TZ_TM;  // room for the widest fold row block past N
+  H.ld = H.rows;
+  if ((size_t)H.rows * H.ld > ((size_t)1 << 40)) return cdz_fail(h, CDZ_ERR_ARG, "protein too long for Q");
+  H.rstart.assign(H.rows, H.N);
+  for (int p = 0; p <= n; p++)
+    for (int r = H.off[p]; r < H.off[p] + g * H.sig[p]; r++) H.rstart[r] = H.off[p];
+  H.tiles = (H.N + TZ_TM - 1) / TZ_TM;
+  H.tile_kmin.resize(H.tiles);
+  for (int ti = 0; ti < H.tiles; ti++) H.tile_kmin[ti] = H.rstart[ti * TZ_TM];
+  H.chunks = (H.N + TZ_KC - 1) / TZ_KC;
+  H.chunk_tiles.assign(H.chunks, 0);
+  for (int c = 0; c < H.chunks; c++)
+    for (int ti = 0; ti < H.tiles; ti++)
+      if (H.tile_kmin[ti] / TZ_KC <= c) H.chunk_tiles[c]++;
+  if (h->opt.prec == CDZ_FP64) return run_tensor<double>(h, H, md, log_z, prefix);
+  return run_tensor<float>(h, H, md, log_z, prefix);
+}

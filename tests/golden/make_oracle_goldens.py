@@ -21,11 +21,16 @@ here comes from the HIP path.
       minimum free energy (Section 4d) of workloads 2 and 3 and the state the
       oracle's traceback returns: mfe, codons [m], pairs [n]
 
+  oracle_tensor_workload2_300nt.npz, oracle_tensor_workload3_900nt.npz
+      the tensor-model free energy (Sections 3b-3c) of the proteins and codon
+      bonuses of workloads 2 and 3 under the synthetic (gamma 9, xi 1) model
+      inputs.tensor_model: logz and the prefix values [m]
+
 Each file also records the sha256 of the oracle sources it was computed
 with.  The 900-nt marginals take about two minutes on 8 cores, so the 900-nt
 frequency matching about half an hour.
 
-Usage: python tests/golden/make_oracle_goldens.py [--only 2|3|4] [--freq 2|3] [--mfe 2|3]
+Usage: python tests/golden/make_oracle_goldens.py [--only 2|3|4] [--freq 2|3] [--mfe 2|3] [--tensor 2|3]
 """
 from __future__ import annotations
 
@@ -104,6 +109,24 @@ def load_mfe(k: int) -> dict:
     return {key: z[key] for key in z.files}
 
 
+def tensor_path_for(k: int) -> str:
+    return os.path.join(HERE, {2: "oracle_tensor_workload2_300nt.npz", 3: "oracle_tensor_workload3_900nt.npz"}[k])
+
+
+def write_tensor(k: int) -> None:
+    prob, model = I.tensor_workload(k)
+    t0 = time.time()
+    lz, pre = oracle.tensor_logz(prob, model)
+    np.savez_compressed(tensor_path_for(k), logz=np.float64(lz), prefix=pre, n=prob.n,
+                        oracle_sha256=oracle_sha256(("tensor.c",)))
+    print(f"tensor workload {k} n={prob.n} logz={lz!r} {time.time() - t0:.1f}s", flush=True)
+
+
+def load_tensor(k: int) -> dict:
+    z = np.load(tensor_path_for(k), allow_pickle=False)
+    return {key: z[key] for key in z.files}
+
+
 def write(k: int) -> None:
     if k == 4:
         prob, en = I.workload(4, index=BATCH_LONGEST)
@@ -143,9 +166,12 @@ if __name__ == "__main__":
     ap.add_argument("--only", type=int, choices=[2, 3, 4])
     ap.add_argument("--freq", type=int, choices=[2, 3])
     ap.add_argument("--mfe", type=int, choices=[2, 3])
+    ap.add_argument("--tensor", type=int, choices=[2, 3])
     a = ap.parse_args()
     oracle.build(force=False)
-    if a.mfe:
+    if a.tensor:
+        write_tensor(a.tensor)
+    elif a.mfe:
         write_mfe(a.mfe)
     elif a.freq:
         write_freq(a.freq)

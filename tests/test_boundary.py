@@ -9,7 +9,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-PRODUCT_HEADERS = ("cdz.h", "cdz_freq.h", "cdz_mfe.h")
+PRODUCT_HEADERS = ("cdz.h", "cdz_freq.h", "cdz_mfe.h", "cdz_tensor.h")
 
 
 def _declared(header=None):
