@@ -174,6 +174,79 @@ def cpu_baseline(prob, en):
                       f"900-nt protein, {dt:.1f} s"}
 
 
+def tensor_cpu_baseline():
+    """The tensor-model oracle (FP64, 8 threads) on the 100-residue (300-nt)
+    protein of workload 2: the 900-nt pass takes about 45 s on 8 cores."""
+    import oracle
+    from paper_2604_19718_amd import inputs as I
+    prob, model = I.tensor_workload(2)
+    t0 = time.perf_counter()
+    oracle.tensor_logz(prob, model)
+    dt = time.perf_counter() - t0
+    return {"value": 1e3 * dt, "unit": "ms per pass", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one FP64 pass over the {prob.n}-nt protein of workload 2, {dt:.2f} s"}
+
+
+MFMA_FP32_PEAK_TFS = 157.3
+MFMA_FP64_PEAK_TFS = 78.6
+
+
+def tensor_prop_algorithmic(sig: np.ndarray, g: int, elt: int):
+    """Algorithmic bytes and useful flops of every propagation launch j of the
+    tensor-model pass, summed over j = 1..n.  Launch j reads, for each row of
+    position blocks p < j, the row from its own block's start to off[j] (the
+    triangle of Q, identity diagonal blocks included), reads the fold row
+    block j (gamma Sigma_j rows of off[j]) and writes gamma Sigma_j columns of
+    off[j] rows; flops = 2 * (triangle entries) * gamma Sigma_j."""
+    n = len(sig) - 1
+    h = g * sig.astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(h)])
+    tot_b = tot_f = 0.0
+    for j in range(1, n + 1):
+        R = off[j]
+        tri = float(np.sum(h[:j] * (R - off[:j])))
+        w = float(h[j])
+        tot_b += (tri + 2.0 * w * R) * elt
+        tot_f += 2.0 * tri * w
+    return tot_b, tot_f
+
+
+def tensor_leg(B, I, h32, h64, steps):
+    """The tensor-based model's free energy (Sections 3b-3c) of the 900-nt
+    protein with synthetic (gamma 9, xi 1) parameters: FP32 (the paper's
+    precision) and FP64 passes, and the propagation kernel against its
+    roofline from per-launch HIP events."""
+    prob, model = I.tensor_workload(3)
+    sig = B.cdz_tensor_dims(prob)
+    out = {"workload": "tensor-model free energy, 300 residues (900 nt), single-codon train with codon "
+                       "bonuses, synthetic V/B/S of gamma 9, xi 1",
+           "sum_sigma": int(sig.sum()), "q_rows": int(9 * sig.sum())}
+    for name, hh in (("fp32", h32), ("fp64", h64)):
+        B.cdz_tensor_logz(hh, model, prob)  # warm-up
+        ts = []
+        for _ in range(steps):
+            lz, _ = B.cdz_tensor_logz(hh, model, prob)
+            ts.append(B.cdz_last_timings(hh)[0])
+        out[f"ms_{name}"] = float(np.median(ts))
+        out[f"logz_{name}"] = lz
+        print(f"# tensor {name} {out[f'ms_{name}']:.2f} ms logz {lz:.6f}", file=sys.stderr, flush=True)
+    B.cdz_set_profiling(h32, True)
+    B.cdz_tensor_logz(h32, model, prob)
+    tm = B.cdz_last_timings(h32)
+    B.cdz_set_profiling(h32, False)
+    launches = int(tm[4])
+    avg = tm[3]
+    byt, flo = tensor_prop_algorithmic(sig, 9, 4)
+    ach = byt / launches / (avg / 1e3) / 1e9
+    out["roofline"] = {"kernel": "tz_prop<float>", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "launches": launches, "avg_launch_ms": avg,
+                       "algorithmic_bytes_per_launch": byt / launches,
+                       "mfma_tflops": flo / (avg * launches / 1e3) / 1e12,
+                       "mfma_frac": flo / (avg * launches / 1e3) / 1e12 / MFMA_FP32_PEAK_TFS,
+                       "useful_flops_per_launch": flo / launches}
+    return out
+
+
 def extra_workloads(B, I):
     """The batch of 256 proteins (30..400 residues; forward + outside + 64 samples
     each, FP32; with direct launches and replayed hipGraphs) and the 3900-nt instance (forward + outside, FP32 and FP64; 1000
@@ -235,6 +308,8 @@ def main():
                          "instance (FP32 and FP64) and report them under extra_workloads")
     ap.add_argument("--no-mfe", dest="mfe", action="store_false",
                     help="skip timing the minimum free energy and its traceback on the same protein")
+    ap.add_argument("--no-tensor", dest="tensor", action="store_false",
+                    help="skip timing the tensor-model free energy (Sections 3b-3c) of the 900-nt protein")
     ap.add_argument("--no-freq", dest="freq", action="store_false",
                     help="skip timing frequency matching (Section S4e) on the same protein")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -352,6 +427,8 @@ def main():
                             "note": "ops / forward time (fills, runs and exterior included)"}}
         print(f"# mfe {v_mfe:.4f} kT forward {tm[0]:.1f} ms traceback {tm[2]:.1f} ms", file=sys.stderr, flush=True)
 
+    tensor = tensor_leg(B, I, h32, h64, 3) if args.tensor else None
+
     res = {
         "metric": "DP cells/s + ms per forward+outside at 900 nt, FP32-scaled vs FP64, one GPU",
         "value": value, "unit": "DP cells/s", "n_gpus": 1, "steps": args.steps,
@@ -371,10 +448,14 @@ def main():
         res["frequency_matching"] = freq
     if mfe is not None:
         res["mfe"] = mfe
+    if tensor is not None:
+        res["tensor_model"] = tensor
     if args.extra:
         res["extra_workloads"] = extra_workloads(B, I)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(prob, en)
+        if tensor is not None:
+            tensor["cpu_baseline"] = tensor_cpu_baseline()
     print(json.dumps(res), flush=True)
 
 

@@ -53,12 +53,19 @@ typedef struct {
  * The workspace (Q, (gamma Sigma)^2 entries with Sigma the summed train
  * dimensions, plus partial sums of the split propagation) is allocated for the
  * call and released before it returns.  Afterwards cdz_last_timings reports
- * [0] the device time of the whole pass, [3] the average propagation kernel
- * (with cdz_set_profiling on, else 0) and [4] the number of propagation
- * launches.  Errors: CDZ_ERR_ARG, CDZ_ERR_PROTEIN, CDZ_ERR_NUMERIC,
- * CDZ_ERR_NOMEM, CDZ_ERR_HIP. */
+ * [0] the device time of the whole pass and, with cdz_set_profiling on (else
+ * 0), [3] the average propagation kernel and [4] the number of propagation
+ * launches (one per position).  Errors: CDZ_ERR_ARG, CDZ_ERR_PROTEIN,
+ * CDZ_ERR_NUMERIC, CDZ_ERR_NOMEM, CDZ_ERR_HIP. */
 cdz_status cdz_tensor_logz(cdz_handle *h, const cdz_tensor_model *model, const cdz_problem *prob, double *log_z,
                            double *prefix);
+
+/* Bond dimensions Sigma_p, p = 0..n (n = 3 n_aa), of prob's single-codon
+ * train (Section 3a, eq. single-tt): 1 at codon boundaries, the number of
+ * distinct first bases after one, the number of distinct third bases before
+ * one.  Q has gamma * sum_p Sigma_p rows.  sig: [n + 1] host int32.  Host
+ * only.  Errors: CDZ_ERR_ARG, CDZ_ERR_PROTEIN. */
+cdz_status cdz_tensor_dims(const cdz_problem *prob, int32_t *sig);
 
 #ifdef __cplusplus
 }

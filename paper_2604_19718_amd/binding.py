@@ -24,7 +24,8 @@ EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_s
            "cdz_forward_dev", "cdz_backward_dev", "cdz_last_timings", "cdz_reset",
            "cdz_set_profiling", "cdz_kernel_timings", "cdz_status_string", "cdz_last_error",
            "cdz_batch", "cdz_partition_batch", "cdz_marginals_batch", "cdz_sample_batch",
-           "cdz_workspace_bytes", "cdz_match_frequencies", "cdz_mfe", "cdz_tensor_logz"]
+           "cdz_workspace_bytes", "cdz_match_frequencies", "cdz_mfe", "cdz_tensor_logz",
+           "cdz_tensor_dims"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -98,6 +99,7 @@ def lib():
                                      ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
             "cdz_tensor_logz": ([vp, ctypes.POINTER(cdz_tensor_model), ctypes.POINTER(cdz_problem), _dp, _dp],
                                 ctypes.c_int),
+            "cdz_tensor_dims": ([ctypes.POINTER(cdz_problem), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_mfe": ([vp, ctypes.POINTER(cdz_problem), _dp, ctypes.POINTER(ctypes.c_uint8),
                          ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_match_frequencies": ([vp, ctypes.POINTER(cdz_problem), _dp, ctypes.c_double, ctypes.c_int32,
@@ -230,6 +232,16 @@ def cdz_tensor_logz(h: Handle, model, prob):
     pre = np.zeros(len(prob.prot))
     h.check(lib().cdz_tensor_logz(h.ptr, ctypes.byref(md), ctypes.byref(p.c), _arr(out), _arr(pre)))
     return float(out[0]), pre
+
+
+def cdz_tensor_dims(prob) -> np.ndarray:
+    """Bond dimensions Sigma_p, p = 0..n, of the protein's single-codon train."""
+    p = _Prob(prob)
+    sig = np.zeros(3 * len(prob.prot) + 1, np.int32)
+    st = lib().cdz_tensor_dims(ctypes.byref(p.c), sig.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if st != 0:
+        raise CdzError(st, "cdz_tensor_dims")
+    return sig
 
 
 def cdz_match_frequencies(h: Handle, prob, f_target: np.ndarray, r_tol: float = 0.002,

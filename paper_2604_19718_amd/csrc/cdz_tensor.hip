@@ -18,9 +18,11 @@
 //                last element is the unpaired base, elements of two or three
 //                bases are zero.
 //   tz_prop (j)  Y_{[0:j), j} = sum_k Q_{[0:j), k} E_{k,j} on the matrix cores
-//                (v_mfma 16x16x4, FP32 or FP64): one wave per 64 rows and
-//                2048-wide chunk of k, triangular (a tile starts at the first
-//                block its rows own), partial sums to a side buffer.
+//                (v_mfma 16x16x4, FP32 or FP64): one workgroup per 64 rows and
+//                2048-wide chunk of k, its eight waves on 256-wide parts,
+//                summed through LDS in a fixed tree; triangular (a tile starts
+//                at the first block its rows own); one partial sum per chunk
+//                to a side buffer.
 // Scaling: column j is divided by h_{j-1} = 2^e, e the binary exponent of the
 // largest entry of its row-0 block, so the prefix block stays in [1, 2);
 // E_{k,j} of a pair is divided by h_k (the inner block carries the factors of
@@ -42,7 +44,9 @@ hipError_t prof_reserve(cdz_handle *h, int launches);
 
 namespace {
 
-constexpr int TZ_KC = 2048;  // k chunk of one propagation wave
+constexpr int TZ_KC = 2048;  // k chunk of one propagation workgroup
+constexpr int TZ_PW = 8;          // waves of one propagation workgroup
+constexpr int TZ_KW = TZ_KC / TZ_PW;  // k sub-chunk of each of its waves
 constexpr int TZ_TM = 64;    // rows of one propagation tile (four 16-row MFMA tiles)
 constexpr int TZ_WMAX = 64;  // widest column block gamma * Sigma (gamma <= 16, Sigma <= 4)
 constexpr int TZ_FT = 256;   // fold workgroup: four waves, one k each
@@ -101,7 +105,7 @@ struct TzDev {
 // (16 bytes) and feeds them to VEC successive instructions, so instruction s
 // multiplies k = k0 + VEC q + s for q = 0..3 -- the same set for A and B.
 template <typename T>
-__global__ __launch_bounds__(64) void tz_prop(TzDev<T> D, int j, int ntiles, int nchunks) {
+__global__ __launch_bounds__(512) void tz_prop(TzDev<T> D, int j, int ntiles, int nchunks) {
   using M = Mf<T>;
   constexpr int VEC = M::VEC, KS = 4 * VEC;
   int b = blockIdx.x, c = 0;
@@ -112,10 +116,10 @@ __global__ __launch_bounds__(64) void tz_prop(TzDev<T> D, int j, int ntiles, int
   }
   const int t = b;
   const int R = D.off[j], w = D.g * D.sig[j], ntn = (w + 15) >> 4;
-  const int lane = threadIdx.x, li = lane & 15, q = lane >> 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, q = lane >> 4;
   const int r0 = t * TZ_TM;
-  const int kb = max(c * TZ_KC, D.tile_kmin[t]) & ~(KS - 1);
-  const int ke = min((c + 1) * TZ_KC, R);
+  const int kb = max(c * TZ_KC + wave * TZ_KW, D.tile_kmin[t]) & ~(KS - 1);
+  const int ke = min(c * TZ_KC + (wave + 1) * TZ_KW, R);
   int kst[4];
   const T *arow[4];
 #pragma unroll
@@ -137,29 +141,74 @@ __global__ __launch_bounds__(64) void tz_prop(TzDev<T> D, int j, int ntiles, int
   for (int m = 0; m < 4; m++)
 #pragma unroll
     for (int nn = 0; nn < 4; nn++) acc[m][nn] = typename M::acc_t{0, 0, 0, 0};
-  for (int k0 = kb; k0 < ke; k0 += KS) {
+  // rows own k from their block's start: steps below the tile's last start,
+  // and the step reaching the chunk end, are masked; the rest are not
+  const int kfull = D.rstart[min(r0 + TZ_TM, R) - 1];
+  typename M::ld_t a[4], bv[4], an[4], bn[4];
+  auto load = [&](typename M::ld_t *A_, typename M::ld_t *B_, int k0) {
     const int kk = k0 + VEC * q;
-    typename M::ld_t a[4], bv[4];
 #pragma unroll
-    for (int m = 0; m < 4; m++) a[m] = *reinterpret_cast<const typename M::ld_t *>(arow[m] + kk);
+    for (int m = 0; m < 4; m++) A_[m] = *reinterpret_cast<const typename M::ld_t *>(arow[m] + kk);
 #pragma unroll
     for (int nn = 0; nn < 4; nn++)
-      if (nn < ntn) bv[nn] = *reinterpret_cast<const typename M::ld_t *>(brow[nn] + kk);
+      if (nn < ntn) B_[nn] = *reinterpret_cast<const typename M::ld_t *>(brow[nn] + kk);
+  };
+  load(a, bv, kb);
+  for (int k0 = kb; k0 < ke; k0 += KS) {
+    if (k0 + KS < ke) load(an, bn, k0 + KS);  // next step's operands in flight during this one
+    const int kk = k0 + VEC * q;
+    const bool edge = k0 < kfull || k0 + KS > ke;
 #pragma unroll
     for (int s = 0; s < VEC; s++) {
       const int k = kk + s;
       T av[4], bs[4];
 #pragma unroll
-      for (int m = 0; m < 4; m++) av[m] = (k >= kst[m] && k < ke) ? a[m][s] : T(0);
+      for (int m = 0; m < 4; m++) av[m] = (!edge || (k >= kst[m] && k < ke)) ? a[m][s] : T(0);
 #pragma unroll
-      for (int nn = 0; nn < 4; nn++) bs[nn] = (nn < ntn && bok[nn] && k < ke) ? bv[nn][s] : T(0);
+      for (int nn = 0; nn < 4; nn++) bs[nn] = (nn < ntn && bok[nn] && (!edge || k < ke)) ? bv[nn][s] : T(0);
 #pragma unroll
       for (int nn = 0; nn < 4; nn++)
         if (nn < ntn)
 #pragma unroll
           for (int m = 0; m < 4; m++) acc[m][nn] = M::mac(av[m], bs[nn], acc[m][nn]);
     }
+#pragma unroll
+    for (int m = 0; m < 4; m++) a[m] = an[m];
+#pragma unroll
+    for (int nn = 0; nn < 4; nn++) bv[nn] = bn[nn];
   }
+  // the eight sums meet through LDS in a fixed tree: w += w + 4 (w < 4),
+  // then wave 0 adds waves 1, 2, 3 in order
+  extern __shared__ __align__(16) unsigned char tz_plds[];
+  typename M::acc_t *red = reinterpret_cast<typename M::acc_t *>(tz_plds);  // [4][4][ntn][64]
+  if (wave >= 4)
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+      for (int nn = 0; nn < 4; nn++)
+        if (nn < ntn) red[(((wave - 4) * 4 + m) * ntn + nn) * 64 + lane] = acc[m][nn];
+  __syncthreads();
+  if (wave < 4)
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+      for (int nn = 0; nn < 4; nn++)
+        if (nn < ntn) acc[m][nn] += red[((wave * 4 + m) * ntn + nn) * 64 + lane];
+  __syncthreads();
+  if (wave >= 1 && wave < 4)
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+      for (int nn = 0; nn < 4; nn++)
+        if (nn < ntn) red[(((wave - 1) * 4 + m) * ntn + nn) * 64 + lane] = acc[m][nn];
+  __syncthreads();
+  if (wave != 0) return;
+  for (int wv = 1; wv < 4; wv++)
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+      for (int nn = 0; nn < 4; nn++)
+        if (nn < ntn) acc[m][nn] += red[(((wv - 1) * 4 + m) * ntn + nn) * 64 + lane];
   T *P = D.P + (size_t)c * D.prow * TZ_WMAX;
 #pragma unroll
   for (int m = 0; m < 4; m++)
@@ -178,8 +227,43 @@ template <typename T>
 __device__ inline T col_sum(const TzDev<T> &D, int r, int col, int nchunks) {
   const int cf = D.tile_kmin[r / TZ_TM] / TZ_KC;
   T y = T(0);
-  for (int c = cf; c < nchunks; c++) y += D.P[((size_t)c * D.prow + r) * TZ_WMAX + col];
+  const T *p = D.P + (size_t)r * TZ_WMAX + col;
+  const size_t cs = (size_t)D.prow * TZ_WMAX;
+  for (int c0 = cf; c0 < nchunks; c0 += 8) {  // eight loads in flight, added in chunk order
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = c0 + u < nchunks ? p[(c0 + u) * cs] : T(0);
+#pragma unroll
+    for (int u = 0; u < 8; u++) y += v[u];
+  }
   return y;
+}
+
+// the same for four entries at once (rows r[u], columns col[u], skipped where
+// ok[u] is false): up to 32 loads in flight, each sum in chunk order
+template <typename T>
+__device__ inline void col_sum4(const TzDev<T> &D, const int *r, const int *col, const bool *ok, int nchunks, T *y) {
+  const size_t cs = (size_t)D.prow * TZ_WMAX;
+  int cf[4], cmin = nchunks;
+  const T *p[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    cf[u] = ok[u] ? D.tile_kmin[r[u] / TZ_TM] / TZ_KC : nchunks;
+    cmin = min(cmin, cf[u]);
+    p[u] = D.P + (size_t)(ok[u] ? r[u] : 0) * TZ_WMAX + (ok[u] ? col[u] : 0);
+    y[u] = T(0);
+  }
+  for (int c0 = cmin; c0 < nchunks; c0 += 8) {
+    T v[4][8];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int x = 0; x < 8; x++) v[u][x] = (c0 + x >= cf[u] && c0 + x < nchunks) ? p[u][(c0 + x) * cs] : T(0);
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int x = 0; x < 8; x++) y[u] += v[u][x];
+  }
 }
 
 __device__ inline int exp_of(double x) {
@@ -205,21 +289,51 @@ template <typename T>
 __device__ inline int column_exponent(const TzDev<T> &D, int jc, int nchunks) {
   const int w = D.g * D.sig[jc];
   T mx = T(0);
-  for (int e = threadIdx.x & 63; e < D.g * w; e += 64) mx = max(mx, col_sum(D, e / w, e % w, nchunks));
+  for (int e0 = threadIdx.x & 63; e0 < D.g * w; e0 += 256) {
+    int r[4], cc[4];
+    bool ok[4];
+    T y[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int e = e0 + 64 * u;
+      ok[u] = e < D.g * w;
+      r[u] = e / w;
+      cc[u] = e % w;
+    }
+    col_sum4(D, r, cc, ok, nchunks, y);
+#pragma unroll
+    for (int u = 0; u < 4; u++) mx = max(mx, y[u]);
+  }
   mx = wave_max(mx);
   return exp_of((double)mx);
 }
 
 // ---- fold: finish column j-1, build row block j --------------------------
-template <typename T>
+// STAGE: the model (S B, B, V) is copied to LDS first; without it (when it
+// does not fit beside the per-wave arrays) the waves read it from memory.
+template <typename T, bool STAGE>
 __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_prev) {
   extern __shared__ __align__(16) unsigned char tz_lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = D.g, xi = D.xi, G4 = 4 * g;
   const int qi = blockIdx.x * 4 + wave;  // item: block row qi of column j-1, element k = qi - 1
-  T *Xs = reinterpret_cast<T *>(tz_lds) + (size_t)wave * (G4 * G4 + 2 * xi * 256);
-  T *ts = Xs + G4 * G4;  // [xi][4 phi_l][4 phi_k][4][4]
-  T *Us = ts + xi * 256; // [xi][4 phi_k][4 phi_l][4][4]
+  const int wstride = G4 * G4 + 2 * xi * 256 + 192;  // Xs, t, U, two cores, combination list
+  T *Xs = reinterpret_cast<T *>(tz_lds) + (size_t)wave * wstride;
+  T *ts = Xs + G4 * G4;  // [combination][sigma_b][sigma_e]
+  T *Us = ts + xi * 256; // [combination][sigma_k][sigma_j]
+  // the model, shared by the four waves: S B, B, V
+  const T *sSB = D.SB, *sB = D.B, *sV = D.V;
+  if (STAGE) {
+    T *l = reinterpret_cast<T *>(tz_lds) + (size_t)4 * wstride;
+    for (int e = threadIdx.x; e < xi * 16 * g * g; e += TZ_FT) {
+      l[e] = D.SB[e];
+      l[xi * 16 * g * g + e] = D.B[e];
+    }
+    for (int e = threadIdx.x; e < 4 * g * g; e += TZ_FT) l[2 * xi * 16 * g * g + e] = D.V[e];
+    sSB = l;
+    sB = l + (size_t)xi * 16 * g * g;
+    sV = l + (size_t)2 * xi * 16 * g * g;
+  }
   __shared__ int e_prev;
   if (wave == 0) {
     const int e = j >= 2 ? column_exponent(D, j - 1, nchunks_prev) : 0;
@@ -235,11 +349,25 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
   if (live && qi < j - 1) {
     const int r0 = D.off[qi], rows = g * D.sig[qi];
     const size_t cbase = (size_t)D.off[j - 1];
-    for (int e = lane; e < rows * wp; e += 64) {
-      const int rr = e / wp, col = e % wp;
-      const T x = ldexp(col_sum(D, r0 + rr, col, nchunks_prev), -e_prev);
-      D.Q[(size_t)(r0 + rr) * D.ld + cbase + col] = x;
-      Xs[rr * wp + col] = x;
+    for (int e0 = lane; e0 < rows * wp; e0 += 256) {
+      int r[4], cc[4];
+      bool ok[4];
+      T y[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int e = e0 + 64 * u;
+        ok[u] = e < rows * wp;
+        r[u] = r0 + e / wp;
+        cc[u] = e % wp;
+      }
+      col_sum4(D, r, cc, ok, nchunks_prev, y);
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+        if (ok[u]) {
+          const T x = ldexp(y[u], -e_prev);
+          D.Q[(size_t)r[u] * D.ld + cbase + cc[u]] = x;
+          Xs[(r[u] - r0) * wp + cc[u]] = x;
+        }
     }
     if (qi == 0 && (j - 1) % 3 == 0) {  // codon boundary: Sigma = 1, a g x g block
       T tr = T(0);
@@ -255,54 +383,64 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
   const int k = qi - 1, l = j - 1;
   const bool pair = live && qi >= 1 && l - k >= 4;
   const int sk = pair ? D.sig[k] : 0, sb = pair ? D.sig[k + 1] : 0, se = pair ? D.sig[l] : 0, sj = D.sig[j];
-  // 2a. t[rho][phi_l][phi_k][sigma_b][sigma_e] = Tr[S B_{phi_l, phi_k} X^{sigma_b, sigma_e}]
+  // the cores of the element's ends and the (rho, phi_k, phi_l) that carry
+  // weight (B nonzero, both bases possible), in (rho, phi_k, phi_l) order
+  T *tk = Us + xi * 256, *tl = tk + 64;
+  int *cmb = reinterpret_cast<int *>(tl + 64);
+  __shared__ int ncmb[4];
   if (pair) {
-    for (int e = lane; e < xi * 256; e += 64) {
-      const int rho = e >> 8, pl = (e >> 6) & 3, pk = (e >> 4) & 3, b = (e >> 2) & 3, ee = e & 3;
-      T acc = T(0);
-      if (b < sb && ee < se && ((D.pairmask >> (4 * pk + pl)) & 1) && ((D.bmask[k] >> pk) & 1) &&
-          ((D.bmask[l] >> pl) & 1)) {
-        const T *sbm = D.SB + ((((size_t)rho * 4 + pl) * 4 + pk) * g) * g;
-        for (int x = 0; x < g; x++)
-          for (int y = 0; y < g; y++) acc += sbm[x * g + y] * Xs[(b * g + y) * wp + ee * g + x];
-      }
-      ts[e] = acc;
+    tk[lane] = D.tc[(size_t)k * 64 + lane];
+    tl[lane] = D.tc[(size_t)l * 64 + lane];
+    if (lane == 0) {
+      int na = 0;
+      for (int rho = 0; rho < xi; rho++)
+        for (int pk = 0; pk < 4; pk++)
+          for (int pl = 0; pl < 4; pl++)
+            if (((D.pairmask >> (4 * pk + pl)) & 1) && ((D.bmask[k] >> pk) & 1) && ((D.bmask[l] >> pl) & 1))
+              cmb[na++] = (rho * 4 + pk) * 4 + pl;
+      ncmb[wave] = na;
     }
+  } else if (live && qi == j - 1) {
+    tk[lane] = D.tc[(size_t)(j - 1) * 64 + lane];
   }
   __syncthreads();
-  // 2b. U[rho][phi_k][phi_l][sigma_k][sigma_j] = (T_k t T_l)[sigma_k][sigma_j]
-  if (pair) {
-    for (int e = lane; e < xi * 256; e += 64) {
-      const int rho = e >> 8, pk = (e >> 6) & 3, pl = (e >> 4) & 3, a = (e >> 2) & 3, cc = e & 3;
-      T u = T(0);
-      if (a < sk && cc < sj)
-        for (int b = 0; b < sb; b++)
-          for (int ee = 0; ee < se; ee++)
-            u += D.tc[(((size_t)k * 4 + pk) * 4 + a) * 4 + b] * ts[(((rho * 4 + pl) * 4 + pk) * 4 + b) * 4 + ee] *
-                 D.tc[(((size_t)l * 4 + pl) * 4 + ee) * 4 + cc];
-      Us[e] = u;
+  const int na = pair ? ncmb[wave] : 0;
+  // 2a. t[a][sigma_b][sigma_e] = Tr[S B_{phi_l, phi_k} X^{sigma_b, sigma_e}] for combination a
+  for (int e = lane; e < na * 16; e += 64) {
+    const int a = e >> 4, b = (e >> 2) & 3, ee = e & 3;
+    T acc = T(0);
+    if (b < sb && ee < se) {
+      const int c3 = cmb[a], rho = c3 >> 4, pk = (c3 >> 2) & 3, pl = c3 & 3;
+      const T *sbm = sSB + ((((size_t)rho * 4 + pl) * 4 + pk) * g) * g;
+      for (int x = 0; x < g; x++)
+        for (int y = 0; y < g; y++) acc += sbm[x * g + y] * Xs[(b * g + y) * wp + ee * g + x];
     }
+    ts[e] = acc;
   }
   __syncthreads();
-  // 2c. E_{k,j} = 2^-e_k sum_{rho, phi_k, phi_l} U (x) B_{phi_k, phi_l}, stored transposed
+  // 2b. U[a][sigma_k][sigma_j] = (T_k^{phi_k} t T_l^{phi_l})[sigma_k][sigma_j]
+  for (int e = lane; e < na * 16; e += 64) {
+    const int a = e >> 4, ak = (e >> 2) & 3, cc = e & 3;
+    const int c3 = cmb[a], pk = (c3 >> 2) & 3, pl = c3 & 3;
+    T u = T(0);
+    if (ak < sk && cc < sj)
+      for (int b = 0; b < sb; b++)
+        for (int ee = 0; ee < se; ee++)
+          u += tk[(pk * 4 + ak) * 4 + b] * ts[a * 16 + b * 4 + ee] * tl[(pl * 4 + ee) * 4 + cc];
+    Us[e] = u;
+  }
+  __syncthreads();
+  // 2c. E_{k,j} = 2^-e_k sum_a U[a] (x) B_{phi_k, phi_l}, stored transposed
   if (live && qi >= 1) {
     const int rows = g * D.sig[k], wj = g * sj;
     const size_t rbase = (size_t)D.off[j], cbase = (size_t)D.off[k];
     const int ek = pair ? D.colexp[k + 1] : 0;
     for (int e = lane; e < rows * wj; e += 64) {
       const int rr = e % rows, cc = e / rows;  // consecutive lanes along the stored row
-      const int a = rr / g, za = rr % g, s2 = cc / g, zb = cc % g;
+      const int ak = rr / g, za = rr % g, s2 = cc / g, zb = cc % g;
       T f = T(0);
-      if (pair) {
-        for (int rho = 0; rho < xi; rho++)
-          for (int pk = 0; pk < 4; pk++)
-            for (int pl = 0; pl < 4; pl++)
-              if ((D.pairmask >> (4 * pk + pl)) & 1)
-                f += Us[(((rho * 4 + pk) * 4 + pl) * 4 + a) * 4 + s2] *
-                     D.B[((((size_t)rho * 4 + pk) * 4 + pl) * g + za) * g + zb];
-        f = ldexp(f, -ek);
-      }
-      D.Q[(rbase + cc) * D.ld + cbase + rr] = f;
+      for (int a = 0; a < na; a++) f += Us[a * 16 + ak * 4 + s2] * sB[(size_t)cmb[a] * g * g + za * g + zb];
+      D.Q[(rbase + cc) * D.ld + cbase + rr] = pair ? ldexp(f, -ek) : T(0);
     }
   }
   // 3. the unpaired base j-1
@@ -313,8 +451,7 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
       const int rr = e % rows, cc = e / rows;
       const int a = rr / g, za = rr % g, s2 = cc / g, zb = cc % g;
       T f = T(0);
-      for (int phi = 0; phi < 4; phi++)
-        f += D.tc[(((size_t)(j - 1) * 4 + phi) * 4 + a) * 4 + s2] * D.V[(phi * g + za) * g + zb];
+      for (int phi = 0; phi < 4; phi++) f += tk[(phi * 4 + a) * 4 + s2] * sV[(phi * g + za) * g + zb];
       D.Q[(rbase + cc) * D.ld + cbase + rr] = f;
     }
   }
@@ -450,16 +587,23 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   D.P = (T *)(base + oP);
   D.colexp = (int *)(base + oCe);
   D.ptr = (double *)(base + oPt);
-  const size_t fold_lds = (size_t)4 * (16 * g * g + 2 * xi * 256) * sizeof(T);
-  if ((int)fold_lds > h->lds_max) return cdz_fail(h, CDZ_ERR_ARG, "gamma too large for the fold's LDS");
+  const size_t wave_lds = (size_t)4 * (16 * g * g + 2 * xi * 256 + 192) * sizeof(T);
+  const size_t model_lds = (size_t)(2 * xi * 16 + 4) * g * g * sizeof(T);
+  const bool stage = wave_lds + model_lds <= (size_t)h->lds_max;
+  const size_t fold_lds = stage ? wave_lds + model_lds : wave_lds;
+  if (wave_lds > (size_t)h->lds_max) return cdz_fail(h, CDZ_ERR_ARG, "gamma too large for the fold's LDS");
+  int ntn_max = 1;
+  for (int p = 0; p <= n; p++) ntn_max = std::max(ntn_max, (g * H.sig[p] + 15) / 16);
+  const size_t prop_lds = (size_t)4 * 4 * ntn_max * 64 * 4 * sizeof(T);
   if (h->profiling) HIPCHK(h, prof_reserve(h, n));
   HIPCHK(h, hipEventRecord(h->ev[0], st));
   tz_init<T><<<2048, 256, 0, st>>>(D.Q, (size_t)H.rows, (size_t)H.ld, (size_t)H.N);
   for (int j = 1; j <= n; j++) {
     const int fgrid = (j + 3) / 4;
-    tz_fold<T><<<fgrid, TZ_FT, fold_lds, st>>>(D, j, j >= 2 ? nchunks_of(H, j - 1) : 0);
+    if (stage) tz_fold<T, true><<<fgrid, TZ_FT, fold_lds, st>>>(D, j, j >= 2 ? nchunks_of(H, j - 1) : 0);
+    else tz_fold<T, false><<<fgrid, TZ_FT, fold_lds, st>>>(D, j, j >= 2 ? nchunks_of(H, j - 1) : 0);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * (j - 1)], st));
-    tz_prop<T><<<prop_grid(H, j), 64, 0, st>>>(D, j, ntiles_of(H, j), nchunks_of(H, j));
+    tz_prop<T><<<prop_grid(H, j), 64 * TZ_PW, prop_lds, st>>>(D, j, ntiles_of(H, j), nchunks_of(H, j));
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * (j - 1) + 1], st));
   }
   tz_final<T><<<1, 64, 0, st>>>(D, nchunks_of(H, n));
@@ -474,8 +618,8 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
   h->times[0] = ms;
   h->times[1] = h->times[2] = 0;
-  h->times[3] = 0;
-  h->times[4] = n;
+  h->prof_fwd_ms = 0;
+  h->prof_fwd_launches = 0;
   if (h->profiling) {
     double tot = 0;
     for (int j = 0; j < n; j++) {
@@ -483,7 +627,8 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
       HIPCHK(h, hipEventElapsedTime(&k, h->pev[2 * j], h->pev[2 * j + 1]));
       tot += k;
     }
-    h->times[3] = tot / n;
+    h->prof_fwd_ms = tot;
+    h->prof_fwd_launches = n;
   }
   const double L2 = 0.6931471805599453094;
   long esum = 0;
@@ -498,26 +643,10 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   return CDZ_OK;
 }
 
-}  // namespace
-
-extern "C" cdz_status cdz_tensor_logz(cdz_handle *h, const cdz_tensor_model *md, const cdz_problem *prob,
-                                      double *log_z, double *prefix) {
-  if (!h || !md || !prob || !log_z) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
-  if (prob->theta2) return cdz_fail(h, CDZ_ERR_ARG, "the single-codon train takes no codon-pair weights");
-  const int g = md->gamma, xi = md->xi;
-  if (g < 1 || g > 16 || xi < 1 || xi > 4 || !md->V || !md->B || !md->S)
-    return cdz_fail(h, CDZ_ERR_ARG, "tensor model: gamma in 1..16, xi in 1..4, V, B, S given");
-  auto ok = [](const double *p, size_t cnt) {
-    for (size_t q = 0; q < cnt; q++)
-      if (!(p[q] >= 0.0) || !std::isfinite(p[q])) return false;
-    return true;
-  };
-  if (!ok(md->V, (size_t)4 * g * g) || !ok(md->B, (size_t)xi * 16 * g * g) || !ok(md->S, (size_t)g * g))
-    return cdz_fail(h, CDZ_ERR_NUMERIC, "tensor model entries must be finite and non-negative");
-  HostTables t;
-  cdz_status s = build_tables(h, prob->n_aa, prob->aa, prob->theta1, nullptr, t);
-  if (s != CDZ_OK) return s;
-  TzHost H;
+// single-codon train (eq. single-tt): core 3a selects the first base,
+// core 3a+1 the codon (first base, middle base, third base) with its bonus,
+// core 3a+2 the third base
+cdz_status build_train(cdz_handle *h, const HostTables &t, const double *theta1, TzHost &H) {
   H.m = t.m;
   H.n = t.n;
   const int n = H.n;
@@ -525,9 +654,6 @@ extern "C" cdz_status cdz_tensor_logz(cdz_handle *h, const cdz_tensor_model *md,
   H.tc.assign((size_t)n * 64, 0.0);
   H.bmask.assign(n, 0);
   auto TC = [&](int p, int phi, int a, int b) -> double & { return H.tc[(((size_t)p * 4 + phi) * 4 + a) * 4 + b]; };
-  // single-codon train (eq. single-tt): core 3a selects the first base,
-  // core 3a+1 the codon (first base, middle base, third base) with its bonus,
-  // core 3a+2 the third base
   for (int a = 0; a < H.m; a++) {
     const int p = 3 * a, d = t.d[p];
     int first[4], third[4], nf = 0, nth = 0;
@@ -549,7 +675,7 @@ extern "C" cdz_status cdz_tensor_logz(cdz_handle *h, const cdz_tensor_model *md,
       int x = 0, y = 0;
       while (first[x] != b0) x++;
       while (third[y] != b2) y++;
-      const double th = prob->theta1 ? prob->theta1[a * 6 + s2] : 0.0;
+      const double th = theta1 ? theta1[a * 6 + s2] : 0.0;
       if (!std::isfinite(th)) return cdz_fail(h, CDZ_ERR_NUMERIC, "non-finite codon bonus");
       TC(p + 1, b1, x, y) += std::exp(th);
     }
@@ -559,6 +685,13 @@ extern "C" cdz_status cdz_tensor_logz(cdz_handle *h, const cdz_tensor_model *md,
     for (int phi = 0; phi < 4; phi++)
       for (int q = 0; q < 16; q++)
         if (H.tc[((size_t)p * 4 + phi) * 16 + q] != 0.0) H.bmask[p] |= (unsigned char)(1u << phi);
+  return CDZ_OK;
+}
+
+// flattened layout of Q and the propagation's tile and chunk tables, then the pass
+cdz_status finish_layout(cdz_handle *h, TzHost &H, int g, const cdz_tensor_model *md, double *log_z,
+                         double *prefix) {
+  const int n = H.n;
   H.off.assign(n + 1, 0);
   int o = 0;
   for (int p = 0; p <= n; p++) {
@@ -582,4 +715,42 @@ extern "C" cdz_status cdz_tensor_logz(cdz_handle *h, const cdz_tensor_model *md,
       if (H.tile_kmin[ti] / TZ_KC <= c) H.chunk_tiles[c]++;
   if (h->opt.prec == CDZ_FP64) return run_tensor<double>(h, H, md, log_z, prefix);
   return run_tensor<float>(h, H, md, log_z, prefix);
+}
+
+}  // namespace
+
+extern "C" cdz_status cdz_tensor_logz(cdz_handle *h, const cdz_tensor_model *md, const cdz_problem *prob,
+                                      double *log_z, double *prefix) {
+  if (!h || !md || !prob || !log_z) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
+  if (prob->theta2) return cdz_fail(h, CDZ_ERR_ARG, "the single-codon train takes no codon-pair weights");
+  const int g = md->gamma, xi = md->xi;
+  if (g < 1 || g > 16 || xi < 1 || xi > 4 || !md->V || !md->B || !md->S)
+    return cdz_fail(h, CDZ_ERR_ARG, "tensor model: gamma in 1..16, xi in 1..4, V, B, S given");
+  auto ok = [](const double *p, size_t cnt) {
+    for (size_t q = 0; q < cnt; q++)
+      if (!(p[q] >= 0.0) || !std::isfinite(p[q])) return false;
+    return true;
+  };
+  if (!ok(md->V, (size_t)4 * g * g) || !ok(md->B, (size_t)xi * 16 * g * g) || !ok(md->S, (size_t)g * g))
+    return cdz_fail(h, CDZ_ERR_NUMERIC, "tensor model entries must be finite and non-negative");
+  HostTables t;
+  cdz_status s = build_tables(h, prob->n_aa, prob->aa, prob->theta1, nullptr, t);
+  if (s != CDZ_OK) return s;
+  TzHost H;
+  s = build_train(h, t, prob->theta1, H);
+  if (s != CDZ_OK) return s;
+  return finish_layout(h, H, g, md, log_z, prefix);
+}
+
+extern "C" cdz_status cdz_tensor_dims(const cdz_problem *prob, int32_t *sig) {
+  if (!prob || !sig || prob->n_aa < 1 || !prob->aa) return CDZ_ERR_ARG;
+  cdz_handle tmp;
+  HostTables t;
+  cdz_status s = build_tables(&tmp, prob->n_aa, prob->aa, nullptr, nullptr, t);
+  if (s != CDZ_OK) return s;
+  TzHost H;
+  s = build_train(&tmp, t, nullptr, H);
+  if (s != CDZ_OK) return s;
+  for (int p = 0; p <= H.n; p++) sig[p] = H.sig[p];
+  return CDZ_OK;
 }

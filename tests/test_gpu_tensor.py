@@ -4,7 +4,7 @@ Alg. fast-pf) through the C-ABI, against the oracle (oracle/tensor.c).
 Every codon boundary of one pass gives a full partition function (the
 protein's prefixes), so each case compares m values element by element.
 FP64: both sides add positive terms in different orders (the propagation sums
-k in 16-wide MFMA groups and 2048-wide chunks), so log Z agrees to a few ulps
+k in 16-wide MFMA groups and 1024-wide chunks), so log Z agrees to a few ulps
 per accumulation level: 1e-11 relative is asked.  FP32: every value is a sum
 of positive terms, each rounding is at most 2^-24 relative and the pass
 nests about n such sums, so |d log Z| <= n * 2^-24 * c; c = 8 covers the
@@ -54,8 +54,8 @@ def test_tensor_against_oracle_small(prot, gamma, xi, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("m", [40, 100])
 def test_tensor_against_oracle_tiles(m, prec):
-    """40 residues: one chunk, ~25 row tiles; 100 residues (300 nt, about 4300
-    rows): three 2048-wide chunks, a ragged last tile and chunk."""
+    """40 residues: two 1024-wide chunks of k, ~28 row tiles; 100 residues
+    (300 nt, about 4450 rows): five chunks, a ragged last tile and chunk."""
     prob, model = I.tensor_workload(2, m=m)
     ref, rpre = oracle.tensor_logz(prob, model)
     got, gpre = B.cdz_tensor_logz(_handle(prec), model, prob)
