@@ -310,6 +310,8 @@ def main():
                     help="skip timing the minimum free energy and its traceback on the same protein")
     ap.add_argument("--no-tensor", dest="tensor", action="store_false",
                     help="skip timing the tensor-model free energy (Sections 3b-3c) of the 900-nt protein")
+    ap.add_argument("--tensor-steps", type=int, default=3,
+                    help="timed tensor-model passes per precision (after one warm-up pass)")
     ap.add_argument("--no-freq", dest="freq", action="store_false",
                     help="skip timing frequency matching (Section S4e) on the same protein")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -427,7 +429,7 @@ def main():
                             "note": "ops / forward time (fills, runs and exterior included)"}}
         print(f"# mfe {v_mfe:.4f} kT forward {tm[0]:.1f} ms traceback {tm[2]:.1f} ms", file=sys.stderr, flush=True)
 
-    tensor = tensor_leg(B, I, h32, h64, 3) if args.tensor else None
+    tensor = tensor_leg(B, I, h32, h64, max(1, args.tensor_steps)) if args.tensor else None
 
     res = {
         "metric": "DP cells/s + ms per forward+outside at 900 nt, FP32-scaled vs FP64, one GPU",

@@ -11,7 +11,7 @@
 // contiguous rows.
 //
 // Column j takes two launches:
-//   tz_fold (j)  one wave per k < j: finishes column j-1 (sums the split-K
+//   tz_fold (j)  one workgroup per k < j: finishes column j-1 (sums the split-K
 //                partials, divides by the column's power of two, writes the
 //                blocks back) and builds E_{k,j} -- a pair (k, j-1) folds the
 //                block Q_{k+1,j-1} it has just finished (eq. design-fold), the
@@ -19,10 +19,10 @@
 //                bases are zero.
 //   tz_prop (j)  Y_{[0:j), j} = sum_k Q_{[0:j), k} E_{k,j} on the matrix cores
 //                (v_mfma 16x16x4, FP32 or FP64): one workgroup per 64 rows and
-//                2048-wide chunk of k, its eight waves on 256-wide parts,
-//                summed through LDS in a fixed tree; triangular (a tile starts
-//                at the first block its rows own); one partial sum per chunk
-//                to a side buffer.
+//                chunk of k (256 to 2048 wide by column length), its eight
+//                waves on eighths of it, summed through LDS in a fixed tree;
+//                triangular (a tile starts at the first block its rows own);
+//                one partial sum per chunk to a side buffer.
 // Scaling: column j is divided by h_{j-1} = 2^e, e the binary exponent of the
 // largest entry of its row-0 block, so the prefix block stays in [1, 2);
 // E_{k,j} of a pair is divided by h_k (the inner block carries the factors of
@@ -44,12 +44,16 @@ hipError_t prof_reserve(cdz_handle *h, int launches);
 
 namespace {
 
-constexpr int TZ_KC = 2048;  // k chunk of one propagation workgroup
+// k chunk of one propagation workgroup, chosen per column: the smallest of
+// these giving at most TZ_MAXCH chunks (the longest otherwise), so short
+// columns get short wave chains and long ones few partial sums
+constexpr int TZ_NKC = 4;
+constexpr int TZ_KCS[TZ_NKC] = {256, 512, 1024, 2048};
+constexpr int TZ_MAXCH = 8;
 constexpr int TZ_PW = 8;          // waves of one propagation workgroup
-constexpr int TZ_KW = TZ_KC / TZ_PW;  // k sub-chunk of each of its waves
 constexpr int TZ_TM = 64;    // rows of one propagation tile (four 16-row MFMA tiles)
 constexpr int TZ_WMAX = 64;  // widest column block gamma * Sigma (gamma <= 16, Sigma <= 4)
-constexpr int TZ_FT = 256;   // fold workgroup: four waves, one k each
+constexpr int TZ_FT = 256;   // fold workgroup: one item (block row / element)
 
 template <typename T>
 struct Mf;
@@ -84,7 +88,6 @@ struct TzDev {
   const int *off;               // [n+1] first row/column of each position
   const int *rstart;            // [rows] off[] of the position owning the row
   const int *tile_kmin;         // [tiles] rstart of the tile's first row
-  const int *chunk_tiles;       // [chunks] number of tiles whose first chunk is <= c
   const unsigned char *bmask;   // [n] bit phi set if core p is nonzero for base phi
   const T *tc;                  // [n][4][4][4] train cores: p, base, sigma_a, sigma_b
   const T *V;                   // [4][g][g]
@@ -104,13 +107,14 @@ struct TzDev {
 // c + 16q, element v holding row 4q + v (f32) or q + 4v (f64).  Each lane loads VEC consecutive k of its row
 // (16 bytes) and feeds them to VEC successive instructions, so instruction s
 // multiplies k = k0 + VEC q + s for q = 0..3 -- the same set for A and B.
-template <typename T>
-__global__ __launch_bounds__(512) void tz_prop(TzDev<T> D, int j, int ntiles, int nchunks) {
+template <typename T, int NTM>
+__global__ __launch_bounds__(512, (sizeof(T) == 4 && NTM == 3) ? 4 : 2) void tz_prop(TzDev<T> D, int j, int ntiles, int nchunks,
+                                                                                  int kc, const int *chunk_tiles) {
   using M = Mf<T>;
   constexpr int VEC = M::VEC, KS = 4 * VEC;
   int b = blockIdx.x, c = 0;
   for (; c < nchunks - 1; c++) {  // chunk-major: chunk c holds the tiles that reach it
-    const int cnt = min(ntiles, D.chunk_tiles[c]);
+    const int cnt = min(ntiles, chunk_tiles[c]);
     if (b < cnt) break;
     b -= cnt;
   }
@@ -118,64 +122,77 @@ __global__ __launch_bounds__(512) void tz_prop(TzDev<T> D, int j, int ntiles, in
   const int R = D.off[j], w = D.g * D.sig[j], ntn = (w + 15) >> 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, q = lane >> 4;
   const int r0 = t * TZ_TM;
-  const int kb = max(c * TZ_KC + wave * TZ_KW, D.tile_kmin[t]) & ~(KS - 1);
-  const int ke = min(c * TZ_KC + (wave + 1) * TZ_KW, R);
+  const int kw = kc / TZ_PW;  // k range of each wave
+  const int kb = max(c * kc + wave * kw, D.tile_kmin[t]) & ~(KS - 1);
+  const int ke = min(c * kc + (wave + 1) * kw, R);
   int kst[4];
-  const T *arow[4];
+  // one row pointer per lane for A and one for B; the other row tiles sit a
+  // uniform 16 rows further on
+  const size_t s16 = (size_t)16 * D.ld;
+  const T *arow0 = D.Q + (size_t)(r0 + li) * D.ld;
+  const T *brow0 = D.Q + (size_t)(R + li) * D.ld;
 #pragma unroll
   for (int m = 0; m < 4; m++) {
     const int row = r0 + 16 * m + li;
     kst[m] = row < R ? D.rstart[row] : INT_MAX;
-    arow[m] = D.Q + (size_t)row * D.ld;
   }
-  const T *brow[4];
-  bool bok[4];
-#pragma unroll
-  for (int nn = 0; nn < 4; nn++) {
-    const int col = 16 * nn + li;
-    bok[nn] = col < w;
-    brow[nn] = D.Q + (size_t)(R + col) * D.ld;
-  }
-  typename M::acc_t acc[4][4];
+  typename M::acc_t acc[4][NTM];
 #pragma unroll
   for (int m = 0; m < 4; m++)
 #pragma unroll
-    for (int nn = 0; nn < 4; nn++) acc[m][nn] = typename M::acc_t{0, 0, 0, 0};
+    for (int nn = 0; nn < NTM; nn++) acc[m][nn] = typename M::acc_t{0, 0, 0, 0};
   // rows own k from their block's start: steps below the tile's last start,
   // and the step reaching the chunk end, are masked; the rest are not
   const int kfull = D.rstart[min(r0 + TZ_TM, R) - 1];
-  typename M::ld_t a[4], bv[4], an[4], bn[4];
   auto load = [&](typename M::ld_t *A_, typename M::ld_t *B_, int k0) {
     const int kk = k0 + VEC * q;
 #pragma unroll
-    for (int m = 0; m < 4; m++) A_[m] = *reinterpret_cast<const typename M::ld_t *>(arow[m] + kk);
+    for (int m = 0; m < 4; m++) A_[m] = *reinterpret_cast<const typename M::ld_t *>(arow0 + m * s16 + kk);
 #pragma unroll
-    for (int nn = 0; nn < 4; nn++)
-      if (nn < ntn) B_[nn] = *reinterpret_cast<const typename M::ld_t *>(brow[nn] + kk);
+    for (int nn = 0; nn < NTM; nn++)
+      if (nn < ntn) B_[nn] = *reinterpret_cast<const typename M::ld_t *>(brow0 + nn * s16 + kk);
   };
-  load(a, bv, kb);
-  for (int k0 = kb; k0 < ke; k0 += KS) {
-    if (k0 + KS < ke) load(an, bn, k0 + KS);  // next step's operands in flight during this one
+  // B columns past w are rows of later positions, still zero when this
+  // column runs (their folds come later), so only the triangle's first steps
+  // and the chunk's last step need masks
+  auto compute = [&](const typename M::ld_t *A_, const typename M::ld_t *B_, int k0) {
+    if (k0 >= kfull && k0 + KS <= ke) {
+#pragma unroll
+      for (int s = 0; s < VEC; s++)
+#pragma unroll
+        for (int nn = 0; nn < NTM; nn++)
+          if (nn < ntn)
+#pragma unroll
+            for (int m = 0; m < 4; m++) acc[m][nn] = M::mac(A_[m][s], B_[nn][s], acc[m][nn]);
+      return;
+    }
     const int kk = k0 + VEC * q;
-    const bool edge = k0 < kfull || k0 + KS > ke;
 #pragma unroll
     for (int s = 0; s < VEC; s++) {
       const int k = kk + s;
-      T av[4], bs[4];
+      T av[4], bs[NTM];
 #pragma unroll
-      for (int m = 0; m < 4; m++) av[m] = (!edge || (k >= kst[m] && k < ke)) ? a[m][s] : T(0);
+      for (int m = 0; m < 4; m++) av[m] = (k >= kst[m] && k < ke) ? A_[m][s] : T(0);
 #pragma unroll
-      for (int nn = 0; nn < 4; nn++) bs[nn] = (nn < ntn && bok[nn] && (!edge || k < ke)) ? bv[nn][s] : T(0);
+      for (int nn = 0; nn < NTM; nn++) bs[nn] = k < ke ? B_[nn][s] : T(0);
 #pragma unroll
-      for (int nn = 0; nn < 4; nn++)
+      for (int nn = 0; nn < NTM; nn++)
         if (nn < ntn)
 #pragma unroll
           for (int m = 0; m < 4; m++) acc[m][nn] = M::mac(av[m], bs[nn], acc[m][nn]);
     }
-#pragma unroll
-    for (int m = 0; m < 4; m++) a[m] = an[m];
-#pragma unroll
-    for (int nn = 0; nn < 4; nn++) bv[nn] = bn[nn];
+  };
+  // operands of two steps in flight: a ring of two register stages (a third
+  // stage measured slower: fewer waves fit the registers)
+  typename M::ld_t a0[4], b0[NTM], a1[4], b1[NTM];
+  if (kb < ke) load(a0, b0, kb);  // a wave whose range lies past the column loads nothing
+  if (kb + KS < ke) load(a1, b1, kb + KS);
+  for (int k0 = kb; k0 < ke; k0 += 2 * KS) {
+    compute(a0, b0, k0);
+    if (k0 + 2 * KS < ke) load(a0, b0, k0 + 2 * KS);
+    if (k0 + KS >= ke) break;
+    compute(a1, b1, k0 + KS);
+    if (k0 + 3 * KS < ke) load(a1, b1, k0 + 3 * KS);
   }
   // the eight sums meet through LDS in a fixed tree: w += w + 4 (w < 4),
   // then wave 0 adds waves 1, 2, 3 in order
@@ -185,21 +202,21 @@ __global__ __launch_bounds__(512) void tz_prop(TzDev<T> D, int j, int ntiles, in
 #pragma unroll
     for (int m = 0; m < 4; m++)
 #pragma unroll
-      for (int nn = 0; nn < 4; nn++)
+      for (int nn = 0; nn < NTM; nn++)
         if (nn < ntn) red[(((wave - 4) * 4 + m) * ntn + nn) * 64 + lane] = acc[m][nn];
   __syncthreads();
   if (wave < 4)
 #pragma unroll
     for (int m = 0; m < 4; m++)
 #pragma unroll
-      for (int nn = 0; nn < 4; nn++)
+      for (int nn = 0; nn < NTM; nn++)
         if (nn < ntn) acc[m][nn] += red[((wave * 4 + m) * ntn + nn) * 64 + lane];
   __syncthreads();
   if (wave >= 1 && wave < 4)
 #pragma unroll
     for (int m = 0; m < 4; m++)
 #pragma unroll
-      for (int nn = 0; nn < 4; nn++)
+      for (int nn = 0; nn < NTM; nn++)
         if (nn < ntn) red[(((wave - 1) * 4 + m) * ntn + nn) * 64 + lane] = acc[m][nn];
   __syncthreads();
   if (wave != 0) return;
@@ -207,13 +224,13 @@ __global__ __launch_bounds__(512) void tz_prop(TzDev<T> D, int j, int ntiles, in
 #pragma unroll
     for (int m = 0; m < 4; m++)
 #pragma unroll
-      for (int nn = 0; nn < 4; nn++)
+      for (int nn = 0; nn < NTM; nn++)
         if (nn < ntn) acc[m][nn] += red[(((wv - 1) * 4 + m) * ntn + nn) * 64 + lane];
   T *P = D.P + (size_t)c * D.prow * TZ_WMAX;
 #pragma unroll
   for (int m = 0; m < 4; m++)
 #pragma unroll
-    for (int nn = 0; nn < 4; nn++)
+    for (int nn = 0; nn < NTM; nn++)
       if (nn < ntn)
 #pragma unroll
         for (int v = 0; v < 4; v++) {
@@ -224,8 +241,8 @@ __global__ __launch_bounds__(512) void tz_prop(TzDev<T> D, int j, int ntiles, in
 
 // sum of the partials of row r, column col of the last propagated column
 template <typename T>
-__device__ inline T col_sum(const TzDev<T> &D, int r, int col, int nchunks) {
-  const int cf = D.tile_kmin[r / TZ_TM] / TZ_KC;
+__device__ inline T col_sum(const TzDev<T> &D, int r, int col, int nchunks, int kc) {
+  const int cf = D.tile_kmin[r / TZ_TM] / kc;
   T y = T(0);
   const T *p = D.P + (size_t)r * TZ_WMAX + col;
   const size_t cs = (size_t)D.prow * TZ_WMAX;
@@ -242,13 +259,14 @@ __device__ inline T col_sum(const TzDev<T> &D, int r, int col, int nchunks) {
 // the same for four entries at once (rows r[u], columns col[u], skipped where
 // ok[u] is false): up to 32 loads in flight, each sum in chunk order
 template <typename T>
-__device__ inline void col_sum4(const TzDev<T> &D, const int *r, const int *col, const bool *ok, int nchunks, T *y) {
+__device__ inline void col_sum4(const TzDev<T> &D, const int *r, const int *col, const bool *ok, int nchunks, int kc,
+                                T *y) {
   const size_t cs = (size_t)D.prow * TZ_WMAX;
   int cf[4], cmin = nchunks;
   const T *p[4];
 #pragma unroll
   for (int u = 0; u < 4; u++) {
-    cf[u] = ok[u] ? D.tile_kmin[r[u] / TZ_TM] / TZ_KC : nchunks;
+    cf[u] = ok[u] ? D.tile_kmin[r[u] / TZ_TM] / kc : nchunks;
     cmin = min(cmin, cf[u]);
     p[u] = D.P + (size_t)(ok[u] ? r[u] : 0) * TZ_WMAX + (ok[u] ? col[u] : 0);
     y[u] = T(0);
@@ -286,7 +304,7 @@ __device__ inline T wave_max(T v) {
 // exponent of column jc's factor: binary exponent of the largest entry of its
 // row-0 block (rows 0..g-1), summed from the partials (one wave)
 template <typename T>
-__device__ inline int column_exponent(const TzDev<T> &D, int jc, int nchunks) {
+__device__ inline int column_exponent(const TzDev<T> &D, int jc, int nchunks, int kc) {
   const int w = D.g * D.sig[jc];
   T mx = T(0);
   for (int e0 = threadIdx.x & 63; e0 < D.g * w; e0 += 256) {
@@ -300,7 +318,7 @@ __device__ inline int column_exponent(const TzDev<T> &D, int jc, int nchunks) {
       r[u] = e / w;
       cc[u] = e % w;
     }
-    col_sum4(D, r, cc, ok, nchunks, y);
+    col_sum4(D, r, cc, ok, nchunks, kc, y);
 #pragma unroll
     for (int u = 0; u < 4; u++) mx = max(mx, y[u]);
   }
@@ -309,58 +327,81 @@ __device__ inline int column_exponent(const TzDev<T> &D, int jc, int nchunks) {
 }
 
 // ---- fold: finish column j-1, build row block j --------------------------
+// One 256-thread workgroup per item q < j: block row q of column j-1 and the
+// element E_{q-1,j} (and, for q = j-1, the unpaired base j-1 as well).
 // STAGE: the model (S B, B, V) is copied to LDS first; without it (when it
-// does not fit beside the per-wave arrays) the waves read it from memory.
+// does not fit beside the item's arrays) the threads read it from memory.
 template <typename T, bool STAGE>
-__global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_prev) {
+__global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_prev, int kc_prev) {
   extern __shared__ __align__(16) unsigned char tz_lds[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int g = D.g, xi = D.xi, G4 = 4 * g;
-  const int qi = blockIdx.x * 4 + wave;  // item: block row qi of column j-1, element k = qi - 1
-  const int wstride = G4 * G4 + 2 * xi * 256 + 192;  // Xs, t, U, two cores, combination list
-  T *Xs = reinterpret_cast<T *>(tz_lds) + (size_t)wave * wstride;
-  T *ts = Xs + G4 * G4;  // [combination][sigma_b][sigma_e]
-  T *Us = ts + xi * 256; // [combination][sigma_k][sigma_j]
-  // the model, shared by the four waves: S B, B, V
+  const int qi = blockIdx.x;  // block row qi of column j-1, element k = qi - 1
+  T *Xs = reinterpret_cast<T *>(tz_lds);  // [g Sigma_q][g Sigma_{j-1}]
+  T *ts = Xs + G4 * G4;                  // [combination][sigma_b][sigma_e]
+  T *Us = ts + xi * 256;                 // [combination][sigma_k][sigma_j]
+  T *tk = Us + xi * 256, *tl = tk + 64;  // cores of the element's two ends
+  int *cmb = reinterpret_cast<int *>(tl + 64);
+  __shared__ int e_prev, ncmb;
+  __shared__ T red[4];
   const T *sSB = D.SB, *sB = D.B, *sV = D.V;
   if (STAGE) {
-    T *l = reinterpret_cast<T *>(tz_lds) + (size_t)4 * wstride;
-    for (int e = threadIdx.x; e < xi * 16 * g * g; e += TZ_FT) {
+    T *l = tk + 192;
+    for (int e = tid; e < xi * 16 * g * g; e += TZ_FT) {
       l[e] = D.SB[e];
       l[xi * 16 * g * g + e] = D.B[e];
     }
-    for (int e = threadIdx.x; e < 4 * g * g; e += TZ_FT) l[2 * xi * 16 * g * g + e] = D.V[e];
+    for (int e = tid; e < 4 * g * g; e += TZ_FT) l[2 * xi * 16 * g * g + e] = D.V[e];
     sSB = l;
     sB = l + (size_t)xi * 16 * g * g;
     sV = l + (size_t)2 * xi * 16 * g * g;
   }
-  __shared__ int e_prev;
-  if (wave == 0) {
-    const int e = j >= 2 ? column_exponent(D, j - 1, nchunks_prev) : 0;
-    if (lane == 0) {
-      e_prev = e;
-      if (blockIdx.x == 0 && j >= 2) D.colexp[j - 1] = e;
-    }
-  }
-  __syncthreads();
-  const bool live = qi < j;
-  const int wp = g * D.sig[j - 1];  // width of column j-1
-  // 1. finish block row qi of column j-1
-  if (live && qi < j - 1) {
-    const int r0 = D.off[qi], rows = g * D.sig[qi];
-    const size_t cbase = (size_t)D.off[j - 1];
-    for (int e0 = lane; e0 < rows * wp; e0 += 256) {
+  // 0. exponent of column j-1: the largest entry of its row-0 block
+  if (j >= 2) {
+    const int w0 = g * D.sig[j - 1];
+    T mx = T(0);
+    {
       int r[4], cc[4];
       bool ok[4];
       T y[4];
 #pragma unroll
       for (int u = 0; u < 4; u++) {
-        const int e = e0 + 64 * u;
-        ok[u] = e < rows * wp;
-        r[u] = r0 + e / wp;
-        cc[u] = e % wp;
+        const int e = tid + TZ_FT * u;
+        ok[u] = e < g * w0;
+        r[u] = ok[u] ? e / w0 : 0;
+        cc[u] = ok[u] ? e % w0 : 0;
       }
-      col_sum4(D, r, cc, ok, nchunks_prev, y);
+      col_sum4(D, r, cc, ok, nchunks_prev, kc_prev, y);  // g * w0 <= 1024 entries
+#pragma unroll
+      for (int u = 0; u < 4; u++) mx = max(mx, y[u]);
+    }
+    mx = wave_max(mx);
+    if (lane == 0) red[wave] = mx;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int e = j >= 2 ? exp_of((double)max(max(red[0], red[1]), max(red[2], red[3]))) : 0;
+    e_prev = e;
+    if (qi == 0 && j >= 2) D.colexp[j - 1] = e;
+  }
+  __syncthreads();
+  const int wp = g * D.sig[j - 1];  // width of column j-1
+  // 1. finish block row qi of column j-1
+  if (qi < j - 1) {
+    const int r0 = D.off[qi], rows = g * D.sig[qi];
+    const size_t cbase = (size_t)D.off[j - 1];
+    for (int e0 = tid; e0 < rows * wp; e0 += 4 * TZ_FT) {
+      int r[4], cc[4];
+      bool ok[4];
+      T y[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int e = e0 + TZ_FT * u;
+        ok[u] = e < rows * wp;
+        r[u] = r0 + (ok[u] ? e / wp : 0);
+        cc[u] = ok[u] ? e % wp : 0;
+      }
+      col_sum4(D, r, cc, ok, nchunks_prev, kc_prev, y);
 #pragma unroll
       for (int u = 0; u < 4; u++)
         if (ok[u]) {
@@ -369,44 +410,40 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
           Xs[(r[u] - r0) * wp + cc[u]] = x;
         }
     }
-    if (qi == 0 && (j - 1) % 3 == 0) {  // codon boundary: Sigma = 1, a g x g block
-      T tr = T(0);
-      for (int e = lane; e < g * g; e += 64) {
-        const int x = e / g, y = e % g;
-        tr += D.S[x * g + y] * ldexp(col_sum(D, y, x, nchunks_prev), -e_prev);
-      }
-      tr = wave_sum(tr);
-      if (lane == 0) D.ptr[(j - 1) / 3 - 1] = (double)tr;
-    }
   }
-  __syncthreads();
   const int k = qi - 1, l = j - 1;
-  const bool pair = live && qi >= 1 && l - k >= 4;
+  const bool pair = qi >= 1 && l - k >= 4;
   const int sk = pair ? D.sig[k] : 0, sb = pair ? D.sig[k + 1] : 0, se = pair ? D.sig[l] : 0, sj = D.sig[j];
   // the cores of the element's ends and the (rho, phi_k, phi_l) that carry
   // weight (B nonzero, both bases possible), in (rho, phi_k, phi_l) order
-  T *tk = Us + xi * 256, *tl = tk + 64;
-  int *cmb = reinterpret_cast<int *>(tl + 64);
-  __shared__ int ncmb[4];
   if (pair) {
-    tk[lane] = D.tc[(size_t)k * 64 + lane];
-    tl[lane] = D.tc[(size_t)l * 64 + lane];
-    if (lane == 0) {
+    if (tid < 64) tk[tid] = D.tc[(size_t)k * 64 + tid];
+    else if (tid < 128) tl[tid - 64] = D.tc[(size_t)l * 64 + tid - 64];
+    if (tid == 128) {
       int na = 0;
       for (int rho = 0; rho < xi; rho++)
         for (int pk = 0; pk < 4; pk++)
           for (int pl = 0; pl < 4; pl++)
             if (((D.pairmask >> (4 * pk + pl)) & 1) && ((D.bmask[k] >> pk) & 1) && ((D.bmask[l] >> pl) & 1))
               cmb[na++] = (rho * 4 + pk) * 4 + pl;
-      ncmb[wave] = na;
+      ncmb = na;
     }
-  } else if (live && qi == j - 1) {
-    tk[lane] = D.tc[(size_t)(j - 1) * 64 + lane];
+  } else if (qi == j - 1 && tid < 64) {
+    tk[tid] = D.tc[(size_t)(j - 1) * 64 + tid];
   }
   __syncthreads();
-  const int na = pair ? ncmb[wave] : 0;
+  if (qi == 0 && (j - 1) % 3 == 0 && j >= 2 && wave == 0) {  // codon boundary: a g x g block, prefix trace
+    T tr = T(0);
+    for (int e = lane; e < g * g; e += 64) {
+      const int x = e / g, y = e % g;
+      tr += D.S[x * g + y] * Xs[y * wp + x];
+    }
+    tr = wave_sum(tr);
+    if (lane == 0) D.ptr[(j - 1) / 3 - 1] = (double)tr;
+  }
+  const int na = pair ? ncmb : 0;
   // 2a. t[a][sigma_b][sigma_e] = Tr[S B_{phi_l, phi_k} X^{sigma_b, sigma_e}] for combination a
-  for (int e = lane; e < na * 16; e += 64) {
+  for (int e = tid; e < na * 16; e += TZ_FT) {
     const int a = e >> 4, b = (e >> 2) & 3, ee = e & 3;
     T acc = T(0);
     if (b < sb && ee < se) {
@@ -419,7 +456,7 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
   }
   __syncthreads();
   // 2b. U[a][sigma_k][sigma_j] = (T_k^{phi_k} t T_l^{phi_l})[sigma_k][sigma_j]
-  for (int e = lane; e < na * 16; e += 64) {
+  for (int e = tid; e < na * 16; e += TZ_FT) {
     const int a = e >> 4, ak = (e >> 2) & 3, cc = e & 3;
     const int c3 = cmb[a], pk = (c3 >> 2) & 3, pl = c3 & 3;
     T u = T(0);
@@ -431,12 +468,12 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
   }
   __syncthreads();
   // 2c. E_{k,j} = 2^-e_k sum_a U[a] (x) B_{phi_k, phi_l}, stored transposed
-  if (live && qi >= 1) {
+  if (qi >= 1) {
     const int rows = g * D.sig[k], wj = g * sj;
     const size_t rbase = (size_t)D.off[j], cbase = (size_t)D.off[k];
     const int ek = pair ? D.colexp[k + 1] : 0;
-    for (int e = lane; e < rows * wj; e += 64) {
-      const int rr = e % rows, cc = e / rows;  // consecutive lanes along the stored row
+    for (int e = tid; e < rows * wj; e += TZ_FT) {
+      const int rr = e % rows, cc = e / rows;  // consecutive threads along the stored row
       const int ak = rr / g, za = rr % g, s2 = cc / g, zb = cc % g;
       T f = T(0);
       for (int a = 0; a < na; a++) f += Us[a * 16 + ak * 4 + s2] * sB[(size_t)cmb[a] * g * g + za * g + zb];
@@ -444,10 +481,10 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
     }
   }
   // 3. the unpaired base j-1
-  if (live && qi == j - 1) {
+  if (qi == j - 1) {
     const int sa = D.sig[j - 1], rows = g * sa, wj = g * sj;
     const size_t rbase = (size_t)D.off[j], cbase = (size_t)D.off[j - 1];
-    for (int e = lane; e < rows * wj; e += 64) {
+    for (int e = tid; e < rows * wj; e += TZ_FT) {
       const int rr = e % rows, cc = e / rows;
       const int a = rr / g, za = rr % g, s2 = cc / g, zb = cc % g;
       T f = T(0);
@@ -459,13 +496,13 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
 
 // after the last column: its exponent and Tr[S Q_{0,n}] (one wave)
 template <typename T>
-__global__ __launch_bounds__(64) void tz_final(TzDev<T> D, int nchunks) {
+__global__ __launch_bounds__(64) void tz_final(TzDev<T> D, int nchunks, int kc) {
   const int n = D.n, g = D.g;
-  const int e = column_exponent(D, n, nchunks);
+  const int e = column_exponent(D, n, nchunks, kc);
   T tr = T(0);
   for (int q = threadIdx.x; q < g * g; q += 64) {
     const int x = q / g, y = q % g;
-    tr += D.S[x * g + y] * ldexp(col_sum(D, y, x, nchunks), -e);
+    tr += D.S[x * g + y] * ldexp(col_sum(D, y, x, nchunks, kc), -e);
   }
   tr = wave_sum(tr);
   if (threadIdx.x == 0) {
@@ -494,17 +531,25 @@ struct DevBuf {
 
 struct TzHost {
   int n = 0, m = 0, N = 0, rows = 0, ld = 0, tiles = 0, chunks = 0;
-  std::vector<int> sig, off, rstart, tile_kmin, chunk_tiles;
+  std::vector<int> sig, off, rstart, tile_kmin;
+  std::vector<int> chunk_tiles;  // per chunk size: [chunks of that size] tiles whose first chunk is <= c
+  int ct_off[TZ_NKC] = {};       // start of each size's table in chunk_tiles
   std::vector<unsigned char> bmask;
   std::vector<double> tc;  // [n][4][4][4]
 };
 
-int nchunks_of(const TzHost &H, int j) { return (H.off[j] + TZ_KC - 1) / TZ_KC; }
+int kci_of(const TzHost &H, int j) {  // index of column j's chunk size
+  for (int i = 0; i < TZ_NKC; i++)
+    if ((H.off[j] + TZ_KCS[i] - 1) / TZ_KCS[i] <= TZ_MAXCH) return i;
+  return TZ_NKC - 1;
+}
+int kc_of(const TzHost &H, int j) { return TZ_KCS[kci_of(H, j)]; }
+int nchunks_of(const TzHost &H, int j) { return (H.off[j] + kc_of(H, j) - 1) / kc_of(H, j); }
 int ntiles_of(const TzHost &H, int j) { return (H.off[j] + TZ_TM - 1) / TZ_TM; }
 int prop_grid(const TzHost &H, int j) {
-  const int nt = ntiles_of(H, j), nc = nchunks_of(H, j);
+  const int nt = ntiles_of(H, j), nc = nchunks_of(H, j), base = H.ct_off[kci_of(H, j)];
   int tot = 0;
-  for (int c = 0; c < nc; c++) tot += c == nc - 1 ? nt : std::min(nt, H.chunk_tiles[c]);
+  for (int c = 0; c < nc; c++) tot += c == nc - 1 ? nt : std::min(nt, H.chunk_tiles[base + c]);
   return tot;
 }
 
@@ -540,7 +585,7 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   const size_t oQ = take((size_t)H.rows * H.ld * sizeof(T)),
                oP = take((size_t)H.chunks * H.rows * TZ_WMAX * sizeof(T)), oSig = take((n + 1) * 4),
                oOff = take((n + 1) * 4), oRs = take((size_t)H.rows * 4), oTk = take((size_t)H.tiles * 4),
-               oCt = take((size_t)H.chunks * 4), oBm = take(n), oTc = take(tc.size() * sizeof(T)),
+               oCt = take(H.chunk_tiles.size() * 4), oBm = take(n), oTc = take(tc.size() * sizeof(T)),
                oV = take(V.size() * sizeof(T)), oB = take(B.size() * sizeof(T)), oSB = take(SB.size() * sizeof(T)),
                oS = take(S.size() * sizeof(T)), oCe = take((n + 1) * 4), oPt = take((size_t)m * 8);
   DevBuf ws;
@@ -558,7 +603,7 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   HIPCHK(h, up(oOff, H.off.data(), (n + 1) * 4));
   HIPCHK(h, up(oRs, H.rstart.data(), (size_t)H.rows * 4));
   HIPCHK(h, up(oTk, H.tile_kmin.data(), (size_t)H.tiles * 4));
-  HIPCHK(h, up(oCt, H.chunk_tiles.data(), (size_t)H.chunks * 4));
+  HIPCHK(h, up(oCt, H.chunk_tiles.data(), H.chunk_tiles.size() * 4));
   HIPCHK(h, up(oBm, H.bmask.data(), n));
   HIPCHK(h, up(oTc, tc.data(), tc.size() * sizeof(T)));
   HIPCHK(h, up(oV, V.data(), V.size() * sizeof(T)));
@@ -575,7 +620,7 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   D.off = (const int *)(base + oOff);
   D.rstart = (const int *)(base + oRs);
   D.tile_kmin = (const int *)(base + oTk);
-  D.chunk_tiles = (const int *)(base + oCt);
+  const int *ct = (const int *)(base + oCt);
   D.bmask = (const unsigned char *)(base + oBm);
   D.tc = (const T *)(base + oTc);
   D.V = (const T *)(base + oV);
@@ -587,7 +632,7 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   D.P = (T *)(base + oP);
   D.colexp = (int *)(base + oCe);
   D.ptr = (double *)(base + oPt);
-  const size_t wave_lds = (size_t)4 * (16 * g * g + 2 * xi * 256 + 192) * sizeof(T);
+  const size_t wave_lds = (size_t)(16 * g * g + 2 * xi * 256 + 192) * sizeof(T);
   const size_t model_lds = (size_t)(2 * xi * 16 + 4) * g * g * sizeof(T);
   const bool stage = wave_lds + model_lds <= (size_t)h->lds_max;
   const size_t fold_lds = stage ? wave_lds + model_lds : wave_lds;
@@ -599,14 +644,21 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   HIPCHK(h, hipEventRecord(h->ev[0], st));
   tz_init<T><<<2048, 256, 0, st>>>(D.Q, (size_t)H.rows, (size_t)H.ld, (size_t)H.N);
   for (int j = 1; j <= n; j++) {
-    const int fgrid = (j + 3) / 4;
-    if (stage) tz_fold<T, true><<<fgrid, TZ_FT, fold_lds, st>>>(D, j, j >= 2 ? nchunks_of(H, j - 1) : 0);
-    else tz_fold<T, false><<<fgrid, TZ_FT, fold_lds, st>>>(D, j, j >= 2 ? nchunks_of(H, j - 1) : 0);
+    const int fgrid = j;
+    const int ncp = j >= 2 ? nchunks_of(H, j - 1) : 0, kcp = j >= 2 ? kc_of(H, j - 1) : TZ_KCS[0];
+    if (stage) tz_fold<T, true><<<fgrid, TZ_FT, fold_lds, st>>>(D, j, ncp, kcp);
+    else tz_fold<T, false><<<fgrid, TZ_FT, fold_lds, st>>>(D, j, ncp, kcp);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * (j - 1)], st));
-    tz_prop<T><<<prop_grid(H, j), 64 * TZ_PW, prop_lds, st>>>(D, j, ntiles_of(H, j), nchunks_of(H, j));
+    const int *ctj = ct + H.ct_off[kci_of(H, j)];
+    if (ntn_max <= 3)
+      tz_prop<T, 3><<<prop_grid(H, j), 64 * TZ_PW, prop_lds, st>>>(D, j, ntiles_of(H, j), nchunks_of(H, j),
+                                                                   kc_of(H, j), ctj);
+    else
+      tz_prop<T, 4><<<prop_grid(H, j), 64 * TZ_PW, prop_lds, st>>>(D, j, ntiles_of(H, j), nchunks_of(H, j),
+                                                                   kc_of(H, j), ctj);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * (j - 1) + 1], st));
   }
-  tz_final<T><<<1, 64, 0, st>>>(D, nchunks_of(H, n));
+  tz_final<T><<<1, 64, 0, st>>>(D, nchunks_of(H, n), kc_of(H, n));
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->ev[1], st));
   std::vector<double> ptr(m);
@@ -708,11 +760,18 @@ cdz_status finish_layout(cdz_handle *h, TzHost &H, int g, const cdz_tensor_model
   H.tiles = (H.N + TZ_TM - 1) / TZ_TM;
   H.tile_kmin.resize(H.tiles);
   for (int ti = 0; ti < H.tiles; ti++) H.tile_kmin[ti] = H.rstart[ti * TZ_TM];
-  H.chunks = (H.N + TZ_KC - 1) / TZ_KC;
-  H.chunk_tiles.assign(H.chunks, 0);
-  for (int c = 0; c < H.chunks; c++)
-    for (int ti = 0; ti < H.tiles; ti++)
-      if (H.tile_kmin[ti] / TZ_KC <= c) H.chunk_tiles[c]++;
+  H.chunk_tiles.clear();
+  for (int i = 0; i < TZ_NKC; i++) {
+    const int kc = TZ_KCS[i], nch = (H.N + kc - 1) / kc;
+    H.ct_off[i] = (int)H.chunk_tiles.size();
+    for (int c = 0; c < nch; c++) {
+      int cnt = 0;
+      for (int ti = 0; ti < H.tiles; ti++) cnt += H.tile_kmin[ti] / kc <= c;
+      H.chunk_tiles.push_back(cnt);
+    }
+  }
+  H.chunks = 1;  // partial-sum slots: the most chunks any column uses
+  for (int j = 1; j <= n; j++) H.chunks = std::max(H.chunks, nchunks_of(H, j));
   if (h->opt.prec == CDZ_FP64) return run_tensor<double>(h, H, md, log_z, prefix);
   return run_tensor<float>(h, H, md, log_z, prefix);
 }
