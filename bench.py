@@ -120,7 +120,9 @@ KERNEL_SOURCES = {
     "out": ["paper_2604_19718_amd/csrc/cdz_out.hip", "paper_2604_19718_amd/csrc/cdz_internal.h",
             "paper_2604_19718_amd/csrc/cdz_dev.h", "include/cdz.h"],
     "fwd": ["paper_2604_19718_amd/csrc/cdz_fwd.hip", "paper_2604_19718_amd/csrc/cdz_dev.h"],
+    "tensor": ["paper_2604_19718_amd/csrc/cdz_tensor.hip"],
 }
+TENSOR_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "tz_prop_float_900nt_traffic.md")
 
 
 def source_sha256(kernel: str = "out") -> str:
@@ -135,14 +137,14 @@ def source_sha256(kernel: str = "out") -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per outside diagonal launch from the committed rocprofv3 FETCH_SIZE and
+def measured_traffic(kernel: str = "out", path: str = TRAFFIC_PROFILE):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE and
     WRITE_SIZE runs (scaled by a copy kernel of known size), or None when those counters
     were taken on other kernel sources."""
     try:
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(path) as fh:
             kv = dict(line.split(": ", 1) for line in fh.read().splitlines() if ": " in line and not line.startswith(("|", "`", "#")))
-        if kv.get("source_sha256", "").strip() != source_sha256():
+        if kv.get("source_sha256", "").strip() != source_sha256(kernel):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -239,7 +241,10 @@ def tensor_leg(B, I, h32, h64, steps):
     byt, flo = tensor_prop_algorithmic(sig, 9, 4)
     ach = byt / launches / (avg / 1e3) / 1e9
     out["roofline"] = {"kernel": "tz_prop<float>", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "launches": launches, "avg_launch_ms": avg,
+                       "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                       "traffic": measured_traffic("tensor", TENSOR_TRAFFIC_PROFILE),
+                       "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                       "launches": launches, "avg_launch_ms": avg,
                        "algorithmic_bytes_per_launch": byt / launches,
                        "mfma_tflops": flo / (avg * launches / 1e3) / 1e12,
                        "mfma_frac": flo / (avg * launches / 1e3) / 1e12 / MFMA_FP32_PEAK_TFS,
