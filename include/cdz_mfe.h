@@ -39,6 +39,29 @@ extern "C" {
  * CDZ_ERR_HIP. */
 cdz_status cdz_mfe(cdz_handle *h, const cdz_problem *prob, double *mfe, uint8_t *codons, int32_t *pairs);
 
+/* Suboptimal states (SI S4d, Alg. subopt): every (codon assignment,
+ * structure) whose energy is at most MFE + gap, in FP64 on the handle's
+ * device and stream.
+ *   gap         >= 0 (kT); the threshold is MFE + gap + 1e-9 max(1, |MFE|).
+ *               The single argmin (the paper's gap < 0) is cdz_mfe.
+ *   max_states  capacity of the outputs; with more states than that the first
+ *               max_states are returned and *more is set.
+ *   mfe         host double: the minimum.
+ *   energies    [max_states] host doubles or NULL: each state's energy (kT).
+ *   codons      [max_states][n_aa] host bytes or NULL: codon slots.
+ *   pairs       [max_states][n] host int32 or NULL: partner per position, -1
+ *               unpaired.
+ *   count       host int32: states written.  more: host int32 or NULL.
+ * States come in a fixed order (a depth-first search over the traceback's
+ * decisions in the order documented for cdz_mfe), each exactly once.  The
+ * workspace of cdz_mfe plus the search's (up to 2^20 pending alternatives of
+ * 112 bytes, the outputs) is allocated for the call.  Errors: CDZ_ERR_ARG (a
+ * negative or non-finite gap, max_states < 0), CDZ_ERR_PROTEIN,
+ * CDZ_ERR_NUMERIC, CDZ_ERR_NOMEM, CDZ_ERR_BUDGET (more pending alternatives
+ * than the search holds: lower the gap), CDZ_ERR_HIP. */
+cdz_status cdz_subopt(cdz_handle *h, const cdz_problem *prob, double gap, int32_t max_states, double *mfe,
+                      double *energies, uint8_t *codons, int32_t *pairs, int32_t *count, int32_t *more);
+
 #ifdef __cplusplus
 }
 #endif

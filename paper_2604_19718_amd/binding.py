@@ -24,7 +24,7 @@ EXPORTS = ["cdz_create", "cdz_destroy", "cdz_partition", "cdz_marginals", "cdz_s
            "cdz_forward_dev", "cdz_backward_dev", "cdz_last_timings", "cdz_reset",
            "cdz_set_profiling", "cdz_kernel_timings", "cdz_status_string", "cdz_last_error",
            "cdz_batch", "cdz_partition_batch", "cdz_marginals_batch", "cdz_sample_batch",
-           "cdz_workspace_bytes", "cdz_match_frequencies", "cdz_mfe", "cdz_tensor_logz",
+           "cdz_workspace_bytes", "cdz_match_frequencies", "cdz_mfe", "cdz_subopt", "cdz_tensor_logz",
            "cdz_tensor_dims"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -100,6 +100,9 @@ def lib():
             "cdz_tensor_logz": ([vp, ctypes.POINTER(cdz_tensor_model), ctypes.POINTER(cdz_problem), _dp, _dp],
                                 ctypes.c_int),
             "cdz_tensor_dims": ([ctypes.POINTER(cdz_problem), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "cdz_subopt": ([vp, ctypes.POINTER(cdz_problem), ctypes.c_double, ctypes.c_int32, _dp, _dp,
+                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
+                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_mfe": ([vp, ctypes.POINTER(cdz_problem), _dp, ctypes.POINTER(ctypes.c_uint8),
                          ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "cdz_match_frequencies": ([vp, ctypes.POINTER(cdz_problem), _dp, ctypes.c_double, ctypes.c_int32,
@@ -217,6 +220,27 @@ def cdz_mfe(h: Handle, prob, traceback: bool = True):
                           None if cod is None else cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                           None if pairs is None else pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return float(out[0]), cod, pairs
+
+
+def cdz_subopt(h: Handle, prob, gap: float, max_states: int = 10000):
+    """Every state within gap (kT) of the minimum free energy: (mfe,
+    energies [k], codon slots [k, n_aa] uint8, pair tables [k, n] int32,
+    complete), complete False when more than max_states states exist."""
+    p = _Prob(prob)
+    m, n = len(prob.prot), 3 * len(prob.prot)
+    cap = max(int(max_states), 1)
+    out = np.zeros(1)
+    en = np.zeros(cap)
+    cod = np.zeros((cap, m), np.uint8)
+    pairs = np.zeros((cap, n), np.int32)
+    cnt = ctypes.c_int32(0)
+    more = ctypes.c_int32(0)
+    h.check(lib().cdz_subopt(h.ptr, ctypes.byref(p.c), float(gap), int(max_states), _arr(out), _arr(en),
+                             cod.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                             pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(cnt),
+                             ctypes.byref(more)))
+    k = cnt.value
+    return float(out[0]), en[:k].copy(), cod[:k].copy(), pairs[:k].copy(), more.value == 0
 
 
 def cdz_tensor_logz(h: Handle, model, prob):

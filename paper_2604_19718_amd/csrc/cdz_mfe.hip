@@ -831,6 +831,447 @@ __global__ __launch_bounds__(MT) void mfe_traceback(MfeDev D) {
   }
 }
 
+// ---- suboptimal enumeration (SI S4d) ------------------------------------
+// Every state within gap of the minimum, by a depth-first search over the
+// traceback's decisions.  A partial state is a stack of pending fragments and
+// a bound: the energy decided so far plus the minimum (the DP entry) of every
+// pending fragment.  Expanding fragment f by an alternative of value V (its
+// own energy plus the entries of the fragments it leaves) gives the bound
+// (bound - entry(f)) + V; alternatives whose bound exceeds the threshold are
+// dropped, the others are tried in the traceback's order.  One workgroup runs
+// the search: thread 0 keeps the levels, and all threads evaluate a
+// fragment's candidate alternatives, kept in enumeration order by a
+// workgroup prefix sum.  A pair's windows are first screened at the level of
+// their outer slots (the window's minimum is a lower bound of its children).
+
+struct SubAlt {
+  double V;
+  int nsub, nas;
+  int sub[3][5];
+  int as[3][3];  // position, slot, partner (-1 unpaired)
+};
+struct SubLevel {
+  int f[5];  // fragment expanded here (kind -1 at the root)
+  int flen0;  // pending length after f was taken off
+  int a0, na, next;
+  double b0;  // bound before f was expanded
+};
+struct SubDev {
+  double thr;
+  int max_states, cap_alts, cap_lv;
+  SubAlt *alts;
+  SubLevel *lv;
+  int *pend;          // [cap_lv][5]
+  int *pk;            // [n + 1] prefix sums of d[k-1] d[k] over k (k >= 1)
+  int *wlist;         // [496 * 36] screened (window, a, dd) of the pair being expanded
+  double *energies;   // [max_states]
+  unsigned char *codons;  // [max_states][m]
+  int *pairs;         // [max_states][n]
+  int *status;        // [0] states, [1] 0 done / 1 more states / 2 alternatives / 3 levels / 4 inconsistent
+};
+
+__device__ double frag_entry(const MfeDev &D, const int *f) {
+  const int n = D.n, i = f[1], j = f[2], s = f[3], s2 = f[4];
+  switch (f[0]) {
+    case K_EXT: return D.Z5[i * 6 + s];
+    case K_PAIR: return cblk(D.Qb, n, i, j)[s * 6 + s2];
+    case K_RUN: return cblk(D.U, n, i, j)[s * 6 + s2];
+    case K_QM1: return cblk(D.Qm1, n, i, j)[s * 6 + s2];
+    case K_QM1P: return cblk(D.Qm1p, n, i, j)[s * 6 + s2];
+    case K_QM: return cblk(D.Qm, n, i, j)[s * 6 + s2];
+    default: return cblk(D.QmX, n, i, j)[s * 6 + s2];
+  }
+}
+
+__device__ __forceinline__ void alt_sub(SubAlt &a, int kind, int i, int j, int s, int s2) {
+  int *q = a.sub[a.nsub++];
+  q[0] = kind;
+  q[1] = i;
+  q[2] = j;
+  q[3] = s;
+  q[4] = s2;
+}
+__device__ __forceinline__ void alt_as(SubAlt &a, int p, int s, int partner) {
+  a.as[a.nas][0] = p;
+  a.as[a.nas][1] = s;
+  a.as[a.nas][2] = partner;
+  a.nas++;
+}
+
+// exclusive prefix of one flag per thread over the workgroup; returns the total
+__device__ int block_scan(bool flag, int &pos, int *wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const unsigned long long m = __ballot(flag);
+  const int below = __popcll(m & ((1ull << lane) - 1ull));
+  __syncthreads();
+  if (lane == 0) wsum[w] = __popcll(m);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int q = 0; q < MT / 64; q++) {
+    if (q < w) off += wsum[q];
+    tot += wsum[q];
+  }
+  pos = off + below;
+  __syncthreads();
+  return tot;
+}
+
+// append, in index order, the candidates idx < cnt that gen() builds and
+// whose bound base + V stays within the threshold
+template <typename G>
+__device__ void emit(const SubDev &S, int cnt, double base, G gen, int *wsum, int *nalts) {
+  for (int c0 = 0; c0 < cnt; c0 += MT) {
+    const int idx = c0 + (int)threadIdx.x;
+    SubAlt a;
+    a.nsub = a.nas = 0;
+    bool pass = false;
+    if (idx < cnt) {
+      gen(idx, a);
+      pass = base + a.V <= S.thr;
+    }
+    int pos;
+    const int tot = block_scan(pass, pos, wsum);
+    const int at = *nalts;
+    if (pass && at + pos < S.cap_alts) S.alts[at + pos] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) *nalts = at + tot;
+    __syncthreads();
+  }
+}
+
+// index of the last k with pk[k] <= idx, searching k in [lo, hi)
+__device__ __forceinline__ int pk_find(const int *pk, int lo, int hi, int idx) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pk[mid] <= idx) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ void sub_alternatives(const MfeDev &D, const SubDev &S, const int *f, double base, int *wsum, int *nalts,
+                                 int *wcount) {
+  const int n = D.n, kind = f[0], i = f[1], j = f[2], s = f[3], s2 = f[4];
+  if (kind == K_EXT) {
+    const int jj = i, t = s;
+    if (jj == 0) {
+      emit(S, 1, base, [&](int, SubAlt &a) {
+        a.V = D.Z5[t];
+        alt_as(a, 0, t, -1);
+      }, wsum, nalts);
+      return;
+    }
+    const int c1 = D.d[jj - 1], c2 = jj >= 4 ? D.d[0] : 0;
+    const int c3 = jj >= 5 ? S.pk[jj - 3] - S.pk[1] : 0;  // k = 1..jj-4
+    emit(S, c1 + c2 + c3, base, [&](int idx, SubAlt &a) {
+      if (idx < c1) {
+        const int sp = idx;
+        a.V = (D.Z5[(jj - 1) * 6 + sp] + E(D, jj - 1, sp, t)) + D.v[jj * 6 + t];
+        alt_as(a, jj, t, -1);
+        alt_sub(a, K_EXT, jj - 1, 0, sp, 0);
+      } else if (idx < c1 + c2) {
+        const int x = idx - c1;
+        a.V = cblk(D.Qb, n, 0, jj)[x * 6 + t];
+        alt_sub(a, K_PAIR, 0, jj, x, t);
+      } else {
+        const int r = idx - c1 - c2 + S.pk[1];
+        const int k = pk_find(S.pk, 1, jj - 3, r), q = r - S.pk[k];
+        const int sp = q / D.d[k], x = q % D.d[k];
+        a.V = D.Z5[(k - 1) * 6 + sp] + E(D, k - 1, sp, x) + cblk(D.Qb, n, k, jj)[x * 6 + t];
+        alt_sub(a, K_EXT, k - 1, 0, sp, 0);
+        alt_sub(a, K_PAIR, k, jj, x, t);
+      }
+    }, wsum, nalts);
+    return;
+  }
+  if (kind == K_RUN) {
+    if (i == j) {
+      emit(S, 1, base, [&](int, SubAlt &a) {
+        a.V = cblk(D.U, n, i, i)[s * 6 + s2];
+        alt_as(a, i, s2, -1);
+      }, wsum, nalts);
+      return;
+    }
+    emit(S, D.d[j - 1], base, [&](int c, SubAlt &a) {
+      a.V = (cblk(D.U, n, i, j - 1)[s * 6 + c] + E(D, j - 1, c, s2)) + D.v[j * 6 + s2];
+      alt_as(a, j, s2, -1);
+      alt_sub(a, K_RUN, i, j - 1, s, c);
+    }, wsum, nalts);
+    return;
+  }
+  if (kind == K_QM1) {
+    emit(S, 1 + D.d[j - 1], base, [&](int idx, SubAlt &a) {
+      if (idx == 0) {
+        a.V = cblk(D.Qb, n, i, j)[s * 6 + s2] + D.ml_b;
+        alt_sub(a, K_PAIR, i, j, s, s2);
+      } else {
+        const int t = idx - 1;
+        a.V = (cblk(D.Qm1, n, i, j - 1)[s * 6 + t] + E(D, j - 1, t, s2)) + D.v[j * 6 + s2] + D.ml_c;
+        alt_as(a, j, s2, -1);
+        alt_sub(a, K_QM1, i, j - 1, s, t);
+      }
+    }, wsum, nalts);
+    return;
+  }
+  if (kind == K_QM1P) {
+    emit(S, 1 + D.d[i + 1], base, [&](int idx, SubAlt &a) {
+      if (idx == 0) {
+        a.V = cblk(D.Qm1, n, i, j)[s * 6 + s2];
+        alt_sub(a, K_QM1, i, j, s, s2);
+      } else {
+        const int t = idx - 1;
+        a.V = D.v[i * 6 + s] + D.ml_c + (E(D, i, s, t) + cblk(D.Qm1p, n, i + 1, j)[t * 6 + s2]);
+        alt_as(a, i, s, -1);
+        alt_sub(a, K_QM1P, i + 1, j, t, s2);
+      }
+    }, wsum, nalts);
+    return;
+  }
+  if (kind == K_QM || kind == K_QMX) {
+    // splits u = i+5 .. j-4 by (slot t of u-1, slot t2 of u), then (Qm only) Qm1p
+    const int cs = j - 4 >= i + 5 ? S.pk[j - 3] - S.pk[i + 5] : 0;
+    emit(S, cs + (kind == K_QM ? 1 : 0), base, [&](int idx, SubAlt &a) {
+      if (idx < cs) {
+        const int r = idx + S.pk[i + 5];
+        const int u = pk_find(S.pk, i + 5, j - 3, r), q = r - S.pk[u];
+        const int t = q / D.d[u], t2 = q % D.d[u];
+        a.V = cblk(D.Qm, n, i, u - 1)[s * 6 + t] + E(D, u - 1, t, t2) + cblk(D.Qm1, n, u, j)[t2 * 6 + s2];
+        alt_sub(a, K_QM, i, u - 1, s, t);
+        alt_sub(a, K_QM1, u, j, t2, s2);
+      } else {
+        a.V = cblk(D.Qm1p, n, i, j)[s * 6 + s2];
+        alt_sub(a, K_QM1P, i, j, s, s2);
+      }
+    }, wsum, nalts);
+    return;
+  }
+  // K_PAIR: every alternative's value is (v_i + v_j) + its term
+  const double vv = D.v[i * 6 + s] + D.v[j * 6 + s2];
+  const int t = bpair(NT(D, i, s), NT(D, j, s2));
+  const int da = D.d[i + 1], db = D.d[j - 1];
+  const double bh = D.hp[j - i - 1];
+  emit(S, da * db, base, [&](int idx, SubAlt &a) {  // hairpin by the end slots of its run
+    const int x = idx / db, y = idx % db;
+    a.V = vv + (bh + hairpin_term(D, i, j, s, s2, t, x, y));
+    alt_as(a, i, s, j);
+    alt_as(a, j, s2, i);
+    alt_sub(a, K_RUN, i + 1, j - 1, x, y);
+  }, wsum, nalts);
+  if ((j - 1) - (i + 1) >= 4)
+    emit(S, da * db, base, [&](int idx, SubAlt &a) {  // stack
+      const int x = idx / db, y = idx % db;
+      a.V = vv + stack_term(D, i, j, s, s2, t, x, y);
+      alt_as(a, i, s, j);
+      alt_as(a, j, s2, i);
+      alt_sub(a, K_PAIR, i + 1, j - 1, x, y);
+    }, wsum, nalts);
+  // bulge and interior windows, l1 then l2 ascending: screen every
+  // (window, a, dd) by the window's minimum, keep the survivors in order
+  {
+    const int nwin = 31 * 31 * 36;
+    if (threadIdx.x == 0) *wcount = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nwin; c0 += MT) {
+      const int e = c0 + (int)threadIdx.x;
+      bool pass = false;
+      if (e < nwin) {
+        const int w = e / 36, a = (e % 36) / 6, dd = e % 6, l1 = w / 31, l2 = w % 31;
+        const int k = i + 1 + l1, l = j - 1 - l2;
+        if (l1 + l2 <= MAXW && (l1 | l2) != 0 && l - k >= 4 && a < da && dd < db) {
+          const bool inter = l1 > 0 && l2 > 0;
+          const double wv0 = window_value(D, i, j, l1, l2, a, dd, cblk(D.U, n, i + 1, k - 1),
+                                          cblk(D.U, n, l + 1, j - 1));
+          const double wv = inter ? wv0 + MM(D, NT(D, i + 1, a), NT(D, j - 1, dd), t) : wv0;
+          pass = base + (vv + outer_term(D, i, j, s, s2, a, dd, wv)) <= S.thr;
+        }
+      }
+      int pos;
+      const int tot = block_scan(pass, pos, wsum);
+      if (pass) S.wlist[*wcount + pos] = e;
+      __syncthreads();
+      if (threadIdx.x == 0) *wcount += tot;
+      __syncthreads();
+    }
+  }
+  const int nw = *wcount;
+  for (int q = 0; q < nw; q++) {
+    const int e = S.wlist[q], w = e / 36, a = (e % 36) / 6, dd = e % 6, l1 = w / 31, l2 = w % 31;
+    const int k = i + 1 + l1, l = j - 1 - l2;
+    if (l2 == 0) {  // left bulge: run i+1..k-1 (a, b), edge (b, x), pair (k, j-1) (x, dd)
+      const int dx = D.d[k];
+      emit(S, D.d[k - 1] * dx, base, [&](int idx, SubAlt &al) {
+        const int b = idx / dx, x = idx % dx;
+        const double wv = D.bulge[l1] + (cblk(D.U, n, i + 1, k - 1)[a * 6 + b] + E(D, k - 1, b, x) +
+                                         cblk(D.Qb, n, k, j - 1)[x * 6 + dd]);
+        al.V = vv + outer_term(D, i, j, s, s2, a, dd, wv);
+        alt_as(al, i, s, j);
+        alt_as(al, j, s2, i);
+        alt_sub(al, K_RUN, i + 1, k - 1, a, b);
+        alt_sub(al, K_PAIR, k, j - 1, x, dd);
+      }, wsum, nalts);
+    } else if (l1 == 0) {  // right bulge: pair (i+1, l) (a, y), edge (y, c), run l+1..j-1 (c, dd)
+      const int dc = D.d[l + 1];
+      emit(S, D.d[l] * dc, base, [&](int idx, SubAlt &al) {
+        const int y = idx / dc, c = idx % dc;
+        const double wv = D.bulge[l2] + (cblk(D.Qb, n, i + 1, l)[a * 6 + y] + E(D, l, y, c) +
+                                         cblk(D.U, n, l + 1, j - 1)[c * 6 + dd]);
+        al.V = vv + outer_term(D, i, j, s, s2, a, dd, wv);
+        alt_as(al, i, s, j);
+        alt_as(al, j, s2, i);
+        alt_sub(al, K_PAIR, i + 1, l, a, y);
+        alt_sub(al, K_RUN, l + 1, j - 1, c, dd);
+      }, wsum, nalts);
+    } else {  // interior: (slot c of l+1, slot b of k-1, inner pair slots x, y)
+      const int dc = D.d[l + 1], dbk = D.d[k - 1], dx = D.d[k], dy = D.d[l];
+      const double mm = MM(D, NT(D, i + 1, a), NT(D, j - 1, dd), t);
+      const double *qb = cblk(D.Qb, n, k, l);
+      emit(S, dc * dbk * dx * dy, base, [&](int idx, SubAlt &al) {
+        const int y = idx % dy, x = (idx / dy) % dx, b = (idx / (dy * dx)) % dbk, c = idx / (dy * dx * dbk);
+        const double dt = di_term(D, qb, k, l, b, c, x, y);
+        const double wv = D.interior[l1 + l2] +
+                          ((cblk(D.U, n, i + 1, k - 1)[a * 6 + b] + dt) + cblk(D.U, n, l + 1, j - 1)[c * 6 + dd]);
+        al.V = vv + outer_term(D, i, j, s, s2, a, dd, wv + mm);
+        alt_as(al, i, s, j);
+        alt_as(al, j, s2, i);
+        alt_sub(al, K_RUN, i + 1, k - 1, a, b);
+        alt_sub(al, K_PAIR, k, l, x, y);
+        alt_sub(al, K_RUN, l + 1, j - 1, c, dd);
+      }, wsum, nalts);
+    }
+  }
+  emit(S, da * db, base, [&](int idx, SubAlt &a) {  // multiloop
+    const int x = idx / db, y = idx % db;
+    a.V = vv + (D.ml_ab + ml_term(D, i, j, s, s2, x, y));
+    alt_as(a, i, s, j);
+    alt_as(a, j, s2, i);
+    alt_sub(a, K_QMX, i + 1, j - 1, x, y);
+  }, wsum, nalts);
+}
+
+__global__ __launch_bounds__(MT) void mfe_subopt(MfeDev D, SubDev S) {
+  __shared__ int wsum[MT / 64];
+  __shared__ int nalts, nlv, npend, wcount, count, rc, act;  // act: 0 continue, 1 expand, 2 stop
+  __shared__ int fexp[5];
+  __shared__ double sbound;
+  const int n = D.n, m = n / 3, tid = threadIdx.x;
+  if (tid == 0) {
+    nalts = 0;
+    count = 0;
+    rc = 0;
+    SubLevel &L = S.lv[0];
+    L.f[0] = -1;
+    L.flen0 = 0;
+    L.b0 = 0.0;
+    L.a0 = 0;
+    nlv = 1;
+  }
+  for (int p = tid; p < n; p += MT) {
+    D.slot[p] = -1;
+    D.pt[p] = -1;
+  }
+  __syncthreads();
+  emit(S, D.d[n - 1], 0.0, [&](int t, SubAlt &a) {  // the root: slot of the last position
+    a.V = D.Z5[(n - 1) * 6 + t];
+    alt_sub(a, K_EXT, n - 1, 0, t, 0);
+  }, wsum, &nalts);
+  if (tid == 0) {
+    S.lv[0].na = nalts;
+    S.lv[0].next = 0;
+  }
+  __syncthreads();
+  while (true) {
+    if (tid == 0) {
+      act = 0;
+      if (nalts > S.cap_alts) {
+        rc = 2;
+        act = 2;
+      } else if (nlv == 0) {
+        act = 2;
+      } else {
+        SubLevel &L = S.lv[nlv - 1];
+        if (L.next == L.na) {  // backtrack: put the expanded fragment back where it was taken from
+          if (L.f[0] >= 0)
+            for (int q = 0; q < 5; q++) S.pend[L.flen0 * 5 + q] = L.f[q];
+          nalts = L.a0;
+          nlv--;
+        } else {
+          const SubAlt &a = S.alts[L.a0 + L.next++];
+          npend = L.flen0;
+          for (int q = 0; q < a.nas; q++) {
+            D.slot[a.as[q][0]] = a.as[q][1];
+            D.pt[a.as[q][0]] = a.as[q][2];
+          }
+          for (int q = 0; q < a.nsub; q++) {
+            for (int r = 0; r < 5; r++) S.pend[npend * 5 + r] = a.sub[q][r];
+            npend++;
+          }
+          const double bound = L.f[0] < 0 ? a.V : (L.b0 - frag_entry(D, L.f)) + a.V;
+          sbound = bound;
+          if (npend == 0) {
+            act = 3;  // a complete state
+          } else if (nlv == S.cap_lv) {
+            rc = 3;
+            act = 2;
+          } else {
+            npend--;
+            SubLevel &N = S.lv[nlv++];
+            for (int q = 0; q < 5; q++) {
+              N.f[q] = S.pend[npend * 5 + q];
+              fexp[q] = N.f[q];
+            }
+            N.flen0 = npend;
+            N.b0 = bound;
+            N.a0 = nalts;
+            act = 1;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const int what = act;
+    if (what == 2) break;
+    if (what == 3) {  // write the state out
+      if (count >= S.max_states) {
+        if (tid == 0) rc = 1;
+        break;
+      }
+      const int c = count;
+      for (int p = tid; p < n; p += MT) S.pairs[(size_t)c * n + p] = D.pt[p];
+      for (int a = tid; a < m; a += MT) {
+        const int sl = D.slot[3 * a];
+        if (sl < 0 || D.slot[3 * a + 1] != sl || D.slot[3 * a + 2] != sl) atomicMax(&rc, 4);
+        S.codons[(size_t)c * m + a] = (unsigned char)sl;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        S.energies[c] = sbound;
+        count = c + 1;
+      }
+      __syncthreads();
+      if (rc == 4) break;
+      continue;
+    }
+    if (what == 1) {
+      int f[5];
+      for (int q = 0; q < 5; q++) f[q] = fexp[q];
+      const double base = sbound - frag_entry(D, f);
+      const int a0 = nalts;
+      sub_alternatives(D, S, f, base, wsum, &nalts, &wcount);
+      if (tid == 0) {
+        SubLevel &N = S.lv[nlv - 1];
+        N.na = nalts - a0;
+        N.next = 0;
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    S.status[0] = count;
+    S.status[1] = rc;
+  }
+}
+
 struct DevBuf {
   void *p = nullptr;
   ~DevBuf() {
@@ -840,7 +1281,21 @@ struct DevBuf {
 
 }  // namespace
 
-extern "C" cdz_status cdz_mfe(cdz_handle *h, const cdz_problem *prob, double *mfe, uint8_t *codons, int32_t *pairs) {
+namespace {
+
+// a request for the states within gap of the minimum instead of one argmin
+struct SubReq {
+  double gap;
+  int max_states;
+  double *energies;
+  uint8_t *codons;
+  int32_t *pairs;
+  int32_t *count;
+  int more;  // set when more than max_states states exist
+};
+
+cdz_status mfe_run(cdz_handle *h, const cdz_problem *prob, double *mfe, uint8_t *codons, int32_t *pairs,
+                   SubReq *sub) {
   if (!h || !prob || !mfe) return cdz_fail(h, CDZ_ERR_ARG, "null argument");
   HostTables t;
   cdz_status st = build_tables(h, prob->n_aa, prob->aa, prob->theta1, prob->theta2, t);
@@ -878,6 +1333,21 @@ extern "C" cdz_status cdz_mfe(cdz_handle *h, const cdz_problem *prob, double *mf
                oStk = take((size_t)(4 * n + 16) * 5 * 4), oOut = take(8), oErr = take(4);
   size_t oArr[7];
   for (int k = 0; k < 7; k++) oArr[k] = take(cell * 8);
+  // suboptimal enumeration: levels, pending stack, alternatives, screened
+  // windows, prefix sums of d[k-1] d[k], outputs and status
+  const int cap_lv = 4 * n + 16, cap_alts = 1 << 20, nst = sub ? std::max(sub->max_states, 1) : 0;
+  size_t oLv = 0, oPd = 0, oAl = 0, oWl = 0, oPk = 0, oEn = 0, oCo = 0, oPa = 0, oSs = 0;
+  if (sub) {
+    oLv = take((size_t)cap_lv * sizeof(SubLevel));
+    oPd = take((size_t)cap_lv * 5 * 4);
+    oAl = take((size_t)cap_alts * sizeof(SubAlt));
+    oWl = take((size_t)31 * 31 * 36 * 4);
+    oPk = take((size_t)(n + 1) * 4);
+    oEn = take((size_t)nst * 8);
+    oCo = take((size_t)nst * m);
+    oPa = take((size_t)nst * n * 4);
+    oSs = take(8);
+  }
   DevBuf ws;
   if (hipMalloc(&ws.p, off) != hipSuccess) {
     (void)hipGetLastError();
@@ -933,7 +1403,35 @@ extern "C" cdz_status cdz_mfe(cdz_handle *h, const cdz_problem *prob, double *mf
   hipLaunchKernelGGL(mfe_exterior, dim3(1), dim3(MT), 0, sm, D);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->ev[5], sm));
-  if (codons || pairs) hipLaunchKernelGGL(mfe_traceback, dim3(1), dim3(MT), 0, sm, D);
+  SubDev S{};
+  if (sub) {
+    std::vector<int> pk(n + 1, 0);  // pk[k + 1] = pk[k] + d[k-1] d[k], k >= 1
+    for (int k = 1; k < n; k++) pk[k + 1] = pk[k] + t.d[k - 1] * t.d[k];
+    HIPCHK(h, hipMemcpyAsync(base + oPk, pk.data(), (n + 1) * 4, hipMemcpyHostToDevice, sm));
+    S.max_states = sub->max_states;
+    S.cap_alts = cap_alts;
+    S.cap_lv = cap_lv;
+    S.alts = (SubAlt *)(base + oAl);
+    S.lv = (SubLevel *)(base + oLv);
+    S.pend = (int *)(base + oPd);
+    S.pk = (int *)(base + oPk);
+    S.wlist = (int *)(base + oWl);
+    S.energies = (double *)(base + oEn);
+    S.codons = (unsigned char *)(base + oCo);
+    S.pairs = (int *)(base + oPa);
+    S.status = (int *)(base + oSs);
+  }
+  if (sub) {
+    // the threshold needs the minimum: read it back first
+    double mn = 0;
+    HIPCHK(h, hipMemcpyAsync(&mn, D.out, 8, hipMemcpyDeviceToHost, sm));
+    HIPCHK(h, hipStreamSynchronize(sm));
+    if (!std::isfinite(mn)) return cdz_fail(h, CDZ_ERR_NUMERIC, "minimum free energy not finite");
+    S.thr = mn + sub->gap + 1e-9 * std::max(1.0, std::fabs(mn));
+    hipLaunchKernelGGL(mfe_subopt, dim3(1), dim3(MT), 0, sm, D, S);
+  } else if (codons || pairs) {
+    hipLaunchKernelGGL(mfe_traceback, dim3(1), dim3(MT), 0, sm, D);
+  }
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipEventRecord(h->ev[6], sm));
   double res = 0;
@@ -955,6 +1453,24 @@ extern "C" cdz_status cdz_mfe(cdz_handle *h, const cdz_problem *prob, double *mf
   }
   *mfe = res;
   if (!std::isfinite(res)) return cdz_fail(h, CDZ_ERR_NUMERIC, "minimum free energy not finite");
+  if (sub) {
+    int st[2] = {0, 0};
+    HIPCHK(h, hipMemcpy(st, S.status, 8, hipMemcpyDeviceToHost));
+    if (st[1] == 2)
+      return cdz_fail(h, CDZ_ERR_BUDGET, "more than " + std::to_string(cap_alts) +
+                                             " pending alternatives: lower the gap");
+    if (st[1] == 3) return cdz_fail(h, CDZ_ERR_STATE, "enumeration level stack overflow");
+    if (st[1] == 4) return cdz_fail(h, CDZ_ERR_STATE, "enumeration left an inconsistent codon");
+    const int cnt = st[0];
+    if (cnt > 0) {
+      if (sub->energies) HIPCHK(h, hipMemcpy(sub->energies, S.energies, (size_t)cnt * 8, hipMemcpyDeviceToHost));
+      if (sub->codons) HIPCHK(h, hipMemcpy(sub->codons, S.codons, (size_t)cnt * m, hipMemcpyDeviceToHost));
+      if (sub->pairs) HIPCHK(h, hipMemcpy(sub->pairs, S.pairs, (size_t)cnt * n * 4, hipMemcpyDeviceToHost));
+    }
+    *sub->count = cnt;
+    sub->more = st[1] == 1;
+    return CDZ_OK;
+  }
   if (codons || pairs) {
     if (err == 1) return cdz_fail(h, CDZ_ERR_STATE, "traceback stack overflow");
     if (err) return cdz_fail(h, CDZ_ERR_STATE, "traceback found no alternative reproducing the minimum");
@@ -968,4 +1484,21 @@ extern "C" cdz_status cdz_mfe(cdz_handle *h, const cdz_problem *prob, double *mf
       for (int p = 0; p < n; p++) pairs[p] = pt[p];
   }
   return CDZ_OK;
+}
+
+}  // namespace
+
+extern "C" cdz_status cdz_mfe(cdz_handle *h, const cdz_problem *prob, double *mfe, uint8_t *codons, int32_t *pairs) {
+  return mfe_run(h, prob, mfe, codons, pairs, nullptr);
+}
+
+extern "C" cdz_status cdz_subopt(cdz_handle *h, const cdz_problem *prob, double gap, int32_t max_states, double *mfe,
+                                 double *energies, uint8_t *codons, int32_t *pairs, int32_t *count, int32_t *more) {
+  if (!h || !prob || !mfe || !count || !(gap >= 0.0) || !std::isfinite(gap) || max_states < 0)
+    return cdz_fail(h, CDZ_ERR_ARG, "null argument, negative or non-finite gap, or negative max_states");
+  SubReq r{gap, max_states, energies, codons, pairs, count, 0};
+  *count = 0;
+  const cdz_status st = mfe_run(h, prob, mfe, nullptr, nullptr, &r);
+  if (more) *more = r.more;
+  return st;
 }
