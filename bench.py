@@ -427,7 +427,13 @@ def main():
         tm = B.cdz_last_timings(h64)
         ops = algorithmic_ops_mfe(d)
         ach = ops / (tm[0] / 1e3) / 1e12
-        mfe = {"mfe_kT": v_mfe, "dtype": "f64", "ms_forward": tm[0], "ms_traceback": tm[2],
+        # suboptimal states within 0.1 kT of the minimum (SI S4d), same protein, at most 500
+        sub = B.cdz_subopt(h64, prob, 0.1, max_states=500)
+        tms = B.cdz_last_timings(h64)
+        subopt = {"gap_kT": 0.1, "states": int(len(sub[1])), "complete": bool(sub[4]), "ms_search": tms[2],
+                  "ms_forward": tms[0]}
+        print(f"# subopt gap 0.1: {len(sub[1])} states, search {tms[2]:.1f} ms", file=sys.stderr, flush=True)
+        mfe = {"mfe_kT": v_mfe, "dtype": "f64", "ms_forward": tm[0], "ms_traceback": tm[2], "subopt": subopt,
                "roofline": {"kernel": "mfe_diag", "bound": "alu", "achieved": ach,
                             "peak": FP64_ALU_PEAK_TOPS, "unit": "TOP/s (FP64 add or min)",
                             "frac": ach / FP64_ALU_PEAK_TOPS, "ops": ops,

@@ -1447,7 +1447,7 @@ cdz_status mfe_run(cdz_handle *h, const cdz_problem *prob, double *mfe, uint8_t 
   float ms = 0;
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev[4], h->ev[5]));
   h->times[0] = ms;
-  if (codons || pairs) {
+  if (codons || pairs || sub) {  // traceback or suboptimal search
     HIPCHK(h, hipEventElapsedTime(&ms, h->ev[5], h->ev[6]));
     h->times[2] = ms;
   }
