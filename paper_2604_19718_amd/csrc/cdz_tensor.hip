@@ -50,6 +50,13 @@ namespace {
 constexpr int TZ_NKC = 4;
 constexpr int TZ_KCS[TZ_NKC] = {256, 512, 1024, 2048};
 constexpr int TZ_MAXCH = 8;
+constexpr int TZ_GRIDCH = 32;  // most chunks a column may have (N <= 32 * 2048 rows)
+
+// the workgroup count of each chunk of one column, passed by value so that
+// a workgroup finds its (tile, chunk) without dependent memory loads
+struct TzGrid {
+  int cnt[TZ_GRIDCH];
+};
 constexpr int TZ_PW = 8;          // waves of one propagation workgroup
 constexpr int TZ_TM = 64;    // rows of one propagation tile (four 16-row MFMA tiles)
 constexpr int TZ_WMAX = 64;  // widest column block gamma * Sigma (gamma <= 16, Sigma <= 4)
@@ -109,12 +116,12 @@ struct TzDev {
 // multiplies k = k0 + VEC q + s for q = 0..3 -- the same set for A and B.
 template <typename T, int NTM>
 __global__ __launch_bounds__(512, (sizeof(T) == 4 && NTM == 3) ? 4 : 2) void tz_prop(TzDev<T> D, int j, int ntiles, int nchunks,
-                                                                                  int kc, const int *chunk_tiles) {
+                                                                                  int kc, TzGrid G) {
   using M = Mf<T>;
   constexpr int VEC = M::VEC, KS = 4 * VEC;
   int b = blockIdx.x, c = 0;
   for (; c < nchunks - 1; c++) {  // chunk-major: chunk c holds the tiles that reach it
-    const int cnt = min(ntiles, chunk_tiles[c]);
+    const int cnt = G.cnt[c];
     if (b < cnt) break;
     b -= cnt;
   }
@@ -342,7 +349,7 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
   T *Us = ts + xi * 256;                 // [combination][sigma_k][sigma_j]
   T *tk = Us + xi * 256, *tl = tk + 64;  // cores of the element's two ends
   int *cmb = reinterpret_cast<int *>(tl + 64);
-  __shared__ int e_prev, ncmb;
+  __shared__ int ncmb;
   __shared__ T red[4];
   const T *sSB = D.SB, *sB = D.B, *sV = D.V;
   if (STAGE) {
@@ -356,7 +363,15 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
     sB = l + (size_t)xi * 16 * g * g;
     sV = l + (size_t)2 * xi * 16 * g * g;
   }
-  // 0. exponent of column j-1: the largest entry of its row-0 block
+  const int wp = g * D.sig[j - 1];  // width of column j-1
+  const int k = qi - 1, l = j - 1;
+  const bool pair = qi >= 1 && l - k >= 4;
+  const int sk = pair ? D.sig[k] : 0, sb = pair ? D.sig[k + 1] : 0, se = pair ? D.sig[l] : 0, sj = D.sig[j];
+  // 1. everything that does not need the column's exponent, loads together:
+  // the largest entry of column j-1's row-0 block, the sums of block row qi
+  // of column j-1 (unscaled, into Xs), the cores of the element's ends and
+  // the (rho, phi_k, phi_l) that carry weight (B nonzero, both bases
+  // possible), in (rho, phi_k, phi_l) order
   if (j >= 2) {
     const int w0 = g * D.sig[j - 1];
     T mx = T(0);
@@ -378,18 +393,8 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
     mx = wave_max(mx);
     if (lane == 0) red[wave] = mx;
   }
-  __syncthreads();
-  if (tid == 0) {
-    const int e = j >= 2 ? exp_of((double)max(max(red[0], red[1]), max(red[2], red[3]))) : 0;
-    e_prev = e;
-    if (qi == 0 && j >= 2) D.colexp[j - 1] = e;
-  }
-  __syncthreads();
-  const int wp = g * D.sig[j - 1];  // width of column j-1
-  // 1. finish block row qi of column j-1
+  const int r0 = D.off[qi], rows = g * D.sig[qi];
   if (qi < j - 1) {
-    const int r0 = D.off[qi], rows = g * D.sig[qi];
-    const size_t cbase = (size_t)D.off[j - 1];
     for (int e0 = tid; e0 < rows * wp; e0 += 4 * TZ_FT) {
       int r[4], cc[4];
       bool ok[4];
@@ -404,18 +409,9 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
       col_sum4(D, r, cc, ok, nchunks_prev, kc_prev, y);
 #pragma unroll
       for (int u = 0; u < 4; u++)
-        if (ok[u]) {
-          const T x = ldexp(y[u], -e_prev);
-          D.Q[(size_t)r[u] * D.ld + cbase + cc[u]] = x;
-          Xs[(r[u] - r0) * wp + cc[u]] = x;
-        }
+        if (ok[u]) Xs[(r[u] - r0) * wp + cc[u]] = y[u];
     }
   }
-  const int k = qi - 1, l = j - 1;
-  const bool pair = qi >= 1 && l - k >= 4;
-  const int sk = pair ? D.sig[k] : 0, sb = pair ? D.sig[k + 1] : 0, se = pair ? D.sig[l] : 0, sj = D.sig[j];
-  // the cores of the element's ends and the (rho, phi_k, phi_l) that carry
-  // weight (B nonzero, both bases possible), in (rho, phi_k, phi_l) order
   if (pair) {
     if (tid < 64) tk[tid] = D.tc[(size_t)k * 64 + tid];
     else if (tid < 128) tl[tid - 64] = D.tc[(size_t)l * 64 + tid - 64];
@@ -430,6 +426,20 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
     }
   } else if (qi == j - 1 && tid < 64) {
     tk[tid] = D.tc[(size_t)(j - 1) * 64 + tid];
+  }
+  __syncthreads();
+  // 2. the exponent (every thread from the four wave maxima), then block row
+  // qi of column j-1 scaled and written back; each thread scales what it summed
+  const int e_prev = j >= 2 ? exp_of((double)max(max(red[0], red[1]), max(red[2], red[3]))) : 0;
+  if (tid == 0 && qi == 0 && j >= 2) D.colexp[j - 1] = e_prev;
+  if (qi < j - 1) {
+    const size_t cbase = (size_t)D.off[j - 1];
+    for (int e = tid; e < rows * wp; e += TZ_FT) {
+      const int rr = e / wp, col = e % wp;
+      const T x = ldexp(Xs[rr * wp + col], -e_prev);
+      Xs[rr * wp + col] = x;
+      D.Q[(size_t)(r0 + rr) * D.ld + cbase + col] = x;
+    }
   }
   __syncthreads();
   if (qi == 0 && (j - 1) % 3 == 0 && j >= 2 && wave == 0) {  // codon boundary: a g x g block, prefix trace
@@ -585,7 +595,7 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   const size_t oQ = take((size_t)H.rows * H.ld * sizeof(T)),
                oP = take((size_t)H.chunks * H.rows * TZ_WMAX * sizeof(T)), oSig = take((n + 1) * 4),
                oOff = take((n + 1) * 4), oRs = take((size_t)H.rows * 4), oTk = take((size_t)H.tiles * 4),
-               oCt = take(H.chunk_tiles.size() * 4), oBm = take(n), oTc = take(tc.size() * sizeof(T)),
+               oBm = take(n), oTc = take(tc.size() * sizeof(T)),
                oV = take(V.size() * sizeof(T)), oB = take(B.size() * sizeof(T)), oSB = take(SB.size() * sizeof(T)),
                oS = take(S.size() * sizeof(T)), oCe = take((n + 1) * 4), oPt = take((size_t)m * 8);
   DevBuf ws;
@@ -603,7 +613,6 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   HIPCHK(h, up(oOff, H.off.data(), (n + 1) * 4));
   HIPCHK(h, up(oRs, H.rstart.data(), (size_t)H.rows * 4));
   HIPCHK(h, up(oTk, H.tile_kmin.data(), (size_t)H.tiles * 4));
-  HIPCHK(h, up(oCt, H.chunk_tiles.data(), H.chunk_tiles.size() * 4));
   HIPCHK(h, up(oBm, H.bmask.data(), n));
   HIPCHK(h, up(oTc, tc.data(), tc.size() * sizeof(T)));
   HIPCHK(h, up(oV, V.data(), V.size() * sizeof(T)));
@@ -620,7 +629,6 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   D.off = (const int *)(base + oOff);
   D.rstart = (const int *)(base + oRs);
   D.tile_kmin = (const int *)(base + oTk);
-  const int *ct = (const int *)(base + oCt);
   D.bmask = (const unsigned char *)(base + oBm);
   D.tc = (const T *)(base + oTc);
   D.V = (const T *)(base + oV);
@@ -649,13 +657,18 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
     if (stage) tz_fold<T, true><<<fgrid, TZ_FT, fold_lds, st>>>(D, j, ncp, kcp);
     else tz_fold<T, false><<<fgrid, TZ_FT, fold_lds, st>>>(D, j, ncp, kcp);
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * (j - 1)], st));
-    const int *ctj = ct + H.ct_off[kci_of(H, j)];
-    if (ntn_max <= 3)
+    TzGrid G{};
+    {
+      const int nt = ntiles_of(H, j), nc = nchunks_of(H, j), b0 = H.ct_off[kci_of(H, j)];
+      for (int c = 0; c < nc; c++) G.cnt[c] = c == nc - 1 ? nt : std::min(nt, H.chunk_tiles[b0 + c]);
+    }
+    if (ntn_max <= 3) {
       tz_prop<T, 3><<<prop_grid(H, j), 64 * TZ_PW, prop_lds, st>>>(D, j, ntiles_of(H, j), nchunks_of(H, j),
-                                                                   kc_of(H, j), ctj);
-    else
+                                                                   kc_of(H, j), G);
+    } else {
       tz_prop<T, 4><<<prop_grid(H, j), 64 * TZ_PW, prop_lds, st>>>(D, j, ntiles_of(H, j), nchunks_of(H, j),
-                                                                   kc_of(H, j), ctj);
+                                                                   kc_of(H, j), G);
+    }
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * (j - 1) + 1], st));
   }
   tz_final<T><<<1, 64, 0, st>>>(D, nchunks_of(H, n), kc_of(H, n));
@@ -772,6 +785,7 @@ cdz_status finish_layout(cdz_handle *h, TzHost &H, int g, const cdz_tensor_model
   }
   H.chunks = 1;  // partial-sum slots: the most chunks any column uses
   for (int j = 1; j <= n; j++) H.chunks = std::max(H.chunks, nchunks_of(H, j));
+  if (H.chunks > TZ_GRIDCH) return cdz_fail(h, CDZ_ERR_ARG, "protein too long for the propagation grid");
   if (h->opt.prec == CDZ_FP64) return run_tensor<double>(h, H, md, log_z, prefix);
   return run_tensor<float>(h, H, md, log_z, prefix);
 }

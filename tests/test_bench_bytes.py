@@ -43,3 +43,41 @@ def test_byte_counts_match_cell_loop(n, seed):
     assert bench.algorithmic_bytes_fwd(d, 4) == _loop_fwd(d, 4)
     assert bench.algorithmic_bytes_out(d, 4) == _loop_out(d, 4)
     assert bench.algorithmic_bytes_out(d, 8) == _loop_out(d, 8)
+
+
+def _loop_tensor(sig, g, elt):
+    """Row by row: each row r of position block p < j reads Q[r][off[p] .. off[j]),
+    the fold row block j (g Sigma_j rows of off[j]) is read once and the column
+    (off[j] rows of g Sigma_j) written once; flops 2 g Sigma_j per element read."""
+    n = len(sig) - 1
+    off = [0]
+    for p in range(n + 1):
+        off.append(off[-1] + g * int(sig[p]))
+    tb = tf = 0
+    for j in range(1, n + 1):
+        R, w = off[j], g * int(sig[j])
+        tri = 0
+        for p in range(j):
+            for r in range(off[p], off[p + 1]):
+                tri += R - off[p]
+        tb += (tri + 2 * w * R) * elt
+        tf += 2 * tri * w
+    return tb, tf
+
+
+@pytest.mark.parametrize("prot,g", [("M", 9), ("MKWLRS", 9), ("ACDEFGHIKLMNPQRSTVWY", 4)])
+def test_tensor_bytes(prot, g):
+    from paper_2604_19718_amd import binding as B
+    from paper_2604_19718_amd import inputs as I
+    sig = B.cdz_tensor_dims(I.Problem(prot, None, None))
+    assert bench.tensor_prop_algorithmic(sig, g, 4) == _loop_tensor(sig, g, 4)
+
+
+def test_tensor_dims_match_the_oracle():
+    """The library's single-codon train dimensions (host only, no device) against
+    the oracle's, for every amino acid."""
+    import oracle
+    from paper_2604_19718_amd import binding as B
+    from paper_2604_19718_amd import inputs as I
+    prot = I.AA_ORDER + "MWLSRKV"
+    assert np.array_equal(B.cdz_tensor_dims(I.Problem(prot, None, None)), oracle.tensor_dims(prot))
