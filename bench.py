@@ -254,8 +254,9 @@ def tensor_leg(B, I, h32, h64, steps):
 
 def extra_workloads(B, I):
     """The batch of 256 proteins (30..400 residues; forward + outside + 64 samples
-    each, FP32; with direct launches and replayed hipGraphs) and the 3900-nt instance (forward + outside, FP32 and FP64; 1000
-    samples FP32), each timed once after one warm-up run, by HIP events."""
+    each, FP32; with direct launches and replayed hipGraphs), the 3900-nt instance (forward + outside, FP32 and FP64; 1000
+    samples FP32) and its tensor-model free energy (FP32 and FP64), each timed once after one warm-up run, by HIP
+    events."""
     out = {}
     probs = []
     for k in range(256):
@@ -297,6 +298,16 @@ def extra_workloads(B, I):
             rec["ms_sample_1000"] = B.cdz_last_timings(h)[2]
         out[f"3900nt_{prec}"] = rec
         print(f"# 3900nt {prec} {rec}", file=sys.stderr, flush=True)
+        del h
+    # the tensor-model free energy of the 3900-nt protein (synthetic gamma 9 model)
+    tprob, tmodel = I.tensor_workload(5)
+    for prec in ("fp32", "fp64"):
+        h = B.cdz_create(en5, prec)
+        B.cdz_tensor_logz(h, tmodel, tprob)
+        lz, _ = B.cdz_tensor_logz(h, tmodel, tprob)
+        rec = {"ms": B.cdz_last_timings(h)[0], "logz": lz, "q_rows": int(9 * B.cdz_tensor_dims(tprob).sum())}
+        out[f"tensor_3900nt_{prec}"] = rec
+        print(f"# tensor 3900nt {prec} {rec}", file=sys.stderr, flush=True)
         del h
     return out
 

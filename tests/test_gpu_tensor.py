@@ -99,3 +99,20 @@ def test_tensor_errors():
     # the handle still works afterwards
     lz, _ = B.cdz_tensor_logz(h, model, prob)
     assert np.isfinite(lz)
+
+
+def test_tensor_largest_3900nt():
+    """The 1300-residue protein (3900 nt, about 56 700 rows of Q, 28 chunks of
+    k in the last columns): FP64 prefix values of its first 100 residues equal
+    the oracle's pass over that prefix, FP32 agrees with FP64 at every prefix
+    within the FP32 bound, and log Z grows with the prefix."""
+    prob, model = I.tensor_workload(5)
+    g64, p64 = B.cdz_tensor_logz(_handle("fp64"), model, prob)
+    g32, p32 = B.cdz_tensor_logz(_handle("fp32"), model, prob)
+    sub = I.Problem(prob.prot[:100], prob.theta1[:100], None)
+    ref, rpre = oracle.tensor_logz(sub, model)
+    print("3900 nt", g64, g32, np.abs(p32 - p64).max(), np.abs(p64[:100] - rpre).max(), flush=True)
+    assert np.all(np.abs(p64[:100] - rpre) <= 1e-11 * np.maximum(1.0, np.abs(rpre)))
+    n = 3 * np.arange(1, prob.m + 1)
+    assert np.all(np.abs(p32 - p64) <= 5e-7 * n)
+    assert np.all(np.diff(p64) > 0)
