@@ -33,8 +33,12 @@ def _tol(prec, ref, n):
     return 1e-11 * np.maximum(1.0, np.abs(ref)) if prec == "fp64" else 5e-7 * n
 
 
+# ("LS", 16, 4): in FP64 the model no longer fits in LDS beside the fold's
+# arrays, so the fold reads it from memory (the unstaged variant); ("GAS", 16, 1)
+# has 64-wide column blocks (four 16-wide MFMA column tiles)
 CASES = [("M", 9, 1), ("MW", 4, 2), ("GCAR", 9, 1), ("MKWLRSGCAT", 9, 1), ("LLLSSSRRR", 9, 2),
-         ("ACDEFGHIKLMNPQRSTVWYACDEFGHIKL", 9, 1), ("KWY", 1, 1), ("GAS", 16, 1), ("VVVPC", 3, 4)]
+         ("ACDEFGHIKLMNPQRSTVWYACDEFGHIKL", 9, 1), ("KWY", 1, 1), ("GAS", 16, 1), ("VVVPC", 3, 4),
+         ("LSW", 16, 4)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
