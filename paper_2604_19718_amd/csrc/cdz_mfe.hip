@@ -898,46 +898,88 @@ __device__ __forceinline__ void alt_as(SubAlt &a, int p, int s, int partner) {
   a.nas++;
 }
 
-// exclusive prefix of one flag per thread over the workgroup; returns the total
-__device__ int block_scan(bool flag, int &pos, int *wsum) {
+// exclusive prefix of one count per thread over the workgroup; returns the total
+__device__ int block_scan_count(int cnt, int &pos, int *wsum) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const unsigned long long m = __ballot(flag);
-  const int below = __popcll(m & ((1ull << lane) - 1ull));
+  int inc = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
   __syncthreads();
-  if (lane == 0) wsum[w] = __popcll(m);
+  if (lane == 63) wsum[w] = inc;
   __syncthreads();
   int off = 0, tot = 0;
   for (int q = 0; q < MT / 64; q++) {
     if (q < w) off += wsum[q];
     tot += wsum[q];
   }
-  pos = off + below;
+  pos = off + inc - cnt;
   __syncthreads();
   return tot;
 }
 
+// candidates per thread and round: each thread takes EPT consecutive indices,
+// so one workgroup prefix sum orders MT * EPT of them
+constexpr int EPT = 8;
+
 // append, in index order, the candidates idx < cnt that gen() builds and
-// whose bound base + V stays within the threshold
+// whose bound base + V stays within the threshold (the few that pass are
+// built a second time when they are written out)
 template <typename G>
 __device__ void emit(const SubDev &S, int cnt, double base, G gen, int *wsum, int *nalts) {
-  for (int c0 = 0; c0 < cnt; c0 += MT) {
-    const int idx = c0 + (int)threadIdx.x;
-    SubAlt a;
-    a.nsub = a.nas = 0;
-    bool pass = false;
-    if (idx < cnt) {
-      gen(idx, a);
-      pass = base + a.V <= S.thr;
+  for (int c0 = 0; c0 < cnt; c0 += MT * EPT) {
+    const int first = c0 + (int)threadIdx.x * EPT;
+    unsigned mask = 0;
+    int mine = 0;
+    for (int u = 0; u < EPT; u++) {
+      const int idx = first + u;
+      if (idx < cnt) {
+        SubAlt a;
+        a.nsub = a.nas = 0;
+        gen(idx, a);
+        if (base + a.V <= S.thr) {
+          mask |= 1u << u;
+          mine++;
+        }
+      }
     }
     int pos;
-    const int tot = block_scan(pass, pos, wsum);
+    const int tot = block_scan_count(mine, pos, wsum);
     const int at = *nalts;
-    if (pass && at + pos < S.cap_alts) S.alts[at + pos] = a;
+    for (int u = 0, q = 0; u < EPT && mask; u++)
+      if ((mask >> u) & 1) {
+        SubAlt a;
+        a.nsub = a.nas = 0;
+        gen(first + u, a);
+        if (at + pos + q < S.cap_alts) S.alts[at + pos + q] = a;
+        q++;
+      }
     __syncthreads();
     if (threadIdx.x == 0) *nalts = at + tot;
     __syncthreads();
   }
 }
+
+// bulge and interior windows (l1, l2), l1 + l2 <= 30 and not both zero, in
+// enumeration order (l1 ascending, then l2 ascending)
+struct AllWin {
+  unsigned char l1[495], l2[495];
+};
+constexpr AllWin make_allwin() {
+  AllWin t{};
+  int m = 0;
+  for (int a = 0; a <= MAXW; a++)
+    for (int b = 0; a + b <= MAXW; b++) {
+      if (a == 0 && b == 0) continue;
+      t.l1[m] = (unsigned char)a;
+      t.l2[m] = (unsigned char)b;
+      m++;
+    }
+  return t;
+}
+__constant__ AllWin kAllWin = make_allwin();
 
 // index of the last k with pk[k] <= idx, searching k in [lo, hi)
 __device__ __forceinline__ int pk_find(const int *pk, int lo, int hi, int idx) {
@@ -1068,28 +1110,39 @@ __device__ void sub_alternatives(const MfeDev &D, const SubDev &S, const int *f,
   // bulge and interior windows, l1 then l2 ascending: screen every
   // (window, a, dd) by the window's minimum, keep the survivors in order
   {
-    const int nwin = 31 * 31 * 36;
+    const int nwin = 495 * 36;
     if (threadIdx.x == 0) *wcount = 0;
     __syncthreads();
-    for (int c0 = 0; c0 < nwin; c0 += MT) {
-      const int e = c0 + (int)threadIdx.x;
-      bool pass = false;
-      if (e < nwin) {
-        const int w = e / 36, a = (e % 36) / 6, dd = e % 6, l1 = w / 31, l2 = w % 31;
+    for (int c0 = 0; c0 < nwin; c0 += MT * EPT) {
+      const int first = c0 + (int)threadIdx.x * EPT;
+      unsigned mask = 0;
+      int mine = 0;
+      int code[EPT];
+      for (int u = 0; u < EPT; u++) {
+        const int e = first + u;
+        code[u] = 0;
+        if (e >= nwin) continue;
+        const int wi = e / 36, a = (e % 36) / 6, dd = e % 6, l1 = kAllWin.l1[wi], l2 = kAllWin.l2[wi];
         const int k = i + 1 + l1, l = j - 1 - l2;
-        if (l1 + l2 <= MAXW && (l1 | l2) != 0 && l - k >= 4 && a < da && dd < db) {
+        if (l - k >= 4 && a < da && dd < db) {
           const bool inter = l1 > 0 && l2 > 0;
           const double wv0 = window_value(D, i, j, l1, l2, a, dd, cblk(D.U, n, i + 1, k - 1),
                                           cblk(D.U, n, l + 1, j - 1));
           const double wv = inter ? wv0 + MM(D, NT(D, i + 1, a), NT(D, j - 1, dd), t) : wv0;
-          pass = base + (vv + outer_term(D, i, j, s, s2, a, dd, wv)) <= S.thr;
+          if (base + (vv + outer_term(D, i, j, s, s2, a, dd, wv)) <= S.thr) {
+            mask |= 1u << u;
+            mine++;
+            code[u] = (l1 * 31 + l2) * 36 + a * 6 + dd;
+          }
         }
       }
       int pos;
-      const int tot = block_scan(pass, pos, wsum);
-      if (pass) S.wlist[*wcount + pos] = e;
+      const int tot = block_scan_count(mine, pos, wsum);
+      const int at = *wcount;
+      for (int u = 0, q = 0; u < EPT; u++)
+        if ((mask >> u) & 1) S.wlist[at + pos + q++] = code[u];
       __syncthreads();
-      if (threadIdx.x == 0) *wcount += tot;
+      if (threadIdx.x == 0) *wcount = at + tot;
       __syncthreads();
     }
   }
