@@ -419,10 +419,10 @@ cdz_status chunk_outside(cdz_handle *h, Chunk<T> &C) {
   if (s != CDZ_OK) return s;
   const DevProb<T> *dP = (const DevProb<T> *)(dev + oP);
   const DevAdj<T> *dA = (const DevAdj<T> *)(dev + oA);
-  if (eta_lds_bytes(nmax) > (size_t)h->lds_max)
+  if (eta_lds_bytes(nmax, sizeof(T)) > (size_t)h->lds_max)
     return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(nmax) + " nt exceeds the LDS layout of the edge kernel");
   HIPCHK(h, hipFuncSetAttribute((const void *)cdz_eta_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)eta_lds_bytes(nmax)));
+                                (int)eta_lds_bytes(nmax, sizeof(T))));
   std::vector<double> sc(cnt);
   for (int b = 0; b < cnt; b++) {
     const double *r = &C.res[(size_t)b * 8];
@@ -444,7 +444,7 @@ cdz_status chunk_outside(cdz_handle *h, Chunk<T> &C) {
                            (const int *)(dev + oO) + Lo.at(dl), cnt, dl);
     }
     if (Le.total(0) > 0)
-      hipLaunchKernelGGL(cdz_eta_batch<T>, dim3(Le.total(0)), dim3(CDZ_NT), eta_lds_bytes(nmax), gs, dP, dA,
+      hipLaunchKernelGGL(cdz_eta_batch<T>, dim3(Le.total(0)), dim3(CDZ_NT), eta_lds_bytes(nmax, sizeof(T)), gs, dP, dA,
                          (const int *)(dev + oE), cnt);
     for (int b = 0; b < cnt; b++) {
       const long long nn = (long long)n[b] * n[b];

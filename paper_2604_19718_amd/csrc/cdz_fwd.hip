@@ -797,13 +797,19 @@ template size_t fwd_lds_bytes<double>(int);
 // ---------------------------------------------------------------------------
 // Both recurrences are sequential in the position; each step's pair terms
 // (up to W of them) are spread over the CDZ_SCAN_NT threads, one pair per
-// thread at the workload sizes, so a step costs one round of loads and one
-// workgroup sum.  The per-step factors v and e are fetched a step ahead by
-// the threads that use them, and every thread derives the step's exponent
+// thread at the workload sizes.  None of a step's loads depends on the
+// previous step: in FP32 the block of Qb and the A[k] (or Z3[jj]) of a
+// thread's first pair of step j + 1 are issued as soon as the thread has used
+// those of step j, so they arrive while the workgroup sums step j (the vectors
+// read were stored at least three steps, and barriers, earlier), and a step
+// costs about one workgroup sum; FP64 loads them in the step.  The per-step factors v and e are fetched a step ahead
+// by the threads that use them, and every thread derives the step's exponent
 // from the sums, so no extra barrier orders it.
 template <typename T>
 __device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, int jend, int dir) {
   constexpr int NT = CDZ_SCAN_NT;
+  // FP32 only: the 72 registers of an FP64 block would spill at 1024 threads
+  constexpr bool PRE = sizeof(T) == 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = D.n, tid = threadIdx.x;
   int *sE = reinterpret_cast<int *>(smem_raw);  // [n + 1] diagonal exponents
@@ -836,6 +842,23 @@ __device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, i
       for (int q = 0; q < 6; q++) ecol[q] = D.ed[q * 6 + tid];
     }
     int R = 0;  // exponent of Z5[j-1]
+    // this thread's first pair (k, j) of step j, k = max(0, j - W) + tid:
+    // Qb(k, j) and A[k], zero outside the slots
+    T fq[6][6];
+    double fa[6];
+    auto issue_first = [&](int jj) __attribute__((always_inline)) {
+      const int k0 = jj - W > 0 ? jj - W : 0, nk = jj - 4 - k0 + 1;
+      if (jj < 4 || jj > jend || tid >= nk) return;
+      const int k = k0 + tid, dk = sd[k], Pk = sP[k], dq = sd[jj], Pq = sP[jj];
+#pragma unroll
+      for (int x = 0; x < 6; x++) fa[x] = (k >= 1 && x < dk) ? D.A5[k * 6 + x] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 6; t++)
+#pragma unroll
+        for (int x = 0; x < 6; x++)
+          fq[x][t] = (t < dq && x < dk) ? D.Qbt[(long long)(Pq + t) * ld + Pk + x] : T(0);
+    };
+    if (PRE) issue_first(4);
     for (int j = 0; j <= jend; j++) {
       const int dj = sd[j], Pj = sP[j];
       double enx[6] = {0, 0, 0, 0, 0, 0}, vnx = 0;
@@ -852,7 +875,29 @@ __device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, i
         if (x == tid && x < dj) part[x] = own;
       if (j >= 4) {  // j paired with k: A[k] Qb(k, j), Qb read along rows of Qbt
         const int k0 = j - W > 0 ? j - W : 0, nk = j - 4 - k0 + 1;
-        for (int it = tid; it < nk; it += NT) {
+        if (PRE && tid < nk) {  // the first pair, loaded a step ahead
+          const int k = k0 + tid, dk = sd[k];
+          double a[6];
+          if (k == 0) {
+            const double sc = ldexp(1.0, sE[j] - R);
+#pragma unroll
+            for (int x = 0; x < 6; x++) a[x] = sc;
+          } else {
+            const double sc = ldexp(1.0, sX[k - 1] + sE[j - k] - R);
+#pragma unroll
+            for (int x = 0; x < 6; x++) a[x] = fa[x] * sc;
+          }
+#pragma unroll
+          for (int t = 0; t < 6; t++) {
+            if (t >= dj) break;
+            double sm = 0;
+#pragma unroll
+            for (int x = 0; x < 6; x++)
+              if (x < dk) sm += a[x] * (double)fq[x][t];
+            part[t] += sm;
+          }
+        }
+        for (int it = PRE ? tid + NT : tid; it < nk; it += NT) {
           const int k = k0 + it, dk = sd[k], Pk = sP[k];
           double a[6];
           if (k == 0) {
@@ -875,6 +920,7 @@ __device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, i
           }
         }
       }
+      if (PRE) issue_first(j + 1);
       // the full first barrier makes the A[.] stored a step earlier visible
       cdz_block_sum<double, 6, NT, true>(part, red, tot);
       const int e = step_exponent(dj);
@@ -931,6 +977,23 @@ __device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, i
     D.H3[n - 1] = 0;
   }
   int R = 0;  // exponent of Z3[p+1]
+  // this thread's first pair (p+1, jj) of step p, jj = p + 5 + tid: Qb(p+1, jj)
+  // and Z3[jj], zero outside the slots
+  T fq[6][6];
+  double fz[6];
+  auto issue_first = [&](int pp) __attribute__((always_inline)) {
+    const int j1 = pp + 1 + W < n - 1 ? pp + 1 + W : n - 1, nj = j1 - (pp + 5) + 1;
+    if (pp < 0 || tid >= nj) return;
+    const int jj = pp + 5 + tid, dq = sd[jj], Pq = sP[jj], d1 = sd[pp + 1], P1 = sP[pp + 1];
+#pragma unroll
+    for (int t = 0; t < 6; t++) fz[t] = t < dq ? D.Z3[jj * 6 + t] : 0.0;
+#pragma unroll
+    for (int x = 0; x < 6; x++)
+#pragma unroll
+      for (int t = 0; t < 6; t++)
+        fq[x][t] = (x < d1 && t < dq) ? D.Qb[(long long)(P1 + x) * ld + Pq + t] : T(0);
+  };
+  if (PRE) issue_first(n - 2);
   for (int p = n - 2; p >= 0; p--) {
     const int dp = sd[p], d1 = sd[p + 1], P1 = sP[p + 1];
     double enx[6] = {0, 0, 0, 0, 0, 0}, vnx = 0;
@@ -948,7 +1011,24 @@ __device__ __forceinline__ void exterior_scan_body(const DevProb<T> &D, int W, i
     for (int x = 0; x < 6; x++)
       if (x == tid && x < d1) w[x] = own;
     const int j1 = p + 1 + W < n - 1 ? p + 1 + W : n - 1, nj = j1 - (p + 5) + 1;
-    for (int it = tid; it < nj; it += NT) {
+    if (PRE && tid < nj) {  // the first pair, loaded a step ahead
+      const int jj = p + 5 + tid, dq = sd[jj];
+      const double sc = ldexp(1.0, sE[jj - p - 1] + sX[jj] - R);
+      double z3[6];
+#pragma unroll
+      for (int t = 0; t < 6; t++) z3[t] = fz[t] * sc;
+#pragma unroll
+      for (int x = 0; x < 6; x++) {
+        if (x >= d1) break;
+        double sm = 0;
+#pragma unroll
+        for (int t = 0; t < 6; t++)
+          if (t < dq) sm += (double)fq[x][t] * z3[t];
+        w[x] += sm;
+      }
+    }
+    if (PRE) issue_first(p - 1);
+    for (int it = PRE ? tid + NT : tid; it < nj; it += NT) {
       const int jj = p + 5 + it, dq = sd[jj], Pq = sP[jj];
       const double sc = ldexp(1.0, sE[jj - p - 1] + sX[jj] - R);
       double z3[6];

@@ -1137,29 +1137,55 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
   const long long ld = D.ld;
   // LDS: exponents, slot counts and offsets of every position (so that the
   // loops below issue one level of global loads), then reduction scratch
+  constexpr int LCH = eta_bulge_chunk<T>();
   int *sE = reinterpret_cast<int *>(smem_raw);
   int *sd = sE + (n + 1), *sP = sd + (n + 1);
   double *red = reinterpret_cast<double *>(smem_raw + ((size_t)3 * (n + 1) * 4 + 15) / 16 * 16);
   double *Mw = red + (CDZ_NT / 64) * 36 + wv * 36;  // per-wave bulge partial products
-  T *tab = reinterpret_cast<T *>(red + 2 * (CDZ_NT / 64) * 36);  // [TB_LEN] Boltzmann tables
-  T *Xw = tab + (TB_LEN + 7) / 8 * 8 + wv * 5 * 36;  // per wave: U, QmX, Qb, G, F of an inner block
-  int *Nw = reinterpret_cast<int *>(tab + (TB_LEN + 7) / 8 * 8 + (CDZ_NT / 64) * 5 * 36) + wv * 12;
+  // the unpaired runs of the bulges through this edge, shared by its cells:
+  // Ubl[l1 - 1](a, b) = U(p + 1 - l1 slot a, p slot b) (left bulges of the
+  // cells (p+1, j)), Ubr[l2 - 1](q, c) = U(p+1 slot c, p + l2 slot q) (right
+  // bulges of the cells (i, p)), zero outside the slots
+  T *Ubl = reinterpret_cast<T *>(red + 2 * (CDZ_NT / 64) * 36);
+  T *Ubr = Ubl + CDZ_MAXLOOP * 36;
+  T *Gw = Ubr + CDZ_MAXLOOP * 36 + wv * LCH * 36;  // per wave: LCH loop sizes of a cell's bulge adjoints
+  T *tab = Ubr + CDZ_MAXLOOP * 36 + (CDZ_NT / 64) * LCH * 36;  // [TB_LEN] Boltzmann tables
+  // per wave: U, QmX, Qb, G, F of an inner block, then the edge factors e of
+  // the position a cell's dressing sums over
+  T *Xw = tab + (TB_LEN + 7) / 8 * 8 + wv * 6 * 36;
+  T *Ew = Xw + 5 * 36;
+  int *Nw = reinterpret_cast<int *>(tab + (TB_LEN + 7) / 8 * 8 + (CDZ_NT / 64) * 6 * 36) + wv * 12;
   for (int k = tid; k < n; k += CDZ_NT) {
     sE[k] = D.E[k];
     sd[k] = D.d[k];
     sP[k] = D.P[k];
   }
   for (int k = tid; k < TB_LEN; k += CDZ_NT) tab[k] = D.tab[k];
+  const int dp = D.d[p], dq = D.d[p + 1], Pp = D.P[p], Pq = D.P[p + 1];
+  const int l1top = min(CDZ_MAXLOOP, p), l2top = min(CDZ_MAXLOOP, n - 2 - p);
+  for (int k = tid; k < CDZ_MAXLOOP * 36; k += CDZ_NT) {
+    const int l = k / 36 + 1, r1 = (k % 36) / 6, r2 = k % 6;
+    T xl = 0, xr = 0;
+    if (l <= l1top && r2 < dp) {  // (a, b) = (r1, r2)
+      const int pa = p + 1 - l;
+      if (r1 < D.d[pa]) xl = D.Ut[(long long)(Pp + r2) * ld + D.P[pa] + r1];
+    }
+    if (l <= l2top && r2 < dq) {  // (q, c) = (r1, r2)
+      const int pz = p + l;
+      if (r1 < D.d[pz]) xr = D.U[(long long)(Pq + r2) * ld + D.P[pz] + r1];
+    }
+    Ubl[k] = xl;
+    Ubr[k] = xr;
+  }
   __syncthreads();
   const int EZ = (int)D.res[2];
-  const int dp = sd[p], dq = sd[p + 1], Pp = sP[p], Pq = sP[p + 1];
   const T *ep = D.e + p * 36;
   // The wave stages block (i+1, j-1) of the loop closed by (i, j) (lane q =
-  // (a, dd)) and the bases of positions i+1 and j-1; inner(a, dd, to) is then
-  // the inner part of that loop for outer pair type to: hairpin, stack,
-  // multiloop, bulge and interior terms with the outer edges removed, in the
-  // units of the cell (i, j).
-  auto stage_inner = [&](int i, int j) {
+  // (a, dd)), the bases of positions i+1 and j-1 and the edge factors e_pe;
+  // inner(a, dd, to) is then the inner part of that loop for outer pair type
+  // to: hairpin, stack, multiloop, bulge and interior terms with the outer
+  // edges removed, in the units of the cell (i, j).
+  auto stage_inner = [&](int i, int j, int pe) {
     if (lane < 36) {
       const int a = lane / 6, dd = lane % 6;
       const bool ok = a < sd[i + 1] && dd < sd[j - 1];
@@ -1169,6 +1195,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
       Xw[72 + lane] = ok ? D.Qb[o] : T(0);
       Xw[108 + lane] = ok ? D.G[o] : T(0);
       Xw[144 + lane] = ok ? D.F[o] : T(0);
+      Ew[lane] = D.e[pe * 36 + lane];
     } else if (lane < 48) {
       const int q = lane - 36;
       Nw[q] = q < 6 ? D.nt[(i + 1) * 6 + q] : D.nt[(j - 1) * 6 + q - 6];
@@ -1202,31 +1229,42 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
       const long long Pi = Pq;
       const int b = u, x = w;
       if (j + 1 <= n - 1) {
+        const T ev = lane < 36 ? D.e[j * 36 + lane] : T(0);  // e_j, into Ew with M
         // left bulges with inner pair (i, j): lane (b, y) forms
-        // M(b, y) = sum_l1 f sum_a Gb(a, y) U(a, b) for the wave
+        // M(b, y) = sum_l1 f sum_a Gb(a, y) U(a, b) for the wave, the
+        // adjoints Gb(i - l1 slot a, j slot y) staged LCH loop sizes at a time
+        // (one round of loads each), the runs U from Ubl
         {
-          const int y = w;
+          const int y = w, l1max = min(CDZ_MAXLOOP, i - 1);
           T M = 0;
-          if (lane < 36 && b < dp && y < dj) {
-            const int l1max = min(CDZ_MAXLOOP, i - 1);
-#pragma unroll 2
-            for (int l1 = 1; l1 <= l1max; l1++) {
-              const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[dl] - sE[dl + l1 + 2]);
-              const int pa = i - l1, da = sd[pa], Pa = sP[pa];
-              T g[6], uu[6];
-#pragma unroll
-              for (int a = 0; a < 6; a++) {
-                g[a] = a < da ? A.Gb[(Pa + a) * ld + Pj + y] : T(0);
-                uu[a] = a < da ? D.Ut[(Pp + b) * ld + Pa + a] : T(0);  // U(Pa + a, Pp + b)
+          for (int l0 = 1; l0 <= l1max; l0 += LCH) {
+            for (int e = lane; e < LCH * 36; e += 64) {
+              const int l1 = l0 + e / 36, a = (e % 36) / 6, yy = e % 6;
+              T g = 0;
+              if (l1 <= l1max && yy < dj) {
+                const int pa = i - l1;
+                if (a < sd[pa]) g = A.Gb[(long long)(sP[pa] + a) * ld + Pj + yy];
               }
-              T sm = 0;
-#pragma unroll
-              for (int a = 0; a < 6; a++)
-                if (a < da) sm += g[a] * uu[a];
-              M += f * sm;
+              Gw[e] = g;
             }
+            cdz_wave_sync();
+            if (lane < 36 && b < dp && y < dj) {
+              const int lend = min(LCH, l1max - l0 + 1);
+              for (int l = 0; l < lend; l++) {
+                const int l1 = l0 + l;
+                const T f = tab[TB_BU + l1] * cdz_p2<T>(sE[l1 - 1] + sE[dl] - sE[dl + l1 + 2]);
+                T sm = 0;
+#pragma unroll
+                for (int a = 0; a < 6; a++) sm += Gw[l * 36 + a * 6 + y] * Ubl[(l1 - 1) * 36 + a * 6 + b];
+                M += f * sm;
+              }
+            }
+            cdz_wave_sync();
           }
-          if (lane < 36) Mw[lane] = (double)M;
+          if (lane < 36) {
+            Mw[lane] = (double)M;
+            Ew[lane] = ev;
+          }
           cdz_wave_sync();
         }
         if (own) {
@@ -1250,7 +1288,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
             const int tin = cdz_ptype(ntj[y], nix);
             T er[6];
 #pragma unroll
-            for (int c = 0; c < 6; c++) er[c] = c < dc ? D.e[j * 36 + y * 6 + c] : T(0);
+            for (int c = 0; c < 6; c++) er[c] = c < dc ? Ew[y * 6 + c] : T(0);
 #pragma unroll
             for (int c = 0; c < 6; c++) {
               if (c >= dc) break;
@@ -1299,7 +1337,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
       const int i = p, j = p + 4 + k, dl = j - i, di = dp, dj = sd[j], Pj = sP[j];
       const long long Pi = Pp;
       const int dm = sd[j - 1], s = u, a = w;
-      stage_inner(i, j);
+      stage_inner(i, j, j - 1);
       if (own) {
         const T eps = ep[s * 6 + a], vis = D.v[i * 6 + s];
         const int nis = D.nt[i * 6 + s];
@@ -1319,7 +1357,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
           if (to < 0 || ac[s2] == T(0) || eps == T(0)) continue;
           T em[6];
 #pragma unroll
-          for (int dd = 0; dd < 6; dd++) em[dd] = dd < dm ? D.e[(j - 1) * 36 + dd * 6 + s2] : T(0);
+          for (int dd = 0; dd < 6; dd++) em[dd] = dd < dm ? Ew[dd * 6 + s2] : T(0);
           T sm = 0;
 #pragma unroll
           for (int dd = 0; dd < 6; dd++)
@@ -1344,7 +1382,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
       const int i = k, j = p + 1, dl = j - i, di = sd[i];
       const long long Pi = sP[i], Pj = Pq;
       const int dd = u, s2 = w;
-      if (dl >= 4) stage_inner(i, j);
+      if (dl >= 4) stage_inner(i, j, i);
       const T eps = own ? ep[dd * 6 + s2] : T(0), vjs = own ? D.v[j * 6 + s2] : T(0);
       if (own && dl >= 4) {
         const int d1 = sd[i + 1], njs = D.nt[j * 6 + s2];
@@ -1365,7 +1403,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
             if (to < 0 || ac[s] == T(0)) continue;
             T ei[6];
 #pragma unroll
-            for (int a = 0; a < 6; a++) ei[a] = a < d1 ? D.e[i * 36 + s * 6 + a] : T(0);
+            for (int a = 0; a < 6; a++) ei[a] = a < d1 ? Ew[s * 6 + a] : T(0);
             T sm = 0;
 #pragma unroll
             for (int a = 0; a < 6; a++)
@@ -1405,31 +1443,42 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
       const int i = k, j = p, dl = j - i, di = sd[i];
       const long long Pi = sP[i], Pj = Pp;
       if (i >= 1) {
+        const T ev = lane < 36 ? D.e[(i - 1) * 36 + lane] : T(0);  // e_{i-1}, into Ew with M
         // right bulges with inner pair (i, p): lane (x, c) forms
-        // M(x, c) = sum_l2 f sum_dd U(c, dd) Gb(x, dd) for the wave
+        // M(x, c) = sum_l2 f sum_dd U(c, dd) Gb(x, dd) for the wave, the
+        // adjoints Gb(i slot x, p + l2 slot dd) staged LCH loop sizes at a
+        // time, the runs U from Ubr
         {
-          const int x = u, c = w;
+          const int x = u, c = w, l2max = l2top;
           T M = 0;
-          if (lane < 36 && x < di && c < dq) {
-            const int l2max = min(CDZ_MAXLOOP, n - 2 - p);
-#pragma unroll 2
-            for (int l2 = 1; l2 <= l2max; l2++) {
-              const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[dl] + sE[l2 - 1] - sE[dl + l2 + 2]);
-              const int pz = p + l2, dz = sd[pz], Pz = sP[pz];
-              T uu[6], g[6];
-#pragma unroll
-              for (int q = 0; q < 6; q++) {
-                uu[q] = q < dz ? D.U[(Pq + c) * ld + Pz + q] : T(0);
-                g[q] = q < dz ? A.Gb[(Pi + x) * ld + Pz + q] : T(0);
+          for (int l0 = 1; l0 <= l2max; l0 += LCH) {
+            for (int e = lane; e < LCH * 36; e += 64) {
+              const int l2 = l0 + e / 36, xx = (e % 36) / 6, q = e % 6;
+              T g = 0;
+              if (l2 <= l2max && xx < di) {
+                const int pz = p + l2;
+                if (q < sd[pz]) g = A.Gb[(Pi + xx) * ld + sP[pz] + q];
               }
-              T sm = 0;
-#pragma unroll
-              for (int q = 0; q < 6; q++)
-                if (q < dz) sm += uu[q] * g[q];
-              M += f * sm;
+              Gw[e] = g;
             }
+            cdz_wave_sync();
+            if (lane < 36 && x < di && c < dq) {
+              const int lend = min(LCH, l2max - l0 + 1);
+              for (int l = 0; l < lend; l++) {
+                const int l2 = l0 + l;
+                const T f = tab[TB_BU + l2] * cdz_p2<T>(sE[dl] + sE[l2 - 1] - sE[dl + l2 + 2]);
+                T sm = 0;
+#pragma unroll
+                for (int q = 0; q < 6; q++) sm += Ubr[(l2 - 1) * 36 + q * 6 + c] * Gw[l * 36 + x * 6 + q];
+                M += f * sm;
+              }
+            }
+            cdz_wave_sync();
           }
-          if (lane < 36) Mw[lane] = (double)M;
+          if (lane < 36) {
+            Mw[lane] = (double)M;
+            Ew[lane] = ev;
+          }
           cdz_wave_sync();
         }
         if (own) {
@@ -1453,7 +1502,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
             const int tin = cdz_ptype(njy, nti[x]);
             T eb[6];
 #pragma unroll
-            for (int b = 0; b < 6; b++) eb[b] = b < db ? D.e[(i - 1) * 36 + b * 6 + x] : T(0);
+            for (int b = 0; b < 6; b++) eb[b] = b < db ? Ew[b * 6 + x] : T(0);
 #pragma unroll
             for (int b = 0; b < 6; b++) {
               if (b >= db) break;
@@ -1566,11 +1615,15 @@ __global__ void cdz_grad_theta(const double *eta, const int *d, int m, double sc
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-size_t eta_lds_bytes(int n) {
-  // d, P, E of every position; reduction and bulge scratch; tables; per-wave
-  // inner blocks and bases
+size_t eta_lds_bytes(int n, int elt) {
+  // d, P, E of every position; reduction and bulge scratch; the runs of the
+  // edge's bulges and the per-wave bulge adjoints; tables; per-wave inner
+  // blocks and bases
+  const int lch = elt == 4 ? eta_bulge_chunk<float>() : eta_bulge_chunk<double>();
   return ((size_t)3 * (n + 1) * 4 + 15) / 16 * 16 + (size_t)(2 * (CDZ_NT / 64) * 36) * 8 +
-         ((size_t)(TB_LEN + 7) / 8 * 8 + (CDZ_NT / 64) * 5 * 36) * 8 + (CDZ_NT / 64) * 12 * 4;
+         ((size_t)2 * CDZ_MAXLOOP * 36 + (size_t)(CDZ_NT / 64) * lch * 36 + (TB_LEN + 7) / 8 * 8 +
+          (CDZ_NT / 64) * 6 * 36) * elt +
+         (CDZ_NT / 64) * 12 * 4;
 }
 
 template <typename T>
@@ -1640,7 +1693,7 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
   }
   HIPCHK(h, hipGetLastError());
   if (n >= 2) {
-    const size_t shm2 = eta_lds_bytes(n);
+    const size_t shm2 = eta_lds_bytes(n, sizeof(T));
     if (shm2 > (size_t)h->lds_max)
       return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the edge kernel");
     HIPCHK(h, hipFuncSetAttribute((const void *)cdz_eta<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm2));
