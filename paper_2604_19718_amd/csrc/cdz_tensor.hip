@@ -49,7 +49,7 @@ namespace {
 // columns get short wave chains and long ones few partial sums
 constexpr int TZ_NKC = 4;
 constexpr int TZ_KCS[TZ_NKC] = {256, 512, 1024, 2048};
-constexpr int TZ_MAXCH = 8;
+constexpr int TZ_MAXCH = 16;
 constexpr int TZ_GRIDCH = 32;  // most chunks a column may have (N <= 32 * 2048 rows)
 
 // the workgroup count of each chunk of one column, passed by value so that
