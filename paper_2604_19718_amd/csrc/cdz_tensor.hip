@@ -105,8 +105,12 @@ struct TzDev {
   T *Q;                         // [rows][ld]
   T *P;                         // [chunks][prow][TZ_WMAX] split-K partial sums
   int *colexp;                  // [n+1] exponent of each column's factor
+  int *done;                    // [n+1] tile-0 propagation workgroups finished per column (zeroed)
   double *ptr;                  // [m] Tr[S Q_{0,3a}] (scaled) at codon boundaries
 };
+
+template <typename T>
+__device__ inline int column_exponent(const TzDev<T> &D, int jc, int nchunks, int kc);
 
 // ---- propagation: Y_{[0:j), j} on the matrix cores ----------------------
 // Lane layout of v_mfma_*_16x16x4 (one block): A row i, k-group q at lane
@@ -244,6 +248,21 @@ __global__ __launch_bounds__(512, (sizeof(T) == 4 && NTM == 3) ? 4 : 2) void tz_
           const int row = r0 + 16 * m + M::drow(q, v), col = 16 * nn + li;
           if (row < R && col < w) P[(size_t)row * TZ_WMAX + col] = acc[m][nn][v];
         }
+  // The last of the column's tile-0 workgroups (tile 0 has one in every
+  // chunk) sums the row-0 block from the partials and sets the column's
+  // exponent, which the next column's fold workgroups then read instead of
+  // each summing that block again: partials stored and released before the
+  // count, acquired after it.
+  if (t == 0) {
+    __threadfence();
+    int last = 0;
+    if (lane == 0) last = atomicAdd(D.done + j, 1) == nchunks - 1;
+    if (__shfl(last, 0)) {
+      __threadfence();
+      const int e = column_exponent(D, j, nchunks, kc);
+      if (lane == 0) D.colexp[j] = e;
+    }
+  }
 }
 
 // sum of the partials of row r, column col of the last propagated column
@@ -350,7 +369,6 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
   T *tk = Us + xi * 256, *tl = tk + 64;  // cores of the element's two ends
   int *cmb = reinterpret_cast<int *>(tl + 64);
   __shared__ int ncmb;
-  __shared__ T red[4];
   const T *sSB = D.SB, *sB = D.B, *sV = D.V;
   if (STAGE) {
     T *l = tk + 192;
@@ -367,32 +385,11 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
   const int k = qi - 1, l = j - 1;
   const bool pair = qi >= 1 && l - k >= 4;
   const int sk = pair ? D.sig[k] : 0, sb = pair ? D.sig[k + 1] : 0, se = pair ? D.sig[l] : 0, sj = D.sig[j];
-  // 1. everything that does not need the column's exponent, loads together:
-  // the largest entry of column j-1's row-0 block, the sums of block row qi
-  // of column j-1 (unscaled, into Xs), the cores of the element's ends and
-  // the (rho, phi_k, phi_l) that carry weight (B nonzero, both bases
-  // possible), in (rho, phi_k, phi_l) order
-  if (j >= 2) {
-    const int w0 = g * D.sig[j - 1];
-    T mx = T(0);
-    {
-      int r[4], cc[4];
-      bool ok[4];
-      T y[4];
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int e = tid + TZ_FT * u;
-        ok[u] = e < g * w0;
-        r[u] = ok[u] ? e / w0 : 0;
-        cc[u] = ok[u] ? e % w0 : 0;
-      }
-      col_sum4(D, r, cc, ok, nchunks_prev, kc_prev, y);  // g * w0 <= 1024 entries
-#pragma unroll
-      for (int u = 0; u < 4; u++) mx = max(mx, y[u]);
-    }
-    mx = wave_max(mx);
-    if (lane == 0) red[wave] = mx;
-  }
+  // 1. loads together: the exponent of column j-1 (set by its propagation),
+  // the sums of block row qi of column j-1 (unscaled, into Xs), the cores of
+  // the element's ends and the (rho, phi_k, phi_l) that carry weight (B
+  // nonzero, both bases possible), in (rho, phi_k, phi_l) order
+  const int e_prev = j >= 2 ? D.colexp[j - 1] : 0;
   const int r0 = D.off[qi], rows = g * D.sig[qi];
   if (qi < j - 1) {
     for (int e0 = tid; e0 < rows * wp; e0 += 4 * TZ_FT) {
@@ -428,10 +425,7 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
     tk[tid] = D.tc[(size_t)(j - 1) * 64 + tid];
   }
   __syncthreads();
-  // 2. the exponent (every thread from the four wave maxima), then block row
-  // qi of column j-1 scaled and written back; each thread scales what it summed
-  const int e_prev = j >= 2 ? exp_of((double)max(max(red[0], red[1]), max(red[2], red[3]))) : 0;
-  if (tid == 0 && qi == 0 && j >= 2) D.colexp[j - 1] = e_prev;
+  // 2. block row qi of column j-1 scaled and written back
   if (qi < j - 1) {
     const size_t cbase = (size_t)D.off[j - 1];
     for (int e = tid; e < rows * wp; e += TZ_FT) {
@@ -597,7 +591,8 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
                oOff = take((n + 1) * 4), oRs = take((size_t)H.rows * 4), oTk = take((size_t)H.tiles * 4),
                oBm = take(n), oTc = take(tc.size() * sizeof(T)),
                oV = take(V.size() * sizeof(T)), oB = take(B.size() * sizeof(T)), oSB = take(SB.size() * sizeof(T)),
-               oS = take(S.size() * sizeof(T)), oCe = take((n + 1) * 4), oPt = take((size_t)m * 8);
+               oS = take(S.size() * sizeof(T)), oCe = take((n + 1) * 4), oPt = take((size_t)m * 8),
+               oDn = take((n + 1) * 4);
   DevBuf ws;
   if (hipMalloc(&ws.p, at) != hipSuccess) {
     (void)hipGetLastError();
@@ -639,6 +634,7 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   D.Q = (T *)(base + oQ);
   D.P = (T *)(base + oP);
   D.colexp = (int *)(base + oCe);
+  D.done = (int *)(base + oDn);
   D.ptr = (double *)(base + oPt);
   const size_t wave_lds = (size_t)(16 * g * g + 2 * xi * 256 + 192) * sizeof(T);
   const size_t model_lds = (size_t)(2 * xi * 16 + 4) * g * g * sizeof(T);
@@ -650,6 +646,7 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   const size_t prop_lds = (size_t)4 * 4 * ntn_max * 64 * 4 * sizeof(T);
   if (h->profiling) HIPCHK(h, prof_reserve(h, n));
   HIPCHK(h, hipEventRecord(h->ev[0], st));
+  HIPCHK(h, hipMemsetAsync(D.done, 0, (n + 1) * 4, st));
   tz_init<T><<<2048, 256, 0, st>>>(D.Q, (size_t)H.rows, (size_t)H.ld, (size_t)H.N);
   for (int j = 1; j <= n; j++) {
     const int fgrid = j;
