@@ -41,7 +41,7 @@ template <typename T>
 __global__ void cdz_out_diag_batch_fused(const DevProb<T> *probs, const DevAdj<T> *adjs, const int *off, int count,
                                          int dl);
 template <typename T>
-__global__ void cdz_eta_batch(const DevProb<T> *probs, const DevAdj<T> *adjs, const int *off, int count);
+__global__ void cdz_eta_batch(const DevProb<T> *probs, const DevAdj<T> *adjs, const int *off, int count, int lch);
 template <typename T>
 __global__ void cdz_pairprob(DevProb<T> D, DevAdj<T> A, double r);
 
@@ -445,7 +445,7 @@ cdz_status chunk_outside(cdz_handle *h, Chunk<T> &C) {
     }
     if (Le.total(0) > 0)
       hipLaunchKernelGGL(cdz_eta_batch<T>, dim3(Le.total(0)), dim3(CDZ_NT), eta_lds_bytes(nmax, sizeof(T)), gs, dP, dA,
-                         (const int *)(dev + oE), cnt);
+                         (const int *)(dev + oE), cnt, eta_bulge_chunk(nmax, sizeof(T)));
     for (int b = 0; b < cnt; b++) {
       const long long nn = (long long)n[b] * n[b];
       hipLaunchKernelGGL(cdz_pairprob<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, gs, C.D[b], C.A[b],

@@ -150,9 +150,10 @@ template <typename T>
 size_t out_lds_bytes(int n);  // dynamic LDS of the outside diagonal kernel
 size_t eta_lds_bytes(int n, int elt);  // dynamic LDS of the edge-marginal kernel (elt = sizeof(T))
 // loop sizes of a cell's bulge adjoints staged per round in the edge-marginal
-// kernel (15 in FP32; 10 in FP64, so three workgroups still fit a CU)
-template <typename T>
-constexpr int eta_bulge_chunk() { return sizeof(T) == 4 ? 15 : 10; }
+// kernel of an n-nt protein (elt = sizeof(T)): 15 in FP32; in FP64 10 while
+// three workgroups still fit a CU (n <= 1100), else 4, so that two do up to
+// 3900 nt
+__host__ __device__ inline int eta_bulge_chunk(int n, int elt) { return elt == 4 ? 15 : n <= 1100 ? 10 : 4; }
 
 // Storage of the interior-loop sums A (alK of carve):
 //   CDZ_AL_RESIDENT (-1): every diagonal in D.AL (block layout)

@@ -1131,13 +1131,13 @@ __device__ __forceinline__ void out_block(const DevProb<T> &D, const DevAdj<T> &
 // per edge; each wavefront takes one cell at a time and lane q < 36 owns
 // output (u, w) = (q / 6, q % 6), the slots of positions p and p+1.
 template <typename T>
-__device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A, int p) {
+__device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A, int p, int LCH) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = D.n, tid = threadIdx.x, lane = tid & 63, wv = cdz_wave_id();
   const long long ld = D.ld;
   // LDS: exponents, slot counts and offsets of every position (so that the
-  // loops below issue one level of global loads), then reduction scratch
-  constexpr int LCH = eta_bulge_chunk<T>();
+  // loops below issue one level of global loads), then reduction scratch;
+  // LCH = eta_bulge_chunk of the length the launch's LDS was sized for
   int *sE = reinterpret_cast<int *>(smem_raw);
   int *sd = sE + (n + 1), *sP = sd + (n + 1);
   double *red = reinterpret_cast<double *>(smem_raw + ((size_t)3 * (n + 1) * 4 + 15) / 16 * 16);
@@ -1547,8 +1547,8 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag_fused(DevProb<T> D, DevAd
   out_block<T, true>(D, A, dl, blockIdx.x);
 }
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A) {
-  eta_edge<T>(D, A, blockIdx.x);
+__global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A, int lch) {
+  eta_edge<T>(D, A, blockIdx.x, lch);
 }
 // batched forms (see cdz_fwd_diag_batch): one launch for diagonal dl / for the
 // edges of every problem of a batch
@@ -1572,12 +1572,12 @@ __global__ __launch_bounds__(CDZ_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T
 }
 template <typename T>
 __global__ __launch_bounds__(CDZ_NT) void cdz_eta_batch(const DevProb<T> *probs, const DevAdj<T> *adjs,
-                                                       const int *off, int count) {
+                                                       const int *off, int count, int lch) {
   int b, w;
   cdz_batch_locate(off, count, blockIdx.x, b, w);
   const DevProb<T> D = probs[b];
   const DevAdj<T> A = adjs[b];
-  eta_edge<T>(D, A, w);
+  eta_edge<T>(D, A, w, lch);
 }
 
 // pair probabilities P[i][j] = r * sum Qb~ Qb'~ over cells with j - i >= 4
@@ -1619,7 +1619,7 @@ size_t eta_lds_bytes(int n, int elt) {
   // d, P, E of every position; reduction and bulge scratch; the runs of the
   // edge's bulges and the per-wave bulge adjoints; tables; per-wave inner
   // blocks and bases
-  const int lch = elt == 4 ? eta_bulge_chunk<float>() : eta_bulge_chunk<double>();
+  const int lch = eta_bulge_chunk(n, elt);
   return ((size_t)3 * (n + 1) * 4 + 15) / 16 * 16 + (size_t)(2 * (CDZ_NT / 64) * 36) * 8 +
          ((size_t)2 * CDZ_MAXLOOP * 36 + (size_t)(CDZ_NT / 64) * lch * 36 + (TB_LEN + 7) / 8 * 8 +
           (CDZ_NT / 64) * 6 * 36) * elt +
@@ -1698,7 +1698,7 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
       return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the edge kernel");
     HIPCHK(h, hipFuncSetAttribute((const void *)cdz_eta<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm2));
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n], st));
-    hipLaunchKernelGGL(cdz_eta<T>, dim3(n - 1), dim3(CDZ_NT), shm2, st, D, A);
+    hipLaunchKernelGGL(cdz_eta<T>, dim3(n - 1), dim3(CDZ_NT), shm2, st, D, A, eta_bulge_chunk(n, sizeof(T)));
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n + 1], st));
   }
   const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz_scaled);
@@ -1886,7 +1886,7 @@ template __global__ void cdz_out_diag_batch_fused<float>(const DevProb<float> *,
                                                           int, int);
 template __global__ void cdz_out_diag_batch_fused<double>(const DevProb<double> *, const DevAdj<double> *,
                                                            const int *, int, int);
-template __global__ void cdz_eta_batch<float>(const DevProb<float> *, const DevAdj<float> *, const int *, int);
-template __global__ void cdz_eta_batch<double>(const DevProb<double> *, const DevAdj<double> *, const int *, int);
+template __global__ void cdz_eta_batch<float>(const DevProb<float> *, const DevAdj<float> *, const int *, int, int);
+template __global__ void cdz_eta_batch<double>(const DevProb<double> *, const DevAdj<double> *, const int *, int, int);
 template __global__ void cdz_pairprob<float>(DevProb<float>, DevAdj<float>, double);
 template __global__ void cdz_pairprob<double>(DevProb<double>, DevAdj<double>, double);
