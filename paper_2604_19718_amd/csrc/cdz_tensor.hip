@@ -105,12 +105,96 @@ struct TzDev {
   T *Q;                         // [rows][ld]
   T *P;                         // [chunks][prow][TZ_WMAX] split-K partial sums
   int *colexp;                  // [n+1] exponent of each column's factor
-  int *done;                    // [n+1] tile-0 propagation workgroups finished per column (zeroed)
+  T *pmax;                      // [n+1][TZ_GRIDCH] largest partial of each chunk in the column's row-0 block
   double *ptr;                  // [m] Tr[S Q_{0,3a}] (scaled) at codon boundaries
 };
 
+// sum of the partials of row r, column col of the last propagated column
 template <typename T>
-__device__ inline int column_exponent(const TzDev<T> &D, int jc, int nchunks, int kc);
+__device__ inline T col_sum(const TzDev<T> &D, int r, int col, int nchunks, int kc) {
+  const int cf = D.tile_kmin[r / TZ_TM] / kc;
+  T y = T(0);
+  const T *p = D.P + (size_t)r * TZ_WMAX + col;
+  const size_t cs = (size_t)D.prow * TZ_WMAX;
+  for (int c0 = cf; c0 < nchunks; c0 += 8) {  // eight loads in flight, added in chunk order
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = c0 + u < nchunks ? p[(c0 + u) * cs] : T(0);
+#pragma unroll
+    for (int u = 0; u < 8; u++) y += v[u];
+  }
+  return y;
+}
+
+// the same for four entries at once (rows r[u], columns col[u], skipped where
+// ok[u] is false): up to 32 loads in flight, each sum in chunk order
+template <typename T>
+__device__ inline void col_sum4(const TzDev<T> &D, const int *r, const int *col, const bool *ok, int nchunks, int kc,
+                                T *y) {
+  const size_t cs = (size_t)D.prow * TZ_WMAX;
+  int cf[4], cmin = nchunks;
+  const T *p[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    cf[u] = ok[u] ? D.tile_kmin[r[u] / TZ_TM] / kc : nchunks;
+    cmin = min(cmin, cf[u]);
+    p[u] = D.P + (size_t)(ok[u] ? r[u] : 0) * TZ_WMAX + (ok[u] ? col[u] : 0);
+    y[u] = T(0);
+  }
+  for (int c0 = cmin; c0 < nchunks; c0 += 8) {
+    T v[4][8];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int x = 0; x < 8; x++) v[u][x] = (c0 + x >= cf[u] && c0 + x < nchunks) ? p[u][(c0 + x) * cs] : T(0);
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+#pragma unroll
+      for (int x = 0; x < 8; x++) y[u] += v[u][x];
+  }
+}
+
+__device__ inline int exp_of(double x) {
+  int e;
+  (void)frexp(x, &e);
+  return e - 1;  // x in [2^(e-1), 2^e)
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+template <typename T>
+__device__ inline T wave_max(T v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// exponent of column jc's factor: binary exponent of the largest entry of its
+// row-0 block (rows 0..g-1), summed from the partials (one wave)
+template <typename T>
+__device__ inline int column_exponent(const TzDev<T> &D, int jc, int nchunks, int kc) {
+  const int w = D.g * D.sig[jc];
+  T mx = T(0);
+  for (int e0 = threadIdx.x & 63; e0 < D.g * w; e0 += 256) {
+    int r[4], cc[4];
+    bool ok[4];
+    T y[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int e = e0 + 64 * u;
+      ok[u] = e < D.g * w;
+      r[u] = e / w;
+      cc[u] = e % w;
+    }
+    col_sum4(D, r, cc, ok, nchunks, kc, y);
+#pragma unroll
+    for (int u = 0; u < 4; u++) mx = max(mx, y[u]);
+  }
+  mx = wave_max(mx);
+  return exp_of((double)mx);
+}
 
 // ---- propagation: Y_{[0:j), j} on the matrix cores ----------------------
 // Lane layout of v_mfma_*_16x16x4 (one block): A row i, k-group q at lane
@@ -248,108 +332,25 @@ __global__ __launch_bounds__(512, (sizeof(T) == 4 && NTM == 3) ? 4 : 2) void tz_
           const int row = r0 + 16 * m + M::drow(q, v), col = 16 * nn + li;
           if (row < R && col < w) P[(size_t)row * TZ_WMAX + col] = acc[m][nn][v];
         }
-  // The last of the column's tile-0 workgroups (tile 0 has one in every
-  // chunk) sums the row-0 block from the partials and sets the column's
-  // exponent, which the next column's fold workgroups then read instead of
-  // each summing that block again: partials stored and released before the
-  // count, acquired after it.
+  // tile 0 (one workgroup in every chunk) records the largest partial of
+  // the column's row-0 block in this chunk: the next column's fold takes the
+  // column's exponent from their sum, read in one round, instead of summing
+  // the block's partials in every workgroup
   if (t == 0) {
-    __threadfence();
-    int last = 0;
-    if (lane == 0) last = atomicAdd(D.done + j, 1) == nchunks - 1;
-    if (__shfl(last, 0)) {
-      __threadfence();
-      const int e = column_exponent(D, j, nchunks, kc);
-      if (lane == 0) D.colexp[j] = e;
-    }
+    T mx = T(0);
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+      for (int nn = 0; nn < NTM; nn++)
+        if (nn < ntn)
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            const int row = 16 * m + M::drow(q, v), col = 16 * nn + li;
+            if (row < D.g && col < w) mx = max(mx, acc[m][nn][v]);
+          }
+    mx = wave_max(mx);
+    if (lane == 0) D.pmax[(size_t)j * TZ_GRIDCH + c] = mx;
   }
-}
-
-// sum of the partials of row r, column col of the last propagated column
-template <typename T>
-__device__ inline T col_sum(const TzDev<T> &D, int r, int col, int nchunks, int kc) {
-  const int cf = D.tile_kmin[r / TZ_TM] / kc;
-  T y = T(0);
-  const T *p = D.P + (size_t)r * TZ_WMAX + col;
-  const size_t cs = (size_t)D.prow * TZ_WMAX;
-  for (int c0 = cf; c0 < nchunks; c0 += 8) {  // eight loads in flight, added in chunk order
-    T v[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) v[u] = c0 + u < nchunks ? p[(c0 + u) * cs] : T(0);
-#pragma unroll
-    for (int u = 0; u < 8; u++) y += v[u];
-  }
-  return y;
-}
-
-// the same for four entries at once (rows r[u], columns col[u], skipped where
-// ok[u] is false): up to 32 loads in flight, each sum in chunk order
-template <typename T>
-__device__ inline void col_sum4(const TzDev<T> &D, const int *r, const int *col, const bool *ok, int nchunks, int kc,
-                                T *y) {
-  const size_t cs = (size_t)D.prow * TZ_WMAX;
-  int cf[4], cmin = nchunks;
-  const T *p[4];
-#pragma unroll
-  for (int u = 0; u < 4; u++) {
-    cf[u] = ok[u] ? D.tile_kmin[r[u] / TZ_TM] / kc : nchunks;
-    cmin = min(cmin, cf[u]);
-    p[u] = D.P + (size_t)(ok[u] ? r[u] : 0) * TZ_WMAX + (ok[u] ? col[u] : 0);
-    y[u] = T(0);
-  }
-  for (int c0 = cmin; c0 < nchunks; c0 += 8) {
-    T v[4][8];
-#pragma unroll
-    for (int u = 0; u < 4; u++)
-#pragma unroll
-      for (int x = 0; x < 8; x++) v[u][x] = (c0 + x >= cf[u] && c0 + x < nchunks) ? p[u][(c0 + x) * cs] : T(0);
-#pragma unroll
-    for (int u = 0; u < 4; u++)
-#pragma unroll
-      for (int x = 0; x < 8; x++) y[u] += v[u][x];
-  }
-}
-
-__device__ inline int exp_of(double x) {
-  int e;
-  (void)frexp(x, &e);
-  return e - 1;  // x in [2^(e-1), 2^e)
-}
-
-template <typename T>
-__device__ inline T wave_sum(T v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-template <typename T>
-__device__ inline T wave_max(T v) {
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
-}
-
-// exponent of column jc's factor: binary exponent of the largest entry of its
-// row-0 block (rows 0..g-1), summed from the partials (one wave)
-template <typename T>
-__device__ inline int column_exponent(const TzDev<T> &D, int jc, int nchunks, int kc) {
-  const int w = D.g * D.sig[jc];
-  T mx = T(0);
-  for (int e0 = threadIdx.x & 63; e0 < D.g * w; e0 += 256) {
-    int r[4], cc[4];
-    bool ok[4];
-    T y[4];
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const int e = e0 + 64 * u;
-      ok[u] = e < D.g * w;
-      r[u] = e / w;
-      cc[u] = e % w;
-    }
-    col_sum4(D, r, cc, ok, nchunks, kc, y);
-#pragma unroll
-    for (int u = 0; u < 4; u++) mx = max(mx, y[u]);
-  }
-  mx = wave_max(mx);
-  return exp_of((double)mx);
 }
 
 // ---- fold: finish column j-1, build row block j --------------------------
@@ -385,11 +386,19 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
   const int k = qi - 1, l = j - 1;
   const bool pair = qi >= 1 && l - k >= 4;
   const int sk = pair ? D.sig[k] : 0, sb = pair ? D.sig[k + 1] : 0, se = pair ? D.sig[l] : 0, sj = D.sig[j];
-  // 1. loads together: the exponent of column j-1 (set by its propagation),
-  // the sums of block row qi of column j-1 (unscaled, into Xs), the cores of
-  // the element's ends and the (rho, phi_k, phi_l) that carry weight (B
-  // nonzero, both bases possible), in (rho, phi_k, phi_l) order
-  const int e_prev = j >= 2 ? D.colexp[j - 1] : 0;
+  // 1. loads together: the exponent of column j-1, that of the sum over its
+  // chunks (in chunk order) of their largest partials of the row-0 block (an
+  // upper bound of the block's largest entry, within a factor of the chunk
+  // count; any exact power of two serves as the factor), the sums of block
+  // row qi of column j-1 (unscaled, into Xs), the cores of the element's ends
+  // and the (rho, phi_k, phi_l) that carry weight (B nonzero, both bases
+  // possible), in (rho, phi_k, phi_l) order
+  int e_prev = 0;
+  if (j >= 2) {
+    T sm = T(0);
+    for (int c = 0; c < nchunks_prev; c++) sm += D.pmax[(size_t)(j - 1) * TZ_GRIDCH + c];
+    e_prev = exp_of((double)sm);
+  }
   const int r0 = D.off[qi], rows = g * D.sig[qi];
   if (qi < j - 1) {
     for (int e0 = tid; e0 < rows * wp; e0 += 4 * TZ_FT) {
@@ -426,6 +435,7 @@ __global__ __launch_bounds__(TZ_FT) void tz_fold(TzDev<T> D, int j, int nchunks_
   }
   __syncthreads();
   // 2. block row qi of column j-1 scaled and written back
+  if (tid == 0 && qi == 0 && j >= 2) D.colexp[j - 1] = e_prev;
   if (qi < j - 1) {
     const size_t cbase = (size_t)D.off[j - 1];
     for (int e = tid; e < rows * wp; e += TZ_FT) {
@@ -592,7 +602,7 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
                oBm = take(n), oTc = take(tc.size() * sizeof(T)),
                oV = take(V.size() * sizeof(T)), oB = take(B.size() * sizeof(T)), oSB = take(SB.size() * sizeof(T)),
                oS = take(S.size() * sizeof(T)), oCe = take((n + 1) * 4), oPt = take((size_t)m * 8),
-               oDn = take((n + 1) * 4);
+               oPm = take((size_t)(n + 1) * TZ_GRIDCH * sizeof(T));
   DevBuf ws;
   if (hipMalloc(&ws.p, at) != hipSuccess) {
     (void)hipGetLastError();
@@ -634,7 +644,7 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   D.Q = (T *)(base + oQ);
   D.P = (T *)(base + oP);
   D.colexp = (int *)(base + oCe);
-  D.done = (int *)(base + oDn);
+  D.pmax = (T *)(base + oPm);
   D.ptr = (double *)(base + oPt);
   const size_t wave_lds = (size_t)(16 * g * g + 2 * xi * 256 + 192) * sizeof(T);
   const size_t model_lds = (size_t)(2 * xi * 16 + 4) * g * g * sizeof(T);
@@ -646,7 +656,6 @@ cdz_status run_tensor(cdz_handle *h, const TzHost &H, const cdz_tensor_model *md
   const size_t prop_lds = (size_t)4 * 4 * ntn_max * 64 * 4 * sizeof(T);
   if (h->profiling) HIPCHK(h, prof_reserve(h, n));
   HIPCHK(h, hipEventRecord(h->ev[0], st));
-  HIPCHK(h, hipMemsetAsync(D.done, 0, (n + 1) * 4, st));
   tz_init<T><<<2048, 256, 0, st>>>(D.Q, (size_t)H.rows, (size_t)H.ld, (size_t)H.N);
   for (int j = 1; j <= n; j++) {
     const int fgrid = j;
