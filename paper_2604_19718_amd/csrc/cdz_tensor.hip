@@ -24,7 +24,9 @@
 //                triangular (a tile starts at the first block its rows own);
 //                one partial sum per chunk to a side buffer.
 // Scaling: column j is divided by h_{j-1} = 2^e, e the binary exponent of the
-// largest entry of its row-0 block, so the prefix block stays in [1, 2);
+// sum over its k chunks of each chunk's largest partial in the row-0 block (at
+// least the block's largest entry, at most the chunk count times it), so the
+// prefix block stays within a few octaves below 1;
 // E_{k,j} of a pair is divided by h_k (the inner block carries the factors of
 // k+1 .. j-2 only).  log Z = log Tr[S Q_{0,n}] + ln 2 * sum of the exponents,
 // and at each codon boundary j = 3a the same gives log Z of the first a
