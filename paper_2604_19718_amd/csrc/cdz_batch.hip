@@ -444,7 +444,7 @@ cdz_status chunk_outside(cdz_handle *h, Chunk<T> &C) {
                            (const int *)(dev + oO) + Lo.at(dl), cnt, dl);
     }
     if (Le.total(0) > 0)
-      hipLaunchKernelGGL(cdz_eta_batch<T>, dim3(Le.total(0)), dim3(CDZ_NT), eta_lds_bytes(nmax, sizeof(T)), gs, dP, dA,
+      hipLaunchKernelGGL(cdz_eta_batch<T>, dim3(Le.total(0)), dim3(cdz_eta_nt(sizeof(T))), eta_lds_bytes(nmax, sizeof(T)), gs, dP, dA,
                          (const int *)(dev + oE), cnt, eta_bulge_chunk(nmax, sizeof(T)));
     for (int b = 0; b < cnt; b++) {
       const long long nn = (long long)n[b] * n[b];

@@ -23,6 +23,9 @@
 #include <stdint.h>
 
 #define CDZ_NT 256      // threads per workgroup of the cell kernels
+// threads per workgroup of the edge-marginal kernel (one edge): eight waves in
+// FP32; four in FP64, whose registers would leave one eight-wave workgroup a CU
+__host__ __device__ constexpr int cdz_eta_nt(int elt) { return elt == 4 ? 512 : 256; }
 #define CDZ_MAXLOOP 30  // bulge / interior loop size bound
 #define CDZ_NA 27      // interior-loop sizes L = 2..28 kept per cell (the recursion in
                        // L reads L - 2 <= 28; sizes 29, 30 only feed the cell itself)

@@ -1133,6 +1133,7 @@ __device__ __forceinline__ void out_block(const DevProb<T> &D, const DevAdj<T> &
 template <typename T>
 __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A, int p, int LCH) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int ENT = cdz_eta_nt(sizeof(T));
   const int n = D.n, tid = threadIdx.x, lane = tid & 63, wv = cdz_wave_id();
   const long long ld = D.ld;
   // LDS: exponents, slot counts and offsets of every position (so that the
@@ -1141,29 +1142,29 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
   int *sE = reinterpret_cast<int *>(smem_raw);
   int *sd = sE + (n + 1), *sP = sd + (n + 1);
   double *red = reinterpret_cast<double *>(smem_raw + ((size_t)3 * (n + 1) * 4 + 15) / 16 * 16);
-  double *Mw = red + (CDZ_NT / 64) * 36 + wv * 36;  // per-wave bulge partial products
+  double *Mw = red + (ENT / 64) * 36 + wv * 36;  // per-wave bulge partial products
   // the unpaired runs of the bulges through this edge, shared by its cells:
   // Ubl[l1 - 1](a, b) = U(p + 1 - l1 slot a, p slot b) (left bulges of the
   // cells (p+1, j)), Ubr[l2 - 1](q, c) = U(p+1 slot c, p + l2 slot q) (right
   // bulges of the cells (i, p)), zero outside the slots
-  T *Ubl = reinterpret_cast<T *>(red + 2 * (CDZ_NT / 64) * 36);
+  T *Ubl = reinterpret_cast<T *>(red + 2 * (ENT / 64) * 36);
   T *Ubr = Ubl + CDZ_MAXLOOP * 36;
   T *Gw = Ubr + CDZ_MAXLOOP * 36 + wv * LCH * 36;  // per wave: LCH loop sizes of a cell's bulge adjoints
-  T *tab = Ubr + CDZ_MAXLOOP * 36 + (CDZ_NT / 64) * LCH * 36;  // [TB_LEN] Boltzmann tables
+  T *tab = Ubr + CDZ_MAXLOOP * 36 + (ENT / 64) * LCH * 36;  // [TB_LEN] Boltzmann tables
   // per wave: U, QmX, Qb, G, F of an inner block, then the edge factors e of
   // the position a cell's dressing sums over
   T *Xw = tab + (TB_LEN + 7) / 8 * 8 + wv * 6 * 36;
   T *Ew = Xw + 5 * 36;
-  int *Nw = reinterpret_cast<int *>(tab + (TB_LEN + 7) / 8 * 8 + (CDZ_NT / 64) * 6 * 36) + wv * 12;
-  for (int k = tid; k < n; k += CDZ_NT) {
+  int *Nw = reinterpret_cast<int *>(tab + (TB_LEN + 7) / 8 * 8 + (ENT / 64) * 6 * 36) + wv * 12;
+  for (int k = tid; k < n; k += ENT) {
     sE[k] = D.E[k];
     sd[k] = D.d[k];
     sP[k] = D.P[k];
   }
-  for (int k = tid; k < TB_LEN; k += CDZ_NT) tab[k] = D.tab[k];
+  for (int k = tid; k < TB_LEN; k += ENT) tab[k] = D.tab[k];
   const int dp = D.d[p], dq = D.d[p + 1], Pp = D.P[p], Pq = D.P[p + 1];
   const int l1top = min(CDZ_MAXLOOP, p), l2top = min(CDZ_MAXLOOP, n - 2 - p);
-  for (int k = tid; k < CDZ_MAXLOOP * 36; k += CDZ_NT) {
+  for (int k = tid; k < CDZ_MAXLOOP * 36; k += ENT) {
     const int l = k / 36 + 1, r1 = (k % 36) / 6, r2 = k % 6;
     T xl = 0, xr = 0;
     if (l <= l1top && r2 < dp) {  // (a, b) = (r1, r2)
@@ -1220,7 +1221,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
   const int nC1 = p + 2;                          // cells (i, p+1), i <= p+1
   const int nC0 = p - 3 > 0 ? p - 3 : 0;          // cells (i, p), i <= p-4
   const int total = nR1 + nR0 + nC1 + nC0;
-  for (int it = wv; it < total; it += CDZ_NT / 64) {
+  for (int it = wv; it < total; it += ENT / 64) {
     int k = it;
     if (k < nR1) {
       // ---- cell (i, j) = (p+1, j): the edge before its first base;
@@ -1533,7 +1534,7 @@ __device__ __forceinline__ void eta_edge(const DevProb<T> &D, const DevAdj<T> &A
   // size recursion, accumulated by the outside pass
   if (tid < 36) {
     double t = 0;
-    for (int v = 0; v < CDZ_NT / 64; v++) t += red[v * 36 + tid];
+    for (int v = 0; v < ENT / 64; v++) t += red[v * 36 + tid];
     A.eta[p * 36 + tid] = t + A.etaV[p * 36 + tid] + A.etaW[p * 36 + tid];
   }
 }
@@ -1547,7 +1548,7 @@ __global__ __launch_bounds__(CDZ_NT) void cdz_out_diag_fused(DevProb<T> D, DevAd
   out_block<T, true>(D, A, dl, blockIdx.x);
 }
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_eta(DevProb<T> D, DevAdj<T> A, int lch) {
+__global__ __launch_bounds__(cdz_eta_nt(sizeof(T))) void cdz_eta(DevProb<T> D, DevAdj<T> A, int lch) {
   eta_edge<T>(D, A, blockIdx.x, lch);
 }
 // batched forms (see cdz_fwd_diag_batch): one launch for diagonal dl / for the
@@ -1571,7 +1572,7 @@ __global__ __launch_bounds__(CDZ_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T
   out_block<T, true>(D, A, dl, w);
 }
 template <typename T>
-__global__ __launch_bounds__(CDZ_NT) void cdz_eta_batch(const DevProb<T> *probs, const DevAdj<T> *adjs,
+__global__ __launch_bounds__(cdz_eta_nt(sizeof(T))) void cdz_eta_batch(const DevProb<T> *probs, const DevAdj<T> *adjs,
                                                        const int *off, int count, int lch) {
   int b, w;
   cdz_batch_locate(off, count, blockIdx.x, b, w);
@@ -1620,10 +1621,10 @@ size_t eta_lds_bytes(int n, int elt) {
   // edge's bulges and the per-wave bulge adjoints; tables; per-wave inner
   // blocks and bases
   const int lch = eta_bulge_chunk(n, elt);
-  return ((size_t)3 * (n + 1) * 4 + 15) / 16 * 16 + (size_t)(2 * (CDZ_NT / 64) * 36) * 8 +
-         ((size_t)2 * CDZ_MAXLOOP * 36 + (size_t)(CDZ_NT / 64) * lch * 36 + (TB_LEN + 7) / 8 * 8 +
-          (CDZ_NT / 64) * 6 * 36) * elt +
-         (CDZ_NT / 64) * 12 * 4;
+  const int nw = cdz_eta_nt(elt) / 64;
+  return ((size_t)3 * (n + 1) * 4 + 15) / 16 * 16 + (size_t)(2 * nw * 36) * 8 +
+         ((size_t)2 * CDZ_MAXLOOP * 36 + (size_t)nw * lch * 36 + (TB_LEN + 7) / 8 * 8 + nw * 6 * 36) * elt +
+         nw * 12 * 4;
 }
 
 template <typename T>
@@ -1698,7 +1699,7 @@ static cdz_status run_outside(cdz_handle *h, DevProb<T> &D, DevAdj<T> &A) {
       return cdz_fail(h, CDZ_ERR_ARG, "sequence of " + std::to_string(n) + " nt exceeds the LDS layout of the edge kernel");
     HIPCHK(h, hipFuncSetAttribute((const void *)cdz_eta<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm2));
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n], st));
-    hipLaunchKernelGGL(cdz_eta<T>, dim3(n - 1), dim3(CDZ_NT), shm2, st, D, A, eta_bulge_chunk(n, sizeof(T)));
+    hipLaunchKernelGGL(cdz_eta<T>, dim3(n - 1), dim3(cdz_eta_nt(sizeof(T))), shm2, st, D, A, eta_bulge_chunk(n, sizeof(T)));
     if (h->profiling) HIPCHK(h, hipEventRecord(h->pev[2 * n + 1], st));
   }
   const double r = std::exp(h->EZ * 0.6931471805599453094 - h->logz_scaled);
